@@ -1,0 +1,519 @@
+"""FP64 CPU oracle for the adaptive GSIS kinetic sweep -- TEST INFRASTRUCTURE.
+
+Only tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP
+library (``paper_2501_02245_amd``): the numerical pieces live in
+``gsis_oracle.c`` (plain loops, FP64), and this module strings them together
+in the order of the paper's algorithm (Zhang, Zeng & Wu, arXiv 2501.02245,
+Sec. 3.1-3.4).  Inputs come from ``gsis_inputs`` only.
+
+Functions with no pin against an independent result are marked
+"parity unpinned" in their docstring.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+NMOM = 14
+PI = np.pi
+
+
+def build(force: bool = False) -> str:
+    """Compile gsis_oracle.c into liboracle.so with gcc (FP64, OpenMP)."""
+    src = os.path.join(_HERE, "gsis_oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_cells", C.c_int32), ("n_faces", C.c_int32),
+                ("n_patches", C.c_int32),
+                ("face_cells", C.c_void_p), ("face_normal", C.c_void_p), ("face_area", C.c_void_p),
+                ("face_center", C.c_void_p), ("cell_volume", C.c_void_p), ("cell_center", C.c_void_p),
+                ("patch_kind", C.c_void_p), ("patch_state", C.c_void_p)]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("vdim", C.c_int32), ("n", C.c_int32 * 3), ("x", C.c_void_p * 3), ("w", C.c_void_p * 3)]
+
+
+class _Gas(C.Structure):
+    _fields_ = [("Kn", C.c_double), ("omega", C.c_double), ("Pr", C.c_double), ("inv_dt", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.c_void_p
+        _lib.oc_nv.restype = C.c_int32
+        _lib.oc_tau.restype = C.c_double
+        for name in ("oc_fixup", "oc_equilibrium", "oc_feq", "oc_sweep", "oc_macro"):
+            getattr(_lib, name).restype = C.c_int32
+        _lib.oc_tau.argtypes = [P, C.c_double, C.c_double]
+        _lib.oc_fixup.argtypes = [P, C.c_double, P, C.c_double, P, P]
+        _lib.oc_maxwellian.argtypes = [P, C.c_double, P, C.c_double, P]
+        _lib.oc_shakhov.argtypes = [P, C.c_double, P, P]
+        _lib.oc_lsq_gradients.argtypes = [P, C.c_int32, P, P, P]
+        _lib.oc_nsf.argtypes = [P, C.c_double, P, P, P, P]
+        _lib.oc_sweep.argtypes = [P, P, P, C.c_int32, P, P, P, P, P]
+        _lib.oc_macro.argtypes = [P, P, P, P, C.c_int32, C.c_double, P]
+        _lib.oc_macro_residual.restype = C.c_int32
+        _lib.oc_macro_residual.argtypes = [P, P, P, P, P]
+        _lib.oc_kinetic_residual.restype = C.c_int32
+        _lib.oc_kinetic_residual.argtypes = [P, P, C.c_int32, P, P, P, P, P]
+    return _lib
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Oracle:
+    """Plain FP64 implementation of one steady problem (mesh + gas + grid)."""
+
+    def __init__(self, mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, inv_dt=0.0):
+        L = lib()
+        self.mesh, self.grid = mesh, grid
+        self.vdim = grid["vdim"]
+        self.nfun = 1 if self.vdim == 3 else 2
+        self._keep = []
+        k = self._keep.append
+        fc = np.ascontiguousarray(mesh["face_cells"], dtype=np.int32); k(fc)
+        arrs = [_f64(mesh[n]) for n in ("face_normal", "face_area", "face_center", "cell_volume", "cell_center")]
+        for a in arrs:
+            k(a)
+        pk = np.array([0 if p["kind"] == "wall" else 1 for p in mesh["patches"]], dtype=np.int32); k(pk)
+        ps = np.array([[p["rho"], *p["u"], p["T"]] for p in mesh["patches"]], dtype=np.float64).reshape(-1, 5); k(ps)
+        self.patch_state = ps
+        self.patch_kind = pk
+        self.cm = _Mesh(mesh["dim"], mesh["n_cells"], mesh["n_faces"], len(mesh["patches"]),
+                        fc.ctypes.data, *[a.ctypes.data for a in arrs], pk.ctypes.data, ps.ctypes.data)
+        self.cg = _Grid()
+        self.cg.vdim = self.vdim
+        for d in range(3):
+            if d < self.vdim:
+                x, w = _f64(grid["nodes"][d]), _f64(grid["weights"][d])
+                k(x); k(w)
+                self.cg.n[d] = len(x)
+                self.cg.x[d] = x.ctypes.data
+                self.cg.w[d] = w.ctypes.data
+            else:
+                self.cg.n[d] = 1
+        self.nv = L.oc_nv(C.byref(self.cg))
+        self.gas = _Gas(Kn, omega, Pr, inv_dt)
+        self.Kn, self.omega, self.Pr = Kn, omega, Pr
+        # per-node velocities and weights (for tests and diagnostics)
+        self.xi, self.w = self._nodes()
+
+    def _nodes(self):
+        g = self.grid
+        if self.vdim == 3:
+            X, Y, Z = np.meshgrid(*g["nodes"], indexing="ij")
+            WX, WY, WZ = np.meshgrid(*g["weights"], indexing="ij")
+            xi = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+            w = (WX * WY * WZ).ravel()
+        else:
+            X, Y = np.meshgrid(*g["nodes"], indexing="ij")
+            WX, WY = np.meshgrid(*g["weights"], indexing="ij")
+            xi = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)
+            w = (WX * WY).ravel()
+        return xi, w
+
+    # --- single-cell pieces -------------------------------------------------
+    def row_shape(self):
+        return (self.nfun, self.nv)
+
+    def moments(self, f):
+        """Moments of rows f[..., nfun, nv] -> [..., 14] (Sec. 2, getmoment)."""
+        f = _f64(f)
+        lead = f.shape[:-2]
+        fr = f.reshape(-1, self.nfun * self.nv)
+        out = np.empty((fr.shape[0], NMOM))
+        for i in range(fr.shape[0]):
+            row = np.ascontiguousarray(fr[i])
+            lib().oc_moments(C.byref(self.cg), _p(row), _p(out[i]))
+        return out.reshape(*lead, NMOM)
+
+    def maxwellian(self, rho, u, T):
+        out = np.empty(self.row_shape())
+        uu = _f64(np.asarray(u, dtype=np.float64).reshape(3))
+        lib().oc_maxwellian(C.byref(self.cg), float(rho), _p(uu), float(T), _p(out))
+        return out
+
+    def shakhov(self, mom):
+        out = np.empty(self.row_shape())
+        m = _f64(mom)
+        lib().oc_shakhov(C.byref(self.cg), float(self.Pr), _p(m), _p(out))
+        return out
+
+    def fixup(self, g, rho, u, T):
+        g = _f64(g).copy()
+        coef = np.zeros(5)
+        uu = _f64(np.asarray(u, dtype=np.float64).reshape(3))
+        r = lib().oc_fixup(C.byref(self.cg), float(rho), _p(uu), float(T), _p(g), _p(coef))
+        if r != 0:
+            raise FloatingPointError("fix-up system singular")
+        return g, coef[: self.vdim + 2]
+
+    def equilibrium(self, mom):
+        out = np.empty(self.row_shape())
+        m = _f64(mom)
+        if lib().oc_equilibrium(C.byref(self.cg), C.byref(self.gas), _p(m), _p(out)) != 0:
+            raise FloatingPointError("fix-up system singular")
+        return out
+
+    def feq(self, W5):
+        out = np.empty(self.row_shape())
+        w = _f64(W5)
+        if lib().oc_feq(C.byref(self.cg), _p(w), _p(out)) != 0:
+            raise FloatingPointError("fix-up system singular")
+        return out
+
+    def g13(self, mom):
+        out = np.empty(self.row_shape())
+        m = _f64(mom)
+        lib().oc_g13(C.byref(self.cg), _p(m), _p(out))
+        return out
+
+    def tau(self, rho, T):
+        return lib().oc_tau(C.byref(self.gas), float(rho), float(T))
+
+    # --- field-level pieces -------------------------------------------------
+    def sweep(self, f_old, kin_cell, slot_of_cell, ghost=None):
+        """One point-Jacobi kinetic sweep (Sec. 3.1).  f_old [n_slots, nfun, nv]."""
+        f_old = _f64(f_old)
+        f_new = np.zeros_like(f_old)
+        kc = np.ascontiguousarray(kin_cell, dtype=np.int32)
+        sc = np.ascontiguousarray(slot_of_cell, dtype=np.int32)
+        if ghost is None:
+            ghost = np.zeros((self.mesh["n_cells"], NMOM))
+        gh = _f64(ghost)
+        r = lib().oc_sweep(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc), _p(kc), _p(sc),
+                           _p(f_old), _p(gh), _p(f_new))
+        if r != 0:
+            raise FloatingPointError("oracle sweep failed (%d)" % r)
+        return f_new
+
+    def lsq(self, phi, bnd):
+        """LSQ gradients (Sec. 3.4 Step 2). phi [n_cells, nvar], bnd [n_patches, nvar]."""
+        phi = _f64(phi)
+        nvar = phi.shape[1]
+        bnd = _f64(bnd).reshape(len(self.mesh["patches"]), nvar)
+        grad = np.zeros((phi.shape[0], nvar, 3))
+        lib().oc_lsq_gradients(C.byref(self.cm), nvar, _p(phi), _p(bnd), _p(grad))
+        return grad
+
+    def nsf(self, T, grad_u, grad_T):
+        s = np.zeros(6)
+        q = np.zeros(3)
+        gu = _f64(grad_u).reshape(9)
+        gt = _f64(grad_T).reshape(3)
+        lib().oc_nsf(C.byref(self.gas), float(T), _p(gu), _p(gt), _p(s), _p(q))
+        return s, q
+
+    def primitive_gradients(self, W):
+        """LSQ gradients of (ux, uy, uz, T, rho, |u|) with patch values at faces."""
+        phi = np.concatenate([W[:, 1:5], W[:, :1], np.linalg.norm(W[:, 1:4], axis=1)[:, None]], 1)
+        bnd = np.full((len(self.mesh["patches"]), 6), np.nan)
+        for p, pt in enumerate(self.mesh["patches"]):
+            bnd[p, 0:3] = pt["u"]
+            bnd[p, 3] = pt["T"]
+            bnd[p, 5] = np.linalg.norm(pt["u"])
+            if pt["kind"] == "far":
+                bnd[p, 4] = pt["rho"]
+        return self.lsq(phi, bnd)
+
+    def nsf_field(self, W, grad=None):
+        """sigma_NSF, q_NSF on every cell from LSQ gradients of W (Sec. 2 NSF_constitutive)."""
+        if grad is None:
+            grad = self.primitive_gradients(W)
+        out = np.zeros((len(W), 9))
+        for i in range(len(W)):
+            s, q = self.nsf(W[i, 4], grad[i, 0:3, :], grad[i, 3, :])
+            out[i, :6] = s
+            out[i, 6:] = q
+        return out
+
+    def ghost_params(self, W, grad=None):
+        """Grad-13 parameters (rho, u, T, sigma_NSF, q_NSF) per cell (Sec. 3.2)."""
+        nsf = self.nsf_field(W, grad)
+        gh = np.zeros((len(W), NMOM))
+        gh[:, 0:5] = W
+        gh[:, 5:11] = nsf[:, :6]
+        gh[:, 11:14] = nsf[:, 6:]
+        if self.vdim == 2:
+            gh[:, 3] = 0.0
+            gh[:, 9:11] = 0.0
+            gh[:, 13] = 0.0
+        return gh
+
+    def kn_gll(self, W, grad=None):
+        """Gradient-length local Kn (Sec. 3.2 eq. Kn_Gll).
+
+        Reading: lambda = Kn T^(omega - 1/2) / rho (scaled mean free path),
+        |grad U| / max(U, a) with a = sqrt(5 T / 6) so that U -> 0 stays finite.
+        """
+        if grad is None:
+            grad = self.primitive_gradients(W)
+        rho, T = W[:, 0], W[:, 4]
+        U = np.linalg.norm(W[:, 1:4], axis=1)
+        a = np.sqrt(5.0 * T / 6.0)
+        lam = self.Kn * T ** (self.omega - 0.5) / rho
+        gr = np.linalg.norm(grad[:, 4, :], axis=1) / rho
+        gu = np.linalg.norm(grad[:, 5, :], axis=1) / np.maximum(U, a)
+        gt = np.linalg.norm(grad[:, 3, :], axis=1) / T
+        return lam * np.maximum(np.maximum(gr, gu), gt)
+
+    def wall_layers(self, n_layers):
+        """Cells within n_layers face-neighbour hops of a wall (reading of the forced wall layers)."""
+        m = self.mesh
+        fc = m["face_cells"]
+        mark = np.zeros(m["n_cells"], dtype=bool)
+        wall_p = [p for p, pt in enumerate(m["patches"]) if pt["kind"] == "wall"]
+        bnd = fc[:, 1] < 0
+        for p in wall_p:
+            mark[fc[bnd & (fc[:, 1] == -1 - p), 0]] = True
+        inner = fc[:, 1] >= 0
+        a, b = fc[inner, 0], fc[inner, 1]
+        cur = mark.copy()
+        for _ in range(max(n_layers - 1, 0)):
+            nxt = cur.copy()
+            nxt[b[cur[a]]] = True
+            nxt[a[cur[b]]] = True
+            cur = nxt
+        return cur if n_layers > 0 else np.zeros_like(mark)
+
+    def flags(self, W, Kn_ref, force_wall_layers=0, grad=None):
+        """DVM region flag = Kn_Gll >= Kn_ref (Sec. 3.2 second eq. updatef; ties are kinetic)."""
+        k = self.kn_gll(W, grad) >= Kn_ref
+        return (k | self.wall_layers(force_wall_layers)).astype(np.uint8)
+
+    def macro(self, W, hot, n_inner, cfl=0.5, src=None):
+        """Synthetic macroscopic solve (Sec. 3.1 eq. macro); see oc_macro for the reading."""
+        Wio = _f64(W).copy()
+        h = _f64(hot)
+        sr = _f64(src) if src is not None else None
+        r = lib().oc_macro(C.byref(self.cm), C.byref(self.gas), _p(h), _p(sr), int(n_inner), float(cfl), _p(Wio))
+        if r != 0:
+            raise FloatingPointError("macro solve produced a non-positive state")
+        return Wio
+
+    def macro_residual(self, W, hot):
+        """Per-unit-volume residual of the synthetic equations at W (no source)."""
+        Wc = _f64(W)
+        h = _f64(hot)
+        out = np.zeros((len(Wc), 5))
+        if lib().oc_macro_residual(C.byref(self.cm), C.byref(self.gas), _p(h), _p(Wc), _p(out)) != 0:
+            raise FloatingPointError("non-positive state")
+        return out
+
+    def kinetic_residual(self, f, kin_cell, slot_of_cell, ghost=None):
+        """Moment balance (mass, momentum, energy per unit volume) of the kinetic scheme at f."""
+        f = _f64(f)
+        kc = np.ascontiguousarray(kin_cell, dtype=np.int32)
+        sc = np.ascontiguousarray(slot_of_cell, dtype=np.int32)
+        gh = _f64(ghost if ghost is not None else np.zeros((self.mesh["n_cells"], NMOM)))
+        out = np.zeros((self.mesh["n_cells"], 5))
+        lib().oc_kinetic_residual(C.byref(self.cm), C.byref(self.cg), len(kc), _p(kc), _p(sc), _p(f), _p(gh), _p(out))
+        return out
+
+    # --- drivers -------------------------------------------------------------
+    def residual(self, W_new, W_old):
+        """Convergence measure of Sec. 4 (volume-weighted relative change of rho, u, T_t).
+
+        Reading: u is taken as a vector; a vanishing denominator falls back to
+        the absolute change.
+        """
+        V = self.mesh["cell_volume"]
+        out = []
+        for sl in (slice(0, 1), slice(1, 4), slice(4, 5)):
+            num = np.sum(np.sum((W_new[:, sl] - W_old[:, sl]) ** 2, axis=1) * V)
+            den = np.sum(np.sum(W_old[:, sl] ** 2, axis=1) * V)
+            out.append(np.sqrt(num / den) if den > 1e-30 else np.sqrt(num))
+        return np.array(out)
+
+
+def regions_from_flags(flags, old_slot_of_cell=None):
+    """Compacted kinetic list (ascending cell id) and slot assignment.
+
+    Cells that stay kinetic keep their slot; leaving cells free theirs; new
+    cells take free slots lowest-first in ascending cell id.  Returns
+    (kin_cell, slot_of_cell, new_cells).
+    """
+    flags = np.asarray(flags).astype(bool)
+    n = len(flags)
+    kin = np.nonzero(flags)[0].astype(np.int32)
+    if old_slot_of_cell is None:
+        slot = np.full(n, -1, dtype=np.int32)
+        slot[kin] = np.arange(len(kin), dtype=np.int32)
+        return kin, slot, kin.copy()
+    slot = np.where(flags, old_slot_of_cell, -1).astype(np.int32)
+    used = set(int(s) for s in slot[slot >= 0])
+    new = np.nonzero(flags & (np.asarray(old_slot_of_cell) < 0))[0].astype(np.int32)
+    free = (s for s in range(n) if s not in used)
+    for c in new:
+        slot[c] = next(free)
+    return kin, slot, new
+
+
+def conductivities(A, d_r):
+    """kappa_t/(mu R), kappa_r/(mu R) from eq. (mu_kappa): (1/2) A^{-1} [5, d_r].
+
+    For d_r = 0 the system reduces to kappa_t = (mu R / 2) 5 / A_tt.
+    """
+    A = np.atleast_2d(np.asarray(A, dtype=np.float64))
+    rhs = np.array([5.0, float(d_r)])[: A.shape[0]]
+    return 0.5 * np.linalg.solve(A, rhs)
+
+
+def eucken_factors(A, d_r):
+    """Eucken factors f = kappa / (mu c_v) with c_v,t = 3R/2 and c_v,r = d_r R / 2."""
+    k = conductivities(A, d_r)
+    out = [k[0] / 1.5]
+    if len(k) > 1:
+        out.append(k[1] / (0.5 * d_r))
+    return np.array(out)
+
+
+def one_cell_mesh():
+    """A single closed cell with no faces (homogeneous relaxation)."""
+    return {"dim": 3, "n_cells": 1, "n_faces": 0,
+            "face_cells": np.zeros((0, 2), dtype=np.int32), "face_normal": np.zeros((0, 3)),
+            "face_area": np.zeros(0), "face_center": np.zeros((0, 3)),
+            "cell_volume": np.ones(1), "cell_center": np.zeros((1, 3)), "patches": []}
+
+
+class SteadySolver:
+    """Outer iteration of Sec. 3.4 (Steps 1-4), one plain step at a time.
+
+    mode 'dvm'  : f^{n+1} = f^{n+1/2} (conventional iteration, no synthetic step)
+    mode 'gsis' : every cell kinetic; Sec. 3.1 synthetic step and correction
+    mode 'agsis': kinetic cells chosen by Kn_Gll >= Kn_ref (Sec. 3.2), NS elsewhere
+
+    State: W [n_cells, 5] primitive (rho, u, T) on every cell; flags; kinetic
+    list and slots; f [n_slots, nfun, nv] for the kinetic cells.
+    """
+
+    def __init__(self, O, mode="gsis", Kn_ref=0.01, n_inner=400, cfl=0.5,
+                 region_every=1, force_wall_layers=0, capacity=None):
+        self.O, self.mode = O, mode
+        self.Kn_ref, self.n_inner, self.cfl = Kn_ref, n_inner, cfl
+        self.region_every, self.layers = region_every, force_wall_layers
+        self.n = O.mesh["n_cells"]
+        self.capacity = capacity if capacity is not None else self.n
+        self.it = 0
+
+    # -- initial state ---------------------------------------------------------
+    def set_state(self, W, f=None, flags=None):
+        """W on all cells; f (rows for the kinetic cells in ascending id) or
+        None to start kinetic cells from the conservation-fixed Maxwellian of W."""
+        O = self.O
+        self.W = np.array(W, dtype=np.float64)
+        if flags is None:
+            flags = np.ones(self.n, np.uint8)
+        self.flags = np.asarray(flags, dtype=np.uint8).copy()
+        self.kin, self.slot, _ = regions_from_flags(self.flags)
+        self.f = np.zeros((self.capacity,) + O.row_shape())
+        if f is None:
+            for c in self.kin:
+                self.f[self.slot[c]] = O.feq(self.W[c])
+        else:
+            self.f[self.slot[self.kin]] = np.asarray(f, dtype=np.float64)
+        if self.mode == "dvm":
+            self.W[self.kin] = O.moments(self.f[self.slot[self.kin]])[:, :5]
+
+    def ns_init(self, tol=1e-6, chunk=None, max_chunks=1000):
+        """Step 1: macroscopic (NSF) solve alone, HoT = 0, to eps < tol."""
+        O = self.O
+        chunk = chunk or self.n_inner
+        hot = np.zeros((self.n, 9))
+        for k in range(max_chunks):
+            Wn = O.macro(self.W, hot, chunk, self.cfl)
+            eps = O.residual(Wn, self.W)
+            self.W = Wn
+            if eps.max() < tol:
+                return k + 1, eps
+        return max_chunks, eps
+
+    def update_regions(self):
+        """Step 2/3: LSQ gradients, Kn_Gll flags, compaction, G13 init of new cells."""
+        O = self.O
+        grad = O.primitive_gradients(self.W)
+        fl = O.flags(self.W, self.Kn_ref, self.layers, grad)
+        kin, slot, new = regions_from_flags(fl, self.slot)
+        if len(kin) > self.capacity:
+            raise MemoryError("kinetic region exceeds capacity")
+        gh = O.ghost_params(self.W, grad)
+        for c in new:
+            self.f[slot[c]] = O.g13(gh[c])
+        self.flags, self.kin, self.slot = fl, kin, slot
+        return len(kin)
+
+    # -- one outer iteration ---------------------------------------------------
+    def step(self):
+        O = self.O
+        kin, slot = self.kin, self.slot
+        rows = slot[kin]
+        ghost = O.ghost_params(self.W) if self.mode == "agsis" else None
+        if self.mode != "dvm":
+            Rk = O.kinetic_residual(self.f, kin, slot, ghost)
+        f_half = O.sweep(self.f, kin, slot, ghost)
+        mom_half = O.moments(f_half[rows])
+        W_old = self.W
+        W_half = W_old.copy()
+        W_half[kin] = mom_half[:, :5]
+        if self.mode == "dvm":
+            W_new = W_half
+            self.f = f_half
+        else:
+            # high-order terms on kinetic cells (eq. full_constitutive)
+            nsf = O.nsf_field(W_half)
+            hot = np.zeros((self.n, 9))
+            hot[kin, :6] = mom_half[:, 5:11] - nsf[kin, :6]
+            hot[kin, 6:] = mom_half[:, 11:14] - nsf[kin, 6:]
+            # Source Q of eq. macro (reading): on kinetic cells, the kinetic
+            # scheme's own moment balance at f^n minus the synthetic residual
+            # at W^n.  The synthetic solve then starts from W^n and acts as a
+            # Newton-like corrector of the conserved moments, and its fixed
+            # point is the fixed point of the kinetic iteration.
+            src = np.zeros((self.n, 5))
+            src[kin] = Rk[kin] - O.macro_residual(W_old, hot)[kin]
+            W_new = O.macro(W_old, hot, self.n_inner, self.cfl, src)
+            # GSIS correction (first eq. updatef)
+            for c in kin:
+                f_half[slot[c]] += O.feq(W_new[c]) - O.feq(W_half[c])
+            self.f = f_half
+        eps = O.residual(W_new, W_old)
+        self.W = W_new
+        self.it += 1
+        self.last_mom = mom_half
+        if self.mode == "agsis" and self.it % self.region_every == 0:
+            self.update_regions()
+        return eps
+
+    def solve(self, tol=1e-6, max_iter=1000, callback=None):
+        for _ in range(max_iter):
+            eps = self.step()
+            if callback:
+                callback(self, eps)
+            if eps.max() < tol:
+                return self.it, eps
+        return self.it, eps

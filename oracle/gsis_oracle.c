@@ -1,0 +1,769 @@
+/*
+ * gsis_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * See gsis_oracle.h for units and layouts.  Each function follows one
+ * passage of Zhang, Zeng & Wu, arXiv 2501.02245, cited by section and
+ * equation label; readings of points the paper leaves open are stated where
+ * they are used.  No blocking, fusion or reordering: loops run over cells,
+ * faces and velocity nodes in the order the definitions are written.
+ */
+#include "gsis_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double PI = 3.14159265358979323846;
+
+int32_t oc_nv(const oc_grid *g)
+{
+    return g->vdim == 3 ? g->n[0] * g->n[1] * g->n[2] : g->n[0] * g->n[1];
+}
+
+int32_t oc_nfun(const oc_grid *g) { return g->vdim == 3 ? 1 : 2; }
+
+/* velocity node k -> (xi, weight); xi_z = 0 for the reduced grid */
+static void node(const oc_grid *g, int32_t k, double *xi, double *w)
+{
+    if (g->vdim == 3) {
+        int32_t iz = k % g->n[2];
+        int32_t iy = (k / g->n[2]) % g->n[1];
+        int32_t ix = k / (g->n[2] * g->n[1]);
+        xi[0] = g->x[0][ix]; xi[1] = g->x[1][iy]; xi[2] = g->x[2][iz];
+        *w = g->w[0][ix] * g->w[1][iy] * g->w[2][iz];
+    } else {
+        int32_t iy = k % g->n[1];
+        int32_t ix = k / g->n[1];
+        xi[0] = g->x[0][ix]; xi[1] = g->x[1][iy]; xi[2] = 0.0;
+        *w = g->w[0][ix] * g->w[1][iy];
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Moments, Sec. 2 eq. (getmoment), scaled:
+ *   rho = sum w f, rho u = sum w xi f, c = xi - u,
+ *   p = rho T = (2/3) sum w c^2 f, sigma = 2 sum w (cc - c^2 I/3) f,
+ *   q = sum w c^2 c f.
+ * Reduced pair (phi, psi): (3/2) p = sum w (c^2 phi + psi),
+ *   sigma_xx = 2 sum w cx^2 phi - p, sigma_zz = 2 sum w psi - p,
+ *   q = sum w c (c^2 phi + psi).
+ * ------------------------------------------------------------------------ */
+void oc_moments(const oc_grid *g, const double *f, double *mom)
+{
+    int32_t nv = oc_nv(g);
+    double xi[3], w;
+    double rho = 0, m[3] = {0, 0, 0};
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        rho += w * f[k];
+        for (int d = 0; d < 3; ++d) m[d] += w * xi[d] * f[k];
+    }
+    double u[3] = {m[0] / rho, m[1] / rho, m[2] / rho};
+    double e = 0, cc[3][3] = {{0}}, q[3] = {0, 0, 0}, psum = 0;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c[3] = {xi[0] - u[0], xi[1] - u[1], xi[2] - u[2]};
+        if (g->vdim == 2) c[2] = 0.0;
+        double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        double fk = f[k];
+        double psik = (g->vdim == 2) ? f[nv + k] : 0.0;
+        e += w * (c2 * fk + psik);
+        psum += w * psik;
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) cc[i][j] += w * c[i] * c[j] * fk;
+            q[i] += w * c[i] * (c2 * fk + psik);
+        }
+    }
+    double p = (2.0 / 3.0) * e;
+    mom[0] = rho;
+    mom[1] = u[0]; mom[2] = u[1]; mom[3] = (g->vdim == 2) ? 0.0 : u[2];
+    mom[4] = p / rho;
+    if (g->vdim == 3) {
+        mom[5] = 2.0 * cc[0][0] - p;
+        mom[6] = 2.0 * cc[1][1] - p;
+        mom[7] = 2.0 * cc[2][2] - p;
+        mom[8] = 2.0 * cc[0][1];
+        mom[9] = 2.0 * cc[0][2];
+        mom[10] = 2.0 * cc[1][2];
+        mom[11] = q[0]; mom[12] = q[1]; mom[13] = q[2];
+    } else {
+        mom[5] = 2.0 * cc[0][0] - p;
+        mom[6] = 2.0 * cc[1][1] - p;
+        mom[7] = 2.0 * psum - p;
+        mom[8] = 2.0 * cc[0][1];
+        mom[9] = 0.0; mom[10] = 0.0;
+        mom[11] = q[0]; mom[12] = q[1]; mom[13] = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Equilibrium (Sec. 3.2, f_eq of the Grad-type construction), scaled:
+ *   M = rho (pi T)^(-3/2) exp(-c^2/T);  reduced: phi = rho (pi T)^(-1)
+ *   exp(-c^2/T), psi = (T/2) phi.
+ * ------------------------------------------------------------------------ */
+void oc_maxwellian(const oc_grid *g, double rho, const double *u, double T, double *out)
+{
+    int32_t nv = oc_nv(g);
+    double xi[3], w;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c2 = 0;
+        for (int d = 0; d < g->vdim; ++d) c2 += (xi[d] - u[d]) * (xi[d] - u[d]);
+        if (g->vdim == 3) {
+            out[k] = rho * pow(PI * T, -1.5) * exp(-c2 / T);
+        } else {
+            double phi = rho / (PI * T) * exp(-c2 / T);
+            out[k] = phi;
+            out[nv + k] = 0.5 * T * phi;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Reference distribution of the kinetic model (Sec. 2, reference
+ * distributions g_0t, g_0r and the heat-flux mixing matrix).  For d_r = 0 the
+ * combination g = (1 - 1/Z_r) g_0t + g_0r / Z_r has heat-flux coefficient
+ * 3 (1 - A_tt) for every Z_r, i.e. the Shakhov form with Pr = A_tt:
+ *   g = M [1 + (4/5)(1 - Pr) q.c / (p T) (c^2/T - 5/2)]   (scaled units).
+ * Reduced (integrated over xi_z, u_z = q_z = 0):
+ *   phi: M2 [1 + K q.c (c^2/T - 2)],  psi: (T/2) M2 [1 + K q.c (c^2/T - 1)].
+ * ------------------------------------------------------------------------ */
+void oc_shakhov(const oc_grid *g, double Pr, const double *mom, double *out)
+{
+    int32_t nv = oc_nv(g);
+    double rho = mom[0], T = mom[4];
+    const double *u = mom + 1, *q = mom + 11;
+    double K = 0.8 * (1.0 - Pr) / (rho * T * T);
+    double xi[3], w;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c[3] = {0, 0, 0}, c2 = 0, qc = 0;
+        for (int d = 0; d < g->vdim; ++d) {
+            c[d] = xi[d] - u[d];
+            c2 += c[d] * c[d];
+            qc += q[d] * c[d];
+        }
+        if (g->vdim == 3) {
+            double M = rho * pow(PI * T, -1.5) * exp(-c2 / T);
+            out[k] = M * (1.0 + K * qc * (c2 / T - 2.5));
+        } else {
+            double M = rho / (PI * T) * exp(-c2 / T);
+            out[k] = M * (1.0 + K * qc * (c2 / T - 2.0));
+            out[nv + k] = 0.5 * T * M * (1.0 + K * qc * (c2 / T - 1.0));
+        }
+    }
+}
+
+/* dense Gaussian elimination with partial pivoting, n <= 8 */
+static int solve_small(int n, double *A, double *b)
+{
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(A[r * n + col]) > fabs(A[piv * n + col])) piv = r;
+        if (A[piv * n + col] == 0.0) return -1;
+        if (piv != col) {
+            for (int j = 0; j < n; ++j) {
+                double t = A[col * n + j]; A[col * n + j] = A[piv * n + j]; A[piv * n + j] = t;
+            }
+            double t = b[col]; b[col] = b[piv]; b[piv] = t;
+        }
+        for (int r = col + 1; r < n; ++r) {
+            double fac = A[r * n + col] / A[col * n + col];
+            for (int j = col; j < n; ++j) A[r * n + j] -= fac * A[col * n + j];
+            b[r] -= fac * b[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int j = r + 1; j < n; ++j) s -= A[r * n + j] * b[j];
+        b[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Conservation fix-up (reading: the paper states that the relaxation term
+ * conserves mass, momentum and energy; on a truncated discrete grid it does
+ * so only to quadrature error, so the target is multiplied by
+ * P(c) = a0 + a.c + b c^2 chosen to make the discrete collision invariants
+ * exact).  Basis and test functions {1, c_d, c^2}; for the reduced pair the
+ * energy test function is c^2 on phi and 1 on psi, and P multiplies both.
+ * ------------------------------------------------------------------------ */
+int32_t oc_fixup(const oc_grid *g, double rho, const double *u, double T, double *gv, double *coef)
+{
+    int32_t nv = oc_nv(g);
+    int nb = g->vdim + 2;
+    double A[25] = {0}, b[5] = {0};
+    double xi[3], w;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c[3] = {0, 0, 0}, c2 = 0;
+        for (int d = 0; d < g->vdim; ++d) { c[d] = xi[d] - u[d]; c2 += c[d] * c[d]; }
+        double p[5];
+        p[0] = 1.0;
+        for (int d = 0; d < g->vdim; ++d) p[1 + d] = c[d];
+        p[nb - 1] = c2;
+        double gf = gv[k];
+        double gp = (g->vdim == 2) ? gv[nv + k] : 0.0;
+        for (int a = 0; a < nb; ++a) {
+            /* test function a applied to (g_phi, g_psi) */
+            double t = p[a] * gf;
+            if (a == nb - 1) t += gp;   /* energy: c^2 phi + psi */
+            for (int bb = 0; bb < nb; ++bb) A[a * nb + bb] += w * t * p[bb];
+        }
+    }
+    b[0] = rho;
+    b[nb - 1] = 1.5 * rho * T;
+    if (solve_small(nb, A, b) != 0) return -1;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c2 = 0, P = b[0];
+        for (int d = 0; d < g->vdim; ++d) {
+            double c = xi[d] - u[d];
+            c2 += c * c;
+            P += b[1 + d] * c;
+        }
+        P += b[nb - 1] * c2;
+        gv[k] *= P;
+        if (g->vdim == 2) gv[nv + k] *= P;
+    }
+    if (coef)
+        for (int a = 0; a < nb; ++a) coef[a] = b[a];
+    return 0;
+}
+
+int32_t oc_equilibrium(const oc_grid *g, const oc_gas *gas, const double *mom, double *out)
+{
+    oc_shakhov(g, gas->Pr, mom, out);
+    return oc_fixup(g, mom[0], mom + 1, mom[4], out, NULL);
+}
+
+int32_t oc_feq(const oc_grid *g, const double *W5, double *out)
+{
+    oc_maxwellian(g, W5[0], W5 + 1, W5[4], out);
+    return oc_fixup(g, W5[0], W5 + 1, W5[4], out, NULL);
+}
+
+/* ------------------------------------------------------------------------
+ * Grad-type distribution (Sec. 3.2, eq. G13_VDF), scaled units:
+ *   f = M [1 + sigma:cc / (p T) + (2 q.c / (p T)) (2 c^2 / (5 T) - 1)].
+ * Reduced pair (sigma_xz = sigma_yz = q_z = u_z = 0):
+ *   phi: M2 [1 + (s2:cc + sigma_zz T/2)/(pT) + (2q.c/(pT))(2c^2/(5T) - 4/5)]
+ *   psi: (T/2) M2 [1 + (s2:cc + 3 T sigma_zz / 2)/(pT) + (2q.c/(pT))(2c^2/(5T) - 2/5)]
+ * ------------------------------------------------------------------------ */
+void oc_g13(const oc_grid *g, const double *mom, double *out)
+{
+    int32_t nv = oc_nv(g);
+    double rho = mom[0], T = mom[4], p = rho * T;
+    const double *u = mom + 1, *s = mom + 5, *q = mom + 11;
+    double xi[3], w;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c[3] = {0, 0, 0}, c2 = 0, qc = 0;
+        for (int d = 0; d < g->vdim; ++d) {
+            c[d] = xi[d] - u[d];
+            c2 += c[d] * c[d];
+            qc += q[d] * c[d];
+        }
+        double scc = s[0] * c[0] * c[0] + s[1] * c[1] * c[1] + s[2] * c[2] * c[2]
+                   + 2.0 * (s[3] * c[0] * c[1] + s[4] * c[0] * c[2] + s[5] * c[1] * c[2]);
+        if (g->vdim == 3) {
+            double M = rho * pow(PI * T, -1.5) * exp(-c2 / T);
+            out[k] = M * (1.0 + scc / (p * T) + 2.0 * qc / (p * T) * (0.4 * c2 / T - 1.0));
+        } else {
+            double M = rho / (PI * T) * exp(-c2 / T);
+            out[k] = M * (1.0 + (scc + 0.5 * T * s[2]) / (p * T)
+                          + 2.0 * qc / (p * T) * (0.4 * c2 / T - 0.8));
+            out[nv + k] = 0.5 * T * M * (1.0 + (scc + 1.5 * T * s[2]) / (p * T)
+                                         + 2.0 * qc / (p * T) * (0.4 * c2 / T - 0.4));
+        }
+    }
+}
+
+/* tau = mu / p_t with mu = mu(T0) (T/T0)^omega and the Kn definition of
+ * Sec. 2: tau = (2 Kn / sqrt(pi)) T^(omega - 1) / rho in scaled units. */
+double oc_tau(const oc_gas *gas, double rho, double T)
+{
+    return 2.0 * gas->Kn / sqrt(PI) * pow(T, gas->omega - 1.0) / rho;
+}
+
+/* cell -> face adjacency (CSR) */
+static void build_adjacency(const oc_mesh *m, int32_t **ptr_out, int32_t **idx_out)
+{
+    int32_t *cnt = (int32_t *)calloc((size_t)m->n_cells + 1, sizeof(int32_t));
+    for (int32_t f = 0; f < m->n_faces; ++f) {
+        cnt[m->face_cells[2 * f] + 1]++;
+        if (m->face_cells[2 * f + 1] >= 0) cnt[m->face_cells[2 * f + 1] + 1]++;
+    }
+    for (int32_t i = 0; i < m->n_cells; ++i) cnt[i + 1] += cnt[i];
+    int32_t *idx = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cnt[m->n_cells] > 0 ? cnt[m->n_cells] : 1));
+    int32_t *pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m->n_cells > 0 ? m->n_cells : 1));
+    for (int32_t i = 0; i < m->n_cells; ++i) pos[i] = cnt[i];
+    for (int32_t f = 0; f < m->n_faces; ++f) {
+        idx[pos[m->face_cells[2 * f]]++] = f;
+        if (m->face_cells[2 * f + 1] >= 0) idx[pos[m->face_cells[2 * f + 1]]++] = f;
+    }
+    free(pos);
+    *ptr_out = cnt;
+    *idx_out = idx;
+}
+
+/* ------------------------------------------------------------------------
+ * Kinetic update of Sec. 3.1 (the discretised kinetic equation before
+ * eq. updatef), first-order upwind face values, point-Jacobi lagging of the
+ * neighbour values (readings: upwind by the sign of xi.n; neighbours and the
+ * reference distribution at iterate n):
+ *
+ *   f_i^{n+1/2} = ( f_i^n/dt + g_i^n/tau_i^n + sum_{a<0} |a| f_j^n )
+ *               / ( 1/dt + 1/tau_i^n + sum_{a>0} a ),   a = (xi.n) S / V.
+ *
+ * Upwind values: kinetic neighbour -> its f^n; NS neighbour -> Grad-13 of
+ * its state (Sec. 3.2); diffuse wall -> rho_w M(u_w, T_w) with rho_w from a
+ * zero discrete mass flux of f_i^n; far field -> M(rho, u, T) of the patch.
+ * ------------------------------------------------------------------------ */
+static double wall_density(const oc_grid *g, const double *fcell, const double *n,
+                           const double *uw, double Tw, double *Mw)
+{
+    /* Mw receives M(1, uw, Tw) at the nodes */
+    int32_t nv = oc_nv(g);
+    oc_maxwellian(g, 1.0, uw, Tw, Mw);
+    double out = 0, in = 0, xi[3], w;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double xn = xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2];
+        if (xn > 0) out += w * xn * fcell[k];
+        else if (xn < 0) in += w * (-xn) * Mw[k];
+    }
+    return out / in;
+}
+
+/* Upwind source rows for the faces of kinetic cell i, all at iterate n:
+ * srcp[l] points at the values on the far side of local face l; nrm[4l..]
+ * holds the outward unit normal and S/V.  `scratch` has room for nf rows. */
+static void face_sources(const oc_mesh *m, const oc_grid *g, const int32_t *cptr, const int32_t *cidx,
+                         int32_t i, const int32_t *slot_of_cell, const double *f_old, const double *ghost,
+                         const double *fi, double *scratch, double *nrm, const double **srcp)
+{
+    size_t row = (size_t)oc_nfun(g) * oc_nv(g);
+    int32_t nf = cptr[i + 1] - cptr[i];
+    for (int32_t l = 0; l < nf; ++l) {
+        int32_t f = cidx[cptr[i] + l];
+        int32_t own = m->face_cells[2 * f], oth = m->face_cells[2 * f + 1];
+        double sgn = (own == i) ? 1.0 : -1.0;
+        int32_t nb = (own == i) ? oth : own;
+        for (int d = 0; d < 3; ++d) nrm[4 * l + d] = sgn * m->face_normal[3 * f + d];
+        nrm[4 * l + 3] = m->face_area[f] / m->cell_volume[i];
+        double *s = scratch + (size_t)l * row;
+        if (nb >= 0) {
+            if (slot_of_cell[nb] >= 0) {
+                srcp[l] = f_old + (size_t)slot_of_cell[nb] * row;
+            } else {
+                oc_g13(g, ghost + (size_t)nb * OC_NMOM, s);
+                srcp[l] = s;
+            }
+        } else {
+            int32_t p = -1 - nb;
+            const double *ps = m->patch_state + 5 * p;
+            if (m->patch_kind[p] == OC_WALL) {
+                double rw = wall_density(g, fi, nrm + 4 * l, ps + 1, ps[4], s);
+                for (size_t k = 0; k < row; ++k) s[k] *= rw;
+            } else {
+                oc_maxwellian(g, ps[0], ps + 1, ps[4], s);
+            }
+            srcp[l] = s;
+        }
+    }
+}
+
+int32_t oc_sweep(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                 int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                 const double *f_old, const double *ghost, double *f_new)
+{
+    int32_t nv = oc_nv(g), nfun = oc_nfun(g);
+    size_t row = (size_t)nfun * nv;
+    int32_t *cptr, *cidx;
+    build_adjacency(m, &cptr, &cidx);
+    int32_t err = 0;
+
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : err)
+    for (int32_t t = 0; t < n_kin; ++t) {
+        int32_t i = kin_cell[t];
+        const double *fi = f_old + (size_t)slot_of_cell[i] * row;
+        double *fo = f_new + (size_t)slot_of_cell[i] * row;
+        int32_t nf = cptr[i + 1] - cptr[i];
+        double mom[OC_NMOM];
+        oc_moments(g, fi, mom);
+        double tau = oc_tau(gas, mom[0], mom[4]);
+        double *geq = (double *)malloc(sizeof(double) * row);
+        double *src = (double *)malloc(sizeof(double) * row * (size_t)(nf > 0 ? nf : 1));
+        double *nrm = (double *)malloc(sizeof(double) * 4 * (size_t)(nf > 0 ? nf : 1));
+        const double **srcp = (const double **)malloc(sizeof(double *) * (size_t)(nf > 0 ? nf : 1));
+        if (oc_equilibrium(g, gas, mom, geq) != 0) err = -7;
+        face_sources(m, g, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, src, nrm, srcp);
+        double xi[3], w;
+        for (int32_t k = 0; k < nv; ++k) {
+            node(g, k, xi, &w);
+            double den = gas->inv_dt + 1.0 / tau;
+            double num[2];
+            for (int32_t q = 0; q < nfun; ++q) num[q] = gas->inv_dt * fi[q * nv + k] + geq[q * nv + k] / tau;
+            for (int32_t l = 0; l < nf; ++l) {
+                double a = (xi[0] * nrm[4 * l] + xi[1] * nrm[4 * l + 1] + xi[2] * nrm[4 * l + 2]) * nrm[4 * l + 3];
+                if (a > 0) den += a;
+                else if (a < 0)
+                    for (int32_t q = 0; q < nfun; ++q) num[q] += -a * srcp[l][q * nv + k];
+            }
+            for (int32_t q = 0; q < nfun; ++q) fo[q * nv + k] = num[q] / den;
+        }
+        free(geq); free(src); free(nrm); free(srcp);
+    }
+    free(cptr);
+    free(cidx);
+    return err;
+}
+
+/* ------------------------------------------------------------------------
+ * Moment balance of the kinetic scheme at iterate n (the flux part of the
+ * discretised kinetic equation of Sec. 3.1, summed against 1, xi, xi^2; the
+ * relaxation term drops out because it conserves these moments):
+ *   R_i = -sum_faces (S/V) sum_k w_k (xi_k.n) psi_k f_up,k
+ * with the same upwind values as the sweep.  R[n_cells][5] = (mass,
+ * momentum, energy) per unit volume; rows of non-kinetic cells are zero.
+ * ------------------------------------------------------------------------ */
+int32_t oc_kinetic_residual(const oc_mesh *m, const oc_grid *g,
+                            int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                            const double *f_old, const double *ghost, double *R)
+{
+    int32_t nv = oc_nv(g), nfun = oc_nfun(g);
+    size_t row = (size_t)nfun * nv;
+    int32_t *cptr, *cidx;
+    build_adjacency(m, &cptr, &cidx);
+    memset(R, 0, sizeof(double) * 5 * (size_t)m->n_cells);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t t = 0; t < n_kin; ++t) {
+        int32_t i = kin_cell[t];
+        const double *fi = f_old + (size_t)slot_of_cell[i] * row;
+        int32_t nf = cptr[i + 1] - cptr[i];
+        double *src = (double *)malloc(sizeof(double) * row * (size_t)(nf > 0 ? nf : 1));
+        double *nrm = (double *)malloc(sizeof(double) * 4 * (size_t)(nf > 0 ? nf : 1));
+        const double **srcp = (const double **)malloc(sizeof(double *) * (size_t)(nf > 0 ? nf : 1));
+        face_sources(m, g, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, src, nrm, srcp);
+        double acc[5] = {0, 0, 0, 0, 0}, xi[3], w;
+        for (int32_t l = 0; l < nf; ++l) {
+            for (int32_t k = 0; k < nv; ++k) {
+                node(g, k, xi, &w);
+                double a = (xi[0] * nrm[4 * l] + xi[1] * nrm[4 * l + 1] + xi[2] * nrm[4 * l + 2]) * nrm[4 * l + 3];
+                const double *up = (a > 0) ? fi : srcp[l];
+                double fphi = up[k];
+                double fpsi = (nfun == 2) ? up[nv + k] : 0.0;
+                double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+                acc[0] -= w * a * fphi;
+                for (int d = 0; d < 3; ++d) acc[1 + d] -= w * a * xi[d] * fphi;
+                acc[4] -= w * a * (x2 * fphi + fpsi);
+            }
+        }
+        for (int c = 0; c < 5; ++c) R[5 * i + c] = acc[c];
+        free(src); free(nrm); free(srcp);
+    }
+    free(cptr);
+    free(cidx);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Least-squares gradients (Sec. 3.4 Step 2).  Reading: neighbours are the
+ * cells across each face, weights 1/|dx|^2; a boundary face contributes the
+ * patch value at the face centre (NaN entries: no contribution).  Only the
+ * first `dim` components are solved; the rest are zero.
+ * ------------------------------------------------------------------------ */
+void oc_lsq_gradients(const oc_mesh *m, int32_t nvar, const double *phi, const double *bnd, double *grad)
+{
+    int32_t *cptr, *cidx;
+    build_adjacency(m, &cptr, &cidx);
+    int dim = m->dim;
+    for (int32_t i = 0; i < m->n_cells; ++i) {
+        for (int32_t v = 0; v < nvar; ++v) {
+            double A[9] = {0}, b[3] = {0};
+            for (int32_t l = cptr[i]; l < cptr[i + 1]; ++l) {
+                int32_t f = cidx[l];
+                int32_t own = m->face_cells[2 * f], oth = m->face_cells[2 * f + 1];
+                int32_t nb = (own == i) ? oth : own;
+                double dx[3], dphi;
+                if (nb >= 0) {
+                    for (int d = 0; d < 3; ++d) dx[d] = m->cell_center[3 * nb + d] - m->cell_center[3 * i + d];
+                    dphi = phi[(size_t)nb * nvar + v] - phi[(size_t)i * nvar + v];
+                } else {
+                    double bv = bnd[(size_t)(-1 - nb) * nvar + v];
+                    if (isnan(bv)) continue;
+                    for (int d = 0; d < 3; ++d) dx[d] = m->face_center[3 * f + d] - m->cell_center[3 * i + d];
+                    dphi = bv - phi[(size_t)i * nvar + v];
+                }
+                double r2 = 0;
+                for (int d = 0; d < dim; ++d) r2 += dx[d] * dx[d];
+                double wgt = 1.0 / r2;
+                for (int a = 0; a < dim; ++a) {
+                    for (int c = 0; c < dim; ++c) A[a * dim + c] += wgt * dx[a] * dx[c];
+                    b[a] += wgt * dx[a] * dphi;
+                }
+            }
+            double *gout = grad + ((size_t)i * nvar + v) * 3;
+            gout[0] = gout[1] = gout[2] = 0.0;
+            if (solve_small(dim, A, b) == 0)
+                for (int d = 0; d < dim; ++d) gout[d] = b[d];
+        }
+    }
+    free(cptr);
+    free(cidx);
+}
+
+/* ------------------------------------------------------------------------
+ * Newton and Fourier laws (Sec. 2, eq. NSF_constitutive) with the
+ * conductivity of eq. mu_kappa for d_r = 0 (kappa = (mu R / 2) 5 / A_tt),
+ * scaled: sigma = -(2 Kn/sqrt(pi)) mu (grad u + grad u^T - (2/3) div u I),
+ *         q = -(5 Kn / (2 sqrt(pi) Pr)) mu grad T,   mu = T^omega.
+ * grad_u[3*i + j] = d u_i / d x_j.
+ * ------------------------------------------------------------------------ */
+void oc_nsf(const oc_gas *gas, double T, const double *grad_u, const double *grad_T,
+            double *sigma6, double *q3)
+{
+    double mu = pow(T, gas->omega);
+    double cs = -2.0 * gas->Kn / sqrt(PI) * mu;
+    double cq = -5.0 * gas->Kn / (2.0 * sqrt(PI) * gas->Pr) * mu;
+    double div = grad_u[0] + grad_u[4] + grad_u[8];
+    sigma6[0] = cs * (2.0 * grad_u[0] - 2.0 / 3.0 * div);
+    sigma6[1] = cs * (2.0 * grad_u[4] - 2.0 / 3.0 * div);
+    sigma6[2] = cs * (2.0 * grad_u[8] - 2.0 / 3.0 * div);
+    sigma6[3] = cs * (grad_u[1] + grad_u[3]);
+    sigma6[4] = cs * (grad_u[2] + grad_u[6]);
+    sigma6[5] = cs * (grad_u[5] + grad_u[7]);
+    for (int d = 0; d < 3; ++d) q3[d] = cq * grad_T[d];
+}
+
+/* ------------------------------------------------------------------------
+ * Synthetic macroscopic equations (Sec. 2 eq. macroscopic_equation_2 with
+ * the constitutive relations of eq. full_constitutive, discretised as in
+ * eq. macro).  The paper defers F and Q to another work; this is the
+ * reading used on both sides:
+ *   conserved U = (rho, rho u, E = rho |u|^2 + 1.5 rho T), fluxes
+ *   F.n = [rho u_n, rho u u_n + (p n + sigma.n)/2, (E + p) u_n + (sigma.n).u + q.n]
+ *   convective part: kinetic flux-vector splitting, the xi.n > 0 half-range
+ *   moments of the owner's Maxwellian plus the xi.n < 0 half of the other
+ *   side's (the first-order upwinding of the kinetic sweep applied to the
+ *   local equilibria, so both solvers carry the same numerical dissipation);
+ *   viscous part: face gradients = mean of the two LSQ cell gradients with the
+ *   centroid-difference correction; sigma_f, q_f = NSF at T_f plus the mean
+ *   of the two cells' high-order terms (zero on NS cells);
+ *   far field: the same splitting against the patch state, no viscous flux;
+ *   diffuse wall: the same splitting, outgoing half of the owner's Maxwellian
+ *   plus rho_w M(u_w, T_w) on the incoming half with zero net mass flux (a
+ *   slip condition whose slip length follows the mean free path), no
+ *   separate viscous wall term;
+ *   source: an optional frozen per-cell term (the GSIS driver puts there the
+ *   difference between the kinetic scheme's moment balance and this
+ *   residual, both at iterate n, on kinetic cells);
+ *   explicit update with local step dt_i = cfl V_i / sum_f S_f (|u_n| + a + 2 nu / d_f)
+ *   (cfl < 0: one global step, the minimum over cells of |cfl| V_i / sum ...),
+ *   nu = max(4/3, 5/(3 Pr)) Kn T^omega / (sqrt(pi) rho).
+ * ------------------------------------------------------------------------ */
+static void prim_from_cons(const double *U, double *P)
+{
+    double rho = U[0];
+    P[0] = rho;
+    double u2 = 0;
+    for (int d = 0; d < 3; ++d) { P[1 + d] = U[1 + d] / rho; u2 += P[1 + d] * P[1 + d]; }
+    P[4] = (U[4] - rho * u2) / (1.5 * rho);
+}
+
+static void cons_from_prim(const double *P, double *U)
+{
+    double u2 = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    U[0] = P[0];
+    for (int d = 0; d < 3; ++d) U[1 + d] = P[0] * P[1 + d];
+    U[4] = P[0] * u2 + 1.5 * P[0] * P[4];
+}
+
+/* Half-range flux of a Maxwellian (kinetic flux-vector splitting): the
+ * moments {1, xi, xi^2} x (xi.n) of M(rho, u, T) over xi.n > 0 (sgn = +1) or
+ * xi.n < 0 (sgn = -1), in closed form with erf:
+ *   <1> = (1 + sgn erf(s))/2 = A, B = sgn exp(-s^2)/(2 sqrt(pi)), s = u_n/sqrt(T)
+ *   <xi_n>   = u_n A + sqrt(T) B
+ *   <xi_n^2> = (u_n^2 + T/2) A + u_n sqrt(T) B
+ *   <xi_n^3> = (u_n^3 + 3 u_n T/2) A + (u_n^2 + T) sqrt(T) B
+ * mass = rho <xi_n>, momentum = rho (u_t <xi_n> + n <xi_n^2>),
+ * energy = rho (<xi_n^3> + (|u_t|^2 + T) <xi_n>). */
+static void half_flux(const double *P, const double *n, double sgn, double *F)
+{
+    double rho = P[0], T = P[4], sT = sqrt(T);
+    double un = P[1] * n[0] + P[2] * n[1] + P[3] * n[2];
+    double ut[3] = {P[1] - un * n[0], P[2] - un * n[1], P[3] - un * n[2]};
+    double ut2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    double s = un / sT;
+    double A = 0.5 * (1.0 + sgn * erf(s));
+    double B = sgn * exp(-s * s) / (2.0 * sqrt(PI));
+    double m1 = un * A + sT * B;
+    double m2 = (un * un + 0.5 * T) * A + un * sT * B;
+    double m3 = (un * un * un + 1.5 * un * T) * A + (un * un + T) * sT * B;
+    F[0] = rho * m1;
+    for (int d = 0; d < 3; ++d) F[1 + d] = rho * (ut[d] * m1 + n[d] * m2);
+    F[4] = rho * (m3 + (ut2 + T) * m1);
+}
+
+/* Residual R_i = -sum_f F_f.n S_f (not divided by V_i) at primitive state W,
+ * and the local-step denominators D_i = sum_f S_f (|u_n| + a + 2 nu / d_f).
+ * Returns -7 if a density or temperature is not positive. */
+static int32_t macro_residual(const oc_mesh *m, const oc_gas *gas,
+                              const double *hot, const double *W,
+                              double *R, double *D, double *pv, double *gr, const double *bv)
+{
+    int32_t nc = m->n_cells, nfc = m->n_faces;
+    const double gam = 5.0 / 3.0;
+    for (int32_t i = 0; i < nc; ++i) {
+        if (!(W[5 * i] > 0) || !(W[5 * i + 4] > 0)) return -7;
+        for (int c = 0; c < 4; ++c) pv[4 * i + c] = W[5 * i + 1 + c];
+    }
+    oc_lsq_gradients(m, 4, pv, bv, gr);
+    memset(R, 0, sizeof(double) * 5 * (size_t)nc);
+    memset(D, 0, sizeof(double) * (size_t)nc);
+    for (int32_t f = 0; f < nfc; ++f) {
+        int32_t L = m->face_cells[2 * f], Rc = m->face_cells[2 * f + 1];
+        const double *n = m->face_normal + 3 * f;
+        double S = m->face_area[f];
+        const double *PL = W + 5 * L;
+        double F[5] = {0, 0, 0, 0, 0};
+        double aL = sqrt(gam * PL[4] / 2.0);
+        double unL = PL[1] * n[0] + PL[2] * n[1] + PL[3] * n[2];
+        double dL, dR = 0;
+        int kindB = -1;
+        const double *PR = NULL;
+        double Pfar[5];
+        if (Rc >= 0) {
+            PR = W + 5 * Rc;
+        } else {
+            int32_t p = -1 - Rc;
+            kindB = m->patch_kind[p];
+            if (kindB == OC_FAR) {
+                for (int c = 0; c < 5; ++c) Pfar[c] = m->patch_state[5 * p + c];
+                PR = Pfar;
+            }
+        }
+        if (PR) {
+            /* convective flux: forward half of M(W_L) + backward half of M(W_R) */
+            double FL[5], FR[5];
+            half_flux(PL, n, 1.0, FL);
+            half_flux(PR, n, -1.0, FR);
+            for (int c = 0; c < 5; ++c) F[c] = FL[c] + FR[c];
+        }
+        if (Rc >= 0) {
+            /* viscous flux on an interior face */
+            double e[3], dd = 0;
+            for (int d = 0; d < 3; ++d) { e[d] = m->cell_center[3 * Rc + d] - m->cell_center[3 * L + d]; dd += e[d] * e[d]; }
+            dd = sqrt(dd);
+            for (int d = 0; d < 3; ++d) e[d] /= dd;
+            double G[4][3];
+            for (int v = 0; v < 4; ++v) {
+                double ge = 0;
+                for (int d = 0; d < 3; ++d) { G[v][d] = 0.5 * (gr[12 * L + 3 * v + d] + gr[12 * Rc + 3 * v + d]); ge += G[v][d] * e[d]; }
+                double jump = (pv[4 * Rc + v] - pv[4 * L + v]) / dd;
+                for (int d = 0; d < 3; ++d) G[v][d] += (jump - ge) * e[d];
+            }
+            double Tf = 0.5 * (PL[4] + PR[4]);
+            double gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+            double sg[6], q[3];
+            oc_nsf(gas, Tf, gu, G[3], sg, q);
+            for (int c = 0; c < 6; ++c) sg[c] += 0.5 * (hot[9 * L + c] + hot[9 * Rc + c]);
+            for (int c = 0; c < 3; ++c) q[c] += 0.5 * (hot[9 * L + 6 + c] + hot[9 * Rc + 6 + c]);
+            double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2],
+                            sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                            sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+            double uf[3] = {0.5 * (PL[1] + PR[1]), 0.5 * (PL[2] + PR[2]), 0.5 * (PL[3] + PR[3])};
+            for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
+            F[4] += sn[0] * uf[0] + sn[1] * uf[1] + sn[2] * uf[2] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+            dL = dd; dR = dd;
+        } else if (kindB == OC_WALL) {
+            /* diffuse wall: outgoing half of M(W_L) plus rho_w M(u_w, T_w) on the
+             * incoming half, rho_w from zero net mass flux */
+            const double *ps = m->patch_state + 5 * (-1 - Rc);
+            double dn = 0;
+            for (int d = 0; d < 3; ++d) dn += (m->face_center[3 * f + d] - m->cell_center[3 * L + d]) * n[d];
+            dL = 2.0 * dn;
+            double Pw[5] = {1.0, ps[1], ps[2], ps[3], ps[4]}, Fo[5], Fi[5];
+            half_flux(PL, n, 1.0, Fo);
+            half_flux(Pw, n, -1.0, Fi);
+            double rw = -Fo[0] / Fi[0];
+            for (int c = 0; c < 5; ++c) F[c] = Fo[c] + rw * Fi[c];
+        } else {
+            double dn = 0;
+            for (int d = 0; d < 3; ++d) dn += (m->face_center[3 * f + d] - m->cell_center[3 * L + d]) * n[d];
+            dL = 2.0 * dn;
+        }
+        for (int c = 0; c < 5; ++c) R[5 * L + c] -= F[c] * S;
+        if (Rc >= 0)
+            for (int c = 0; c < 5; ++c) R[5 * Rc + c] += F[c] * S;
+        /* spectral radii for the local step */
+        double nuL = fmax(4.0 / 3.0, 5.0 / (3.0 * gas->Pr)) * gas->Kn * pow(PL[4], gas->omega) / (sqrt(PI) * PL[0]);
+        D[L] += S * (fabs(unL) + aL + 2.0 * nuL / dL);
+        if (Rc >= 0) {
+            double aR = sqrt(gam * PR[4] / 2.0);
+            double unR = PR[1] * n[0] + PR[2] * n[1] + PR[3] * n[2];
+            double nuR = fmax(4.0 / 3.0, 5.0 / (3.0 * gas->Pr)) * gas->Kn * pow(PR[4], gas->omega) / (sqrt(PI) * PR[0]);
+            D[Rc] += S * (fabs(unR) + aR + 2.0 * nuR / dR);
+        }
+    }
+    return 0;
+}
+
+int32_t oc_macro_residual(const oc_mesh *m, const oc_gas *gas, const double *hot,
+                          const double *W, double *Rv)
+{
+    int32_t nc = m->n_cells;
+    double *D = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *pv = (double *)malloc(sizeof(double) * 4 * (size_t)nc);
+    double *gr = (double *)malloc(sizeof(double) * 12 * (size_t)nc);
+    double *bv = (double *)malloc(sizeof(double) * 4 * (size_t)(m->n_patches > 0 ? m->n_patches : 1));
+    for (int32_t p = 0; p < m->n_patches; ++p)
+        for (int c = 0; c < 4; ++c) bv[4 * p + c] = m->patch_state[5 * p + 1 + c];
+    int32_t st = macro_residual(m, gas, hot, W, Rv, D, pv, gr, bv);
+    if (st == 0)
+        for (int32_t i = 0; i < nc; ++i)
+            for (int c = 0; c < 5; ++c) Rv[5 * i + c] /= m->cell_volume[i];
+    free(D); free(pv); free(gr); free(bv);
+    return st;
+}
+
+int32_t oc_macro(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *src,
+                 int32_t n_inner, double cfl, double *W)
+{
+    int32_t nc = m->n_cells;
+    double *U = (double *)malloc(sizeof(double) * 5 * (size_t)nc);
+    double *R = (double *)malloc(sizeof(double) * 5 * (size_t)nc);
+    double *D = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *pv = (double *)malloc(sizeof(double) * 4 * (size_t)nc);
+    double *gr = (double *)malloc(sizeof(double) * 12 * (size_t)nc);
+    double *bv = (double *)malloc(sizeof(double) * 4 * (size_t)(m->n_patches > 0 ? m->n_patches : 1));
+    for (int32_t p = 0; p < m->n_patches; ++p)
+        for (int c = 0; c < 4; ++c) bv[4 * p + c] = m->patch_state[5 * p + 1 + c];
+    for (int32_t i = 0; i < nc; ++i) cons_from_prim(W + 5 * i, U + 5 * i);
+    int32_t status = 0;
+    for (int32_t it = 0; it < n_inner && status == 0; ++it) {
+        status = macro_residual(m, gas, hot, W, R, D, pv, gr, bv);
+        if (status) break;
+        if (src)
+            for (int32_t i = 0; i < nc; ++i)
+                for (int c = 0; c < 5; ++c) R[5 * i + c] += src[5 * i + c] * m->cell_volume[i];
+        /* R_i is not yet divided by V_i.  Local step: dt_i / V_i = cfl / D_i.
+         * cfl < 0 selects one global step dt = |cfl| min_i V_i / D_i, which
+         * conserves sum_i V_i U_i exactly. */
+        double gdt = INFINITY;
+        if (cfl < 0)
+            for (int32_t i = 0; i < nc; ++i) gdt = fmin(gdt, -cfl * m->cell_volume[i] / D[i]);
+        for (int32_t i = 0; i < nc; ++i) {
+            double k = (cfl < 0) ? gdt / m->cell_volume[i] : cfl / D[i];
+            for (int c = 0; c < 5; ++c) U[5 * i + c] += k * R[5 * i + c];
+        }
+        for (int32_t i = 0; i < nc; ++i) prim_from_cons(U + 5 * i, W + 5 * i);
+    }
+    for (int32_t i = 0; i < nc && status == 0; ++i)
+        if (!(W[5 * i] > 0) || !(W[5 * i + 4] > 0)) status = -7;
+    free(U); free(R); free(D); free(pv); free(gr); free(bv);
+    return status;
+}

@@ -1,0 +1,136 @@
+/*
+ * gsis_oracle.h -- plain FP64 CPU oracle for the adaptive GSIS kinetic sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this code; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code with the HIP library.
+ *
+ * Every function is the slow, obviously-correct form of one step of the
+ * method of Zhang, Zeng & Wu, "Adaptive GSIS for rarefied gas flow
+ * simulations" (arXiv 2501.02245), written in the dimensionless units
+ *   x / L,  xi / v_m (v_m = sqrt(2 R T0)),  T / T0,  rho / rho0,
+ *   p, sigma / (rho0 R T0),  q / (rho0 R T0 v_m),  f / (rho0 / v_m^3),
+ * so that R T -> T/2 and the Maxwellian is rho (pi T)^(-3/2) exp(-c^2/T).
+ *
+ * Monatomic specialisation of the two-VDF kinetic model (d_r = 0): the
+ * reference distribution reduces to the Shakhov form with Prandtl number
+ * Pr = A_tt (Sec. 2, reference distributions and heat-flux mixing).
+ *
+ * Velocity grids are tensor products.  vdim = 3 stores one function per
+ * cell, index k = (ix*ny + iy)*nz + iz.  vdim = 2 stores the reduced pair
+ * (phi, psi) = (int f dxi_z, int xi_z^2 f dxi_z) per cell, index
+ * k = ix*ny + iy, layout [fun][k].
+ *
+ * Moment vector (NMOM = 14): rho, ux, uy, uz, T, sxx, syy, szz, sxy, sxz,
+ * syz, qx, qy, qz.
+ */
+#ifndef GSIS_ORACLE_H
+#define GSIS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OC_NMOM 14
+#define OC_WALL 0
+#define OC_FAR 1
+
+typedef struct {
+    int32_t dim, n_cells, n_faces, n_patches;
+    const int32_t *face_cells;   /* [n_faces][2] owner, other (<0: patch -1-p) */
+    const double *face_normal;   /* [n_faces][3] unit, owner -> other */
+    const double *face_area;     /* [n_faces] */
+    const double *face_center;   /* [n_faces][3] */
+    const double *cell_volume;   /* [n_cells] */
+    const double *cell_center;   /* [n_cells][3] */
+    const int32_t *patch_kind;   /* [n_patches] OC_WALL | OC_FAR */
+    const double *patch_state;   /* [n_patches][5] rho, ux, uy, uz, T */
+} oc_mesh;
+
+typedef struct {
+    int32_t vdim;                /* 2 (reduced) or 3 */
+    int32_t n[3];                /* nodes per axis (n[2] ignored for vdim 2) */
+    const double *x[3];
+    const double *w[3];
+} oc_grid;
+
+typedef struct {
+    double Kn;      /* reference Knudsen number (Sec. 2, definition of Kn) */
+    double omega;   /* viscosity index, mu ~ T^omega */
+    double Pr;      /* A_tt of the monatomic gas = Prandtl number */
+    double inv_dt;  /* 1/dt of the kinetic update; 0 = steady iteration */
+} oc_gas;
+
+int32_t oc_nv(const oc_grid *g);
+int32_t oc_nfun(const oc_grid *g);
+
+/* Moments of one cell's distribution(s) f[nfun][nv] -> mom[OC_NMOM]. */
+void oc_moments(const oc_grid *g, const double *f, double *mom);
+
+/* Discrete Maxwellian M(rho, u, T) at the nodes -> out[nfun][nv]. */
+void oc_maxwellian(const oc_grid *g, double rho, const double *u, double T, double *out);
+
+/* Shakhov reference distribution built from moments (rho, u, T, q). */
+void oc_shakhov(const oc_grid *g, double Pr, const double *mom, double *out);
+
+/* Multiply g by (a0 + a.c + b c^2), c = xi - u, so that its discrete mass,
+ * momentum and energy equal those of a gas at (rho, u, T).  Returns 0, or -1
+ * if the linear system is singular. coef (nullable) receives a0, a[vdim], b. */
+int32_t oc_fixup(const oc_grid *g, double rho, const double *u, double T, double *gv, double *coef);
+
+/* Conservation-fixed Shakhov target of the relaxation term, from moments. */
+int32_t oc_equilibrium(const oc_grid *g, const oc_gas *gas, const double *mom, double *out);
+
+/* Conservation-fixed Maxwellian whose discrete (rho, rho u, E) equal W. */
+int32_t oc_feq(const oc_grid *g, const double *W5, double *out);
+
+/* Grad-13 type distribution from (rho, u, T, sigma[6], q[3]). */
+void oc_g13(const oc_grid *g, const double *mom, double *out);
+
+/* Mean collision time tau = mu / p in scaled units. */
+double oc_tau(const oc_gas *gas, double rho, double T);
+
+/* One point-Jacobi sweep of the implicit kinetic update over the kinetic
+ * cells.  f_old/f_new: [n_slots][nfun][nv] addressed by slot_of_cell.
+ * ghost: [n_cells][OC_NMOM] Grad-13 parameters used for NS neighbours.
+ * Returns 0 or a negative error. */
+int32_t oc_sweep(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                 int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                 const double *f_old, const double *ghost, double *f_new);
+
+/* Moment balance of the kinetic scheme at f (per unit volume): R[n_cells][5]
+ * = -sum_faces (S/V) sum_k w (xi.n) (1, xi, |xi|^2) f_upwind; zero rows for
+ * non-kinetic cells. */
+int32_t oc_kinetic_residual(const oc_mesh *m, const oc_grid *g,
+                            int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                            const double *f_old, const double *ghost, double *R);
+
+/* Least-squares cell gradients of nvar fields phi[n_cells][nvar];
+ * bnd[n_patches][nvar] holds boundary values (NaN = use the cell value).
+ * grad[n_cells][nvar][3]. */
+void oc_lsq_gradients(const oc_mesh *m, int32_t nvar, const double *phi, const double *bnd, double *grad);
+
+/* NSF stress and heat flux from gradients of u (3x3, row = component) and T. */
+void oc_nsf(const oc_gas *gas, double T, const double *grad_u, const double *grad_T,
+            double *sigma6, double *q3);
+
+/* Residual of the synthetic macroscopic equations at primitive W, per unit
+ * volume: Rv[n_cells][5] = -(1/V) sum_f F.n S (no source term). */
+int32_t oc_macro_residual(const oc_mesh *m, const oc_gas *gas, const double *hot,
+                          const double *W, double *Rv);
+
+/* N_inner explicit pseudo-time iterations of the synthetic macroscopic
+ * equations (NSF + high-order terms) with an optional frozen source
+ * src[n_cells][5] (per unit volume, nullable).  W[n_cells][5] primitive
+ * (rho, u, T) in/out; hot[n_cells][9] (sigma 6, q 3, zero on NS cells).
+ * cfl > 0: local steps; cfl < 0: one global step (conservative).
+ * Returns 0, or -7 on a non-positive density/temperature. */
+int32_t oc_macro(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *src,
+                 int32_t n_inner, double cfl, double *W);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
