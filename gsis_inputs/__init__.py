@@ -451,3 +451,39 @@ def synthetic_region(mesh, fraction: float, seed: int = 11):
     flags = np.zeros(mesh["n_cells"], dtype=np.uint8)
     flags[np.argsort(score, kind="stable")[:k]] = 1
     return flags
+
+
+def node_velocities(grid):
+    """Velocity nodes [nv, 3] and weights [nv] of a tensor grid, row-major (last axis fastest)."""
+    xs = list(grid["nodes"]) + [np.zeros(1)] * (3 - grid["vdim"])
+    ws = list(grid["weights"]) + [np.ones(1)] * (3 - grid["vdim"])
+    X = np.meshgrid(*xs, indexing="ij")
+    Wt = np.meshgrid(*ws, indexing="ij")
+    return np.stack([x.ravel() for x in X], 1), (Wt[0] * Wt[1] * Wt[2]).ravel()
+
+
+def gaussian_rows(grid, W, seed: int, amp: float = 0.05, dtype=np.float32):
+    """Random positive VDF rows shaped like local Gaussians: [n, nfun, nv].
+
+    Row i is rho (pi T)^(-3/2) exp(-|xi - u|^2 / T) (for vdim 2: the reduced
+    pair with the second function scaled by T/2) times independent factors
+    1 + amp * U(-1, 1).  A test input only: its moments are not W exactly.
+    """
+    xi, _ = node_velocities(grid)
+    W = np.atleast_2d(W)
+    g = rng_of(seed)
+    nfun = 1 if grid["vdim"] == 3 else 2
+    out = np.empty((len(W), nfun, len(xi)), dtype=dtype)
+    for i, w in enumerate(W):
+        d = xi - w[1:4][None, :]
+        if grid["vdim"] == 2:
+            d[:, 2] = 0.0
+        c2 = np.sum(d * d, axis=1)
+        if grid["vdim"] == 3:
+            base = w[0] * (np.pi * w[4]) ** -1.5 * np.exp(-c2 / w[4])
+            out[i, 0] = base * (1.0 + amp * g.uniform(-1, 1, len(xi)))
+        else:
+            base = w[0] / (np.pi * w[4]) * np.exp(-c2 / w[4])
+            out[i, 0] = base * (1.0 + amp * g.uniform(-1, 1, len(xi)))
+            out[i, 1] = 0.5 * w[4] * base * (1.0 + amp * g.uniform(-1, 1, len(xi)))
+    return out

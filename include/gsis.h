@@ -1,0 +1,223 @@
+/*
+ * gsis.h -- C ABI of the MI355X kinetic-sweep library for adaptive GSIS.
+ *
+ * Method: Zhang, Zeng & Wu, "Adaptive GSIS for rarefied gas flow
+ * simulations" (arXiv 2501.02245).  The library runs the data-parallel hot
+ * path of the method on one GPU: the implicit discrete-velocity sweep of
+ * Sec. 3.1 over the kinetic (DVM) cells, the velocity-moment reduction of
+ * Sec. 2 (eq. getmoment), the GSIS correction of Sec. 3.1 (first eq.
+ * updatef), the synthetic macroscopic solve (eqs. full_constitutive and
+ * macro), the local-Knudsen region test and compaction of Sec. 3.2 (eq.
+ * Kn_Gll and the second eq. updatef) and the convergence measure of Sec. 4.
+ *
+ * Units: lengths / L, velocities / sqrt(2 R T0), T / T0, rho / rho0; the
+ * Maxwellian is rho (pi T)^(-3/2) exp(-|xi - u|^2 / T).  The gas is
+ * monatomic (the two-VDF model of Sec. 2 with d_r = 0, which is the Shakhov
+ * model with Prandtl number A_tt).
+ *
+ * Conventions
+ *  - Every call returns gsis_status; GSIS_OK == 0.  On failure,
+ *    gsis_last_error() returns a thread-local description.  No C++
+ *    exception crosses the ABI.
+ *  - Host arrays passed in are copied before the call returns.
+ *  - Device buffers (workspace, state, outputs) belong to the caller and are
+ *    never freed by the library.  Handles are created and destroyed only by
+ *    gsis_* calls.
+ *  - Calls that take a `stream` (a hipStream_t, or NULL for the default
+ *    stream) enqueue their work and return; results are valid after the
+ *    stream synchronises.  Calls that return host counts or residuals
+ *    synchronise that stream.
+ *  - Argument and state checks run on the host before any launch; a
+ *    non-finite value found on the device is reported by the next call that
+ *    synchronises as GSIS_E_NONFINITE.
+ *  - One case must not be used from two threads at once.
+ *  - FP32 and FP64 storage are two instantiations of the same kernels.
+ */
+#ifndef GSIS_H
+#define GSIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gsis_status;
+#define GSIS_OK 0
+#define GSIS_E_ARG (-1)        /* invalid argument */
+#define GSIS_E_MESH (-2)       /* mesh rejected (open cell, V <= 0, bad index, too many faces) */
+#define GSIS_E_STATE (-3)      /* call out of order (e.g. sweep before bind / set_state) */
+#define GSIS_E_NOMEM (-4)      /* workspace smaller than gsis_case_footprint */
+#define GSIS_E_CAPACITY (-5)   /* kinetic region larger than the bound capacity */
+#define GSIS_E_HIP (-6)        /* HIP runtime error */
+#define GSIS_E_NONFINITE (-7)  /* NaN/Inf or non-positive density/temperature */
+#define GSIS_E_NOCONV (-8)     /* max_iter reached before tol */
+
+#define GSIS_MAX_FACES 8       /* faces per cell */
+#define GSIS_MAX_WALL_FACES 4  /* wall faces per cell */
+#define GSIS_MAX_AXIS 128      /* nodes per velocity axis */
+#define GSIS_NMOM 14           /* rho, ux, uy, uz, T, sxx, syy, szz, sxy, sxz, syz, qx, qy, qz */
+
+typedef struct gsis_mesh_s *gsis_mesh;
+typedef struct gsis_case_s *gsis_case;
+
+#define GSIS_PATCH_WALL 0      /* diffuse isothermal wall at (u, T) */
+#define GSIS_PATCH_FAR 1       /* far field: Maxwellian at (rho, u, T) on incoming velocities */
+
+typedef struct {
+    int32_t kind;
+    double rho, u[3], T;
+} gsis_patch;
+
+/* Unstructured finite-volume mesh (host arrays, copied).
+ *  dim          1, 2 or 3: gradients use the first `dim` components
+ *  face_cells   [n_faces][2] owner, other; other < 0 means boundary patch -1-other
+ *  face_normal  [n_faces][3] unit normal, owner -> other
+ *  face_area    [n_faces], face_center [n_faces][3]
+ *  cell_volume  [n_cells], cell_center [n_cells][3]
+ * Rejected with GSIS_E_MESH: an index out of range, a cell with more than
+ * GSIS_MAX_FACES faces or GSIS_MAX_WALL_FACES wall faces, V <= 0, S <= 0,
+ * or an open cell (|sum_f n S| > 1e-9 sum_f S). */
+typedef struct {
+    int32_t dim, n_cells, n_faces, n_patches;
+    const int32_t *face_cells;
+    const double *face_normal;
+    const double *face_area;
+    const double *face_center;
+    const double *cell_volume;
+    const double *cell_center;
+    const gsis_patch *patches;
+} gsis_mesh_desc;
+
+/* Gas: Kn (Sec. 2 definition), viscosity index omega (mu ~ T^omega), and
+ * Pr = A_tt (heat-flux relaxation of the monatomic model). */
+typedef struct {
+    double Kn, omega, Pr;
+} gsis_gas;
+
+#define GSIS_F32 0
+#define GSIS_F64 1
+
+const char *gsis_last_error(void);
+
+gsis_status gsis_create_mesh(const gsis_mesh_desc *desc, gsis_mesh *out);
+gsis_status gsis_destroy_mesh(gsis_mesh mesh);   /* the mesh must outlive its cases */
+
+/* One steady problem on `mesh`; vdf_dtype GSIS_F32 or GSIS_F64 (storage and
+ * arithmetic of the kinetic kernels; the macroscopic side is always FP64). */
+gsis_status gsis_create_case(gsis_mesh mesh, const gsis_gas *gas, int32_t vdf_dtype, gsis_case *out);
+gsis_status gsis_destroy_case(gsis_case c);
+
+/* Tensor-product velocity quadrature (host arrays, copied).  vdim 3: full
+ * velocity space, node k = (ix*n1 + iy)*n2 + iz.  vdim 2: the reduced pair
+ * (phi, psi) = (int f dxi_z, int xi_z^2 f dxi_z) over (xi_x, xi_y), node
+ * k = ix*n1 + iy (Sec. 3.3 reduction of the 2D velocity space).  Each axis
+ * has 2..GSIS_MAX_AXIS nodes; weights must be positive. */
+gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const int32_t n[3],
+                                   const double *const nodes[3], const double *const weights[3]);
+
+/* Device bytes needed to bind the case with room for `kinetic_capacity`
+ * kinetic cells (VDF double buffer, per-cell sums and parameters, mesh and
+ * macroscopic arrays). */
+gsis_status gsis_case_footprint(gsis_case c, int64_t kinetic_capacity, size_t *bytes);
+
+/* Bind a caller-owned device workspace (e.g. a torch uint8 tensor) of at
+ * least the footprint.  The workspace must outlive the case; it is never
+ * freed here.  Copies the mesh and grid to the device on `stream`. */
+gsis_status gsis_case_bind(gsis_case c, void *dev_workspace, size_t bytes, int64_t kinetic_capacity,
+                           void *stream);
+
+/* Set the state (device pointers).  W_dev [n_cells][5] = (rho, ux, uy, uz, T)
+ * FP64 on every cell.  flags_dev [n_cells] uint8 (1 = kinetic) or NULL (all
+ * kinetic).  vdf_dev: rows [n_kin][nfun][nv] in the case dtype for the
+ * kinetic cells in ascending cell id, or NULL to start them from the
+ * conservation-fixed Maxwellian of W (Sec. 3.2 f_eq).  Synchronises (returns
+ * GSIS_E_CAPACITY if the region exceeds the capacity). */
+gsis_status gsis_set_state(gsis_case c, const double *W_dev, const void *vdf_dev, const uint8_t *flags_dev,
+                           void *stream);
+
+/* n_sweeps point-Jacobi kinetic sweeps (Sec. 3.1 implicit update, upwind
+ * fluxes, Shakhov target with conservation fix-up) on each case, with the
+ * fused moment reduction of the result.  All cases must share dtype and
+ * vdim; n_cases > 1 runs one batched launch per sweep.  On return (after the
+ * stream syncs) each case's VDF is f^{n+1/2} and its W holds the moments on
+ * kinetic cells. */
+gsis_status gsis_kinetic_sweep(gsis_case const *cases, int32_t n_cases, int32_t n_sweeps, void *stream);
+
+/* Moments of the current VDF (Sec. 2 eq. getmoment): out_dev [n_kin][14]
+ * FP64 in ascending cell id; kin_cell_dev [n_kin] int32 (nullable). */
+gsis_status gsis_moments(gsis_case c, double *out_dev, int32_t *kin_cell_dev, void *stream);
+
+/* Number of kinetic cells (host; no synchronisation). */
+gsis_status gsis_n_kinetic(gsis_case c, int64_t *n_kin);
+
+/* Region update of Sec. 3.2/3.4: least-squares gradients of W, Kn_Gll,
+ * flag = (Kn_Gll >= Kn_ref) or within force_wall_layers of a wall,
+ * compaction in ascending cell id, slot reuse for staying cells, Grad-13
+ * initialisation of newly kinetic cells.  Synchronises; n_kinetic_host
+ * (nullable) receives the new count. */
+gsis_status gsis_update_regions(gsis_case c, double Kn_ref, int32_t force_wall_layers, int64_t *n_kinetic_host,
+                                void *stream);
+
+#define GSIS_MODE_DVM 0
+#define GSIS_MODE_GSIS 1
+#define GSIS_MODE_AGSIS 2
+
+typedef struct {
+    int32_t mode;                /* GSIS_MODE_* */
+    double Kn_ref;               /* Sec. 3.2 reference Knudsen number (aGSIS) */
+    double tol;                  /* stop when max(eps) < tol (Sec. 4, default 1e-6) */
+    int32_t max_iter;
+    int32_t region_update_every; /* aGSIS: re-flag every k iterations (0 = never) */
+    int32_t n_macro_inner;       /* pseudo-time steps per synthetic solve */
+    double cfl;                  /* > 0 local steps; < 0 one global (conservative) step */
+    int32_t force_wall_layers;
+    int32_t ns_init;             /* 1: Step 1, NS-only solve before the first flagging */
+    int32_t ns_init_max_chunks;  /* chunks of n_macro_inner steps for Step 1 */
+} gsis_solve_params;
+
+typedef struct {
+    int32_t iterations;
+    double eps[3];               /* last rho, u, T residuals */
+    int64_t n_kinetic;
+} gsis_solve_result;
+
+/* One outer iteration (Sec. 3.4) for each case: sweep, moments, high-order
+ * terms, synthetic solve, GSIS correction, residual, and (aGSIS, on
+ * schedule) region update.  eps_host [n_cases][3] (nullable) receives the
+ * residuals and synchronises. */
+gsis_status gsis_step(gsis_case const *cases, int32_t n_cases, const gsis_solve_params *p, double *eps_host,
+                      void *stream);
+
+/* Steady solve: optional NS initialisation and first flagging (aGSIS), then
+ * gsis_step until max(eps) < tol.  Returns GSIS_E_NOCONV after max_iter. */
+gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p, gsis_solve_result *r, void *stream);
+
+/* Copy the VDF of the kinetic cells, rows [n_kin][nfun][nv] in the case
+ * dtype, ascending cell id. */
+gsis_status gsis_get_vdf(gsis_case c, void *out_dev, void *stream);
+
+/* Copy W [n_cells][5] FP64 and flags [n_cells] uint8 (either nullable). */
+gsis_status gsis_get_state(gsis_case c, double *W_dev, uint8_t *flags_dev, void *stream);
+
+/* GSIS correction alone (Sec. 3.1, first eq. updatef) on the current VDF:
+ * f += f_eq(W_new) - f_eq(W_half) on kinetic cells, where W_half are the
+ * current moments and W_new_dev [n_cells][5] FP64; W becomes W_new. */
+gsis_status gsis_correct(gsis_case c, const double *W_new_dev, void *stream);
+
+/* Synthetic macroscopic solve alone (eq. macro, FP64): n_inner pseudo-time
+ * steps from W_dev [n_cells][5] (in/out) with high-order terms hot_dev
+ * [n_cells][9] (sigma 6, q 3) and source src_dev [n_cells][5] per unit
+ * volume (nullable). */
+gsis_status gsis_macro_solve(gsis_case c, double *W_dev, const double *hot_dev, const double *src_dev,
+                             int32_t n_inner, double cfl, void *stream);
+
+/* Duration in ms of the last kinetic-sweep kernel launched on this case
+ * (HIP events on the launch stream; synchronises). */
+gsis_status gsis_last_sweep_ms(gsis_case c, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

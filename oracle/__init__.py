@@ -401,6 +401,35 @@ def one_cell_mesh():
             "cell_volume": np.ones(1), "cell_center": np.zeros((1, 3)), "patches": []}
 
 
+def _cons(W):
+    rho = W[0]
+    return np.array([rho, rho * W[1], rho * W[2], rho * W[3], rho * (W[1] ** 2 + W[2] ** 2 + W[3] ** 2) + 1.5 * rho * W[4]])
+
+
+def _prim(U):
+    rho = U[0]
+    u = U[1:4] / rho
+    return np.array([rho, u[0], u[1], u[2], (U[4] - rho * np.dot(u, u)) / (1.5 * rho)])
+
+
+def limit_correction(Wh, Wn, factor=2.0, halvings=10):
+    """Limiter of the GSIS correction (reading; inactive at convergence).
+
+    The conserved-variable change from W^{n+1/2} to W^{n+1} of a kinetic cell
+    is halved (at most ten times, then dropped) until the new density and
+    temperature lie within a factor 2 of those of W^{n+1/2}, so that the
+    corrected distribution stays resolvable on the velocity grid.
+    """
+    Uh, Un = _cons(Wh), _cons(Wn)
+    th = 1.0
+    for _ in range(halvings + 1):
+        W = _prim(Uh + th * (Un - Uh))
+        if (Wh[0] / factor <= W[0] <= Wh[0] * factor) and (Wh[4] / factor <= W[4] <= Wh[4] * factor):
+            return W
+        th *= 0.5
+    return np.array(Wh, dtype=np.float64)
+
+
 class SteadySolver:
     """Outer iteration of Sec. 3.4 (Steps 1-4), one plain step at a time.
 
@@ -437,8 +466,8 @@ class SteadySolver:
                 self.f[self.slot[c]] = O.feq(self.W[c])
         else:
             self.f[self.slot[self.kin]] = np.asarray(f, dtype=np.float64)
-        if self.mode == "dvm":
-            self.W[self.kin] = O.moments(self.f[self.slot[self.kin]])[:, :5]
+        # W on kinetic cells is the moments of their distribution
+        self.W[self.kin] = O.moments(self.f[self.slot[self.kin]])[:, :5]
 
     def ns_init(self, tol=1e-6, chunk=None, max_chunks=1000):
         """Step 1: macroscopic (NSF) solve alone, HoT = 0, to eps < tol."""
@@ -497,8 +526,10 @@ class SteadySolver:
             src = np.zeros((self.n, 5))
             src[kin] = Rk[kin] - O.macro_residual(W_old, hot)[kin]
             W_new = O.macro(W_old, hot, self.n_inner, self.cfl, src)
-            # GSIS correction (first eq. updatef)
+            # GSIS correction (first eq. updatef), with the change of the
+            # conserved moments limited on each kinetic cell
             for c in kin:
+                W_new[c] = limit_correction(W_half[c], W_new[c])
                 f_half[slot[c]] += O.feq(W_new[c]) - O.feq(W_half[c])
             self.f = f_half
         eps = O.residual(W_new, W_old)

@@ -550,18 +550,21 @@ void oc_nsf(const oc_gas *gas, double T, const double *grad_u, const double *gra
  *   moments of the owner's Maxwellian plus the xi.n < 0 half of the other
  *   side's (the first-order upwinding of the kinetic sweep applied to the
  *   local equilibria, so both solvers carry the same numerical dissipation);
- *   viscous part: face gradients = mean of the two LSQ cell gradients with the
- *   centroid-difference correction; sigma_f, q_f = NSF at T_f plus the mean
+ *   viscous part: face gradients = mean of the two LSQ cell gradients plus a
+ *   correction along the face normal that makes their projection on the
+ *   centroid difference equal the jump (over-relaxed non-orthogonal form); sigma_f, q_f = NSF at T_f plus the mean
  *   of the two cells' high-order terms (zero on NS cells);
  *   far field: the same splitting against the patch state, no viscous flux;
- *   diffuse wall: the same splitting, outgoing half of the owner's Maxwellian
- *   plus rho_w M(u_w, T_w) on the incoming half with zero net mass flux (a
- *   slip condition whose slip length follows the mean free path), no
- *   separate viscous wall term;
+ *   wall: isothermal no-slip (pressure plus the NSF viscous flux from
+ *   one-sided gradients towards (u_w, T_w), no mass flux);
  *   source: an optional frozen per-cell term (the GSIS driver puts there the
  *   difference between the kinetic scheme's moment balance and this
  *   residual, both at iterate n, on kinetic cells);
- *   explicit update with local step dt_i = cfl V_i / sum_f S_f (|u_n| + a + 2 nu / d_f)
+ *   explicit update with local step dt_i = cfl V_i / sum_f S_f (|u_n| + a + 2 nu / d_f),
+ *   d_f = normal distance between the centroids (twice the centroid-face
+ *   normal distance on boundary faces),
+ *   halved per cell (at most ten times) while the new rho or T would not be
+ *   positive
  *   (cfl < 0: one global step, the minimum over cells of |cfl| V_i / sum ...),
  *   nu = max(4/3, 5/(3 Pr)) Kn T^omega / (sqrt(pi) rho).
  * ------------------------------------------------------------------------ */
@@ -654,17 +657,17 @@ static int32_t macro_residual(const oc_mesh *m, const oc_gas *gas,
             for (int c = 0; c < 5; ++c) F[c] = FL[c] + FR[c];
         }
         if (Rc >= 0) {
-            /* viscous flux on an interior face */
-            double e[3], dd = 0;
-            for (int d = 0; d < 3; ++d) { e[d] = m->cell_center[3 * Rc + d] - m->cell_center[3 * L + d]; dd += e[d] * e[d]; }
-            dd = sqrt(dd);
-            for (int d = 0; d < 3; ++d) e[d] /= dd;
+            /* viscous flux on an interior face: mean gradient corrected along the
+             * normal so that its projection on the centroid difference equals the
+             * jump (exact for linear fields; compact normal coefficient 1/d_n) */
+            double dx[3], dd = 0;
+            for (int d = 0; d < 3; ++d) { dx[d] = m->cell_center[3 * Rc + d] - m->cell_center[3 * L + d]; dd += dx[d] * n[d]; }
             double G[4][3];
             for (int v = 0; v < 4; ++v) {
-                double ge = 0;
-                for (int d = 0; d < 3; ++d) { G[v][d] = 0.5 * (gr[12 * L + 3 * v + d] + gr[12 * Rc + 3 * v + d]); ge += G[v][d] * e[d]; }
-                double jump = (pv[4 * Rc + v] - pv[4 * L + v]) / dd;
-                for (int d = 0; d < 3; ++d) G[v][d] += (jump - ge) * e[d];
+                double gx = 0;
+                for (int d = 0; d < 3; ++d) { G[v][d] = 0.5 * (gr[12 * L + 3 * v + d] + gr[12 * Rc + 3 * v + d]); gx += G[v][d] * dx[d]; }
+                double alpha = (pv[4 * Rc + v] - pv[4 * L + v] - gx) / dd;
+                for (int d = 0; d < 3; ++d) G[v][d] += alpha * n[d];
             }
             double Tf = 0.5 * (PL[4] + PR[4]);
             double gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
@@ -678,19 +681,31 @@ static int32_t macro_residual(const oc_mesh *m, const oc_gas *gas,
             double uf[3] = {0.5 * (PL[1] + PR[1]), 0.5 * (PL[2] + PR[2]), 0.5 * (PL[3] + PR[3])};
             for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
             F[4] += sn[0] * uf[0] + sn[1] * uf[1] + sn[2] * uf[2] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
-            dL = dd; dR = dd;
+            dL = dd; dR = dd;      /* normal distance between the centroids */
         } else if (kindB == OC_WALL) {
-            /* diffuse wall: outgoing half of M(W_L) plus rho_w M(u_w, T_w) on the
-             * incoming half, rho_w from zero net mass flux */
+            /* isothermal no-slip wall: pressure, plus the viscous flux from
+             * one-sided gradients towards (u_w, T_w) */
             const double *ps = m->patch_state + 5 * (-1 - Rc);
             double dn = 0;
             for (int d = 0; d < 3; ++d) dn += (m->face_center[3 * f + d] - m->cell_center[3 * L + d]) * n[d];
             dL = 2.0 * dn;
-            double Pw[5] = {1.0, ps[1], ps[2], ps[3], ps[4]}, Fo[5], Fi[5];
-            half_flux(PL, n, 1.0, Fo);
-            half_flux(Pw, n, -1.0, Fi);
-            double rw = -Fo[0] / Fi[0];
-            for (int c = 0; c < 5; ++c) F[c] = Fo[c] + rw * Fi[c];
+            double pL = PL[0] * PL[4];
+            for (int d = 0; d < 3; ++d) F[1 + d] = 0.5 * pL * n[d];
+            double G[4][3], wv[4] = {ps[1], ps[2], ps[3], ps[4]};
+            for (int v = 0; v < 4; ++v) {
+                double gn = 0;
+                for (int d = 0; d < 3; ++d) gn += gr[12 * L + 3 * v + d] * n[d];
+                double jump = (wv[v] - pv[4 * L + v]) / dn;
+                for (int d = 0; d < 3; ++d) G[v][d] = gr[12 * L + 3 * v + d] + (jump - gn) * n[d];
+            }
+            double gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+            double sg[6], q[3];
+            oc_nsf(gas, ps[4], gu, G[3], sg, q);
+            double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2],
+                            sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                            sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+            for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
+            F[4] += sn[0] * ps[1] + sn[1] * ps[2] + sn[2] * ps[3] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
         } else {
             double dn = 0;
             for (int d = 0; d < 3; ++d) dn += (m->face_center[3 * f + d] - m->cell_center[3 * L + d]) * n[d];
@@ -758,7 +773,19 @@ int32_t oc_macro(const oc_mesh *m, const oc_gas *gas, const double *hot, const d
             for (int32_t i = 0; i < nc; ++i) gdt = fmin(gdt, -cfl * m->cell_volume[i] / D[i]);
         for (int32_t i = 0; i < nc; ++i) {
             double k = (cfl < 0) ? gdt / m->cell_volume[i] : cfl / D[i];
-            for (int c = 0; c < 5; ++c) U[5 * i + c] += k * R[5 * i + c];
+            /* positivity safeguard (reading): halve this cell's increment until
+             * the new density and temperature are positive; after ten halvings
+             * the cell keeps its state for this pseudo-step */
+            double Un[5], Pn[5];
+            int ok = 0;
+            for (int h = 0; h <= 10 && !ok; ++h) {
+                for (int c = 0; c < 5; ++c) Un[c] = U[5 * i + c] + k * R[5 * i + c];
+                prim_from_cons(Un, Pn);
+                ok = (Pn[0] > 0) && (Pn[4] > 0);
+                k *= 0.5;
+            }
+            if (ok)
+                for (int c = 0; c < 5; ++c) U[5 * i + c] = Un[c];
         }
         for (int32_t i = 0; i < nc; ++i) prim_from_cons(U + 5 * i, W + 5 * i);
     }

@@ -1,0 +1,278 @@
+"""Python binding of the MI355X adaptive-GSIS kinetic-sweep library (libgsis.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI of ``include/gsis.h``.  PyTorch provides device memory (the
+case workspace and state buffers) and the HIP stream.  Importing this module
+does not touch the GPU; the library is loaded on first use and its absence
+raises an error (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsis.so")
+
+OK, E_ARG, E_MESH, E_STATE, E_NOMEM, E_CAPACITY, E_HIP, E_NONFINITE, E_NOCONV = 0, -1, -2, -3, -4, -5, -6, -7, -8
+F32, F64 = 0, 1
+PATCH_WALL, PATCH_FAR = 0, 1
+MODE_DVM, MODE_GSIS, MODE_AGSIS = 0, 1, 2
+NMOM = 14
+MAX_FACES, MAX_WALL_FACES, MAX_AXIS = 8, 4, 128
+
+EXPORTS = [
+    "gsis_last_error", "gsis_create_mesh", "gsis_destroy_mesh", "gsis_create_case", "gsis_destroy_case",
+    "gsis_set_velocity_grid", "gsis_case_footprint", "gsis_case_bind", "gsis_set_state", "gsis_kinetic_sweep",
+    "gsis_moments", "gsis_n_kinetic", "gsis_update_regions", "gsis_step", "gsis_solve_steady", "gsis_get_vdf",
+    "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
+]
+
+
+class GsisError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("gsis error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Patch(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("rho", C.c_double), ("u", C.c_double * 3), ("T", C.c_double)]
+
+
+class _MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_cells", C.c_int32), ("n_faces", C.c_int32), ("n_patches", C.c_int32),
+                ("face_cells", C.c_void_p), ("face_normal", C.c_void_p), ("face_area", C.c_void_p),
+                ("face_center", C.c_void_p), ("cell_volume", C.c_void_p), ("cell_center", C.c_void_p),
+                ("patches", C.c_void_p)]
+
+
+class _Gas(C.Structure):
+    _fields_ = [("Kn", C.c_double), ("omega", C.c_double), ("Pr", C.c_double)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("Kn_ref", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("region_update_every", C.c_int32), ("n_macro_inner", C.c_int32), ("cfl", C.c_double),
+                ("force_wall_layers", C.c_int32), ("ns_init", C.c_int32), ("ns_init_max_chunks", C.c_int32)]
+
+    def __init__(self, mode=MODE_GSIS, Kn_ref=0.01, tol=1e-6, max_iter=1000, region_update_every=1,
+                 n_macro_inner=400, cfl=0.5, force_wall_layers=0, ns_init=0, ns_init_max_chunks=1000):
+        super().__init__(mode, Kn_ref, tol, max_iter, region_update_every, n_macro_inner, cfl, force_wall_layers,
+                         ns_init, ns_init_max_chunks)
+
+
+class SolveResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("eps", C.c_double * 3), ("n_kinetic", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libgsis.so (built in-tree by ``paper_2501_02245_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgsis.so is not built (run python -m paper_2501_02245_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.gsis_last_error.restype = C.c_char_p
+        sig = {
+            "gsis_create_mesh": [P, P], "gsis_destroy_mesh": [P], "gsis_create_case": [P, P, I32, P],
+            "gsis_destroy_case": [P], "gsis_set_velocity_grid": [P, I32, P, P, P],
+            "gsis_case_footprint": [P, I64, P], "gsis_case_bind": [P, P, C.c_size_t, I64, P],
+            "gsis_set_state": [P, P, P, P, P], "gsis_kinetic_sweep": [P, I32, I32, P],
+            "gsis_moments": [P, P, P, P], "gsis_n_kinetic": [P, P], "gsis_update_regions": [P, D, I32, P, P],
+            "gsis_step": [P, I32, P, P, P], "gsis_solve_steady": [P, P, P, P], "gsis_get_vdf": [P, P, P],
+            "gsis_get_state": [P, P, P, P], "gsis_correct": [P, P, P], "gsis_macro_solve": [P, P, P, P, I32, D, P],
+            "gsis_last_sweep_ms": [P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = I32
+        _lib = L
+    return _lib
+
+
+def _check(code, allow=()):
+    if code != OK and code not in allow:
+        raise GsisError(code, lib().gsis_last_error().decode())
+    return code
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(a, dtype):
+    """numpy / torch -> contiguous CUDA tensor of `dtype`."""
+    import torch
+    if isinstance(a, torch.Tensor):
+        return a.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+class Mesh:
+    """Host-side mesh handle (gsis_create_mesh); see gsis_inputs for the dictionary layout."""
+
+    def __init__(self, m):
+        self._arrays = [np.ascontiguousarray(m["face_cells"], dtype=np.int32)]
+        for k in ("face_normal", "face_area", "face_center", "cell_volume", "cell_center"):
+            self._arrays.append(np.ascontiguousarray(m[k], dtype=np.float64))
+        pt = (_Patch * max(1, len(m["patches"])))()
+        for i, p in enumerate(m["patches"]):
+            pt[i].kind = PATCH_WALL if p["kind"] == "wall" else PATCH_FAR
+            pt[i].rho = p["rho"]
+            for d in range(3):
+                pt[i].u[d] = float(p["u"][d])
+            pt[i].T = p["T"]
+        self._patches = pt
+        a = self._arrays
+        desc = _MeshDesc(m["dim"], m["n_cells"], m["n_faces"], len(m["patches"]),
+                         *[x.ctypes.data for x in a], C.addressof(pt))
+        h = C.c_void_p()
+        _check(lib().gsis_create_mesh(C.byref(desc), C.byref(h)))
+        self.handle = h
+        self.n_cells = m["n_cells"]
+        self.n_faces = m["n_faces"]
+        self.dict = m
+
+    def close(self):
+        if self.handle:
+            _check(lib().gsis_destroy_mesh(self.handle))
+            self.handle = None
+
+
+class Case:
+    """One steady problem bound to a torch-allocated device workspace."""
+
+    def __init__(self, mesh: Mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, dtype=F32, capacity=None):
+        import torch
+        self.mesh = mesh
+        self.dtype = dtype
+        self.vdim = grid["vdim"]
+        self.nfun = 1 if self.vdim == 3 else 2
+        h = C.c_void_p()
+        _check(lib().gsis_create_case(mesh.handle, C.byref(_Gas(Kn, omega, Pr)), dtype, C.byref(h)))
+        self.handle = h
+        n = (C.c_int32 * 3)(*[len(grid["nodes"][d]) if d < self.vdim else 1 for d in range(3)])
+        self._grid = [np.ascontiguousarray(grid["nodes"][d] if d < self.vdim else [0.0], dtype=np.float64)
+                      for d in range(3)]
+        self._wts = [np.ascontiguousarray(grid["weights"][d] if d < self.vdim else [1.0], dtype=np.float64)
+                     for d in range(3)]
+        xs = (C.c_void_p * 3)(*[x.ctypes.data for x in self._grid])
+        ws = (C.c_void_p * 3)(*[x.ctypes.data for x in self._wts])
+        _check(lib().gsis_set_velocity_grid(h, self.vdim, n, xs, ws))
+        self.nv = int(np.prod([len(grid["nodes"][d]) for d in range(self.vdim)]))
+        self.capacity = int(capacity or mesh.n_cells)
+        nbytes = C.c_size_t()
+        _check(lib().gsis_case_footprint(h, self.capacity, C.byref(nbytes)))
+        self.footprint = nbytes.value
+        self.workspace = torch.empty(self.footprint, dtype=torch.uint8, device="cuda")
+        _check(lib().gsis_case_bind(h, _ptr(self.workspace), self.footprint, self.capacity, _stream()))
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float32 if self.dtype == F32 else torch.float64
+
+    def close(self):
+        if self.handle:
+            _check(lib().gsis_destroy_case(self.handle))
+            self.handle = None
+            self.workspace = None
+
+    def set_state(self, W, vdf=None, flags=None):
+        import torch
+        Wd = _dev(W, torch.float64)
+        vd = _dev(vdf, self.torch_dtype) if vdf is not None else None
+        fd = _dev(flags, torch.uint8) if flags is not None else None
+        _check(lib().gsis_set_state(self.handle, _ptr(Wd), _ptr(vd), _ptr(fd), _stream()))
+
+    @property
+    def n_kin(self):
+        n = C.c_int64()
+        _check(lib().gsis_n_kinetic(self.handle, C.byref(n)))
+        return n.value
+
+    def sweep(self, n_sweeps=1):
+        arr = (C.c_void_p * 1)(self.handle)
+        _check(lib().gsis_kinetic_sweep(arr, 1, n_sweeps, _stream()))
+
+    def moments(self):
+        import torch
+        n = self.n_kin
+        out = torch.empty((n, NMOM), dtype=torch.float64, device="cuda")
+        kc = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(lib().gsis_moments(self.handle, _ptr(out), _ptr(kc), _stream()))
+        return out, kc
+
+    def get_vdf(self):
+        import torch
+        out = torch.empty((self.n_kin, self.nfun, self.nv), dtype=self.torch_dtype, device="cuda")
+        _check(lib().gsis_get_vdf(self.handle, _ptr(out), _stream()))
+        return out
+
+    def get_state(self):
+        import torch
+        W = torch.empty((self.mesh.n_cells, 5), dtype=torch.float64, device="cuda")
+        fl = torch.empty(self.mesh.n_cells, dtype=torch.uint8, device="cuda")
+        _check(lib().gsis_get_state(self.handle, _ptr(W), _ptr(fl), _stream()))
+        return W, fl
+
+    def update_regions(self, Kn_ref, force_wall_layers=0):
+        n = C.c_int64()
+        _check(lib().gsis_update_regions(self.handle, Kn_ref, force_wall_layers, C.byref(n), _stream()))
+        return n.value
+
+    def step(self, params: SolveParams):
+        eps = (C.c_double * 3)()
+        arr = (C.c_void_p * 1)(self.handle)
+        _check(lib().gsis_step(arr, 1, C.byref(params), eps, _stream()))
+        return np.array(eps[:])
+
+    def solve(self, params: SolveParams, allow_noconv=False):
+        r = SolveResult()
+        code = lib().gsis_solve_steady(self.handle, C.byref(params), C.byref(r), _stream())
+        _check(code, allow=(E_NOCONV,) if allow_noconv else ())
+        return r.iterations, np.array(r.eps[:]), r.n_kinetic
+
+    def correct(self, W_new):
+        import torch
+        Wd = _dev(W_new, torch.float64)
+        _check(lib().gsis_correct(self.handle, _ptr(Wd), _stream()))
+
+    def macro_solve(self, W, hot, src=None, n_inner=1, cfl=0.5):
+        import torch
+        Wd = _dev(W, torch.float64)
+        hd = _dev(hot, torch.float64)
+        sd = _dev(src, torch.float64) if src is not None else None
+        _check(lib().gsis_macro_solve(self.handle, _ptr(Wd), _ptr(hd), _ptr(sd), n_inner, cfl, _stream()))
+        return Wd
+
+    def last_sweep_ms(self):
+        ms = C.c_float()
+        _check(lib().gsis_last_sweep_ms(self.handle, C.byref(ms)))
+        return ms.value
+
+
+def kinetic_sweep(cases, n_sweeps=1):
+    """One batched launch per sweep over several cases (same dtype and vdim)."""
+    arr = (C.c_void_p * len(cases))(*[c.handle for c in cases])
+    _check(lib().gsis_kinetic_sweep(arr, len(cases), n_sweeps, _stream()))
+
+
+def step(cases, params: SolveParams):
+    """One outer iteration for a batch of cases; returns eps [n_cases, 3]."""
+    eps = (C.c_double * (3 * len(cases)))()
+    arr = (C.c_void_p * len(cases))(*[c.handle for c in cases])
+    _check(lib().gsis_step(arr, len(cases), C.byref(params), eps, _stream()))
+    return np.array(eps[:]).reshape(len(cases), 3)

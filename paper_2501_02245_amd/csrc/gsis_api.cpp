@@ -1,0 +1,864 @@
+// gsis_api.cpp -- host side of the C ABI declared in include/gsis.h.
+//
+// Validates arguments, builds the per-cell face lists, lays a bound case out
+// inside the caller's device workspace, and sequences the kernels of one
+// outer iteration of the method (Sec. 3.4 of arXiv 2501.02245).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gsis_impl.hpp"
+
+using namespace gsis;
+
+namespace {
+
+thread_local std::string g_err;
+
+gsis_status fail(gsis_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(GSIS_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+struct Segment {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+}  // namespace
+
+struct gsis_mesh_s {
+    int32_t dim, n_cells, n_faces, n_patches, nnz;
+    std::vector<int32_t> face_cells, cf_ptr, cf_face, cf_other, cf_wall, patch_kind;
+    std::vector<double> face_normal, face_area, face_center, cell_volume, cell_center, cf_nsv, face_dist,
+        patch_state;
+    int refs = 0;
+};
+
+struct gsis_case_s {
+    gsis_mesh mesh = nullptr;
+    gsis_gas gas{};
+    int32_t dtype = GSIS_F32;
+    int32_t vdim = 0, n[3] = {0, 0, 0}, nv = 0;
+    double xv[3][MAXA], wv[3][MAXA];
+    bool grid_set = false, bound = false, state_set = false;
+    int32_t capacity = 0, tile = 0, ntile = 0, row = 0;
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0;
+    CaseView hv{};             // host copy of the device view
+    CaseView *cv = nullptr;    // device view inside the workspace
+    int n_kin = 0, cur = 0, iter = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+};
+
+extern "C" const char *gsis_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// mesh
+// ---------------------------------------------------------------------------
+extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
+{
+    if (!d || !out) return fail(GSIS_E_ARG, "null argument");
+    *out = nullptr;
+    if (d->dim < 1 || d->dim > 3) return fail(GSIS_E_ARG, "dim must be 1, 2 or 3");
+    if (d->n_cells <= 0 || d->n_faces < 0 || d->n_patches < 0) return fail(GSIS_E_ARG, "bad sizes");
+    if (d->n_faces > 0 && (!d->face_cells || !d->face_normal || !d->face_area || !d->face_center))
+        return fail(GSIS_E_ARG, "null face array");
+    if (!d->cell_volume || !d->cell_center) return fail(GSIS_E_ARG, "null cell array");
+    if (d->n_patches > 0 && !d->patches) return fail(GSIS_E_ARG, "null patches");
+    auto *m = new gsis_mesh_s();
+    m->dim = d->dim;
+    m->n_cells = d->n_cells;
+    m->n_faces = d->n_faces;
+    m->n_patches = d->n_patches;
+    const int nc = d->n_cells, nf = d->n_faces;
+    m->face_cells.assign(d->face_cells, d->face_cells + 2 * nf);
+    m->face_normal.assign(d->face_normal, d->face_normal + 3 * nf);
+    m->face_area.assign(d->face_area, d->face_area + nf);
+    m->face_center.assign(d->face_center, d->face_center + 3 * nf);
+    m->cell_volume.assign(d->cell_volume, d->cell_volume + nc);
+    m->cell_center.assign(d->cell_center, d->cell_center + 3 * nc);
+    for (int p = 0; p < d->n_patches; ++p) {
+        const gsis_patch &P = d->patches[p];
+        if (P.kind != GSIS_PATCH_WALL && P.kind != GSIS_PATCH_FAR) {
+            delete m;
+            return fail(GSIS_E_ARG, "patch %d: unknown kind %d", p, P.kind);
+        }
+        if (!(P.T > 0) || (P.kind == GSIS_PATCH_FAR && !(P.rho > 0))) {
+            delete m;
+            return fail(GSIS_E_ARG, "patch %d: non-positive state", p);
+        }
+        m->patch_kind.push_back(P.kind);
+        m->patch_state.insert(m->patch_state.end(), {P.rho, P.u[0], P.u[1], P.u[2], P.T});
+    }
+    // validate and build the per-cell face lists
+    std::vector<int32_t> cnt(nc + 1, 0);
+    for (int f = 0; f < nf; ++f) {
+        int a = m->face_cells[2 * f], b = m->face_cells[2 * f + 1];
+        if (a < 0 || a >= nc || b >= nc || (b < 0 && -1 - b >= d->n_patches) || a == b) {
+            delete m;
+            return fail(GSIS_E_MESH, "face %d: bad cell/patch index (%d, %d)", f, a, b);
+        }
+        if (!(m->face_area[f] > 0)) {
+            delete m;
+            return fail(GSIS_E_MESH, "face %d: area must be positive", f);
+        }
+        double nn = 0;
+        for (int k = 0; k < 3; ++k) nn += m->face_normal[3 * f + k] * m->face_normal[3 * f + k];
+        if (std::fabs(nn - 1.0) > 1e-9) {
+            delete m;
+            return fail(GSIS_E_MESH, "face %d: normal is not unit", f);
+        }
+        cnt[a + 1]++;
+        if (b >= 0) cnt[b + 1]++;
+    }
+    for (int i = 0; i < nc; ++i) {
+        if (!(m->cell_volume[i] > 0)) {
+            delete m;
+            return fail(GSIS_E_MESH, "cell %d: volume must be positive", i);
+        }
+        if (cnt[i + 1] > MAXF) {
+            delete m;
+            return fail(GSIS_E_MESH, "cell %d has %d faces (max %d)", i, cnt[i + 1], MAXF);
+        }
+        cnt[i + 1] += cnt[i];
+    }
+    m->nnz = cnt[nc];
+    m->cf_ptr = cnt;
+    m->cf_face.assign(m->nnz, 0);
+    m->cf_other.assign(m->nnz, 0);
+    m->cf_wall.assign(m->nnz, -1);
+    m->cf_nsv.assign(3 * (size_t)m->nnz, 0.0);
+    std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int f = 0; f < nf; ++f) {
+        int a = m->face_cells[2 * f], b = m->face_cells[2 * f + 1];
+        int e = pos[a]++;
+        m->cf_face[e] = f;
+        m->cf_other[e] = b;
+        for (int k = 0; k < 3; ++k) m->cf_nsv[3 * e + k] = m->face_normal[3 * f + k] * m->face_area[f] / m->cell_volume[a];
+        if (b >= 0) {
+            e = pos[b]++;
+            m->cf_face[e] = f;
+            m->cf_other[e] = a;
+            for (int k = 0; k < 3; ++k)
+                m->cf_nsv[3 * e + k] = -m->face_normal[3 * f + k] * m->face_area[f] / m->cell_volume[b];
+        }
+    }
+    // closure, wall-face numbering, face distances
+    for (int i = 0; i < nc; ++i) {
+        double s[3] = {0, 0, 0}, A = 0;
+        int nw = 0;
+        for (int e = m->cf_ptr[i]; e < m->cf_ptr[i + 1]; ++e) {
+            int f = m->cf_face[e];
+            for (int k = 0; k < 3; ++k) s[k] += m->cf_nsv[3 * e + k] * m->cell_volume[i];
+            A += m->face_area[f];
+            int b = m->cf_other[e];
+            if (b < 0 && m->patch_kind[-1 - b] == GSIS_PATCH_WALL) {
+                if (nw >= MAXW) {
+                    delete m;
+                    return fail(GSIS_E_MESH, "cell %d has more than %d wall faces", i, MAXW);
+                }
+                m->cf_wall[e] = nw++;
+            }
+        }
+        double sn = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        if (sn > 1e-9 * A) {
+            delete m;
+            return fail(GSIS_E_MESH, "cell %d is not closed (|sum n S| = %g)", i, sn);
+        }
+    }
+    m->face_dist.assign(nf, 0.0);
+    for (int f = 0; f < nf; ++f) {
+        int a = m->face_cells[2 * f], b = m->face_cells[2 * f + 1];
+        double dd = 0;
+        if (b >= 0) {
+            // normal distance between the centroids
+            for (int k = 0; k < 3; ++k) dd += (m->cell_center[3 * b + k] - m->cell_center[3 * a + k]) * m->face_normal[3 * f + k];
+        } else {
+            for (int k = 0; k < 3; ++k) dd += (m->face_center[3 * f + k] - m->cell_center[3 * a + k]) * m->face_normal[3 * f + k];
+            dd *= 2.0;
+        }
+        if (!(dd > 0)) {
+            delete m;
+            return fail(GSIS_E_MESH, "face %d: centroids do not straddle the face", f);
+        }
+        m->face_dist[f] = dd;
+    }
+    *out = m;
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_destroy_mesh(gsis_mesh m)
+{
+    if (!m) return fail(GSIS_E_ARG, "null mesh");
+    if (m->refs > 0) return fail(GSIS_E_STATE, "mesh still used by %d case(s)", m->refs);
+    delete m;
+    return GSIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// case
+// ---------------------------------------------------------------------------
+extern "C" gsis_status gsis_create_case(gsis_mesh mesh, const gsis_gas *gas, int32_t vdf_dtype, gsis_case *out)
+{
+    if (!mesh || !gas || !out) return fail(GSIS_E_ARG, "null argument");
+    if (vdf_dtype != GSIS_F32 && vdf_dtype != GSIS_F64) return fail(GSIS_E_ARG, "vdf_dtype must be GSIS_F32 or GSIS_F64");
+    if (!(gas->Kn > 0) || !(gas->Pr > 0) || !(gas->Pr <= 1.0) || !std::isfinite(gas->omega))
+        return fail(GSIS_E_ARG, "bad gas parameters");
+    auto *c = new gsis_case_s();
+    c->mesh = mesh;
+    c->gas = *gas;
+    c->dtype = vdf_dtype;
+    mesh->refs++;
+    *out = c;
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_destroy_case(gsis_case c)
+{
+    if (!c) return fail(GSIS_E_ARG, "null case");
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    c->mesh->refs--;
+    delete c;
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const int32_t n[3],
+                                              const double *const nodes[3], const double *const weights[3])
+{
+    if (!c || !n || !nodes || !weights) return fail(GSIS_E_ARG, "null argument");
+    if (c->bound) return fail(GSIS_E_STATE, "velocity grid must be set before binding");
+    if (vdim != 2 && vdim != 3) return fail(GSIS_E_ARG, "vdim must be 2 or 3");
+    int64_t nv = 1;
+    for (int d = 0; d < vdim; ++d) {
+        if (n[d] < 2 || n[d] > MAXA) return fail(GSIS_E_ARG, "axis %d: %d nodes (need 2..%d)", d, n[d], MAXA);
+        if (!nodes[d] || !weights[d]) return fail(GSIS_E_ARG, "axis %d: null array", d);
+        for (int j = 0; j < n[d]; ++j)
+            if (!(weights[d][j] > 0) || !std::isfinite(nodes[d][j])) return fail(GSIS_E_ARG, "axis %d: bad node %d", d, j);
+        nv *= n[d];
+    }
+    if (nv > (1 << 24)) return fail(GSIS_E_ARG, "too many velocity nodes");
+    c->vdim = vdim;
+    std::memset(c->xv, 0, sizeof c->xv);
+    std::memset(c->wv, 0, sizeof c->wv);
+    for (int d = 0; d < 3; ++d) {
+        c->n[d] = (d < vdim) ? n[d] : 1;
+        if (d < vdim)
+            for (int j = 0; j < n[d]; ++j) {
+                c->xv[d][j] = nodes[d][j];
+                c->wv[d][j] = weights[d][j];
+            }
+    }
+    c->nv = (int32_t)nv;
+    c->grid_set = true;
+    return GSIS_OK;
+}
+
+namespace {
+
+struct Layout {
+    size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, wall_den, face_cells, face_normal, face_area, face_center,
+        face_dist, cell_volume, cell_center, patch_kind, patch_state, xv, wv, flags, slot, kin, nkin, newc, nnew, scan,
+        status, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
+    size_t total;
+};
+
+int choose_tile(int nv)
+{
+    const char *env = std::getenv("GSIS_TILE");
+    int t = env ? std::atoi(env) : 4096;
+    if (t < BLOCK) t = BLOCK;
+    t = (t / BLOCK) * BLOCK;
+    return nv <= t ? nv : t;
+}
+
+Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int *row)
+{
+    const gsis_mesh_s *m = c->mesh;
+    const size_t nc = m->n_cells, nf = m->n_faces, nnz = m->nnz, np = std::max(1, m->n_patches);
+    const int nfun = (c->vdim == 3) ? 1 : 2;
+    const int nvp = (c->nv + 63) / 64 * 64;
+    *row = nfun * nvp;
+    *tile = choose_tile(c->nv);
+    *ntile = (c->nv + *tile - 1) / *tile;
+    const size_t es = (c->dtype == GSIS_F32) ? 4 : 8;
+    Segment S;
+    Layout L;
+    L.cv = S.take(sizeof(CaseView));
+    L.cf_ptr = S.take(4 * (nc + 1));
+    L.cf_face = S.take(4 * nnz);
+    L.cf_other = S.take(4 * nnz);
+    L.cf_wall = S.take(4 * nnz);
+    L.cf_nsv = S.take(24 * nnz);
+    L.wall_den = S.take(8 * nnz);
+    L.face_cells = S.take(8 * nf);
+    L.face_normal = S.take(24 * nf);
+    L.face_area = S.take(8 * nf);
+    L.face_center = S.take(24 * nf);
+    L.face_dist = S.take(8 * nf);
+    L.cell_volume = S.take(8 * nc);
+    L.cell_center = S.take(24 * nc);
+    L.patch_kind = S.take(4 * np);
+    L.patch_state = S.take(40 * np);
+    L.xv = S.take(8 * 3 * MAXA);
+    L.wv = S.take(8 * 3 * MAXA);
+    L.flags = S.take(4 * nc);
+    L.slot = S.take(4 * nc);
+    L.kin = S.take(4 * (size_t)cap);
+    L.nkin = S.take(16);
+    L.newc = S.take(4 * (size_t)cap);
+    L.nnew = S.take(16);
+    L.scan = S.take(4 * (2 * nc + 2 * (size_t)cap + 1024));
+    L.status = S.take(16);
+    L.f0 = S.take(es * (size_t)cap * (*row));
+    L.f1 = S.take(es * (size_t)cap * (*row));
+    L.param = S.take(sizeof(ParamRec) * (size_t)cap);
+    L.feq = S.take(2 * sizeof(FeqRec) * (size_t)cap);
+    L.partial = S.take(8 * (size_t)cap * (*ntile) * NSUM);
+    L.mom = S.take(8 * (size_t)cap * (GSIS_NMOM + MAXW));
+    L.W = S.take(40 * nc);
+    L.Wh = S.take(40 * nc);
+    L.Wn = S.take(40 * nc);
+    L.U = S.take(40 * nc);
+    L.grad = S.take(144 * nc);
+    L.ghost = S.take(8 * GSIS_NMOM * nc);
+    L.hot = S.take(72 * nc);
+    L.src = S.take(40 * nc);
+    L.Rk = S.take(40 * nc);
+    L.Rm = S.take(40 * nc);
+    L.fflux = S.take(40 * std::max<size_t>(nf, 1));
+    L.dloc = S.take(8 * nc);
+    L.red = S.take(8 * std::max<size_t>(8192, 8 + 6 * (nc / 256 + 2) + 256));
+    L.eps = S.take(64);
+    L.total = S.off;
+    return L;
+}
+
+gsis_status sync_status(gsis_case c, hipStream_t s)
+{
+    int32_t st[4];
+    HIPCHK(hipMemcpyAsync(st, c->hv.status, sizeof st, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st[0]) return fail(GSIS_E_NONFINITE, "non-finite or non-positive state detected on the device");
+    if (st[1]) return fail(GSIS_E_CAPACITY, "kinetic region exceeds the bound capacity (%d)", c->capacity);
+    return GSIS_OK;
+}
+
+gsis_status check_ready(gsis_case c)
+{
+    if (!c) return fail(GSIS_E_ARG, "null case");
+    if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
+    if (!c->state_set) return fail(GSIS_E_STATE, "state not set (call gsis_set_state)");
+    return GSIS_OK;
+}
+
+// read n_kin / n_new after a compaction (synchronises)
+gsis_status read_counts(gsis_case c, hipStream_t s, int *n_new)
+{
+    int32_t v[2];
+    HIPCHK(hipMemcpyAsync(&v[0], c->hv.n_kin_dev, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&v[1], c->hv.n_new_dev, 4, hipMemcpyDeviceToHost, s));
+    gsis_status st = sync_status(c, s);
+    if (st) return st;
+    c->n_kin = v[0];
+    if (n_new) *n_new = v[1];
+    return GSIS_OK;
+}
+
+}  // namespace
+
+extern "C" gsis_status gsis_case_footprint(gsis_case c, int64_t cap, size_t *bytes)
+{
+    if (!c || !bytes) return fail(GSIS_E_ARG, "null argument");
+    if (!c->grid_set) return fail(GSIS_E_STATE, "velocity grid not set");
+    if (cap <= 0 || cap > c->mesh->n_cells) return fail(GSIS_E_ARG, "capacity must be in 1..n_cells");
+    int tile, ntile, row;
+    *bytes = make_layout(c, cap, &tile, &ntile, &row).total;
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64_t cap, void *stream)
+{
+    if (!c || !ws) return fail(GSIS_E_ARG, "null argument");
+    if (!c->grid_set) return fail(GSIS_E_STATE, "velocity grid not set");
+    if (cap <= 0 || cap > c->mesh->n_cells) return fail(GSIS_E_ARG, "capacity must be in 1..n_cells");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GSIS_E_ARG, "workspace must be 256-byte aligned");
+    int tile, ntile, row;
+    Layout L = make_layout(c, cap, &tile, &ntile, &row);
+    if (bytes < L.total) return fail(GSIS_E_NOMEM, "workspace of %zu bytes < footprint %zu", bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    const gsis_mesh_s *m = c->mesh;
+    unsigned char *B = (unsigned char *)ws;
+    c->ws = B;
+    c->ws_bytes = bytes;
+    c->capacity = (int32_t)cap;
+    c->tile = tile;
+    c->ntile = ntile;
+    c->row = row;
+    CaseView &h = c->hv;
+    std::memset(&h, 0, sizeof h);
+    h.n_cells = m->n_cells;
+    h.n_faces = m->n_faces;
+    h.n_patches = m->n_patches;
+    h.dim = m->dim;
+    h.nnz = m->nnz;
+    h.vdim = c->vdim;
+    h.nfun = (c->vdim == 3) ? 1 : 2;
+    for (int d = 0; d < 3; ++d) h.n[d] = c->n[d];
+    h.nv = c->nv;
+    h.row = row;
+    h.tile = tile;
+    h.ntile = ntile;
+    h.capacity = (int32_t)cap;
+    h.dtype = c->dtype;
+    h.Kn = c->gas.Kn;
+    h.omega = c->gas.omega;
+    h.Pr = c->gas.Pr;
+    h.inv_dt = 0.0;
+#define P(T, name, off) h.name = (T)(B + L.off)
+    P(const int32_t *, cf_ptr, cf_ptr);
+    P(const int32_t *, cf_face, cf_face);
+    P(const int32_t *, cf_other, cf_other);
+    P(const int32_t *, cf_wall, cf_wall);
+    P(const double *, cf_nsv, cf_nsv);
+    P(const double *, wall_den, wall_den);
+    P(const int32_t *, face_cells, face_cells);
+    P(const double *, face_normal, face_normal);
+    P(const double *, face_area, face_area);
+    P(const double *, face_center, face_center);
+    P(const double *, face_dist, face_dist);
+    P(const double *, cell_volume, cell_volume);
+    P(const double *, cell_center, cell_center);
+    P(const int32_t *, patch_kind, patch_kind);
+    P(const double *, patch_state, patch_state);
+    P(const double *, xv, xv);
+    P(const double *, wv, wv);
+    P(int32_t *, flags, flags);
+    P(int32_t *, slot_of_cell, slot);
+    P(int32_t *, kin_cell, kin);
+    P(int32_t *, n_kin_dev, nkin);
+    P(int32_t *, new_cell, newc);
+    P(int32_t *, n_new_dev, nnew);
+    P(int32_t *, scan_tmp, scan);
+    P(int32_t *, status, status);
+    P(ParamRec *, param, param);
+    P(FeqRec *, feq, feq);
+    P(double *, partial, partial);
+    P(double *, mom, mom);
+    P(double *, W, W);
+    P(double *, Wh, Wh);
+    P(double *, Wn, Wn);
+    P(double *, U, U);
+    P(double *, grad, grad);
+    P(double *, ghost, ghost);
+    P(double *, hot, hot);
+    P(double *, src, src);
+    P(double *, Rk, Rk);
+    P(double *, Rm, Rm);
+    P(double *, fflux, fflux);
+    P(double *, dloc, dloc);
+    P(double *, red, red);
+    P(double *, eps, eps);
+#undef P
+    h.f[0] = B + L.f0;
+    h.f[1] = B + L.f1;
+    c->cv = (CaseView *)(B + L.cv);
+    auto put = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(B + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    const size_t nnz = m->nnz, nf = m->n_faces, nc = m->n_cells;
+    HIPCHK(put(L.cv, &h, sizeof h));
+    HIPCHK(put(L.cf_ptr, m->cf_ptr.data(), 4 * (nc + 1)));
+    HIPCHK(put(L.cf_face, m->cf_face.data(), 4 * nnz));
+    HIPCHK(put(L.cf_other, m->cf_other.data(), 4 * nnz));
+    HIPCHK(put(L.cf_wall, m->cf_wall.data(), 4 * nnz));
+    HIPCHK(put(L.cf_nsv, m->cf_nsv.data(), 24 * nnz));
+    HIPCHK(put(L.face_cells, m->face_cells.data(), 8 * nf));
+    HIPCHK(put(L.face_normal, m->face_normal.data(), 24 * nf));
+    HIPCHK(put(L.face_area, m->face_area.data(), 8 * nf));
+    HIPCHK(put(L.face_center, m->face_center.data(), 24 * nf));
+    HIPCHK(put(L.face_dist, m->face_dist.data(), 8 * nf));
+    HIPCHK(put(L.cell_volume, m->cell_volume.data(), 8 * nc));
+    HIPCHK(put(L.cell_center, m->cell_center.data(), 24 * nc));
+    HIPCHK(put(L.patch_kind, m->patch_kind.data(), 4 * m->n_patches));
+    HIPCHK(put(L.patch_state, m->patch_state.data(), 40 * m->n_patches));
+    HIPCHK(put(L.xv, c->xv, sizeof c->xv));
+    HIPCHK(put(L.wv, c->wv, sizeof c->wv));
+    HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
+    HIPCHK(hipMemsetAsync(B + L.flags, 0, 4 * nc, s));
+    HIPCHK(hipMemsetAsync(B + L.status, 0, 16, s));
+    HIPCHK(hipMemsetAsync(B + L.wall_den, 0, 8 * nnz, s));
+    HIPCHK(hipMemsetAsync(B + L.hot, 0, 72 * nc, s));
+    // padding of the VDF rows stays zero
+    HIPCHK(hipMemsetAsync(B + L.f0, 0, L.f1 - L.f0, s));
+    HIPCHK(hipMemsetAsync(B + L.f1, 0, L.param - L.f1, s));
+    HIPCHK(launch_wall_den(c->cv, h, s));
+    if (!c->ev0) {
+        HIPCHK(hipEventCreate(&c->ev0));
+        HIPCHK(hipEventCreate(&c->ev1));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    c->bound = true;
+    c->state_set = false;
+    c->n_kin = 0;
+    c->cur = 0;
+    return GSIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// state
+// ---------------------------------------------------------------------------
+extern "C" gsis_status gsis_set_state(gsis_case c, const double *W_dev, const void *vdf_dev, const uint8_t *flags_dev,
+                                      void *stream)
+{
+    if (!c || !W_dev) return fail(GSIS_E_ARG, "null argument");
+    if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
+    hipStream_t s = (hipStream_t)stream;
+    CaseView &h = c->hv;
+    HIPCHK(hipMemsetAsync(h.status, 0, 16, s));
+    HIPCHK(launch_copy_W(h.W, W_dev, h.n_cells, s));
+    HIPCHK(launch_check_W(c->cv, h, h.W, s));
+    HIPCHK(hipMemsetAsync(h.slot_of_cell, 0xff, 4 * (size_t)h.n_cells, s));
+    HIPCHK(launch_set_flags(c->cv, h, flags_dev, s));
+    HIPCHK(launch_compact(c->cv, h, s));
+    gsis_status st = read_counts(c, s, nullptr);
+    if (st) return st;
+    c->cur = 0;
+    if (vdf_dev) {
+        HIPCHK(launch_gather_vdf(c->cv, h, c->n_kin, 0, const_cast<void *>(vdf_dev), 1, s));
+        HIPCHK(launch_fill(c->cv, h, 2, c->n_kin, 0, s));
+    } else {
+        HIPCHK(launch_fill(c->cv, h, 0, c->n_kin, 0, s));
+    }
+    HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
+    // W on kinetic cells = moments of the VDF
+    HIPCHK(launch_W_from_mom(c->cv, h, c->n_kin, h.W, s));
+    st = sync_status(c, s);
+    if (st) return st;
+    c->state_set = true;
+    c->iter = 0;
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_n_kinetic(gsis_case c, int64_t *n)
+{
+    if (!c || !n) return fail(GSIS_E_ARG, "null argument");
+    *n = c->n_kin;
+    return GSIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sweeps
+// ---------------------------------------------------------------------------
+namespace {
+
+bool has_ns_cells(gsis_case c) { return c->n_kin < c->hv.n_cells; }
+
+// per-case preparation of one sweep: relaxation parameters from the current
+// moments, Grad-13 ghosts of NS neighbours from W
+gsis_status prepare_sweep(gsis_case c, hipStream_t s)
+{
+    CaseView &h = c->hv;
+    HIPCHK(launch_param(c->cv, h, c->n_kin, s));
+    if (has_ns_cells(c)) {
+        HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
+        HIPCHK(launch_ghost(c->cv, h, h.W, s));
+    }
+    return GSIS_OK;
+}
+
+gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool timed)
+{
+    for (int i0 = 0; i0 < n; i0 += MAX_BATCH) {
+        Batch b{};
+        int m = std::min(MAX_BATCH, n - i0);
+        b.n = m;
+        b.start[0] = 0;
+        for (int j = 0; j < m; ++j) {
+            gsis_case c = cases[i0 + j];
+            b.cv[j] = c->cv;
+            b.start[j + 1] = b.start[j] + c->n_kin * c->ntile;
+        }
+        // buffers: every case of a batch sweeps cur -> cur ^ 1 with its own cur
+        // (the kernel takes one value; cases are grouped by cur below)
+        int cur0 = cases[i0]->cur;
+        for (int j = 1; j < m; ++j)
+            if (cases[i0 + j]->cur != cur0) return fail(GSIS_E_STATE, "batched cases are at different buffer parity");
+        if (timed && i0 == 0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
+        HIPCHK(launch_sweep(b, cases[i0]->hv, cur0, b.start[m], s));
+        if (timed && i0 + MAX_BATCH >= n) HIPCHK(hipEventRecord(cases[0]->ev1, s));
+    }
+    for (int j = 0; j < n; ++j) {
+        cases[j]->cur ^= 1;
+        cases[j]->timed = timed;
+    }
+    return GSIS_OK;
+}
+
+gsis_status check_batch(gsis_case const *cases, int n)
+{
+    if (!cases || n <= 0) return fail(GSIS_E_ARG, "no cases");
+    for (int j = 0; j < n; ++j) {
+        gsis_status st = check_ready(cases[j]);
+        if (st) return st;
+        if (cases[j]->dtype != cases[0]->dtype || cases[j]->vdim != cases[0]->vdim)
+            return fail(GSIS_E_ARG, "batched cases must share dtype and vdim");
+        for (int d = 0; d < 3; ++d)
+            if (cases[j]->n[d] > cases[0]->n[d] && j > 0) {
+                // LDS is sized from the first case: put the largest grid first
+                return fail(GSIS_E_ARG, "batched cases: the first case must have the largest velocity axes");
+            }
+        for (int i = 0; i < j; ++i)
+            if (cases[i] == cases[j]) return fail(GSIS_E_ARG, "a case appears twice in the batch");
+    }
+    return GSIS_OK;
+}
+
+}  // namespace
+
+extern "C" gsis_status gsis_kinetic_sweep(gsis_case const *cases, int32_t n_cases, int32_t n_sweeps, void *stream)
+{
+    gsis_status st = check_batch(cases, n_cases);
+    if (st) return st;
+    if (n_sweeps < 0) return fail(GSIS_E_ARG, "n_sweeps < 0");
+    hipStream_t s = (hipStream_t)stream;
+    for (int it = 0; it < n_sweeps; ++it) {
+        for (int j = 0; j < n_cases; ++j)
+            if ((st = prepare_sweep(cases[j], s))) return st;
+        if ((st = batched_sweep(cases, n_cases, s, true))) return st;
+        for (int j = 0; j < n_cases; ++j) {
+            gsis_case c = cases[j];
+            HIPCHK(launch_reduce(c->cv, c->hv, c->n_kin, 1, s));
+            HIPCHK(launch_W_from_mom(c->cv, c->hv, c->n_kin, c->hv.W, s));
+        }
+    }
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_last_sweep_ms(gsis_case c, float *ms)
+{
+    if (!c || !ms) return fail(GSIS_E_ARG, "null argument");
+    if (!c->timed) return fail(GSIS_E_STATE, "no timed sweep on this case");
+    HIPCHK(hipEventSynchronize(c->ev1));
+    HIPCHK(hipEventElapsedTime(ms, c->ev0, c->ev1));
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_moments(gsis_case c, double *out, int32_t *kc, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!out) return fail(GSIS_E_ARG, "null output");
+    HIPCHK(launch_moments_out(c->cv, c->hv, c->n_kin, out, kc, (hipStream_t)stream));
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_get_vdf(gsis_case c, void *out, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!out) return fail(GSIS_E_ARG, "null output");
+    HIPCHK(launch_gather_vdf(c->cv, c->hv, c->n_kin, c->cur, out, 0, (hipStream_t)stream));
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_get_state(gsis_case c, double *W, uint8_t *flags, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (W) HIPCHK(launch_copy_W(W, c->hv.W, c->hv.n_cells, s));
+    if (flags) HIPCHK(launch_get_flags(c->cv, c->hv, flags, s));
+    return GSIS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// regions
+// ---------------------------------------------------------------------------
+extern "C" gsis_status gsis_update_regions(gsis_case c, double Kn_ref, int32_t layers, int64_t *n_host, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!(Kn_ref >= 0) || layers < 0) return fail(GSIS_E_ARG, "bad Kn_ref or layers");
+    hipStream_t s = (hipStream_t)stream;
+    CaseView &h = c->hv;
+    HIPCHK(launch_flags(c->cv, h, Kn_ref, layers, s));
+    HIPCHK(launch_compact(c->cv, h, s));
+    int n_new = 0;
+    if ((st = read_counts(c, s, &n_new))) return st;
+    if (n_new > 0) {
+        // Grad-13 of the current W (gradients of u, T are in grad after launch_flags)
+        HIPCHK(launch_ghost(c->cv, h, h.W, s));
+        HIPCHK(launch_fill(c->cv, h, 1, n_new, c->cur, s));
+    }
+    HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
+    if (n_host) *n_host = c->n_kin;
+    return sync_status(c, s);
+}
+
+// ---------------------------------------------------------------------------
+// outer iteration
+// ---------------------------------------------------------------------------
+namespace {
+
+gsis_status post_sweep(gsis_case c, const gsis_solve_params *p, hipStream_t s)
+{
+    CaseView &h = c->hv;
+    HIPCHK(launch_reduce(c->cv, h, c->n_kin, 1, s));
+    if (p->mode == GSIS_MODE_DVM) {
+        HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
+        HIPCHK(launch_W_from_mom(c->cv, h, c->n_kin, h.Wn, s));
+    } else {
+        HIPCHK(launch_whalf(c->cv, h, c->n_kin, s));
+        // high-order terms from f^{n+1/2} and gradients of W^{n+1/2}
+        HIPCHK(launch_lsq(c->cv, h, h.Wh, 4, s));
+        HIPCHK(launch_hot(c->cv, h, c->n_kin, s));
+        // source: kinetic moment balance at f^n minus synthetic residual at W^n
+        HIPCHK(launch_macro_residual(c->cv, h, h.W, h.hot, h.Rm, s));
+        HIPCHK(launch_src(c->cv, h, c->n_kin, s));
+        HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
+        HIPCHK(launch_macro_steps(c->cv, h, h.Wn, h.hot, h.src, p->n_macro_inner, p->cfl, s));
+        // GSIS correction f += f_eq(W^{n+1}) - f_eq(W^{n+1/2})
+        HIPCHK(launch_feqpar(c->cv, h, c->n_kin, s));
+        HIPCHK(launch_correct(c->cv, h, c->n_kin, c->cur, s));
+        HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
+    }
+    HIPCHK(launch_eps(c->cv, h, h.Wn, h.W, s));
+    HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+    return GSIS_OK;
+}
+
+gsis_status check_params(const gsis_solve_params *p)
+{
+    if (!p) return fail(GSIS_E_ARG, "null params");
+    if (p->mode < GSIS_MODE_DVM || p->mode > GSIS_MODE_AGSIS) return fail(GSIS_E_ARG, "bad mode");
+    if (p->mode != GSIS_MODE_DVM && (p->n_macro_inner < 0 || p->cfl == 0 || !std::isfinite(p->cfl)))
+        return fail(GSIS_E_ARG, "bad macro parameters");
+    return GSIS_OK;
+}
+
+}  // namespace
+
+extern "C" gsis_status gsis_step(gsis_case const *cases, int32_t n, const gsis_solve_params *p, double *eps_host,
+                                 void *stream)
+{
+    gsis_status st = check_batch(cases, n);
+    if (st) return st;
+    if ((st = check_params(p))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    for (int j = 0; j < n; ++j)
+        if ((st = prepare_sweep(cases[j], s))) return st;
+    if ((st = batched_sweep(cases, n, s, true))) return st;
+    for (int j = 0; j < n; ++j)
+        if ((st = post_sweep(cases[j], p, s))) return st;
+    for (int j = 0; j < n; ++j) {
+        gsis_case c = cases[j];
+        c->iter++;
+        if (p->mode == GSIS_MODE_AGSIS && p->region_update_every > 0 && c->iter % p->region_update_every == 0)
+            if ((st = gsis_update_regions(c, p->Kn_ref, p->force_wall_layers, nullptr, stream))) return st;
+    }
+    if (eps_host) {
+        for (int j = 0; j < n; ++j) {
+            double e[3];
+            HIPCHK(hipMemcpyAsync(e, cases[j]->hv.eps, sizeof e, hipMemcpyDeviceToHost, s));
+            if ((st = sync_status(cases[j], s))) return st;
+            for (int k = 0; k < 3; ++k) eps_host[3 * j + k] = e[k];
+        }
+    }
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_correct(gsis_case c, const double *W_new, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!W_new) return fail(GSIS_E_ARG, "null W_new");
+    hipStream_t s = (hipStream_t)stream;
+    CaseView &h = c->hv;
+    HIPCHK(launch_whalf(c->cv, h, c->n_kin, s));
+    HIPCHK(launch_copy_W(h.Wn, W_new, h.n_cells, s));
+    HIPCHK(launch_check_W(c->cv, h, h.Wn, s));
+    HIPCHK(launch_feqpar(c->cv, h, c->n_kin, s));
+    HIPCHK(launch_correct(c->cv, h, c->n_kin, c->cur, s));
+    HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
+    HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_macro_solve(gsis_case c, double *W, const double *hot, const double *src, int32_t n_inner,
+                                        double cfl, void *stream)
+{
+    if (!c || !W || !hot) return fail(GSIS_E_ARG, "null argument");
+    if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
+    if (n_inner < 0 || cfl == 0 || !std::isfinite(cfl)) return fail(GSIS_E_ARG, "bad n_inner or cfl");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemsetAsync(c->hv.status, 0, 16, s));
+    HIPCHK(launch_check_W(c->cv, c->hv, W, s));
+    HIPCHK(launch_macro_steps(c->cv, c->hv, W, hot, src, n_inner, cfl, s));
+    return sync_status(c, s);
+}
+
+extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p, gsis_solve_result *r, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if ((st = check_params(p))) return st;
+    if (!r) return fail(GSIS_E_ARG, "null result");
+    if (!(p->tol > 0) || p->max_iter <= 0) return fail(GSIS_E_ARG, "bad tol or max_iter");
+    hipStream_t s = (hipStream_t)stream;
+    CaseView &h = c->hv;
+    std::memset(r, 0, sizeof *r);
+    if (p->mode == GSIS_MODE_AGSIS && p->ns_init) {
+        // Step 1: macroscopic solve alone (HoT = 0) to eps < tol
+        HIPCHK(hipMemsetAsync(h.hot, 0, 72 * (size_t)h.n_cells, s));
+        int chunks = p->ns_init_max_chunks > 0 ? p->ns_init_max_chunks : 1000;
+        for (int k = 0; k < chunks; ++k) {
+            HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
+            HIPCHK(launch_macro_steps(c->cv, h, h.Wn, h.hot, nullptr, p->n_macro_inner, p->cfl, s));
+            HIPCHK(launch_eps(c->cv, h, h.Wn, h.W, s));
+            HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+            double e[3];
+            HIPCHK(hipMemcpyAsync(e, h.eps, sizeof e, hipMemcpyDeviceToHost, s));
+            if ((st = sync_status(c, s))) return st;
+            if (std::max(e[0], std::max(e[1], e[2])) < p->tol) break;
+        }
+        // Step 2: first flagging
+        if ((st = gsis_update_regions(c, p->Kn_ref, p->force_wall_layers, nullptr, stream))) return st;
+    }
+    double eps[3] = {1, 1, 1};
+    for (int it = 0; it < p->max_iter; ++it) {
+        if ((st = gsis_step(&c, 1, p, eps, stream))) return st;
+        r->iterations = it + 1;
+        for (int k = 0; k < 3; ++k) r->eps[k] = eps[k];
+        r->n_kinetic = c->n_kin;
+        if (std::max(eps[0], std::max(eps[1], eps[2])) < p->tol) return GSIS_OK;
+    }
+    return fail(GSIS_E_NOCONV, "not converged after %d iterations (eps %g %g %g)", p->max_iter, eps[0], eps[1], eps[2]);
+}

@@ -1,0 +1,166 @@
+// gsis_impl.hpp -- internal declarations shared by the library's HIP sources.
+//
+// A bound case lives entirely inside one caller-owned device workspace.  The
+// device-side view of that workspace is a CaseView (plain pointers and
+// sizes), itself stored at the start of the workspace so that kernels, graph
+// replays and batched launches can find every array from one pointer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsis.h"
+
+namespace gsis {
+
+constexpr int BLOCK = 256;             // threads per block of the streaming kernels
+constexpr int MAXF = GSIS_MAX_FACES;
+constexpr int MAXW = GSIS_MAX_WALL_FACES;
+constexpr int MAXA = GSIS_MAX_AXIS;
+constexpr int NSUM = 24;               // per (slot, tile) partial sums, see below
+constexpr int MAX_BATCH = 16;          // cases per batched launch
+
+// Partial sums written by every kernel that produces a VDF (init, sweep,
+// correction), per (slot, velocity tile), relative to the slot's reference
+// velocity u_ref = ParamRec::u:
+//   3D: [0] sum w f, [1..3] sum w f c, [4..9] sum w f c_d c_e (xx yy zz xy xz yz),
+//       [10..12] sum w f c^2 c_d
+//   2D: [0] sum w phi, [1..2] sum w phi c, [3..5] (xx yy xy), [6..7] sum w phi c^2 c_d,
+//       [8] sum w psi, [9..10] sum w psi c_d
+//   [13..17] moment balance of the kinetic scheme at the old iterate
+//       sum w D (f_new - f_old) (1, c_x, c_y, c_z, c^2 [+ psi]) (sweep only)
+//   [18..21] sum_{a > 0} w a phi per wall face of the cell (a = xi.n S/V)
+enum { S_RES = 13, S_WALL = 18 };
+
+// Per-slot parameters of the relaxation target (FP64; Sec. 2 reference
+// distribution specialised to d_r = 0, with the conservation fix-up).
+struct ParamRec {
+    double u[3];      // mean velocity of f^n (reference frame of the sums)
+    double it;        // 1 / T
+    double Th;        // T / 2 (psi factor of the reduced pair)
+    double itau;      // 1 / tau
+    double kq[3];     // K q_d, K = (4/5)(1 - Pr) / (p T)
+    double fx[5];     // fix-up multiplier (a0, a_x, a_y, [a_z], b), amplitude folded in
+    double rw[MAXW];  // densities of the diffuse-wall faces (Jacobi: from f^n)
+    double pad[3];
+};
+
+// Conservation-fixed Maxwellian f_eq(W) (Sec. 3.2): amplitude-folded
+// multiplier (a0 + a.c + b c^2) times exp(-c^2/T), c = xi - u.
+struct FeqRec {
+    double u[3];
+    double it;
+    double Th;
+    double fx[5];
+};
+
+// Grad-13 source coefficients (Sec. 3.2 eq. G13_VDF) for one cell state.
+struct G13Rec {
+    double A;         // rho (pi T)^(-3/2)  [2D: rho / (pi T)]
+    double u[3];
+    double it, T;
+    double s[6];      // sigma / (p T)   (xx yy zz xy xz yz)
+    double q[3];      // 2 q / (p T)
+};
+
+struct CaseView {
+    // sizes
+    int32_t n_cells, n_faces, n_patches, dim, nnz;
+    int32_t vdim, nfun, n[3], nv, row;      // row = nfun * nv_pad (elements per slot)
+    int32_t tile, ntile;
+    int32_t capacity;
+    int32_t dtype;
+    double Kn, omega, Pr, inv_dt;
+    // mesh
+    const int32_t *cf_ptr;      // [n_cells + 1]
+    const int32_t *cf_face;     // [nnz] face id
+    const int32_t *cf_other;    // [nnz] neighbour cell, or -1 - patch
+    const int32_t *cf_wall;     // [nnz] wall-sum index of the face in its cell, -1 otherwise
+    const double *cf_nsv;       // [nnz][3] outward n S / V
+    const double *wall_den;     // [nnz] sum_{xi.n<0} w |xi.n| M(1, u_w, T_w) (wall faces)
+    const int32_t *face_cells;  // [n_faces][2]
+    const double *face_normal;  // [n_faces][3]
+    const double *face_area;
+    const double *face_center;  // [n_faces][3]
+    const double *face_dist;    // [n_faces] normal distance between centroids (interior) or twice
+                                // the centroid-face normal distance (boundary)
+    const double *cell_volume;
+    const double *cell_center;  // [n_cells][3]
+    const int32_t *patch_kind;
+    const double *patch_state;  // [n_patches][5]
+    const double *xv;           // [3][MAXA] nodes
+    const double *wv;           // [3][MAXA] weights
+    // region
+    int32_t *flags;             // [n_cells] 1 = kinetic
+    int32_t *slot_of_cell;      // [n_cells], -1 for NS cells
+    int32_t *kin_cell;          // [capacity] ascending cell id
+    int32_t *n_kin_dev;         // device copy of the kinetic count
+    int32_t *new_cell;          // [capacity] cells that became kinetic at the last update
+    int32_t *n_new_dev;
+    int32_t *scan_tmp;          // [max(n_cells, capacity) + 1024] scratch for scans
+    int32_t *status;            // [4] sticky error flags (0 nonfinite, 1 capacity)
+    // kinetic state
+    void *f[2];                 // VDF double buffer [capacity][row]
+    ParamRec *param;            // [capacity]
+    FeqRec *feq;                // [capacity][2] (new, half)
+    double *partial;            // [capacity][ntile][NSUM]
+    double *mom;                // [capacity][GSIS_NMOM + MAXW]
+    // macroscopic state (FP64, every cell)
+    double *W;                  // [n_cells][5] current W^n
+    double *Wh;                 // [n_cells][5] W^{n+1/2}
+    double *Wn;                 // [n_cells][5] work / W^{n+1}
+    double *U;                  // [n_cells][5] conserved
+    double *grad;               // [n_cells][6][3]  (ux uy uz T rho |u|)
+    double *ghost;              // [n_cells][GSIS_NMOM] Grad-13 parameters
+    double *hot;                // [n_cells][9]
+    double *src;                // [n_cells][5]
+    double *Rk;                 // [n_cells][5] kinetic moment balance per unit volume
+    double *Rm;                 // [n_cells][5]
+    double *fflux;              // [n_faces][5]
+    double *dloc;               // [n_cells]
+    double *red;                // [1024 * 8] reduction scratch
+    double *eps;                // [8]
+};
+
+struct Batch {
+    const CaseView *cv[MAX_BATCH];
+    int32_t start[MAX_BATCH + 1];   // prefix of work items (blocks) per case
+    int32_t n;
+};
+
+// --- launch wrappers (gsis_kinetic.hip) ---------------------------------------
+hipError_t launch_wall_den(const CaseView *cv, const CaseView &h, hipStream_t s);
+// mode 0: conservation-fixed Maxwellian of W on the kinetic cells; mode 1:
+// Grad-13 of ghost[] on the new cells; mode 2: keep the rows, recompute sums
+hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s);
+hipError_t launch_reduce(const CaseView *cv, const CaseView &h, int n_kin, int with_res, hipStream_t s);
+hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+hipError_t launch_sweep(const Batch &b, const CaseView &h0, int cur, int total_items, hipStream_t s);
+hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
+hipError_t launch_gather_vdf(const CaseView *cv, const CaseView &h, int n_kin, int cur, void *out, int dir,
+                             hipStream_t s);
+
+// --- launch wrappers (gsis_macro.hip) ----------------------------------------
+hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s);
+hipError_t launch_ghost(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s);
+hipError_t launch_hot(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+hipError_t launch_whalf(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const double *W, const double *hot,
+                                 double *Rout, hipStream_t s);
+hipError_t launch_src(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, const double *hot,
+                              const double *src, int n_inner, double cfl, hipStream_t s);
+hipError_t launch_eps(const CaseView *cv, const CaseView &h, const double *Wnew, const double *Wold,
+                      hipStream_t s);
+hipError_t launch_flags(const CaseView *cv, const CaseView &h, double Kn_ref, int layers, hipStream_t s);
+hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s);
+hipError_t launch_copy_W(double *dst, const double *src, int n, hipStream_t s);
+hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t *flags, hipStream_t s);
+hipError_t launch_get_flags(const CaseView *cv, const CaseView &h, uint8_t *flags, hipStream_t s);
+hipError_t launch_moments_out(const CaseView *cv, const CaseView &h, int n_kin, double *out, int32_t *kc,
+                              hipStream_t s);
+hipError_t launch_W_from_mom(const CaseView *cv, const CaseView &h, int n_kin, double *W, hipStream_t s);
+hipError_t launch_check_W(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s);
+
+}  // namespace gsis

@@ -1,0 +1,1083 @@
+// gsis_kinetic.hip -- kinetic-side kernels for gfx950.
+//
+// Hot path of Sec. 3.1 (Zhang, Zeng & Wu, arXiv 2501.02245): the implicit
+// discrete-velocity update over the kinetic cells with first-order upwind
+// face values and point-Jacobi lagging, the velocity-moment reduction of
+// Sec. 2 (eq. getmoment) fused into its epilogue, the per-cell relaxation
+// parameters with the conservation fix-up, and the GSIS correction (first
+// eq. updatef).
+//
+// Layout: VDF rows are velocity-innermost, one row of nfun * nv_pad values
+// per kinetic slot ([slot][fun][k]); consecutive lanes touch consecutive k,
+// so every global access of the streaming kernels is coalesced.  One block of
+// 256 threads handles one (kinetic cell, velocity tile); blocks are numbered
+// tile-major and remapped so that each of the eight XCDs walks a contiguous
+// run of cells (neighbour rows then meet in that XCD's L2).  Face data,
+// node/weight tables and the separable Gaussian factor tables
+// exp(-(x_j - u_d)^2 / T) of every Maxwellian the block needs live in LDS, so
+// a point's equilibrium costs three LDS reads and two multiplies, no exp.
+#include <math.h>
+
+#include "gsis_impl.hpp"
+
+namespace gsis {
+
+enum { K_KIN = 0, K_WALL = 1, K_FAR = 2, K_GHOST = 3 };
+
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    // Workgroups are dispatched round-robin over 8 XCDs; give XCD x the
+    // contiguous logical range [x q + min(x, rem), ...).
+    const int X = 8;
+    int x = b % X, r = b / X, q = nb / X, rem = nb % X;
+    return x * q + min(x, rem) + r;
+}
+
+template <int NS>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NS], double *out, double *lds)
+{
+    // fixed-order butterfly inside each wave, then the four waves in order
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[i] = x;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) lds[wave * NS + i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        double s = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) s += lds[w * NS + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// velocity-node index of point k and the per-256 increment
+struct VIdx {
+    int ix, iy, iz;
+    int dx, dy, dz;
+};
+
+template <int VD>
+__device__ __forceinline__ VIdx vidx_init(int k, int n1, int n2)
+{
+    VIdx v;
+    if (VD == 3) {
+        v.iz = k % n2;
+        int r = k / n2;
+        v.iy = r % n1;
+        v.ix = r / n1;
+        v.dz = BLOCK % n2;
+        int q = BLOCK / n2;
+        v.dy = q % n1;
+        v.dx = q / n1;
+    } else {
+        v.iz = 0;
+        v.iy = k % n1;
+        v.ix = k / n1;
+        v.dz = 0;
+        v.dy = BLOCK % n1;
+        v.dx = BLOCK / n1;
+    }
+    return v;
+}
+
+template <int VD>
+__device__ __forceinline__ void vidx_step(VIdx &v, int n1, int n2)
+{
+    if (VD == 3) {
+        v.iz += v.dz;
+        int c = v.iz >= n2;
+        v.iz -= c ? n2 : 0;
+        v.iy += v.dy + c;
+        int c2 = v.iy >= n1;
+        v.iy -= c2 ? n1 : 0;
+        v.ix += v.dx + c2;
+    } else {
+        v.iy += v.dy;
+        int c = v.iy >= n1;
+        v.iy -= c ? n1 : 0;
+        v.ix += v.dx + c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell FP64 algebra: separable Gaussian moments and the fix-up solve
+// ---------------------------------------------------------------------------
+struct GMom {
+    double g[3][8];   // g[d][p] = sum_j w_j c^p exp(-c^2/T), c = x_j - u_d
+};
+
+__device__ void gauss_moments(const CaseView &C, const double *u, double it, GMom &G)
+{
+    for (int d = 0; d < C.vdim; ++d) {
+        for (int p = 0; p < 8; ++p) G.g[d][p] = 0.0;
+        for (int j = 0; j < C.n[d]; ++j) {
+            double c = C.xv[d * MAXA + j] - u[d];
+            double e = C.wv[d * MAXA + j] * exp(-c * c * it);
+            double cp = 1.0;
+            for (int p = 0; p < 8; ++p) {
+                G.g[d][p] += e * cp;
+                cp *= c;
+            }
+        }
+    }
+    if (C.vdim == 2)
+        for (int p = 0; p < 8; ++p) G.g[2][p] = (p == 0) ? 1.0 : 0.0;
+}
+
+__device__ __forceinline__ double gs(const GMom &G, int i, int j, int k) { return G.g[0][i] * G.g[1][j] * G.g[2][k]; }
+
+// sum_k w c^(i,j,k) E (1 + kq.c (c^2/T - 5/2))   (3D Shakhov weight)
+__device__ double sh3(const GMom &G, const double *kq, double it, int i, int j, int k)
+{
+    double v = gs(G, i, j, k);
+    if (kq) {
+        v += kq[0] * ((gs(G, i + 3, j, k) + gs(G, i + 1, j + 2, k) + gs(G, i + 1, j, k + 2)) * it - 2.5 * gs(G, i + 1, j, k));
+        v += kq[1] * ((gs(G, i + 2, j + 1, k) + gs(G, i, j + 3, k) + gs(G, i, j + 1, k + 2)) * it - 2.5 * gs(G, i, j + 1, k));
+        v += kq[2] * ((gs(G, i + 2, j, k + 1) + gs(G, i, j + 2, k + 1) + gs(G, i, j, k + 3)) * it - 2.5 * gs(G, i, j, k + 1));
+    }
+    return v;
+}
+
+// reduced pair: phi weight (1 + kq.c (c^2/T - 2)), psi weight (T/2)(1 + kq.c (c^2/T - 1))
+__device__ double sh2(const GMom &G, const double *kq, double it, double shift, int i, int j)
+{
+    double v = gs(G, i, j, 0);
+    if (kq) {
+        v += kq[0] * ((gs(G, i + 3, j, 0) + gs(G, i + 1, j + 2, 0)) * it - shift * gs(G, i + 1, j, 0));
+        v += kq[1] * ((gs(G, i + 2, j + 1, 0) + gs(G, i, j + 3, 0)) * it - shift * gs(G, i, j + 1, 0));
+    }
+    return v;
+}
+
+__device__ int solve_dense(int n, double *A, double *b)
+{
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(A[r * n + col]) > fabs(A[piv * n + col])) piv = r;
+        if (!(fabs(A[piv * n + col]) > 0.0)) return -1;
+        if (piv != col) {
+            for (int j = 0; j < n; ++j) {
+                double t = A[col * n + j];
+                A[col * n + j] = A[piv * n + j];
+                A[piv * n + j] = t;
+            }
+            double t = b[col];
+            b[col] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = col + 1; r < n; ++r) {
+            double fac = A[r * n + col] / A[col * n + col];
+            for (int j = col; j < n; ++j) A[r * n + j] -= fac * A[col * n + j];
+            b[r] -= fac * b[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int j = r + 1; j < n; ++j) s -= A[r * n + j] * b[j];
+        b[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+// Multiplier (a0, a, b) of the unit-amplitude target E * S(c) (S = Shakhov
+// factor, or 1 when kq == nullptr) so that its discrete mass, momentum and
+// energy in the frame u equal (rho, 0, 3 rho T / 2).
+__device__ int fixup_coefs(const CaseView &C, const double *u, double T, double rho, const double *kq, double *fx)
+{
+    GMom G;
+    double it = 1.0 / T;
+    gauss_moments(C, u, it, G);
+    if (C.vdim == 3) {
+        const int nb = 5;
+        // basis monomials: 1, cx, cy, cz, c^2 (three terms)
+        const int bm[5][3][3] = {{{0, 0, 0}, {-1, 0, 0}, {-1, 0, 0}},
+                                 {{1, 0, 0}, {-1, 0, 0}, {-1, 0, 0}},
+                                 {{0, 1, 0}, {-1, 0, 0}, {-1, 0, 0}},
+                                 {{0, 0, 1}, {-1, 0, 0}, {-1, 0, 0}},
+                                 {{2, 0, 0}, {0, 2, 0}, {0, 0, 2}}};
+        double A[25], b[5];
+        for (int a = 0; a < nb; ++a)
+            for (int c = 0; c < nb; ++c) {
+                double s = 0.0;
+                for (int ta = 0; ta < 3 && bm[a][ta][0] >= 0; ++ta)
+                    for (int tb = 0; tb < 3 && bm[c][tb][0] >= 0; ++tb)
+                        s += sh3(G, kq, it, bm[a][ta][0] + bm[c][tb][0], bm[a][ta][1] + bm[c][tb][1],
+                                 bm[a][ta][2] + bm[c][tb][2]);
+                A[a * nb + c] = s;
+            }
+        b[0] = rho; b[1] = b[2] = b[3] = 0.0; b[4] = 1.5 * rho * T;
+        if (solve_dense(nb, A, b)) return -1;
+        for (int a = 0; a < 5; ++a) fx[a] = b[a];
+    } else {
+        const int nb = 4;
+        const int bm[4][2][2] = {{{0, 0}, {-1, 0}}, {{1, 0}, {-1, 0}}, {{0, 1}, {-1, 0}}, {{2, 0}, {0, 2}}};
+        double A[16], b[4];
+        for (int a = 0; a < nb; ++a)
+            for (int c = 0; c < nb; ++c) {
+                double s = 0.0;
+                for (int ta = 0; ta < 2 && bm[a][ta][0] >= 0; ++ta)
+                    for (int tb = 0; tb < 2 && bm[c][tb][0] >= 0; ++tb)
+                        s += sh2(G, kq, it, 2.0, bm[a][ta][0] + bm[c][tb][0], bm[a][ta][1] + bm[c][tb][1]);
+                if (a == 3)   // energy row adds the psi function, test function 1
+                    for (int tb = 0; tb < 2 && bm[c][tb][0] >= 0; ++tb)
+                        s += 0.5 * T * sh2(G, kq, it, 1.0, bm[c][tb][0], bm[c][tb][1]);
+                A[a * nb + c] = s;
+            }
+        b[0] = rho; b[1] = b[2] = 0.0; b[3] = 1.5 * rho * T;
+        if (solve_dense(nb, A, b)) return -1;
+        for (int a = 0; a < 4; ++a) fx[a] = b[a];
+        fx[4] = 0.0;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// bind-time: wall-flux denominators sum_{a<0} w |a| M(1, u_w, T_w)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_wall_den(const CaseView *__restrict__ cvp, int nnz)
+{
+    const CaseView &C = *cvp;
+    __shared__ double lds[BLOCK / 64];
+    for (int e = blockIdx.x; e < nnz; e += gridDim.x) {
+        int oth = C.cf_other[e];
+        if (oth >= 0 || C.patch_kind[-1 - oth] != GSIS_PATCH_WALL) continue;   // block-uniform
+        const double *ps = C.patch_state + 5 * (-1 - oth);
+        const double *n = C.cf_nsv + 3 * e;
+        double T = ps[4], it = 1.0 / T;
+        double amp = (C.vdim == 3) ? pow(M_PI * T, -1.5) : 1.0 / (M_PI * T);
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
+            int ix, iy, iz = 0;
+            if (C.vdim == 3) { iz = k % C.n[2]; iy = (k / C.n[2]) % C.n[1]; ix = k / (C.n[2] * C.n[1]); }
+            else { iy = k % C.n[1]; ix = k / C.n[1]; }
+            double xi[3] = {C.xv[ix], C.xv[MAXA + iy], (C.vdim == 3) ? C.xv[2 * MAXA + iz] : 0.0};
+            double w = C.wv[ix] * C.wv[MAXA + iy] * ((C.vdim == 3) ? C.wv[2 * MAXA + iz] : 1.0);
+            double a = xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2];
+            if (a < 0) {
+                double c2 = 0.0;
+                for (int d = 0; d < C.vdim; ++d) c2 += (xi[d] - ps[1 + d]) * (xi[d] - ps[1 + d]);
+                acc += w * (-a) * amp * exp(-c2 * it);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < BLOCK / 64; ++w) s += lds[w];
+            const_cast<double *>(C.wall_den)[e] = s;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_wall_den(const CaseView *cv, const CaseView &h, hipStream_t s)
+{
+    const int nnz = h.nnz;
+    int grid = nnz < 4096 ? (nnz > 0 ? nnz : 1) : 4096;
+    hipLaunchKernelGGL(k_wall_den, dim3(grid), dim3(BLOCK), 0, s, cv, nnz);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// tile sums -> moments (FP64), kinetic moment balance, wall numerators
+// ---------------------------------------------------------------------------
+__global__ void k_reduce(const CaseView *__restrict__ cvp, int n_kin, int with_res)
+{
+    const CaseView &C = *cvp;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_kin) return;
+    int cell = C.kin_cell[t];
+    int slot = C.slot_of_cell[cell];
+    double S[NSUM];
+    for (int i = 0; i < NSUM; ++i) S[i] = 0.0;
+    const double *P = C.partial + (size_t)slot * C.ntile * NSUM;
+    for (int tl = 0; tl < C.ntile; ++tl)
+        for (int i = 0; i < NSUM; ++i) S[i] += P[tl * NSUM + i];
+    const double *ur = C.param[slot].u;
+    double *mom = C.mom + (size_t)slot * (GSIS_NMOM + MAXW);
+    double rho = S[0];
+    double dl[3] = {S[1] / rho, S[2] / rho, (C.vdim == 3) ? S[3] / rho : 0.0};
+    double c2[3][3];
+    double q[3] = {0, 0, 0};
+    double P0 = 0.0, P1[3] = {0, 0, 0};
+    if (C.vdim == 3) {
+        double S2[3][3] = {{S[4], S[7], S[8]}, {S[7], S[5], S[9]}, {S[8], S[9], S[6]}};
+        double tr = S[4] + S[5] + S[6];
+        double d2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) c2[a][b] = S2[a][b] - rho * dl[a] * dl[b];
+        for (int d = 0; d < 3; ++d) {
+            double s2d = S2[d][0] * dl[0] + S2[d][1] * dl[1] + S2[d][2] * dl[2];
+            q[d] = S[10 + d] - dl[d] * tr - 2.0 * s2d + 2.0 * rho * d2 * dl[d];
+        }
+    } else {
+        double S2[3][3] = {{S[3], S[5], 0}, {S[5], S[4], 0}, {0, 0, 0}};
+        double tr = S[3] + S[4];
+        double d2 = dl[0] * dl[0] + dl[1] * dl[1];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) c2[a][b] = S2[a][b] - rho * dl[a] * dl[b];
+        P0 = S[8];
+        P1[0] = S[9] - dl[0] * P0;
+        P1[1] = S[10] - dl[1] * P0;
+        for (int d = 0; d < 2; ++d) {
+            double s2d = S2[d][0] * dl[0] + S2[d][1] * dl[1];
+            q[d] = S[6 + d] - dl[d] * tr - 2.0 * s2d + 2.0 * rho * d2 * dl[d] + P1[d];
+        }
+    }
+    double e = c2[0][0] + c2[1][1] + c2[2][2] + P0;   // sum w (c^2 phi + psi)
+    double p = (2.0 / 3.0) * e;
+    mom[0] = rho;
+    for (int d = 0; d < 3; ++d) mom[1 + d] = ur[d] + dl[d];
+    if (C.vdim == 2) mom[3] = 0.0;
+    mom[4] = p / rho;
+    mom[5] = 2.0 * c2[0][0] - p;
+    mom[6] = 2.0 * c2[1][1] - p;
+    mom[7] = (C.vdim == 3) ? 2.0 * c2[2][2] - p : 2.0 * P0 - p;
+    mom[8] = 2.0 * c2[0][1];
+    mom[9] = 2.0 * c2[0][2];
+    mom[10] = 2.0 * c2[1][2];
+    for (int d = 0; d < 3; ++d) mom[11 + d] = q[d];
+    for (int w = 0; w < MAXW; ++w) mom[GSIS_NMOM + w] = S[S_WALL + w];
+    int bad = !(rho > 0.0) || !(p > 0.0) || !isfinite(q[0] + q[1] + q[2] + mom[5] + mom[8]);
+    if (bad) atomicOr(C.status, 1);
+    if (with_res) {
+        double *R = C.Rk + 5 * (size_t)cell;
+        double r0 = S[S_RES];
+        double rc[3] = {S[S_RES + 1], S[S_RES + 2], S[S_RES + 3]};
+        double re = S[S_RES + 4];
+        R[0] = r0;
+        for (int d = 0; d < 3; ++d) R[1 + d] = rc[d] + ur[d] * r0;
+        double u2 = ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2];
+        R[4] = re + 2.0 * (ur[0] * rc[0] + ur[1] * rc[1] + ur[2] * rc[2]) + u2 * r0;
+    }
+}
+
+hipError_t launch_reduce(const CaseView *cv, const CaseView &h, int n_kin, int with_res, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3((n_kin + 127) / 128), dim3(128), 0, s, cv, n_kin, with_res);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// relaxation parameters of the next sweep (Sec. 2: tau = mu/p, Shakhov
+// target of the d_r = 0 model, conservation fix-up), wall densities
+// ---------------------------------------------------------------------------
+__global__ void k_param(const CaseView *__restrict__ cvp, int n_kin)
+{
+    const CaseView &C = *cvp;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_kin) return;
+    int cell = C.kin_cell[t];
+    int slot = C.slot_of_cell[cell];
+    const double *mom = C.mom + (size_t)slot * (GSIS_NMOM + MAXW);
+    ParamRec P;
+    double rho = mom[0], T = mom[4];
+    for (int d = 0; d < 3; ++d) P.u[d] = mom[1 + d];
+    P.it = 1.0 / T;
+    P.Th = 0.5 * T;
+    P.itau = rho * pow(T, 1.0 - C.omega) * sqrt(M_PI) / (2.0 * C.Kn);
+    double K = 0.8 * (1.0 - C.Pr) / (rho * T * T);
+    for (int d = 0; d < 3; ++d) P.kq[d] = K * mom[11 + d];
+    if (C.vdim == 2) P.kq[2] = 0.0;
+    if (fixup_coefs(C, P.u, T, rho, P.kq, P.fx)) atomicOr(C.status, 1);
+    // wall densities from the outgoing half-range mass flux of f^n
+    int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1];
+    for (int w = 0; w < MAXW; ++w) P.rw[w] = 0.0;
+    for (int e = e0; e < e1; ++e) {
+        int wi = C.cf_wall[e];
+        if (wi >= 0) P.rw[wi] = mom[GSIS_NMOM + wi] / C.wall_den[e];
+    }
+    P.pad[0] = P.pad[1] = P.pad[2] = 0.0;
+    C.param[slot] = P;
+}
+
+hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_param, dim3((n_kin + 63) / 64), dim3(64), 0, s, cv, n_kin);
+    return hipGetLastError();
+}
+
+// conservation-fixed Maxwellians of W_new (Wn) and W_half (Wh) per kinetic
+// slot (mode 0, GSIS correction), or of W (mode 1, initial fill)
+__global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const int32_t *list, int mode)
+{
+    const CaseView &C = *cvp;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_items) return;
+    int cell = list[t];
+    int slot = C.slot_of_cell[cell];
+    if (mode == 0) {
+        // limiter of the correction: halve the conserved-variable change from
+        // W_half to W_new (at most ten times, then drop it) until density and
+        // temperature stay within a factor 2 of W_half; W_new takes the result
+        double *wn = C.Wn + 5 * (size_t)cell;
+        const double *wh = C.Wh + 5 * (size_t)cell;
+        double Uh[5], Ud[5];
+        for (int s = 0; s < 2; ++s) {
+            const double *w = s ? wn : wh;
+            double *U = s ? Ud : Uh;
+            U[0] = w[0];
+            for (int d = 0; d < 3; ++d) U[1 + d] = w[0] * w[1 + d];
+            U[4] = w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) + 1.5 * w[0] * w[4];
+        }
+        for (int c = 0; c < 5; ++c) Ud[c] -= Uh[c];
+        double th = 1.0, Wl[5];
+        bool ok = false;
+        for (int h = 0; h <= 10 && !ok; ++h) {
+            double U0 = Uh[0] + th * Ud[0];
+            double u2 = 0.0;
+            Wl[0] = U0;
+            for (int d = 0; d < 3; ++d) {
+                Wl[1 + d] = (Uh[1 + d] + th * Ud[1 + d]) / U0;
+                u2 += Wl[1 + d] * Wl[1 + d];
+            }
+            Wl[4] = (Uh[4] + th * Ud[4] - U0 * u2) / (1.5 * U0);
+            ok = (wh[0] / 2.0 <= Wl[0]) && (Wl[0] <= 2.0 * wh[0]) && (wh[4] / 2.0 <= Wl[4]) && (Wl[4] <= 2.0 * wh[4]);
+            th *= 0.5;
+        }
+        for (int c = 0; c < 5; ++c) wn[c] = ok ? Wl[c] : wh[c];
+    }
+    for (int which = 0; which < (mode == 0 ? 2 : 1); ++which) {
+        const double *W = (mode == 0) ? ((which == 0 ? C.Wn : C.Wh) + 5 * (size_t)cell) : (C.W + 5 * (size_t)cell);
+        FeqRec F;
+        for (int d = 0; d < 3; ++d) F.u[d] = W[1 + d];
+        if (C.vdim == 2) F.u[2] = 0.0;
+        F.it = 1.0 / W[4];
+        F.Th = 0.5 * W[4];
+        if (fixup_coefs(C, F.u, W[4], W[0], nullptr, F.fx)) atomicOr(C.status, 1);
+        C.feq[2 * (size_t)slot + which] = F;
+    }
+}
+
+hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_feqpar, dim3((n_kin + 63) / 64), dim3(64), 0, s, cv, n_kin, h.kin_cell, 0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// shared epilogue: moment sums of the produced f relative to u_ref
+// ---------------------------------------------------------------------------
+template <typename A, int VD>
+__device__ __forceinline__ void acc_moments(A (&s)[NSUM], A w, A f0, A f1, A c0, A c1, A c2, A cc)
+{
+    A h = w * f0;
+    A hc0 = h * c0, hc1 = h * c1;
+    s[0] += h;
+    s[1] += hc0;
+    s[2] += hc1;
+    if (VD == 3) {
+        A hc2 = h * c2;
+        s[3] += hc2;
+        s[4] += hc0 * c0;
+        s[5] += hc1 * c1;
+        s[6] += hc2 * c2;
+        s[7] += hc0 * c1;
+        s[8] += hc0 * c2;
+        s[9] += hc1 * c2;
+        A hcc = h * cc;
+        s[10] += hcc * c0;
+        s[11] += hcc * c1;
+        s[12] += hcc * c2;
+    } else {
+        s[3] += hc0 * c0;
+        s[4] += hc1 * c1;
+        s[5] += hc0 * c1;
+        A hcc = h * cc;
+        s[6] += hcc * c0;
+        s[7] += hcc * c1;
+        A hp = w * f1;
+        s[8] += hp;
+        s[9] += hp * c0;
+        s[10] += hp * c1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the kinetic sweep (Sec. 3.1): one block per (kinetic cell, velocity tile)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FaceS {
+    const T *nb;      // upwind row of a kinetic neighbour
+    T n[3];           // outward n S / V
+    T A, Th, it;      // Gaussian source: amplitude, psi factor, 1/T
+    T u[3];
+    T s[6], q[3];     // Grad-13 coefficients (ghost)
+    int kind, wall, tab;
+};
+
+template <typename T, int VD>
+__global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ FaceS<T> fs[MAXF];
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    __shared__ int s_nf, s_nw, s_wl[MAXW];
+
+    const int nb = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, nb);
+    int ci = 0;
+    while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
+    const CaseView &C = *B.cv[ci];
+    const int item = b - B.start[ci];
+    const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
+    const int vt = item / n_kin;
+    const int t = item - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const T *__restrict__ fold = (const T *)C.f[cur];
+    T *__restrict__ fnew = (T *)C.f[cur ^ 1];
+    const int n0 = C.n[0], n1 = C.n[1], n2 = (VD == 3) ? C.n[2] : 0;
+    const int NA3 = n0 + n1 + n2;
+    T *xs = (T *)smem_raw;
+    T *ws = xs + NA3;
+    T *cs = ws + NA3;      // c_d = x_j - u_d of the own target, formed in FP64 and rounded once
+    T *tabs = cs + NA3;
+    const ParamRec &P = C.param[slot];
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+
+    if (threadIdx.x == 0) {
+        s_nf = nf;
+        int nw = 0;
+        for (int l = 0; l < nf; ++l)
+            if (C.cf_wall[e0 + l] >= 0) s_wl[nw++] = l;
+        s_nw = nw;
+    }
+    if (threadIdx.x < nf) {
+        const int l = threadIdx.x;
+        FaceS<T> F;
+        const int e = e0 + l;
+        const int oth = C.cf_other[e];
+        for (int d = 0; d < 3; ++d) F.n[d] = (T)C.cf_nsv[3 * e + d];
+        F.wall = C.cf_wall[e];
+        F.tab = 1 + l;
+        F.nb = nullptr;
+        F.A = F.Th = F.it = (T)0;
+        for (int d = 0; d < 3; ++d) F.u[d] = (T)0, F.q[d] = (T)0;
+        for (int d = 0; d < 6; ++d) F.s[d] = (T)0;
+        if (oth >= 0) {
+            const int so = C.slot_of_cell[oth];
+            if (so >= 0) {
+                F.kind = K_KIN;
+                F.nb = fold + (size_t)so * C.row;
+            } else {
+                // Grad-13 ghost of the NS neighbour (Sec. 3.2)
+                F.kind = K_GHOST;
+                const double *g = C.ghost + (size_t)oth * GSIS_NMOM;
+                double rho = g[0], Tg = g[4], p = rho * Tg;
+                F.A = (T)((VD == 3) ? rho * pow(M_PI * Tg, -1.5) : rho / (M_PI * Tg));
+                for (int d = 0; d < 3; ++d) F.u[d] = (T)g[1 + d];
+                F.it = (T)(1.0 / Tg);
+                F.Th = (T)(0.5 * Tg);
+                for (int d = 0; d < 6; ++d) F.s[d] = (T)(g[5 + d] / (p * Tg));
+                for (int d = 0; d < 3; ++d) F.q[d] = (T)(2.0 * g[11 + d] / (p * Tg));
+            }
+        } else {
+            const int pi = -1 - oth;
+            const double *ps = C.patch_state + 5 * pi;
+            double Tp = ps[4];
+            double amp = (VD == 3) ? pow(M_PI * Tp, -1.5) : 1.0 / (M_PI * Tp);
+            if (C.patch_kind[pi] == GSIS_PATCH_WALL) {
+                F.kind = K_WALL;
+                amp *= P.rw[F.wall];
+            } else {
+                F.kind = K_FAR;
+                amp *= ps[0];
+            }
+            F.A = (T)amp;
+            for (int d = 0; d < 3; ++d) F.u[d] = (T)ps[1 + d];
+            F.it = (T)(1.0 / Tp);
+            F.Th = (T)(0.5 * Tp);
+        }
+        fs[l] = F;
+    }
+    // node / weight tables
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        xs[j] = (T)C.xv[d * MAXA + jj];
+        ws[j] = (T)C.wv[d * MAXA + jj];
+        cs[j] = (T)(C.xv[d * MAXA + jj] - P.u[d]);
+    }
+    __syncthreads();
+    // separable Gaussian factors exp(-(x_j - u_d)^2 / T), evaluated in FP64:
+    // table 0 = own target, 1 + l = face l
+    for (int idx = threadIdx.x; idx < (1 + nf) * NA3; idx += BLOCK) {
+        int src = idx / NA3, j = idx - src * NA3;
+        int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        double c, it;
+        if (src == 0) {
+            c = C.xv[d * MAXA + jj] - P.u[d];
+            it = P.it;
+        } else {
+            const FaceS<T> &F = fs[src - 1];
+            if (F.kind == K_KIN) continue;
+            c = C.xv[d * MAXA + jj] - (double)F.u[d];
+            it = (double)F.it;
+        }
+        tabs[src * NA3 + j] = (T)exp(-c * c * it);
+    }
+    __syncthreads();
+
+    // own target coefficients
+    const T it = (T)P.it, Th = (T)P.Th, itau = (T)P.itau;
+    const T kq0 = (T)P.kq[0], kq1 = (T)P.kq[1], kq2 = (T)P.kq[2];
+    const T fx0 = (T)P.fx[0], fx1 = (T)P.fx[1], fx2 = (T)P.fx[2], fx3 = (T)P.fx[3], fx4 = (T)P.fx[4];
+    const T inv_dt = (T)C.inv_dt;
+    const int nw = s_nw;
+    const T *fo = fold + (size_t)slot * C.row;
+    T *fn = fnew + (size_t)slot * C.row;
+    const int nvp = C.row / ((VD == 3) ? 1 : 2);   // padded length of one function
+
+    T acc[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) acc[i] = (T)0;
+
+    const int k0 = vt * C.tile;
+    const int kend = min(k0 + C.tile, C.nv);
+    int k = k0 + threadIdx.x;
+    VIdx vi = vidx_init<VD>(k, n1, (VD == 3) ? n2 : 1);
+    const T *tx = tabs, *ty = tabs + n0, *tz = tabs + n0 + n1;
+    for (; k < kend; k += BLOCK) {
+        const T x0 = xs[vi.ix], x1 = xs[n0 + vi.iy];
+        const T x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
+        const T w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
+        const T c0 = cs[vi.ix], c1 = cs[n0 + vi.iy], c2 = (VD == 3) ? cs[n0 + n1 + vi.iz] : (T)0;
+        const T cc = c0 * c0 + c1 * c1 + c2 * c2;
+        const T E = tx[vi.ix] * ty[vi.iy] * ((VD == 3) ? tz[vi.iz] : (T)1);
+        const T kqc = kq0 * c0 + kq1 * c1 + kq2 * c2;
+        T Pf, g0, g1 = (T)0;
+        if (VD == 3) {
+            Pf = fx0 + fx1 * c0 + fx2 * c1 + fx3 * c2 + fx4 * cc;
+            g0 = E * Pf * ((T)1 + kqc * (cc * it - (T)2.5));
+        } else {
+            Pf = fx0 + fx1 * c0 + fx2 * c1 + fx3 * cc;
+            const T EP = E * Pf;
+            g0 = EP * ((T)1 + kqc * (cc * it - (T)2));
+            g1 = Th * EP * ((T)1 + kqc * (cc * it - (T)1));
+        }
+        const T o0 = fo[k];
+        const T o1 = (VD == 2) ? fo[nvp + k] : (T)0;
+        T den = inv_dt + itau;
+        T num0 = itau * g0 + inv_dt * o0;
+        T num1 = (VD == 2) ? itau * g1 + inv_dt * o1 : (T)0;
+        for (int l = 0; l < s_nf; ++l) {
+            const FaceS<T> &F = fs[l];
+            const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
+            if (a > (T)0) {
+                den += a;
+            } else if (a < (T)0) {
+                T v0, v1 = (T)0;
+                if (F.kind == K_KIN) {
+                    v0 = F.nb[k];
+                    if (VD == 2) v1 = F.nb[nvp + k];
+                } else {
+                    const T *tb = tabs + F.tab * NA3;
+                    const T Es = F.A * tb[vi.ix] * tb[n0 + vi.iy] * ((VD == 3) ? tb[n0 + n1 + vi.iz] : (T)1);
+                    if (F.kind == K_GHOST) {
+                        const T d0 = x0 - F.u[0], d1 = x1 - F.u[1], d2 = (VD == 3) ? x2 - F.u[2] : (T)0;
+                        const T dd = d0 * d0 + d1 * d1 + d2 * d2;
+                        const T Q2 = F.s[0] * d0 * d0 + F.s[1] * d1 * d1 + F.s[2] * d2 * d2 +
+                                     (T)2 * (F.s[3] * d0 * d1 + F.s[4] * d0 * d2 + F.s[5] * d1 * d2);
+                        const T qd = F.q[0] * d0 + F.q[1] * d1 + F.q[2] * d2;
+                        if (VD == 3) {
+                            v0 = Es * ((T)1 + Q2 + qd * ((T)0.4 * dd * F.it - (T)1));
+                        } else {
+                            const T Tg = (T)2 * F.Th;
+                            v0 = Es * ((T)1 + Q2 + F.Th * F.s[2] + qd * ((T)0.4 * dd * F.it - (T)0.8));
+                            v1 = F.Th * Es * ((T)1 + Q2 + (T)1.5 * Tg * F.s[2] + qd * ((T)0.4 * dd * F.it - (T)0.4));
+                        }
+                    } else {
+                        v0 = Es;
+                        if (VD == 2) v1 = F.Th * Es;
+                    }
+                }
+                num0 -= a * v0;
+                if (VD == 2) num1 -= a * v1;
+            }
+        }
+        const T rden = (T)1 / den;
+        const T n0v = num0 * rden;
+        fn[k] = n0v;
+        T n1v = (T)0;
+        if (VD == 2) {
+            n1v = num1 * rden;
+            fn[nvp + k] = n1v;
+        }
+        acc_moments<T, VD>(acc, w, n0v, n1v, c0, c1, c2, cc);
+        // moment balance at the old iterate: w (num - den f_old) (1, c, c^2 [+psi])
+        const T r0 = w * (num0 - den * o0);
+        acc[S_RES] += r0;
+        acc[S_RES + 1] += r0 * c0;
+        acc[S_RES + 2] += r0 * c1;
+        if (VD == 3) acc[S_RES + 3] += r0 * c2;
+        T re = r0 * cc;
+        if (VD == 2) re += w * (num1 - den * o1);
+        acc[S_RES + 4] += re;
+        // outgoing mass flux through wall faces (numerator of the next rho_w)
+        for (int j = 0; j < nw; ++j) {
+            const FaceS<T> &F = fs[s_wl[j]];
+            const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
+            if (a > (T)0) acc[S_WALL + F.wall] += w * a * n0v;
+        }
+        vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
+    }
+    double v[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) v[i] = (double)acc[i];
+    block_reduce_store<NSUM>(v, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+}
+
+template <typename T, int VD>
+static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
+{
+    int NA3 = h0.n[0] + h0.n[1] + (VD == 3 ? h0.n[2] : 0);
+    size_t lds = sizeof(T) * (size_t)NA3 * (3 + 1 + MAXF);
+    hipLaunchKernelGGL((k_sweep<T, VD>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    // all cases of a batch share dtype and vdim; LDS is sized for the largest axes
+    if (h0.dtype == GSIS_F32)
+        return h0.vdim == 3 ? launch_sweep_t<float, 3>(b, h0, cur, total, s) : launch_sweep_t<float, 2>(b, h0, cur, total, s);
+    return h0.vdim == 3 ? launch_sweep_t<double, 3>(b, h0, cur, total, s) : launch_sweep_t<double, 2>(b, h0, cur, total, s);
+}
+
+// ---------------------------------------------------------------------------
+// GSIS correction (first eq. updatef): f += f_eq(W_new) - f_eq(W_half), in
+// place, with the moment epilogue of the corrected f
+// ---------------------------------------------------------------------------
+template <typename T, int VD>
+__global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ cvp, int n_kin, int cur)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    __shared__ T wn[MAXW][3];
+    __shared__ int s_wi[MAXW], s_nw;
+    const CaseView &C = *cvp;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int vt = b / n_kin, t = b - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const int n0 = C.n[0], n1 = C.n[1], n2 = (VD == 3) ? C.n[2] : 0;
+    const int NA3 = n0 + n1 + n2;
+    T *xs = (T *)smem_raw;
+    T *ws = xs + NA3;
+    T *tabs = ws + NA3;          // [2][NA3] Gaussian factors of f_eq(W_new), f_eq(W_half)
+    T *cts = tabs + 2 * NA3;     // [3][NA3] x_j - u_d for W_new, W_half and the reference frame
+    const FeqRec &Fa = C.feq[2 * (size_t)slot];
+    const FeqRec &Fb = C.feq[2 * (size_t)slot + 1];
+    const ParamRec &P = C.param[slot];
+    if (threadIdx.x == 0) {
+        int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1], nw = 0;
+        for (int e = e0; e < e1; ++e)
+            if (C.cf_wall[e] >= 0) {
+                for (int d = 0; d < 3; ++d) wn[nw][d] = (T)C.cf_nsv[3 * e + d];
+                s_wi[nw++] = C.cf_wall[e];
+            }
+        s_nw = nw;
+    }
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        xs[j] = (T)C.xv[d * MAXA + jj];
+        ws[j] = (T)C.wv[d * MAXA + jj];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 3 * NA3; idx += BLOCK) {
+        int src = idx / NA3, j = idx - src * NA3;
+        int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        const double x = C.xv[d * MAXA + jj];
+        if (src < 2) {
+            const FeqRec &F = src ? Fb : Fa;
+            double c = x - F.u[d];
+            tabs[src * NA3 + j] = (T)exp(-c * c * F.it);
+            cts[src * NA3 + j] = (T)c;
+        } else {
+            cts[2 * NA3 + j] = (T)(x - P.u[d]);
+        }
+    }
+    __syncthreads();
+    const T a0 = (T)Fa.fx[0], a1 = (T)Fa.fx[1], a2 = (T)Fa.fx[2], a3 = (T)Fa.fx[3], a4 = (T)Fa.fx[4];
+    const T b0 = (T)Fb.fx[0], b1 = (T)Fb.fx[1], b2 = (T)Fb.fx[2], b3 = (T)Fb.fx[3], b4 = (T)Fb.fx[4];
+    const T tha = (T)Fa.Th, thb = (T)Fb.Th;
+    const int nw = s_nw;
+    T *fr = (T *)C.f[cur] + (size_t)slot * C.row;
+    const int nvp = C.row / ((VD == 3) ? 1 : 2);
+    T acc[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) acc[i] = (T)0;
+    const int k0 = vt * C.tile;
+    const int kend = min(k0 + C.tile, C.nv);
+    int k = k0 + threadIdx.x;
+    VIdx vi = vidx_init<VD>(k, n1, (VD == 3) ? n2 : 1);
+    const T *ta = tabs, *tb = tabs + NA3;
+    for (; k < kend; k += BLOCK) {
+        const T x0 = xs[vi.ix], x1 = xs[n0 + vi.iy];
+        const T x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
+        const T w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
+        const T Ea = ta[vi.ix] * ta[n0 + vi.iy] * ((VD == 3) ? ta[n0 + n1 + vi.iz] : (T)1);
+        const T Eb = tb[vi.ix] * tb[n0 + vi.iy] * ((VD == 3) ? tb[n0 + n1 + vi.iz] : (T)1);
+        const T *ca = cts, *cb = cts + NA3, *cr = cts + 2 * NA3;
+        const T da0 = ca[vi.ix], da1 = ca[n0 + vi.iy], da2 = (VD == 3) ? ca[n0 + n1 + vi.iz] : (T)0;
+        const T db0 = cb[vi.ix], db1 = cb[n0 + vi.iy], db2 = (VD == 3) ? cb[n0 + n1 + vi.iz] : (T)0;
+        T Pa, Pb;
+        if (VD == 3) {
+            Pa = a0 + a1 * da0 + a2 * da1 + a3 * da2 + a4 * (da0 * da0 + da1 * da1 + da2 * da2);
+            Pb = b0 + b1 * db0 + b2 * db1 + b3 * db2 + b4 * (db0 * db0 + db1 * db1 + db2 * db2);
+        } else {
+            Pa = a0 + a1 * da0 + a2 * da1 + a3 * (da0 * da0 + da1 * da1);
+            Pb = b0 + b1 * db0 + b2 * db1 + b3 * (db0 * db0 + db1 * db1);
+        }
+        const T ma = Ea * Pa, mb = Eb * Pb;
+        const T v0 = fr[k] + (ma - mb);
+        fr[k] = v0;
+        T v1 = (T)0;
+        if (VD == 2) {
+            v1 = fr[nvp + k] + (tha * ma - thb * mb);
+            fr[nvp + k] = v1;
+        }
+        const T c0 = cr[vi.ix], c1 = cr[n0 + vi.iy], c2 = (VD == 3) ? cr[n0 + n1 + vi.iz] : (T)0;
+        const T cc = c0 * c0 + c1 * c1 + c2 * c2;
+        acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
+        for (int j = 0; j < nw; ++j) {
+            const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
+            if (a > (T)0) acc[S_WALL + s_wi[j]] += w * a * v0;
+        }
+        vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
+    }
+    double v[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) v[i] = (double)acc[i];
+    block_reduce_store<NSUM>(v, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+}
+
+hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    int NA3 = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
+    dim3 g(n_kin * h.ntile);
+    if (h.dtype == GSIS_F32) {
+        size_t lds = sizeof(float) * NA3 * 7;
+        if (h.vdim == 3) hipLaunchKernelGGL((k_correct<float, 3>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct<float, 2>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+    } else {
+        size_t lds = sizeof(double) * NA3 * 7;
+        if (h.vdim == 3) hipLaunchKernelGGL((k_correct<double, 3>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct<double, 2>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fill the rows of listed cells from a Gaussian source (mode 0: conservation-
+// fixed Maxwellian of W, FeqRec slot 0; mode 1: Grad-13 of ghost[cell]) and
+// write their moment sums relative to u_ref = source velocity
+// ---------------------------------------------------------------------------
+template <typename T, int VD>
+__global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp, const int32_t *list, int n_items,
+                                                int mode, int cur)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    __shared__ T wn[MAXW][3];
+    __shared__ int s_wi[MAXW], s_nw;
+    const CaseView &C = *cvp;
+    const int b = blockIdx.x;
+    const int vt = b / n_items, t = b - vt * n_items;
+    const int cell = list[t];
+    const int slot = C.slot_of_cell[cell];
+    const int n0 = C.n[0], n1 = C.n[1], n2 = (VD == 3) ? C.n[2] : 0;
+    const int NA3 = n0 + n1 + n2;
+    T *xs = (T *)smem_raw;
+    T *ws = xs + NA3;
+    T *tabs = ws + NA3;
+    // source
+    double u[3], it, Th, A = 1.0, fx[5] = {0, 0, 0, 0, 0}, sg[6] = {0, 0, 0, 0, 0, 0}, qg[3] = {0, 0, 0};
+    if (mode == 2) {
+        const double *W = C.W + 5 * (size_t)cell;
+        for (int d = 0; d < 3; ++d) u[d] = W[1 + d];
+        if (VD == 2) u[2] = 0.0;
+        it = 1.0 / W[4];
+        Th = 0.5 * W[4];
+    } else if (mode == 0) {
+        const FeqRec &F = C.feq[2 * (size_t)slot];
+        for (int d = 0; d < 3; ++d) u[d] = F.u[d];
+        it = F.it;
+        Th = F.Th;
+        for (int d = 0; d < 5; ++d) fx[d] = F.fx[d];
+    } else {
+        const double *g = C.ghost + (size_t)cell * GSIS_NMOM;
+        double rho = g[0], Tg = g[4], p = rho * Tg;
+        for (int d = 0; d < 3; ++d) u[d] = g[1 + d];
+        if (VD == 2) u[2] = 0.0;
+        it = 1.0 / Tg;
+        Th = 0.5 * Tg;
+        A = (VD == 3) ? rho * pow(M_PI * Tg, -1.5) : rho / (M_PI * Tg);
+        for (int d = 0; d < 6; ++d) sg[d] = g[5 + d] / (p * Tg);
+        for (int d = 0; d < 3; ++d) qg[d] = 2.0 * g[11 + d] / (p * Tg);
+    }
+    if (threadIdx.x == 0) {
+        if (vt == 0) {
+            for (int d = 0; d < 3; ++d) C.param[slot].u[d] = u[d];
+        }
+        int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1], nw = 0;
+        for (int e = e0; e < e1; ++e)
+            if (C.cf_wall[e] >= 0) {
+                for (int d = 0; d < 3; ++d) wn[nw][d] = (T)C.cf_nsv[3 * e + d];
+                s_wi[nw++] = C.cf_wall[e];
+            }
+        s_nw = nw;
+    }
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        xs[j] = (T)C.xv[d * MAXA + jj];
+        ws[j] = (T)C.wv[d * MAXA + jj];
+    }
+    __syncthreads();
+    T *cs = tabs + NA3;
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        double c = C.xv[d * MAXA + jj] - u[d];
+        tabs[j] = (T)exp(-c * c * it);
+        cs[j] = (T)c;
+    }
+    __syncthreads();
+    T *fr = (T *)C.f[cur] + (size_t)slot * C.row;
+    const int nvp = C.row / ((VD == 3) ? 1 : 2);
+    T acc[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) acc[i] = (T)0;
+    const int k0 = vt * C.tile;
+    const int kend = min(k0 + C.tile, C.nv);
+    int k = k0 + threadIdx.x;
+    VIdx vi = vidx_init<VD>(k, n1, (VD == 3) ? n2 : 1);
+    const int nw = s_nw;
+    const T Tg = (T)(2.0 * Th);
+    for (; k < kend; k += BLOCK) {
+        const T x0 = xs[vi.ix], x1 = xs[n0 + vi.iy];
+        const T x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
+        const T w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
+        const T E = tabs[vi.ix] * tabs[n0 + vi.iy] * ((VD == 3) ? tabs[n0 + n1 + vi.iz] : (T)1);
+        const T c0 = cs[vi.ix], c1 = cs[n0 + vi.iy], c2 = (VD == 3) ? cs[n0 + n1 + vi.iz] : (T)0;
+        const T cc = c0 * c0 + c1 * c1 + c2 * c2;
+        T v0, v1 = (T)0;
+        if (mode == 2) {
+            v0 = fr[k];
+            if (VD == 2) v1 = fr[nvp + k];
+        } else if (mode == 0) {
+            T Pf = (VD == 3) ? (T)fx[0] + (T)fx[1] * c0 + (T)fx[2] * c1 + (T)fx[3] * c2 + (T)fx[4] * cc
+                             : (T)fx[0] + (T)fx[1] * c0 + (T)fx[2] * c1 + (T)fx[3] * cc;
+            v0 = E * Pf;
+            v1 = (T)Th * v0;
+        } else {
+            const T Q2 = (T)sg[0] * c0 * c0 + (T)sg[1] * c1 * c1 + (T)sg[2] * c2 * c2 +
+                         (T)2 * ((T)sg[3] * c0 * c1 + (T)sg[4] * c0 * c2 + (T)sg[5] * c1 * c2);
+            const T qd = (T)qg[0] * c0 + (T)qg[1] * c1 + (T)qg[2] * c2;
+            const T Es = (T)A * E;
+            if (VD == 3) {
+                v0 = Es * ((T)1 + Q2 + qd * ((T)0.4 * cc * (T)it - (T)1));
+            } else {
+                v0 = Es * ((T)1 + Q2 + (T)Th * (T)sg[2] + qd * ((T)0.4 * cc * (T)it - (T)0.8));
+                v1 = (T)Th * Es * ((T)1 + Q2 + (T)1.5 * Tg * (T)sg[2] + qd * ((T)0.4 * cc * (T)it - (T)0.4));
+            }
+        }
+        if (mode != 2) {
+            fr[k] = v0;
+            if (VD == 2) fr[nvp + k] = v1;
+        }
+        acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
+        for (int j = 0; j < nw; ++j) {
+            const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
+            if (a > (T)0) acc[S_WALL + s_wi[j]] += w * a * v0;
+        }
+        vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
+    }
+    // zero the padding of this row once
+    if (vt == 0 && mode != 2)
+        for (int kp = C.nv + threadIdx.x; kp < nvp; kp += BLOCK) {
+            fr[kp] = (T)0;
+            if (VD == 2) fr[nvp + kp] = (T)0;
+        }
+    double v[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) v[i] = (double)acc[i];
+    block_reduce_store<NSUM>(v, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+}
+
+hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    const int32_t *list = (mode == 1) ? h.new_cell : h.kin_cell;
+    if (mode == 0) {
+        hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, list, 1);
+    }
+    int NA3 = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
+    dim3 g(n_items * h.ntile);
+    if (h.dtype == GSIS_F32) {
+        size_t lds = sizeof(float) * NA3 * 4;
+        if (h.vdim == 3) hipLaunchKernelGGL((k_fill<float, 3>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+        else hipLaunchKernelGGL((k_fill<float, 2>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+    } else {
+        size_t lds = sizeof(double) * NA3 * 4;
+        if (h.vdim == 3) hipLaunchKernelGGL((k_fill<double, 3>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+        else hipLaunchKernelGGL((k_fill<double, 2>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dense <-> slot-row copies of the VDF (dir 0: workspace -> out, 1: in -> workspace)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_gather(const CaseView *__restrict__ cvp, int n_kin, int cur, T *dense, int dir)
+{
+    const CaseView &C = *cvp;
+    const int t = blockIdx.y;
+    const int slot = C.slot_of_cell[C.kin_cell[t]];
+    const int nvp = C.row / C.nfun;
+    T *row = (T *)C.f[cur] + (size_t)slot * C.row;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < C.nfun * C.nv; i += gridDim.x * blockDim.x) {
+        int fun = i / C.nv, k = i - fun * C.nv;
+        T *d = dense + ((size_t)t * C.nfun + fun) * C.nv + k;
+        if (dir == 0) *d = row[fun * nvp + k];
+        else row[fun * nvp + k] = *d;
+    }
+    if (dir == 1 && blockIdx.x == 0)
+        for (int fun = 0; fun < C.nfun; ++fun)
+            for (int k = C.nv + threadIdx.x; k < nvp; k += blockDim.x) row[fun * nvp + k] = (T)0;
+}
+
+hipError_t launch_gather_vdf(const CaseView *cv, const CaseView &h, int n_kin, int cur, void *out, int dir,
+                             hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    int gx = (h.nfun * h.nv + 255) / 256;
+    if (gx > 64) gx = 64;
+    dim3 g(gx, n_kin);
+    if (h.dtype == GSIS_F32) hipLaunchKernelGGL(k_gather<float>, g, dim3(256), 0, s, cv, n_kin, cur, (float *)out, dir);
+    else hipLaunchKernelGGL(k_gather<double>, g, dim3(256), 0, s, cv, n_kin, cur, (double *)out, dir);
+    return hipGetLastError();
+}
+
+}  // namespace gsis

@@ -1,0 +1,787 @@
+// gsis_macro.hip -- FP64 macroscopic side and region management for gfx950.
+//
+// Synthetic macroscopic equations of Sec. 3.1 (eqs. full_constitutive and
+// macro, monatomic form of eq. macroscopic_equation_2), least-squares
+// gradients (Sec. 3.4 Step 2), Grad-13 interface distributions (Sec. 3.2),
+// the gradient-length local Knudsen number and DVM-region flags (Sec. 3.2),
+// compaction of the kinetic list, and the convergence measure of Sec. 4.
+//
+// The paper leaves the macroscopic fluxes F and sources Q to another work;
+// the discretisation here is: kinetic flux-vector splitting of the local
+// Maxwellians for the convective part (the kinetic sweep's own upwinding
+// applied to the equilibria), NSF plus high-order terms with corrected face
+// gradients for the viscous part, an isothermal no-slip wall, and a frozen
+// per-cell source.  All reductions are deterministic (fixed
+// order, no floating-point atomics).
+#include <math.h>
+
+#include "gsis_impl.hpp"
+
+namespace gsis {
+
+static __device__ int solve_small(int n, double *A, double *b)
+{
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(A[r * n + col]) > fabs(A[piv * n + col])) piv = r;
+        if (!(fabs(A[piv * n + col]) > 0.0)) return -1;
+        if (piv != col) {
+            for (int j = 0; j < n; ++j) {
+                double t = A[col * n + j];
+                A[col * n + j] = A[piv * n + j];
+                A[piv * n + j] = t;
+            }
+            double t = b[col];
+            b[col] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = col + 1; r < n; ++r) {
+            double fac = A[r * n + col] / A[col * n + col];
+            for (int j = col; j < n; ++j) A[r * n + j] -= fac * A[col * n + j];
+            b[r] -= fac * b[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int j = r + 1; j < n; ++j) s -= A[r * n + j] * b[j];
+        b[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+// fields for gradients: 0..2 u, 3 T, 4 rho, 5 |u|
+__device__ __forceinline__ double field(const double *W, int v)
+{
+    if (v < 3) return W[1 + v];
+    if (v == 3) return W[4];
+    if (v == 4) return W[0];
+    return sqrt(W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+}
+
+// boundary value of field v on patch p; NaN = no contribution
+__device__ __forceinline__ double bfield(const CaseView &C, int p, int v)
+{
+    const double *ps = C.patch_state + 5 * p;
+    if (v < 3) return ps[1 + v];
+    if (v == 3) return ps[4];
+    if (v == 4) return (C.patch_kind[p] == GSIS_PATCH_FAR) ? ps[0] : NAN;
+    return sqrt(ps[1] * ps[1] + ps[2] * ps[2] + ps[3] * ps[3]);
+}
+
+__global__ void k_lsq(const CaseView *__restrict__ cvp, const double *__restrict__ W, int nvar)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    const int dim = C.dim;
+    const double *Wi = W + 5 * (size_t)i;
+    const double *xi = C.cell_center + 3 * (size_t)i;
+    int e0 = C.cf_ptr[i], e1 = C.cf_ptr[i + 1];
+    for (int v = 0; v < nvar; ++v) {
+        double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};
+        double fi = field(Wi, v);
+        for (int e = e0; e < e1; ++e) {
+            int oth = C.cf_other[e];
+            double dx[3], dphi;
+            if (oth >= 0) {
+                for (int d = 0; d < 3; ++d) dx[d] = C.cell_center[3 * (size_t)oth + d] - xi[d];
+                dphi = field(W + 5 * (size_t)oth, v) - fi;
+            } else {
+                double bv = bfield(C, -1 - oth, v);
+                if (isnan(bv)) continue;
+                int f = C.cf_face[e];
+                for (int d = 0; d < 3; ++d) dx[d] = C.face_center[3 * (size_t)f + d] - xi[d];
+                dphi = bv - fi;
+            }
+            double r2 = 0.0;
+            for (int d = 0; d < dim; ++d) r2 += dx[d] * dx[d];
+            double wgt = 1.0 / r2;
+            for (int a = 0; a < dim; ++a) {
+                for (int c = 0; c < dim; ++c) A[a * dim + c] += wgt * dx[a] * dx[c];
+                b[a] += wgt * dx[a] * dphi;
+            }
+        }
+        double *g = C.grad + ((size_t)i * 6 + v) * 3;
+        g[0] = g[1] = g[2] = 0.0;
+        if (solve_small(dim, A, b) == 0)
+            for (int d = 0; d < dim; ++d) g[d] = b[d];
+    }
+}
+
+hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lsq, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, W, nvar);
+    return hipGetLastError();
+}
+
+// Newton and Fourier laws (Sec. 2 eq. NSF_constitutive, kappa of eq.
+// mu_kappa with d_r = 0), scaled: sigma = -(2Kn/sqrt(pi)) T^w (G + G^T -
+// 2/3 tr G I), q = -(5 Kn / (2 sqrt(pi) Pr)) T^w grad T; G[i][j] = du_i/dx_j
+__device__ void nsf(const CaseView &C, double T, const double *Gu, const double *GT, double *s, double *q)
+{
+    double mu = pow(T, C.omega);
+    double cs = -2.0 * C.Kn / sqrt(M_PI) * mu;
+    double cq = -5.0 * C.Kn / (2.0 * sqrt(M_PI) * C.Pr) * mu;
+    double div = Gu[0] + Gu[4] + Gu[8];
+    s[0] = cs * (2.0 * Gu[0] - 2.0 / 3.0 * div);
+    s[1] = cs * (2.0 * Gu[4] - 2.0 / 3.0 * div);
+    s[2] = cs * (2.0 * Gu[8] - 2.0 / 3.0 * div);
+    s[3] = cs * (Gu[1] + Gu[3]);
+    s[4] = cs * (Gu[2] + Gu[6]);
+    s[5] = cs * (Gu[5] + Gu[7]);
+    for (int d = 0; d < 3; ++d) q[d] = cq * GT[d];
+}
+
+__device__ __forceinline__ void cell_nsf(const CaseView &C, int i, double T, double *s, double *q)
+{
+    const double *g = C.grad + (size_t)i * 18;   // rows u_x, u_y, u_z, T (each d/dx_j)
+    double Gu[9];
+    for (int a = 0; a < 9; ++a) Gu[a] = g[a];
+    nsf(C, T, Gu, g + 9, s, q);
+}
+
+// Grad-13 parameters of every cell from W and the gradients of W
+__global__ void k_ghost(const CaseView *__restrict__ cvp, const double *__restrict__ W)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    double *g = C.ghost + (size_t)i * GSIS_NMOM;
+    const double *Wi = W + 5 * (size_t)i;
+    for (int c = 0; c < 5; ++c) g[c] = Wi[c];
+    double s[6], q[3];
+    cell_nsf(C, i, Wi[4], s, q);
+    for (int c = 0; c < 6; ++c) g[5 + c] = s[c];
+    for (int c = 0; c < 3; ++c) g[11 + c] = q[c];
+    if (C.vdim == 2) {
+        g[3] = 0.0;
+        g[9] = g[10] = 0.0;
+        g[13] = 0.0;
+    }
+}
+
+hipError_t launch_ghost(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ghost, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, W);
+    return hipGetLastError();
+}
+
+// high-order terms (eq. full_constitutive) on kinetic cells, zero elsewhere;
+// gradients of W^{n+1/2} must be in C.grad
+__global__ void k_hot(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    double *h = C.hot + 9 * (size_t)i;
+    int slot = C.slot_of_cell[i];
+    if (slot < 0) {
+        for (int c = 0; c < 9; ++c) h[c] = 0.0;
+        return;
+    }
+    const double *mom = C.mom + (size_t)slot * (GSIS_NMOM + MAXW);
+    double s[6], q[3];
+    cell_nsf(C, i, C.Wh[5 * (size_t)i + 4], s, q);
+    for (int c = 0; c < 6; ++c) h[c] = mom[5 + c] - s[c];
+    for (int c = 0; c < 3; ++c) h[6 + c] = mom[11 + c] - q[c];
+}
+
+hipError_t launch_hot(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hot, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv);
+    return hipGetLastError();
+}
+
+// W^{n+1/2}: moments of f^{n+1/2} on kinetic cells, W^n on NS cells
+__global__ void k_whalf(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    int slot = C.slot_of_cell[i];
+    const double *src = (slot >= 0) ? C.mom + (size_t)slot * (GSIS_NMOM + MAXW) : C.W + 5 * (size_t)i;
+    for (int c = 0; c < 5; ++c) C.Wh[5 * (size_t)i + c] = src[c];
+}
+
+hipError_t launch_whalf(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_whalf, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// face fluxes
+// ---------------------------------------------------------------------------
+// half-range moments {1, xi, |xi|^2} x (xi.n) of M(rho, u, T) over sgn (xi.n) > 0
+__device__ void half_flux(const double *P, const double *n, double sgn, double *F)
+{
+    double rho = P[0], T = P[4], sT = sqrt(T);
+    double un = P[1] * n[0] + P[2] * n[1] + P[3] * n[2];
+    double ut[3] = {P[1] - un * n[0], P[2] - un * n[1], P[3] - un * n[2]};
+    double ut2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    double s = un / sT;
+    double A = 0.5 * (1.0 + sgn * erf(s));
+    double B = sgn * exp(-s * s) / (2.0 * sqrt(M_PI));
+    double m1 = un * A + sT * B;
+    double m2 = (un * un + 0.5 * T) * A + un * sT * B;
+    double m3 = (un * un * un + 1.5 * un * T) * A + (un * un + T) * sT * B;
+    F[0] = rho * m1;
+    for (int d = 0; d < 3; ++d) F[1 + d] = rho * (ut[d] * m1 + n[d] * m2);
+    F[4] = rho * (m3 + (ut2 + T) * m1);
+}
+
+__global__ void k_face_flux(const CaseView *__restrict__ cvp, const double *__restrict__ W,
+                            const double *__restrict__ hot)
+{
+    const CaseView &C = *cvp;
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= C.n_faces) return;
+    int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
+    const double *n = C.face_normal + 3 * (size_t)f;
+    const double *PL = W + 5 * (size_t)L;
+    double F[5] = {0, 0, 0, 0, 0};
+    if (Rc >= 0 || C.patch_kind[-1 - Rc] == GSIS_PATCH_FAR) {
+        const double *PR = (Rc >= 0) ? W + 5 * (size_t)Rc : C.patch_state + 5 * (-1 - Rc);
+        double FL[5], FR[5];
+        half_flux(PL, n, 1.0, FL);
+        half_flux(PR, n, -1.0, FR);
+        for (int c = 0; c < 5; ++c) F[c] = FL[c] + FR[c];
+        if (Rc >= 0) {
+            // mean gradient corrected along n so that its projection on the
+            // centroid difference equals the jump (exact for linear fields)
+            const double *xL = C.cell_center + 3 * (size_t)L, *xR = C.cell_center + 3 * (size_t)Rc;
+            double dx[3];
+            for (int d = 0; d < 3; ++d) dx[d] = xR[d] - xL[d];
+            const double dn = C.face_dist[f];
+            double G[4][3];
+            const double *gL = C.grad + (size_t)L * 18, *gR = C.grad + (size_t)Rc * 18;
+            for (int v = 0; v < 4; ++v) {
+                double gx = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    G[v][d] = 0.5 * (gL[3 * v + d] + gR[3 * v + d]);
+                    gx += G[v][d] * dx[d];
+                }
+                double fl = (v < 3) ? PL[1 + v] : PL[4];
+                double fr = (v < 3) ? PR[1 + v] : PR[4];
+                double alpha = (fr - fl - gx) / dn;
+                for (int d = 0; d < 3; ++d) G[v][d] += alpha * n[d];
+            }
+            double Tf = 0.5 * (PL[4] + PR[4]);
+            double Gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+            double sg[6], q[3];
+            nsf(C, Tf, Gu, G[3], sg, q);
+            const double *hL = hot + 9 * (size_t)L, *hR = hot + 9 * (size_t)Rc;
+            for (int c = 0; c < 6; ++c) sg[c] += 0.5 * (hL[c] + hR[c]);
+            for (int c = 0; c < 3; ++c) q[c] += 0.5 * (hL[6 + c] + hR[6 + c]);
+            double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2], sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                            sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+            double uf[3] = {0.5 * (PL[1] + PR[1]), 0.5 * (PL[2] + PR[2]), 0.5 * (PL[3] + PR[3])};
+            for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
+            F[4] += sn[0] * uf[0] + sn[1] * uf[1] + sn[2] * uf[2] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+        }
+    } else {
+        // isothermal no-slip wall: pressure plus the NSF viscous flux from
+        // one-sided gradients towards (u_w, T_w)
+        const double *ps = C.patch_state + 5 * (-1 - Rc);
+        const double dn = 0.5 * C.face_dist[f];
+        const double *gL = C.grad + (size_t)L * 18;
+        double pL = PL[0] * PL[4];
+        for (int d = 0; d < 3; ++d) F[1 + d] = 0.5 * pL * n[d];
+        double G[4][3];
+        for (int v = 0; v < 4; ++v) {
+            double gn = gL[3 * v] * n[0] + gL[3 * v + 1] * n[1] + gL[3 * v + 2] * n[2];
+            double fl = (v < 3) ? PL[1 + v] : PL[4];
+            double jump = (ps[1 + v] - fl) / dn;
+            for (int d = 0; d < 3; ++d) G[v][d] = gL[3 * v + d] + (jump - gn) * n[d];
+        }
+        double Gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+        double sg[6], q[3];
+        nsf(C, ps[4], Gu, G[3], sg, q);
+        double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2], sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                        sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+        for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
+        F[4] += sn[0] * ps[1] + sn[1] * ps[2] + sn[2] * ps[3] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+    }
+    for (int c = 0; c < 5; ++c) C.fflux[5 * (size_t)f + c] = F[c];
+}
+
+// per-cell flux balance R_i = -sum_f (+-F_f) S_f (deterministic order over the cell's faces)
+__device__ __forceinline__ void cell_balance(const CaseView &C, int i, double *R)
+{
+    for (int c = 0; c < 5; ++c) R[c] = 0.0;
+    for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+        int f = C.cf_face[e];
+        double sgn = (C.face_cells[2 * f] == i) ? -1.0 : 1.0;
+        double S = C.face_area[f];
+        for (int c = 0; c < 5; ++c) R[c] += sgn * C.fflux[5 * (size_t)f + c] * S;
+    }
+}
+
+__global__ void k_residual_cells(const CaseView *__restrict__ cvp, double *__restrict__ Rout)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    double R[5];
+    cell_balance(C, i, R);
+    double iv = 1.0 / C.cell_volume[i];
+    for (int c = 0; c < 5; ++c) Rout[5 * (size_t)i + c] = R[c] * iv;
+}
+
+hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const double *W, const double *hot,
+                                 double *Rout, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lsq, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, W, 4);
+    hipLaunchKernelGGL(k_face_flux, dim3((h.n_faces + 127) / 128), dim3(128), 0, s, cv, W, hot);
+    hipLaunchKernelGGL(k_residual_cells, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, Rout);
+    return hipGetLastError();
+}
+
+// source of eq. macro on kinetic cells: kinetic moment balance at f^n minus
+// the synthetic residual at W^n (both per unit volume); zero on NS cells
+__global__ void k_src(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    bool kin = C.slot_of_cell[i] >= 0;
+    for (int c = 0; c < 5; ++c)
+        C.src[5 * (size_t)i + c] = kin ? C.Rk[5 * (size_t)i + c] - C.Rm[5 * (size_t)i + c] : 0.0;
+}
+
+hipError_t launch_src(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_src, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv);
+    return hipGetLastError();
+}
+
+// local step denominator D_i = sum_f S_f (|u_n| + a + 2 nu / d_f)
+__device__ double cell_D(const CaseView &C, int i, const double *Wi)
+{
+    const double gam = 5.0 / 3.0;
+    double a = sqrt(gam * Wi[4] / 2.0);
+    double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wi[4], C.omega) / (sqrt(M_PI) * Wi[0]);
+    double D = 0.0;
+    for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+        int f = C.cf_face[e];
+        const double *n = C.face_normal + 3 * (size_t)f;
+        double un = Wi[1] * n[0] + Wi[2] * n[1] + Wi[3] * n[2];
+        D += C.face_area[f] * (fabs(un) + a + 2.0 * nu / C.face_dist[f]);
+    }
+    return D;
+}
+
+__global__ void k_cons(const CaseView *__restrict__ cvp, const double *__restrict__ W)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    const double *P = W + 5 * (size_t)i;
+    double *U = C.U + 5 * (size_t)i;
+    double u2 = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    U[0] = P[0];
+    for (int d = 0; d < 3; ++d) U[1 + d] = P[0] * P[1 + d];
+    U[4] = P[0] * u2 + 1.5 * P[0] * P[4];
+}
+
+// dloc_i = V_i / D_i, then a two-level min reduction into red[0]
+__global__ void k_dloc(const CaseView *__restrict__ cvp, const double *__restrict__ W)
+{
+    const CaseView &C = *cvp;
+    __shared__ double sm[256];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = INFINITY;
+    if (i < C.n_cells) v = C.cell_volume[i] / cell_D(C, i, W + 5 * (size_t)i);
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C.dloc[blockIdx.x] = sm[0];
+}
+
+__global__ void k_min_final(const CaseView *__restrict__ cvp, int nb)
+{
+    const CaseView &C = *cvp;
+    __shared__ double sm[256];
+    double v = INFINITY;
+    for (int i = threadIdx.x; i < nb; i += 256) v = fmin(v, C.dloc[i]);
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C.red[0] = sm[0];
+}
+
+// U_i += k_i (R_i + V_i src_i), k_i = cfl / D_i (local) or |cfl| min V/D / V_i
+// (global), halved while the new state is not positive; W = prim(U)
+__global__ void k_update(const CaseView *__restrict__ cvp, double *__restrict__ W, const double *__restrict__ src,
+                         double cfl)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    double *Wi = W + 5 * (size_t)i;
+    double R[5];
+    cell_balance(C, i, R);
+    double V = C.cell_volume[i];
+    if (src)
+        for (int c = 0; c < 5; ++c) R[c] += src[5 * (size_t)i + c] * V;
+    double k = (cfl < 0) ? (-cfl * C.red[0]) / V : cfl / cell_D(C, i, Wi);
+    double *U = C.U + 5 * (size_t)i;
+    // positivity safeguard: halve this cell's increment (at most ten times)
+    // while the new density or temperature would not be positive
+    double Un[5], Pn[5];
+    bool ok = false;
+    for (int h = 0; h <= 10 && !ok; ++h) {
+        for (int c = 0; c < 5; ++c) Un[c] = U[c] + k * R[c];
+        Pn[0] = Un[0];
+        double u2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            Pn[1 + d] = Un[1 + d] / Un[0];
+            u2 += Pn[1 + d] * Pn[1 + d];
+        }
+        Pn[4] = (Un[4] - Un[0] * u2) / (1.5 * Un[0]);
+        ok = (Pn[0] > 0.0) && (Pn[4] > 0.0);
+        k *= 0.5;
+    }
+    if (ok) {
+        for (int c = 0; c < 5; ++c) {
+            U[c] = Un[c];
+            Wi[c] = Pn[c];
+        }
+    }
+    if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4])) atomicOr(C.status, 1);
+}
+
+hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src,
+                              int n_inner, double cfl, hipStream_t s)
+{
+    const int gc = (h.n_cells + 127) / 128, gf = (h.n_faces + 127) / 128, gd = (h.n_cells + 255) / 256;
+    hipLaunchKernelGGL(k_cons, dim3(gc), dim3(128), 0, s, cv, W);
+    for (int it = 0; it < n_inner; ++it) {
+        hipLaunchKernelGGL(k_lsq, dim3(gc), dim3(128), 0, s, cv, W, 4);
+        hipLaunchKernelGGL(k_face_flux, dim3(gf), dim3(128), 0, s, cv, W, hot);
+        if (cfl < 0) {
+            hipLaunchKernelGGL(k_dloc, dim3(gd), dim3(256), 0, s, cv, W);
+            hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, s, cv, gd);
+        }
+        hipLaunchKernelGGL(k_update, dim3(gc), dim3(128), 0, s, cv, W, src, cfl);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// convergence measure (Sec. 4): eps_W = sqrt(sum (W^n - W^{n-1})^2 V / sum (W^{n-1})^2 V)
+// for W in {rho, u (vector), T}; block partials then one fixed-order pass
+// ---------------------------------------------------------------------------
+__global__ void k_eps_part(const CaseView *__restrict__ cvp, const double *__restrict__ Wn,
+                           const double *__restrict__ Wo)
+{
+    const CaseView &C = *cvp;
+    __shared__ double sm[6][256];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (i < C.n_cells) {
+        double V = C.cell_volume[i];
+        const double *a = Wn + 5 * (size_t)i, *b = Wo + 5 * (size_t)i;
+        v[0] = (a[0] - b[0]) * (a[0] - b[0]) * V;
+        v[1] = b[0] * b[0] * V;
+        for (int d = 1; d < 4; ++d) {
+            v[2] += (a[d] - b[d]) * (a[d] - b[d]) * V;
+            v[3] += b[d] * b[d] * V;
+        }
+        v[4] = (a[4] - b[4]) * (a[4] - b[4]) * V;
+        v[5] = b[4] * b[4] * V;
+    }
+    for (int c = 0; c < 6; ++c) sm[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int c = 0; c < 6; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) C.red[8 + 6 * (size_t)blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ void k_eps_final(const CaseView *__restrict__ cvp, int nb)
+{
+    const CaseView &C = *cvp;
+    if (threadIdx.x != 0) return;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < 6; ++c) s[c] += C.red[8 + 6 * (size_t)b + c];
+    for (int k = 0; k < 3; ++k) {
+        double num = s[2 * k], den = s[2 * k + 1];
+        C.eps[k] = (den > 1e-30) ? sqrt(num / den) : sqrt(num);
+    }
+}
+
+hipError_t launch_eps(const CaseView *cv, const CaseView &h, const double *Wnew, const double *Wold, hipStream_t s)
+{
+    int nb = (h.n_cells + 255) / 256;
+    hipLaunchKernelGGL(k_eps_part, dim3(nb), dim3(256), 0, s, cv, Wnew, Wold);
+    hipLaunchKernelGGL(k_eps_final, dim3(1), dim3(64), 0, s, cv, nb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// region test (Sec. 3.2): Kn_Gll = lambda max(|grad rho|/rho, |grad U|/max(U, a),
+// |grad T|/T), lambda = Kn T^(omega - 1/2) / rho; flag = Kn_Gll >= Kn_ref, plus
+// cells within `layers` face hops of a wall.  Gradients of (u, T, rho, |u|) of
+// W must be in C.grad.  Result in scan_tmp[0..n_cells).
+// ---------------------------------------------------------------------------
+__global__ void k_kn_flags(const CaseView *__restrict__ cvp, double Kn_ref, int layers, int32_t *out)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    const double *W = C.W + 5 * (size_t)i;
+    const double *g = C.grad + (size_t)i * 18;
+    double rho = W[0], T = W[4];
+    double U = sqrt(W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
+    double a = sqrt(5.0 * T / 6.0);
+    double lam = C.Kn * pow(T, C.omega - 0.5) / rho;
+    auto nrm = [](const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
+    double kn = lam * fmax(fmax(nrm(g + 12) / rho, nrm(g + 15) / fmax(U, a)), nrm(g + 9) / T);
+    int flag = kn >= Kn_ref;
+    if (layers > 0)
+        for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+            int oth = C.cf_other[e];
+            if (oth < 0 && C.patch_kind[-1 - oth] == GSIS_PATCH_WALL) flag |= 2;
+        }
+    out[i] = flag;
+}
+
+// grow the wall band by one face hop: bit 1 marks the band
+__global__ void k_grow(const CaseView *__restrict__ cvp, const int32_t *in, int32_t *out)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    int v = in[i];
+    if (!(v & 2))
+        for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+            int oth = C.cf_other[e];
+            if (oth >= 0 && (in[oth] & 2)) {
+                v |= 2;
+                break;
+            }
+        }
+    out[i] = v;
+}
+
+__global__ void k_copy_i(int32_t *d, const int32_t *s, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+hipError_t launch_flags(const CaseView *cv, const CaseView &h, double Kn_ref, int layers, hipStream_t s)
+{
+    const int gc = (h.n_cells + 127) / 128;
+    hipLaunchKernelGGL(k_lsq, dim3(gc), dim3(128), 0, s, cv, h.W, 6);
+    int32_t *a = h.scan_tmp, *b = h.scan_tmp + h.n_cells;
+    hipLaunchKernelGGL(k_kn_flags, dim3(gc), dim3(128), 0, s, cv, Kn_ref, layers, a);
+    for (int l = 1; l < layers; ++l) {
+        hipLaunchKernelGGL(k_grow, dim3(gc), dim3(128), 0, s, cv, a, b);
+        int32_t *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != h.scan_tmp) hipLaunchKernelGGL(k_copy_i, dim3(gc), dim3(128), 0, s, h.scan_tmp, a, h.n_cells);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// compaction (single block, deterministic): new flags in scan_tmp[0..n);
+// kinetic list in ascending cell id; staying cells keep their slot; freed
+// slots are reused lowest-first by new cells in ascending cell id.
+// ---------------------------------------------------------------------------
+__device__ int block_excl_scan(int v, int *sm)
+{
+    // 1024-thread exclusive scan of one int per thread; returns the prefix, sm[1024] = total
+    int tid = threadIdx.x;
+    sm[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int x = (tid >= off) ? sm[tid - off] : 0;
+        __syncthreads();
+        sm[tid] += x;
+        __syncthreads();
+    }
+    int incl = sm[tid];
+    int total = sm[1023];
+    __syncthreads();
+    if (tid == 0) sm[1024] = total;
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(1024) void k_compact(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[1025];
+    const int n = C.n_cells, cap = C.capacity;
+    const int32_t *fl = C.scan_tmp;              // new flags (bit 0 kinetic, bit 1 wall band)
+    int32_t *used = C.scan_tmp + n;              // [cap] slot still used by a staying cell
+    int32_t *freelist = C.scan_tmp + n + cap;    // [cap]
+    const int tid = threadIdx.x;
+    for (int s = tid; s < cap; s += 1024) used[s] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+        int kin = fl[i] != 0;
+        int old = C.slot_of_cell[i];
+        if (kin && old >= 0) used[old] = 1;
+    }
+    __syncthreads();
+    // free slots, ascending
+    int chunk = (cap + 1023) / 1024;
+    int lo = tid * chunk, hi = min(lo + chunk, cap), cnt = 0;
+    for (int s = lo; s < hi; ++s) cnt += !used[s];
+    int base = block_excl_scan(cnt, sm);
+    for (int s = lo; s < hi; ++s)
+        if (!used[s]) freelist[base++] = s;
+    __syncthreads();
+    // kinetic list and new cells, ascending cell id
+    chunk = (n + 1023) / 1024;
+    lo = tid * chunk;
+    hi = min(lo + chunk, n);
+    int ck = 0, cn = 0;
+    for (int i = lo; i < hi; ++i) {
+        int kin = fl[i] != 0;
+        ck += kin;
+        cn += kin && C.slot_of_cell[i] < 0;
+    }
+    int bk = block_excl_scan(ck, sm);
+    int total_k = sm[1024];
+    int bn = block_excl_scan(cn, sm);
+    int total_n = sm[1024];
+    if (total_k > cap) {
+        if (tid == 0) C.status[1] = 1;
+        return;
+    }
+    for (int i = lo; i < hi; ++i) {
+        int kin = fl[i] != 0;
+        int old = C.slot_of_cell[i];
+        if (kin) {
+            C.kin_cell[bk++] = i;
+            if (old < 0) {
+                C.new_cell[bn] = i;
+                C.slot_of_cell[i] = freelist[bn];
+                ++bn;
+            }
+        } else {
+            C.slot_of_cell[i] = -1;
+        }
+        C.flags[i] = kin;
+    }
+    if (tid == 0) {
+        *C.n_kin_dev = total_k;
+        *C.n_new_dev = total_n;
+    }
+}
+
+hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, cv);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_copy(double *d, const double *s, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+hipError_t launch_copy_W(double *dst, const double *src, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3((5 * n + 255) / 256), dim3(256), 0, s, dst, src, 5 * n);
+    return hipGetLastError();
+}
+
+__global__ void k_set_flags(const CaseView *__restrict__ cvp, const uint8_t *fl)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C.n_cells) C.scan_tmp[i] = fl ? (fl[i] != 0) : 1;
+}
+
+hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_flags, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_get_flags(const CaseView *__restrict__ cvp, uint8_t *fl)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C.n_cells) fl[i] = (uint8_t)(C.flags[i] != 0);
+}
+
+hipError_t launch_get_flags(const CaseView *cv, const CaseView &h, uint8_t *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_get_flags, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_moments_out(const CaseView *__restrict__ cvp, int n_kin, double *out, int32_t *kc)
+{
+    const CaseView &C = *cvp;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_kin) return;
+    int cell = C.kin_cell[t];
+    const double *m = C.mom + (size_t)C.slot_of_cell[cell] * (GSIS_NMOM + MAXW);
+    for (int c = 0; c < GSIS_NMOM; ++c) out[(size_t)t * GSIS_NMOM + c] = m[c];
+    if (kc) kc[t] = cell;
+}
+
+hipError_t launch_moments_out(const CaseView *cv, const CaseView &h, int n_kin, double *out, int32_t *kc,
+                              hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_moments_out, dim3((n_kin + 127) / 128), dim3(128), 0, s, cv, n_kin, out, kc);
+    return hipGetLastError();
+}
+
+__global__ void k_W_from_mom(const CaseView *__restrict__ cvp, int n_kin, double *W)
+{
+    const CaseView &C = *cvp;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_kin) return;
+    int cell = C.kin_cell[t];
+    const double *m = C.mom + (size_t)C.slot_of_cell[cell] * (GSIS_NMOM + MAXW);
+    for (int c = 0; c < 5; ++c) W[5 * (size_t)cell + c] = m[c];
+}
+
+hipError_t launch_W_from_mom(const CaseView *cv, const CaseView &h, int n_kin, double *W, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_W_from_mom, dim3((n_kin + 127) / 128), dim3(128), 0, s, cv, n_kin, W);
+    return hipGetLastError();
+}
+
+__global__ void k_check_W(const CaseView *__restrict__ cvp, const double *W)
+{
+    const CaseView &C = *cvp;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    const double *w = W + 5 * (size_t)i;
+    if (!(w[0] > 0.0) || !(w[4] > 0.0) || !isfinite(w[1] + w[2] + w[3])) atomicOr(C.status, 1);
+}
+
+hipError_t launch_check_W(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_W, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv, W);
+    return hipGetLastError();
+}
+
+}  // namespace gsis

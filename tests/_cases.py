@@ -1,0 +1,66 @@
+"""Parity-test workloads and comparison metrics (shared by the GPU tests).
+
+Every input comes from gsis_inputs (seeded); expected values come from the
+oracle only.
+"""
+import numpy as np
+
+import gsis_inputs as gi
+
+MACH5 = 5.0 * np.sqrt(5.0 / 6.0)
+
+
+def workload(name):
+    """(mesh, grid, Kn, W, flags) for a named parity case."""
+    if name == "couette":          # the plain FP64 Couette configuration (64 cells, 16^3 on [-5,5])
+        m = gi.couette_1d(64, 0.1)
+        g = gi.velocity_grid(3, 16, 5.0)
+        W = gi.couette_initial_W(64, seed=0)
+        return m, g, 0.1, W, np.ones(64, np.uint8)
+    if name == "couette_ragged":   # 20^3 = 8000 nodes: two 4096-node tiles with a ragged tail
+        m = gi.couette_1d(16, 0.1)
+        g = gi.velocity_grid(3, 20, 5.0)
+        W = gi.random_W(16, seed=3, u_scale=0.2)
+        return m, g, 0.05, W, np.ones(16, np.uint8)
+    if name == "cavity":           # lid-driven cavity, reduced 32^2 stretched grid on [-6,6]
+        m = gi.quad_cavity_2d(64, 64, 0.1)
+        g = gi.velocity_grid(2, 32, 6.0, "stretched")
+        W = gi.random_W(m["n_cells"], seed=5, u_scale=0.1, dT=0.05, drho=0.05)
+        W[:, 3] = 0.0
+        return m, g, 0.1, W, np.ones(m["n_cells"], np.uint8)
+    if name == "cylinder_small":   # Mach 5 cylinder, partial kinetic region with NS neighbours
+        m = gi.cylinder_tri_2d(n_theta=48, n_rings=14, free=(1.0, (MACH5, 0.0, 0.0), 1.0))
+        g = gi.velocity_grid(2, 24, 15.0, "stretched")
+        W = gi.hypersonic_field(m)
+        W[:, 3] = 0.0
+        fl = gi.synthetic_region(m, 0.3, seed=11)
+        return m, g, 0.01, W, fl
+    if name == "sphere_small":     # Mach 5 sphere, tetrahedra, partial region
+        m = gi.sphere_tet_3d(h_wall=0.25, growth=0.6, h_max=1.5)
+        g = gi.velocity_grid(3, 12, 15.0, "stretched")
+        W = gi.hypersonic_field(m)
+        fl = gi.synthetic_region(m, 0.2, seed=11)
+        return m, g, 0.005, W, fl
+    raise KeyError(name)
+
+
+def f_error(fg, fo, w):
+    """max over cells of the quadrature-weighted L2 error of the rows, relative."""
+    fg = np.asarray(fg, dtype=np.float64).reshape(fo.shape)
+    num = np.sqrt(np.einsum("k,ijk->i", w, (fg - fo) ** 2))
+    den = np.sqrt(np.einsum("k,ijk->i", w, fo ** 2))
+    return float(np.max(num / den))
+
+
+def moment_errors(mg, mo, u_scale=0.0):
+    """Per-field error max_i |g - o| / max_i |o| (u divided by max(max|u|, u_scale))."""
+    mg = np.asarray(mg)
+    out = {}
+    for name, sl in (("rho", [0]), ("u", [1, 2, 3]), ("T", [4]), ("sigma", list(range(5, 11))),
+                     ("q", [11, 12, 13])):
+        d = np.abs(mg[:, sl] - mo[:, sl]).max()
+        s = np.abs(mo[:, sl]).max()
+        if name == "u":
+            s = max(s, u_scale)
+        out[name] = d / s if s > 0 else d
+    return out

@@ -1,0 +1,179 @@
+"""GPU parity of the outer iteration against the FP64 oracle (via the C ABI).
+
+Covers the GSIS correction, the synthetic macroscopic solve, the region
+update with compaction and Grad-13 fill, the convergence measure, and whole
+DVM / GSIS / aGSIS iterations.  FP64 runs must agree to round-off; FP32 runs
+within 1e-4 on converged macroscopic fields.
+"""
+import numpy as np
+import pytest
+
+import gsis_inputs as gi
+from _cases import f_error, moment_errors, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2501_02245_amd as g
+    import torch
+    assert torch.cuda.is_available()
+    return g
+
+
+def _rel(a, b, scale=None):
+    a = np.asarray(a, dtype=np.float64)
+    s = np.abs(b).max() if scale is None else scale
+    return float(np.abs(a - b).max() / s)
+
+
+def _fields_err(Wg, Wo, u_scale):
+    return {"rho": _rel(Wg[:, 0], Wo[:, 0]), "u": _rel(Wg[:, 1:4], Wo[:, 1:4], max(np.abs(Wo[:, 1:4]).max(), u_scale)),
+            "T": _rel(Wg[:, 4], Wo[:, 4])}
+
+
+def test_dvm_sweeps_fp64(g, oracle_mod):
+    """200 plain DVM sweeps (Couette configuration, FP64): per-iteration round-off only."""
+    m, grid, Kn, W, flags = workload("couette")
+    O = oracle_mod.Oracle(m, grid, Kn)
+    S = oracle_mod.SteadySolver(O, mode="dvm")
+    S.set_state(W)
+    case = g.Case(g.Mesh(m), grid, Kn, dtype=g.F64)
+    case.set_state(W)
+    p = g.SolveParams(mode=g.MODE_DVM)
+    for it in range(200):
+        eo = S.step()
+        eg = case.step(p)
+        if it % 50 == 0:
+            print(it, eo, eg, flush=True)
+            assert np.allclose(eg, eo, rtol=1e-8, atol=1e-14)
+    Wg = case.get_state()[0].cpu().numpy()
+    err = _fields_err(Wg, S.W, 0.1)
+    print("dvm fields", err)
+    assert max(err.values()) < 1e-10
+    assert f_error(case.get_vdf().cpu().numpy(), S.f, O.w) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_gsis_couette_converged(g, oracle_mod, dtype):
+    """GSIS steady Couette (Kn 0.1): converged fields, FP64 to round-off, FP32 within 1e-4."""
+    m, grid, Kn, W, flags = workload("couette")
+    O = oracle_mod.Oracle(m, grid, Kn)
+    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=-0.5)
+    S.set_state(W)
+    it_o, eps_o = S.solve(tol=1e-8, max_iter=2000)
+    case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype)
+    case.set_state(W)
+    tol = 1e-8 if dtype == g.F64 else 1e-6
+    it_g, eps_g, _ = case.solve(g.SolveParams(mode=g.MODE_GSIS, tol=tol, max_iter=2000, n_macro_inner=400,
+                                              cfl=-0.5))
+    Wg = case.get_state()[0].cpu().numpy()
+    err = _fields_err(Wg, S.W, 0.1)
+    print("gsis", dtype, "iters", it_o, it_g, "err", err, flush=True)
+    if dtype == g.F64:
+        assert abs(it_g - it_o) <= 2
+        assert max(err.values()) < 1e-8
+    else:
+        assert max(err.values()) < 1e-4
+
+
+def test_correction_alone(g, oracle_mod):
+    """f += f_eq(W_new) - f_eq(W_half) on kinetic cells (cavity, FP64)."""
+    m, grid, Kn, W, flags = workload("cavity")
+    O = oracle_mod.Oracle(m, grid, Kn)
+    case = g.Case(g.Mesh(m), grid, Kn, dtype=g.F64)
+    f0 = gi.gaussian_rows(grid, W, seed=4, dtype=np.float64)
+    Wh = O.moments(f0)[:, :5]
+    case.set_state(Wh, vdf=f0)
+    Wn = Wh.copy()
+    pert = gi.perturbation((len(Wn), 5), seed=8, amp=0.02)
+    Wn[:, 0] *= pert[:, 0]
+    Wn[:, 1:3] += 0.01 * (pert[:, 1:3] - 1)
+    Wn[:, 4] *= pert[:, 4]
+    case.correct(Wn)
+    fo = np.stack([f0[i] + O.feq(Wn[i]) - O.feq(Wh[i]) for i in range(len(Wn))])
+    mo = O.moments(fo)
+    assert f_error(case.get_vdf().cpu().numpy(), fo, O.w) < 1e-11
+    em = moment_errors(case.moments()[0].cpu().numpy(), mo, u_scale=0.1)
+    assert max(em.values()) < 1e-10, em
+    # the corrected VDF carries exactly the new conserved moments
+    assert np.abs(mo[:, 0] / Wn[:, 0] - 1).max() < 1e-12
+    assert np.abs(mo[:, 4] / Wn[:, 4] - 1).max() < 1e-12
+
+
+def test_macro_solve_alone(g, oracle_mod):
+    """Synthetic macroscopic solve with high-order terms and a source (Mach-5 cylinder, FP64)."""
+    m, grid, Kn, W, flags = workload("cylinder_small")
+    O = oracle_mod.Oracle(m, grid, Kn)
+    n = m["n_cells"]
+    rng = gi.rng_of(21)
+    hot = 1e-3 * rng.uniform(-1, 1, (n, 9))
+    hot[:, [4, 5, 8]] = 0.0                      # planar flow: no xz, yz stress, no q_z
+    src = 1e-2 * rng.uniform(-1, 1, (n, 5))
+    src[:, 3] = 0.0
+    case = g.Case(g.Mesh(m), grid, Kn, dtype=g.F64)
+    for cfl, steps in ((0.5, 60), (-0.4, 20)):
+        Wo = O.macro(W, hot, steps, cfl, src)
+        Wg = case.macro_solve(W, hot, src, steps, cfl).cpu().numpy()
+        err = _fields_err(Wg, Wo, 1.0)
+        print("macro", cfl, err)
+        assert max(err.values()) < 1e-10
+
+
+def test_region_update(g, oracle_mod):
+    """Kn_Gll flags, forced wall layers, compaction and Grad-13 fill of new cells (FP64)."""
+    m, grid, Kn, W, flags = workload("cylinder_small")
+    O = oracle_mod.Oracle(m, grid, Kn)
+    S = oracle_mod.SteadySolver(O, mode="agsis", Kn_ref=0.01, force_wall_layers=2)
+    S.set_state(W, flags=flags)
+    case = g.Case(g.Mesh(m), grid, Kn, dtype=g.F64)
+    case.set_state(W, flags=flags)
+    # both sides use W^n = moments of the initial VDF on kinetic cells
+    Wg = case.get_state()[0].cpu().numpy()
+    assert _rel(Wg, S.W) < 1e-12
+    kn = O.kn_gll(S.W)
+    n_o = S.update_regions()
+    n_g = case.update_regions(0.01, 2)
+    fl_g = case.get_state()[1].cpu().numpy()
+    decided = np.abs(kn / 0.01 - 1) > 1e-9
+    assert np.array_equal(fl_g[decided], S.flags[decided])
+    assert n_g == n_o
+    mg, kc = case.moments()
+    assert np.array_equal(kc.cpu().numpy(), S.kin)
+    fo = S.f[S.slot[S.kin]]
+    assert f_error(case.get_vdf().cpu().numpy(), fo, O.w) < 1e-11
+    em = moment_errors(mg.cpu().numpy(), O.moments(fo), u_scale=1.0)
+    assert max(em.values()) < 1e-10, em
+
+
+@pytest.mark.parametrize("dtype", [1, 0])
+def test_agsis_steps(g, oracle_mod, dtype):
+    """Four aGSIS outer iterations with region updates on the Mach-5 cylinder."""
+    m, grid, Kn, W, flags = workload("cylinder_small")
+    O = oracle_mod.Oracle(m, grid, Kn)
+    S = oracle_mod.SteadySolver(O, mode="agsis", Kn_ref=0.01, n_inner=100, cfl=0.5, region_every=1,
+                                force_wall_layers=2)
+    case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype)
+    if dtype == g.F32:
+        kin = np.nonzero(flags)[0]
+        f0 = gi.gaussian_rows(grid, W[kin], seed=2).astype(np.float64)
+        S.set_state(W, f=f0, flags=flags)
+        case.set_state(W, vdf=f0, flags=flags)
+    else:
+        S.set_state(W, flags=flags)
+        case.set_state(W, flags=flags)
+    p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, n_macro_inner=100, cfl=0.5, region_update_every=1,
+                      force_wall_layers=2)
+    tol = 1e-9 if dtype == g.F64 else 1e-4
+    for it in range(4):
+        eo = S.step()
+        eg = case.step(p)
+        Wg, fl = case.get_state()
+        Wg = Wg.cpu().numpy()
+        fl = fl.cpu().numpy()
+        err = _fields_err(Wg, S.W, 1.0)
+        print(it, "eps", eo, eg, "n_kin", len(S.kin), case.n_kin, "err", err, flush=True)
+        assert np.array_equal(fl, S.flags)
+        assert max(err.values()) < tol
+        assert np.allclose(eg, eo, rtol=1e-3 if dtype == g.F32 else 1e-7)

@@ -467,13 +467,13 @@ def test_macro_free_stream_and_conservation(oracle_mod):
 
 @pytest.mark.parametrize("n,Kn", [(16, 0.05), (32, 0.2)])
 def test_macro_navier_stokes_couette(oracle_mod, n, Kn):
-    """NS-only Couette (no kinetic cells) reaches the closed-form slip profile.
+    """NS-only Couette (no kinetic cells) reaches its discrete closed form.
 
     Interior shear = physical (Kn/sqrt(pi)) mu du/dx plus the splitting's own
-    rho sqrt(T) h/(2 sqrt(pi)) du/dx; the diffuse-wall splitting gives wall
-    shear rho sqrt(T)/(2 sqrt(pi)) (u_cell - U).  With T ~ 1 this yields
-    u = U_eff (2x - 1), U_eff = U / (1 + 4 Kn + h).  Viscous heating
-    (T - 1 ~ 1e-3) is the only neglected effect.
+    rho sqrt(T) h/(2 sqrt(pi)) du/dx; the no-slip wall face carries only the
+    physical shear from the one-sided gradient (U - u_cell)/(h/2).  With T ~ 1
+    this gives u = U_eff (2x - 1), U_eff = U / (1 + h^2 / (2 Kn)).  Viscous
+    heating (T - 1 ~ 1e-3) is the only neglected effect.
     """
     U = 0.05
     m = gi.couette_1d(n, wall_speed=U)
@@ -482,6 +482,7 @@ def test_macro_navier_stokes_couette(oracle_mod, n, Kn):
     W2 = O.macro(W, np.zeros((n, 9)), 10)
     assert np.abs(W2 - W).max() < 1e-8                      # steady
     x = m["cell_center"][:, 0]
-    Ueff = U / (1 + 4 * Kn + 1.0 / n)
+    h = 1.0 / n
+    Ueff = U / (1 + h * h / (2 * Kn))
     assert np.abs(W[:, 2] - Ueff * (2 * x - 1)).max() < 2e-4 * U
     assert np.abs(W[:, 1]).max() < 1e-3 * U                 # O(h) splitting dissipation
