@@ -8,11 +8,17 @@ sphere on a seeded ~200k-tetrahedron mesh, 32^3 stretched velocity grid on
 [-15, 15]^3, FP32 VDF, FP64 macroscopic side; inputs already resident in HBM
 when the timed region starts.
 
-Prints one JSON line (see the repository's benchmark contract).
+Beside the headline number the same JSON line carries the roofline of the
+sweep kernel (HIP events around its launches), the plain FP64 sweep on the
+same GPU, and the FP64 CPU oracle timed on a bounded sample of the workload.
+
+Prints one JSON line (see the repository's benchmark contract); progress
+goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KN, KN_REF, MACH = 0.005, 0.01, 5.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_sphere32.json")
 
 
 def parse():
@@ -31,69 +39,178 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--fraction", type=float, default=0.2, help="kinetic fraction of the synthetic region")
+    ap.add_argument("--fraction", type=float, default=0.2, help="kinetic fraction of the initial region")
+    ap.add_argument("--capacity", type=float, default=0.6, help="kinetic capacity as a fraction of the cells")
     ap.add_argument("--n-inner", type=int, default=400)
     ap.add_argument("--nv1d", type=int, default=32)
-    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--region-every", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-sweep", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (scale for HBM counters)")
     return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(nv1d, fraction):
+    import gsis_inputs as gi
+    u_inf = MACH * np.sqrt(5.0 / 6.0)
+    mesh = gi.sphere_tet_3d(free=(1.0, (u_inf, 0.0, 0.0), 1.0))
+    grid = gi.velocity_grid(3, nv1d, 15.0, "stretched")
+    W = gi.hypersonic_field(mesh)
+    flags = gi.synthetic_region(mesh, fraction, seed=11)
+    return mesh, grid, W, flags
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for name in ("gsis_sweep.hip", "gsis_impl.hpp"):
+        with open(os.path.join(ROOT, "paper_2501_02245_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_kin_mean, nv):
+    """HBM bytes per sweep launch from the committed counter summary, scaled to
+    this launch's kinetic count; None if the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_hash") != sweep_source_hash():
+        return None
+    return float(t["bytes_per_point"]) * n_kin_mean * nv
+
+
+def cpu_baseline(mesh, grid, W, flags, seconds):
+    """Oracle (FP64, OpenMP) sweep + moments of a chunk of kinetic cells, with
+    their kinetic neighbours' rows present, repeated for `seconds`."""
+    import gsis_inputs as gi
+    import oracle
+    O = oracle.Oracle(mesh, grid, KN)
+    kin = np.nonzero(flags)[0]
+    chunk = kin[: min(64, len(kin))]
+    fc = mesh["face_cells"].reshape(-1, 2)
+    inchunk = np.zeros(mesh["n_cells"], bool)
+    inchunk[chunk] = True
+    a_, b_ = fc[:, 0], fc[:, 1]
+    touch = (b_ >= 0) & (inchunk[a_] | inchunk[np.maximum(b_, 0)])
+    nb = np.union1d(chunk, np.concatenate([a_[touch], b_[touch]]))
+    rows = nb[flags[nb] != 0].astype(np.int64)
+    slot = -np.ones(mesh["n_cells"], np.int32)
+    slot[rows] = np.arange(len(rows), dtype=np.int32)
+    f0 = gi.gaussian_rows(grid, W[rows], seed=4, dtype=np.float64)
+    ghost = O.ghost_params(W)
+    O.sweep(f0, chunk, slot, ghost)       # first touch
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fn = O.sweep(f0, chunk, slot, ghost)
+        O.moments(fn[slot[chunk]])
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    nv = O.nv
+    return {"value": reps * len(chunk) * nv / el, "unit": "updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "%d x (FP64 oracle sweep + moments of %d kinetic cells of this workload, "
+                      "%d velocities, kinetic neighbours' rows present) in %.1f s" % (reps, len(chunk), nv, el)}
+
+
+def fp64_sweep(g, torch, M, grid, W, flags, steps=3):
+    """Plain FP64 sweeps of the initial region on the same GPU."""
+    cap = int(flags.sum()) + 64
+    case = g.Case(M, grid, KN, dtype=g.F64, capacity=cap)
+    case.set_state(W, flags=flags)
+    case.sweep(1)
+    torch.cuda.synchronize()
+    ms = []
+    t = time.perf_counter()
+    for _ in range(steps):
+        case.sweep(1)
+        ms.append(case.last_sweep_ms())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    n, nv = case.n_kin, case.nv
+    out = {"updates_per_s": steps * n * nv / dt, "kernel_ms": float(np.mean(ms)),
+           "achieved_gbs": 16.0 * n * nv / (np.mean(ms) / 1e3) / 1e9, "kinetic_cells": n}
+    case.close()
+    return out
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (DESIGN.md describes how "
+              "the sweep would shard)", file=sys.stderr)
         sys.exit(2)
     import torch
-    import gsis_inputs as gi
     import paper_2501_02245_amd as g
 
     t0 = time.time()
-    mach = 5.0
-    u_inf = mach * np.sqrt(5.0 / 6.0)
-    mesh = gi.sphere_tet_3d(free=(1.0, (u_inf, 0.0, 0.0), 1.0))
-    grid = gi.velocity_grid(3, a.nv1d, 15.0, "stretched")
-    W = gi.hypersonic_field(mesh)
-    flags = gi.synthetic_region(mesh, a.fraction, seed=11)
+    mesh, grid, W, flags = workload(a.nv1d, a.fraction)
     n_cells = mesh["n_cells"]
-    Kn = 0.005
     dtype = g.F32 if a.dtype == "f32" else g.F64
-    cap = min(n_cells, int(flags.sum() * 1.5) + 64)
+    cap = max(int(flags.sum()) + 64, min(n_cells, int(a.capacity * n_cells)))
     M = g.Mesh(mesh)
-    case = g.Case(M, grid, Kn, dtype=dtype, capacity=cap)
+    case = g.Case(M, grid, KN, dtype=dtype, capacity=cap)
     case.set_state(W, flags=flags)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     nv = case.nv
-    params = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, tol=1e-12, n_macro_inner=a.n_inner, cfl=0.5,
+    log("setup %.1f s: %d cells, %d kinetic, capacity %d, %d velocities, layout %s"
+        % (setup_s, n_cells, case.n_kin, cap, nv, case.sweep_layout()))
+    params = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=KN_REF, tol=1e-12, n_macro_inner=a.n_inner, cfl=0.5,
                            region_update_every=a.region_every, force_wall_layers=2)
 
     def one():
         if a.sweep_only:
             case.sweep(1)
-        else:
-            case.step(params)
+            return None
+        return case.step(params)
 
-    for _ in range(a.warmup):
-        one()
+    for i in range(a.warmup):
+        e = one()
+        log("warmup %d n_kin %d eps %s" % (i, case.n_kin, e))
     torch.cuda.synchronize()
     kin_counts, sweep_ms = [], []
     t = time.perf_counter()
-    for _ in range(a.steps):
+    for i in range(a.steps):
         kin_counts.append(case.n_kin)
-        one()
+        e = one()
         sweep_ms.append(case.last_sweep_ms())
+        log("step %d n_kin %d sweep %.3f ms eps %s" % (i, kin_counts[-1], sweep_ms[-1], e))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     updates = float(sum(kin_counts)) * nv
-    ms_step = 1e3 * dt / a.steps
     es = 4 if dtype == g.F32 else 8
-    sweep_s = np.mean(sweep_ms) / 1e3
+    sweep_s = float(np.mean(sweep_ms)) / 1e3
     n_kin_mean = float(np.mean(kin_counts))
     alg_bytes = 2 * es * n_kin_mean * nv          # read f^n, write f^{n+1/2}
     achieved = alg_bytes / sweep_s / 1e9
+    traffic = measured_traffic(n_kin_mean, nv) if dtype == g.F32 else None
+    case.close()
+
+    if a.calibrate_copy > 0:
+        n = a.calibrate_copy * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    fp64 = None
+    if not a.no_fp64_sweep and dtype == g.F32:
+        fp64 = fp64_sweep(g, torch, M, grid, W, flags)
+        log("fp64 sweep", fp64)
+
     out = {
         "metric": "kinetic cell-velocity updates/s",
         "value": updates / dt,
@@ -101,22 +218,27 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": 1e3 * dt / a.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if dtype == g.F32 else "f64",
         "data": "synthetic",
         "config": {"workload": "3D Mach-5 sphere, %d tetrahedra, %d^3 stretched velocities on [-15,15]^3, "
-                               "aGSIS Kn=0.005 Kn_ref=0.01" % (n_cells, a.nv1d),
+                               "aGSIS Kn=%g Kn_ref=%g" % (n_cells, a.nv1d, KN, KN_REF),
                    "kinetic_cells_mean": n_kin_mean, "n_macro_inner": a.n_inner,
                    "sweep_only": bool(a.sweep_only)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_sweep_fast",
                      "kernel_ms": 1e3 * sweep_s},
         "sweep_updates_per_s": n_kin_mean * nv / sweep_s,
+        "fp64_sweep": fp64,
         "setup_s": setup_s,
     }
+    if not a.no_cpu_baseline:
+        t1 = time.time()
+        out["cpu_baseline"] = cpu_baseline(mesh, grid, W, flags, a.cpu_seconds)
+        log("cpu baseline %.1f s" % (time.time() - t1))
     print(json.dumps(out), flush=True)
 
 

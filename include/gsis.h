@@ -217,6 +217,14 @@ gsis_status gsis_macro_solve(gsis_case c, double *W_dev, const double *hot_dev, 
  * (HIP events on the launch stream; synchronises). */
 gsis_status gsis_last_sweep_ms(gsis_case c, float *ms);
 
+/* Sweep layout chosen at bind (all outputs host, nullable): *fast = 1 when the
+ * plane kernel runs (3D: n_z divides 256 and 256 divides n_y n_z; reduced 2D:
+ * n_y divides 256), 0 for the generic kernel; *tile = velocity nodes per
+ * block; *n_tiles = blocks per kinetic cell.  The environment variable
+ * GSIS_TILE (nodes per tile, default 4096) and GSIS_GENERIC_SWEEP=1 (force the
+ * generic kernel) are read at bind.  E_STATE if the case is not bound. */
+gsis_status gsis_sweep_layout(gsis_case c, int32_t *fast, int32_t *tile, int32_t *n_tiles);
+
 #ifdef __cplusplus
 }
 #endif

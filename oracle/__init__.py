@@ -60,6 +60,7 @@ def lib():
         _lib = C.CDLL(build())
         P = C.c_void_p
         _lib.oc_nv.restype = C.c_int32
+        _lib.oc_threads.restype = C.c_int32
         _lib.oc_tau.restype = C.c_double
         for name in ("oc_fixup", "oc_equilibrium", "oc_feq", "oc_sweep", "oc_macro"):
             getattr(_lib, name).restype = C.c_int32
@@ -349,6 +350,11 @@ class Oracle:
             den = np.sum(np.sum(W_old[:, sl] ** 2, axis=1) * V)
             out.append(np.sqrt(num / den) if den > 1e-30 else np.sqrt(num))
         return np.array(out)
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oc_threads())
 
 
 def regions_from_flags(flags, old_slot_of_cell=None):

@@ -12,6 +12,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static const double PI = 3.14159265358979323846;
 
@@ -21,6 +24,16 @@ int32_t oc_nv(const oc_grid *g)
 }
 
 int32_t oc_nfun(const oc_grid *g) { return g->vdim == 3 ? 1 : 2; }
+
+/* threads an OpenMP loop of the oracle uses (reported beside its timings) */
+int32_t oc_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* velocity node k -> (xi, weight); xi_z = 0 for the reduced grid */
 static void node(const oc_grid *g, int32_t k, double *xi, double *w)

@@ -28,6 +28,7 @@ EXPORTS = [
     "gsis_set_velocity_grid", "gsis_case_footprint", "gsis_case_bind", "gsis_set_state", "gsis_kinetic_sweep",
     "gsis_moments", "gsis_n_kinetic", "gsis_update_regions", "gsis_step", "gsis_solve_steady", "gsis_get_vdf",
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
+    "gsis_sweep_layout",
 ]
 
 
@@ -88,6 +89,7 @@ def lib():
             "gsis_step": [P, I32, P, P, P], "gsis_solve_steady": [P, P, P, P], "gsis_get_vdf": [P, P, P],
             "gsis_get_state": [P, P, P, P], "gsis_correct": [P, P, P], "gsis_macro_solve": [P, P, P, P, I32, D, P],
             "gsis_last_sweep_ms": [P, P],
+            "gsis_sweep_layout": [P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -257,6 +259,12 @@ class Case:
         sd = _dev(src, torch.float64) if src is not None else None
         _check(lib().gsis_macro_solve(self.handle, _ptr(Wd), _ptr(hd), _ptr(sd), n_inner, cfl, _stream()))
         return Wd
+
+    def sweep_layout(self):
+        """(fast, tile, n_tiles) of the sweep kernel chosen at bind."""
+        v = [C.c_int32() for _ in range(3)]
+        _check(lib().gsis_sweep_layout(self.handle, *[C.byref(x) for x in v]))
+        return tuple(int(x.value) for x in v)
 
     def last_sweep_ms(self):
         ms = C.c_float()

@@ -52,7 +52,7 @@ struct Segment {
 }  // namespace
 
 struct gsis_mesh_s {
-    int32_t dim, n_cells, n_faces, n_patches, nnz;
+    int32_t dim, n_cells, n_faces, n_patches, nnz, max_faces = 0;
     std::vector<int32_t> face_cells, cf_ptr, cf_face, cf_other, cf_wall, patch_kind;
     std::vector<double> face_normal, face_area, face_center, cell_volume, cell_center, cf_nsv, face_dist,
         patch_state;
@@ -71,7 +71,7 @@ struct gsis_case_s {
     size_t ws_bytes = 0;
     CaseView hv{};             // host copy of the device view
     CaseView *cv = nullptr;    // device view inside the workspace
-    int n_kin = 0, cur = 0, iter = 0;
+    int n_kin = 0, n_ghost = 0, cur = 0, iter = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
 };
@@ -149,6 +149,7 @@ extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
         cnt[i + 1] += cnt[i];
     }
     m->nnz = cnt[nc];
+    for (int i = 0; i < nc; ++i) m->max_faces = std::max(m->max_faces, cnt[i + 1] - cnt[i]);
     m->cf_ptr = cnt;
     m->cf_face.assign(m->nnz, 0);
     m->cf_other.assign(m->nnz, 0);
@@ -285,28 +286,68 @@ namespace {
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, cell_volume, cell_center, patch_kind, patch_state, xv, wv, flags, slot, kin, nkin, newc, nnew, scan,
-        status, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
+        status, prow, grow, gslot, gcell, ngh, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
 
-int choose_tile(int nv)
+// Tile of the sweep: a contiguous range of velocity nodes per block.  When
+// the fastest velocity axis divides the block (3D: n2 | 256 and 256 | n1 n2;
+// reduced 2D: n1 | 256) the fast kernel handles whole x-planes / x-lines;
+// otherwise the generic kernel takes any contiguous range.
+struct TileChoice {
+    int tile, ntile, fast, xp;
+};
+
+TileChoice choose_tile(const gsis_case_s *c)
 {
     const char *env = std::getenv("GSIS_TILE");
-    int t = env ? std::atoi(env) : 4096;
-    if (t < BLOCK) t = BLOCK;
-    t = (t / BLOCK) * BLOCK;
-    return nv <= t ? nv : t;
+    int target = env ? std::atoi(env) : 4096;
+    if (target < BLOCK) target = BLOCK;
+    const char *gen = std::getenv("GSIS_GENERIC_SWEEP");
+    const bool allow_fast = !(gen && gen[0] == '1');
+    const int nx = c->n[0], ny = c->n[1], nz = c->n[2];
+    TileChoice t{};
+    if (allow_fast && c->vdim == 3 && BLOCK % nz == 0 && (ny * nz) % BLOCK == 0) {
+        const int P = ny * nz;
+        t.fast = 1;
+        t.xp = std::max(1, target / P);
+        t.tile = t.xp * P;
+        t.ntile = (nx + t.xp - 1) / t.xp;
+    } else if (allow_fast && c->vdim == 2 && BLOCK % ny == 0) {
+        const int q = BLOCK / ny;
+        t.fast = 1;
+        t.xp = std::max(q, (target / ny) / q * q);
+        t.tile = t.xp * ny;
+        t.ntile = (nx + t.xp - 1) / t.xp;
+    } else {
+        target = (target / BLOCK) * BLOCK;
+        t.fast = 0;
+        t.xp = 0;
+        t.tile = c->nv <= target ? c->nv : target;
+        t.ntile = (c->nv + t.tile - 1) / t.tile;
+    }
+    return t;
 }
 
-Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int *row)
+// rows reserved for the Grad-13 ghosts of NS cells next to the kinetic region
+size_t ghost_capacity(int64_t n_cells, int64_t cap)
+{
+    return (size_t)std::min<int64_t>(n_cells, std::max<int64_t>(cap, 256));
+}
+
+Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int *row, int *fast = nullptr,
+                   int *xp = nullptr)
 {
     const gsis_mesh_s *m = c->mesh;
     const size_t nc = m->n_cells, nf = m->n_faces, nnz = m->nnz, np = std::max(1, m->n_patches);
     const int nfun = (c->vdim == 3) ? 1 : 2;
     const int nvp = (c->nv + 63) / 64 * 64;
     *row = nfun * nvp;
-    *tile = choose_tile(c->nv);
-    *ntile = (c->nv + *tile - 1) / *tile;
+    TileChoice tc = choose_tile(c);
+    *tile = tc.tile;
+    *ntile = tc.ntile;
+    if (fast) *fast = tc.fast;
+    if (xp) *xp = tc.xp;
     const size_t es = (c->dtype == GSIS_F32) ? 4 : 8;
     Segment S;
     Layout L;
@@ -336,6 +377,12 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.nnew = S.take(16);
     L.scan = S.take(4 * (2 * nc + 2 * (size_t)cap + 1024));
     L.status = S.take(16);
+    const size_t gcap = ghost_capacity(m->n_cells, cap);
+    L.prow = S.take(es * np * (*row));
+    L.grow = S.take(es * gcap * (*row));
+    L.gslot = S.take(4 * nc);
+    L.gcell = S.take(4 * gcap);
+    L.ngh = S.take(16);
     L.f0 = S.take(es * (size_t)cap * (*row));
     L.f1 = S.take(es * (size_t)cap * (*row));
     L.param = S.take(sizeof(ParamRec) * (size_t)cap);
@@ -381,12 +428,18 @@ gsis_status check_ready(gsis_case c)
 // read n_kin / n_new after a compaction (synchronises)
 gsis_status read_counts(gsis_case c, hipStream_t s, int *n_new)
 {
-    int32_t v[2];
+    int32_t v[3];
     HIPCHK(hipMemcpyAsync(&v[0], c->hv.n_kin_dev, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&v[1], c->hv.n_new_dev, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&v[2], c->hv.n_ghost_dev, 4, hipMemcpyDeviceToHost, s));
     gsis_status st = sync_status(c, s);
-    if (st) return st;
+    if (st) {
+        // the region lists may be partial: no further sweep until set_state
+        c->state_set = false;
+        return st;
+    }
     c->n_kin = v[0];
+    c->n_ghost = v[2];
     if (n_new) *n_new = v[1];
     return GSIS_OK;
 }
@@ -409,8 +462,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     if (!c->grid_set) return fail(GSIS_E_STATE, "velocity grid not set");
     if (cap <= 0 || cap > c->mesh->n_cells) return fail(GSIS_E_ARG, "capacity must be in 1..n_cells");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GSIS_E_ARG, "workspace must be 256-byte aligned");
-    int tile, ntile, row;
-    Layout L = make_layout(c, cap, &tile, &ntile, &row);
+    int tile, ntile, row, fast, xp;
+    Layout L = make_layout(c, cap, &tile, &ntile, &row, &fast, &xp);
     if (bytes < L.total) return fail(GSIS_E_NOMEM, "workspace of %zu bytes < footprint %zu", bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     const gsis_mesh_s *m = c->mesh;
@@ -435,6 +488,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     h.row = row;
     h.tile = tile;
     h.ntile = ntile;
+    h.fast = fast;
+    h.xp = xp;
     h.capacity = (int32_t)cap;
     h.dtype = c->dtype;
     h.Kn = c->gas.Kn;
@@ -467,6 +522,13 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(int32_t *, n_new_dev, nnew);
     P(int32_t *, scan_tmp, scan);
     P(int32_t *, status, status);
+    P(void *, prow, prow);
+    P(void *, grow, grow);
+    P(int32_t *, ghost_slot, gslot);
+    P(int32_t *, ghost_cell, gcell);
+    P(int32_t *, n_ghost_dev, ngh);
+    h.gcap = (int32_t)ghost_capacity(m->n_cells, cap);
+    h.nfmax = m->max_faces;
     P(ParamRec *, param, param);
     P(FeqRec *, feq, feq);
     P(double *, partial, partial);
@@ -514,12 +576,16 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.flags, 0, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.status, 0, 16, s));
+    HIPCHK(hipMemsetAsync(B + L.gslot, 0xff, 4 * nc, s));
+    HIPCHK(hipMemsetAsync(B + L.ngh, 0, 16, s));
+    HIPCHK(hipMemsetAsync(B + L.prow, 0, L.gslot - L.prow, s));
     HIPCHK(hipMemsetAsync(B + L.wall_den, 0, 8 * nnz, s));
     HIPCHK(hipMemsetAsync(B + L.hot, 0, 72 * nc, s));
     // padding of the VDF rows stays zero
     HIPCHK(hipMemsetAsync(B + L.f0, 0, L.f1 - L.f0, s));
     HIPCHK(hipMemsetAsync(B + L.f1, 0, L.param - L.f1, s));
     HIPCHK(launch_wall_den(c->cv, h, s));
+    HIPCHK(launch_patch_rows(c->cv, h, s));
     if (!c->ev0) {
         HIPCHK(hipEventCreate(&c->ev0));
         HIPCHK(hipEventCreate(&c->ev1));
@@ -542,6 +608,7 @@ extern "C" gsis_status gsis_set_state(gsis_case c, const double *W_dev, const vo
     if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
     hipStream_t s = (hipStream_t)stream;
     CaseView &h = c->hv;
+    c->state_set = false;
     HIPCHK(hipMemsetAsync(h.status, 0, 16, s));
     HIPCHK(launch_copy_W(h.W, W_dev, h.n_cells, s));
     HIPCHK(launch_check_W(c->cv, h, h.W, s));
@@ -590,6 +657,7 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
         HIPCHK(launch_ghost(c->cv, h, h.W, s));
+        if (h.fast) HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
     }
     return GSIS_OK;
 }
@@ -605,6 +673,7 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
             gsis_case c = cases[i0 + j];
             b.cv[j] = c->cv;
             b.start[j + 1] = b.start[j] + c->n_kin * c->ntile;
+            b.nfmax = std::max(b.nfmax, c->hv.nfmax);
         }
         // buffers: every case of a batch sweeps cur -> cur ^ 1 with its own cur
         // (the kernel takes one value; cases are grouped by cur below)
@@ -628,8 +697,9 @@ gsis_status check_batch(gsis_case const *cases, int n)
     for (int j = 0; j < n; ++j) {
         gsis_status st = check_ready(cases[j]);
         if (st) return st;
-        if (cases[j]->dtype != cases[0]->dtype || cases[j]->vdim != cases[0]->vdim)
-            return fail(GSIS_E_ARG, "batched cases must share dtype and vdim");
+        if (cases[j]->dtype != cases[0]->dtype || cases[j]->vdim != cases[0]->vdim ||
+            cases[j]->hv.fast != cases[0]->hv.fast)
+            return fail(GSIS_E_ARG, "batched cases must share dtype, vdim and sweep layout");
         for (int d = 0; d < 3; ++d)
             if (cases[j]->n[d] > cases[0]->n[d] && j > 0) {
                 // LDS is sized from the first case: put the largest grid first
@@ -659,6 +729,16 @@ extern "C" gsis_status gsis_kinetic_sweep(gsis_case const *cases, int32_t n_case
             HIPCHK(launch_W_from_mom(c->cv, c->hv, c->n_kin, c->hv.W, s));
         }
     }
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_sweep_layout(gsis_case c, int32_t *fast, int32_t *tile, int32_t *n_tiles)
+{
+    if (!c) return fail(GSIS_E_ARG, "null case");
+    if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
+    if (fast) *fast = c->hv.fast;
+    if (tile) *tile = c->hv.tile;
+    if (n_tiles) *n_tiles = c->hv.ntile;
     return GSIS_OK;
 }
 

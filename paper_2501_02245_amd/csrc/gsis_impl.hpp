@@ -67,7 +67,8 @@ struct CaseView {
     // sizes
     int32_t n_cells, n_faces, n_patches, dim, nnz;
     int32_t vdim, nfun, n[3], nv, row;      // row = nfun * nv_pad (elements per slot)
-    int32_t tile, ntile;
+    int32_t tile, ntile;        // velocity nodes per tile (a contiguous k range), tiles per row
+    int32_t fast, xp;           // fast sweep layout: x-planes (3D) or x-lines (2D) per tile
     int32_t capacity;
     int32_t dtype;
     double Kn, omega, Pr, inv_dt;
@@ -99,6 +100,13 @@ struct CaseView {
     int32_t *n_new_dev;
     int32_t *scan_tmp;          // [max(n_cells, capacity) + 1024] scratch for scans
     int32_t *status;            // [4] sticky error flags (0 nonfinite, 1 capacity)
+    // boundary rows used by the fast sweep: every face is a row times a scale
+    void *prow;                 // [n_patches][row] wall: M(1, u_w, T_w); far field: M(rho, u, T)
+    void *grow;                 // [gcap][row] Grad-13 rows of NS cells next to the kinetic region
+    int32_t *ghost_slot;        // [n_cells] row of the cell in grow, -1 otherwise
+    int32_t *ghost_cell;        // [gcap] ascending cell id
+    int32_t *n_ghost_dev;
+    int32_t gcap, nfmax;
     // kinetic state
     void *f[2];                 // VDF double buffer [capacity][row]
     ParamRec *param;            // [capacity]
@@ -126,6 +134,7 @@ struct Batch {
     const CaseView *cv[MAX_BATCH];
     int32_t start[MAX_BATCH + 1];   // prefix of work items (blocks) per case
     int32_t n;
+    int32_t nfmax;                  // largest faces-per-cell over the cases
 };
 
 // --- launch wrappers (gsis_kinetic.hip) ---------------------------------------
@@ -137,7 +146,11 @@ hipError_t launch_reduce(const CaseView *cv, const CaseView &h, int n_kin, int w
 hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 hipError_t launch_sweep(const Batch &b, const CaseView &h0, int cur, int total_items, hipStream_t s);
+// (gsis_sweep.hip) tensor grids whose fastest axis divides the block
+hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int cur, int total_items, hipStream_t s);
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
+hipError_t launch_patch_rows(const CaseView *cv, const CaseView &h, hipStream_t s);
+hipError_t launch_ghost_rows(const CaseView *cv, const CaseView &h, int n_ghost, hipStream_t s);
 hipError_t launch_gather_vdf(const CaseView *cv, const CaseView &h, int n_kin, int cur, void *out, int dir,
                              hipStream_t s);
 
@@ -154,7 +167,7 @@ hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, 
 hipError_t launch_eps(const CaseView *cv, const CaseView &h, const double *Wnew, const double *Wold,
                       hipStream_t s);
 hipError_t launch_flags(const CaseView *cv, const CaseView &h, double Kn_ref, int layers, hipStream_t s);
-hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s);
+hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s);   // also builds the ghost list
 hipError_t launch_copy_W(double *dst, const double *src, int n, hipStream_t s);
 hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t *flags, hipStream_t s);
 hipError_t launch_get_flags(const CaseView *cv, const CaseView &h, uint8_t *flags, hipStream_t s);

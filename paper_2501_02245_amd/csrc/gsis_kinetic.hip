@@ -754,6 +754,7 @@ static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int cur, in
 hipError_t launch_sweep(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
+    if (h0.fast) return launch_sweep_fast(b, h0, cur, total, s);
     // all cases of a batch share dtype and vdim; LDS is sized for the largest axes
     if (h0.dtype == GSIS_F32)
         return h0.vdim == 3 ? launch_sweep_t<float, 3>(b, h0, cur, total, s) : launch_sweep_t<float, 2>(b, h0, cur, total, s);
@@ -904,7 +905,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
     const int b = blockIdx.x;
     const int vt = b / n_items, t = b - vt * n_items;
     const int cell = list[t];
-    const int slot = C.slot_of_cell[cell];
+    const int slot = (mode == 3) ? C.ghost_slot[cell] : C.slot_of_cell[cell];
     const int n0 = C.n[0], n1 = C.n[1], n2 = (VD == 3) ? C.n[2] : 0;
     const int NA3 = n0 + n1 + n2;
     T *xs = (T *)smem_raw;
@@ -924,7 +925,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
         it = F.it;
         Th = F.Th;
         for (int d = 0; d < 5; ++d) fx[d] = F.fx[d];
-    } else {
+    } else {   // modes 1 and 3: Grad-13 of the cell's ghost parameters
         const double *g = C.ghost + (size_t)cell * GSIS_NMOM;
         double rho = g[0], Tg = g[4], p = rho * Tg;
         for (int d = 0; d < 3; ++d) u[d] = g[1 + d];
@@ -936,7 +937,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
         for (int d = 0; d < 3; ++d) qg[d] = 2.0 * g[11 + d] / (p * Tg);
     }
     if (threadIdx.x == 0) {
-        if (vt == 0) {
+        if (vt == 0 && mode != 3) {
             for (int d = 0; d < 3; ++d) C.param[slot].u[d] = u[d];
         }
         int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1], nw = 0;
@@ -963,7 +964,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
         cs[j] = (T)c;
     }
     __syncthreads();
-    T *fr = (T *)C.f[cur] + (size_t)slot * C.row;
+    T *fr = (T *)((mode == 3) ? C.grow : C.f[cur]) + (size_t)slot * C.row;
     const int nvp = C.row / ((VD == 3) ? 1 : 2);
     T acc[NSUM];
 #pragma unroll
@@ -972,7 +973,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
     const int kend = min(k0 + C.tile, C.nv);
     int k = k0 + threadIdx.x;
     VIdx vi = vidx_init<VD>(k, n1, (VD == 3) ? n2 : 1);
-    const int nw = s_nw;
+    const int nw = (mode == 3) ? 0 : s_nw;
     const T Tg = (T)(2.0 * Th);
     for (; k < kend; k += BLOCK) {
         const T x0 = xs[vi.ix], x1 = xs[n0 + vi.iy];
@@ -1019,6 +1020,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
             fr[kp] = (T)0;
             if (VD == 2) fr[nvp + kp] = (T)0;
         }
+    if (mode == 3) return;   // ghost rows carry no sums (block-uniform exit)
     double v[NSUM];
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) v[i] = (double)acc[i];
@@ -1028,7 +1030,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
 hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
-    const int32_t *list = (mode == 1) ? h.new_cell : h.kin_cell;
+    const int32_t *list = (mode == 1) ? h.new_cell : ((mode == 3) ? h.ghost_cell : h.kin_cell);
     if (mode == 0) {
         hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, list, 1);
     }
@@ -1043,6 +1045,54 @@ hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_it
         if (h.vdim == 3) hipLaunchKernelGGL((k_fill<double, 3>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
         else hipLaunchKernelGGL((k_fill<double, 2>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_rows(const CaseView *cv, const CaseView &h, int n_ghost, hipStream_t s)
+{
+    return launch_fill(cv, h, 3, n_ghost, 0, s);
+}
+
+// wall patches: M(1, u_w, T_w); far-field patches: M(rho, u, T) (FP64, rounded once)
+template <typename T>
+__global__ void k_patch_rows(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    const int p = blockIdx.y;
+    const double *ps = C.patch_state + 5 * p;
+    const double rho = (C.patch_kind[p] == GSIS_PATCH_WALL) ? 1.0 : ps[0];
+    const double Tp = ps[4], it = 1.0 / Tp;
+    const double amp = (C.vdim == 3) ? rho * pow(M_PI * Tp, -1.5) : rho / (M_PI * Tp);
+    const int nvp = C.row / C.nfun;
+    T *r = (T *)C.prow + (size_t)p * C.row;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nvp; k += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (k < C.nv) {
+            int ix, iy, iz = 0;
+            if (C.vdim == 3) {
+                iz = k % C.n[2];
+                iy = (k / C.n[2]) % C.n[1];
+                ix = k / (C.n[2] * C.n[1]);
+            } else {
+                iy = k % C.n[1];
+                ix = k / C.n[1];
+            }
+            double c0 = C.xv[ix] - ps[1], c1 = C.xv[MAXA + iy] - ps[2];
+            double c2 = (C.vdim == 3) ? C.xv[2 * MAXA + iz] - ps[3] : 0.0;
+            v = amp * exp(-(c0 * c0 + c1 * c1 + c2 * c2) * it);
+        }
+        r[k] = (T)v;
+        if (C.vdim == 2) r[nvp + k] = (T)(0.5 * Tp * v);
+    }
+}
+
+hipError_t launch_patch_rows(const CaseView *cv, const CaseView &h, hipStream_t s)
+{
+    if (h.n_patches <= 0) return hipSuccess;
+    int nvp = h.row / h.nfun;
+    dim3 g((nvp + 255) / 256 < 256 ? (nvp + 255) / 256 : 256, h.n_patches);
+    if (h.dtype == GSIS_F32) hipLaunchKernelGGL(k_patch_rows<float>, g, dim3(256), 0, s, cv);
+    else hipLaunchKernelGGL(k_patch_rows<double>, g, dim3(256), 0, s, cv);
     return hipGetLastError();
 }
 

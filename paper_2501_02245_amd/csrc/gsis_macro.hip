@@ -686,9 +686,51 @@ __global__ __launch_bounds__(1024) void k_compact(const CaseView *__restrict__ c
     }
 }
 
+// NS cells with a kinetic face neighbour, ascending cell id -> rows of grow
+__global__ __launch_bounds__(1024) void k_ghost_list(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[1025];
+    const int n = C.n_cells, tid = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int lo = tid * chunk, hi = min(lo + chunk, n);
+    int cnt = 0;
+    for (int i = lo; i < hi; ++i) {
+        int g = 0;
+        if (C.slot_of_cell[i] < 0)
+            for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+                int o = C.cf_other[e];
+                if (o >= 0 && C.slot_of_cell[o] >= 0) g = 1;
+            }
+        cnt += g;
+    }
+    int base = block_excl_scan(cnt, sm);
+    int total = sm[1024];
+    if (total > C.gcap) {
+        if (tid == 0) C.status[1] = 1;
+        return;
+    }
+    for (int i = lo; i < hi; ++i) {
+        int g = 0;
+        if (C.slot_of_cell[i] < 0)
+            for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+                int o = C.cf_other[e];
+                if (o >= 0 && C.slot_of_cell[o] >= 0) g = 1;
+            }
+        if (g) {
+            C.ghost_cell[base] = i;
+            C.ghost_slot[i] = base++;
+        } else {
+            C.ghost_slot[i] = -1;
+        }
+    }
+    if (tid == 0) *C.n_ghost_dev = total;
+}
+
 hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s)
 {
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, cv);
+    hipLaunchKernelGGL(k_ghost_list, dim3(1), dim3(1024), 0, s, cv);
     return hipGetLastError();
 }
 

@@ -1,0 +1,404 @@
+// gsis_sweep.hip -- the kinetic sweep of Sec. 3.1 for tensor grids whose
+// fastest velocity axis divides the block (the bandwidth-bound hot kernel).
+//
+// Same update and same outputs as the generic k_sweep (gsis_kinetic.hip):
+//   f_i^{n+1/2} = (g_i/tau_i + sum_{a<0} |a| f_j^n) / (1/tau_i + sum_{a>0} a),
+//   a = (xi.n) S/V, upwind values from kinetic neighbours, Grad-13 ghosts,
+//   diffuse walls or the far field; fused moment, moment-balance and wall sums.
+// Every face is a row times a wave-uniform scale: a kinetic neighbour's row of
+// f^n, the Grad-13 row of an NS neighbour (built once per sweep), or the
+// patch Maxwellian row (built at bind) scaled by the wall density rho_w or 1.
+//
+// gfx950 mapping.  One block of 256 threads = one (kinetic cell, tile of
+// whole x-planes (3D) or x-lines (reduced 2D)).  Because the fastest axis
+// (z in 3D, y in 2D) divides 256, every lane keeps the same fastest-axis node
+// for all its points: that axis's Gaussian factor, offsets and each face's
+// contribution to xi.n are lane constants, and the moment sums only need
+// powers of the varying offsets (the lane constant is multiplied in once, in
+// FP64, at the end).  Per-axis records (offset c, Gaussian factor E, fix-up
+// polynomial part P, Shakhov part K, weight w) are built in FP64 and held in
+// LDS.  Face data and neighbour-row bases are wave-uniform (SGPRs); all loads
+// of a point are issued before any is consumed.  NF (4 or 8) bounds the faces
+// per cell; absent faces read the cell's own row with a zero normal.
+#include <math.h>
+
+#include "gsis_impl.hpp"
+
+namespace gsis {
+
+namespace {
+
+template <typename T>
+using gcptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+__device__ __forceinline__ int xcd_remap2(int b, int nb)
+{
+    const int X = 8;
+    int x = b % X, r = b / X, q = nb / X, rem = nb % X;
+    return x * q + min(x, rem) + r;
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
+template <int NS>
+__device__ __forceinline__ void block_reduce2(double (&v)[NS], double *out, double *lds)
+{
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[i] = x;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) lds[wave * NS + i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        double s = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) s += lds[w * NS + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+}  // namespace
+
+template <typename T, int VD, int NF>
+__global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B, int cur)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[(BLOCK / 64) * NSUM];
+
+    // ---- locate the work item -------------------------------------------
+    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    int ci = 0;
+    while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
+    const CaseView &C = *B.cv[ci];
+    const int item = b - B.start[ci];
+    const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
+    const int vt = item / n_kin;
+    const int t = item - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const int nx = C.n[0], ny = C.n[1], nz = (VD == 3) ? C.n[2] : 1;
+    const int NA = nx + ny + ((VD == 3) ? nz : 0);
+    const size_t row = (size_t)C.row;
+    const int nvp = C.row / ((VD == 3) ? 1 : 2);
+    gcptr<T> fold = (gcptr<T>)C.f[cur];
+    gptr<T> fn = (gptr<T>)C.f[cur ^ 1] + (size_t)slot * row;
+    gcptr<T> fo = fold + (size_t)slot * row;
+
+    // ---- LDS: per-axis records of the own target ---------------------------
+    T *rc = (T *)smem_raw;       // offset x_j - u_d
+    T *rE = rc + NA;             // exp(-c^2 / T)
+    T *rP = rE + NA;             // fix-up polynomial part of the axis
+    T *rK = rP + NA;             // Shakhov part kq_d c
+    T *rw = rK + NA;             // weight
+    T *rlo = rw + NA;            // x axis: low part of c, c^2 and its low part, c^3 and its low part
+
+    // ---- wave-uniform face data: row, scale, (n S/V), u.n S/V ----------------
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    int fwall[NF];
+    T fnx[NF], fny[NF], fnz[NF], fun[NF], fsc[NF];
+    gcptr<T> fnb[NF];
+    int nw = 0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fwall[l] = -1;
+        fnx[l] = fny[l] = fnz[l] = fun[l] = (T)0;
+        fsc[l] = (T)0;
+        fnb[l] = fo;
+        if (l < nf) {
+            const int e = e0 + l;
+            const int oth = C.cf_other[e];
+            const double n0 = C.cf_nsv[3 * e], n1 = C.cf_nsv[3 * e + 1], n2 = C.cf_nsv[3 * e + 2];
+            fnx[l] = (T)n0;
+            fny[l] = (T)n1;
+            fnz[l] = (T)n2;
+            fun[l] = (T)(P.u[0] * n0 + P.u[1] * n1 + P.u[2] * n2);   // xi.n S/V = c.n S/V + u.n S/V
+            fwall[l] = C.cf_wall[e];
+            nw += (fwall[l] >= 0);
+            fsc[l] = (T)1;
+            if (oth >= 0) {
+                const int so = C.slot_of_cell[oth];
+                fnb[l] = (so >= 0) ? fold + (size_t)so * row
+                                   : (gcptr<T>)C.grow + (size_t)C.ghost_slot[oth] * row;
+            } else {
+                const int pi = -1 - oth;
+                fnb[l] = (gcptr<T>)C.prow + (size_t)pi * row;
+                if (fwall[l] >= 0) fsc[l] = (T)P.rw[fwall[l]];
+            }
+        }
+    }
+    // own-target records (FP64, rounded once)
+    {
+        const double it = P.it;
+        const double fq = (VD == 3) ? P.fx[4] : P.fx[3];
+        for (int j = threadIdx.x; j < NA; j += BLOCK) {
+            const int d = (j < nx) ? 0 : ((j < nx + ny) ? 1 : 2);
+            const int jj = j - ((d == 0) ? 0 : ((d == 1) ? nx : nx + ny));
+            const double x = C.xv[d * MAXA + jj];
+            const double c = x - P.u[d];
+            const double pl = (d == 0) ? P.fx[0] + P.fx[1] * c + fq * c * c : P.fx[1 + d] * c + fq * c * c;
+            rc[j] = (T)c;
+            rE[j] = (T)exp(-c * c * it);
+            rP[j] = (T)pl;
+            rK[j] = (T)(P.kq[d] * c);
+            rw[j] = (T)C.wv[d * MAXA + jj];
+            if (d == 0) {
+                const double c2 = c * c, c3 = c2 * c;
+                rlo[jj] = (T)(c - (double)(T)c);
+                rlo[nx + jj] = (T)c2;
+                rlo[2 * nx + jj] = (T)(c2 - (double)(T)c2);
+                rlo[3 * nx + jj] = (T)c3;
+                rlo[4 * nx + jj] = (T)(c3 - (double)(T)c3);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- constants --------------------------------------------------------
+    const T it = (T)P.it, Th = (T)P.Th, itau = (T)P.itau, idt = (T)C.inv_dt;
+    const T shift0 = (VD == 3) ? (T)2.5 : (T)2, shift1 = (T)1;
+
+    // lane-constant (fastest axis) data
+    const int ilc = (VD == 3) ? (int)(threadIdx.x % nz) : (int)(threadIdx.x % ny);
+    const int jlc = (VD == 3) ? nx + ny + ilc : nx + ilc;
+    const T cL = rc[jlc], EL = rE[jlc], PL = rP[jlc], KL = rK[jlc];
+    T AL[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) AL[l] = ((VD == 3) ? fnz[l] : fny[l]) * cL + fun[l];
+
+    // per-lane accumulators
+    T A0 = 0, A1 = 0, A2 = 0, A3 = 0, B1 = 0, B2 = 0, B3 = 0, C1 = 0, C2 = 0, D2 = 0;   // moments (see fold)
+    T Q0 = 0, Q1 = 0;                                                                   // reduced psi
+    T R0 = 0, R1 = 0, R2 = 0, R3 = 0, Rp = 0;                                           // moment balance
+    T Wf[NF];                                                                           // outgoing wall sums
+#pragma unroll
+    for (int l = 0; l < NF; ++l) Wf[l] = (T)0;
+
+    if (VD == 3) {
+        // ---- 3D: lanes own z = ilc; loop x-planes, then the M y-values ----
+        const int q = BLOCK / nz;
+        const int M = ny / q;
+        const int yq = threadIdx.x / nz;
+        const int ix0 = vt * C.xp, ix1 = min(ix0 + C.xp, nx);
+        for (int ix = ix0; ix < ix1; ++ix) {
+            const T cx = rc[ix], Ex = rE[ix], Px = rP[ix], Kx = rK[ix], wx = rw[ix];
+            const T Exz = Ex * EL, Pxz = Px + PL, Kxz = Kx + KL, cxz2 = cx * cx + cL * cL;
+            T Ax[NF];
+#pragma unroll
+            for (int l = 0; l < NF; ++l) Ax[l] = fnx[l] * cx + AL[l];
+            T T0 = 0, T1 = 0, T2 = 0, T3 = 0, S0 = 0, S1 = 0, S2 = 0;
+            int iy = yq;
+            int k = (ix * ny + iy) * nz + ilc;
+            const int kstep = q * nz;
+            for (int m = 0; m < M; ++m, iy += q, k += kstep) {
+                // loads first
+                const T o = fo[k];
+                T v[NF];
+#pragma unroll
+                for (int l = 0; l < NF; ++l) v[l] = fnb[l][k];
+                const int jy = nx + iy;
+                const T cy = rc[jy], Ey = rE[jy], Py = rP[jy], Ky = rK[jy], wy = rw[jy];
+                const T cc = cy * cy + cxz2;
+                const T g = Exz * Ey * (Pxz + Py) * ((Kxz + Ky) * (cc * it - shift0) + (T)1);
+                T num = itau * g + idt * o;
+                T den = itau + idt;
+#pragma unroll
+                for (int l = 0; l < NF; ++l) {
+                    const T a = fny[l] * cy + Ax[l];
+                    den += fmax(a, (T)0);
+                    num -= fmin(a, (T)0) * fsc[l] * v[l];
+                }
+                const T fnv = num * fast_rcp(den);
+                fn[k] = fnv;
+                // moment sums: powers of c_y only
+                const T w = wx * wy;
+                const T h = w * fnv;
+                T0 += h;
+                const T hy = h * cy;
+                T1 += hy;
+                const T hy2 = hy * cy;
+                T2 += hy2;
+                T3 += hy2 * cy;
+                const T r = w * (num - den * o);
+                S0 += r;
+                const T ry = r * cy;
+                S1 += ry;
+                S2 += ry * cy;
+                if (nw > 0) {
+#pragma unroll
+                    for (int l = 0; l < NF; ++l)
+                        if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[l], (T)0);
+                }
+            }
+            // fold this plane: x powers from the records, compensated by their low parts
+            const T clo = rlo[ix], c2 = rlo[nx + ix], c2lo = rlo[2 * nx + ix], c3 = rlo[3 * nx + ix],
+                    c3lo = rlo[4 * nx + ix];
+            A0 += T0;
+            A1 += cx * T0 + clo * T0;
+            A2 += c2 * T0 + c2lo * T0;
+            A3 += c3 * T0 + c3lo * T0;
+            B1 += T1;
+            B2 += T2;
+            B3 += T3;
+            C1 += cx * T1 + clo * T1;
+            C2 += c2 * T1 + c2lo * T1;
+            D2 += cx * T2 + clo * T2;
+            R0 += S0;
+            R1 += cx * S0 + clo * S0;
+            R2 += S1;
+            R3 += c2 * S0 + c2lo * S0 + S2;
+        }
+    } else {
+        // ---- reduced 2D: lanes own y = ilc; x varies per step --------------
+        const int q = BLOCK / ny;
+        const int xq = threadIdx.x / ny;
+        const int ix0 = vt * C.xp, ix1 = min(ix0 + C.xp, nx);
+        for (int ix = ix0 + xq; ix < ix1; ix += q) {
+            const int k = ix * ny + ilc;
+            const T o0 = fo[k], o1 = fo[nvp + k];
+            T v0[NF], v1[NF];
+#pragma unroll
+            for (int l = 0; l < NF; ++l) {
+                v0[l] = fnb[l][k];
+                v1[l] = fnb[l][nvp + k];
+            }
+            const T cx = rc[ix], Ex = rE[ix], Px = rP[ix], Kx = rK[ix], wx = rw[ix];
+            const T cc = cx * cx + cL * cL;
+            const T EP = Ex * EL * (Px + PL);
+            const T Kc = Kx + KL;
+            const T g0 = EP * (Kc * (cc * it - shift0) + (T)1);
+            const T g1 = Th * EP * (Kc * (cc * it - shift1) + (T)1);
+            T num0 = itau * g0 + idt * o0, num1 = itau * g1 + idt * o1;
+            T den = itau + idt;
+#pragma unroll
+            for (int l = 0; l < NF; ++l) {
+                const T a = fnx[l] * cx + AL[l];
+                den += fmax(a, (T)0);
+                const T mn = fmin(a, (T)0) * fsc[l];
+                num0 -= mn * v0[l];
+                num1 -= mn * v1[l];
+            }
+            const T rd = fast_rcp(den);
+            const T f0 = num0 * rd, f1 = num1 * rd;
+            fn[k] = f0;
+            fn[nvp + k] = f1;
+            const T h = wx * f0;
+            A0 += h;
+            const T hx = h * cx;
+            A1 += hx;
+            const T hx2 = hx * cx;
+            A2 += hx2;
+            A3 += hx2 * cx;
+            const T hp = wx * f1;
+            Q0 += hp;
+            Q1 += hp * cx;
+            const T r = wx * (num0 - den * o0);
+            R0 += r;
+            const T rx1 = r * cx;
+            R1 += rx1;
+            R3 += rx1 * cx;
+            Rp += wx * (num1 - den * o1);
+            if (nw > 0) {
+#pragma unroll
+                for (int l = 0; l < NF; ++l)
+                    if (fwall[l] >= 0) Wf[l] += h * fmax(fnx[l] * cx + AL[l], (T)0);
+            }
+        }
+    }
+
+    // ---- per-lane constants in FP64, standard partial-sum layout ----------
+    double v[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) v[i] = 0.0;
+    {
+        const int d = (VD == 3) ? 2 : 1;
+        const double cl = C.xv[d * MAXA + ilc] - P.u[d];
+        const double wl = C.wv[d * MAXA + ilc];
+        const double cl2 = cl * cl;
+        if (VD == 3) {
+            const double a0 = A0, a1 = A1, a2 = A2, a3 = A3, b1 = B1, b2 = B2, b3 = B3, c1 = C1, c2 = C2, d2 = D2;
+            v[0] = wl * a0;
+            v[1] = wl * a1;
+            v[2] = wl * b1;
+            v[3] = wl * cl * a0;
+            v[4] = wl * a2;
+            v[5] = wl * b2;
+            v[6] = wl * cl2 * a0;
+            v[7] = wl * c1;
+            v[8] = wl * cl * a1;
+            v[9] = wl * cl * b1;
+            v[10] = wl * (a3 + d2 + cl2 * a1);
+            v[11] = wl * (c2 + b3 + cl2 * b1);
+            v[12] = wl * cl * (a2 + b2 + cl2 * a0);
+            v[S_RES] = wl * (double)R0;
+            v[S_RES + 1] = wl * (double)R1;
+            v[S_RES + 2] = wl * (double)R2;
+            v[S_RES + 3] = wl * cl * (double)R0;
+            v[S_RES + 4] = wl * ((double)R3 + cl2 * (double)R0);
+        } else {
+            const double a0 = A0, a1 = A1, a2 = A2, a3 = A3;
+            v[0] = wl * a0;
+            v[1] = wl * a1;
+            v[2] = wl * cl * a0;
+            v[3] = wl * a2;
+            v[4] = wl * cl2 * a0;
+            v[5] = wl * cl * a1;
+            v[6] = wl * (a3 + cl2 * a1);
+            v[7] = wl * cl * (a2 + cl2 * a0);
+            v[8] = wl * (double)Q0;
+            v[9] = wl * (double)Q1;
+            v[10] = wl * cl * (double)Q0;
+            v[S_RES] = wl * (double)R0;
+            v[S_RES + 1] = wl * (double)R1;
+            v[S_RES + 2] = wl * cl * (double)R0;
+            v[S_RES + 4] = wl * ((double)R3 + cl2 * (double)R0 + (double)Rp);
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < MAXW; ++q2) {
+            double sw = 0.0;
+#pragma unroll
+            for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? (double)Wf[l] : 0.0;
+            v[S_WALL + q2] = wl * sw;
+        }
+    }
+    block_reduce2<NSUM>(v, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+}
+
+size_t sweep_fast_lds(const CaseView &h, size_t es)
+{
+    const int NA = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
+    return es * ((size_t)5 * NA + 5 * h.n[0]);
+}
+
+template <typename T, int VD>
+void launch_nf(const Batch &b, size_t lds, int cur, int total, hipStream_t s)
+{
+    if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_fast<T, VD, 4>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+    else hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+}
+
+hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
+{
+    if (h0.dtype == GSIS_F32) {
+        size_t lds = sweep_fast_lds(h0, sizeof(float));
+        if (h0.vdim == 3) launch_nf<float, 3>(b, lds, cur, total, s);
+        else launch_nf<float, 2>(b, lds, cur, total, s);
+    } else {
+        size_t lds = sweep_fast_lds(h0, sizeof(double));
+        if (h0.vdim == 3) launch_nf<double, 3>(b, lds, cur, total, s);
+        else launch_nf<double, 2>(b, lds, cur, total, s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gsis

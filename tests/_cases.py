@@ -3,6 +3,9 @@
 Every input comes from gsis_inputs (seeded); expected values come from the
 oracle only.
 """
+import contextlib
+import os
+
 import numpy as np
 
 import gsis_inputs as gi
@@ -10,8 +13,39 @@ import gsis_inputs as gi
 MACH5 = 5.0 * np.sqrt(5.0 / 6.0)
 
 
+@contextlib.contextmanager
+def sweep_layout(generic):
+    """Force the generic sweep kernel for cases bound inside the block."""
+    old = os.environ.get("GSIS_GENERIC_SWEEP")
+    if generic:
+        os.environ["GSIS_GENERIC_SWEEP"] = "1"
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("GSIS_GENERIC_SWEEP", None)
+        else:
+            os.environ["GSIS_GENERIC_SWEEP"] = old
+
+
+def make_case(g, name, m, grid, Kn, dtype, **kw):
+    """Bind a case for workload `name`; a ':generic' suffix forces the generic
+    sweep kernel.  The layout chosen is checked against the grid shape."""
+    generic = name.endswith(":generic")
+    with sweep_layout(generic):
+        case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype, **kw)
+    n = [len(x) for x in grid["nodes"]]
+    if grid["vdim"] == 3:
+        can_fast = 256 % n[2] == 0 and (n[1] * n[2]) % 256 == 0
+    else:
+        can_fast = 256 % n[1] == 0
+    assert case.sweep_layout()[0] == int(can_fast and not generic)
+    return case
+
+
 def workload(name):
-    """(mesh, grid, Kn, W, flags) for a named parity case."""
+    """(mesh, grid, Kn, W, flags) for a named parity case (':generic' ignored)."""
+    name = name.split(":")[0]
     if name == "couette":          # the plain FP64 Couette configuration (64 cells, 16^3 on [-5,5])
         m = gi.couette_1d(64, 0.1)
         g = gi.velocity_grid(3, 16, 5.0)
@@ -35,6 +69,19 @@ def workload(name):
         W[:, 3] = 0.0
         fl = gi.synthetic_region(m, 0.3, seed=11)
         return m, g, 0.01, W, fl
+    if name == "cylinder_fast":    # as cylinder_small on a 32^2 grid (plane kernel)
+        m = gi.cylinder_tri_2d(n_theta=48, n_rings=14, free=(1.0, (MACH5, 0.0, 0.0), 1.0))
+        g = gi.velocity_grid(2, 32, 15.0, "stretched")
+        W = gi.hypersonic_field(m)
+        W[:, 3] = 0.0
+        fl = gi.synthetic_region(m, 0.3, seed=11)
+        return m, g, 0.01, W, fl
+    if name == "sphere_fast":      # as sphere_small on a 16^3 grid (plane kernel)
+        m = gi.sphere_tet_3d(h_wall=0.25, growth=0.6, h_max=1.5)
+        g = gi.velocity_grid(3, 16, 15.0, "stretched")
+        W = gi.hypersonic_field(m)
+        fl = gi.synthetic_region(m, 0.2, seed=11)
+        return m, g, 0.005, W, fl
     if name == "sphere_small":     # Mach 5 sphere, tetrahedra, partial region
         m = gi.sphere_tet_3d(h_wall=0.25, growth=0.6, h_max=1.5)
         g = gi.velocity_grid(3, 12, 15.0, "stretched")

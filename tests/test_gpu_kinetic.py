@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import gsis_inputs as gi
-from _cases import f_error, moment_errors, workload
+from _cases import f_error, make_case, moment_errors, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -32,14 +32,16 @@ def _setup(g, oracle_mod, name, dtype, seed=1):
     # W on kinetic cells is the moments of the VDF (both sides do this at set_state)
     W = W.copy()
     W[kin] = O.moments(f0)[:, :5]
-    case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype)
+    case = make_case(g, name, m, grid, Kn, dtype)
     case.set_state(W, vdf=f0, flags=flags)
     return m, grid, O, W, flags, kin, slot, f0, case
 
 
-@pytest.mark.parametrize("name,dtype", [("couette", 1), ("couette", 0), ("couette_ragged", 0),
-                                        ("cavity", 0), ("cavity", 1), ("cylinder_small", 0),
-                                        ("sphere_small", 0), ("sphere_small", 1)])
+@pytest.mark.parametrize("name,dtype", [("couette", 1), ("couette", 0), ("couette:generic", 0),
+                                        ("couette_ragged", 0), ("cavity", 0), ("cavity", 1),
+                                        ("cavity:generic", 0), ("cylinder_small", 0), ("cylinder_fast", 0),
+                                        ("cylinder_fast", 1), ("sphere_small", 0), ("sphere_small", 1),
+                                        ("sphere_fast", 0), ("sphere_fast", 1)])
 def test_one_sweep(g, oracle_mod, name, dtype):
     print("case", name, "dtype", dtype, flush=True)
     m, grid, O, W, flags, kin, slot, f0, case = _setup(g, oracle_mod, name, dtype)
@@ -78,15 +80,17 @@ def test_moments_of_filled_state(g, oracle_mod):
     assert f_error(case.get_vdf().cpu().numpy()[:50], fo, O.w) < 1e-12
 
 
-def test_batched_equals_alone(g, oracle_mod):
-    """Cases swept in one batched launch give bitwise the results of separate launches."""
-    specs = [("couette", 0), ("couette_ragged", 0)]
+@pytest.mark.parametrize("specs", [[("couette_ragged:generic", 0), ("couette:generic", 0)],
+                                   [("sphere_fast", 0), ("couette", 0)]])
+def test_batched_equals_alone(g, oracle_mod, specs):
+    """Cases swept in one batched launch give bitwise the results of separate launches
+    (generic kernel: different grids; plane kernel: different meshes and regions)."""
     alone, mixed = [], []
     for _ in range(2):
         cs = []
         for name, dt in specs:
             m, grid, Kn, W, flags = workload(name)
-            c = g.Case(g.Mesh(m), grid, Kn, dtype=dt)
+            c = make_case(g, name, m, grid, Kn, dt)
             c.set_state(W, flags=flags)
             cs.append(c)
         if not alone:
@@ -94,10 +98,9 @@ def test_batched_equals_alone(g, oracle_mod):
                 c.sweep(3)
             alone = [c.get_vdf().cpu().numpy() for c in cs]
         else:
-            # the first case of a batch must have the largest velocity axes
-            cs = cs[::-1]
+            # specs list the case with the largest velocity axes first, as a batch requires
             g.kinetic_sweep(cs, 3)
-            mixed = [c.get_vdf().cpu().numpy() for c in cs[::-1]]
+            mixed = [c.get_vdf().cpu().numpy() for c in cs]
     for a, b in zip(alone, mixed):
         assert np.array_equal(a, b)
 

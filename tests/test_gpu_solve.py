@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import gsis_inputs as gi
-from _cases import f_error, moment_errors, workload
+from _cases import f_error, make_case, moment_errors, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -147,14 +147,17 @@ def test_region_update(g, oracle_mod):
     assert max(em.values()) < 1e-10, em
 
 
-@pytest.mark.parametrize("dtype", [1, 0])
-def test_agsis_steps(g, oracle_mod, dtype):
-    """Four aGSIS outer iterations with region updates on the Mach-5 cylinder."""
-    m, grid, Kn, W, flags = workload("cylinder_small")
+@pytest.mark.parametrize("name,dtype", [("cylinder_small", 1), ("cylinder_small", 0), ("cylinder_fast", 1),
+                                        ("cylinder_fast", 0)])
+def test_agsis_steps(g, oracle_mod, name, dtype):
+    """Four aGSIS outer iterations with region updates on the Mach-5 cylinder
+    (24^2 grid: generic sweep kernel; 32^2: plane kernel)."""
+    print("case", name, "dtype", dtype, flush=True)
+    m, grid, Kn, W, flags = workload(name)
     O = oracle_mod.Oracle(m, grid, Kn)
     S = oracle_mod.SteadySolver(O, mode="agsis", Kn_ref=0.01, n_inner=100, cfl=0.5, region_every=1,
                                 force_wall_layers=2)
-    case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype)
+    case = make_case(g, name, m, grid, Kn, dtype)
     if dtype == g.F32:
         kin = np.nonzero(flags)[0]
         f0 = gi.gaussian_rows(grid, W[kin], seed=2).astype(np.float64)
