@@ -173,8 +173,10 @@ typedef struct {
     int32_t n_macro_inner;       /* pseudo-time steps per synthetic solve */
     double cfl;                  /* > 0 local steps; < 0 one global (conservative) step */
     int32_t force_wall_layers;
-    int32_t ns_init;             /* 1: Step 1, NS-only solve before the first flagging */
-    int32_t ns_init_max_chunks;  /* chunks of n_macro_inner steps for Step 1 */
+    int32_t ns_init;             /* 1 (aGSIS): Step 1 of Sec. 3.4 first -- every cell NS, the
+                                    synthetic solve alone (HoT = 0) to eps < 1e-6, then the first
+                                    flagging with Grad-13 rows for every kinetic cell */
+    int32_t ns_init_max_chunks;  /* chunks of n_macro_inner steps for Step 1 (0: 1000) */
 } gsis_solve_params;
 
 typedef struct {
@@ -191,7 +193,9 @@ gsis_status gsis_step(gsis_case const *cases, int32_t n_cases, const gsis_solve_
                       void *stream);
 
 /* Steady solve: optional NS initialisation and first flagging (aGSIS), then
- * gsis_step until max(eps) < tol.  Returns GSIS_E_NOCONV after max_iter. */
+ * gsis_step until max(eps) < tol.  Returns GSIS_E_NOCONV after max_iter.
+ * max_iter = 0 is allowed with ns_init: the call then stops after the first
+ * flagging (r->n_kinetic set). */
 gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p, gsis_solve_result *r, void *stream);
 
 /* Copy the VDF of the kinetic cells, rows [n_kin][nfun][nv] in the case

@@ -613,7 +613,7 @@ extern "C" gsis_status gsis_set_state(gsis_case c, const double *W_dev, const vo
     HIPCHK(launch_copy_W(h.W, W_dev, h.n_cells, s));
     HIPCHK(launch_check_W(c->cv, h, h.W, s));
     HIPCHK(hipMemsetAsync(h.slot_of_cell, 0xff, 4 * (size_t)h.n_cells, s));
-    HIPCHK(launch_set_flags(c->cv, h, flags_dev, s));
+    HIPCHK(launch_set_flags(c->cv, h, flags_dev, 1, s));
     HIPCHK(launch_compact(c->cv, h, s));
     gsis_status st = read_counts(c, s, nullptr);
     if (st) return st;
@@ -911,12 +911,18 @@ extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p
     if (st) return st;
     if ((st = check_params(p))) return st;
     if (!r) return fail(GSIS_E_ARG, "null result");
-    if (!(p->tol > 0) || p->max_iter <= 0) return fail(GSIS_E_ARG, "bad tol or max_iter");
+    const bool ns_init = p->mode == GSIS_MODE_AGSIS && p->ns_init;
+    if (!(p->tol > 0) || p->max_iter < 0 || (p->max_iter == 0 && !ns_init))
+        return fail(GSIS_E_ARG, "bad tol or max_iter");
     hipStream_t s = (hipStream_t)stream;
     CaseView &h = c->hv;
     std::memset(r, 0, sizeof *r);
-    if (p->mode == GSIS_MODE_AGSIS && p->ns_init) {
-        // Step 1: macroscopic solve alone (HoT = 0) to eps < tol
+    if (ns_init) {
+        // Step 1: every cell NS, macroscopic solve alone (HoT = 0) to eps < 1e-6
+        const double ns_tol = 1e-6;
+        HIPCHK(launch_set_flags(c->cv, h, nullptr, 0, s));
+        HIPCHK(launch_compact(c->cv, h, s));
+        if ((st = read_counts(c, s, nullptr))) return st;
         HIPCHK(hipMemsetAsync(h.hot, 0, 72 * (size_t)h.n_cells, s));
         int chunks = p->ns_init_max_chunks > 0 ? p->ns_init_max_chunks : 1000;
         for (int k = 0; k < chunks; ++k) {
@@ -927,10 +933,12 @@ extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p
             double e[3];
             HIPCHK(hipMemcpyAsync(e, h.eps, sizeof e, hipMemcpyDeviceToHost, s));
             if ((st = sync_status(c, s))) return st;
-            if (std::max(e[0], std::max(e[1], e[2])) < p->tol) break;
+            if (std::max(e[0], std::max(e[1], e[2])) < ns_tol) break;
         }
-        // Step 2: first flagging
+        // Step 2: first flagging; every kinetic cell is new and starts from Grad-13
         if ((st = gsis_update_regions(c, p->Kn_ref, p->force_wall_layers, nullptr, stream))) return st;
+        r->n_kinetic = c->n_kin;
+        if (p->max_iter == 0) return GSIS_OK;
     }
     double eps[3] = {1, 1, 1};
     for (int it = 0; it < p->max_iter; ++it) {

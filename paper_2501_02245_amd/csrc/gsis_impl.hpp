@@ -169,7 +169,8 @@ hipError_t launch_eps(const CaseView *cv, const CaseView &h, const double *Wnew,
 hipError_t launch_flags(const CaseView *cv, const CaseView &h, double Kn_ref, int layers, hipStream_t s);
 hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s);   // also builds the ghost list
 hipError_t launch_copy_W(double *dst, const double *src, int n, hipStream_t s);
-hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t *flags, hipStream_t s);
+// flags NULL: every cell gets `fill`
+hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t *flags, int fill, hipStream_t s);
 hipError_t launch_get_flags(const CaseView *cv, const CaseView &h, uint8_t *flags, hipStream_t s);
 hipError_t launch_moments_out(const CaseView *cv, const CaseView &h, int n_kin, double *out, int32_t *kc,
                               hipStream_t s);

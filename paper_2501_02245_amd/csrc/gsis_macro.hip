@@ -749,16 +749,16 @@ hipError_t launch_copy_W(double *dst, const double *src, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_set_flags(const CaseView *__restrict__ cvp, const uint8_t *fl)
+__global__ void k_set_flags(const CaseView *__restrict__ cvp, const uint8_t *fl, int fill)
 {
     const CaseView &C = *cvp;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < C.n_cells) C.scan_tmp[i] = fl ? (fl[i] != 0) : 1;
+    if (i < C.n_cells) C.scan_tmp[i] = fl ? (fl[i] != 0) : fill;
 }
 
-hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t *flags, hipStream_t s)
+hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t *flags, int fill, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_flags, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv, flags);
+    hipLaunchKernelGGL(k_set_flags, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv, flags, fill);
     return hipGetLastError();
 }
 
