@@ -128,6 +128,23 @@ def renumber_cells(mesh, order):
                    mesh["cell_center"][order], mesh["patches"])
 
 
+def morton_order(mesh, bits: int = 20):
+    """Order of the cells along a Z-order (Morton) curve of their centroids.
+
+    Consecutive cells are spatially clustered at every scale, so face
+    neighbours mostly sit a short distance apart in the numbering: streaming
+    kernels that visit cells in order then find neighbour data in cache."""
+    x = mesh["cell_center"][:, : max(mesh["dim"], 1)]
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    q = ((x - lo) / np.maximum(hi - lo, 1e-300) * ((1 << bits) - 1)).astype(np.uint64)
+    code = np.zeros(len(x), dtype=np.uint64)
+    nd = x.shape[1]
+    for b in range(bits):
+        for d in range(nd):
+            code |= ((q[:, d] >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * nd + d)
+    return np.argsort(code, kind="stable")
+
+
 def rcm_order(mesh):
     """Reverse Cuthill-McKee order of the cell adjacency graph (locality)."""
     import scipy.sparse as sp
@@ -303,7 +320,7 @@ def cylinder_tri_2d(n_theta: int = 160, n_rings: int = 62, first_layer: float = 
     rho_f, u_f, T_f = free
     patches = [_patch("wall", T=wall_T), _patch("far", rho=rho_f, u=u_f, T=T_f)]
     m = _finish(2, np.stack([own, other], 1), n, area, fcen, vol, cc, patches)
-    return renumber_cells(m, rcm_order(m))
+    return renumber_cells(m, morton_order(m))
 
 
 def sphere_tet_3d(h_wall: float = 0.05, growth: float = 0.27, h_max: float = 1.0,
@@ -366,7 +383,7 @@ def sphere_tet_3d(h_wall: float = 0.05, growth: float = 0.27, h_max: float = 1.0
     rho_f, u_f, T_f = free
     patches = [_patch("wall", T=wall_T), _patch("far", rho=rho_f, u=u_f, T=T_f)]
     m = _finish(3, np.stack([own, other], 1), n, area, fcen, vol, cen[keep], patches)
-    return renumber_cells(m, rcm_order(m))
+    return renumber_cells(m, morton_order(m))
 
 
 # ---------------------------------------------------------------------------

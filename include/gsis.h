@@ -225,8 +225,10 @@ gsis_status gsis_last_sweep_ms(gsis_case c, float *ms);
  * plane kernel runs (3D: n_z divides 256 and 256 divides n_y n_z; reduced 2D:
  * n_y divides 256), 0 for the generic kernel; *tile = velocity nodes per
  * block; *n_tiles = blocks per kinetic cell.  The environment variable
- * GSIS_TILE (nodes per tile, default 4096) and GSIS_GENERIC_SWEEP=1 (force the
- * generic kernel) are read at bind.  E_STATE if the case is not bound. */
+ * GSIS_TILE (nodes per tile) and GSIS_GENERIC_SWEEP=1 (force the
+ * generic kernel) are read at bind; by default the tile is the largest power
+ * of two (at most 32768 nodes) that gives at least 4096 blocks at full
+ * capacity.  E_STATE if the case is not bound. */
 gsis_status gsis_sweep_layout(gsis_case c, int32_t *fast, int32_t *tile, int32_t *n_tiles);
 
 #ifdef __cplusplus

@@ -56,6 +56,10 @@ struct gsis_mesh_s {
     std::vector<int32_t> face_cells, cf_ptr, cf_face, cf_other, cf_wall, patch_kind;
     std::vector<double> face_normal, face_area, face_center, cell_volume, cell_center, cf_nsv, face_dist,
         patch_state;
+    // geometry-only factors of the macroscopic kernels
+    std::vector<double> lsq;      // [nnz][2][3] least-squares coefficients: all faces / no wall faces
+    std::vector<double> cf_fs;    // [nnz] -S (owner) or +S: the face's sign and area in the cell balance
+    std::vector<double> cell_sS;  // [n_cells][2] sum S, sum S / d over the cell's faces
     int refs = 0;
 };
 
@@ -81,6 +85,98 @@ extern "C" const char *gsis_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // mesh
 // ---------------------------------------------------------------------------
+namespace {
+
+// Gauss elimination with partial pivoting (n <= 3); false if a pivot vanishes
+bool solve_small_host(int n, double *A, double *b)
+{
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(A[r * n + col]) > std::fabs(A[piv * n + col])) piv = r;
+        if (!(std::fabs(A[piv * n + col]) > 0.0)) return false;
+        if (piv != col) {
+            for (int j = 0; j < n; ++j) std::swap(A[col * n + j], A[piv * n + j]);
+            std::swap(b[col], b[piv]);
+        }
+        for (int r = col + 1; r < n; ++r) {
+            double fac = A[r * n + col] / A[col * n + col];
+            for (int j = col; j < n; ++j) A[r * n + j] -= fac * A[col * n + j];
+            b[r] -= fac * b[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double v = b[r];
+        for (int j = r + 1; j < n; ++j) v -= A[r * n + j] * b[j];
+        b[r] = v / A[r * n + r];
+    }
+    return true;
+}
+
+// Least-squares gradient (Sec. 3.4 Step 2) as fixed per-face coefficients:
+// grad phi_i = sum_e c_e (phi_e - phi_i), c_e = A^-1 w_e dx_e with
+// A = sum_e w_e dx_e dx_e^T, w_e = 1/|dx_e|^2, dx_e to the neighbour centroid
+// (or the face centre on a boundary).  Variant 1 leaves out wall faces (no
+// density is prescribed there).  A singular system gives a zero gradient.
+// Also the signed face areas of the cell balance and the per-cell sums
+// sum S and sum S/d of the local pseudo-time step.
+void build_macro_factors(gsis_mesh_s *m)
+{
+    const int dim = m->dim;
+    m->lsq.assign(6 * (size_t)m->nnz, 0.0);
+    m->cf_fs.assign(m->nnz, 0.0);
+    m->cell_sS.assign(2 * (size_t)m->n_cells, 0.0);
+    for (int i = 0; i < m->n_cells; ++i) {
+        const int e0 = m->cf_ptr[i], e1 = m->cf_ptr[i + 1];
+        for (int var = 0; var < 2; ++var) {
+            double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double dxs[MAXF][3], wgt[MAXF];
+            bool use[MAXF];
+            for (int e = e0; e < e1; ++e) {
+                const int l = e - e0, oth = m->cf_other[e];
+                use[l] = !(var == 1 && oth < 0 && m->patch_kind[-1 - oth] == GSIS_PATCH_WALL);
+                const double *xo = (oth >= 0) ? &m->cell_center[3 * (size_t)oth]
+                                              : &m->face_center[3 * (size_t)m->cf_face[e]];
+                double r2 = 0.0;
+                for (int d = 0; d < 3; ++d) dxs[l][d] = xo[d] - m->cell_center[3 * (size_t)i + d];
+                for (int d = 0; d < dim; ++d) r2 += dxs[l][d] * dxs[l][d];
+                wgt[l] = 1.0 / r2;
+                if (!use[l]) continue;
+                for (int a = 0; a < dim; ++a)
+                    for (int c = 0; c < dim; ++c) A[a * dim + c] += wgt[l] * dxs[l][a] * dxs[l][c];
+            }
+            double Ainv[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            bool ok = true;
+            for (int col = 0; col < dim && ok; ++col) {
+                double Ac[9], b[3] = {0, 0, 0};
+                std::copy(A, A + 9, Ac);
+                b[col] = 1.0;
+                ok = solve_small_host(dim, Ac, b);
+                for (int r = 0; r < dim; ++r) Ainv[r * dim + col] = b[r];
+            }
+            if (!ok) continue;
+            for (int e = e0; e < e1; ++e) {
+                const int l = e - e0;
+                if (!use[l]) continue;
+                for (int a = 0; a < dim; ++a) {
+                    double v = 0.0;
+                    for (int c = 0; c < dim; ++c) v += Ainv[a * dim + c] * wgt[l] * dxs[l][c];
+                    m->lsq[6 * (size_t)e + 3 * var + a] = v;
+                }
+            }
+        }
+        for (int e = e0; e < e1; ++e) {
+            const int f = m->cf_face[e];
+            const double S = m->face_area[f];
+            m->cf_fs[e] = (m->face_cells[2 * f] == i) ? -S : S;
+            m->cell_sS[2 * (size_t)i] += S;
+            m->cell_sS[2 * (size_t)i + 1] += S / m->face_dist[f];
+        }
+    }
+}
+
+}  // namespace
+
 extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
 {
     if (!d || !out) return fail(GSIS_E_ARG, "null argument");
@@ -210,6 +306,7 @@ extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
         }
         m->face_dist[f] = dd;
     }
+    build_macro_factors(m);
     *out = m;
     return GSIS_OK;
 }
@@ -284,7 +381,7 @@ extern "C" gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const i
 namespace {
 
 struct Layout {
-    size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, wall_den, face_cells, face_normal, face_area, face_center,
+    size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, cell_volume, cell_center, patch_kind, patch_state, xv, wv, flags, slot, kin, nkin, newc, nnew, scan,
         status, prow, grow, gslot, gcell, ngh, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
@@ -298,10 +395,15 @@ struct TileChoice {
     int tile, ntile, fast, xp;
 };
 
-TileChoice choose_tile(const gsis_case_s *c)
+TileChoice choose_tile(const gsis_case_s *c, int64_t cap)
 {
+    // Default: the largest power-of-two tile (at most a whole row) that still
+    // gives at least 4096 blocks at full capacity.  Fewer, longer blocks
+    // amortise each block's set-up and final reduction.
     const char *env = std::getenv("GSIS_TILE");
-    int target = env ? std::atoi(env) : 4096;
+    int target = 32768;
+    while (target > 1024 && cap * (int64_t)((c->nv + target - 1) / target) < 4096) target /= 2;
+    if (env) target = std::atoi(env);
     if (target < BLOCK) target = BLOCK;
     const char *gen = std::getenv("GSIS_GENERIC_SWEEP");
     const bool allow_fast = !(gen && gen[0] == '1');
@@ -343,7 +445,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     const int nfun = (c->vdim == 3) ? 1 : 2;
     const int nvp = (c->nv + 63) / 64 * 64;
     *row = nfun * nvp;
-    TileChoice tc = choose_tile(c);
+    TileChoice tc = choose_tile(c, cap);
     *tile = tc.tile;
     *ntile = tc.ntile;
     if (fast) *fast = tc.fast;
@@ -357,6 +459,9 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.cf_other = S.take(4 * nnz);
     L.cf_wall = S.take(4 * nnz);
     L.cf_nsv = S.take(24 * nnz);
+    L.lsq = S.take(48 * nnz);
+    L.cf_fs = S.take(8 * nnz);
+    L.cell_sS = S.take(16 * nc);
     L.wall_den = S.take(8 * nnz);
     L.face_cells = S.take(8 * nf);
     L.face_normal = S.take(24 * nf);
@@ -502,6 +607,9 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(const int32_t *, cf_other, cf_other);
     P(const int32_t *, cf_wall, cf_wall);
     P(const double *, cf_nsv, cf_nsv);
+    P(const double *, lsq, lsq);
+    P(const double *, cf_fs, cf_fs);
+    P(const double *, cell_sS, cell_sS);
     P(const double *, wall_den, wall_den);
     P(const int32_t *, face_cells, face_cells);
     P(const double *, face_normal, face_normal);
@@ -562,6 +670,9 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(put(L.cf_other, m->cf_other.data(), 4 * nnz));
     HIPCHK(put(L.cf_wall, m->cf_wall.data(), 4 * nnz));
     HIPCHK(put(L.cf_nsv, m->cf_nsv.data(), 24 * nnz));
+    HIPCHK(put(L.lsq, m->lsq.data(), 48 * nnz));
+    HIPCHK(put(L.cf_fs, m->cf_fs.data(), 8 * nnz));
+    HIPCHK(put(L.cell_sS, m->cell_sS.data(), 16 * nc));
     HIPCHK(put(L.face_cells, m->face_cells.data(), 8 * nf));
     HIPCHK(put(L.face_normal, m->face_normal.data(), 24 * nf));
     HIPCHK(put(L.face_area, m->face_area.data(), 8 * nf));

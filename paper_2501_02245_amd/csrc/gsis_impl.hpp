@@ -78,6 +78,9 @@ struct CaseView {
     const int32_t *cf_other;    // [nnz] neighbour cell, or -1 - patch
     const int32_t *cf_wall;     // [nnz] wall-sum index of the face in its cell, -1 otherwise
     const double *cf_nsv;       // [nnz][3] outward n S / V
+    const double *lsq;          // [nnz][2][3] least-squares coefficients (all faces / no wall faces)
+    const double *cf_fs;        // [nnz] -S_f if the cell owns the face, +S_f otherwise
+    const double *cell_sS;      // [n_cells][2] sum S_f, sum S_f / d_f
     const double *wall_den;     // [nnz] sum_{xi.n<0} w |xi.n| M(1, u_w, T_w) (wall faces)
     const int32_t *face_cells;  // [n_faces][2]
     const double *face_normal;  // [n_faces][3]
@@ -149,6 +152,7 @@ hipError_t launch_sweep(const Batch &b, const CaseView &h0, int cur, int total_i
 // (gsis_sweep.hip) tensor grids whose fastest axis divides the block
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int cur, int total_items, hipStream_t s);
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
+hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_patch_rows(const CaseView *cv, const CaseView &h, hipStream_t s);
 hipError_t launch_ghost_rows(const CaseView *cv, const CaseView &h, int n_ghost, hipStream_t s);
 hipError_t launch_gather_vdf(const CaseView *cv, const CaseView &h, int n_kin, int cur, void *out, int dir,

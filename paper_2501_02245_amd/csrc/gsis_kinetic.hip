@@ -541,7 +541,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
     T *__restrict__ fnew = (T *)C.f[cur ^ 1];
     const int n0 = C.n[0], n1 = C.n[1], n2 = (VD == 3) ? C.n[2] : 0;
     const int NA3 = n0 + n1 + n2;
-    T *xs = (T *)smem_raw;
+    // FP64 offsets and weights for the moment sums (the sums are accumulated
+    // in FP64 from the stored values: this kernel serves any grid shape, so
+    // there is no plane structure to compensate the FP32 products with)
+    double *csd = (double *)smem_raw;
+    double *wsd = csd + NA3;
+    T *xs = (T *)(wsd + NA3);
     T *ws = xs + NA3;
     T *cs = ws + NA3;      // c_d = x_j - u_d of the own target, formed in FP64 and rounded once
     T *tabs = cs + NA3;
@@ -611,6 +616,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
         xs[j] = (T)C.xv[d * MAXA + jj];
         ws[j] = (T)C.wv[d * MAXA + jj];
         cs[j] = (T)(C.xv[d * MAXA + jj] - P.u[d]);
+        csd[j] = C.xv[d * MAXA + jj] - P.u[d];
+        wsd[j] = C.wv[d * MAXA + jj];
     }
     __syncthreads();
     // separable Gaussian factors exp(-(x_j - u_d)^2 / T), evaluated in FP64:
@@ -643,9 +650,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
     T *fn = fnew + (size_t)slot * C.row;
     const int nvp = C.row / ((VD == 3) ? 1 : 2);   // padded length of one function
 
-    T acc[NSUM];
+    double acc[NSUM];
 #pragma unroll
-    for (int i = 0; i < NSUM; ++i) acc[i] = (T)0;
+    for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
 
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
@@ -718,35 +725,35 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
             n1v = num1 * rden;
             fn[nvp + k] = n1v;
         }
-        acc_moments<T, VD>(acc, w, n0v, n1v, c0, c1, c2, cc);
+        const double wd = wsd[vi.ix] * wsd[n0 + vi.iy] * ((VD == 3) ? wsd[n0 + n1 + vi.iz] : 1.0);
+        const double d0 = csd[vi.ix], d1 = csd[n0 + vi.iy], d2 = (VD == 3) ? csd[n0 + n1 + vi.iz] : 0.0;
+        const double dcc = d0 * d0 + d1 * d1 + d2 * d2;
+        acc_moments<double, VD>(acc, wd, (double)n0v, (double)n1v, d0, d1, d2, dcc);
         // moment balance at the old iterate: w (num - den f_old) (1, c, c^2 [+psi])
-        const T r0 = w * (num0 - den * o0);
+        const double r0 = wd * (double)(num0 - den * o0);
         acc[S_RES] += r0;
-        acc[S_RES + 1] += r0 * c0;
-        acc[S_RES + 2] += r0 * c1;
-        if (VD == 3) acc[S_RES + 3] += r0 * c2;
-        T re = r0 * cc;
-        if (VD == 2) re += w * (num1 - den * o1);
+        acc[S_RES + 1] += r0 * d0;
+        acc[S_RES + 2] += r0 * d1;
+        if (VD == 3) acc[S_RES + 3] += r0 * d2;
+        double re = r0 * dcc;
+        if (VD == 2) re += wd * (double)(num1 - den * o1);
         acc[S_RES + 4] += re;
         // outgoing mass flux through wall faces (numerator of the next rho_w)
         for (int j = 0; j < nw; ++j) {
             const FaceS<T> &F = fs[s_wl[j]];
             const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
-            if (a > (T)0) acc[S_WALL + F.wall] += w * a * n0v;
+            if (a > (T)0) acc[S_WALL + F.wall] += wd * (double)(a * n0v);
         }
         vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
-    double v[NSUM];
-#pragma unroll
-    for (int i = 0; i < NSUM; ++i) v[i] = (double)acc[i];
-    block_reduce_store<NSUM>(v, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+    block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
 }
 
 template <typename T, int VD>
 static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
 {
     int NA3 = h0.n[0] + h0.n[1] + (VD == 3 ? h0.n[2] : 0);
-    size_t lds = sizeof(T) * (size_t)NA3 * (3 + 1 + MAXF);
+    size_t lds = sizeof(double) * (size_t)NA3 * 2 + sizeof(T) * (size_t)NA3 * (3 + 1 + MAXF);
     hipLaunchKernelGGL((k_sweep<T, VD>), dim3(total), dim3(BLOCK), lds, s, b, cur);
     return hipGetLastError();
 }
@@ -874,6 +881,7 @@ __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ 
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
 {
     if (n_kin <= 0) return hipSuccess;
+    if (h.fast) return launch_correct_fast(cv, h, n_kin, cur, s);
     int NA3 = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
     dim3 g(n_kin * h.ntile);
     if (h.dtype == GSIS_F32) {

@@ -19,37 +19,6 @@
 
 namespace gsis {
 
-static __device__ int solve_small(int n, double *A, double *b)
-{
-    for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < n; ++r)
-            if (fabs(A[r * n + col]) > fabs(A[piv * n + col])) piv = r;
-        if (!(fabs(A[piv * n + col]) > 0.0)) return -1;
-        if (piv != col) {
-            for (int j = 0; j < n; ++j) {
-                double t = A[col * n + j];
-                A[col * n + j] = A[piv * n + j];
-                A[piv * n + j] = t;
-            }
-            double t = b[col];
-            b[col] = b[piv];
-            b[piv] = t;
-        }
-        for (int r = col + 1; r < n; ++r) {
-            double fac = A[r * n + col] / A[col * n + col];
-            for (int j = col; j < n; ++j) A[r * n + j] -= fac * A[col * n + j];
-            b[r] -= fac * b[col];
-        }
-    }
-    for (int r = n - 1; r >= 0; --r) {
-        double s = b[r];
-        for (int j = r + 1; j < n; ++j) s -= A[r * n + j] * b[j];
-        b[r] = s / A[r * n + r];
-    }
-    return 0;
-}
-
 // fields for gradients: 0..2 u, 3 T, 4 rho, 5 |u|
 __device__ __forceinline__ double field(const double *W, int v)
 {
@@ -69,49 +38,66 @@ __device__ __forceinline__ double bfield(const CaseView &C, int p, int v)
     return sqrt(ps[1] * ps[1] + ps[2] * ps[2] + ps[3] * ps[3]);
 }
 
-__global__ void k_lsq(const CaseView *__restrict__ cvp, const double *__restrict__ W, int nvar)
+// least-squares gradients (Sec. 3.4 Step 2) from the per-face coefficients
+// built with the mesh: grad_v = sum_e c_e (phi_e - phi_i); the density uses
+// the coefficients without wall faces.  Variables: 0..2 u, 3 T [, 4 rho, 5 |u|].
+template <int NV>
+__global__ __launch_bounds__(256) void k_lsq(const CaseView *__restrict__ cvp, const double *__restrict__ W)
 {
     const CaseView &C = *cvp;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= C.n_cells) return;
-    const int dim = C.dim;
     const double *Wi = W + 5 * (size_t)i;
-    const double *xi = C.cell_center + 3 * (size_t)i;
-    int e0 = C.cf_ptr[i], e1 = C.cf_ptr[i + 1];
-    for (int v = 0; v < nvar; ++v) {
-        double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, b[3] = {0, 0, 0};
-        double fi = field(Wi, v);
-        for (int e = e0; e < e1; ++e) {
-            int oth = C.cf_other[e];
-            double dx[3], dphi;
-            if (oth >= 0) {
-                for (int d = 0; d < 3; ++d) dx[d] = C.cell_center[3 * (size_t)oth + d] - xi[d];
-                dphi = field(W + 5 * (size_t)oth, v) - fi;
+    double fi[NV], g[NV][3];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        fi[v] = field(Wi, v);
+        g[v][0] = g[v][1] = g[v][2] = 0.0;
+    }
+    const int e0 = C.cf_ptr[i], e1 = C.cf_ptr[i + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int oth = C.cf_other[e];
+        const double *ca = C.lsq + 6 * (size_t)e;
+        double fo[NV];
+        bool wall = false;
+        if (oth >= 0) {
+            const double *Wo = W + 5 * (size_t)oth;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fo[v] = field(Wo, v);
+        } else {
+            const int p = -1 - oth;
+            wall = C.patch_kind[p] == GSIS_PATCH_WALL;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fo[v] = (v == 4 && wall) ? 0.0 : bfield(C, p, v);
+        }
+        const double c0 = ca[0], c1 = ca[1], c2 = ca[2];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (v == 4) {
+                if (wall) continue;
+                const double d = fo[v] - fi[v];
+                g[v][0] += ca[3] * d;
+                g[v][1] += ca[4] * d;
+                g[v][2] += ca[5] * d;
             } else {
-                double bv = bfield(C, -1 - oth, v);
-                if (isnan(bv)) continue;
-                int f = C.cf_face[e];
-                for (int d = 0; d < 3; ++d) dx[d] = C.face_center[3 * (size_t)f + d] - xi[d];
-                dphi = bv - fi;
-            }
-            double r2 = 0.0;
-            for (int d = 0; d < dim; ++d) r2 += dx[d] * dx[d];
-            double wgt = 1.0 / r2;
-            for (int a = 0; a < dim; ++a) {
-                for (int c = 0; c < dim; ++c) A[a * dim + c] += wgt * dx[a] * dx[c];
-                b[a] += wgt * dx[a] * dphi;
+                const double d = fo[v] - fi[v];
+                g[v][0] += c0 * d;
+                g[v][1] += c1 * d;
+                g[v][2] += c2 * d;
             }
         }
-        double *g = C.grad + ((size_t)i * 6 + v) * 3;
-        g[0] = g[1] = g[2] = 0.0;
-        if (solve_small(dim, A, b) == 0)
-            for (int d = 0; d < dim; ++d) g[d] = b[d];
     }
+    double *go = C.grad + (size_t)i * 18;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int d = 0; d < 3; ++d) go[3 * v + d] = g[v][d];
 }
 
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lsq, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, W, nvar);
+    const dim3 g((h.n_cells + 255) / 256);
+    if (nvar == 6) hipLaunchKernelGGL(k_lsq<6>, g, dim3(256), 0, s, cv, W);
+    else hipLaunchKernelGGL(k_lsq<4>, g, dim3(256), 0, s, cv, W);
     return hipGetLastError();
 }
 
@@ -311,10 +297,9 @@ __device__ __forceinline__ void cell_balance(const CaseView &C, int i, double *R
 {
     for (int c = 0; c < 5; ++c) R[c] = 0.0;
     for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
-        int f = C.cf_face[e];
-        double sgn = (C.face_cells[2 * f] == i) ? -1.0 : 1.0;
-        double S = C.face_area[f];
-        for (int c = 0; c < 5; ++c) R[c] += sgn * C.fflux[5 * (size_t)f + c] * S;
+        const int f = C.cf_face[e];
+        const double fs = C.cf_fs[e];   // -S if i owns the face, +S otherwise
+        for (int c = 0; c < 5; ++c) R[c] += C.fflux[5 * (size_t)f + c] * fs;
     }
 }
 
@@ -332,7 +317,8 @@ __global__ void k_residual_cells(const CaseView *__restrict__ cvp, double *__res
 hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const double *W, const double *hot,
                                  double *Rout, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lsq, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, W, 4);
+    hipError_t e = launch_lsq(cv, h, W, 4, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_face_flux, dim3((h.n_faces + 127) / 128), dim3(128), 0, s, cv, W, hot);
     hipLaunchKernelGGL(k_residual_cells, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, Rout);
     return hipGetLastError();
@@ -362,14 +348,14 @@ __device__ double cell_D(const CaseView &C, int i, const double *Wi)
     const double gam = 5.0 / 3.0;
     double a = sqrt(gam * Wi[4] / 2.0);
     double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wi[4], C.omega) / (sqrt(M_PI) * Wi[0]);
-    double D = 0.0;
+    // sum_f S_f |u.n_f| = V sum_e |u . (n S / V)_e|; the rest from the per-cell sums
+    double un = 0.0;
     for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
-        int f = C.cf_face[e];
-        const double *n = C.face_normal + 3 * (size_t)f;
-        double un = Wi[1] * n[0] + Wi[2] * n[1] + Wi[3] * n[2];
-        D += C.face_area[f] * (fabs(un) + a + 2.0 * nu / C.face_dist[f]);
+        const double *n = C.cf_nsv + 3 * (size_t)e;
+        un += fabs(Wi[1] * n[0] + Wi[2] * n[1] + Wi[3] * n[2]);
     }
-    return D;
+    const double *sS = C.cell_sS + 2 * (size_t)i;
+    return C.cell_volume[i] * un + a * sS[0] + 2.0 * nu * sS[1];
 }
 
 __global__ void k_cons(const CaseView *__restrict__ cvp, const double *__restrict__ W)
@@ -464,7 +450,7 @@ hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, 
     const int gc = (h.n_cells + 127) / 128, gf = (h.n_faces + 127) / 128, gd = (h.n_cells + 255) / 256;
     hipLaunchKernelGGL(k_cons, dim3(gc), dim3(128), 0, s, cv, W);
     for (int it = 0; it < n_inner; ++it) {
-        hipLaunchKernelGGL(k_lsq, dim3(gc), dim3(128), 0, s, cv, W, 4);
+        hipLaunchKernelGGL(k_lsq<4>, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv, W);
         hipLaunchKernelGGL(k_face_flux, dim3(gf), dim3(128), 0, s, cv, W, hot);
         if (cfl < 0) {
             hipLaunchKernelGGL(k_dloc, dim3(gd), dim3(256), 0, s, cv, W);
@@ -508,15 +494,25 @@ __global__ void k_eps_part(const CaseView *__restrict__ cvp, const double *__res
     if (threadIdx.x < 6) C.red[8 + 6 * (size_t)blockIdx.x + threadIdx.x] = sm[threadIdx.x][0];
 }
 
-__global__ void k_eps_final(const CaseView *__restrict__ cvp, int nb)
+// one block: thread t sums block partials t, t + 256, ... (fixed order), then
+// a fixed-order tree
+__global__ __launch_bounds__(256) void k_eps_final(const CaseView *__restrict__ cvp, int nb)
 {
     const CaseView &C = *cvp;
-    if (threadIdx.x != 0) return;
+    __shared__ double sm[6][256];
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = 0; b < nb; ++b)
+    for (int b = threadIdx.x; b < nb; b += 256)
         for (int c = 0; c < 6; ++c) s[c] += C.red[8 + 6 * (size_t)b + c];
-    for (int k = 0; k < 3; ++k) {
-        double num = s[2 * k], den = s[2 * k + 1];
+    for (int c = 0; c < 6; ++c) sm[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int c = 0; c < 6; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        double num = sm[2 * k][0], den = sm[2 * k + 1][0];
         C.eps[k] = (den > 1e-30) ? sqrt(num / den) : sqrt(num);
     }
 }
@@ -525,7 +521,7 @@ hipError_t launch_eps(const CaseView *cv, const CaseView &h, const double *Wnew,
 {
     int nb = (h.n_cells + 255) / 256;
     hipLaunchKernelGGL(k_eps_part, dim3(nb), dim3(256), 0, s, cv, Wnew, Wold);
-    hipLaunchKernelGGL(k_eps_final, dim3(1), dim3(64), 0, s, cv, nb);
+    hipLaunchKernelGGL(k_eps_final, dim3(1), dim3(256), 0, s, cv, nb);
     return hipGetLastError();
 }
 
@@ -584,7 +580,8 @@ __global__ void k_copy_i(int32_t *d, const int32_t *s, int n)
 hipError_t launch_flags(const CaseView *cv, const CaseView &h, double Kn_ref, int layers, hipStream_t s)
 {
     const int gc = (h.n_cells + 127) / 128;
-    hipLaunchKernelGGL(k_lsq, dim3(gc), dim3(128), 0, s, cv, h.W, 6);
+    hipError_t e = launch_lsq(cv, h, h.W, 6, s);
+    if (e != hipSuccess) return e;
     int32_t *a = h.scan_tmp, *b = h.scan_tmp + h.n_cells;
     hipLaunchKernelGGL(k_kn_flags, dim3(gc), dim3(128), 0, s, cv, Kn_ref, layers, a);
     for (int l = 1; l < layers; ++l) {
@@ -686,7 +683,22 @@ __global__ __launch_bounds__(1024) void k_compact(const CaseView *__restrict__ c
     }
 }
 
-// NS cells with a kinetic face neighbour, ascending cell id -> rows of grow
+// NS cells with a kinetic face neighbour -> mark in scan_tmp (after compaction)
+__global__ void k_ghost_mark(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n_cells) return;
+    int g = 0;
+    if (C.slot_of_cell[i] < 0)
+        for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+            const int o = C.cf_other[e];
+            if (o >= 0 && C.slot_of_cell[o] >= 0) g = 1;
+        }
+    C.scan_tmp[i] = g;
+}
+
+// marked cells in ascending id -> rows of grow (single block, deterministic)
 __global__ __launch_bounds__(1024) void k_ghost_list(const CaseView *__restrict__ cvp)
 {
     const CaseView &C = *cvp;
@@ -695,29 +707,15 @@ __global__ __launch_bounds__(1024) void k_ghost_list(const CaseView *__restrict_
     const int chunk = (n + 1023) / 1024;
     const int lo = tid * chunk, hi = min(lo + chunk, n);
     int cnt = 0;
-    for (int i = lo; i < hi; ++i) {
-        int g = 0;
-        if (C.slot_of_cell[i] < 0)
-            for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
-                int o = C.cf_other[e];
-                if (o >= 0 && C.slot_of_cell[o] >= 0) g = 1;
-            }
-        cnt += g;
-    }
+    for (int i = lo; i < hi; ++i) cnt += C.scan_tmp[i];
     int base = block_excl_scan(cnt, sm);
-    int total = sm[1024];
+    const int total = sm[1024];
     if (total > C.gcap) {
         if (tid == 0) C.status[1] = 1;
         return;
     }
     for (int i = lo; i < hi; ++i) {
-        int g = 0;
-        if (C.slot_of_cell[i] < 0)
-            for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
-                int o = C.cf_other[e];
-                if (o >= 0 && C.slot_of_cell[o] >= 0) g = 1;
-            }
-        if (g) {
+        if (C.scan_tmp[i]) {
             C.ghost_cell[base] = i;
             C.ghost_slot[i] = base++;
         } else {
@@ -730,6 +728,7 @@ __global__ __launch_bounds__(1024) void k_ghost_list(const CaseView *__restrict_
 hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s)
 {
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, cv);
+    hipLaunchKernelGGL(k_ghost_mark, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv);
     hipLaunchKernelGGL(k_ghost_list, dim3(1), dim3(1024), 0, s, cv);
     return hipGetLastError();
 }

@@ -66,9 +66,102 @@ __device__ __forceinline__ void block_reduce2(double (&v)[NS], double *out, doub
     }
 }
 
+// Per-lane moment sums of the plane kernels.  3D: with c_z the lane constant
+// and (c_x, c_y) varying, sum_k w f c_x^a c_y^b is kept for the (a, b) the
+// moments need; A* = (a, 0), B* = (0, b), C1 = (1, 1), C2 = (2, 1), D2 = (1, 2).
+// Reduced 2D (lane constant c_y): A* powers of c_x on phi, Q* on psi.
+// R* = moment balance w (num - den f_old) (1, c_x, c_y, c^2 parts), Rp its psi.
+template <typename T>
+struct PlaneSums {
+    T A0 = 0, A1 = 0, A2 = 0, A3 = 0, B1 = 0, B2 = 0, B3 = 0, C1 = 0, C2 = 0, D2 = 0;
+    T Q0 = 0, Q1 = 0;
+    T R0 = 0, R1 = 0, R2 = 0, R3 = 0, Rp = 0;
+
+    // fold one x-plane's sums of powers of c_y (T*) and its balance sums (S*):
+    // x powers from the records, compensated by their low parts
+    __device__ __forceinline__ void fold(T cx, T clo, T c2, T c2lo, T c3, T c3lo, T T0, T T1, T T2, T T3, T S0,
+                                         T S1, T S2)
+    {
+        A0 += T0;
+        A1 += cx * T0 + clo * T0;
+        A2 += c2 * T0 + c2lo * T0;
+        A3 += c3 * T0 + c3lo * T0;
+        B1 += T1;
+        B2 += T2;
+        B3 += T3;
+        C1 += cx * T1 + clo * T1;
+        C2 += c2 * T1 + c2lo * T1;
+        D2 += cx * T2 + clo * T2;
+        R0 += S0;
+        R1 += cx * S0 + clo * S0;
+        R2 += S1;
+        R3 += c2 * S0 + c2lo * S0 + S2;
+    }
+};
+
+// Multiply in the lane constant (offset cl, weight wl) in FP64, map to the
+// NSUM layout of the partial sums, add the outgoing wall sums of the faces
+// and reduce over the block into out[NSUM].
+template <typename T, int VD, int NF>
+__device__ __forceinline__ void finish_partials(const PlaneSums<T> &S, const T (&Wf)[NF], const int (&fwall)[NF],
+                                                double cl, double wl, double *out, double *red)
+{
+    double v[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) v[i] = 0.0;
+    const double cl2 = cl * cl;
+    if (VD == 3) {
+        const double a0 = S.A0, a1 = S.A1, a2 = S.A2, a3 = S.A3, b1 = S.B1, b2 = S.B2, b3 = S.B3, c1 = S.C1,
+                     c2 = S.C2, d2 = S.D2;
+        v[0] = wl * a0;
+        v[1] = wl * a1;
+        v[2] = wl * b1;
+        v[3] = wl * cl * a0;
+        v[4] = wl * a2;
+        v[5] = wl * b2;
+        v[6] = wl * cl2 * a0;
+        v[7] = wl * c1;
+        v[8] = wl * cl * a1;
+        v[9] = wl * cl * b1;
+        v[10] = wl * (a3 + d2 + cl2 * a1);
+        v[11] = wl * (c2 + b3 + cl2 * b1);
+        v[12] = wl * cl * (a2 + b2 + cl2 * a0);
+        v[S_RES] = wl * (double)S.R0;
+        v[S_RES + 1] = wl * (double)S.R1;
+        v[S_RES + 2] = wl * (double)S.R2;
+        v[S_RES + 3] = wl * cl * (double)S.R0;
+        v[S_RES + 4] = wl * ((double)S.R3 + cl2 * (double)S.R0);
+    } else {
+        const double a0 = S.A0, a1 = S.A1, a2 = S.A2, a3 = S.A3;
+        v[0] = wl * a0;
+        v[1] = wl * a1;
+        v[2] = wl * cl * a0;
+        v[3] = wl * a2;
+        v[4] = wl * cl2 * a0;
+        v[5] = wl * cl * a1;
+        v[6] = wl * (a3 + cl2 * a1);
+        v[7] = wl * cl * (a2 + cl2 * a0);
+        v[8] = wl * (double)S.Q0;
+        v[9] = wl * (double)S.Q1;
+        v[10] = wl * cl * (double)S.Q0;
+        v[S_RES] = wl * (double)S.R0;
+        v[S_RES + 1] = wl * (double)S.R1;
+        v[S_RES + 2] = wl * cl * (double)S.R0;
+        v[S_RES + 4] = wl * ((double)S.R3 + cl2 * (double)S.R0 + (double)S.Rp);
+    }
+#pragma unroll
+    for (int q2 = 0; q2 < MAXW; ++q2) {
+        double sw = 0.0;
+#pragma unroll
+        for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? (double)Wf[l] : 0.0;
+        v[S_WALL + q2] = wl * sw;
+    }
+    block_reduce2<NSUM>(v, out, red);
+}
+
 }  // namespace
 
-template <typename T, int VD, int NF>
+template <typename T, int VD, int NF, int U>
 __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B, int cur)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -177,10 +270,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B, int cur)
     for (int l = 0; l < NF; ++l) AL[l] = ((VD == 3) ? fnz[l] : fny[l]) * cL + fun[l];
 
     // per-lane accumulators
-    T A0 = 0, A1 = 0, A2 = 0, A3 = 0, B1 = 0, B2 = 0, B3 = 0, C1 = 0, C2 = 0, D2 = 0;   // moments (see fold)
-    T Q0 = 0, Q1 = 0;                                                                   // reduced psi
-    T R0 = 0, R1 = 0, R2 = 0, R3 = 0, Rp = 0;                                           // moment balance
-    T Wf[NF];                                                                           // outgoing wall sums
+    PlaneSums<T> S;
+    T Wf[NF];   // outgoing wall sums
 #pragma unroll
     for (int l = 0; l < NF; ++l) Wf[l] = (T)0;
 
@@ -196,82 +287,89 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B, int cur)
             T Ax[NF];
 #pragma unroll
             for (int l = 0; l < NF; ++l) Ax[l] = fnx[l] * cx + AL[l];
-            T T0 = 0, T1 = 0, T2 = 0, T3 = 0, S0 = 0, S1 = 0, S2 = 0;
+            T T0 = 0, T1 = 0, T2 = 0, T3 = 0, Z0 = 0, Z1 = 0, Z2 = 0;   // this plane
             int iy = yq;
             int k = (ix * ny + iy) * nz + ilc;
             const int kstep = q * nz;
-            for (int m = 0; m < M; ++m, iy += q, k += kstep) {
-                // loads first
-                const T o = fo[k];
-                T v[NF];
+            // U points per round (U divides M): every load of the round is in
+            // flight before the first is consumed
+            for (int m = 0; m < M; m += U, iy += U * q, k += U * kstep) {
+                T o[U], v[U][NF];
 #pragma unroll
-                for (int l = 0; l < NF; ++l) v[l] = fnb[l][k];
-                const int jy = nx + iy;
-                const T cy = rc[jy], Ey = rE[jy], Py = rP[jy], Ky = rK[jy], wy = rw[jy];
-                const T cc = cy * cy + cxz2;
-                const T g = Exz * Ey * (Pxz + Py) * ((Kxz + Ky) * (cc * it - shift0) + (T)1);
-                T num = itau * g + idt * o;
-                T den = itau + idt;
+                for (int u = 0; u < U; ++u) {
+                    o[u] = fo[k + u * kstep];
 #pragma unroll
-                for (int l = 0; l < NF; ++l) {
-                    const T a = fny[l] * cy + Ax[l];
-                    den += fmax(a, (T)0);
-                    num -= fmin(a, (T)0) * fsc[l] * v[l];
+                    for (int l = 0; l < NF; ++l) v[u][l] = fnb[l][k + u * kstep];
                 }
-                const T fnv = num * fast_rcp(den);
-                fn[k] = fnv;
-                // moment sums: powers of c_y only
-                const T w = wx * wy;
-                const T h = w * fnv;
-                T0 += h;
-                const T hy = h * cy;
-                T1 += hy;
-                const T hy2 = hy * cy;
-                T2 += hy2;
-                T3 += hy2 * cy;
-                const T r = w * (num - den * o);
-                S0 += r;
-                const T ry = r * cy;
-                S1 += ry;
-                S2 += ry * cy;
-                if (nw > 0) {
 #pragma unroll
-                    for (int l = 0; l < NF; ++l)
-                        if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[l], (T)0);
+                for (int u = 0; u < U; ++u) {
+                    const int jy = nx + iy + u * q;
+                    const T cy = rc[jy], Ey = rE[jy], Py = rP[jy], Ky = rK[jy], wy = rw[jy];
+                    const T cc = cy * cy + cxz2;
+                    const T g = Exz * Ey * (Pxz + Py) * ((Kxz + Ky) * (cc * it - shift0) + (T)1);
+                    T num = itau * g + idt * o[u];
+                    T den = itau + idt;
+#pragma unroll
+                    for (int l = 0; l < NF; ++l) {
+                        const T a = fny[l] * cy + Ax[l];
+                        den += fmax(a, (T)0);
+                        num -= fmin(a, (T)0) * fsc[l] * v[u][l];
+                    }
+                    const T fnv = num * fast_rcp(den);
+                    fn[k + u * kstep] = fnv;
+                    // moment sums: powers of c_y only
+                    const T w = wx * wy;
+                    const T h = w * fnv;
+                    T0 += h;
+                    const T hy = h * cy;
+                    T1 += hy;
+                    const T hy2 = hy * cy;
+                    T2 += hy2;
+                    T3 += hy2 * cy;
+                    const T r = w * (num - den * o[u]);
+                    Z0 += r;
+                    const T ry = r * cy;
+                    Z1 += ry;
+                    Z2 += ry * cy;
+                    if (nw > 0) {
+#pragma unroll
+                        for (int l = 0; l < NF; ++l)
+                            if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[l], (T)0);
+                    }
                 }
             }
-            // fold this plane: x powers from the records, compensated by their low parts
-            const T clo = rlo[ix], c2 = rlo[nx + ix], c2lo = rlo[2 * nx + ix], c3 = rlo[3 * nx + ix],
-                    c3lo = rlo[4 * nx + ix];
-            A0 += T0;
-            A1 += cx * T0 + clo * T0;
-            A2 += c2 * T0 + c2lo * T0;
-            A3 += c3 * T0 + c3lo * T0;
-            B1 += T1;
-            B2 += T2;
-            B3 += T3;
-            C1 += cx * T1 + clo * T1;
-            C2 += c2 * T1 + c2lo * T1;
-            D2 += cx * T2 + clo * T2;
-            R0 += S0;
-            R1 += cx * S0 + clo * S0;
-            R2 += S1;
-            R3 += c2 * S0 + c2lo * S0 + S2;
+            S.fold(cx, rlo[ix], rlo[nx + ix], rlo[2 * nx + ix], rlo[3 * nx + ix], rlo[4 * nx + ix], T0, T1, T2, T3,
+                   Z0, Z1, Z2);
         }
     } else {
         // ---- reduced 2D: lanes own y = ilc; x varies per step --------------
         const int q = BLOCK / ny;
         const int xq = threadIdx.x / ny;
         const int ix0 = vt * C.xp, ix1 = min(ix0 + C.xp, nx);
-        for (int ix = ix0 + xq; ix < ix1; ix += q) {
-            const int k = ix * ny + ilc;
-            const T o0 = fo[k], o1 = fo[nvp + k];
-            T v0[NF], v1[NF];
+        for (int ixr = ix0 + xq; ixr < ix1; ixr += U * q) {
+          // U lines per round, loads first (lines past the tile are skipped)
+          T o0u[U], o1u[U], v0u[U][NF], v1u[U][NF];
 #pragma unroll
-            for (int l = 0; l < NF; ++l) {
-                v0[l] = fnb[l][k];
-                v1[l] = fnb[l][nvp + k];
+          for (int u = 0; u < U; ++u) {
+            const int ix = ixr + u * q;
+            const int k = ix * ny + ilc;
+            if (ix < ix1) {
+                o0u[u] = fo[k];
+                o1u[u] = fo[nvp + k];
+#pragma unroll
+                for (int l = 0; l < NF; ++l) {
+                    v0u[u][l] = fnb[l][k];
+                    v1u[u][l] = fnb[l][nvp + k];
+                }
             }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int ix = ixr + u * q;
+            if (ix >= ix1) break;
+            const int k = ix * ny + ilc;
+            const T o0 = o0u[u], o1 = o1u[u];
+            const T *v0 = v0u[u], *v1 = v1u[u];
             const T cx = rc[ix], Ex = rE[ix], Px = rP[ix], Kx = rK[ix], wx = rw[ix];
             const T cc = cx * cx + cL * cL;
             const T EP = Ex * EL * (Px + PL);
@@ -293,85 +391,215 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B, int cur)
             fn[k] = f0;
             fn[nvp + k] = f1;
             const T h = wx * f0;
-            A0 += h;
+            S.A0 += h;
             const T hx = h * cx;
-            A1 += hx;
+            S.A1 += hx;
             const T hx2 = hx * cx;
-            A2 += hx2;
-            A3 += hx2 * cx;
+            S.A2 += hx2;
+            S.A3 += hx2 * cx;
             const T hp = wx * f1;
-            Q0 += hp;
-            Q1 += hp * cx;
+            S.Q0 += hp;
+            S.Q1 += hp * cx;
             const T r = wx * (num0 - den * o0);
-            R0 += r;
+            S.R0 += r;
             const T rx1 = r * cx;
-            R1 += rx1;
-            R3 += rx1 * cx;
-            Rp += wx * (num1 - den * o1);
+            S.R1 += rx1;
+            S.R3 += rx1 * cx;
+            S.Rp += wx * (num1 - den * o1);
             if (nw > 0) {
 #pragma unroll
                 for (int l = 0; l < NF; ++l)
                     if (fwall[l] >= 0) Wf[l] += h * fmax(fnx[l] * cx + AL[l], (T)0);
             }
+          }
         }
     }
 
     // ---- per-lane constants in FP64, standard partial-sum layout ----------
-    double v[NSUM];
+    const int dl = (VD == 3) ? 2 : 1;
+    finish_partials<T, VD, NF>(S, Wf, fwall, C.xv[dl * MAXA + ilc] - P.u[dl], C.wv[dl * MAXA + ilc],
+                               C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+}
+
+// ---------------------------------------------------------------------------
+// GSIS correction (Sec. 3.1): f += f_eq(W^{n+1}) - f_eq(W^{n+1/2}) on the plane
+// layout, with the same fused moment and wall sums as the sweep.  Both f_eq
+// are conservation-fixed Maxwellians, separable per axis: E = E_x E_y E_z and
+// multiplier P = P_x + P_y + P_z (a_0 folded into P_x), tabulated in FP64 per
+// axis and rounded once.
+// ---------------------------------------------------------------------------
+template <typename T, int VD, int NF, int U>
+__global__ __launch_bounds__(BLOCK) void k_correct_fast(const CaseView *__restrict__ cvp, int n_kin, int cur)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    const CaseView &C = *cvp;
+    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int vt = b / n_kin, t = b - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const FeqRec &Fa = C.feq[2 * (size_t)slot];       // f_eq(W^{n+1})
+    const FeqRec &Fb = C.feq[2 * (size_t)slot + 1];   // f_eq(W^{n+1/2})
+    const int nx = C.n[0], ny = C.n[1], nz = (VD == 3) ? C.n[2] : 1;
+    const int NA = nx + ny + ((VD == 3) ? nz : 0);
+    const int nvp = C.row / ((VD == 3) ? 1 : 2);
+    gptr<T> fr = (gptr<T>)C.f[cur] + (size_t)slot * C.row;
+
+    T *rc = (T *)smem_raw;   // x_j - u_d of the moment frame
+    T *rw = rc + NA;
+    T *Ea = rw + NA, *Pa = Ea + NA, *Eb = Pa + NA, *Pb = Eb + NA;
+    T *rlo = Pb + NA;        // x axis: low part of c, c^2 and its low part, c^3 and its low part
+
+    // wall faces only (outgoing sums for the next wall density)
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    int fwall[NF];
+    T fnx[NF], fny[NF], fnz[NF], fun[NF];
+    int nw = 0;
 #pragma unroll
-    for (int i = 0; i < NSUM; ++i) v[i] = 0.0;
-    {
-        const int d = (VD == 3) ? 2 : 1;
-        const double cl = C.xv[d * MAXA + ilc] - P.u[d];
-        const double wl = C.wv[d * MAXA + ilc];
-        const double cl2 = cl * cl;
-        if (VD == 3) {
-            const double a0 = A0, a1 = A1, a2 = A2, a3 = A3, b1 = B1, b2 = B2, b3 = B3, c1 = C1, c2 = C2, d2 = D2;
-            v[0] = wl * a0;
-            v[1] = wl * a1;
-            v[2] = wl * b1;
-            v[3] = wl * cl * a0;
-            v[4] = wl * a2;
-            v[5] = wl * b2;
-            v[6] = wl * cl2 * a0;
-            v[7] = wl * c1;
-            v[8] = wl * cl * a1;
-            v[9] = wl * cl * b1;
-            v[10] = wl * (a3 + d2 + cl2 * a1);
-            v[11] = wl * (c2 + b3 + cl2 * b1);
-            v[12] = wl * cl * (a2 + b2 + cl2 * a0);
-            v[S_RES] = wl * (double)R0;
-            v[S_RES + 1] = wl * (double)R1;
-            v[S_RES + 2] = wl * (double)R2;
-            v[S_RES + 3] = wl * cl * (double)R0;
-            v[S_RES + 4] = wl * ((double)R3 + cl2 * (double)R0);
-        } else {
-            const double a0 = A0, a1 = A1, a2 = A2, a3 = A3;
-            v[0] = wl * a0;
-            v[1] = wl * a1;
-            v[2] = wl * cl * a0;
-            v[3] = wl * a2;
-            v[4] = wl * cl2 * a0;
-            v[5] = wl * cl * a1;
-            v[6] = wl * (a3 + cl2 * a1);
-            v[7] = wl * cl * (a2 + cl2 * a0);
-            v[8] = wl * (double)Q0;
-            v[9] = wl * (double)Q1;
-            v[10] = wl * cl * (double)Q0;
-            v[S_RES] = wl * (double)R0;
-            v[S_RES + 1] = wl * (double)R1;
-            v[S_RES + 2] = wl * cl * (double)R0;
-            v[S_RES + 4] = wl * ((double)R3 + cl2 * (double)R0 + (double)Rp);
-        }
-#pragma unroll
-        for (int q2 = 0; q2 < MAXW; ++q2) {
-            double sw = 0.0;
-#pragma unroll
-            for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? (double)Wf[l] : 0.0;
-            v[S_WALL + q2] = wl * sw;
+    for (int l = 0; l < NF; ++l) {
+        fwall[l] = -1;
+        fnx[l] = fny[l] = fnz[l] = fun[l] = (T)0;
+        if (l < nf) {
+            const int e = e0 + l;
+            fwall[l] = C.cf_wall[e];
+            if (fwall[l] >= 0) {
+                const double n0 = C.cf_nsv[3 * e], n1 = C.cf_nsv[3 * e + 1], n2 = C.cf_nsv[3 * e + 2];
+                fnx[l] = (T)n0;
+                fny[l] = (T)n1;
+                fnz[l] = (T)n2;
+                fun[l] = (T)(P.u[0] * n0 + P.u[1] * n1 + P.u[2] * n2);
+                ++nw;
+            }
         }
     }
-    block_reduce2<NSUM>(v, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+    {
+        const int nq = (VD == 3) ? 4 : 3;   // index of the c^2 coefficient in fx
+        for (int j = threadIdx.x; j < NA; j += BLOCK) {
+            const int d = (j < nx) ? 0 : ((j < nx + ny) ? 1 : 2);
+            const int jj = j - ((d == 0) ? 0 : ((d == 1) ? nx : nx + ny));
+            const double x = C.xv[d * MAXA + jj];
+            const double c = x - P.u[d];
+            rc[j] = (T)c;
+            rw[j] = (T)C.wv[d * MAXA + jj];
+            const double ca = x - Fa.u[d], cb = x - Fb.u[d];
+            Ea[j] = (T)exp(-ca * ca * Fa.it);
+            Eb[j] = (T)exp(-cb * cb * Fb.it);
+            Pa[j] = (T)(((d == 0) ? Fa.fx[0] : 0.0) + Fa.fx[1 + d] * ca + Fa.fx[nq] * ca * ca);
+            Pb[j] = (T)(((d == 0) ? Fb.fx[0] : 0.0) + Fb.fx[1 + d] * cb + Fb.fx[nq] * cb * cb);
+            if (d == 0) {
+                const double c2 = c * c, c3 = c2 * c;
+                rlo[jj] = (T)(c - (double)(T)c);
+                rlo[nx + jj] = (T)c2;
+                rlo[2 * nx + jj] = (T)(c2 - (double)(T)c2);
+                rlo[3 * nx + jj] = (T)c3;
+                rlo[4 * nx + jj] = (T)(c3 - (double)(T)c3);
+            }
+        }
+    }
+    __syncthreads();
+
+    const int ilc = (VD == 3) ? (int)(threadIdx.x % nz) : (int)(threadIdx.x % ny);
+    const int jlc = (VD == 3) ? nx + ny + ilc : nx + ilc;
+    const T cL = rc[jlc], EaL = Ea[jlc], PaL = Pa[jlc], EbL = Eb[jlc], PbL = Pb[jlc];
+    const T tha = (T)Fa.Th, thb = (T)Fb.Th;
+    T AL[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) AL[l] = ((VD == 3) ? fnz[l] : fny[l]) * cL + fun[l];
+    PlaneSums<T> S;
+    T Wf[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) Wf[l] = (T)0;
+    const int ix0 = vt * C.xp, ix1 = min(ix0 + C.xp, nx);
+
+    if (VD == 3) {
+        const int q = BLOCK / nz;
+        const int M = ny / q;
+        const int yq = threadIdx.x / nz;
+        for (int ix = ix0; ix < ix1; ++ix) {
+            const T cx = rc[ix], wx = rw[ix];
+            const T Exa = Ea[ix] * EaL, Pxa = Pa[ix] + PaL, Exb = Eb[ix] * EbL, Pxb = Pb[ix] + PbL;
+            T Ax[NF];
+#pragma unroll
+            for (int l = 0; l < NF; ++l) Ax[l] = fnx[l] * cx + AL[l];
+            T T0 = 0, T1 = 0, T2 = 0, T3 = 0;
+            int iy = yq;
+            int k = (ix * ny + iy) * nz + ilc;
+            const int kstep = q * nz;
+            for (int m = 0; m < M; m += U, iy += U * q, k += U * kstep) {
+                T o[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) o[u] = fr[k + u * kstep];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int jy = nx + iy + u * q;
+                    const T cy = rc[jy];
+                    const T fv = o[u] + (Exa * Ea[jy] * (Pxa + Pa[jy]) - Exb * Eb[jy] * (Pxb + Pb[jy]));
+                    fr[k + u * kstep] = fv;
+                    const T h = wx * rw[jy] * fv;
+                    T0 += h;
+                    const T hy = h * cy;
+                    T1 += hy;
+                    const T hy2 = hy * cy;
+                    T2 += hy2;
+                    T3 += hy2 * cy;
+                    if (nw > 0) {
+#pragma unroll
+                        for (int l = 0; l < NF; ++l)
+                            if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[l], (T)0);
+                    }
+                }
+            }
+            S.fold(cx, rlo[ix], rlo[nx + ix], rlo[2 * nx + ix], rlo[3 * nx + ix], rlo[4 * nx + ix], T0, T1, T2, T3,
+                   (T)0, (T)0, (T)0);
+        }
+    } else {
+        const int q = BLOCK / ny;
+        const int xq = threadIdx.x / ny;
+        for (int ixr = ix0 + xq; ixr < ix1; ixr += U * q) {
+            T o0u[U], o1u[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ix = ixr + u * q;
+                const int k = ix * ny + ilc;
+                if (ix < ix1) {
+                    o0u[u] = fr[k];
+                    o1u[u] = fr[nvp + k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ix = ixr + u * q;
+                if (ix >= ix1) break;
+                const int k = ix * ny + ilc;
+                const T cx = rc[ix], wx = rw[ix];
+                const T ma = Ea[ix] * EaL * (Pa[ix] + PaL), mb = Eb[ix] * EbL * (Pb[ix] + PbL);
+                const T f0 = o0u[u] + (ma - mb);
+                const T f1 = o1u[u] + (tha * ma - thb * mb);
+                fr[k] = f0;
+                fr[nvp + k] = f1;
+                const T h = wx * f0;
+                S.A0 += h;
+                const T hx = h * cx;
+                S.A1 += hx;
+                const T hx2 = hx * cx;
+                S.A2 += hx2;
+                S.A3 += hx2 * cx;
+                const T hp = wx * f1;
+                S.Q0 += hp;
+                S.Q1 += hp * cx;
+                if (nw > 0) {
+#pragma unroll
+                    for (int l = 0; l < NF; ++l)
+                        if (fwall[l] >= 0) Wf[l] += h * fmax(fnx[l] * cx + AL[l], (T)0);
+                }
+            }
+        }
+    }
+    const int dl = (VD == 3) ? 2 : 1;
+    finish_partials<T, VD, NF>(S, Wf, fwall, C.xv[dl * MAXA + ilc] - P.u[dl], C.wv[dl * MAXA + ilc],
+                               C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
 }
 
 size_t sweep_fast_lds(const CaseView &h, size_t es)
@@ -380,23 +608,79 @@ size_t sweep_fast_lds(const CaseView &h, size_t es)
     return es * ((size_t)5 * NA + 5 * h.n[0]);
 }
 
-template <typename T, int VD>
-void launch_nf(const Batch &b, size_t lds, int cur, int total, hipStream_t s)
+template <typename T, int VD, int U>
+void launch_u(const Batch &b, size_t lds, int cur, int total, hipStream_t s)
 {
-    if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_fast<T, VD, 4>), dim3(total), dim3(BLOCK), lds, s, b, cur);
-    else hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+    if (b.nfmax <= 4)
+        hipLaunchKernelGGL((k_sweep_fast<T, VD, 4, U>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+    else
+        hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF, U>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+}
+
+// points per load round: 3D, the largest of 4, 2, 1 that divides the y-values
+// per lane and plane, M = n_y n_z / 256; reduced 2D, 4 lines (guarded);
+// at most 2 for FP64 or 8-face meshes (register budget)
+int rounds_u(const CaseView &h, size_t es, int nfmax)
+{
+    int U = 4;
+    if (h.vdim == 3) {
+        const int M = h.n[1] * h.n[2] / BLOCK;
+        U = (M % 4 == 0) ? 4 : ((M % 2 == 0) ? 2 : 1);
+    }
+    if (es == 8 || nfmax > 4) U = (U > 2) ? 2 : U;
+    return U;
+}
+
+template <typename T, int VD>
+void launch_nf(const Batch &b, const CaseView &h0, size_t lds, int cur, int total, hipStream_t s)
+{
+    const int U = rounds_u(h0, sizeof(T), b.nfmax);
+    if (U == 4) launch_u<T, VD, 4>(b, lds, cur, total, s);
+    else if (U == 2) launch_u<T, VD, 2>(b, lds, cur, total, s);
+    else launch_u<T, VD, 1>(b, lds, cur, total, s);
 }
 
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
 {
     if (h0.dtype == GSIS_F32) {
         size_t lds = sweep_fast_lds(h0, sizeof(float));
-        if (h0.vdim == 3) launch_nf<float, 3>(b, lds, cur, total, s);
-        else launch_nf<float, 2>(b, lds, cur, total, s);
+        if (h0.vdim == 3) launch_nf<float, 3>(b, h0, lds, cur, total, s);
+        else launch_nf<float, 2>(b, h0, lds, cur, total, s);
     } else {
         size_t lds = sweep_fast_lds(h0, sizeof(double));
-        if (h0.vdim == 3) launch_nf<double, 3>(b, lds, cur, total, s);
-        else launch_nf<double, 2>(b, lds, cur, total, s);
+        if (h0.vdim == 3) launch_nf<double, 3>(b, h0, lds, cur, total, s);
+        else launch_nf<double, 2>(b, h0, lds, cur, total, s);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int VD, int U>
+void launch_correct_u(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
+{
+    const int NA = h.n[0] + h.n[1] + (VD == 3 ? h.n[2] : 0);
+    const size_t lds = sizeof(T) * ((size_t)6 * NA + 5 * h.n[0]);
+    dim3 g(n_kin * h.ntile);
+    if (h.nfmax <= 4) hipLaunchKernelGGL((k_correct_fast<T, VD, 4, U>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+    else hipLaunchKernelGGL((k_correct_fast<T, VD, MAXF, U>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+}
+
+template <typename T, int VD>
+void launch_correct_t(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
+{
+    const int U = rounds_u(h, sizeof(T), h.nfmax);
+    if (U == 4) launch_correct_u<T, VD, 4>(cv, h, n_kin, cur, s);
+    else if (U == 2) launch_correct_u<T, VD, 2>(cv, h, n_kin, cur, s);
+    else launch_correct_u<T, VD, 1>(cv, h, n_kin, cur, s);
+}
+
+hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
+{
+    if (h.dtype == GSIS_F32) {
+        if (h.vdim == 3) launch_correct_t<float, 3>(cv, h, n_kin, cur, s);
+        else launch_correct_t<float, 2>(cv, h, n_kin, cur, s);
+    } else {
+        if (h.vdim == 3) launch_correct_t<double, 3>(cv, h, n_kin, cur, s);
+        else launch_correct_t<double, 2>(cv, h, n_kin, cur, s);
     }
     return hipGetLastError();
 }
