@@ -57,7 +57,7 @@ struct gsis_mesh_s {
     std::vector<double> face_normal, face_area, face_center, cell_volume, cell_center, cf_nsv, face_dist,
         patch_state;
     // geometry-only factors of the macroscopic kernels
-    std::vector<double> lsq;      // [nnz][2][3] least-squares coefficients: all faces / no wall faces
+    std::vector<double> lsq;      // [2][nnz][3] least-squares coefficients: all faces / no wall faces
     std::vector<double> cf_fs;    // [nnz] -S (owner) or +S: the face's sign and area in the cell balance
     std::vector<double> cell_sS;  // [n_cells][2] sum S, sum S / d over the cell's faces
     int refs = 0;
@@ -161,7 +161,7 @@ void build_macro_factors(gsis_mesh_s *m)
                 for (int a = 0; a < dim; ++a) {
                     double v = 0.0;
                     for (int c = 0; c < dim; ++c) v += Ainv[a * dim + c] * wgt[l] * dxs[l][c];
-                    m->lsq[6 * (size_t)e + 3 * var + a] = v;
+                    m->lsq[3 * ((size_t)var * m->nnz + e) + a] = v;
                 }
             }
         }

@@ -78,7 +78,7 @@ struct CaseView {
     const int32_t *cf_other;    // [nnz] neighbour cell, or -1 - patch
     const int32_t *cf_wall;     // [nnz] wall-sum index of the face in its cell, -1 otherwise
     const double *cf_nsv;       // [nnz][3] outward n S / V
-    const double *lsq;          // [nnz][2][3] least-squares coefficients (all faces / no wall faces)
+    const double *lsq;          // [2][nnz][3] least-squares coefficients (all faces / no wall faces)
     const double *cf_fs;        // [nnz] -S_f if the cell owns the face, +S_f otherwise
     const double *cell_sS;      // [n_cells][2] sum S_f, sum S_f / d_f
     const double *wall_den;     // [nnz] sum_{xi.n<0} w |xi.n| M(1, u_w, T_w) (wall faces)

@@ -41,63 +41,71 @@ __device__ __forceinline__ double bfield(const CaseView &C, int p, int v)
 // least-squares gradients (Sec. 3.4 Step 2) from the per-face coefficients
 // built with the mesh: grad_v = sum_e c_e (phi_e - phi_i); the density uses
 // the coefficients without wall faces.  Variables: 0..2 u, 3 T [, 4 rho, 5 |u|].
-template <int NV>
+// NF bounds the faces per cell: all loads of a cell are issued first.
+template <int NV, int NF>
 __global__ __launch_bounds__(256) void k_lsq(const CaseView *__restrict__ cvp, const double *__restrict__ W)
 {
     const CaseView &C = *cvp;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= C.n_cells) return;
-    const double *Wi = W + 5 * (size_t)i;
-    double fi[NV], g[NV][3];
+    const size_t nnz = (size_t)C.nnz;
+    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
+    int oth[NF];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        fi[v] = field(Wi, v);
-        g[v][0] = g[v][1] = g[v][2] = 0.0;
-    }
-    const int e0 = C.cf_ptr[i], e1 = C.cf_ptr[i + 1];
-    for (int e = e0; e < e1; ++e) {
-        const int oth = C.cf_other[e];
-        const double *ca = C.lsq + 6 * (size_t)e;
-        double fo[NV];
-        bool wall = false;
-        if (oth >= 0) {
-            const double *Wo = W + 5 * (size_t)oth;
+    for (int l = 0; l < NF; ++l) oth[l] = (l < nf) ? C.cf_other[e0 + l] : 0;
+    double c[NF][3], cr[NF][3], fo[NF][NV];
+    bool wall[NF];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) fo[v] = field(Wo, v);
-        } else {
-            const int p = -1 - oth;
-            wall = C.patch_kind[p] == GSIS_PATCH_WALL;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) fo[v] = (v == 4 && wall) ? 0.0 : bfield(C, p, v);
-        }
-        const double c0 = ca[0], c1 = ca[1], c2 = ca[2];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            if (v == 4) {
-                if (wall) continue;
-                const double d = fo[v] - fi[v];
-                g[v][0] += ca[3] * d;
-                g[v][1] += ca[4] * d;
-                g[v][2] += ca[5] * d;
+    for (int l = 0; l < NF; ++l) {
+        wall[l] = false;
+        for (int d = 0; d < 3; ++d) c[l][d] = cr[l][d] = 0.0;
+        for (int v = 0; v < NV; ++v) fo[l][v] = 0.0;
+        if (l < nf) {
+            const double *ca = C.lsq + 3 * (size_t)(e0 + l);
+            for (int d = 0; d < 3; ++d) c[l][d] = ca[d];
+            if (NV > 4)
+                for (int d = 0; d < 3; ++d) cr[l][d] = ca[3 * nnz + d];
+            if (oth[l] >= 0) {
+                const double *Wo = W + 5 * (size_t)oth[l];
+                for (int v = 0; v < NV; ++v) fo[l][v] = field(Wo, v);
             } else {
-                const double d = fo[v] - fi[v];
-                g[v][0] += c0 * d;
-                g[v][1] += c1 * d;
-                g[v][2] += c2 * d;
+                const int p = -1 - oth[l];
+                wall[l] = C.patch_kind[p] == GSIS_PATCH_WALL;
+                for (int v = 0; v < NV; ++v) fo[l][v] = (v == 4 && wall[l]) ? 0.0 : bfield(C, p, v);
             }
         }
     }
+    const double *Wi = W + 5 * (size_t)i;
     double *go = C.grad + (size_t)i * 18;
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-        for (int d = 0; d < 3; ++d) go[3 * v + d] = g[v][d];
+    for (int v = 0; v < NV; ++v) {
+        const double fi = field(Wi, v);
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+        for (int l = 0; l < NF; ++l) {
+            if (l >= nf || (v == 4 && wall[l])) continue;
+            const double d = fo[l][v] - fi;
+            const double *cc = (v == 4) ? cr[l] : c[l];
+            g0 += cc[0] * d;
+            g1 += cc[1] * d;
+            g2 += cc[2] * d;
+        }
+        go[3 * v] = g0;
+        go[3 * v + 1] = g1;
+        go[3 * v + 2] = g2;
+    }
 }
 
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s)
 {
     const dim3 g((h.n_cells + 255) / 256);
-    if (nvar == 6) hipLaunchKernelGGL(k_lsq<6>, g, dim3(256), 0, s, cv, W);
-    else hipLaunchKernelGGL(k_lsq<4>, g, dim3(256), 0, s, cv, W);
+    if (h.nfmax <= 4) {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, 4>), g, dim3(256), 0, s, cv, W);
+        else hipLaunchKernelGGL((k_lsq<4, 4>), g, dim3(256), 0, s, cv, W);
+    } else {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, MAXF>), g, dim3(256), 0, s, cv, W);
+        else hipLaunchKernelGGL((k_lsq<4, MAXF>), g, dim3(256), 0, s, cv, W);
+    }
     return hipGetLastError();
 }
 
@@ -217,7 +225,7 @@ __device__ void half_flux(const double *P, const double *n, double sgn, double *
     F[4] = rho * (m3 + (ut2 + T) * m1);
 }
 
-__global__ void k_face_flux(const CaseView *__restrict__ cvp, const double *__restrict__ W,
+__global__ __launch_bounds__(128) void k_face_flux(const CaseView *__restrict__ cvp, const double *__restrict__ W,
                             const double *__restrict__ hot)
 {
     const CaseView &C = *cvp;
@@ -404,20 +412,53 @@ __global__ void k_min_final(const CaseView *__restrict__ cvp, int nb)
 }
 
 // U_i += k_i (R_i + V_i src_i), k_i = cfl / D_i (local) or |cfl| min V/D / V_i
-// (global), halved while the new state is not positive; W = prim(U)
-__global__ void k_update(const CaseView *__restrict__ cvp, double *__restrict__ W, const double *__restrict__ src,
-                         double cfl)
+// (global), halved while the new state is not positive; W = prim(U).  NF
+// bounds the faces per cell: the face data of a cell is loaded first.
+template <int NF>
+__global__ __launch_bounds__(256) void k_update(const CaseView *__restrict__ cvp, double *__restrict__ W,
+                                                const double *__restrict__ src, double cfl)
 {
     const CaseView &C = *cvp;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= C.n_cells) return;
     double *Wi = W + 5 * (size_t)i;
-    double R[5];
-    cell_balance(C, i, R);
-    double V = C.cell_volume[i];
+    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
+    int fc[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) fc[l] = (l < nf) ? C.cf_face[e0 + l] : 0;
+    double fs[NF], F[NF][5], ns[NF][3];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fs[l] = 0.0;
+        for (int c = 0; c < 5; ++c) F[l][c] = 0.0;
+        for (int d = 0; d < 3; ++d) ns[l][d] = 0.0;
+        if (l < nf) {
+            fs[l] = C.cf_fs[e0 + l];
+            for (int c = 0; c < 5; ++c) F[l][c] = C.fflux[5 * (size_t)fc[l] + c];
+            for (int d = 0; d < 3; ++d) ns[l][d] = C.cf_nsv[3 * (size_t)(e0 + l) + d];
+        }
+    }
+    // per-cell flux balance R_i = -sum_f (+-F_f) S_f, fixed order over the faces
+    double R[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int l = 0; l < NF; ++l)
+        for (int c = 0; c < 5; ++c) R[c] += F[l][c] * fs[l];
+    const double V = C.cell_volume[i];
     if (src)
         for (int c = 0; c < 5; ++c) R[c] += src[5 * (size_t)i + c] * V;
-    double k = (cfl < 0) ? (-cfl * C.red[0]) / V : cfl / cell_D(C, i, Wi);
+    double k;
+    if (cfl < 0) {
+        k = (-cfl * C.red[0]) / V;
+    } else {
+        // D_i = sum_f S_f (|u.n| + a + 2 nu / d_f)
+        double un = 0.0;
+#pragma unroll
+        for (int l = 0; l < NF; ++l) un += fabs(Wi[1] * ns[l][0] + Wi[2] * ns[l][1] + Wi[3] * ns[l][2]);
+        const double a = sqrt(5.0 / 3.0 * Wi[4] / 2.0);
+        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wi[4], C.omega) / (sqrt(M_PI) * Wi[0]);
+        const double *sS = C.cell_sS + 2 * (size_t)i;
+        k = cfl / (V * un + a * sS[0] + 2.0 * nu * sS[1]);
+    }
     double *U = C.U + 5 * (size_t)i;
     // positivity safeguard: halve this cell's increment (at most ten times)
     // while the new density or temperature would not be positive
@@ -448,15 +489,18 @@ hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, 
                               int n_inner, double cfl, hipStream_t s)
 {
     const int gc = (h.n_cells + 127) / 128, gf = (h.n_faces + 127) / 128, gd = (h.n_cells + 255) / 256;
+    const int gu = (h.n_cells + 255) / 256;
     hipLaunchKernelGGL(k_cons, dim3(gc), dim3(128), 0, s, cv, W);
     for (int it = 0; it < n_inner; ++it) {
-        hipLaunchKernelGGL(k_lsq<4>, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv, W);
+        hipError_t e = launch_lsq(cv, h, W, 4, s);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_face_flux, dim3(gf), dim3(128), 0, s, cv, W, hot);
         if (cfl < 0) {
             hipLaunchKernelGGL(k_dloc, dim3(gd), dim3(256), 0, s, cv, W);
             hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, s, cv, gd);
         }
-        hipLaunchKernelGGL(k_update, dim3(gc), dim3(128), 0, s, cv, W, src, cfl);
+        if (h.nfmax <= 4) hipLaunchKernelGGL(k_update<4>, dim3(gu), dim3(256), 0, s, cv, W, src, cfl);
+        else hipLaunchKernelGGL(k_update<MAXF>, dim3(gu), dim3(256), 0, s, cv, W, src, cfl);
     }
     return hipGetLastError();
 }
