@@ -476,17 +476,24 @@ class SteadySolver:
         self.W[self.kin] = O.moments(self.f[self.slot[self.kin]])[:, :5]
 
     def ns_init(self, tol=1e-6, chunk=None, max_chunks=1000):
-        """Step 1: macroscopic (NSF) solve alone, HoT = 0, to eps < tol."""
+        """Step 1 (Sec. 3.4): every cell NS, the macroscopic (NSF) solve alone,
+        HoT = 0, to eps < tol; then the first flagging (Step 2), so that every
+        kinetic cell starts from the Grad-13 distribution of the NS field."""
         O = self.O
+        self.flags = np.zeros(self.n, np.uint8)
+        self.kin, self.slot, _ = regions_from_flags(self.flags)
         chunk = chunk or self.n_inner
         hot = np.zeros((self.n, 9))
-        for k in range(max_chunks):
+        k, eps = max_chunks, None
+        for j in range(max_chunks):
             Wn = O.macro(self.W, hot, chunk, self.cfl)
             eps = O.residual(Wn, self.W)
             self.W = Wn
             if eps.max() < tol:
-                return k + 1, eps
-        return max_chunks, eps
+                k = j + 1
+                break
+        self.update_regions()
+        return k, eps
 
     def update_regions(self):
         """Step 2/3: LSQ gradients, Kn_Gll flags, compaction, G13 init of new cells."""
