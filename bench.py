@@ -61,10 +61,7 @@ def log(*a):
 def workload(nv1d):
     """Mesh, velocity grid and the synthetic starting field (no kinetic cells)."""
     import gsis_inputs as gi
-    u_inf = MACH * np.sqrt(5.0 / 6.0)
-    mesh = gi.sphere_tet_3d(free=(1.0, (u_inf, 0.0, 0.0), 1.0))
-    grid = gi.velocity_grid(3, nv1d, 15.0, "stretched")
-    W = gi.hypersonic_field(mesh)
+    mesh, grid, W = gi.sphere_workload(nv1d, MACH)
     return mesh, grid, W, np.zeros(mesh["n_cells"], np.uint8)
 
 

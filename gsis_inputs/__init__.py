@@ -504,3 +504,41 @@ def gaussian_rows(grid, W, seed: int, amp: float = 0.05, dtype=np.float32):
             out[i, 0] = base * (1.0 + amp * g.uniform(-1, 1, len(xi)))
             out[i, 1] = 0.5 * w[4] * base * (1.0 + amp * g.uniform(-1, 1, len(xi)))
     return out
+
+
+def separable_row_factors(grid, W, cells, seed: int, amp: float = 0.05):
+    """Per-axis factors (3D grids) of random Gaussian-shaped rows, one set per
+    listed cell, drawn from a stream keyed by (seed, cell id) so that any
+    subset of cells can be regenerated alone.
+
+    Row of cell c = a_x[c] (x) a_y[c] (x) a_z[c] (outer product, x slowest),
+    a_d[j] = s exp(-(xi_{d,j} - u_d)^2 / T) (1 + amp U(-1, 1)),
+    s = (rho (pi T)^(-3/2))^(1/3); returned in FP32: ([n, nx], [n, ny], [n, nz]).
+    """
+    assert grid["vdim"] == 3
+    out = [np.empty((len(cells), len(grid["nodes"][d])), dtype=np.float32) for d in range(3)]
+    for i, c in enumerate(np.asarray(cells, dtype=np.int64)):
+        w = W[c]
+        g = np.random.Generator(np.random.PCG64([seed, int(c)]))
+        s = (w[0] * (np.pi * w[4]) ** -1.5) ** (1.0 / 3.0)
+        for d in range(3):
+            x = grid["nodes"][d]
+            f = s * np.exp(-(x - w[1 + d]) ** 2 / w[4]) * (1.0 + amp * g.uniform(-1, 1, len(x)))
+            out[d][i] = f.astype(np.float32)
+    return out
+
+
+def assemble_separable_rows(ax, ay, az):
+    """Rows [n, 1, nx ny nz] = (a_x a_y) a_z in FP32, in that association order."""
+    r = (ax[:, :, None, None] * ay[:, None, :, None]) * az[:, None, None, :]
+    return r.reshape(len(ax), 1, -1)
+
+
+def sphere_workload(nv1d: int = 32, mach: float = 5.0):
+    """Mach-5 sphere at the benchmark size: mesh (~192k tetrahedra, Morton
+    order), stretched nv1d^3 velocity grid on [-15, 15]^3 and the synthetic
+    starting field."""
+    u_inf = mach * np.sqrt(5.0 / 6.0)
+    mesh = sphere_tet_3d(free=(1.0, (u_inf, 0.0, 0.0), 1.0))
+    grid = velocity_grid(3, nv1d, 15.0, "stretched")
+    return mesh, grid, hypersonic_field(mesh, mach=mach)

@@ -1,0 +1,150 @@
+"""Parity at the benchmark size and in the launch configuration the benchmark
+times: Mach-5 sphere, 192,445 tetrahedra, 32^3 stretched velocities, FP32,
+capacity 0.7 n_cells (one whole-row tile per kinetic cell, plane kernel,
+4-face template).  About 45% of the cells are kinetic (87k rows, 11 GB).
+
+The oracle cannot sweep 2.8e9 points in a test, so one sweep is compared on
+48 sampled kinetic cells (random ones, wall cells, cells next to the NS
+region and to the far field), each recomputed from exactly the same FP32
+input rows; the GSIS correction is checked by a property that holds at any
+size (the conserved moments of the corrected VDF are the new W).
+"""
+import numpy as np
+import pytest
+
+import gsis_inputs as gi
+from _cases import f_error, moment_errors
+
+pytestmark = pytest.mark.gpu
+
+KN = 0.005
+CAP_FRACTION = 0.7     # the benchmark's capacity rule
+SEED_ROWS = 21
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2501_02245_amd as g
+    import torch
+    assert torch.cuda.is_available()
+    return g
+
+
+@pytest.fixture(scope="module")
+def big(g):
+    import torch
+    mesh, grid, W = gi.sphere_workload(32)
+    flags = gi.synthetic_region(mesh, 0.45, seed=11)
+    kin = np.nonzero(flags)[0]
+    print("sphere", mesh["n_cells"], "cells,", len(kin), "kinetic", flush=True)
+    ax, ay, az = gi.separable_row_factors(grid, W, kin, seed=SEED_ROWS)
+    case = g.Case(g.Mesh(mesh), grid, KN, dtype=g.F32, capacity=int(CAP_FRACTION * mesh["n_cells"]))
+    assert case.sweep_layout() == (1, 32768, 1)
+    # assemble the rows on the device with the same FP32 products, in the same
+    # association order, as gi.assemble_separable_rows
+    tx, ty, tz = (torch.from_numpy(a).cuda() for a in (ax, ay, az))
+    rows = ((tx[:, :, None, None] * ty[:, None, :, None]) * tz[:, None, None, :]).reshape(len(kin), 1, -1)
+    case.set_state(W, vdf=rows, flags=flags)
+    del rows, tx, ty, tz
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return {"mesh": mesh, "grid": grid, "W": W, "flags": flags, "kin": kin, "case": case}
+
+
+def _sample(mesh, flags, kin, seed=5):
+    """16 random kinetic cells, 16 with a wall face, 16 next to an NS cell or the far field."""
+    fc = mesh["face_cells"]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wall_p = {p for p, pt in enumerate(mesh["patches"]) if pt["kind"] == "wall"}
+    bnd = fc[:, 1] < 0
+    wall_cells = set(fc[bnd & np.isin(-1 - fc[:, 1], list(wall_p)), 0].tolist())
+    far_cells = set(fc[bnd & ~np.isin(-1 - fc[:, 1], list(wall_p)), 0].tolist())
+    inner = ~bnd
+    a, b = fc[inner, 0], fc[inner, 1]
+    edge = set(a[(flags[a] == 1) & (flags[b] == 0)].tolist()) | set(b[(flags[b] == 1) & (flags[a] == 0)].tolist())
+    kset = set(kin.tolist())
+    picks = set(rng.choice(kin, 16, replace=False).tolist())
+    for pool in (sorted(wall_cells & kset), sorted((edge | far_cells) & kset)):
+        pool = [c for c in pool if c not in picks]
+        picks |= set(rng.choice(pool, min(16, len(pool)), replace=False).tolist())
+    return np.array(sorted(picks), dtype=np.int64)
+
+
+def _neighbours(mesh, cells):
+    fc = mesh["face_cells"]
+    inner = fc[:, 1] >= 0
+    a, b = fc[inner, 0], fc[inner, 1]
+    m = np.zeros(mesh["n_cells"], bool)
+    m[cells] = True
+    return np.union1d(b[m[a]], a[m[b]])
+
+
+def test_fullsize_sweep_sampled(g, oracle_mod, big):
+    import torch
+    mesh, grid, W, flags, kin, case = (big[k] for k in ("mesh", "grid", "W", "flags", "kin", "case"))
+    sample = _sample(mesh, flags, kin)
+    pos = np.searchsorted(kin, sample)
+    print("sampled", len(sample), "cells", flush=True)
+    # rows the oracle needs: the sample, its kinetic neighbours, and the kinetic
+    # neighbours of its NS neighbours (their moments enter the ghosts' gradients)
+    nb = _neighbours(mesh, sample)
+    ns_nb = nb[flags[nb] == 0]
+    need = np.union1d(np.union1d(sample, nb[flags[nb] == 1]), _neighbours(mesh, ns_nb))
+    need = need[flags[need] == 1]
+    axs = gi.separable_row_factors(grid, W, need, seed=SEED_ROWS)
+    rows32 = gi.assemble_separable_rows(*axs)
+    # the device holds exactly these inputs
+    fg0 = case.get_vdf()
+    idx = torch.from_numpy(np.searchsorted(kin, need)).cuda()
+    assert np.array_equal(fg0[idx].cpu().numpy(), rows32)
+    del fg0
+    torch.cuda.empty_cache()
+
+    O = oracle_mod.Oracle(mesh, grid, KN)
+    rows = rows32.astype(np.float64)
+    Wo = W.copy()
+    Wo[need] = O.moments(rows)[:, :5]
+    ghost = O.ghost_params(Wo)
+    slot = -np.ones(mesh["n_cells"], np.int32)
+    slot[need] = np.arange(len(need), dtype=np.int32)
+    fo = O.sweep(rows, sample, slot, ghost)[slot[sample]]
+    mo = O.moments(fo)
+
+    case.sweep(1)
+    fg = case.get_vdf()
+    fs = fg[torch.from_numpy(pos).cuda()].cpu().numpy()
+    del fg
+    torch.cuda.empty_cache()
+    mg, kc = case.moments()
+    assert np.array_equal(kc.cpu().numpy(), kin)
+    ms = mg.cpu().numpy()[pos]
+    ef = f_error(fs, fo, O.w)
+    em = moment_errors(ms, mo, u_scale=1.0)
+    print("full size: f", ef, "moments", em, flush=True)
+    assert ef < 1e-5
+    for k, v in em.items():
+        assert v < 1e-5, (k, v)
+
+
+def test_fullsize_correction_property(g, big):
+    """f += f_eq(W_new) - f_eq(W_half) with fixed-up Maxwellians: the conserved
+    moments of the result are W_new on every kinetic cell (FP32 storage)."""
+    import torch
+    mesh, flags, kin, case = (big[k] for k in ("mesh", "flags", "kin", "case"))
+    Wh, _ = case.get_state()
+    Wh = Wh.cpu().numpy()
+    n = mesh["n_cells"]
+    ph = np.arange(n, dtype=np.float64)
+    Wn = Wh.copy()
+    Wn[:, 0] *= 1.0 + 0.01 * np.sin(ph)
+    Wn[:, 1:4] += 0.01 * np.cos(ph)[:, None]
+    Wn[:, 4] *= 1.0 + 0.01 * np.cos(0.7 * ph)
+    case.correct(Wn)
+    mg, kc = case.moments()
+    mg = mg.cpu().numpy()
+    Wk = Wn[kin]
+    err_rho = np.abs(mg[:, 0] / Wk[:, 0] - 1).max()
+    err_u = np.abs(mg[:, 1:4] - Wk[:, 1:4]).max()
+    err_T = np.abs(mg[:, 4] / Wk[:, 4] - 1).max()
+    print("correction property: rho", err_rho, "u", err_u, "T", err_T, flush=True)
+    assert err_rho < 1e-5 and err_u < 1e-5 and err_T < 1e-5
