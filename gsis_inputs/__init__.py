@@ -542,3 +542,64 @@ def sphere_workload(nv1d: int = 32, mach: float = 5.0):
     mesh = sphere_tet_3d(free=(1.0, (u_inf, 0.0, 0.0), 1.0))
     grid = velocity_grid(3, nv1d, 15.0, "stretched")
     return mesh, grid, hypersonic_field(mesh, mach=mach)
+
+
+def serving_requests(n: int, rate: float, seed: int = 7, kinds=("couette", "fourier", "cylinder"),
+                     cells_1d=(32, 512), nv_1d=(16, 32), cells_2d=(2000, 20000), nv_2d=(32, 64),
+                     Kn_range=(1e-3, 1.0), mach_range=(1.0, 8.0)):
+    """Seeded steady-solve requests with Poisson arrivals (`rate` per second).
+
+    Each request is a dict: arrival time, kind, mesh, velocity grid, Kn, Mach,
+    starting field, forced wall layers and kinetic capacity (fraction of cells).
+      couette : walls moving -+Ma a0/2 (a0 = sqrt(5/6)) at T = 1, uniform start;
+      fourier : stationary walls at T = 1 and 1 + 0.1 Ma, linear-T start;
+      cylinder: Mach-Ma flow past a unit cylinder, synthetic start, 2 wall layers.
+    The 1D boxes are solved fully kinetic (GSIS, global pseudo-time step); the
+    cylinder adaptively (aGSIS from the NS start).
+    Cells log-uniform in the given ranges; Kn log-uniform; Mach uniform; the
+    velocity range is max(5 or 15, u + 4 sqrt(T_stag)), T_stag = 1 + Ma^2/3.
+    """
+    g = rng_of(seed)
+    t = 0.0
+    out = []
+    a0 = math.sqrt(5.0 / 6.0)
+    for i in range(n):
+        t += g.exponential(1.0 / rate)
+        kind = kinds[int(g.integers(len(kinds)))]
+        Kn = float(10 ** g.uniform(math.log10(Kn_range[0]), math.log10(Kn_range[1])))
+        Ma = float(g.uniform(*mach_range))
+        T_stag = 1.0 + Ma * Ma / 3.0
+        if kind in ("couette", "fourier"):
+            nc = int(round(math.exp(g.uniform(math.log(cells_1d[0]), math.log(cells_1d[1])))))
+            nv = int(nv_1d[int(g.integers(len(nv_1d)))])
+            if kind == "couette":
+                U = 0.5 * Ma * a0
+                mesh = couette_1d(nc, U)
+                V = max(5.0, U + 4.0 * math.sqrt(T_stag))
+                W0 = uniform_W(nc)
+            else:
+                TR = 1.0 + 0.1 * Ma
+                mesh = fourier_1d(nc, 1.0, TR)
+                V = max(5.0, 4.0 * math.sqrt(TR) + 1.0)
+                W0 = uniform_W(nc)
+                W0[:, 4] = 1.0 + (TR - 1.0) * mesh["cell_center"][:, 0]
+            grid = velocity_grid(3, nv, V, "stretched")
+            # closed box, every cell kinetic: GSIS with one global (conservative) step
+            layers, cap, mode, cfl = 0, 1.0, "gsis", -0.5
+        else:
+            nc = math.exp(g.uniform(math.log(cells_2d[0]), math.log(cells_2d[1])))
+            nt = max(24, int(round(math.sqrt(nc / 0.8))))
+            nr = max(8, int(round(0.4 * nt)))
+            u = Ma * a0
+            mesh = cylinder_tri_2d(n_theta=nt, n_rings=nr, free=(1.0, (u, 0.0, 0.0), 1.0),
+                                   seed=int(g.integers(1 << 30)))
+            nv = int(nv_2d[int(g.integers(len(nv_2d)))])
+            V = max(15.0, u + 4.0 * math.sqrt(T_stag))
+            grid = velocity_grid(2, nv, V, "stretched")
+            W0 = hypersonic_field(mesh, mach=Ma)
+            W0[:, 3] = 0.0
+            # open domain: aGSIS from the NS start, local steps
+            layers, cap, mode, cfl = 2, 0.4, "agsis", 0.5
+        out.append({"rid": i, "arrival": t, "kind": kind, "mesh": mesh, "grid": grid, "Kn": Kn, "mach": Ma,
+                    "W0": W0, "layers": layers, "capacity": cap, "mode": mode, "cfl": cfl})
+    return out

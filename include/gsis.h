@@ -188,7 +188,10 @@ typedef struct {
 /* One outer iteration (Sec. 3.4) for each case: sweep, moments, high-order
  * terms, synthetic solve, GSIS correction, residual, and (aGSIS, on
  * schedule) region update.  eps_host [n_cases][3] (nullable) receives the
- * residuals and synchronises. */
+ * residuals and synchronises.  The cases of one call share batched launches.
+ * If a case's region update or state check fails, its residuals are NaN, the
+ * other cases still complete the step, and the call returns the first error
+ * (a failed region update leaves that case needing gsis_set_state). */
 gsis_status gsis_step(gsis_case const *cases, int32_t n_cases, const gsis_solve_params *p, double *eps_host,
                       void *stream);
 

@@ -153,6 +153,25 @@ class Mesh:
             self.handle = None
 
 
+def footprint(mesh: Mesh, grid, Kn, dtype=F32, capacity=None, omega=0.5, Pr=2.0 / 3.0):
+    """Device bytes a case of this mesh, grid and kinetic capacity binds (no allocation)."""
+    h = C.c_void_p()
+    _check(lib().gsis_create_case(mesh.handle, C.byref(_Gas(Kn, omega, Pr)), dtype, C.byref(h)))
+    try:
+        vdim = grid["vdim"]
+        n = (C.c_int32 * 3)(*[len(grid["nodes"][d]) if d < vdim else 1 for d in range(3)])
+        xs_ = [np.ascontiguousarray(grid["nodes"][d] if d < vdim else [0.0], dtype=np.float64) for d in range(3)]
+        ws_ = [np.ascontiguousarray(grid["weights"][d] if d < vdim else [1.0], dtype=np.float64) for d in range(3)]
+        xs = (C.c_void_p * 3)(*[x.ctypes.data for x in xs_])
+        ws = (C.c_void_p * 3)(*[x.ctypes.data for x in ws_])
+        _check(lib().gsis_set_velocity_grid(h, vdim, n, xs, ws))
+        nbytes = C.c_size_t()
+        _check(lib().gsis_case_footprint(h, int(capacity or mesh.n_cells), C.byref(nbytes)))
+        return nbytes.value
+    finally:
+        _check(lib().gsis_destroy_case(h))
+
+
 class Case:
     """One steady problem bound to a torch-allocated device workspace."""
 
@@ -279,8 +298,18 @@ def kinetic_sweep(cases, n_sweeps=1):
 
 
 def step(cases, params: SolveParams):
-    """One outer iteration for a batch of cases; returns eps [n_cases, 3]."""
+    """One outer iteration for a batch of cases; returns eps [n_cases, 3].
+
+    On failure the GsisError carries `eps`: NaN rows mark the cases that
+    failed; the others completed the step."""
     eps = (C.c_double * (3 * len(cases)))()
     arr = (C.c_void_p * len(cases))(*[c.handle for c in cases])
-    _check(lib().gsis_step(arr, len(cases), C.byref(params), eps, _stream()))
-    return np.array(eps[:]).reshape(len(cases), 3)
+    code = lib().gsis_step(arr, len(cases), C.byref(params), eps, _stream())
+    out = np.array(eps[:]).reshape(len(cases), 3)
+    if code != OK:
+        err = GsisError(code, lib().gsis_last_error().decode())
+        if not np.isnan(out).any():   # failed before the per-case endings: every case
+            out[:] = np.nan
+        err.eps = out
+        raise err
+    return out

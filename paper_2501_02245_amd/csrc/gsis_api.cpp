@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -785,14 +786,12 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
             b.cv[j] = c->cv;
             b.start[j + 1] = b.start[j] + c->n_kin * c->ntile;
             b.nfmax = std::max(b.nfmax, c->hv.nfmax);
+            if (c->vdim == 3) b.mdiv = std::gcd(b.mdiv, c->n[1] * c->n[2] / BLOCK);
         }
-        // buffers: every case of a batch sweeps cur -> cur ^ 1 with its own cur
-        // (the kernel takes one value; cases are grouped by cur below)
-        int cur0 = cases[i0]->cur;
-        for (int j = 1; j < m; ++j)
-            if (cases[i0 + j]->cur != cur0) return fail(GSIS_E_STATE, "batched cases are at different buffer parity");
+        // every case sweeps its own f^n buffer (cur) into the other one
+        for (int j = 0; j < m; ++j) b.cur[j] = cases[i0 + j]->cur;
         if (timed && i0 == 0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
-        HIPCHK(launch_sweep(b, cases[i0]->hv, cur0, b.start[m], s));
+        HIPCHK(launch_sweep(b, cases[i0]->hv, b.start[m], s));
         if (timed && i0 + MAX_BATCH >= n) HIPCHK(hipEventRecord(cases[0]->ev1, s));
     }
     for (int j = 0; j < n; ++j) {
@@ -919,24 +918,51 @@ extern "C" gsis_status gsis_update_regions(gsis_case c, double Kn_ref, int32_t l
 // ---------------------------------------------------------------------------
 namespace {
 
-gsis_status post_sweep(gsis_case c, const gsis_solve_params *p, hipStream_t s)
+// after the sweep, up to the synthetic solve: moments of f^{n+1/2}, W^{n+1/2},
+// high-order terms, the source of eq. macro, W^{n+1} <- W^n (GSIS/aGSIS);
+// W^{n+1} <- W^{n+1/2} (DVM)
+gsis_status pre_macro(gsis_case c, const gsis_solve_params *p, hipStream_t s)
 {
     CaseView &h = c->hv;
     HIPCHK(launch_reduce(c->cv, h, c->n_kin, 1, s));
     if (p->mode == GSIS_MODE_DVM) {
         HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
         HIPCHK(launch_W_from_mom(c->cv, h, c->n_kin, h.Wn, s));
-    } else {
-        HIPCHK(launch_whalf(c->cv, h, c->n_kin, s));
-        // high-order terms from f^{n+1/2} and gradients of W^{n+1/2}
-        HIPCHK(launch_lsq(c->cv, h, h.Wh, 4, s));
-        HIPCHK(launch_hot(c->cv, h, c->n_kin, s));
-        // source: kinetic moment balance at f^n minus synthetic residual at W^n
-        HIPCHK(launch_macro_residual(c->cv, h, h.W, h.hot, h.Rm, s));
-        HIPCHK(launch_src(c->cv, h, c->n_kin, s));
-        HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
-        HIPCHK(launch_macro_steps(c->cv, h, h.Wn, h.hot, h.src, p->n_macro_inner, p->cfl, s));
-        // GSIS correction f += f_eq(W^{n+1}) - f_eq(W^{n+1/2})
+        return GSIS_OK;
+    }
+    HIPCHK(launch_whalf(c->cv, h, c->n_kin, s));
+    // high-order terms from f^{n+1/2} and gradients of W^{n+1/2}
+    HIPCHK(launch_lsq(c->cv, h, h.Wh, 4, s));
+    HIPCHK(launch_hot(c->cv, h, c->n_kin, s));
+    // source: kinetic moment balance at f^n minus synthetic residual at W^n
+    HIPCHK(launch_macro_residual(c->cv, h, h.W, h.hot, h.Rm, s));
+    HIPCHK(launch_src(c->cv, h, c->n_kin, s));
+    HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
+    return GSIS_OK;
+}
+
+// the synthetic solves of a batch: one launch per kernel and pseudo-time step
+// for all cases (up to 16 per launch)
+gsis_status macro_solves(gsis_case const *cases, int n, const gsis_solve_params *p, hipStream_t s)
+{
+    if (p->mode == GSIS_MODE_DVM) return GSIS_OK;
+    for (int j0 = 0; j0 < n; j0 += MAX_BATCH) {
+        MBatch b{};
+        for (int j = j0; j < std::min(n, j0 + MAX_BATCH); ++j) {
+            CaseView &h = cases[j]->hv;
+            mbatch_add(b, cases[j]->cv, h, h.Wn, h.hot, h.src);
+        }
+        HIPCHK(launch_macro_steps_batch(b, p->n_macro_inner, p->cfl, s));
+    }
+    return GSIS_OK;
+}
+
+// after the synthetic solve: GSIS correction f += f_eq(W^{n+1}) - f_eq(W^{n+1/2}),
+// moments of f^{n+1}, the residual, W <- W^{n+1}
+gsis_status post_macro(gsis_case c, const gsis_solve_params *p, hipStream_t s)
+{
+    CaseView &h = c->hv;
+    if (p->mode != GSIS_MODE_DVM) {
         HIPCHK(launch_feqpar(c->cv, h, c->n_kin, s));
         HIPCHK(launch_correct(c->cv, h, c->n_kin, c->cur, s));
         HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
@@ -968,21 +994,34 @@ extern "C" gsis_status gsis_step(gsis_case const *cases, int32_t n, const gsis_s
         if ((st = prepare_sweep(cases[j], s))) return st;
     if ((st = batched_sweep(cases, n, s, true))) return st;
     for (int j = 0; j < n; ++j)
-        if ((st = post_sweep(cases[j], p, s))) return st;
+        if ((st = pre_macro(cases[j], p, s))) return st;
+    if ((st = macro_solves(cases, n, p, s))) return st;
+    for (int j = 0; j < n; ++j)
+        if ((st = post_macro(cases[j], p, s))) return st;
+    // per-case endings: a case whose region update or state check fails is
+    // reported with NaN residuals; the others complete the step
+    gsis_status first = GSIS_OK;
+    std::string first_msg;
     for (int j = 0; j < n; ++j) {
         gsis_case c = cases[j];
         c->iter++;
+        st = GSIS_OK;
         if (p->mode == GSIS_MODE_AGSIS && p->region_update_every > 0 && c->iter % p->region_update_every == 0)
-            if ((st = gsis_update_regions(c, p->Kn_ref, p->force_wall_layers, nullptr, stream))) return st;
-    }
-    if (eps_host) {
-        for (int j = 0; j < n; ++j) {
-            double e[3];
-            HIPCHK(hipMemcpyAsync(e, cases[j]->hv.eps, sizeof e, hipMemcpyDeviceToHost, s));
-            if ((st = sync_status(cases[j], s))) return st;
-            for (int k = 0; k < 3; ++k) eps_host[3 * j + k] = e[k];
+            st = gsis_update_regions(c, p->Kn_ref, p->force_wall_layers, nullptr, stream);
+        double e[3] = {NAN, NAN, NAN};
+        if (!st && eps_host) {
+            HIPCHK(hipMemcpyAsync(e, c->hv.eps, sizeof e, hipMemcpyDeviceToHost, s));
+            st = sync_status(c, s);
+            if (st) e[0] = e[1] = e[2] = NAN;
         }
+        if (st && !first) {
+            first = st;
+            first_msg = "case " + std::to_string(j) + " of the batch: " + g_err;
+        }
+        if (eps_host)
+            for (int k = 0; k < 3; ++k) eps_host[3 * j + k] = st ? NAN : e[k];
     }
+    if (first) return fail(first, "%s", first_msg.c_str());
     return GSIS_OK;
 }
 

@@ -138,6 +138,25 @@ struct Batch {
     int32_t start[MAX_BATCH + 1];   // prefix of work items (blocks) per case
     int32_t n;
     int32_t nfmax;                  // largest faces-per-cell over the cases
+    int32_t mdiv;                   // plane kernel, 3D: gcd over the cases of the y-values per lane
+                                    // and plane, M = n_y n_z / 256 (load rounds must divide it)
+    int32_t cur[MAX_BATCH];         // per case: the buffer holding f^n (the sweep writes the other)
+};
+
+// Cases of one batched macroscopic launch: each case owns whole blocks
+// (cell kernels: MBLOCK cells per block, face kernels: MBLOCK_F faces), so the
+// case of a block is block-uniform.
+constexpr int MBLOCK = 256;
+constexpr int MBLOCK_F = 128;
+struct MBatch {
+    const CaseView *cv[MAX_BATCH];
+    double *W[MAX_BATCH];            // state advanced by the pseudo-time steps
+    const double *hot[MAX_BATCH];    // [n_cells][9] high-order terms
+    const double *src[MAX_BATCH];    // [n_cells][5] sources per unit volume, or null
+    int32_t bc[MAX_BATCH + 1];       // prefix of cell blocks
+    int32_t bf[MAX_BATCH + 1];       // prefix of face blocks
+    int32_t n;
+    int32_t nfmax;
 };
 
 // --- launch wrappers (gsis_kinetic.hip) ---------------------------------------
@@ -148,9 +167,9 @@ hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_it
 hipError_t launch_reduce(const CaseView *cv, const CaseView &h, int n_kin, int with_res, hipStream_t s);
 hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
-hipError_t launch_sweep(const Batch &b, const CaseView &h0, int cur, int total_items, hipStream_t s);
+hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
 // (gsis_sweep.hip) tensor grids whose fastest axis divides the block
-hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int cur, int total_items, hipStream_t s);
+hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_patch_rows(const CaseView *cv, const CaseView &h, hipStream_t s);
@@ -166,6 +185,10 @@ hipError_t launch_whalf(const CaseView *cv, const CaseView &h, int n_kin, hipStr
 hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const double *W, const double *hot,
                                  double *Rout, hipStream_t s);
 hipError_t launch_src(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+// n_inner pseudo-time steps for every case of a batch (cfl > 0 local steps,
+// cfl < 0 one global step per case)
+hipError_t launch_macro_steps_batch(const MBatch &b, int n_inner, double cfl, hipStream_t s);
+void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src);
 hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, const double *hot,
                               const double *src, int n_inner, double cfl, hipStream_t s);
 hipError_t launch_eps(const CaseView *cv, const CaseView &h, const double *Wnew, const double *Wold,

@@ -519,7 +519,7 @@ struct FaceS {
 };
 
 template <typename T, int VD>
-__global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
+__global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ FaceS<T> fs[MAXF];
@@ -531,6 +531,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
     int ci = 0;
     while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
     const CaseView &C = *B.cv[ci];
+    const int cur = B.cur[ci];
     const int item = b - B.start[ci];
     const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
     const int vt = item / n_kin;
@@ -750,22 +751,22 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B, int cur)
 }
 
 template <typename T, int VD>
-static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
+static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
     int NA3 = h0.n[0] + h0.n[1] + (VD == 3 ? h0.n[2] : 0);
     size_t lds = sizeof(double) * (size_t)NA3 * 2 + sizeof(T) * (size_t)NA3 * (3 + 1 + MAXF);
-    hipLaunchKernelGGL((k_sweep<T, VD>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+    hipLaunchKernelGGL((k_sweep<T, VD>), dim3(total), dim3(BLOCK), lds, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
+hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
-    if (h0.fast) return launch_sweep_fast(b, h0, cur, total, s);
+    if (h0.fast) return launch_sweep_fast(b, h0, total, s);
     // all cases of a batch share dtype and vdim; LDS is sized for the largest axes
     if (h0.dtype == GSIS_F32)
-        return h0.vdim == 3 ? launch_sweep_t<float, 3>(b, h0, cur, total, s) : launch_sweep_t<float, 2>(b, h0, cur, total, s);
-    return h0.vdim == 3 ? launch_sweep_t<double, 3>(b, h0, cur, total, s) : launch_sweep_t<double, 2>(b, h0, cur, total, s);
+        return h0.vdim == 3 ? launch_sweep_t<float, 3>(b, h0, total, s) : launch_sweep_t<float, 2>(b, h0, total, s);
+    return h0.vdim == 3 ? launch_sweep_t<double, 3>(b, h0, total, s) : launch_sweep_t<double, 2>(b, h0, total, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -38,15 +38,39 @@ __device__ __forceinline__ double bfield(const CaseView &C, int p, int v)
     return sqrt(ps[1] * ps[1] + ps[2] * ps[2] + ps[3] * ps[3]);
 }
 
+// case of a block in a batched launch (block-uniform)
+__device__ __forceinline__ int mb_case(const int32_t *start, int n)
+{
+    int j = 0;
+    while (j + 1 < n && (int)blockIdx.x >= start[j + 1]) ++j;
+    return j;
+}
+
+void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src)
+{
+    const int j = b.n;
+    if (j == 0) b.bc[0] = b.bf[0] = 0, b.nfmax = 0;
+    b.cv[j] = cv;
+    b.W[j] = W;
+    b.hot[j] = hot;
+    b.src[j] = src;
+    b.bc[j + 1] = b.bc[j] + (h.n_cells + MBLOCK - 1) / MBLOCK;
+    b.bf[j + 1] = b.bf[j] + (h.n_faces + MBLOCK_F - 1) / MBLOCK_F;
+    b.nfmax = (h.nfmax > b.nfmax) ? h.nfmax : b.nfmax;
+    b.n = j + 1;
+}
+
 // least-squares gradients (Sec. 3.4 Step 2) from the per-face coefficients
 // built with the mesh: grad_v = sum_e c_e (phi_e - phi_i); the density uses
 // the coefficients without wall faces.  Variables: 0..2 u, 3 T [, 4 rho, 5 |u|].
 // NF bounds the faces per cell: all loads of a cell are issued first.
 template <int NV, int NF>
-__global__ __launch_bounds__(256) void k_lsq(const CaseView *__restrict__ cvp, const double *__restrict__ W)
+__global__ __launch_bounds__(MBLOCK) void k_lsq(MBatch B)
 {
-    const CaseView &C = *cvp;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = mb_case(B.bc, B.n);
+    const CaseView &C = *B.cv[j];
+    const double *__restrict__ W = B.W[j];
+    const int i = ((int)blockIdx.x - B.bc[j]) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     const size_t nnz = (size_t)C.nnz;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
@@ -96,16 +120,23 @@ __global__ __launch_bounds__(256) void k_lsq(const CaseView *__restrict__ cvp, c
     }
 }
 
+static void launch_lsq_b(const MBatch &b, int nvar, hipStream_t s)
+{
+    const dim3 g(b.bc[b.n]);
+    if (b.nfmax <= 4) {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, 4>), g, dim3(MBLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_lsq<4, 4>), g, dim3(MBLOCK), 0, s, b);
+    } else {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, MAXF>), g, dim3(MBLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_lsq<4, MAXF>), g, dim3(MBLOCK), 0, s, b);
+    }
+}
+
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s)
 {
-    const dim3 g((h.n_cells + 255) / 256);
-    if (h.nfmax <= 4) {
-        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, 4>), g, dim3(256), 0, s, cv, W);
-        else hipLaunchKernelGGL((k_lsq<4, 4>), g, dim3(256), 0, s, cv, W);
-    } else {
-        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, MAXF>), g, dim3(256), 0, s, cv, W);
-        else hipLaunchKernelGGL((k_lsq<4, MAXF>), g, dim3(256), 0, s, cv, W);
-    }
+    MBatch b{};
+    mbatch_add(b, cv, h, const_cast<double *>(W), nullptr, nullptr);
+    launch_lsq_b(b, nvar, s);
     return hipGetLastError();
 }
 
@@ -225,11 +256,13 @@ __device__ void half_flux(const double *P, const double *n, double sgn, double *
     F[4] = rho * (m3 + (ut2 + T) * m1);
 }
 
-__global__ __launch_bounds__(128) void k_face_flux(const CaseView *__restrict__ cvp, const double *__restrict__ W,
-                            const double *__restrict__ hot)
+__global__ __launch_bounds__(MBLOCK_F) void k_face_flux(MBatch B)
 {
-    const CaseView &C = *cvp;
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = mb_case(B.bf, B.n);
+    const CaseView &C = *B.cv[j];
+    const double *__restrict__ W = B.W[j];
+    const double *__restrict__ hot = B.hot[j];
+    const int f = ((int)blockIdx.x - B.bf[j]) * MBLOCK_F + (int)threadIdx.x;
     if (f >= C.n_faces) return;
     int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
     const double *n = C.face_normal + 3 * (size_t)f;
@@ -327,7 +360,9 @@ hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const do
 {
     hipError_t e = launch_lsq(cv, h, W, 4, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_face_flux, dim3((h.n_faces + 127) / 128), dim3(128), 0, s, cv, W, hot);
+    MBatch b{};
+    mbatch_add(b, cv, h, const_cast<double *>(W), hot, nullptr);
+    if (b.bf[1] > 0) hipLaunchKernelGGL(k_face_flux, dim3(b.bf[1]), dim3(MBLOCK_F), 0, s, b);
     hipLaunchKernelGGL(k_residual_cells, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, Rout);
     return hipGetLastError();
 }
@@ -366,10 +401,12 @@ __device__ double cell_D(const CaseView &C, int i, const double *Wi)
     return C.cell_volume[i] * un + a * sS[0] + 2.0 * nu * sS[1];
 }
 
-__global__ void k_cons(const CaseView *__restrict__ cvp, const double *__restrict__ W)
+__global__ __launch_bounds__(MBLOCK) void k_cons(MBatch B)
 {
-    const CaseView &C = *cvp;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = mb_case(B.bc, B.n);
+    const CaseView &C = *B.cv[j];
+    const double *__restrict__ W = B.W[j];
+    const int i = ((int)blockIdx.x - B.bc[j]) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     const double *P = W + 5 * (size_t)i;
     double *U = C.U + 5 * (size_t)i;
@@ -380,32 +417,39 @@ __global__ void k_cons(const CaseView *__restrict__ cvp, const double *__restric
 }
 
 // dloc_i = V_i / D_i, then a two-level min reduction into red[0]
-__global__ void k_dloc(const CaseView *__restrict__ cvp, const double *__restrict__ W)
+// dloc[block] = min over the block's cells of V_i / D_i (blocks of each case)
+__global__ __launch_bounds__(MBLOCK) void k_dloc(MBatch B)
 {
-    const CaseView &C = *cvp;
-    __shared__ double sm[256];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = mb_case(B.bc, B.n);
+    const CaseView &C = *B.cv[j];
+    const double *__restrict__ W = B.W[j];
+    const int blk = (int)blockIdx.x - B.bc[j];
+    const int i = blk * MBLOCK + (int)threadIdx.x;
+    __shared__ double sm[MBLOCK];
     double v = INFINITY;
     if (i < C.n_cells) v = C.cell_volume[i] / cell_D(C, i, W + 5 * (size_t)i);
     sm[threadIdx.x] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+    for (int st = MBLOCK / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + st]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) C.dloc[blockIdx.x] = sm[0];
+    if (threadIdx.x == 0) C.dloc[blk] = sm[0];
 }
 
-__global__ void k_min_final(const CaseView *__restrict__ cvp, int nb)
+// one block per case: red[0] = the case's global pseudo-time step factor
+__global__ __launch_bounds__(256) void k_min_final(MBatch B)
 {
-    const CaseView &C = *cvp;
+    const int j = blockIdx.x;
+    const CaseView &C = *B.cv[j];
+    const int nb = B.bc[j + 1] - B.bc[j];
     __shared__ double sm[256];
     double v = INFINITY;
     for (int i = threadIdx.x; i < nb; i += 256) v = fmin(v, C.dloc[i]);
     sm[threadIdx.x] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + st]);
         __syncthreads();
     }
     if (threadIdx.x == 0) C.red[0] = sm[0];
@@ -415,11 +459,13 @@ __global__ void k_min_final(const CaseView *__restrict__ cvp, int nb)
 // (global), halved while the new state is not positive; W = prim(U).  NF
 // bounds the faces per cell: the face data of a cell is loaded first.
 template <int NF>
-__global__ __launch_bounds__(256) void k_update(const CaseView *__restrict__ cvp, double *__restrict__ W,
-                                                const double *__restrict__ src, double cfl)
+__global__ __launch_bounds__(MBLOCK) void k_update(MBatch B, double cfl)
 {
-    const CaseView &C = *cvp;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = mb_case(B.bc, B.n);
+    const CaseView &C = *B.cv[j];
+    double *__restrict__ W = B.W[j];
+    const double *__restrict__ src = B.src[j];
+    const int i = ((int)blockIdx.x - B.bc[j]) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     double *Wi = W + 5 * (size_t)i;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
@@ -485,24 +531,31 @@ __global__ __launch_bounds__(256) void k_update(const CaseView *__restrict__ cvp
     if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4])) atomicOr(C.status, 1);
 }
 
+hipError_t launch_macro_steps_batch(const MBatch &b, int n_inner, double cfl, hipStream_t s)
+{
+    if (b.n <= 0) return hipSuccess;
+    const dim3 gc(b.bc[b.n]), gf(b.bf[b.n]);
+    hipLaunchKernelGGL(k_cons, gc, dim3(MBLOCK), 0, s, b);
+    for (int it = 0; it < n_inner; ++it) {
+        launch_lsq_b(b, 4, s);
+        if (b.bf[b.n] > 0) hipLaunchKernelGGL(k_face_flux, gf, dim3(MBLOCK_F), 0, s, b);
+        if (cfl < 0) {
+            // one global (conservative) step per case
+            hipLaunchKernelGGL(k_dloc, gc, dim3(MBLOCK), 0, s, b);
+            hipLaunchKernelGGL(k_min_final, dim3(b.n), dim3(256), 0, s, b);
+        }
+        if (b.nfmax <= 4) hipLaunchKernelGGL(k_update<4>, gc, dim3(MBLOCK), 0, s, b, cfl);
+        else hipLaunchKernelGGL(k_update<MAXF>, gc, dim3(MBLOCK), 0, s, b, cfl);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src,
                               int n_inner, double cfl, hipStream_t s)
 {
-    const int gc = (h.n_cells + 127) / 128, gf = (h.n_faces + 127) / 128, gd = (h.n_cells + 255) / 256;
-    const int gu = (h.n_cells + 255) / 256;
-    hipLaunchKernelGGL(k_cons, dim3(gc), dim3(128), 0, s, cv, W);
-    for (int it = 0; it < n_inner; ++it) {
-        hipError_t e = launch_lsq(cv, h, W, 4, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_face_flux, dim3(gf), dim3(128), 0, s, cv, W, hot);
-        if (cfl < 0) {
-            hipLaunchKernelGGL(k_dloc, dim3(gd), dim3(256), 0, s, cv, W);
-            hipLaunchKernelGGL(k_min_final, dim3(1), dim3(256), 0, s, cv, gd);
-        }
-        if (h.nfmax <= 4) hipLaunchKernelGGL(k_update<4>, dim3(gu), dim3(256), 0, s, cv, W, src, cfl);
-        else hipLaunchKernelGGL(k_update<MAXF>, dim3(gu), dim3(256), 0, s, cv, W, src, cfl);
-    }
-    return hipGetLastError();
+    MBatch b{};
+    mbatch_add(b, cv, h, W, hot, src);
+    return launch_macro_steps_batch(b, n_inner, cfl, s);
 }
 
 // ---------------------------------------------------------------------------

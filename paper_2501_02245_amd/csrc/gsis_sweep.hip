@@ -162,7 +162,7 @@ __device__ __forceinline__ void finish_partials(const PlaneSums<T> &S, const T (
 }  // namespace
 
 template <typename T, int VD, int NF, int U>
-__global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B, int cur)
+__global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[(BLOCK / 64) * NSUM];
@@ -172,6 +172,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B, int cur)
     int ci = 0;
     while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
     const CaseView &C = *B.cv[ci];
+    const int cur = B.cur[ci];
     const int item = b - B.start[ci];
     const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
     const int vt = item / n_kin;
@@ -609,47 +610,45 @@ size_t sweep_fast_lds(const CaseView &h, size_t es)
 }
 
 template <typename T, int VD, int U>
-void launch_u(const Batch &b, size_t lds, int cur, int total, hipStream_t s)
+void launch_u(const Batch &b, size_t lds, int total, hipStream_t s)
 {
     if (b.nfmax <= 4)
-        hipLaunchKernelGGL((k_sweep_fast<T, VD, 4, U>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+        hipLaunchKernelGGL((k_sweep_fast<T, VD, 4, U>), dim3(total), dim3(BLOCK), lds, s, b);
     else
-        hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF, U>), dim3(total), dim3(BLOCK), lds, s, b, cur);
+        hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF, U>), dim3(total), dim3(BLOCK), lds, s, b);
 }
 
-// points per load round: 3D, the largest of 4, 2, 1 that divides the y-values
-// per lane and plane, M = n_y n_z / 256; reduced 2D, 4 lines (guarded);
-// at most 2 for FP64 or 8-face meshes (register budget)
-int rounds_u(const CaseView &h, size_t es, int nfmax)
+// points per load round: 3D, the largest of 4, 2, 1 that divides M, the
+// y-values per lane and plane (M = n_y n_z / 256; for a batch, the gcd over
+// its cases); reduced 2D, 4 lines (guarded); at most 2 for FP64 or 8-face
+// meshes (register budget)
+int rounds_u(int vdim, int mdiv, size_t es, int nfmax)
 {
     int U = 4;
-    if (h.vdim == 3) {
-        const int M = h.n[1] * h.n[2] / BLOCK;
-        U = (M % 4 == 0) ? 4 : ((M % 2 == 0) ? 2 : 1);
-    }
+    if (vdim == 3) U = (mdiv % 4 == 0) ? 4 : ((mdiv % 2 == 0) ? 2 : 1);
     if (es == 8 || nfmax > 4) U = (U > 2) ? 2 : U;
     return U;
 }
 
 template <typename T, int VD>
-void launch_nf(const Batch &b, const CaseView &h0, size_t lds, int cur, int total, hipStream_t s)
+void launch_nf(const Batch &b, const CaseView &h0, size_t lds, int total, hipStream_t s)
 {
-    const int U = rounds_u(h0, sizeof(T), b.nfmax);
-    if (U == 4) launch_u<T, VD, 4>(b, lds, cur, total, s);
-    else if (U == 2) launch_u<T, VD, 2>(b, lds, cur, total, s);
-    else launch_u<T, VD, 1>(b, lds, cur, total, s);
+    const int U = rounds_u(h0.vdim, b.mdiv, sizeof(T), b.nfmax);
+    if (U == 4) launch_u<T, VD, 4>(b, lds, total, s);
+    else if (U == 2) launch_u<T, VD, 2>(b, lds, total, s);
+    else launch_u<T, VD, 1>(b, lds, total, s);
 }
 
-hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int cur, int total, hipStream_t s)
+hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
     if (h0.dtype == GSIS_F32) {
         size_t lds = sweep_fast_lds(h0, sizeof(float));
-        if (h0.vdim == 3) launch_nf<float, 3>(b, h0, lds, cur, total, s);
-        else launch_nf<float, 2>(b, h0, lds, cur, total, s);
+        if (h0.vdim == 3) launch_nf<float, 3>(b, h0, lds, total, s);
+        else launch_nf<float, 2>(b, h0, lds, total, s);
     } else {
         size_t lds = sweep_fast_lds(h0, sizeof(double));
-        if (h0.vdim == 3) launch_nf<double, 3>(b, h0, lds, cur, total, s);
-        else launch_nf<double, 2>(b, h0, lds, cur, total, s);
+        if (h0.vdim == 3) launch_nf<double, 3>(b, h0, lds, total, s);
+        else launch_nf<double, 2>(b, h0, lds, total, s);
     }
     return hipGetLastError();
 }
@@ -667,7 +666,7 @@ void launch_correct_u(const CaseView *cv, const CaseView &h, int n_kin, int cur,
 template <typename T, int VD>
 void launch_correct_t(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
 {
-    const int U = rounds_u(h, sizeof(T), h.nfmax);
+    const int U = rounds_u(h.vdim, h.n[1] * h.n[2] / BLOCK, sizeof(T), h.nfmax);
     if (U == 4) launch_correct_u<T, VD, 4>(cv, h, n_kin, cur, s);
     else if (U == 2) launch_correct_u<T, VD, 2>(cv, h, n_kin, cur, s);
     else launch_correct_u<T, VD, 1>(cv, h, n_kin, cur, s);

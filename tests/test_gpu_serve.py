@@ -1,0 +1,71 @@
+"""Served (continuously batched) solves: each result is the same alone and in
+the mix, and the served FP32 results match the FP64 oracle's converged state."""
+import numpy as np
+import pytest
+
+import gsis_inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2501_02245_amd as g
+    import torch
+    assert torch.cuda.is_available()
+    return g
+
+
+def _requests(n, seed, **kw):
+    import paper_2501_02245_amd.serve as sv
+    return [sv.Request.from_spec(d) for d in gi.serving_requests(n, 50.0, seed=seed, **kw)]
+
+
+def test_served_equals_alone(g):
+    """Six requests arriving together (1D boxes of different sizes and grids,
+    one small cylinder) share batched launches; every one ends bitwise where it
+    ends alone, after the same number of iterations."""
+    import paper_2501_02245_amd.serve as sv
+    reqs = _requests(5, 3, kinds=("couette", "fourier"), cells_1d=(24, 64), nv_1d=(16, 32),
+                     Kn_range=(0.01, 0.5), mach_range=(1.0, 3.0))
+    reqs += _requests(1, 4, kinds=("cylinder",), cells_2d=(1200, 1400), nv_2d=(32,), Kn_range=(0.01, 0.05),
+                      mach_range=(2.0, 3.0))
+    reqs[-1].rid = len(reqs) - 1
+    for r in reqs:
+        r.arrival = 0.0
+    srv = sv.Server(budget_bytes=8 << 30, max_iter=40)
+    res = srv.run(reqs, log=lambda m: print(m, flush=True))
+    for out in res:
+        print("served", out.rid, out.kind, out.status, out.iterations, flush=True)
+    assert len(res) == len(reqs)
+    assert srv.peak_active == len(reqs)
+    for r, out in zip(reqs, res):
+        it, eps, nk, W, status = sv.solve_alone(r, g.F32, max_iter=40)
+        print(r.rid, r.kind, status, out.status, it, out.iterations, flush=True)
+        assert status == out.status and it == out.iterations
+        assert np.array_equal(W, out.W)
+
+
+def test_served_matches_oracle(g, oracle_mod):
+    """Three 1D requests served in FP32 against the FP64 oracle run with the
+    same steps and stopping rule (GSIS, global pseudo-time step, tol 1e-6 on
+    the fields the request converges on): converged fields within 1e-4."""
+    import paper_2501_02245_amd.serve as sv
+    reqs = _requests(3, 12, kinds=("couette", "fourier"), cells_1d=(24, 40), nv_1d=(16,), Kn_range=(0.03, 0.12),
+                     mach_range=(1.0, 2.0))
+    srv = sv.Server(budget_bytes=4 << 30, max_iter=300)
+    res = srv.run(reqs)
+    for r, out in zip(reqs, res):
+        assert out.status == "ok", out.status
+        O = oracle_mod.Oracle(r.mesh, r.grid, r.Kn)
+        S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=r.cfl)
+        S.set_state(r.W0)
+        for _ in range(300):
+            e = S.step()
+            if np.max(e[list(r.fields)]) < 1e-6:
+                break
+        err = {"rho": np.abs(out.W[:, 0] - S.W[:, 0]).max() / np.abs(S.W[:, 0]).max(),
+               "u": np.abs(out.W[:, 1:4] - S.W[:, 1:4]).max() / max(np.abs(S.W[:, 1:4]).max(), 0.1),
+               "T": np.abs(out.W[:, 4] - S.W[:, 4]).max() / np.abs(S.W[:, 4]).max()}
+        print(r.rid, r.kind, out.iterations, S.it, err, flush=True)
+        assert max(err.values()) < 1e-4
