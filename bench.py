@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--no-fp64-sweep", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
+    ap.add_argument("--serve-requests", type=int, default=12, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving leg (1/s)")
+    ap.add_argument("--serve-max-iter", type=int, default=200)
+    ap.add_argument("--serve-tol", type=float, default=1e-5)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain streaming kernel over MIB MiB (scale for HBM counters)")
     return ap.parse_args()
@@ -118,6 +122,41 @@ def cpu_baseline(mesh, grid, W, flags, seconds):
             "kind": "oracle",
             "sample": "%d x (FP64 oracle sweep + moments of %d kinetic cells of this workload, "
                       "%d velocities, kinetic neighbours' rows present) in %.1f s" % (reps, len(chunk), nv, el)}
+
+
+def serving(g, n, rate, max_iter, tol, seed=7):
+    """Continuous-batching FP32 server on a seeded request stream, against the
+    same requests solved one after another by the plain per-case FP64 path."""
+    import gsis_inputs as gi
+    import paper_2501_02245_amd.serve as sv
+    reqs = [sv.Request.from_spec(d) for d in gi.serving_requests(n, rate, seed=seed)]
+    budget = 64 << 30
+    srv = sv.Server(budget, dtype=g.F32, max_iter=max_iter, tol=tol)
+    t = time.perf_counter()
+    res = srv.run(reqs, log=log)
+    wall = time.perf_counter() - t
+    out = sv.summarize(res, wall)
+    out.update({"wall_s": wall, "peak_active": srv.peak_active, "peak_bytes": srv.peak_bytes,
+                "requeued": srv.requeued, "dtype": "f32", "tol": srv.tol, "max_iter": max_iter,
+                "mix": "seed %d: %d requests, Poisson rate %g/s, 1D Couette/Fourier 32-512 cells 16^3/32^3, "
+                       "2D cylinder 2k-20k cells 32^2/64^2, Kn log-uniform [1e-3, 1], Mach [1, 8], Kn_ref 0.01"
+                       % (seed, n, rate)})
+    # the plain per-case FP64 path on the same requests, one at a time
+    t = time.perf_counter()
+    base, diff = [], []
+    for r, rr in zip(reqs, res):
+        it, eps, nk, W, status = sv.solve_alone(r, g.F64, max_iter=max_iter, tol=tol)
+        base.append(status)
+        if status == "ok" and rr.status == "ok":
+            scale = np.maximum(np.abs(W).max(axis=0), 1e-3)
+            diff.append(float((np.abs(W - rr.W).max(axis=0) / scale).max()))
+        log("fp64 alone: request %d %s after %d iterations" % (r.rid, status, it))
+    wall64 = time.perf_counter() - t
+    n64 = sum(1 for b in base if b == "ok")
+    out["fp64_per_case"] = {"solved": n64, "wall_s": wall64, "solves_per_s": n64 / wall64}
+    out["speedup_vs_fp64_per_case"] = out["solves_per_s"] / (n64 / wall64) if n64 else None
+    out["max_field_diff_vs_fp64"] = max(diff) if diff else None
+    return out
 
 
 def fp64_sweep(g, torch, M, grid, W, flags, steps=3):
@@ -240,6 +279,10 @@ def main():
         "fp64_sweep": fp64,
         "setup_s": setup_s,
     }
+    if a.serve_requests > 0 and not a.sweep_only:
+        t1 = time.time()
+        out["serving"] = serving(g, a.serve_requests, a.serve_rate, a.serve_max_iter, a.serve_tol)
+        log("serving leg %.1f s" % (time.time() - t1))
     if not a.no_cpu_baseline:
         t1 = time.time()
         out["cpu_baseline"] = cpu_baseline(mesh, grid, W, flags, a.cpu_seconds)

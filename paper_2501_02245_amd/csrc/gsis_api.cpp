@@ -384,7 +384,7 @@ namespace {
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, cell_volume, cell_center, patch_kind, patch_state, xv, wv, flags, slot, kin, nkin, newc, nnew, scan,
-        status, prow, grow, gslot, gcell, ngh, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
+        status, prow, grow, gslot, gcell, ngh, axtab, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
 
@@ -430,6 +430,13 @@ TileChoice choose_tile(const gsis_case_s *c, int64_t cap)
         t.ntile = (c->nv + t.tile - 1) / t.tile;
     }
     return t;
+}
+
+// elements per slot of the plane sweep's axis tables (4 NA + 5 nx, padded to 64)
+int axtab_len(const gsis_case_s *c)
+{
+    const int NA = c->n[0] + c->n[1] + (c->vdim == 3 ? c->n[2] : 0);
+    return (4 * NA + 5 * c->n[0] + 63) / 64 * 64;
 }
 
 // rows reserved for the Grad-13 ghosts of NS cells next to the kinetic region
@@ -489,6 +496,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.gslot = S.take(4 * nc);
     L.gcell = S.take(4 * gcap);
     L.ngh = S.take(16);
+    L.axtab = S.take(es * (size_t)cap * axtab_len(c));
     L.f0 = S.take(es * (size_t)cap * (*row));
     L.f1 = S.take(es * (size_t)cap * (*row));
     L.param = S.take(sizeof(ParamRec) * (size_t)cap);
@@ -638,6 +646,12 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(int32_t *, n_ghost_dev, ngh);
     h.gcap = (int32_t)ghost_capacity(m->n_cells, cap);
     h.nfmax = m->max_faces;
+    P(void *, axtab, axtab);
+    h.tabp = axtab_len(c);
+    {
+        const char *env = std::getenv("GSIS_SWEEP_ORDER");
+        h.order = env ? std::atoi(env) : 0;
+    }
     P(ParamRec *, param, param);
     P(FeqRec *, feq, feq);
     P(double *, partial, partial);
@@ -766,6 +780,7 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
 {
     CaseView &h = c->hv;
     HIPCHK(launch_param(c->cv, h, c->n_kin, s));
+    if (h.fast) HIPCHK(launch_axtab(c->cv, h, c->n_kin, s));
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
         HIPCHK(launch_ghost(c->cv, h, h.W, s));
@@ -790,6 +805,7 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         }
         // every case sweeps its own f^n buffer (cur) into the other one
         for (int j = 0; j < m; ++j) b.cur[j] = cases[i0 + j]->cur;
+        b.order = cases[i0]->hv.order;
         if (timed && i0 == 0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
         HIPCHK(launch_sweep(b, cases[i0]->hv, b.start[m], s));
         if (timed && i0 + MAX_BATCH >= n) HIPCHK(hipEventRecord(cases[0]->ev1, s));

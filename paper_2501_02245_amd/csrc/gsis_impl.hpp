@@ -110,6 +110,11 @@ struct CaseView {
     int32_t *ghost_cell;        // [gcap] ascending cell id
     int32_t *n_ghost_dev;
     int32_t gcap, nfmax;
+    // per-slot axis tables of the relaxation target for the plane sweep, in the
+    // case dtype: offsets c, Gaussian factors E, fix-up parts P, Shakhov parts K
+    // (each [NA]), then the x axis' low parts (5 nx); tabp elements per slot
+    void *axtab;
+    int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major
     // kinetic state
     void *f[2];                 // VDF double buffer [capacity][row]
     ParamRec *param;            // [capacity]
@@ -141,6 +146,7 @@ struct Batch {
     int32_t mdiv;                   // plane kernel, 3D: gcd over the cases of the y-values per lane
                                     // and plane, M = n_y n_z / 256 (load rounds must divide it)
     int32_t cur[MAX_BATCH];         // per case: the buffer holding f^n (the sweep writes the other)
+    int32_t order;                  // 0: blocks tile-major, 1: cell-major (all tiles of a cell together)
 };
 
 // Cases of one batched macroscopic launch: each case owns whole blocks
@@ -170,6 +176,7 @@ hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipSt
 hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
 // (gsis_sweep.hip) tensor grids whose fastest axis divides the block
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
+hipError_t launch_axtab(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_patch_rows(const CaseView *cv, const CaseView &h, hipStream_t s);

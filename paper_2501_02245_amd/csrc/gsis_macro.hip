@@ -46,6 +46,33 @@ __device__ __forceinline__ int mb_case(const int32_t *start, int n)
     return j;
 }
 
+// a single case: the same kernels without the batch lookup (all pointers are
+// direct kernel arguments)
+struct MOne {
+    const CaseView *cv;
+    double *W;
+    const double *hot;
+    const double *src;
+};
+
+struct MLoc {
+    const CaseView *cv;
+    double *W;
+    const double *hot;
+    const double *src;
+    int base;   // first block of the case
+};
+
+__device__ __forceinline__ MLoc mb_loc(const MBatch &B, bool faces)
+{
+    const int j = mb_case(faces ? B.bf : B.bc, B.n);
+    return {B.cv[j], B.W[j], B.hot[j], B.src[j], faces ? B.bf[j] : B.bc[j]};
+}
+
+__device__ __forceinline__ MLoc mb_loc(const MOne &B, bool) { return {B.cv, B.W, B.hot, B.src, 0}; }
+
+static MOne mone_of(const MBatch &b) { return {b.cv[0], b.W[0], b.hot[0], b.src[0]}; }
+
 void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src)
 {
     const int j = b.n;
@@ -64,13 +91,13 @@ void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, con
 // built with the mesh: grad_v = sum_e c_e (phi_e - phi_i); the density uses
 // the coefficients without wall faces.  Variables: 0..2 u, 3 T [, 4 rho, 5 |u|].
 // NF bounds the faces per cell: all loads of a cell are issued first.
-template <int NV, int NF>
-__global__ __launch_bounds__(MBLOCK) void k_lsq(MBatch B)
+template <int NV, int NF, class BT>
+__global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
 {
-    const int j = mb_case(B.bc, B.n);
-    const CaseView &C = *B.cv[j];
-    const double *__restrict__ W = B.W[j];
-    const int i = ((int)blockIdx.x - B.bc[j]) * MBLOCK + (int)threadIdx.x;
+    const MLoc ML = mb_loc(B, false);
+    const CaseView &C = *ML.cv;
+    const double *__restrict__ W = ML.W;
+    const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     const size_t nnz = (size_t)C.nnz;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
@@ -120,16 +147,23 @@ __global__ __launch_bounds__(MBLOCK) void k_lsq(MBatch B)
     }
 }
 
+template <class BT>
+static void launch_lsq_t(const BT &b, dim3 g, int nfmax, int nvar, hipStream_t s)
+{
+    if (nfmax <= 4) {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, 4, BT>), g, dim3(MBLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_lsq<4, 4, BT>), g, dim3(MBLOCK), 0, s, b);
+    } else {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, MAXF, BT>), g, dim3(MBLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_lsq<4, MAXF, BT>), g, dim3(MBLOCK), 0, s, b);
+    }
+}
+
 static void launch_lsq_b(const MBatch &b, int nvar, hipStream_t s)
 {
     const dim3 g(b.bc[b.n]);
-    if (b.nfmax <= 4) {
-        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, 4>), g, dim3(MBLOCK), 0, s, b);
-        else hipLaunchKernelGGL((k_lsq<4, 4>), g, dim3(MBLOCK), 0, s, b);
-    } else {
-        if (nvar == 6) hipLaunchKernelGGL((k_lsq<6, MAXF>), g, dim3(MBLOCK), 0, s, b);
-        else hipLaunchKernelGGL((k_lsq<4, MAXF>), g, dim3(MBLOCK), 0, s, b);
-    }
+    if (b.n == 1) launch_lsq_t(mone_of(b), g, b.nfmax, nvar, s);
+    else launch_lsq_t(b, g, b.nfmax, nvar, s);
 }
 
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s)
@@ -256,13 +290,14 @@ __device__ void half_flux(const double *P, const double *n, double sgn, double *
     F[4] = rho * (m3 + (ut2 + T) * m1);
 }
 
-__global__ __launch_bounds__(MBLOCK_F) void k_face_flux(MBatch B)
+template <class BT>
+__global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
 {
-    const int j = mb_case(B.bf, B.n);
-    const CaseView &C = *B.cv[j];
-    const double *__restrict__ W = B.W[j];
-    const double *__restrict__ hot = B.hot[j];
-    const int f = ((int)blockIdx.x - B.bf[j]) * MBLOCK_F + (int)threadIdx.x;
+    const MLoc ML = mb_loc(B, true);
+    const CaseView &C = *ML.cv;
+    const double *__restrict__ W = ML.W;
+    const double *__restrict__ hot = ML.hot;
+    const int f = ((int)blockIdx.x - ML.base) * MBLOCK_F + (int)threadIdx.x;
     if (f >= C.n_faces) return;
     int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
     const double *n = C.face_normal + 3 * (size_t)f;
@@ -362,7 +397,7 @@ hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const do
     if (e != hipSuccess) return e;
     MBatch b{};
     mbatch_add(b, cv, h, const_cast<double *>(W), hot, nullptr);
-    if (b.bf[1] > 0) hipLaunchKernelGGL(k_face_flux, dim3(b.bf[1]), dim3(MBLOCK_F), 0, s, b);
+    if (b.bf[1] > 0) hipLaunchKernelGGL(k_face_flux<MOne>, dim3(b.bf[1]), dim3(MBLOCK_F), 0, s, mone_of(b));
     hipLaunchKernelGGL(k_residual_cells, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, Rout);
     return hipGetLastError();
 }
@@ -401,12 +436,13 @@ __device__ double cell_D(const CaseView &C, int i, const double *Wi)
     return C.cell_volume[i] * un + a * sS[0] + 2.0 * nu * sS[1];
 }
 
-__global__ __launch_bounds__(MBLOCK) void k_cons(MBatch B)
+template <class BT>
+__global__ __launch_bounds__(MBLOCK) void k_cons(BT B)
 {
-    const int j = mb_case(B.bc, B.n);
-    const CaseView &C = *B.cv[j];
-    const double *__restrict__ W = B.W[j];
-    const int i = ((int)blockIdx.x - B.bc[j]) * MBLOCK + (int)threadIdx.x;
+    const MLoc ML = mb_loc(B, false);
+    const CaseView &C = *ML.cv;
+    const double *__restrict__ W = ML.W;
+    const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     const double *P = W + 5 * (size_t)i;
     double *U = C.U + 5 * (size_t)i;
@@ -418,12 +454,13 @@ __global__ __launch_bounds__(MBLOCK) void k_cons(MBatch B)
 
 // dloc_i = V_i / D_i, then a two-level min reduction into red[0]
 // dloc[block] = min over the block's cells of V_i / D_i (blocks of each case)
-__global__ __launch_bounds__(MBLOCK) void k_dloc(MBatch B)
+template <class BT>
+__global__ __launch_bounds__(MBLOCK) void k_dloc(BT B)
 {
-    const int j = mb_case(B.bc, B.n);
-    const CaseView &C = *B.cv[j];
-    const double *__restrict__ W = B.W[j];
-    const int blk = (int)blockIdx.x - B.bc[j];
+    const MLoc ML = mb_loc(B, false);
+    const CaseView &C = *ML.cv;
+    const double *__restrict__ W = ML.W;
+    const int blk = (int)blockIdx.x - ML.base;
     const int i = blk * MBLOCK + (int)threadIdx.x;
     __shared__ double sm[MBLOCK];
     double v = INFINITY;
@@ -458,14 +495,14 @@ __global__ __launch_bounds__(256) void k_min_final(MBatch B)
 // U_i += k_i (R_i + V_i src_i), k_i = cfl / D_i (local) or |cfl| min V/D / V_i
 // (global), halved while the new state is not positive; W = prim(U).  NF
 // bounds the faces per cell: the face data of a cell is loaded first.
-template <int NF>
-__global__ __launch_bounds__(MBLOCK) void k_update(MBatch B, double cfl)
+template <int NF, class BT>
+__global__ __launch_bounds__(MBLOCK) void k_update(BT B, double cfl)
 {
-    const int j = mb_case(B.bc, B.n);
-    const CaseView &C = *B.cv[j];
-    double *__restrict__ W = B.W[j];
-    const double *__restrict__ src = B.src[j];
-    const int i = ((int)blockIdx.x - B.bc[j]) * MBLOCK + (int)threadIdx.x;
+    const MLoc ML = mb_loc(B, false);
+    const CaseView &C = *ML.cv;
+    double *__restrict__ W = ML.W;
+    const double *__restrict__ src = ML.src;
+    const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     double *Wi = W + 5 * (size_t)i;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
@@ -531,22 +568,29 @@ __global__ __launch_bounds__(MBLOCK) void k_update(MBatch B, double cfl)
     if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4])) atomicOr(C.status, 1);
 }
 
+template <class BT>
+static void macro_steps_t(const BT &bt, const MBatch &b, int n_inner, double cfl, hipStream_t s)
+{
+    const dim3 gc(b.bc[b.n]), gf(b.bf[b.n]);
+    hipLaunchKernelGGL(k_cons<BT>, gc, dim3(MBLOCK), 0, s, bt);
+    for (int it = 0; it < n_inner; ++it) {
+        launch_lsq_t(bt, gc, b.nfmax, 4, s);
+        if (b.bf[b.n] > 0) hipLaunchKernelGGL(k_face_flux<BT>, gf, dim3(MBLOCK_F), 0, s, bt);
+        if (cfl < 0) {
+            // one global (conservative) step per case
+            hipLaunchKernelGGL(k_dloc<BT>, gc, dim3(MBLOCK), 0, s, bt);
+            hipLaunchKernelGGL(k_min_final, dim3(b.n), dim3(256), 0, s, b);
+        }
+        if (b.nfmax <= 4) hipLaunchKernelGGL((k_update<4, BT>), gc, dim3(MBLOCK), 0, s, bt, cfl);
+        else hipLaunchKernelGGL((k_update<MAXF, BT>), gc, dim3(MBLOCK), 0, s, bt, cfl);
+    }
+}
+
 hipError_t launch_macro_steps_batch(const MBatch &b, int n_inner, double cfl, hipStream_t s)
 {
     if (b.n <= 0) return hipSuccess;
-    const dim3 gc(b.bc[b.n]), gf(b.bf[b.n]);
-    hipLaunchKernelGGL(k_cons, gc, dim3(MBLOCK), 0, s, b);
-    for (int it = 0; it < n_inner; ++it) {
-        launch_lsq_b(b, 4, s);
-        if (b.bf[b.n] > 0) hipLaunchKernelGGL(k_face_flux, gf, dim3(MBLOCK_F), 0, s, b);
-        if (cfl < 0) {
-            // one global (conservative) step per case
-            hipLaunchKernelGGL(k_dloc, gc, dim3(MBLOCK), 0, s, b);
-            hipLaunchKernelGGL(k_min_final, dim3(b.n), dim3(256), 0, s, b);
-        }
-        if (b.nfmax <= 4) hipLaunchKernelGGL(k_update<4>, gc, dim3(MBLOCK), 0, s, b, cfl);
-        else hipLaunchKernelGGL(k_update<MAXF>, gc, dim3(MBLOCK), 0, s, b, cfl);
-    }
+    if (b.n == 1) macro_steps_t(mone_of(b), b, n_inner, cfl, s);
+    else macro_steps_t(b, b, n_inner, cfl, s);
     return hipGetLastError();
 }
 

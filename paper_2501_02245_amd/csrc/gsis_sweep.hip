@@ -43,27 +43,21 @@ __device__ __forceinline__ int xcd_remap2(int b, int nb)
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
-template <int NS>
-__device__ __forceinline__ void block_reduce2(double (&v)[NS], double *out, double *lds)
+// byte offset of the epilogue's LDS area after `tab` table elements of T
+template <typename T>
+__host__ __device__ constexpr size_t red_offset(size_t tab)
 {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-        double x = v[i];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        v[i] = x;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) lds[wave * NS + i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x < NS) {
-        double s = 0.0;
-        for (int w = 0; w < BLOCK / 64; ++w) s += lds[w * NS + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
+    return (sizeof(T) * tab + 15) / 16 * 16;
+}
+
+// bytes of the epilogue's LDS area: the raw lane sums, then (reused) the
+// per-node partial sums
+template <typename T, int NF>
+constexpr size_t red_bytes()
+{
+    return (sizeof(T) * (17 + NF) * BLOCK > sizeof(double) * NSUM * BLOCK / 2)
+               ? sizeof(T) * (17 + NF) * BLOCK
+               : sizeof(double) * NSUM * BLOCK / 2;
 }
 
 // Per-lane moment sums of the plane kernels.  3D: with c_z the lane constant
@@ -99,64 +93,98 @@ struct PlaneSums {
     }
 };
 
-// Multiply in the lane constant (offset cl, weight wl) in FP64, map to the
-// NSUM layout of the partial sums, add the outgoing wall sums of the faces
-// and reduce over the block into out[NSUM].
+// Block epilogue.  Lanes that share the fastest-axis node (lane constant)
+// first pool their raw sums: every lane writes its 17 + NF FP32 sums to LDS,
+// then one thread per node adds its lanes' values in FP64, multiplies in the
+// node's offset cl and weight wl, maps to the NSUM layout of the partial sums
+// (with the outgoing wall sums of the faces), and the nodes are added in a
+// fixed order.  red must hold (17 + NF) * BLOCK values of T and
+// NSUM * n_node doubles (it is reused between the two stages).
 template <typename T, int VD, int NF>
 __device__ __forceinline__ void finish_partials(const PlaneSums<T> &S, const T (&Wf)[NF], const int (&fwall)[NF],
-                                                double cl, double wl, double *out, double *red)
+                                                int n_node, const double *xl, const double *wlv, double ul,
+                                                double *out, T *red)
 {
+    constexpr int K = 17 + NF;
+    const int tid = threadIdx.x;
+    {
+        const T raw[17] = {S.A0, S.A1, S.A2, S.A3, S.B1, S.B2, S.B3, S.C1, S.C2, S.D2,
+                           S.Q0, S.Q1, S.R0, S.R1, S.R2, S.R3, S.Rp};
+#pragma unroll
+        for (int k = 0; k < 17; ++k) red[k * BLOCK + tid] = raw[k];
+#pragma unroll
+        for (int l = 0; l < NF; ++l) red[(17 + l) * BLOCK + tid] = Wf[l];
+    }
+    __syncthreads();
     double v[NSUM];
+    if (tid < n_node) {
+        double r[K];
 #pragma unroll
-    for (int i = 0; i < NSUM; ++i) v[i] = 0.0;
-    const double cl2 = cl * cl;
-    if (VD == 3) {
-        const double a0 = S.A0, a1 = S.A1, a2 = S.A2, a3 = S.A3, b1 = S.B1, b2 = S.B2, b3 = S.B3, c1 = S.C1,
-                     c2 = S.C2, d2 = S.D2;
-        v[0] = wl * a0;
-        v[1] = wl * a1;
-        v[2] = wl * b1;
-        v[3] = wl * cl * a0;
-        v[4] = wl * a2;
-        v[5] = wl * b2;
-        v[6] = wl * cl2 * a0;
-        v[7] = wl * c1;
-        v[8] = wl * cl * a1;
-        v[9] = wl * cl * b1;
-        v[10] = wl * (a3 + d2 + cl2 * a1);
-        v[11] = wl * (c2 + b3 + cl2 * b1);
-        v[12] = wl * cl * (a2 + b2 + cl2 * a0);
-        v[S_RES] = wl * (double)S.R0;
-        v[S_RES + 1] = wl * (double)S.R1;
-        v[S_RES + 2] = wl * (double)S.R2;
-        v[S_RES + 3] = wl * cl * (double)S.R0;
-        v[S_RES + 4] = wl * ((double)S.R3 + cl2 * (double)S.R0);
-    } else {
-        const double a0 = S.A0, a1 = S.A1, a2 = S.A2, a3 = S.A3;
-        v[0] = wl * a0;
-        v[1] = wl * a1;
-        v[2] = wl * cl * a0;
-        v[3] = wl * a2;
-        v[4] = wl * cl2 * a0;
-        v[5] = wl * cl * a1;
-        v[6] = wl * (a3 + cl2 * a1);
-        v[7] = wl * cl * (a2 + cl2 * a0);
-        v[8] = wl * (double)S.Q0;
-        v[9] = wl * (double)S.Q1;
-        v[10] = wl * cl * (double)S.Q0;
-        v[S_RES] = wl * (double)S.R0;
-        v[S_RES + 1] = wl * (double)S.R1;
-        v[S_RES + 2] = wl * cl * (double)S.R0;
-        v[S_RES + 4] = wl * ((double)S.R3 + cl2 * (double)S.R0 + (double)S.Rp);
+        for (int k = 0; k < K; ++k) {
+            double acc = 0.0;
+            for (int ln = tid; ln < BLOCK; ln += n_node) acc += (double)red[k * BLOCK + ln];
+            r[k] = acc;
+        }
+        const double cl = xl[tid] - ul, wl = wlv[tid], cl2 = cl * cl;
+#pragma unroll
+        for (int i = 0; i < NSUM; ++i) v[i] = 0.0;
+        const double a0 = r[0], a1 = r[1], a2 = r[2], a3 = r[3];
+        if (VD == 3) {
+            const double b1 = r[4], b2 = r[5], b3 = r[6], c1 = r[7], c2 = r[8], d2 = r[9];
+            v[0] = wl * a0;
+            v[1] = wl * a1;
+            v[2] = wl * b1;
+            v[3] = wl * cl * a0;
+            v[4] = wl * a2;
+            v[5] = wl * b2;
+            v[6] = wl * cl2 * a0;
+            v[7] = wl * c1;
+            v[8] = wl * cl * a1;
+            v[9] = wl * cl * b1;
+            v[10] = wl * (a3 + d2 + cl2 * a1);
+            v[11] = wl * (c2 + b3 + cl2 * b1);
+            v[12] = wl * cl * (a2 + b2 + cl2 * a0);
+            v[S_RES] = wl * r[12];
+            v[S_RES + 1] = wl * r[13];
+            v[S_RES + 2] = wl * r[14];
+            v[S_RES + 3] = wl * cl * r[12];
+            v[S_RES + 4] = wl * (r[15] + cl2 * r[12]);
+        } else {
+            v[0] = wl * a0;
+            v[1] = wl * a1;
+            v[2] = wl * cl * a0;
+            v[3] = wl * a2;
+            v[4] = wl * cl2 * a0;
+            v[5] = wl * cl * a1;
+            v[6] = wl * (a3 + cl2 * a1);
+            v[7] = wl * cl * (a2 + cl2 * a0);
+            v[8] = wl * r[10];
+            v[9] = wl * r[11];
+            v[10] = wl * cl * r[10];
+            v[S_RES] = wl * r[12];
+            v[S_RES + 1] = wl * r[13];
+            v[S_RES + 2] = wl * cl * r[12];
+            v[S_RES + 4] = wl * (r[15] + cl2 * r[12] + r[16]);
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < MAXW; ++q2) {
+            double sw = 0.0;
+#pragma unroll
+            for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? r[17 + l] : 0.0;
+            v[S_WALL + q2] = wl * sw;
+        }
     }
+    __syncthreads();
+    double *vd = (double *)red;
+    if (tid < n_node)
 #pragma unroll
-    for (int q2 = 0; q2 < MAXW; ++q2) {
-        double sw = 0.0;
-#pragma unroll
-        for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? (double)Wf[l] : 0.0;
-        v[S_WALL + q2] = wl * sw;
+        for (int i = 0; i < NSUM; ++i) vd[i * n_node + tid] = v[i];
+    __syncthreads();
+    if (tid < NSUM) {
+        double acc = 0.0;
+        for (int z = 0; z < n_node; ++z) acc += vd[tid * n_node + z];
+        out[tid] = acc;
     }
-    block_reduce2<NSUM>(v, out, red);
 }
 
 }  // namespace
@@ -165,7 +193,6 @@ template <typename T, int VD, int NF, int U>
 __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[(BLOCK / 64) * NSUM];
 
     // ---- locate the work item -------------------------------------------
     const int b = xcd_remap2(blockIdx.x, gridDim.x);
@@ -175,8 +202,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
     const int cur = B.cur[ci];
     const int item = b - B.start[ci];
     const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
-    const int vt = item / n_kin;
-    const int t = item - vt * n_kin;
+    int vt, t;
+    if (B.order) {   // cell-major: the tiles of one cell are consecutive
+        t = item / C.ntile;
+        vt = item - t * C.ntile;
+    } else {         // tile-major
+        vt = item / n_kin;
+        t = item - vt * n_kin;
+    }
     const int cell = C.kin_cell[t];
     const int slot = C.slot_of_cell[cell];
     const ParamRec &P = C.param[slot];
@@ -195,6 +228,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
     T *rK = rP + NA;             // Shakhov part kq_d c
     T *rw = rK + NA;             // weight
     T *rlo = rw + NA;            // x axis: low part of c, c^2 and its low part, c^3 and its low part
+    const size_t red_off = red_offset<T>((size_t)5 * NA + 5 * nx);
 
     // ---- wave-uniform face data: row, scale, (n S/V), u.n S/V ----------------
     const int e0 = C.cf_ptr[cell];
@@ -231,29 +265,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
             }
         }
     }
-    // own-target records (FP64, rounded once)
+    // own-target records: the slot's axis tables (built once per sweep) and weights
     {
-        const double it = P.it;
-        const double fq = (VD == 3) ? P.fx[4] : P.fx[3];
+        gcptr<T> tb = (gcptr<T>)C.axtab + (size_t)slot * C.tabp;
+        for (int j = threadIdx.x; j < 4 * NA; j += BLOCK) rc[j] = tb[j];      // rc, rE, rP, rK
+        for (int j = threadIdx.x; j < 5 * nx; j += BLOCK) rlo[j] = tb[4 * NA + j];
         for (int j = threadIdx.x; j < NA; j += BLOCK) {
             const int d = (j < nx) ? 0 : ((j < nx + ny) ? 1 : 2);
             const int jj = j - ((d == 0) ? 0 : ((d == 1) ? nx : nx + ny));
-            const double x = C.xv[d * MAXA + jj];
-            const double c = x - P.u[d];
-            const double pl = (d == 0) ? P.fx[0] + P.fx[1] * c + fq * c * c : P.fx[1 + d] * c + fq * c * c;
-            rc[j] = (T)c;
-            rE[j] = (T)exp(-c * c * it);
-            rP[j] = (T)pl;
-            rK[j] = (T)(P.kq[d] * c);
             rw[j] = (T)C.wv[d * MAXA + jj];
-            if (d == 0) {
-                const double c2 = c * c, c3 = c2 * c;
-                rlo[jj] = (T)(c - (double)(T)c);
-                rlo[nx + jj] = (T)c2;
-                rlo[2 * nx + jj] = (T)(c2 - (double)(T)c2);
-                rlo[3 * nx + jj] = (T)c3;
-                rlo[4 * nx + jj] = (T)(c3 - (double)(T)c3);
-            }
         }
     }
     __syncthreads();
@@ -418,8 +438,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
 
     // ---- per-lane constants in FP64, standard partial-sum layout ----------
     const int dl = (VD == 3) ? 2 : 1;
-    finish_partials<T, VD, NF>(S, Wf, fwall, C.xv[dl * MAXA + ilc] - P.u[dl], C.wv[dl * MAXA + ilc],
-                               C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+    finish_partials<T, VD, NF>(S, Wf, fwall, (VD == 3) ? nz : ny, C.xv + dl * MAXA, C.wv + dl * MAXA, P.u[dl],
+                               C.partial + ((size_t)slot * C.ntile + vt) * NSUM, (T *)(smem_raw + red_off));
 }
 
 // ---------------------------------------------------------------------------
@@ -433,7 +453,6 @@ template <typename T, int VD, int NF, int U>
 __global__ __launch_bounds__(BLOCK) void k_correct_fast(const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[(BLOCK / 64) * NSUM];
     const CaseView &C = *cvp;
     const int b = xcd_remap2(blockIdx.x, gridDim.x);
     const int vt = b / n_kin, t = b - vt * n_kin;
@@ -451,6 +470,7 @@ __global__ __launch_bounds__(BLOCK) void k_correct_fast(const CaseView *__restri
     T *rw = rc + NA;
     T *Ea = rw + NA, *Pa = Ea + NA, *Eb = Pa + NA, *Pb = Eb + NA;
     T *rlo = Pb + NA;        // x axis: low part of c, c^2 and its low part, c^3 and its low part
+    const size_t red_off = red_offset<T>((size_t)6 * NA + 5 * nx);
 
     // wall faces only (outgoing sums for the next wall density)
     const int e0 = C.cf_ptr[cell];
@@ -518,42 +538,65 @@ __global__ __launch_bounds__(BLOCK) void k_correct_fast(const CaseView *__restri
         const int q = BLOCK / nz;
         const int M = ny / q;
         const int yq = threadIdx.x / nz;
-        for (int ix = ix0; ix < ix1; ++ix) {
-            const T cx = rc[ix], wx = rw[ix];
-            const T Exa = Ea[ix] * EaL, Pxa = Pa[ix] + PaL, Exb = Eb[ix] * EbL, Pxb = Pb[ix] + PbL;
-            T Ax[NF];
+        // two x-planes per pass: the loads of both planes' rounds are in flight together
+        for (int ix = ix0; ix < ix1; ix += 2) {
+            const int npl = (ix + 1 < ix1) ? 2 : 1;
+            T cx[2], wx[2], Exa[2], Pxa[2], Exb[2], Pxb[2], Ax[2][NF], Tp[2][4];
 #pragma unroll
-            for (int l = 0; l < NF; ++l) Ax[l] = fnx[l] * cx + AL[l];
-            T T0 = 0, T1 = 0, T2 = 0, T3 = 0;
+            for (int p = 0; p < 2; ++p) {
+                const int jx = (p < npl) ? ix + p : ix;
+                cx[p] = rc[jx];
+                wx[p] = rw[jx];
+                Exa[p] = Ea[jx] * EaL;
+                Pxa[p] = Pa[jx] + PaL;
+                Exb[p] = Eb[jx] * EbL;
+                Pxb[p] = Pb[jx] + PbL;
+#pragma unroll
+                for (int l = 0; l < NF; ++l) Ax[p][l] = fnx[l] * cx[p] + AL[l];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Tp[p][c] = (T)0;
+            }
+            const int kstep = q * nz, pstep = ny * nz;
             int iy = yq;
             int k = (ix * ny + iy) * nz + ilc;
-            const int kstep = q * nz;
             for (int m = 0; m < M; m += U, iy += U * q, k += U * kstep) {
-                T o[U];
+                T o[2][U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) o[u] = fr[k + u * kstep];
+                for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int jy = nx + iy + u * q;
-                    const T cy = rc[jy];
-                    const T fv = o[u] + (Exa * Ea[jy] * (Pxa + Pa[jy]) - Exb * Eb[jy] * (Pxb + Pb[jy]));
-                    fr[k + u * kstep] = fv;
-                    const T h = wx * rw[jy] * fv;
-                    T0 += h;
-                    const T hy = h * cy;
-                    T1 += hy;
-                    const T hy2 = hy * cy;
-                    T2 += hy2;
-                    T3 += hy2 * cy;
-                    if (nw > 0) {
+                    for (int u = 0; u < U; ++u) o[p][u] = (p < npl) ? fr[k + p * pstep + u * kstep] : (T)0;
 #pragma unroll
-                        for (int l = 0; l < NF; ++l)
-                            if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[l], (T)0);
+                for (int p = 0; p < 2; ++p) {
+                    if (p >= npl) break;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int jy = nx + iy + u * q;
+                        const T cy = rc[jy];
+                        const T fv =
+                            o[p][u] + (Exa[p] * Ea[jy] * (Pxa[p] + Pa[jy]) - Exb[p] * Eb[jy] * (Pxb[p] + Pb[jy]));
+                        fr[k + p * pstep + u * kstep] = fv;
+                        const T h = wx[p] * rw[jy] * fv;
+                        Tp[p][0] += h;
+                        const T hy = h * cy;
+                        Tp[p][1] += hy;
+                        const T hy2 = hy * cy;
+                        Tp[p][2] += hy2;
+                        Tp[p][3] += hy2 * cy;
+                        if (nw > 0) {
+#pragma unroll
+                            for (int l = 0; l < NF; ++l)
+                                if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[p][l], (T)0);
+                        }
                     }
                 }
             }
-            S.fold(cx, rlo[ix], rlo[nx + ix], rlo[2 * nx + ix], rlo[3 * nx + ix], rlo[4 * nx + ix], T0, T1, T2, T3,
-                   (T)0, (T)0, (T)0);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                if (p >= npl) break;
+                const int jx = ix + p;
+                S.fold(cx[p], rlo[jx], rlo[nx + jx], rlo[2 * nx + jx], rlo[3 * nx + jx], rlo[4 * nx + jx], Tp[p][0],
+                       Tp[p][1], Tp[p][2], Tp[p][3], (T)0, (T)0, (T)0);
+            }
         }
     } else {
         const int q = BLOCK / ny;
@@ -599,23 +642,71 @@ __global__ __launch_bounds__(BLOCK) void k_correct_fast(const CaseView *__restri
         }
     }
     const int dl = (VD == 3) ? 2 : 1;
-    finish_partials<T, VD, NF>(S, Wf, fwall, C.xv[dl * MAXA + ilc] - P.u[dl], C.wv[dl * MAXA + ilc],
-                               C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+    finish_partials<T, VD, NF>(S, Wf, fwall, (VD == 3) ? nz : ny, C.xv + dl * MAXA, C.wv + dl * MAXA, P.u[dl],
+                               C.partial + ((size_t)slot * C.ntile + vt) * NSUM, (T *)(smem_raw + red_off));
 }
 
-size_t sweep_fast_lds(const CaseView &h, size_t es)
+// ---------------------------------------------------------------------------
+// axis tables of each kinetic slot's relaxation target (FP64, rounded once):
+// c = x_j - u_d, E = exp(-c^2 / T), fix-up part (a_0 folded into the x axis),
+// Shakhov part kq_d c; then c, c^2, c^3 of the x axis split into rounded value
+// and low part for the compensated plane fold
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(128) void k_axtab(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    const int cell = C.kin_cell[blockIdx.x];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const int nx = C.n[0], ny = C.n[1], vd = C.vdim;
+    const int NA = nx + ny + ((vd == 3) ? C.n[2] : 0);
+    const double it = P.it;
+    const double fq = (vd == 3) ? P.fx[4] : P.fx[3];
+    T *tb = (T *)C.axtab + (size_t)slot * C.tabp;
+    for (int j = threadIdx.x; j < NA; j += blockDim.x) {
+        const int d = (j < nx) ? 0 : ((j < nx + ny) ? 1 : 2);
+        const int jj = j - ((d == 0) ? 0 : ((d == 1) ? nx : nx + ny));
+        const double c = C.xv[d * MAXA + jj] - P.u[d];
+        const double pl = (d == 0) ? P.fx[0] + P.fx[1] * c + fq * c * c : P.fx[1 + d] * c + fq * c * c;
+        tb[j] = (T)c;
+        tb[NA + j] = (T)exp(-c * c * it);
+        tb[2 * NA + j] = (T)pl;
+        tb[3 * NA + j] = (T)(P.kq[d] * c);
+        if (d == 0) {
+            const double c2 = c * c, c3 = c2 * c;
+            T *lo = tb + 4 * NA;
+            lo[jj] = (T)(c - (double)(T)c);
+            lo[nx + jj] = (T)c2;
+            lo[2 * nx + jj] = (T)(c2 - (double)(T)c2);
+            lo[3 * nx + jj] = (T)c3;
+            lo[4 * nx + jj] = (T)(c3 - (double)(T)c3);
+        }
+    }
+}
+
+hipError_t launch_axtab(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    if (h.dtype == GSIS_F32) hipLaunchKernelGGL(k_axtab<float>, dim3(n_kin), dim3(128), 0, s, cv);
+    else hipLaunchKernelGGL(k_axtab<double>, dim3(n_kin), dim3(128), 0, s, cv);
+    return hipGetLastError();
+}
+
+// table elements in LDS: five per-axis tables and the x axis' low parts
+size_t sweep_fast_tab(const CaseView &h)
 {
     const int NA = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
-    return es * ((size_t)5 * NA + 5 * h.n[0]);
+    return (size_t)5 * NA + 5 * h.n[0];
 }
 
 template <typename T, int VD, int U>
-void launch_u(const Batch &b, size_t lds, int total, hipStream_t s)
+void launch_u(const Batch &b, size_t tab, int total, hipStream_t s)
 {
-    if (b.nfmax <= 4)
-        hipLaunchKernelGGL((k_sweep_fast<T, VD, 4, U>), dim3(total), dim3(BLOCK), lds, s, b);
-    else
-        hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF, U>), dim3(total), dim3(BLOCK), lds, s, b);
+    const size_t off = red_offset<T>(tab);
+    const size_t l4 = off + red_bytes<T, 4>(), l8 = off + red_bytes<T, MAXF>();
+    if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_fast<T, VD, 4, U>), dim3(total), dim3(BLOCK), l4, s, b);
+    else hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF, U>), dim3(total), dim3(BLOCK), l8, s, b);
 }
 
 // points per load round: 3D, the largest of 4, 2, 1 that divides M, the
@@ -642,11 +733,11 @@ void launch_nf(const Batch &b, const CaseView &h0, size_t lds, int total, hipStr
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
     if (h0.dtype == GSIS_F32) {
-        size_t lds = sweep_fast_lds(h0, sizeof(float));
+        const size_t lds = sweep_fast_tab(h0);
         if (h0.vdim == 3) launch_nf<float, 3>(b, h0, lds, total, s);
         else launch_nf<float, 2>(b, h0, lds, total, s);
     } else {
-        size_t lds = sweep_fast_lds(h0, sizeof(double));
+        const size_t lds = sweep_fast_tab(h0);
         if (h0.vdim == 3) launch_nf<double, 3>(b, h0, lds, total, s);
         else launch_nf<double, 2>(b, h0, lds, total, s);
     }
@@ -657,10 +748,11 @@ template <typename T, int VD, int U>
 void launch_correct_u(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
 {
     const int NA = h.n[0] + h.n[1] + (VD == 3 ? h.n[2] : 0);
-    const size_t lds = sizeof(T) * ((size_t)6 * NA + 5 * h.n[0]);
+    const size_t off = red_offset<T>((size_t)6 * NA + 5 * h.n[0]);
     dim3 g(n_kin * h.ntile);
-    if (h.nfmax <= 4) hipLaunchKernelGGL((k_correct_fast<T, VD, 4, U>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
-    else hipLaunchKernelGGL((k_correct_fast<T, VD, MAXF, U>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+    const size_t l4 = off + red_bytes<T, 4>(), l8 = off + red_bytes<T, MAXF>();
+    if (h.nfmax <= 4) hipLaunchKernelGGL((k_correct_fast<T, VD, 4, U>), g, dim3(BLOCK), l4, s, cv, n_kin, cur);
+    else hipLaunchKernelGGL((k_correct_fast<T, VD, MAXF, U>), g, dim3(BLOCK), l8, s, cv, n_kin, cur);
 }
 
 template <typename T, int VD>
