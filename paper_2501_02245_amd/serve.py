@@ -186,7 +186,8 @@ class Server:
                 results.append(self._retire(a, status, t0))
                 if log:
                     log("request %d (%s) %s after %d iterations, %.3f s, eps %s" % (
-                        a.req.rid, a.req.kind, status, a.it, results[-1].latency, np.array2string(a.eps, precision=2)))
+                        a.req.rid, a.req.kind, status, a.it, results[-1].latency,
+                        " ".join("%.2e" % x for x in a.eps)))
         torch.cuda.synchronize()
         return sorted(results, key=lambda r: r.rid)
 
