@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
     ap.add_argument("--serve-requests", type=int, default=12, help="requests in the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving leg (1/s)")
-    ap.add_argument("--serve-max-iter", type=int, default=200)
+    ap.add_argument("--serve-max-iter", type=int, default=150)
     ap.add_argument("--serve-tol", type=float, default=1e-4,
                     help="served solves stop at this residual (the explicit synthetic solver converges slowly in "
                          "transitional closed boxes)")

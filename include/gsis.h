@@ -195,6 +195,15 @@ typedef struct {
 gsis_status gsis_step(gsis_case const *cases, int32_t n_cases, const gsis_solve_params *p, double *eps_host,
                       void *stream);
 
+/* Steps 1-2 of Sec. 3.4 for a batch of aGSIS cases: every cell NS, the
+ * synthetic solve alone (HoT = 0, n_macro_inner steps per chunk, at most
+ * ns_init_max_chunks chunks) to eps < 1e-6, then the first flagging with
+ * Grad-13 rows for every kinetic cell.  The cases' solves share batched
+ * launches; a case leaves the batch when it converges.  chunks (host,
+ * nullable) receives the chunks each case ran.  Synchronises. */
+gsis_status gsis_ns_init(gsis_case const *cases, int32_t n_cases, const gsis_solve_params *p, int32_t *chunks,
+                         void *stream);
+
 /* Steady solve: optional NS initialisation and first flagging (aGSIS), then
  * gsis_step until max(eps) < tol.  Returns GSIS_E_NOCONV after max_iter.
  * max_iter = 0 is allowed with ns_init: the call then stops after the first

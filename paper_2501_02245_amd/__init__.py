@@ -28,7 +28,7 @@ EXPORTS = [
     "gsis_set_velocity_grid", "gsis_case_footprint", "gsis_case_bind", "gsis_set_state", "gsis_kinetic_sweep",
     "gsis_moments", "gsis_n_kinetic", "gsis_update_regions", "gsis_step", "gsis_solve_steady", "gsis_get_vdf",
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
-    "gsis_sweep_layout",
+    "gsis_sweep_layout", "gsis_ns_init",
 ]
 
 
@@ -90,6 +90,7 @@ def lib():
             "gsis_get_state": [P, P, P, P], "gsis_correct": [P, P, P], "gsis_macro_solve": [P, P, P, P, I32, D, P],
             "gsis_last_sweep_ms": [P, P],
             "gsis_sweep_layout": [P, P, P, P],
+            "gsis_ns_init": [P, I32, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -295,6 +296,15 @@ def kinetic_sweep(cases, n_sweeps=1):
     """One batched launch per sweep over several cases (same dtype and vdim)."""
     arr = (C.c_void_p * len(cases))(*[c.handle for c in cases])
     _check(lib().gsis_kinetic_sweep(arr, len(cases), n_sweeps, _stream()))
+
+
+def ns_init(cases, params: SolveParams):
+    """Steps 1-2 (NS start, first flagging) for several aGSIS cases with batched
+    launches; returns the chunks each case ran."""
+    arr = (C.c_void_p * len(cases))(*[c.handle for c in cases])
+    chunks = (C.c_int32 * len(cases))()
+    _check(lib().gsis_ns_init(arr, len(cases), C.byref(params), chunks, _stream()))
+    return list(chunks)
 
 
 def step(cases, params: SolveParams):

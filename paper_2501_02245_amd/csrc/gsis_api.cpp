@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -80,6 +81,10 @@ struct gsis_case_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
 };
+
+namespace {
+void drop_graphs_of(gsis_case c);   // captured synthetic solves that use the case
+}  // namespace
 
 extern "C" const char *gsis_last_error(void) { return g_err.c_str(); }
 
@@ -341,6 +346,7 @@ extern "C" gsis_status gsis_create_case(gsis_mesh mesh, const gsis_gas *gas, int
 extern "C" gsis_status gsis_destroy_case(gsis_case c)
 {
     if (!c) return fail(GSIS_E_ARG, "null case");
+    drop_graphs_of(c);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     c->mesh->refs--;
@@ -579,6 +585,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     int tile, ntile, row, fast, xp;
     Layout L = make_layout(c, cap, &tile, &ntile, &row, &fast, &xp);
     if (bytes < L.total) return fail(GSIS_E_NOMEM, "workspace of %zu bytes < footprint %zu", bytes, L.total);
+    drop_graphs_of(c);   // captured launches point into the previous workspace
     hipStream_t s = (hipStream_t)stream;
     const gsis_mesh_s *m = c->mesh;
     unsigned char *B = (unsigned char *)ws;
@@ -957,19 +964,101 @@ gsis_status pre_macro(gsis_case c, const gsis_solve_params *p, hipStream_t s)
     return GSIS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// HIP graphs of the synthetic solve: the n_inner pseudo-time steps of a batch
+// (3-5 launches each) are captured once per batch composition on a private
+// stream and replayed on the caller's stream.  Every pointer a captured launch
+// uses lives in the cases' workspaces, so a graph stays valid while its cases
+// stay bound; binding again or destroying a case drops its graphs.  Set
+// GSIS_GRAPHS=0 to launch eagerly.
+// ---------------------------------------------------------------------------
+struct MacroGraph {
+    std::vector<gsis_case> cases;
+    int n_inner;
+    double cfl;
+    bool with_src;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+
+std::mutex g_graph_mu;
+std::vector<MacroGraph> g_graphs;
+hipStream_t g_capture_stream = nullptr;
+uint64_t g_graph_clock = 0;
+constexpr size_t MAX_GRAPHS = 64;
+
+bool graphs_enabled()
+{
+    const char *env = std::getenv("GSIS_GRAPHS");
+    return !(env && env[0] == '0');
+}
+
+void drop_graphs_of(gsis_case c)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (size_t k = 0; k < g_graphs.size();) {
+        MacroGraph &G = g_graphs[k];
+        if (std::find(G.cases.begin(), G.cases.end(), c) != G.cases.end()) {
+            (void)hipGraphExecDestroy(G.exec);
+            (void)hipGraphDestroy(G.graph);
+            g_graphs.erase(g_graphs.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+}
+
+// n_inner pseudo-time steps of the cases' synthetic equations, W <- Wn
+gsis_status run_macro_batch(gsis_case const *cases, int n, int n_inner, double cfl, bool with_src, hipStream_t s)
+{
+    MBatch b{};
+    for (int j = 0; j < n; ++j) {
+        CaseView &h = cases[j]->hv;
+        mbatch_add(b, cases[j]->cv, h, h.Wn, h.hot, with_src ? h.src : nullptr);
+    }
+    if (!graphs_enabled() || n_inner <= 0) {
+        HIPCHK(launch_macro_steps_batch(b, n_inner, cfl, s));
+        return GSIS_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    std::vector<gsis_case> key(cases, cases + n);
+    MacroGraph *hit = nullptr;
+    for (auto &G : g_graphs)
+        if (G.cases == key && G.n_inner == n_inner && G.cfl == cfl && G.with_src == with_src) hit = &G;
+    if (!hit) {
+        if (!g_capture_stream) HIPCHK(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+        if (g_graphs.size() >= MAX_GRAPHS) {
+            auto lru = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                        [](const MacroGraph &a, const MacroGraph &c) { return a.last_use < c.last_use; });
+            (void)hipGraphExecDestroy(lru->exec);
+            (void)hipGraphDestroy(lru->graph);
+            g_graphs.erase(lru);
+        }
+        MacroGraph G{key, n_inner, cfl, with_src, nullptr, nullptr, 0};
+        HIPCHK(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_macro_steps_batch(b, n_inner, cfl, g_capture_stream);
+        hipError_t e2 = hipStreamEndCapture(g_capture_stream, &G.graph);
+        HIPCHK(e);
+        HIPCHK(e2);
+        HIPCHK(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+        g_graphs.push_back(G);
+        hit = &g_graphs.back();
+    }
+    hit->last_use = ++g_graph_clock;
+    HIPCHK(hipGraphLaunch(hit->exec, s));
+    return GSIS_OK;
+}
+
 // the synthetic solves of a batch: one launch per kernel and pseudo-time step
 // for all cases (up to 16 per launch)
 gsis_status macro_solves(gsis_case const *cases, int n, const gsis_solve_params *p, hipStream_t s)
 {
     if (p->mode == GSIS_MODE_DVM) return GSIS_OK;
-    for (int j0 = 0; j0 < n; j0 += MAX_BATCH) {
-        MBatch b{};
-        for (int j = j0; j < std::min(n, j0 + MAX_BATCH); ++j) {
-            CaseView &h = cases[j]->hv;
-            mbatch_add(b, cases[j]->cv, h, h.Wn, h.hot, h.src);
-        }
-        HIPCHK(launch_macro_steps_batch(b, p->n_macro_inner, p->cfl, s));
-    }
+    gsis_status st;
+    for (int j0 = 0; j0 < n; j0 += MAX_BATCH)
+        if ((st = run_macro_batch(cases + j0, std::min(MAX_BATCH, n - j0), p->n_macro_inner, p->cfl, true, s)))
+            return st;
     return GSIS_OK;
 }
 
@@ -1071,6 +1160,67 @@ extern "C" gsis_status gsis_macro_solve(gsis_case c, double *W, const double *ho
     return sync_status(c, s);
 }
 
+extern "C" gsis_status gsis_ns_init(gsis_case const *cases, int32_t n, const gsis_solve_params *p, int32_t *chunks,
+                                    void *stream)
+{
+    if (!cases || n <= 0 || n > 1024) return fail(GSIS_E_ARG, "bad case list");
+    gsis_status st;
+    if ((st = check_params(p))) return st;
+    if (p->mode != GSIS_MODE_AGSIS) return fail(GSIS_E_ARG, "the NS start belongs to aGSIS");
+    for (int j = 0; j < n; ++j) {
+        if ((st = check_ready(cases[j]))) return st;
+        for (int i = 0; i < j; ++i)
+            if (cases[i] == cases[j]) return fail(GSIS_E_ARG, "a case appears twice");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // Step 1: every cell NS, the synthetic solve alone (HoT = 0) to eps < 1e-6
+    const double ns_tol = 1e-6;
+    for (int j = 0; j < n; ++j) {
+        gsis_case c = cases[j];
+        CaseView &h = c->hv;
+        HIPCHK(launch_set_flags(c->cv, h, nullptr, 0, s));
+        HIPCHK(launch_compact(c->cv, h, s));
+        if ((st = read_counts(c, s, nullptr))) return st;
+        HIPCHK(hipMemsetAsync(h.hot, 0, 72 * (size_t)h.n_cells, s));
+        if (chunks) chunks[j] = 0;
+    }
+    std::vector<gsis_case> active(cases, cases + n);
+    std::vector<int> idx(n);
+    for (int j = 0; j < n; ++j) idx[j] = j;
+    const int max_chunks = p->ns_init_max_chunks > 0 ? p->ns_init_max_chunks : 1000;
+    for (int k = 0; k < max_chunks && !active.empty(); ++k) {
+        for (gsis_case c : active) HIPCHK(launch_copy_W(c->hv.Wn, c->hv.W, c->hv.n_cells, s));
+        for (size_t j0 = 0; j0 < active.size(); j0 += MAX_BATCH)
+            if ((st = run_macro_batch(active.data() + j0, (int)std::min<size_t>(MAX_BATCH, active.size() - j0),
+                                      p->n_macro_inner, p->cfl, false, s)))
+                return st;
+        std::vector<double> e(3 * active.size());
+        for (size_t j = 0; j < active.size(); ++j) {
+            CaseView &h = active[j]->hv;
+            HIPCHK(launch_eps(active[j]->cv, h, h.Wn, h.W, s));
+            HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+            HIPCHK(hipMemcpyAsync(&e[3 * j], h.eps, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<gsis_case> still;
+        std::vector<int> still_idx;
+        for (size_t j = 0; j < active.size(); ++j) {
+            if ((st = sync_status(active[j], s))) return st;
+            if (chunks) chunks[idx[j]] = k + 1;
+            if (std::max(e[3 * j], std::max(e[3 * j + 1], e[3 * j + 2])) >= ns_tol) {
+                still.push_back(active[j]);
+                still_idx.push_back(idx[j]);
+            }
+        }
+        active.swap(still);
+        idx.swap(still_idx);
+    }
+    // Step 2: first flagging; every kinetic cell is new and starts from Grad-13
+    for (int j = 0; j < n; ++j)
+        if ((st = gsis_update_regions(cases[j], p->Kn_ref, p->force_wall_layers, nullptr, stream))) return st;
+    return GSIS_OK;
+}
+
 extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p, gsis_solve_result *r, void *stream)
 {
     gsis_status st = check_ready(c);
@@ -1080,29 +1230,9 @@ extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p
     const bool ns_init = p->mode == GSIS_MODE_AGSIS && p->ns_init;
     if (!(p->tol > 0) || p->max_iter < 0 || (p->max_iter == 0 && !ns_init))
         return fail(GSIS_E_ARG, "bad tol or max_iter");
-    hipStream_t s = (hipStream_t)stream;
-    CaseView &h = c->hv;
     std::memset(r, 0, sizeof *r);
     if (ns_init) {
-        // Step 1: every cell NS, macroscopic solve alone (HoT = 0) to eps < 1e-6
-        const double ns_tol = 1e-6;
-        HIPCHK(launch_set_flags(c->cv, h, nullptr, 0, s));
-        HIPCHK(launch_compact(c->cv, h, s));
-        if ((st = read_counts(c, s, nullptr))) return st;
-        HIPCHK(hipMemsetAsync(h.hot, 0, 72 * (size_t)h.n_cells, s));
-        int chunks = p->ns_init_max_chunks > 0 ? p->ns_init_max_chunks : 1000;
-        for (int k = 0; k < chunks; ++k) {
-            HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
-            HIPCHK(launch_macro_steps(c->cv, h, h.Wn, h.hot, nullptr, p->n_macro_inner, p->cfl, s));
-            HIPCHK(launch_eps(c->cv, h, h.Wn, h.W, s));
-            HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
-            double e[3];
-            HIPCHK(hipMemcpyAsync(e, h.eps, sizeof e, hipMemcpyDeviceToHost, s));
-            if ((st = sync_status(c, s))) return st;
-            if (std::max(e[0], std::max(e[1], e[2])) < ns_tol) break;
-        }
-        // Step 2: first flagging; every kinetic cell is new and starts from Grad-13
-        if ((st = gsis_update_regions(c, p->Kn_ref, p->force_wall_layers, nullptr, stream))) return st;
+        if ((st = gsis_ns_init(&c, 1, p, nullptr, stream))) return st;
         r->n_kinetic = c->n_kin;
         if (p->max_iter == 0) return GSIS_OK;
     }

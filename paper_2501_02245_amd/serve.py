@@ -19,7 +19,8 @@ from collections import defaultdict, deque
 
 import numpy as np
 
-from . import (E_CAPACITY, F32, MODE_AGSIS, MODE_GSIS, Case, GsisError, Mesh, SolveParams, footprint, step)
+from . import (E_CAPACITY, F32, MODE_AGSIS, MODE_GSIS, Case, GsisError, Mesh, SolveParams, footprint, ns_init,
+               step)
 
 
 @dataclasses.dataclass
@@ -36,6 +37,7 @@ class Request:
     mode: str = "agsis"          # "agsis": NS start, then adaptive steps; "gsis": every cell kinetic
     cfl: float = 0.5             # synthetic pseudo-time step (< 0: one global step)
     fields: tuple = (0, 1, 2)    # residuals (rho, u, T) that must fall below tol
+    solo: bool = False           # run the NS start alone (after a failed batched start)
 
     @classmethod
     def from_spec(cls, d):
@@ -79,8 +81,9 @@ class Server:
     """FIFO admission by footprint, one batched outer iteration per tick."""
 
     def __init__(self, budget_bytes, dtype=F32, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400,
-                 ns_chunks=200, max_active=64, keep_fields=True):
+                 ns_chunks=50, max_active=64, keep_fields=True, min_iter=5):
         self.budget = int(budget_bytes)
+        self.min_iter = min_iter     # a first small change is not convergence
         self.dtype, self.Kn_ref, self.tol, self.max_iter = dtype, Kn_ref, tol, max_iter
         self.n_inner, self.ns_chunks = n_inner, ns_chunks
         self.max_active, self.keep_fields = max_active, keep_fields
@@ -91,9 +94,36 @@ class Server:
     def _params(self, mode, cfl, layers, **kw):
         return params_for(mode, cfl, layers, self.Kn_ref, self.tol, self.n_inner, **kw)
 
-    def _admit(self, r, fp, t0):
-        case = start_case(r, self.dtype, self.Kn_ref, self.tol, self.n_inner, self.ns_chunks)
+    def _bind(self, r, fp, t0):
+        """Bind the case and set W0; aGSIS cases start every cell NS (Step 1 follows)."""
+        M = Mesh(r.mesh)
+        cap = max(1, int(round(r.capacity * M.n_cells)))
+        case = Case(M, r.grid, r.Kn, dtype=self.dtype, capacity=cap)
+        if r.mode == "agsis":
+            case.set_state(r.W0, flags=np.zeros(M.n_cells, np.uint8))
+        else:
+            case.set_state(r.W0)
         return _Active(r, case, fp, time.perf_counter() - t0)
+
+    def _ns_starts(self, fresh):
+        """Steps 1-2 for newly bound aGSIS cases, batched by launch compatibility;
+        returns [(active, outcome)]: None (started), "retry" (the batched start
+        failed: restart alone), or the error of a start run alone."""
+        out = []
+        groups = defaultdict(list)
+        for k, a in enumerate(fresh):
+            if a.req.mode == "agsis":
+                groups[(a.case.dtype, a.req.cfl, a.req.layers, k if a.req.solo else -1)].append(a)
+            else:
+                out.append((a, None))
+        for (_, cfl, layers, _), grp in groups.items():
+            p = self._params("agsis", cfl, layers, max_iter=0, ns_init=1, ns_init_max_chunks=self.ns_chunks)
+            try:
+                ns_init([a.case for a in grp], p)
+                out += [(a, None) for a in grp]
+            except GsisError as e:
+                out += [(a, "retry" if len(grp) > 1 else e) for a in grp]
+        return out
 
     def _retire(self, a, status, t0):
         W = a.case.get_state()[0].cpu().numpy() if (self.keep_fields and status in ("ok", "noconv")) else None
@@ -113,15 +143,17 @@ class Server:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            # admission: FIFO while the head fits
-            while queue and len(active) < self.max_active:
+            # admission: FIFO while the head fits; the new aGSIS cases then run
+            # their NS starts together
+            fresh = []
+            while queue and len(active) + len(fresh) < self.max_active:
                 r = queue[0]
                 M = Mesh(r.mesh)
                 cap = max(1, int(round(r.capacity * M.n_cells)))
                 fp = footprint(M, r.grid, r.Kn, self.dtype, cap)
                 M.close()
                 if used + fp > self.budget:
-                    if not active:
+                    if not active and not fresh:
                         queue.popleft()
                         results.append(Result(r.rid, r.kind, r.arrival, now, now, 0, np.full(3, np.inf), 0,
                                               "rejected: footprint %d B > budget" % fp))
@@ -129,18 +161,30 @@ class Server:
                     break
                 queue.popleft()
                 try:
-                    a = self._admit(r, fp, t0)
+                    fresh.append(self._bind(r, fp, t0))
                 except GsisError as e:
-                    if e.code == E_CAPACITY and r.capacity < 1.0:
-                        # region larger than the reservation: retry with twice the reservation
-                        queue.appendleft(dataclasses.replace(r, capacity=min(1.0, 2.0 * r.capacity)))
-                        self.requeued += 1
-                        continue
                     results.append(Result(r.rid, r.kind, r.arrival, now, time.perf_counter() - t0, 0,
                                           np.full(3, np.inf), 0, "error: %s" % e))
                     continue
-                active.append(a)
                 used += fp
+            for a, err in self._ns_starts(fresh):
+                if err is None:
+                    active.append(a)
+                    continue
+                used -= a.fp
+                a.case.close()
+                a.case.mesh.close()
+                r = a.req
+                if err == "retry":
+                    queue.appendleft(dataclasses.replace(r, solo=True))
+                    self.requeued += 1
+                elif err.code == E_CAPACITY and r.capacity < 1.0:
+                    # region larger than the reservation: retry with twice the reservation
+                    queue.appendleft(dataclasses.replace(r, capacity=min(1.0, 2.0 * r.capacity)))
+                    self.requeued += 1
+                else:
+                    results.append(Result(r.rid, r.kind, r.arrival, a.t_admit, time.perf_counter() - t0, 0,
+                                          np.full(3, np.inf), 0, "error: %s" % err))
             self.peak_active = max(self.peak_active, len(active))
             self.peak_bytes = max(self.peak_bytes, used)
             if not active:
@@ -170,7 +214,7 @@ class Server:
                             done.append((a, "requeue" if requeue else "error: %s" % err))
                             continue
                         a.eps = e
-                        if np.max(e[list(a.req.fields)]) < self.tol:
+                        if a.it >= self.min_iter and np.max(e[list(a.req.fields)]) < self.tol:
                             done.append((a, "ok"))
                         elif a.it >= self.max_iter:
                             done.append((a, "noconv"))
@@ -197,7 +241,7 @@ def params_for(mode, cfl, layers, Kn_ref=0.01, tol=1e-6, n_inner=400, **kw):
                        n_macro_inner=n_inner, cfl=cfl, region_update_every=1, force_wall_layers=layers, **kw)
 
 
-def start_case(r: Request, dtype, Kn_ref=0.01, tol=1e-6, n_inner=400, ns_chunks=200):
+def start_case(r: Request, dtype, Kn_ref=0.01, tol=1e-6, n_inner=400, ns_chunks=50):
     """Bind a case for the request and set its start: aGSIS requests run Steps
     1-2 of Sec. 3.4 (NS start, first flagging); GSIS requests start kinetic
     everywhere from the conservation-fixed Maxwellian of W0."""
@@ -218,7 +262,7 @@ def start_case(r: Request, dtype, Kn_ref=0.01, tol=1e-6, n_inner=400, ns_chunks=
     return case
 
 
-def solve_alone(r: Request, dtype, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400, ns_chunks=200):
+def solve_alone(r: Request, dtype, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400, ns_chunks=50, min_iter=5):
     """One request on its own, with the same steps, stopping rule and
     reservation doubling as the server."""
     while True:
@@ -235,7 +279,7 @@ def solve_alone(r: Request, dtype, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=
             while it < max_iter:
                 eps = case.step(p)
                 it += 1
-                if np.max(eps[list(r.fields)]) < tol:
+                if it >= min_iter and np.max(eps[list(r.fields)]) < tol:
                     status = "ok"
                     break
         except GsisError as e:
