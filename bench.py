@@ -182,6 +182,31 @@ def fp64_sweep(g, torch, M, grid, W, flags, steps=3):
     return out
 
 
+def surface_leg(g, torch, case, mesh, es):
+    """Surface quantities on the sphere (stress, pressure, heat flux per wall face,
+    force and heat totals) at the state after the timed steps: kernel time over
+    3 calls, the bytes of the kinetic wall rows it reads, and the coefficients
+    (reference area: the sphere's cross-section)."""
+    faces, out, tot = case.surface()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        faces, out, tot = case.surface()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    _, fl = case.get_state()
+    fl = fl.cpu().numpy()
+    f = faces.cpu().numpy()
+    kin_walls = int(fl[mesh["face_cells"][f, 0]].sum())
+    u_inf = mesh["patches"][[p["kind"] for p in mesh["patches"]].index("far")]["u"]
+    coef = g.force_coefficients(tot.cpu().numpy(), 1.0, u_inf, np.pi / 4)
+    return {"ms": ms, "wall_faces": int(len(f)), "kinetic_wall_faces": kin_walls,
+            "read_gbs": kin_walls * case.nv * es / (ms / 1e3) / 1e9, **coef,
+            "state": "after the timed steps (not converged)"}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -239,6 +264,8 @@ def main():
     alg_bytes = 2 * es * n_kin_mean * nv          # read f^n, write f^{n+1/2}
     achieved = alg_bytes / sweep_s / 1e9
     traffic = measured_traffic(n_kin_mean, nv) if dtype == g.F32 else None
+    surface = surface_leg(g, torch, case, mesh, es)
+    log("surface", surface)
     case.close()
 
     if a.calibrate_copy > 0:
@@ -279,6 +306,7 @@ def main():
                      "kernel_ms": 1e3 * sweep_s},
         "sweep_updates_per_s": n_kin_mean * nv / sweep_s,
         "fp64_sweep": fp64,
+        "surface": surface,
         "setup_s": setup_s,
     }
     if a.serve_requests > 0 and not a.sweep_only:

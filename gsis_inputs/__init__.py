@@ -544,6 +544,25 @@ def sphere_workload(nv1d: int = 32, mach: float = 5.0):
     return mesh, grid, hypersonic_field(mesh, mach=mach)
 
 
+def resolving_size(nv: int, sizes, V: float, u: float, max_spacing: float = 0.7, alpha: float = 0.4) -> int:
+    """Smallest axis size >= nv that resolves a unit-temperature Maxwellian
+    centred at u on the stretched axis of half-width V: node spacing at u at
+    most max_spacing (the Maxwellian exp(-c^2) has standard deviation 0.71).
+    Sizes beyond the listed ones double the largest; coarser axes leave the
+    conservation-fixed Maxwellian of the free stream negative in its tails."""
+    eta = abs(u) / V
+    for _ in range(60):      # invert xi(eta) = V (alpha eta + (1 - alpha) eta^3) by Newton
+        f = alpha * eta + (1.0 - alpha) * eta ** 3 - abs(u) / V
+        eta -= f / (alpha + 3.0 * (1.0 - alpha) * eta * eta)
+    slope = V * (alpha + 3.0 * (1.0 - alpha) * eta * eta)
+    cands = sorted(x for x in sizes if x >= nv)
+    while True:
+        for n in cands:
+            if slope * 2.0 / (n - 1) <= max_spacing:
+                return int(n)
+        cands = [2 * cands[-1]]
+
+
 def serving_requests(n: int, rate: float, seed: int = 7, kinds=("couette", "fourier", "cylinder"),
                      cells_1d=(32, 512), nv_1d=(16, 32), cells_2d=(2000, 20000), nv_2d=(32, 64),
                      Kn_range=(1e-3, 1.0), mach_range=(1.0, 8.0)):
@@ -557,7 +576,9 @@ def serving_requests(n: int, rate: float, seed: int = 7, kinds=("couette", "four
     The 1D boxes are solved fully kinetic (GSIS, global pseudo-time step); the
     cylinder adaptively (aGSIS from the NS start).
     Cells log-uniform in the given ranges; Kn log-uniform; Mach uniform; the
-    velocity range is max(5 or 15, u + 4 sqrt(T_stag)), T_stag = 1 + Ma^2/3.
+    velocity range is max(5 or 15, u + 4 sqrt(T_stag)), T_stag = 1 + Ma^2/3;
+    the drawn axis size grows (resolving_size) until the unit-temperature
+    Maxwellian of the free stream or the moving walls is resolved.
     """
     g = rng_of(seed)
     t = 0.0
@@ -583,6 +604,7 @@ def serving_requests(n: int, rate: float, seed: int = 7, kinds=("couette", "four
                 V = max(5.0, 4.0 * math.sqrt(TR) + 1.0)
                 W0 = uniform_W(nc)
                 W0[:, 4] = 1.0 + (TR - 1.0) * mesh["cell_center"][:, 0]
+            nv = resolving_size(nv, nv_1d, V, U if kind == "couette" else 0.0)
             grid = velocity_grid(3, nv, V, "stretched")
             # closed box, every cell kinetic: GSIS with one global (conservative) step
             layers, cap, mode, cfl = 0, 1.0, "gsis", -0.5
@@ -595,6 +617,7 @@ def serving_requests(n: int, rate: float, seed: int = 7, kinds=("couette", "four
                                    seed=int(g.integers(1 << 30)))
             nv = int(nv_2d[int(g.integers(len(nv_2d)))])
             V = max(15.0, u + 4.0 * math.sqrt(T_stag))
+            nv = resolving_size(nv, nv_2d, V, u)
             grid = velocity_grid(2, nv, V, "stretched")
             W0 = hypersonic_field(mesh, mach=Ma)
             W0[:, 3] = 0.0

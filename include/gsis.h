@@ -217,6 +217,28 @@ gsis_status gsis_get_vdf(gsis_case c, void *out_dev, void *stream);
 /* Copy W [n_cells][5] FP64 and flags [n_cells] uint8 (either nullable). */
 gsis_status gsis_get_state(gsis_case c, double *W_dev, uint8_t *flags_dev, void *stream);
 
+/* Surface quantities on the diffuse walls (Sec. 4.2 and 4.3: surface
+ * pressure, heat flux, drag and lift), one row per wall face in ascending face
+ * id, GSIS_NSURF FP64 values:
+ *   [0..2] stress vector tau exerted by the gas on the wall, tau = P.n,
+ *          units rho0 R T0;
+ *   [3]    pressure p = tau.n;   [4..6] shear tau - p n;
+ *   [7]    heat flux into the wall, units rho0 R T0 v_m;
+ *   [8]    net mass flux through the face (zero up to rounding on kinetic cells).
+ * n is the unit face normal pointing out of the gas.  On a kinetic wall cell
+ * the sums run over the cell's current VDF for incoming velocities (c.n > 0,
+ * c = xi - u_w) and over rho_w M(u_w, T_w) for reflected ones, rho_w from the
+ * discrete zero-mass-flux condition: tau = 2 sum w c (c.n) f,
+ * q = sum w (c.n) |c|^2 f (reduced 2D: |c|^2 phi + psi).  On an NS wall cell
+ * tau = rho T n + sigma_NSF.n and q = q_NSF.n with the one-sided wall
+ * gradients of the synthetic solve.  face_dev [n_wall] int32 (nullable)
+ * receives the face ids; totals_dev [4] (nullable) the integrals
+ * sum tau S (3) and sum q S in fixed order.  All device buffers are the
+ * caller's; nothing synchronises. */
+#define GSIS_NSURF 9
+gsis_status gsis_n_wall_faces(gsis_case c, int32_t *n_wall);
+gsis_status gsis_surface(gsis_case c, int32_t *face_dev, double *out_dev, double *totals_dev, void *stream);
+
 /* GSIS correction alone (Sec. 3.1, first eq. updatef) on the current VDF:
  * f += f_eq(W_new) - f_eq(W_half) on kinetic cells, where W_half are the
  * current moments and W_new_dev [n_cells][5] FP64; W becomes W_new. */

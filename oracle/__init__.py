@@ -326,6 +326,75 @@ class Oracle:
             raise FloatingPointError("non-positive state")
         return out
 
+    def wall_faces(self):
+        """Boundary faces on diffuse-wall patches, ascending face id."""
+        fc = self.mesh["face_cells"]
+        kinds = self.patch_kind
+        return np.array([f for f in range(len(fc)) if fc[f, 1] < 0 and kinds[-1 - fc[f, 1]] == 0], dtype=np.int64)
+
+    def surface(self, f, slot_of_cell, W, grad=None):
+        """Surface quantities on every diffuse-wall face (Sec. 4.2/4.3: surface
+        pressure, heat flux, aerodynamic forces), rows [n_wall][9]:
+        stress tau = P.n exerted by the gas (3), p = tau.n, shear tau - p n (3),
+        heat flux into the wall, net mass flux.  n points out of the gas.
+
+        Kinetic wall cell (slot >= 0), in the wall frame c = xi - u_w:
+        incoming velocities (c.n > 0) carry the cell's distribution, reflected
+        ones rho_w M(u_w, T_w) with rho_w making the net mass flux zero (the
+        diffuse wall of the sweep); tau = 2 sum w c (c.n) f (P = 2 int c c f in
+        these units), q = sum w (c.n) |c|^2 f, reduced 2D q = sum w (c.n)
+        (|c|^2 phi + psi).  NS wall cell: tau = rho T n + sigma.n and
+        q = q.n with the NSF laws at T_w evaluated on the LSQ cell gradient
+        whose normal part is replaced by the one-sided difference to the wall
+        values (the wall flux of the synthetic equations).
+        """
+        m = self.mesh
+        fc = m["face_cells"]
+        faces = self.wall_faces()
+        out = np.zeros((len(faces), 9))
+        if grad is None:
+            grad = self.primitive_gradients(W)
+        for j, fi in enumerate(faces):
+            L = fc[fi, 0]
+            pt = m["patches"][-1 - fc[fi, 1]]
+            n = np.asarray(m["face_normal"][fi], dtype=np.float64)
+            uw = np.asarray(pt["u"], dtype=np.float64)
+            Tw = float(pt["T"])
+            s = slot_of_cell[L]
+            if s >= 0:
+                c = self.xi.copy()
+                c[:, : self.vdim] -= uw[: self.vdim]
+                a = c @ n
+                c2 = np.sum(c * c, axis=1)
+                M = self.maxwellian(1.0, uw, Tw).reshape(self.nfun, self.nv)
+                row = np.asarray(f[s], dtype=np.float64).reshape(self.nfun, self.nv)
+                inc, ref = a > 0, a < 0
+                rho_w = np.sum(self.w[inc] * a[inc] * row[0, inc]) / np.sum(self.w[ref] * -a[ref] * M[0, ref])
+                g = np.where(inc[None, :], row, np.where(ref[None, :], rho_w * M, 0.0))
+                tau = 2.0 * np.sum((self.w * a * g[0])[:, None] * c, axis=0)
+                e = c2 * g[0] + (g[1] if self.nfun == 2 else 0.0)
+                q = np.sum(self.w * a * e)
+                mass = np.sum(self.w * a * g[0])
+            else:
+                dn = float(np.dot(m["face_center"][fi] - m["cell_center"][L], n))
+                wall = np.concatenate([uw, [Tw]])
+                cellv = np.concatenate([W[L, 1:4], [W[L, 4]]])
+                G = grad[L, 0:4, :].copy()
+                for v in range(4):
+                    G[v] += ((wall[v] - cellv[v]) / dn - np.dot(G[v], n)) * n
+                sg, qv = self.nsf(Tw, G[0:3], G[3])
+                S = np.array([[sg[0], sg[3], sg[4]], [sg[3], sg[1], sg[5]], [sg[4], sg[5], sg[2]]])
+                tau = W[L, 0] * W[L, 4] * n + S @ n
+                q = float(np.dot(qv, n))
+                mass = 0.0
+            p = float(np.dot(tau, n))
+            out[j, 0:3] = tau
+            out[j, 3] = p
+            out[j, 4:7] = tau - p * n
+            out[j, 7] = q
+            out[j, 8] = mass
+        return faces, out
+
     def kinetic_residual(self, f, kin_cell, slot_of_cell, ghost=None):
         """Moment balance (mass, momentum, energy per unit volume) of the kinetic scheme at f."""
         f = _f64(f)

@@ -21,6 +21,7 @@ F32, F64 = 0, 1
 PATCH_WALL, PATCH_FAR = 0, 1
 MODE_DVM, MODE_GSIS, MODE_AGSIS = 0, 1, 2
 NMOM = 14
+NSURF = 9
 MAX_FACES, MAX_WALL_FACES, MAX_AXIS = 8, 4, 128
 
 EXPORTS = [
@@ -28,8 +29,22 @@ EXPORTS = [
     "gsis_set_velocity_grid", "gsis_case_footprint", "gsis_case_bind", "gsis_set_state", "gsis_kinetic_sweep",
     "gsis_moments", "gsis_n_kinetic", "gsis_update_regions", "gsis_step", "gsis_solve_steady", "gsis_get_vdf",
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
-    "gsis_sweep_layout", "gsis_ns_init",
+    "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface",
 ]
+
+
+def force_coefficients(totals, rho_inf, u_inf, area):
+    """Drag and lift coefficients (Sec. 4.3) from surface totals [Fx, Fy, Fz, Q]:
+    C_d = F.e / (rho u^2 A) along the free stream e, C_l the same for the
+    in-plane normal of e (the dynamic pressure rho |u|^2 / 2 is rho u^2 in units
+    rho0 R T0); C_h = Q / (rho |u|^3 A) (heat, units rho0 R T0 v_m)."""
+    t = np.asarray(totals, dtype=np.float64)
+    u = np.asarray(u_inf, dtype=np.float64)
+    U = float(np.linalg.norm(u))
+    e = u / U
+    el = np.array([-e[1], e[0], 0.0])
+    q = rho_inf * U * U * area
+    return {"C_d": float(t[:3] @ e) / q, "C_l": float(t[:3] @ el) / q, "C_h": float(t[3]) / (q * U)}
 
 
 class GsisError(RuntimeError):
@@ -91,6 +106,7 @@ def lib():
             "gsis_last_sweep_ms": [P, P],
             "gsis_sweep_layout": [P, P, P, P],
             "gsis_ns_init": [P, I32, P, P, P],
+            "gsis_n_wall_faces": [P, P], "gsis_surface": [P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -249,6 +265,19 @@ class Case:
         fl = torch.empty(self.mesh.n_cells, dtype=torch.uint8, device="cuda")
         _check(lib().gsis_get_state(self.handle, _ptr(W), _ptr(fl), _stream()))
         return W, fl
+
+    def surface(self, totals=True):
+        """Wall-face surface quantities (Sec. 4.2/4.3): (face ids [n_wall] int32,
+        rows [n_wall][9] FP64: tau (3), p, shear (3), heat flux, mass flux,
+        totals [4] = sum tau S, sum q S or None), device tensors."""
+        import torch
+        n = C.c_int32()
+        _check(lib().gsis_n_wall_faces(self.handle, C.byref(n)))
+        faces = torch.empty(max(n.value, 1), dtype=torch.int32, device="cuda")
+        out = torch.empty((max(n.value, 1), NSURF), dtype=torch.float64, device="cuda")
+        tot = torch.empty(4, dtype=torch.float64, device="cuda") if totals else None
+        _check(lib().gsis_surface(self.handle, _ptr(faces), _ptr(out), _ptr(tot) if totals else None, _stream()))
+        return faces[: n.value], out[: n.value], tot
 
     def update_regions(self, Kn_ref, force_wall_layers=0):
         n = C.c_int64()

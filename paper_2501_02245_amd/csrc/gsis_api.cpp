@@ -56,6 +56,7 @@ struct Segment {
 struct gsis_mesh_s {
     int32_t dim, n_cells, n_faces, n_patches, nnz, max_faces = 0;
     std::vector<int32_t> face_cells, cf_ptr, cf_face, cf_other, cf_wall, patch_kind;
+    std::vector<int32_t> wall_faces;   // boundary faces on diffuse-wall patches, ascending id
     std::vector<double> face_normal, face_area, face_center, cell_volume, cell_center, cf_nsv, face_dist,
         patch_state;
     // geometry-only factors of the macroscopic kernels
@@ -313,6 +314,10 @@ extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
         m->face_dist[f] = dd;
     }
     build_macro_factors(m);
+    for (int f = 0; f < nf; ++f) {
+        int b = m->face_cells[2 * f + 1];
+        if (b < 0 && m->patch_kind[-1 - b] == GSIS_PATCH_WALL) m->wall_faces.push_back(f);
+    }
     *out = m;
     return GSIS_OK;
 }
@@ -389,7 +394,7 @@ namespace {
 
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
-        face_dist, cell_volume, cell_center, patch_kind, patch_state, xv, wv, flags, slot, kin, nkin, newc, nnew, scan,
+        face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, flags, slot, kin, nkin, newc, nnew, scan,
         status, prow, grow, gslot, gcell, ngh, axtab, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
@@ -486,6 +491,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.cell_center = S.take(24 * nc);
     L.patch_kind = S.take(4 * np);
     L.patch_state = S.take(40 * np);
+    L.wallf = S.take(4 * std::max<size_t>(1, m->wall_faces.size()));
     L.xv = S.take(8 * 3 * MAXA);
     L.wv = S.take(8 * 3 * MAXA);
     L.flags = S.take(4 * nc);
@@ -636,6 +642,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(const double *, cell_center, cell_center);
     P(const int32_t *, patch_kind, patch_kind);
     P(const double *, patch_state, patch_state);
+    P(const int32_t *, wall_face, wallf);
+    h.n_wall = (int32_t)m->wall_faces.size();
     P(const double *, xv, xv);
     P(const double *, wv, wv);
     P(int32_t *, flags, flags);
@@ -658,6 +666,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     {
         const char *env = std::getenv("GSIS_SWEEP_ORDER");
         h.order = env ? std::atoi(env) : 0;
+        const char *genv = std::getenv("GSIS_SWEEP_GROUP");
+        h.group = genv ? std::max(1, std::atoi(genv)) : 256;
     }
     P(ParamRec *, param, param);
     P(FeqRec *, feq, feq);
@@ -704,6 +714,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(put(L.cell_center, m->cell_center.data(), 24 * nc));
     HIPCHK(put(L.patch_kind, m->patch_kind.data(), 4 * m->n_patches));
     HIPCHK(put(L.patch_state, m->patch_state.data(), 40 * m->n_patches));
+    HIPCHK(put(L.wallf, m->wall_faces.data(), 4 * m->wall_faces.size()));
     HIPCHK(put(L.xv, c->xv, sizeof c->xv));
     HIPCHK(put(L.wv, c->wv, sizeof c->wv));
     HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
@@ -813,6 +824,7 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         // every case sweeps its own f^n buffer (cur) into the other one
         for (int j = 0; j < m; ++j) b.cur[j] = cases[i0 + j]->cur;
         b.order = cases[i0]->hv.order;
+        b.group = cases[i0]->hv.group;
         if (timed && i0 == 0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
         HIPCHK(launch_sweep(b, cases[i0]->hv, b.start[m], s));
         if (timed && i0 + MAX_BATCH >= n) HIPCHK(hipEventRecord(cases[0]->ev1, s));
@@ -1144,6 +1156,26 @@ extern "C" gsis_status gsis_correct(gsis_case c, const double *W_new, void *stre
     HIPCHK(launch_correct(c->cv, h, c->n_kin, c->cur, s));
     HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
     HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_n_wall_faces(gsis_case c, int32_t *n_wall)
+{
+    if (!c || !n_wall) return fail(GSIS_E_ARG, "null argument");
+    *n_wall = (int32_t)c->mesh->wall_faces.size();
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_surface(gsis_case c, int32_t *face_dev, double *out, double *totals, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!out) return fail(GSIS_E_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    CaseView &h = c->hv;
+    if (face_dev && h.n_wall > 0)
+        HIPCHK(hipMemcpyAsync(face_dev, h.wall_face, 4 * (size_t)h.n_wall, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_surface(c->cv, h, c->cur, out, totals, s));
     return GSIS_OK;
 }
 

@@ -92,6 +92,8 @@ struct CaseView {
     const double *cell_center;  // [n_cells][3]
     const int32_t *patch_kind;
     const double *patch_state;  // [n_patches][5]
+    const int32_t *wall_face;   // [n_wall] boundary faces on diffuse walls, ascending id
+    int32_t n_wall, pad_w;
     const double *xv;           // [3][MAXA] nodes
     const double *wv;           // [3][MAXA] weights
     // region
@@ -114,7 +116,9 @@ struct CaseView {
     // case dtype: offsets c, Gaussian factors E, fix-up parts P, Shakhov parts K
     // (each [NA]), then the x axis' low parts (5 nx); tabp elements per slot
     void *axtab;
-    int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major
+    int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major,
+                                // 2 = groups of `group` cells, tile-major inside a group
+    int32_t group, pad_g;
     // kinetic state
     void *f[2];                 // VDF double buffer [capacity][row]
     ParamRec *param;            // [capacity]
@@ -146,7 +150,9 @@ struct Batch {
     int32_t mdiv;                   // plane kernel, 3D: gcd over the cases of the y-values per lane
                                     // and plane, M = n_y n_z / 256 (load rounds must divide it)
     int32_t cur[MAX_BATCH];         // per case: the buffer holding f^n (the sweep writes the other)
-    int32_t order;                  // 0: blocks tile-major, 1: cell-major (all tiles of a cell together)
+    int32_t order;                  // 0: blocks tile-major, 1: cell-major (all tiles of a cell together),
+                                    // 2: groups of `group` consecutive cells, tile-major inside each group
+    int32_t group;
 };
 
 // Cases of one batched macroscopic launch: each case owns whole blocks
@@ -209,6 +215,8 @@ hipError_t launch_get_flags(const CaseView *cv, const CaseView &h, uint8_t *flag
 hipError_t launch_moments_out(const CaseView *cv, const CaseView &h, int n_kin, double *out, int32_t *kc,
                               hipStream_t s);
 hipError_t launch_W_from_mom(const CaseView *cv, const CaseView &h, int n_kin, double *W, hipStream_t s);
+// surface quantities of the wall faces (GSIS_NSURF per face) and optional totals
+hipError_t launch_surface(const CaseView *cv, const CaseView &h, int cur, double *out, double *totals, hipStream_t s);
 hipError_t launch_check_W(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s);
 
 }  // namespace gsis

@@ -603,6 +603,154 @@ hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, 
 }
 
 // ---------------------------------------------------------------------------
+// surface quantities on the diffuse walls (Sec. 4.2/4.3): one block per wall
+// face.  Kinetic wall cell: incoming velocities (c.n > 0, c = xi - u_w) from
+// the cell's VDF, reflected ones from rho_w M(1, u_w, T_w) with rho_w from
+// zero net mass flux; FP64 sums per thread, then a fixed-order block tree.
+// NS wall cell: pressure plus the NSF stress and heat flux of the one-sided
+// wall gradients (the wall flux of the synthetic solve).
+// ---------------------------------------------------------------------------
+constexpr int NSS = 10;   // incoming: a f, c (c.n) f (3), (c.n) e f; reflected: |a| M, c (c.n) M (3), (c.n) e M
+
+template <class T>
+__global__ __launch_bounds__(256) void k_surface(const CaseView *__restrict__ cvp, int cur, double *__restrict__ out)
+{
+    const CaseView &C = *cvp;
+    const int j = blockIdx.x;   // grid = n_wall
+    const int f = C.wall_face[j];
+    const int L = C.face_cells[2 * f], p = -1 - C.face_cells[2 * f + 1];
+    const double *ps = C.patch_state + 5 * p;
+    const double *n = C.face_normal + 3 * (size_t)f;
+    const int slot = C.slot_of_cell[L];
+    double *o = out + (size_t)j * GSIS_NSURF;
+    if (slot < 0) {
+        if (threadIdx.x != 0) return;
+        const double *PL = C.W + 5 * (size_t)L;
+        const double dn = 0.5 * C.face_dist[f];
+        const double *gL = C.grad + (size_t)L * 18;
+        double G[4][3];
+        for (int v = 0; v < 4; ++v) {
+            double gn = gL[3 * v] * n[0] + gL[3 * v + 1] * n[1] + gL[3 * v + 2] * n[2];
+            double fl = (v < 3) ? PL[1 + v] : PL[4];
+            double jump = (ps[1 + v] - fl) / dn;
+            for (int d = 0; d < 3; ++d) G[v][d] = gL[3 * v + d] + (jump - gn) * n[d];
+        }
+        double Gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+        double sg[6], q[3];
+        nsf(C, ps[4], Gu, G[3], sg, q);
+        const double pL = PL[0] * PL[4];
+        double tau[3] = {pL * n[0] + sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2],
+                         pL * n[1] + sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                         pL * n[2] + sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+        const double pn = tau[0] * n[0] + tau[1] * n[1] + tau[2] * n[2];
+        for (int d = 0; d < 3; ++d) {
+            o[d] = tau[d];
+            o[4 + d] = tau[d] - pn * n[d];
+        }
+        o[3] = pn;
+        o[7] = q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+        o[8] = 0.0;
+        return;
+    }
+    const int vd = C.vdim;
+    const int nvp = C.row / C.nfun;
+    const T *row = (const T *)C.f[cur] + (size_t)slot * C.row;
+    const double Tw = ps[4], it = 1.0 / Tw;
+    const double amp = (vd == 3) ? pow(M_PI * Tw, -1.5) : 1.0 / (M_PI * Tw);
+    double acc[NSS];
+    for (int a = 0; a < NSS; ++a) acc[a] = 0.0;
+    for (int k = threadIdx.x; k < C.nv; k += 256) {
+        int ix, iy, iz = 0;
+        if (vd == 3) {
+            iz = k % C.n[2];
+            iy = (k / C.n[2]) % C.n[1];
+            ix = k / (C.n[2] * C.n[1]);
+        } else {
+            iy = k % C.n[1];
+            ix = k / C.n[1];
+        }
+        const double w = C.wv[ix] * C.wv[MAXA + iy] * ((vd == 3) ? C.wv[2 * MAXA + iz] : 1.0);
+        double c[3] = {C.xv[ix] - ps[1], C.xv[MAXA + iy] - ps[2], (vd == 3) ? C.xv[2 * MAXA + iz] - ps[3] : 0.0};
+        const double a = c[0] * n[0] + c[1] * n[1] + c[2] * n[2];
+        const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        if (a > 0.0) {
+            const double f0 = (double)row[k];
+            const double e = (vd == 3) ? c2 * f0 : c2 * f0 + (double)row[nvp + k];
+            acc[0] += w * a * f0;
+            for (int d = 0; d < 3; ++d) acc[1 + d] += w * a * c[d] * f0;
+            acc[4] += w * a * e;
+        } else if (a < 0.0) {
+            const double m = amp * exp(-c2 * it);
+            const double e = (vd == 3) ? c2 * m : (c2 + 0.5 * Tw) * m;
+            acc[5] -= w * a * m;
+            for (int d = 0; d < 3; ++d) acc[6 + d] += w * a * c[d] * m;
+            acc[9] += w * a * e;
+        }
+    }
+    __shared__ double lds[4][NSS];
+    for (int a = 0; a < NSS; ++a) {
+        double v = acc[a];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6][a] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double S[NSS];
+    for (int a = 0; a < NSS; ++a) S[a] = ((lds[0][a] + lds[1][a]) + lds[2][a]) + lds[3][a];
+    const double rw = S[0] / S[5];
+    double tau[3];
+    for (int d = 0; d < 3; ++d) tau[d] = 2.0 * (S[1 + d] + rw * S[6 + d]);
+    const double pn = tau[0] * n[0] + tau[1] * n[1] + tau[2] * n[2];
+    for (int d = 0; d < 3; ++d) {
+        o[d] = tau[d];
+        o[4 + d] = tau[d] - pn * n[d];
+    }
+    o[3] = pn;
+    o[7] = S[4] + rw * S[9];
+    o[8] = S[0] - rw * S[5];
+}
+
+// integrals sum tau S (3) and sum q S over the wall faces, fixed order
+__global__ __launch_bounds__(256) void k_surface_totals(const CaseView *__restrict__ cvp, const double *__restrict__ out,
+                                                        double *__restrict__ tot)
+{
+    const CaseView &C = *cvp;
+    __shared__ double sm[4][256];
+    double a[4] = {0, 0, 0, 0};
+    for (int j = threadIdx.x; j < C.n_wall; j += 256) {
+        const double S = C.face_area[C.wall_face[j]];
+        const double *o = out + (size_t)j * GSIS_NSURF;
+        a[0] += o[0] * S;
+        a[1] += o[1] * S;
+        a[2] += o[2] * S;
+        a[3] += o[7] * S;
+    }
+    for (int c = 0; c < 4; ++c) sm[c][threadIdx.x] = a[c];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int c = 0; c < 4; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) tot[threadIdx.x] = sm[threadIdx.x][0];
+}
+
+hipError_t launch_surface(const CaseView *cv, const CaseView &h, int cur, double *out, double *totals, hipStream_t s)
+{
+    if (h.n_wall <= 0) {
+        if (totals) return hipMemsetAsync(totals, 0, 4 * sizeof(double), s);
+        return hipSuccess;
+    }
+    // one-sided wall gradients of the NS wall cells come from the current W
+    hipError_t e = launch_lsq(cv, h, h.W, 4, s);
+    if (e != hipSuccess) return e;
+    if (h.dtype == GSIS_F32) hipLaunchKernelGGL(k_surface<float>, dim3(h.n_wall), dim3(256), 0, s, cv, cur, out);
+    else hipLaunchKernelGGL(k_surface<double>, dim3(h.n_wall), dim3(256), 0, s, cv, cur, out);
+    if (totals) hipLaunchKernelGGL(k_surface_totals, dim3(1), dim3(256), 0, s, cv, (const double *)out, totals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // convergence measure (Sec. 4): eps_W = sqrt(sum (W^n - W^{n-1})^2 V / sum (W^{n-1})^2 V)
 // for W in {rho, u (vector), T}; block partials then one fixed-order pass
 // ---------------------------------------------------------------------------

@@ -203,7 +203,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
     const int item = b - B.start[ci];
     const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
     int vt, t;
-    if (B.order) {   // cell-major: the tiles of one cell are consecutive
+    if (B.order == 2) {   // groups of G consecutive cells, tile-major inside a group
+        const int G = B.group;
+        const int gi = item / (G * C.ntile);
+        const int r = item - gi * G * C.ntile;
+        const int gc = min(G, n_kin - gi * G);
+        vt = r / gc;
+        t = gi * G + (r - vt * gc);
+    } else if (B.order) {   // cell-major: the tiles of one cell are consecutive
         t = item / C.ntile;
         vt = item - t * C.ntile;
     } else {         // tile-major

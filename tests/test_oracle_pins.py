@@ -381,6 +381,157 @@ def test_free_molecular_fourier(oracle_mod):
 
 
 # ---------------------------------------------------------------------------
+# surface quantities (Sec. 4.2/4.3): stress, pressure, heat flux on the walls
+# ---------------------------------------------------------------------------
+def _wall_side(m, faces):
+    """+1 for a wall face whose normal points along +x, -1 along -x."""
+    return np.sign(m["face_normal"][faces, 0])
+
+
+@pytest.mark.parametrize("vdim", [3, 2])
+def test_surface_global_maxwellian(oracle_mod, vdim):
+    """Gas at rest in equilibrium with its walls: the stress on every wall face is
+    the pressure rho T along the normal (P = rho T I in units rho0 R T0), no
+    shear, no heat flux, no mass flux -- on kinetic and on NS wall cells."""
+    if vdim == 3:
+        m = gi.couette_1d(6, wall_speed=0.0)
+        g = gi.velocity_grid(3, 24, 6.0)
+    else:
+        m = gi.quad_cavity_2d(5, 4, lid_speed=0.0)
+        g = gi.velocity_grid(2, 28, 6.0, "stretched")
+    O = oracle_mod.Oracle(m, g, Kn=0.1)
+    nc = m["n_cells"]
+    rho, T = 1.3, 1.0
+    f = np.stack([O.maxwellian(rho, [0, 0, 0], T)] * nc)
+    W = gi.uniform_W(nc, rho=rho, T=T)
+    for slot in (np.arange(nc), -np.ones(nc, np.int64)):
+        faces, out = O.surface(f, slot, W)
+        assert len(faces) > 0
+        n = m["face_normal"][faces]
+        # quadrature error of the second moment: ~1e-10 on the stretched 28-node axis
+        assert np.abs(out[:, 3] / (rho * T) - 1).max() < 1e-9
+        assert np.abs(out[:, 0:3] - rho * T * n).max() < 1e-9
+        assert np.abs(out[:, 4:7]).max() < 1e-12
+        assert np.abs(out[:, 7]).max() < 1e-12
+        assert np.abs(out[:, 8]).max() < 1e-13
+
+
+def test_surface_free_molecular_couette(oracle_mod):
+    """Discrete steady free-molecular Couette flow: the wall shear equals the
+    gas shear stress sigma_xy (P_xy is uniform and u_x = 0), with opposite signs
+    on the two walls; the lab-frame energy flux into the walls, q + u_w.tau,
+    sums to zero; the continuous closed form sigma_xy = -2 U / sqrt(pi) holds to
+    the half-range quadrature error of 16 nodes."""
+    U, n = 0.1, 16
+    m = gi.couette_1d(n, wall_speed=U)
+    O = oracle_mod.Oracle(m, gi.velocity_grid(3, 16, 5.0), Kn=1e14)
+    f = np.stack([O.maxwellian(1.0, [0, 0, 0], 1.0)] * n)
+    kin = np.arange(n)
+    for _ in range(n + 2):
+        f = O.sweep(f, kin, kin)
+    mom = O.moments(f)
+    W = np.concatenate([mom[:, :5]], 1)
+    faces, out = O.surface(f, kin, W)
+    side = _wall_side(m, faces)
+    R, L = np.nonzero(side > 0)[0][0], np.nonzero(side < 0)[0][0]
+    sxy = mom[0, 8]
+    assert abs(out[R, 1] / sxy - 1) < 1e-10
+    assert abs(out[L, 1] / -sxy - 1) < 1e-10
+    assert abs(out[R, 1] / (-2 * U / math.sqrt(math.pi)) - 1) < 0.05
+    assert abs(out[R, 3] / out[L, 3] - 1) < 1e-12
+    uw = np.array([m["patches"][-1 - m["face_cells"][fi, 1]]["u"] for fi in faces])
+    e_lab = out[:, 7] + np.sum(uw * out[:, 0:3], axis=1)
+    assert abs(e_lab.sum()) < 1e-12 * np.abs(out[:, 7]).max()
+    assert np.abs(out[:, 8]).max() < 1e-14
+
+
+def test_surface_free_molecular_fourier(oracle_mod):
+    """Discrete steady free-molecular Fourier flow between stationary walls: the
+    heat into the cold wall equals the gas heat flux q_x and leaves the hot
+    wall (sum zero); against the continuous closed form
+    q = n_L sqrt(T_L)(T_L - T_R)/sqrt(pi) to the quadrature error."""
+    TL, TR, n = 1.0, 1.5, 12
+    m = gi.fourier_1d(n, TL, TR)
+    O = oracle_mod.Oracle(m, gi.velocity_grid(3, (96, 16, 16), (8.0, 6.0, 6.0)), Kn=1e14)
+    f = np.stack([O.maxwellian(1.0, [0, 0, 0], 1.0)] * n)
+    kin = np.arange(n)
+    for _ in range(n + 2):
+        f = O.sweep(f, kin, kin)
+    mom = O.moments(f)
+    faces, out = O.surface(f, kin, mom[:, :5])
+    side = _wall_side(m, faces)
+    R, L = np.nonzero(side > 0)[0][0], np.nonzero(side < 0)[0][0]
+    qx = mom[0, 11]
+    assert qx < 0      # heat flows from the hot right wall to the cold left wall
+    assert abs(out[L, 7] / -qx - 1) < 1e-10
+    assert abs(out[R, 7] / qx - 1) < 1e-10
+    assert abs(out[L, 7] + out[R, 7]) < 1e-12 * abs(qx)
+    xi, w = O.xi, O.w
+    pos, neg = xi[:, 0] > 0, xi[:, 0] < 0
+    wn = w * np.abs(xi[:, 0])
+    M0, ML = gauss(xi, 1.0, [0, 0, 0], 1.0), gauss(xi, 1.0, [0, 0, 0], TL)
+    nL = np.sum(wn[neg] * M0[neg]) / np.sum(wn[pos] * ML[pos])
+    qcf = nL * math.sqrt(TL) * (TL - TR) / math.sqrt(math.pi)
+    assert abs(out[R, 7] / qcf - 1) < 5e-3
+
+
+def test_surface_reduced_equals_3d(oracle_mod):
+    """Reduced 2D surface sums (phi, psi and the reduced wall Maxwellian) equal
+    the 3D sums of the same distribution integrated over xi_z, on walls with a
+    tangential velocity and a temperature of their own."""
+    g2 = gi.velocity_grid(2, 24, 6.0, "stretched")
+    g3 = _grid3_from2(g2)
+    m = gi.couette_1d(3, wall_speed=0.2)
+    for p in m["patches"]:
+        p["T"] = 1.2 if p["u"][1] > 0 else 0.9
+    O2 = oracle_mod.Oracle(m, g2, Kn=0.1)
+    O3 = oracle_mod.Oracle(m, g3, Kn=0.1)
+    rng = gi.rng_of(3)
+    f3 = []
+    for i in range(3):
+        mom = np.zeros(14)
+        mom[0], mom[1], mom[2], mom[4] = 1.0 + 0.2 * i, 0.1 * rng.standard_normal(), 0.1, 1.1 + 0.1 * i
+        mom[8], mom[11], mom[12] = 0.03, 0.05 * rng.standard_normal(), -0.02
+        f3.append(O3.g13(mom))
+    f3 = np.stack(f3)
+    f2 = np.stack([_reduce(O3, r[0]) for r in f3])
+    W = gi.uniform_W(3)
+    kin = np.arange(3)
+    faces2, o2 = O2.surface(f2, kin, W)
+    faces3, o3 = O3.surface(f3, kin, W)
+    assert np.array_equal(faces2, faces3)
+    sel = [0, 1, 3, 4, 5, 7, 8]
+    assert np.abs(o2[:, sel] - o3[:, sel]).max() < 1e-10 * np.abs(o3[:, sel]).max()
+
+
+def test_surface_ns_wall_linear_fields(oracle_mod):
+    """NS wall cells: with u_y and T linear in x and the walls at the end values,
+    the one-sided wall gradients are exact, so the wall shear is the Newton
+    stress -(2 Kn/sqrt(pi)) T_w^omega du_y/dx n_x and the heat into the wall is
+    the Fourier flux (5 Kn/(2 sqrt(pi) Pr)) T_w^omega dT/dx (-n_x)."""
+    n, a, b, Kn = 10, 0.3, 0.4, 0.05
+    m = gi.couette_1d(n, wall_speed=0.5 * a)
+    for p in m["patches"]:
+        x0 = 0.0 if p["u"][1] < 0 else 1.0
+        p["T"] = 1.0 + b * x0
+    x = m["cell_center"][:, 0]
+    W = np.zeros((n, 5))
+    W[:, 0] = 1.0
+    W[:, 2] = a * (x - 0.5)
+    W[:, 4] = 1.0 + b * x
+    O = oracle_mod.Oracle(m, gi.velocity_grid(3, 8, 5.0), Kn=Kn)
+    faces, out = O.surface(np.zeros((n, 1, O.nv)), -np.ones(n, np.int64), W)
+    side = _wall_side(m, faces)
+    for j, fi in enumerate(faces):
+        Tw = m["patches"][-1 - m["face_cells"][fi, 1]]["T"]
+        mu = Tw ** 0.5
+        L = m["face_cells"][fi, 0]
+        assert abs(out[j, 1] - (-(2 * Kn / math.sqrt(math.pi)) * mu * a * side[j])) < 1e-12
+        assert abs(out[j, 7] - (-(5 * Kn / (2 * math.sqrt(math.pi) * (2.0 / 3.0))) * mu * b * side[j])) < 1e-12
+        assert abs(out[j, 3] - W[L, 0] * W[L, 4]) < 1e-12
+
+
+# ---------------------------------------------------------------------------
 # P10: least squares, Kn_Gll, compaction
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("make", [lambda: gi.quad_cavity_2d(6, 5), lambda: gi.cylinder_tri_2d(n_theta=40, n_rings=10)])
