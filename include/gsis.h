@@ -146,7 +146,8 @@ gsis_status gsis_set_state(gsis_case c, const double *W_dev, const void *vdf_dev
 gsis_status gsis_kinetic_sweep(gsis_case const *cases, int32_t n_cases, int32_t n_sweeps, void *stream);
 
 /* Moments of the current VDF (Sec. 2 eq. getmoment): out_dev [n_kin][14]
- * FP64 in ascending cell id; kin_cell_dev [n_kin] int32 (nullable). */
+ * FP64 in ascending cell id (may be null when there is no kinetic cell);
+ * kin_cell_dev [n_kin] int32 (nullable). */
 gsis_status gsis_moments(gsis_case c, double *out_dev, int32_t *kin_cell_dev, void *stream);
 
 /* Number of kinetic cells (host; no synchronisation). */
@@ -211,7 +212,7 @@ gsis_status gsis_ns_init(gsis_case const *cases, int32_t n_cases, const gsis_sol
 gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p, gsis_solve_result *r, void *stream);
 
 /* Copy the VDF of the kinetic cells, rows [n_kin][nfun][nv] in the case
- * dtype, ascending cell id. */
+ * dtype, ascending cell id (out_dev may be null when there is no kinetic cell). */
 gsis_status gsis_get_vdf(gsis_case c, void *out_dev, void *stream);
 
 /* Copy W [n_cells][5] FP64 and flags [n_cells] uint8 (either nullable). */

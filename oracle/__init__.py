@@ -253,13 +253,25 @@ class Oracle:
             out[i, 6:] = q
         return out
 
+    G13_RMAX = 0.5
+
     def ghost_params(self, W, grad=None):
-        """Grad-13 parameters (rho, u, T, sigma_NSF, q_NSF) per cell (Sec. 3.2)."""
+        """Grad-13 parameters (rho, u, T, sigma_NSF, q_NSF) per cell (Sec. 3.2).
+
+        Reading: the Grad expansion is used inside its range of validity.  With
+        r = max(max_ij |sigma_ij| / p, |q| / (p sqrt(T))), p = rho T, the pair
+        (sigma, q) is scaled by min(1, 0.5 / r), so that the polynomial factor
+        of the Grad-13 distribution stays of order one at thermal speeds (an
+        unlimited one from a strongly sheared NS field is negative over much
+        of velocity space)."""
         nsf = self.nsf_field(W, grad)
+        p = W[:, 0] * W[:, 4]
+        r = np.maximum(np.abs(nsf[:, :6]).max(axis=1) / p, np.linalg.norm(nsf[:, 6:9], axis=1) / (p * np.sqrt(W[:, 4])))
+        theta = np.where(r > self.G13_RMAX, self.G13_RMAX / np.where(r > 0, r, 1.0), 1.0)
         gh = np.zeros((len(W), NMOM))
         gh[:, 0:5] = W
-        gh[:, 5:11] = nsf[:, :6]
-        gh[:, 11:14] = nsf[:, 6:]
+        gh[:, 5:11] = nsf[:, :6] * theta[:, None]
+        gh[:, 11:14] = nsf[:, 6:] * theta[:, None]
         if self.vdim == 2:
             gh[:, 3] = 0.0
             gh[:, 9:11] = 0.0
@@ -618,7 +630,7 @@ class SteadySolver:
         self.W = W_new
         self.it += 1
         self.last_mom = mom_half
-        if self.mode == "agsis" and self.it % self.region_every == 0:
+        if self.mode == "agsis" and self.region_every > 0 and self.it % self.region_every == 0:
             self.update_regions()
         return eps
 

@@ -668,6 +668,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
         h.order = env ? std::atoi(env) : 0;
         const char *genv = std::getenv("GSIS_SWEEP_GROUP");
         h.group = genv ? std::max(1, std::atoi(genv)) : 256;
+        const char *renv = std::getenv("GSIS_SWEEP_ROT");
+        h.rot = renv ? std::max(0, std::atoi(renv)) : 0;
     }
     P(ParamRec *, param, param);
     P(FeqRec *, feq, feq);
@@ -825,6 +827,7 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         for (int j = 0; j < m; ++j) b.cur[j] = cases[i0 + j]->cur;
         b.order = cases[i0]->hv.order;
         b.group = cases[i0]->hv.group;
+        b.rot = cases[i0]->hv.rot;
         if (timed && i0 == 0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
         HIPCHK(launch_sweep(b, cases[i0]->hv, b.start[m], s));
         if (timed && i0 + MAX_BATCH >= n) HIPCHK(hipEventRecord(cases[0]->ev1, s));
@@ -900,7 +903,7 @@ extern "C" gsis_status gsis_moments(gsis_case c, double *out, int32_t *kc, void 
 {
     gsis_status st = check_ready(c);
     if (st) return st;
-    if (!out) return fail(GSIS_E_ARG, "null output");
+    if (!out && c->n_kin > 0) return fail(GSIS_E_ARG, "null output");
     HIPCHK(launch_moments_out(c->cv, c->hv, c->n_kin, out, kc, (hipStream_t)stream));
     return GSIS_OK;
 }
@@ -909,7 +912,7 @@ extern "C" gsis_status gsis_get_vdf(gsis_case c, void *out, void *stream)
 {
     gsis_status st = check_ready(c);
     if (st) return st;
-    if (!out) return fail(GSIS_E_ARG, "null output");
+    if (!out && c->n_kin > 0) return fail(GSIS_E_ARG, "null output");
     HIPCHK(launch_gather_vdf(c->cv, c->hv, c->n_kin, c->cur, out, 0, (hipStream_t)stream));
     return GSIS_OK;
 }

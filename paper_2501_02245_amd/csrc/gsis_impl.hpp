@@ -118,7 +118,7 @@ struct CaseView {
     void *axtab;
     int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major,
                                 // 2 = groups of `group` cells, tile-major inside a group
-    int32_t group, pad_g;
+    int32_t group, rot;
     // kinetic state
     void *f[2];                 // VDF double buffer [capacity][row]
     ParamRec *param;            // [capacity]
@@ -153,6 +153,7 @@ struct Batch {
     int32_t order;                  // 0: blocks tile-major, 1: cell-major (all tiles of a cell together),
                                     // 2: groups of `group` consecutive cells, tile-major inside each group
     int32_t group;
+    int32_t rot;                    // plane kernel: start plane advances every `rot` blocks per XCD (0: plane 0)
 };
 
 // Cases of one batched macroscopic launch: each case owns whole blocks

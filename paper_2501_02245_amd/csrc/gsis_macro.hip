@@ -201,6 +201,8 @@ __device__ __forceinline__ void cell_nsf(const CaseView &C, int i, double T, dou
 }
 
 // Grad-13 parameters of every cell from W and the gradients of W
+constexpr double G13_RMAX = 0.5;
+
 __global__ void k_ghost(const CaseView *__restrict__ cvp, const double *__restrict__ W)
 {
     const CaseView &C = *cvp;
@@ -211,8 +213,15 @@ __global__ void k_ghost(const CaseView *__restrict__ cvp, const double *__restri
     for (int c = 0; c < 5; ++c) g[c] = Wi[c];
     double s[6], q[3];
     cell_nsf(C, i, Wi[4], s, q);
-    for (int c = 0; c < 6; ++c) g[5 + c] = s[c];
-    for (int c = 0; c < 3; ++c) g[11 + c] = q[c];
+    // Grad expansion inside its range: (sigma, q) scaled by min(1, 0.5 / r),
+    // r = max(max |sigma_ij| / p, |q| / (p sqrt T)), p = rho T
+    const double p = Wi[0] * Wi[4];
+    double smax = 0.0;
+    for (int c = 0; c < 6; ++c) smax = fmax(smax, fabs(s[c]));
+    const double r = fmax(smax / p, sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (p * sqrt(Wi[4])));
+    const double th = (r > G13_RMAX) ? G13_RMAX / r : 1.0;
+    for (int c = 0; c < 6; ++c) g[5 + c] = s[c] * th;
+    for (int c = 0; c < 3; ++c) g[11 + c] = q[c] * th;
     if (C.vdim == 2) {
         g[3] = 0.0;
         g[9] = g[10] = 0.0;

@@ -22,9 +22,26 @@
 // per cell; absent faces read the cell's own row with a zero normal.
 #include <math.h>
 
+#include <algorithm>
+#include <cstdlib>
+#include <type_traits>
+
 #include "gsis_impl.hpp"
 
 namespace gsis {
+
+// waves per SIMD the plane sweep is compiled for (caps its VGPRs at 512 / SWEEP_WAVES)
+#ifndef SWEEP_WAVES
+#define SWEEP_WAVES 4
+#endif
+#ifndef CORRECT_WAVES
+#define CORRECT_WAVES 4
+#endif
+// largest points per load round of the correction (two planes per pass)
+#ifndef CORRECT_UMAX
+#define CORRECT_UMAX 2
+#endif
+
 
 namespace {
 
@@ -38,6 +55,29 @@ __device__ __forceinline__ int xcd_remap2(int b, int nb)
     const int X = 8;
     int x = b % X, r = b / X, q = nb / X, rem = nb % X;
     return x * q + min(x, rem) + r;
+}
+
+// a wave-uniform pointer held in SGPRs (the value is the same in every lane)
+template <typename P>
+__device__ __forceinline__ P uniform_ptr(P p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P)(((uint64_t)hi << 32) | lo);
+}
+
+// loads and stores at a 32-bit byte offset from a wave-uniform base (the
+// SGPR-base, VGPR-offset addressing form: no 64-bit address arithmetic per access)
+template <typename T>
+__device__ __forceinline__ T ldb(gcptr<T> p, uint32_t off)
+{
+    return *(gcptr<T>)((const __attribute__((address_space(1))) char *)p + off);
+}
+template <typename T>
+__device__ __forceinline__ void stb(gptr<T> p, uint32_t off, T v)
+{
+    *(gptr<T>)((__attribute__((address_space(1))) char *)p + off) = v;
 }
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -190,7 +230,7 @@ __device__ __forceinline__ void finish_partials(const PlaneSums<T> &S, const T (
 }  // namespace
 
 template <typename T, int VD, int NF, int U>
-__global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES))) void k_sweep_fast(Batch B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
 
@@ -305,70 +345,96 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
 
     if (VD == 3) {
         // ---- 3D: lanes own z = ilc; loop x-planes, then the M y-values ----
+        // Node k = (ix ny + iy) nz + ilc with iy = yq + m q and q nz = BLOCK, so
+        // k = ix ny nz + tid + m BLOCK: every row is addressed by one 32-bit
+        // byte offset per round from a wave-uniform base (point u of the round
+        // at +u BLOCK elements).
         const int q = BLOCK / nz;
         const int M = ny / q;
         const int yq = threadIdx.x / nz;
         const int ix0 = vt * C.xp, ix1 = min(ix0 + C.xp, nx);
-        for (int ix = ix0; ix < ix1; ++ix) {
-            const T cx = rc[ix], Ex = rE[ix], Px = rP[ix], Kx = rK[ix], wx = rw[ix];
-            const T Exz = Ex * EL, Pxz = Px + PL, Kxz = Kx + KL, cxz2 = cx * cx + cL * cL;
-            T Ax[NF];
+        const uint32_t plane_bytes = (uint32_t)(ny * nz * sizeof(T));
+        const uint32_t lane_bytes = (uint32_t)(threadIdx.x * sizeof(T));
+        constexpr uint32_t ustep = BLOCK * sizeof(T);
+        // the diagonal 1/dt + 1/tau + sum_{a>0} a is written 1/dt + 1/tau - sum_{a<0} a
+        // (the cell is closed: sum_l n_l S_l = 0)
+        const T den0 = itau + idt;
+        gcptr<T> fo_u = uniform_ptr(fo);
+        gptr<T> fn_u = uniform_ptr(fn);
+        gcptr<T> fnb_u[NF];
 #pragma unroll
-            for (int l = 0; l < NF; ++l) Ax[l] = fnx[l] * cx + AL[l];
-            T T0 = 0, T1 = 0, T2 = 0, T3 = 0, Z0 = 0, Z1 = 0, Z2 = 0;   // this plane
-            int iy = yq;
-            int k = (ix * ny + iy) * nz + ilc;
-            const int kstep = q * nz;
-            // U points per round (U divides M): every load of the round is in
-            // flight before the first is consumed
-            for (int m = 0; m < M; m += U, iy += U * q, k += U * kstep) {
-                T o[U], v[U][NF];
+        for (int l = 0; l < NF; ++l) fnb_u[l] = uniform_ptr(fnb[l]);
+        auto planes = [&](auto walls) {
+            constexpr bool WALLS = decltype(walls)::value;
+            for (int ix = ix0; ix < ix1; ++ix) {
+                const T cx = rc[ix], wx = rw[ix];
+                const T Exz = itau * rE[ix] * EL, Pxz = rP[ix] + PL, Kxz = rK[ix] + KL;
+                const T Axz = (cx * cx + cL * cL) * it - shift0;
+                T Ax[NF];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    o[u] = fo[k + u * kstep];
+                for (int l = 0; l < NF; ++l) Ax[l] = fnx[l] * cx + AL[l];
+                T T0 = 0, T1 = 0, T2 = 0, T3 = 0, Z0 = 0, Z1 = 0, Z2 = 0;   // this plane
+                uint32_t off = ix * plane_bytes + lane_bytes;
+                int jy0 = nx + yq;
+                for (int m = 0; m < M; m += U, off += U * ustep, jy0 += U * q) {
+                    // every load of the round is in flight before the first is consumed
+                    T o[U], v[U][NF];
 #pragma unroll
-                    for (int l = 0; l < NF; ++l) v[u][l] = fnb[l][k + u * kstep];
-                }
+                    for (int u = 0; u < U; ++u) {
+                        o[u] = ldb(fo_u, off + u * ustep);
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int jy = nx + iy + u * q;
-                    const T cy = rc[jy], Ey = rE[jy], Py = rP[jy], Ky = rK[jy], wy = rw[jy];
-                    const T cc = cy * cy + cxz2;
-                    const T g = Exz * Ey * (Pxz + Py) * ((Kxz + Ky) * (cc * it - shift0) + (T)1);
-                    T num = itau * g + idt * o[u];
-                    T den = itau + idt;
-#pragma unroll
-                    for (int l = 0; l < NF; ++l) {
-                        const T a = fny[l] * cy + Ax[l];
-                        den += fmax(a, (T)0);
-                        num -= fmin(a, (T)0) * fsc[l] * v[u][l];
+                        for (int l = 0; l < NF; ++l) v[u][l] = ldb(fnb_u[l], off + u * ustep);
                     }
-                    const T fnv = num * fast_rcp(den);
-                    fn[k + u * kstep] = fnv;
-                    // moment sums: powers of c_y only
-                    const T w = wx * wy;
-                    const T h = w * fnv;
-                    T0 += h;
-                    const T hy = h * cy;
-                    T1 += hy;
-                    const T hy2 = hy * cy;
-                    T2 += hy2;
-                    T3 += hy2 * cy;
-                    const T r = w * (num - den * o[u]);
-                    Z0 += r;
-                    const T ry = r * cy;
-                    Z1 += ry;
-                    Z2 += ry * cy;
-                    if (nw > 0) {
 #pragma unroll
-                        for (int l = 0; l < NF; ++l)
-                            if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[l], (T)0);
+                    for (int u = 0; u < U; ++u) {
+                        const int jy = jy0 + u * q;
+                        const T cy = rc[jy], Ey = rE[jy], Py = rP[jy], Ky = rK[jy], wy = rw[jy];
+                        // relaxation target (1/tau folded into the x-z factor)
+                        const T g = Exz * Ey * (Pxz + Py) * ((Kxz + Ky) * (Axz + cy * cy * it) + (T)1);
+                        T num = g + idt * o[u];
+                        T den = den0;
+                        T aw[NF];
+#pragma unroll
+                        for (int l = 0; l < NF; ++l) {
+                            const T a = fny[l] * cy + Ax[l];
+                            const T mn = fmin(a, (T)0);
+                            den -= mn;
+                            if constexpr (WALLS) {
+                                aw[l] = a - mn;                      // max(a, 0)
+                                num -= (mn * fsc[l]) * v[u][l];
+                            } else {
+                                num -= mn * v[u][l];
+                            }
+                        }
+                        const T fnv = num * fast_rcp(den);
+                        stb(fn_u, off + u * ustep, fnv);
+                        // moment sums: powers of c_y only
+                        const T w = wx * wy;
+                        const T h = w * fnv;
+                        T0 += h;
+                        const T hy = h * cy;
+                        T1 += hy;
+                        const T hy2 = hy * cy;
+                        T2 += hy2;
+                        T3 += hy2 * cy;
+                        const T r = w * (num - den * o[u]);
+                        Z0 += r;
+                        const T ry = r * cy;
+                        Z1 += ry;
+                        Z2 += ry * cy;
+                        if constexpr (WALLS) {
+#pragma unroll
+                            for (int l = 0; l < NF; ++l)
+                                if (fwall[l] >= 0) Wf[l] += h * aw[l];
+                        }
                     }
                 }
+                S.fold(cx, rlo[ix], rlo[nx + ix], rlo[2 * nx + ix], rlo[3 * nx + ix], rlo[4 * nx + ix], T0, T1, T2,
+                       T3, Z0, Z1, Z2);
             }
-            S.fold(cx, rlo[ix], rlo[nx + ix], rlo[2 * nx + ix], rlo[3 * nx + ix], rlo[4 * nx + ix], T0, T1, T2, T3,
-                   Z0, Z1, Z2);
-        }
+        };
+        if (nw > 0) planes(std::true_type{});
+        else planes(std::false_type{});
     } else {
         // ---- reduced 2D: lanes own y = ilc; x varies per step --------------
         const int q = BLOCK / ny;
@@ -457,7 +523,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(Batch B)
 // axis and rounded once.
 // ---------------------------------------------------------------------------
 template <typename T, int VD, int NF, int U>
-__global__ __launch_bounds__(BLOCK) void k_correct_fast(const CaseView *__restrict__ cvp, int n_kin, int cur)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CORRECT_WAVES))) void k_correct_fast(
+    const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const CaseView &C = *cvp;
@@ -545,66 +612,77 @@ __global__ __launch_bounds__(BLOCK) void k_correct_fast(const CaseView *__restri
         const int q = BLOCK / nz;
         const int M = ny / q;
         const int yq = threadIdx.x / nz;
+        // node k = ix ny nz + tid + m BLOCK (q nz = BLOCK): one 32-bit byte
+        // offset per round from the wave-uniform row base
+        gptr<T> fr_u = uniform_ptr(fr);
+        const uint32_t plane_bytes = (uint32_t)(ny * nz * sizeof(T));
+        const uint32_t lane_bytes = (uint32_t)(threadIdx.x * sizeof(T));
+        constexpr uint32_t ustep = BLOCK * sizeof(T);
         // two x-planes per pass: the loads of both planes' rounds are in flight together
-        for (int ix = ix0; ix < ix1; ix += 2) {
-            const int npl = (ix + 1 < ix1) ? 2 : 1;
-            T cx[2], wx[2], Exa[2], Pxa[2], Exb[2], Pxb[2], Ax[2][NF], Tp[2][4];
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const int jx = (p < npl) ? ix + p : ix;
-                cx[p] = rc[jx];
-                wx[p] = rw[jx];
-                Exa[p] = Ea[jx] * EaL;
-                Pxa[p] = Pa[jx] + PaL;
-                Exb[p] = Eb[jx] * EbL;
-                Pxb[p] = Pb[jx] + PbL;
-#pragma unroll
-                for (int l = 0; l < NF; ++l) Ax[p][l] = fnx[l] * cx[p] + AL[l];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Tp[p][c] = (T)0;
-            }
-            const int kstep = q * nz, pstep = ny * nz;
-            int iy = yq;
-            int k = (ix * ny + iy) * nz + ilc;
-            for (int m = 0; m < M; m += U, iy += U * q, k += U * kstep) {
-                T o[2][U];
-#pragma unroll
-                for (int p = 0; p < 2; ++p)
-#pragma unroll
-                    for (int u = 0; u < U; ++u) o[p][u] = (p < npl) ? fr[k + p * pstep + u * kstep] : (T)0;
+        auto planes = [&](auto walls) {
+            constexpr bool WALLS = decltype(walls)::value;
+            for (int ix = ix0; ix < ix1; ix += 2) {
+                const int npl = (ix + 1 < ix1) ? 2 : 1;
+                T cx[2], wx[2], Exa[2], Pxa[2], Exb[2], Pxb[2], Ax[2][NF], Tp[2][4];
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    if (p >= npl) break;
+                    const int jx = (p < npl) ? ix + p : ix;
+                    cx[p] = rc[jx];
+                    wx[p] = rw[jx];
+                    Exa[p] = Ea[jx] * EaL;
+                    Pxa[p] = Pa[jx] + PaL;
+                    Exb[p] = Eb[jx] * EbL;
+                    Pxb[p] = Pb[jx] + PbL;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int jy = nx + iy + u * q;
-                        const T cy = rc[jy];
-                        const T fv =
-                            o[p][u] + (Exa[p] * Ea[jy] * (Pxa[p] + Pa[jy]) - Exb[p] * Eb[jy] * (Pxb[p] + Pb[jy]));
-                        fr[k + p * pstep + u * kstep] = fv;
-                        const T h = wx[p] * rw[jy] * fv;
-                        Tp[p][0] += h;
-                        const T hy = h * cy;
-                        Tp[p][1] += hy;
-                        const T hy2 = hy * cy;
-                        Tp[p][2] += hy2;
-                        Tp[p][3] += hy2 * cy;
-                        if (nw > 0) {
+                    for (int l = 0; l < NF; ++l) Ax[p][l] = fnx[l] * cx[p] + AL[l];
 #pragma unroll
-                            for (int l = 0; l < NF; ++l)
-                                if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[p][l], (T)0);
+                    for (int c = 0; c < 4; ++c) Tp[p][c] = (T)0;
+                }
+                uint32_t off = ix * plane_bytes + lane_bytes;
+                int jy0 = nx + yq;
+                for (int m = 0; m < M; m += U, off += U * ustep, jy0 += U * q) {
+                    T o[2][U];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            o[p][u] = (p < npl) ? ldb(gcptr<T>(fr_u), off + p * plane_bytes + u * ustep) : (T)0;
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        if (p >= npl) break;
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int jy = jy0 + u * q;
+                            const T cy = rc[jy];
+                            const T fv = o[p][u] + (Exa[p] * Ea[jy] * (Pxa[p] + Pa[jy]) -
+                                                    Exb[p] * Eb[jy] * (Pxb[p] + Pb[jy]));
+                            stb(fr_u, off + p * plane_bytes + u * ustep, fv);
+                            const T h = wx[p] * rw[jy] * fv;
+                            Tp[p][0] += h;
+                            const T hy = h * cy;
+                            Tp[p][1] += hy;
+                            const T hy2 = hy * cy;
+                            Tp[p][2] += hy2;
+                            Tp[p][3] += hy2 * cy;
+                            if constexpr (WALLS) {
+#pragma unroll
+                                for (int l = 0; l < NF; ++l)
+                                    if (fwall[l] >= 0) Wf[l] += h * fmax(fny[l] * cy + Ax[p][l], (T)0);
+                            }
                         }
                     }
                 }
-            }
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                if (p >= npl) break;
-                const int jx = ix + p;
-                S.fold(cx[p], rlo[jx], rlo[nx + jx], rlo[2 * nx + jx], rlo[3 * nx + jx], rlo[4 * nx + jx], Tp[p][0],
-                       Tp[p][1], Tp[p][2], Tp[p][3], (T)0, (T)0, (T)0);
+                for (int p = 0; p < 2; ++p) {
+                    if (p >= npl) break;
+                    const int jx = ix + p;
+                    S.fold(cx[p], rlo[jx], rlo[nx + jx], rlo[2 * nx + jx], rlo[3 * nx + jx], rlo[4 * nx + jx],
+                           Tp[p][0], Tp[p][1], Tp[p][2], Tp[p][3], (T)0, (T)0, (T)0);
+                }
             }
-        }
+        };
+        if (nw > 0) planes(std::true_type{});
+        else planes(std::false_type{});
     } else {
         const int q = BLOCK / ny;
         const int xq = threadIdx.x / ny;
@@ -711,7 +789,14 @@ template <typename T, int VD, int U>
 void launch_u(const Batch &b, size_t tab, int total, hipStream_t s)
 {
     const size_t off = red_offset<T>(tab);
-    const size_t l4 = off + red_bytes<T, 4>(), l8 = off + red_bytes<T, MAXF>();
+    size_t l4 = off + red_bytes<T, 4>(), l8 = off + red_bytes<T, MAXF>();
+    // GSIS_SWEEP_LDS: minimum LDS bytes per block (caps the blocks per CU)
+    static const size_t lds_min = [] {
+        const char *e = std::getenv("GSIS_SWEEP_LDS");
+        return e ? (size_t)std::atol(e) : (size_t)0;
+    }();
+    l4 = std::max(l4, lds_min);
+    l8 = std::max(l8, lds_min);
     if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_fast<T, VD, 4, U>), dim3(total), dim3(BLOCK), l4, s, b);
     else hipLaunchKernelGGL((k_sweep_fast<T, VD, MAXF, U>), dim3(total), dim3(BLOCK), l8, s, b);
 }
@@ -765,7 +850,12 @@ void launch_correct_u(const CaseView *cv, const CaseView &h, int n_kin, int cur,
 template <typename T, int VD>
 void launch_correct_t(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
 {
-    const int U = rounds_u(h.vdim, h.n[1] * h.n[2] / BLOCK, sizeof(T), h.nfmax);
+    int U = rounds_u(h.vdim, h.n[1] * h.n[2] / BLOCK, sizeof(T), h.nfmax);
+    static const int umax = [] {
+        const char *e = std::getenv("GSIS_CORRECT_U");
+        return e ? std::atoi(e) : CORRECT_UMAX;
+    }();
+    while (U > 1 && U > umax) U /= 2;
     if (U == 4) launch_correct_u<T, VD, 4>(cv, h, n_kin, cur, s);
     else if (U == 2) launch_correct_u<T, VD, 2>(cv, h, n_kin, cur, s);
     else launch_correct_u<T, VD, 1>(cv, h, n_kin, cur, s);

@@ -101,3 +101,26 @@ def test_product_path_has_no_oracle_or_fallback():
             if fn.endswith((".py", ".cpp", ".hip", ".hpp")):
                 src = open(os.path.join(root, fn)).read()
                 assert "oracle" not in src, fn
+
+
+def test_serving_mix_grids_resolve_the_free_stream():
+    """Every request of the serving mix resolves the unit-temperature Maxwellian
+    of its free stream (cylinder) or moving walls (Couette): node spacing at that
+    speed <= 0.7, so the conservation-fixed Maxwellian stays positive."""
+    import math
+    import oracle
+    a0 = math.sqrt(5.0 / 6.0)
+    for r in gi.serving_requests(24, 20.0, seed=7):
+        x = np.asarray(r["grid"]["nodes"][0])
+        if r["kind"] == "cylinder":
+            u = r["mach"] * a0
+        elif r["kind"] == "couette":
+            u = 0.5 * r["mach"] * a0
+        else:
+            u = 0.0
+        i = int(np.searchsorted(x, u))
+        assert x[i] - x[i - 1] <= 0.7 + 1e-12, (r["rid"], r["kind"], len(x))
+        assert len(x) <= 128
+        O = oracle.Oracle(r["mesh"], r["grid"], r["Kn"])
+        f = O.feq(np.array([1.0, u, 0.0, 0.0, 1.0]))
+        assert f.min() > -1e-8 * f.max(), (r["rid"], f.min() / f.max())

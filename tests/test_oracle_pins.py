@@ -531,6 +531,38 @@ def test_surface_ns_wall_linear_fields(oracle_mod):
         assert abs(out[j, 3] - W[L, 0] * W[L, 4]) < 1e-12
 
 
+def test_grad13_limiter_keeps_rows_positive_near_thermal_speeds(oracle_mod):
+    """Grad-13 parameters from a strongly sheared NS field: after limiting,
+    r = max(|sigma_ij| / p, |q| / (p sqrt T)) is min(r_NSF, 0.5) and the rows are
+    positive at thermal speeds |c| <= sqrt(T); a weak field keeps its NSF
+    values exactly (the limiter is inactive below r = 0.5)."""
+    m = gi.couette_1d(12, wall_speed=0.0)
+    g = gi.velocity_grid(3, 24, 6.0)
+    x = m["cell_center"][:, 0]
+    for amp, Kn in ((3.0, 0.3), (0.02, 0.01)):
+        W = np.zeros((12, 5))
+        W[:, 0] = 1.0
+        W[:, 2] = amp * np.sin(2 * np.pi * x)
+        W[:, 4] = 1.0 + 0.5 * amp * x
+        O = oracle_mod.Oracle(m, g, Kn=Kn)
+        raw = O.nsf_field(W)
+        gh = O.ghost_params(W)
+        p = W[:, 0] * W[:, 4]
+        r_raw = np.maximum(np.abs(raw[:, :6]).max(1) / p, np.linalg.norm(raw[:, 6:], axis=1) / (p * np.sqrt(W[:, 4])))
+        r_lim = np.maximum(np.abs(gh[:, 5:11]).max(1) / p, np.linalg.norm(gh[:, 11:], axis=1) / (p * np.sqrt(W[:, 4])))
+        assert np.all(r_lim <= 0.5 + 1e-12)
+        assert np.allclose(r_lim, np.minimum(r_raw, 0.5), rtol=1e-12, atol=0)
+        if amp < 0.1:
+            assert np.array_equal(gh[:, 5:11], raw[:, :6]) and np.array_equal(gh[:, 11:], raw[:, 6:])
+        else:
+            assert r_raw.max() > 1.0
+            # limited rows: at thermal speeds the Grad polynomial stays positive
+            for i in range(12):
+                row = O.g13(gh[i])[0]
+                c2 = np.sum((O.xi - gh[i, 1:4]) ** 2, axis=1) / gh[i, 4]
+                assert row[c2 <= 1.0].min() > 0
+
+
 # ---------------------------------------------------------------------------
 # P10: least squares, Kn_Gll, compaction
 # ---------------------------------------------------------------------------
