@@ -30,7 +30,8 @@
 
 namespace gsis {
 
-// waves per SIMD the plane sweep is compiled for (caps its VGPRs at 512 / SWEEP_WAVES)
+// waves per SIMD the FP32 plane kernels are compiled for (caps their VGPRs at
+// 512 / waves); the FP64 instantiations are left unconstrained (no spills)
 #ifndef SWEEP_WAVES
 #define SWEEP_WAVES 4
 #endif
@@ -230,7 +231,8 @@ __device__ __forceinline__ void finish_partials(const PlaneSums<T> &S, const T (
 }  // namespace
 
 template <typename T, int VD, int NF, int U>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES))) void k_sweep_fast(Batch B)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? SWEEP_WAVES : 1))) void
+k_sweep_fast(Batch B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
 
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SWEEP_WAV
 // axis and rounded once.
 // ---------------------------------------------------------------------------
 template <typename T, int VD, int NF, int U>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CORRECT_WAVES))) void k_correct_fast(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? CORRECT_WAVES : 1))) void k_correct_fast(
     const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
