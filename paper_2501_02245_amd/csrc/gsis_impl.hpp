@@ -161,6 +161,7 @@ struct Batch {
 // case of a block is block-uniform.
 constexpr int MBLOCK = 256;
 constexpr int MBLOCK_F = 128;
+constexpr int MCELLS_Q = 64;     // cells per block of the lane-per-face kernels
 struct MBatch {
     const CaseView *cv[MAX_BATCH];
     double *W[MAX_BATCH];            // state advanced by the pseudo-time steps
@@ -168,6 +169,7 @@ struct MBatch {
     const double *src[MAX_BATCH];    // [n_cells][5] sources per unit volume, or null
     int32_t bc[MAX_BATCH + 1];       // prefix of cell blocks
     int32_t bf[MAX_BATCH + 1];       // prefix of face blocks
+    int32_t bq[MAX_BATCH + 1];       // prefix of cell-group blocks (MCELLS_Q cells, one lane per face)
     int32_t n;
     int32_t nfmax;
 };

@@ -14,6 +14,7 @@
 // per-cell source.  All reductions are deterministic (fixed
 // order, no floating-point atomics).
 #include <math.h>
+#include <stdlib.h>
 
 #include "gsis_impl.hpp"
 
@@ -63,26 +64,31 @@ struct MLoc {
     int base;   // first block of the case
 };
 
-__device__ __forceinline__ MLoc mb_loc(const MBatch &B, bool faces)
+// block prefix kinds: cells (MBLOCK per block), faces (MBLOCK_F), cell groups (MCELLS_Q)
+enum { PK_CELL = 0, PK_FACE = 1, PK_GROUP = 2 };
+
+__device__ __forceinline__ MLoc mb_loc(const MBatch &B, int kind)
 {
-    const int j = mb_case(faces ? B.bf : B.bc, B.n);
-    return {B.cv[j], B.W[j], B.hot[j], B.src[j], faces ? B.bf[j] : B.bc[j]};
+    const int32_t *pre = (kind == PK_FACE) ? B.bf : ((kind == PK_GROUP) ? B.bq : B.bc);
+    const int j = mb_case(pre, B.n);
+    return {B.cv[j], B.W[j], B.hot[j], B.src[j], pre[j]};
 }
 
-__device__ __forceinline__ MLoc mb_loc(const MOne &B, bool) { return {B.cv, B.W, B.hot, B.src, 0}; }
+__device__ __forceinline__ MLoc mb_loc(const MOne &B, int) { return {B.cv, B.W, B.hot, B.src, 0}; }
 
 static MOne mone_of(const MBatch &b) { return {b.cv[0], b.W[0], b.hot[0], b.src[0]}; }
 
 void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src)
 {
     const int j = b.n;
-    if (j == 0) b.bc[0] = b.bf[0] = 0, b.nfmax = 0;
+    if (j == 0) b.bc[0] = b.bf[0] = b.bq[0] = 0, b.nfmax = 0;
     b.cv[j] = cv;
     b.W[j] = W;
     b.hot[j] = hot;
     b.src[j] = src;
     b.bc[j + 1] = b.bc[j] + (h.n_cells + MBLOCK - 1) / MBLOCK;
     b.bf[j + 1] = b.bf[j] + (h.n_faces + MBLOCK_F - 1) / MBLOCK_F;
+    b.bq[j + 1] = b.bq[j] + (h.n_cells + MCELLS_Q - 1) / MCELLS_Q;
     b.nfmax = (h.nfmax > b.nfmax) ? h.nfmax : b.nfmax;
     b.n = j + 1;
 }
@@ -94,7 +100,7 @@ void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, con
 template <int NV, int NF, class BT>
 __global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
 {
-    const MLoc ML = mb_loc(B, false);
+    const MLoc ML = mb_loc(B, PK_CELL);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
     const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
@@ -147,6 +153,69 @@ __global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
     }
 }
 
+// The same gradients with one lane per face: G lanes (G >= the cell's faces)
+// per cell each gather one neighbour and form its contribution, then the G
+// lanes add theirs in a fixed butterfly order.  Four (eight) times the
+// memory-level parallelism of one thread per cell.
+template <int NV, int G, class BT>
+__global__ __launch_bounds__(MCELLS_Q * G) void k_lsq_q(BT B)
+{
+    const MLoc ML = mb_loc(B, PK_GROUP);
+    const CaseView &C = *ML.cv;
+    const double *__restrict__ W = ML.W;
+    const int i = ((int)blockIdx.x - ML.base) * MCELLS_Q + (int)threadIdx.x / G;
+    const int l = (int)threadIdx.x % G;
+    if (i >= C.n_cells) return;   // whole groups leave together
+    const size_t nnz = (size_t)C.nnz;
+    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
+    const double *Wi = W + 5 * (size_t)i;
+    double g[NV][3];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g[v][0] = g[v][1] = g[v][2] = 0.0;
+    if (l < nf) {
+        const int e = e0 + l;
+        const int oth = C.cf_other[e];
+        const double *ca = C.lsq + 3 * (size_t)e;
+        double c[3] = {ca[0], ca[1], ca[2]}, cr[3] = {0.0, 0.0, 0.0};
+        if (NV > 4)
+            for (int d = 0; d < 3; ++d) cr[d] = ca[3 * nnz + d];
+        bool wall = false;
+        double fo[NV];
+        if (oth >= 0) {
+            const double *Wo = W + 5 * (size_t)oth;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fo[v] = field(Wo, v);
+        } else {
+            const int p = -1 - oth;
+            wall = C.patch_kind[p] == GSIS_PATCH_WALL;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fo[v] = (v == 4 && wall) ? 0.0 : bfield(C, p, v);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            if (v == 4 && wall) continue;
+            const double d = fo[v] - field(Wi, v);
+            const double *cc = (v == 4) ? cr : c;
+            g[v][0] = cc[0] * d;
+            g[v][1] = cc[1] * d;
+            g[v][2] = cc[2] * d;
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[v][d] += __shfl_xor(g[v][d], off, G);
+    // every lane holds the sums: lane l writes the variables v = l (mod G)
+    double *go = C.grad + (size_t)i * 18;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        if (v % G == l)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) go[3 * v + d] = g[v][d];
+}
+
 template <class BT>
 static void launch_lsq_t(const BT &b, dim3 g, int nfmax, int nvar, hipStream_t s)
 {
@@ -159,12 +228,41 @@ static void launch_lsq_t(const BT &b, dim3 g, int nfmax, int nvar, hipStream_t s
     }
 }
 
+template <class BT>
+static void launch_lsq_q(const BT &b, dim3 g, int nfmax, int nvar, hipStream_t s)
+{
+    if (nfmax <= 4) {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq_q<6, 4, BT>), g, dim3(MCELLS_Q * 4), 0, s, b);
+        else hipLaunchKernelGGL((k_lsq_q<4, 4, BT>), g, dim3(MCELLS_Q * 4), 0, s, b);
+    } else {
+        if (nvar == 6) hipLaunchKernelGGL((k_lsq_q<6, MAXF, BT>), g, dim3(MCELLS_Q * MAXF), 0, s, b);
+        else hipLaunchKernelGGL((k_lsq_q<4, MAXF, BT>), g, dim3(MCELLS_Q * MAXF), 0, s, b);
+    }
+}
+
+// GSIS_MACRO_LANES=0 selects the one-thread-per-cell gradient and update kernels
+bool macro_lanes()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GSIS_MACRO_LANES");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 static void launch_lsq_b(const MBatch &b, int nvar, hipStream_t s)
 {
+    if (macro_lanes()) {
+        const dim3 g(b.bq[b.n]);
+        if (b.n == 1) launch_lsq_q(mone_of(b), g, b.nfmax, nvar, s);
+        else launch_lsq_q(b, g, b.nfmax, nvar, s);
+        return;
+    }
     const dim3 g(b.bc[b.n]);
     if (b.n == 1) launch_lsq_t(mone_of(b), g, b.nfmax, nvar, s);
     else launch_lsq_t(b, g, b.nfmax, nvar, s);
 }
+
 
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s)
 {
@@ -302,7 +400,7 @@ __device__ void half_flux(const double *P, const double *n, double sgn, double *
 template <class BT>
 __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
 {
-    const MLoc ML = mb_loc(B, true);
+    const MLoc ML = mb_loc(B, PK_FACE);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
     const double *__restrict__ hot = ML.hot;
@@ -448,7 +546,7 @@ __device__ double cell_D(const CaseView &C, int i, const double *Wi)
 template <class BT>
 __global__ __launch_bounds__(MBLOCK) void k_cons(BT B)
 {
-    const MLoc ML = mb_loc(B, false);
+    const MLoc ML = mb_loc(B, PK_CELL);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
     const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
@@ -466,7 +564,7 @@ __global__ __launch_bounds__(MBLOCK) void k_cons(BT B)
 template <class BT>
 __global__ __launch_bounds__(MBLOCK) void k_dloc(BT B)
 {
-    const MLoc ML = mb_loc(B, false);
+    const MLoc ML = mb_loc(B, PK_CELL);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
     const int blk = (int)blockIdx.x - ML.base;
@@ -507,7 +605,7 @@ __global__ __launch_bounds__(256) void k_min_final(MBatch B)
 template <int NF, class BT>
 __global__ __launch_bounds__(MBLOCK) void k_update(BT B, double cfl)
 {
-    const MLoc ML = mb_loc(B, false);
+    const MLoc ML = mb_loc(B, PK_CELL);
     const CaseView &C = *ML.cv;
     double *__restrict__ W = ML.W;
     const double *__restrict__ src = ML.src;
@@ -577,21 +675,101 @@ __global__ __launch_bounds__(MBLOCK) void k_update(BT B, double cfl)
     if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4])) atomicOr(C.status, 1);
 }
 
+// The update with one lane per face: each of the G lanes of a cell loads one
+// face's flux and geometry; the flux balance and sum |u.n S/V| are added over
+// the lanes in a fixed butterfly order, then lane 0 updates the cell exactly
+// as k_update does.
+template <int G, class BT>
+__global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
+{
+    const MLoc ML = mb_loc(B, PK_GROUP);
+    const CaseView &C = *ML.cv;
+    double *__restrict__ W = ML.W;
+    const double *__restrict__ src = ML.src;
+    const int i = ((int)blockIdx.x - ML.base) * MCELLS_Q + (int)threadIdx.x / G;
+    const int l = (int)threadIdx.x % G;
+    if (i >= C.n_cells) return;   // whole groups leave together
+    double *Wi = W + 5 * (size_t)i;
+    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
+    double R[5] = {0, 0, 0, 0, 0}, un = 0.0;
+    if (l < nf) {
+        const int e = e0 + l;
+        const double fs = C.cf_fs[e];
+        const double *F = C.fflux + 5 * (size_t)C.cf_face[e];
+        for (int c = 0; c < 5; ++c) R[c] = F[c] * fs;
+        if (cfl >= 0) {
+            const double *n = C.cf_nsv + 3 * (size_t)e;
+            un = fabs(Wi[1] * n[0] + Wi[2] * n[1] + Wi[3] * n[2]);
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) R[c] += __shfl_xor(R[c], off, G);
+        un += __shfl_xor(un, off, G);
+    }
+    if (l != 0) return;
+    const double V = C.cell_volume[i];
+    if (src)
+        for (int c = 0; c < 5; ++c) R[c] += src[5 * (size_t)i + c] * V;
+    double k;
+    if (cfl < 0) {
+        k = (-cfl * C.red[0]) / V;
+    } else {
+        const double a = sqrt(5.0 / 3.0 * Wi[4] / 2.0);
+        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wi[4], C.omega) / (sqrt(M_PI) * Wi[0]);
+        const double *sS = C.cell_sS + 2 * (size_t)i;
+        k = cfl / (V * un + a * sS[0] + 2.0 * nu * sS[1]);
+    }
+    double *U = C.U + 5 * (size_t)i;
+    // positivity safeguard: halve this cell's increment (at most ten times)
+    // while the new density or temperature would not be positive
+    double Un[5], Pn[5];
+    bool ok = false;
+    for (int h = 0; h <= 10 && !ok; ++h) {
+        for (int c = 0; c < 5; ++c) Un[c] = U[c] + k * R[c];
+        Pn[0] = Un[0];
+        double u2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            Pn[1 + d] = Un[1 + d] / Un[0];
+            u2 += Pn[1 + d] * Pn[1 + d];
+        }
+        Pn[4] = (Un[4] - Un[0] * u2) / (1.5 * Un[0]);
+        ok = (Pn[0] > 0.0) && (Pn[4] > 0.0);
+        k *= 0.5;
+    }
+    if (ok) {
+        for (int c = 0; c < 5; ++c) {
+            U[c] = Un[c];
+            Wi[c] = Pn[c];
+        }
+    }
+    if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4])) atomicOr(C.status, 1);
+}
+
 template <class BT>
 static void macro_steps_t(const BT &bt, const MBatch &b, int n_inner, double cfl, hipStream_t s)
 {
     const dim3 gc(b.bc[b.n]), gf(b.bf[b.n]);
     hipLaunchKernelGGL(k_cons<BT>, gc, dim3(MBLOCK), 0, s, bt);
+    const bool lanes = macro_lanes();
+    const dim3 gq(b.bq[b.n]);
     for (int it = 0; it < n_inner; ++it) {
-        launch_lsq_t(bt, gc, b.nfmax, 4, s);
+        if (lanes) launch_lsq_q(bt, gq, b.nfmax, 4, s);
+        else launch_lsq_t(bt, gc, b.nfmax, 4, s);
         if (b.bf[b.n] > 0) hipLaunchKernelGGL(k_face_flux<BT>, gf, dim3(MBLOCK_F), 0, s, bt);
         if (cfl < 0) {
             // one global (conservative) step per case
             hipLaunchKernelGGL(k_dloc<BT>, gc, dim3(MBLOCK), 0, s, bt);
             hipLaunchKernelGGL(k_min_final, dim3(b.n), dim3(256), 0, s, b);
         }
-        if (b.nfmax <= 4) hipLaunchKernelGGL((k_update<4, BT>), gc, dim3(MBLOCK), 0, s, bt, cfl);
-        else hipLaunchKernelGGL((k_update<MAXF, BT>), gc, dim3(MBLOCK), 0, s, bt, cfl);
+        if (lanes) {
+            if (b.nfmax <= 4) hipLaunchKernelGGL((k_update_q<4, BT>), gq, dim3(MCELLS_Q * 4), 0, s, bt, cfl);
+            else hipLaunchKernelGGL((k_update_q<MAXF, BT>), gq, dim3(MCELLS_Q * MAXF), 0, s, bt, cfl);
+        } else {
+            if (b.nfmax <= 4) hipLaunchKernelGGL((k_update<4, BT>), gc, dim3(MBLOCK), 0, s, bt, cfl);
+            else hipLaunchKernelGGL((k_update<MAXF, BT>), gc, dim3(MBLOCK), 0, s, bt, cfl);
+        }
     }
 }
 
