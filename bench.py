@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--region-every", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-sweep", action="store_true")
+    ap.add_argument("--no-point-grid", action="store_true", help="skip the non-tensor velocity-grid sweep leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
     ap.add_argument("--serve-requests", type=int, default=12, help="requests in the serving leg (0: skip)")
@@ -182,6 +183,30 @@ def fp64_sweep(g, torch, M, grid, W, flags, steps=3):
     return out
 
 
+def point_grid_sweep(g, torch, M, nv1d, W, flags, steps=3):
+    """The same region on a non-tensor velocity set: the nv1d^3 stretched grid
+    cropped to the ball |xi| <= 15 (a point set with its own weights; one exp
+    per node and source, generic kernel), FP32 sweeps on the same GPU."""
+    import gsis_inputs as gi
+    grid = gi.ball_grid(nv1d, 15.0, "stretched")
+    cap = int(flags.sum()) + 64
+    case = g.Case(M, grid, KN, dtype=g.F32, capacity=cap)
+    case.set_state(W, flags=flags)
+    case.sweep(1)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        case.sweep(1)
+        ms.append(case.last_sweep_ms())
+    torch.cuda.synchronize()
+    n, nv = case.n_kin, case.nv
+    kms = float(np.mean(ms))
+    out = {"velocities": nv, "of_tensor": nv1d ** 3, "kinetic_cells": n, "kernel_ms": kms,
+           "updates_per_s": n * nv / (kms / 1e3), "achieved_gbs": 8.0 * n * nv / (kms / 1e3) / 1e9}
+    case.close()
+    return out
+
+
 def surface_leg(g, torch, case, mesh, es):
     """Surface quantities on the sphere (stress, pressure, heat flux per wall face,
     force and heat totals) at the state after the timed steps: kernel time over
@@ -282,6 +307,10 @@ def main():
     if not a.no_fp64_sweep and dtype == g.F32:
         fp64 = fp64_sweep(g, torch, M, grid, W, flags)
         log("fp64 sweep", fp64)
+    points = None
+    if not a.no_point_grid and not a.sweep_only:
+        points = point_grid_sweep(g, torch, M, a.nv1d, W, flags)
+        log("point-grid sweep", points)
 
     out = {
         "metric": "kinetic cell-velocity updates/s",
@@ -306,6 +335,7 @@ def main():
                      "kernel_ms": 1e3 * sweep_s},
         "sweep_updates_per_s": n_kin_mean * nv / sweep_s,
         "fp64_sweep": fp64,
+        "point_grid_sweep": points,
         "surface": surface,
         "setup_s": setup_s,
     }

@@ -84,7 +84,26 @@ def velocity_grid(vdim: int, n, half_width, kind: str = "uniform", alpha: float 
     return {"vdim": vdim, "nodes": nodes, "weights": weights, "kind": kind}
 
 
+def ball_grid(n, half_width, kind: str = "uniform", radius=None, alpha: float = 0.4):
+    """Non-tensor 3D velocity set: the nodes of the tensor grid
+    velocity_grid(3, n, half_width, kind) that lie in the ball |xi| <= radius
+    (default: the half-width), each keeping its tensor weight.  Returned as a
+    point set: dict(vdim=3, kind="points", points [nv, 3], pweights [nv]), in
+    the tensor grid's row-major order."""
+    g = velocity_grid(3, n, half_width, kind, alpha)
+    X = np.meshgrid(*g["nodes"], indexing="ij")
+    Wt = np.meshgrid(*g["weights"], indexing="ij")
+    pts = np.stack([x.ravel() for x in X], 1)
+    w = (Wt[0] * Wt[1] * Wt[2]).ravel()
+    r = float(np.max(half_width) if radius is None else radius)
+    keep = np.sum(pts * pts, axis=1) <= r * r * (1.0 + 1e-12)
+    return {"vdim": 3, "kind": "points", "points": np.ascontiguousarray(pts[keep]),
+            "pweights": np.ascontiguousarray(w[keep])}
+
+
 def grid_size(grid) -> int:
+    if grid.get("kind") == "points":
+        return int(len(grid["pweights"]))
     return int(np.prod([len(x) for x in grid["nodes"]]))
 
 
@@ -471,7 +490,10 @@ def synthetic_region(mesh, fraction: float, seed: int = 11):
 
 
 def node_velocities(grid):
-    """Velocity nodes [nv, 3] and weights [nv] of a tensor grid, row-major (last axis fastest)."""
+    """Velocity nodes [nv, 3] and weights [nv]: a tensor grid row-major (last
+    axis fastest), or a point set as given."""
+    if grid.get("kind") == "points":
+        return np.asarray(grid["points"], dtype=np.float64), np.asarray(grid["pweights"], dtype=np.float64)
     xs = list(grid["nodes"]) + [np.zeros(1)] * (3 - grid["vdim"])
     ws = list(grid["weights"]) + [np.ones(1)] * (3 - grid["vdim"])
     X = np.meshgrid(*xs, indexing="ij")

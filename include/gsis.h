@@ -117,6 +117,15 @@ gsis_status gsis_destroy_case(gsis_case c);
 gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const int32_t n[3],
                                    const double *const nodes[3], const double *const weights[3]);
 
+/* Non-tensor velocity quadrature (Sec. 4.3 and 5: unstructured / hybrid
+ * velocity space): n_points nodes xi [n_points][3] with their own positive
+ * weights w [n_points] (host arrays, copied), full 3D velocity space, node k
+ * = point k.  Every kinetic kernel then evaluates the Gaussian and Grad-13
+ * forms per node (one exp per node and source) and the conservation fix-up
+ * from direct FP64 sums over the nodes; the generic (non-plane) sweep and
+ * correction kernels run.  1..2^24 points. */
+gsis_status gsis_set_velocity_points(gsis_case c, int32_t n_points, const double *xi, const double *w);
+
 /* Device bytes needed to bind the case with room for `kinetic_capacity`
  * kinetic cells (VDF double buffer, per-cell sums and parameters, mesh and
  * macroscopic arrays). */
@@ -139,8 +148,9 @@ gsis_status gsis_set_state(gsis_case c, const double *W_dev, const void *vdf_dev
 
 /* n_sweeps point-Jacobi kinetic sweeps (Sec. 3.1 implicit update, upwind
  * fluxes, Shakhov target with conservation fix-up) on each case, with the
- * fused moment reduction of the result.  All cases must share dtype and
- * vdim; n_cases > 1 runs one batched launch per sweep.  On return (after the
+ * fused moment reduction of the result.  All cases must share dtype, vdim,
+ * grid kind (tensor or point set) and sweep layout, and the first case must
+ * have the largest velocity axes; n_cases > 1 runs one batched launch per sweep.  On return (after the
  * stream syncs) each case's VDF is f^{n+1/2} and its W holds the moments on
  * kinetic cells. */
 gsis_status gsis_kinetic_sweep(gsis_case const *cases, int32_t n_cases, int32_t n_sweeps, void *stream);

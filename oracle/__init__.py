@@ -44,7 +44,8 @@ class _Mesh(C.Structure):
 
 
 class _Grid(C.Structure):
-    _fields_ = [("vdim", C.c_int32), ("n", C.c_int32 * 3), ("x", C.c_void_p * 3), ("w", C.c_void_p * 3)]
+    _fields_ = [("vdim", C.c_int32), ("n", C.c_int32 * 3), ("x", C.c_void_p * 3), ("w", C.c_void_p * 3),
+                ("npts", C.c_int32), ("pts", C.c_void_p), ("pw", C.c_void_p)]
 
 
 class _Gas(C.Structure):
@@ -109,8 +110,17 @@ class Oracle:
                         fc.ctypes.data, *[a.ctypes.data for a in arrs], pk.ctypes.data, ps.ctypes.data)
         self.cg = _Grid()
         self.cg.vdim = self.vdim
+        if grid.get("kind") == "points":
+            # a point set with its own weights (non-tensor velocity grid)
+            pts, pw = _f64(grid["points"]).reshape(-1, 3), _f64(grid["pweights"])
+            k(pts); k(pw)
+            self.cg.npts = len(pw)
+            self.cg.pts = pts.ctypes.data
+            self.cg.pw = pw.ctypes.data
         for d in range(3):
-            if d < self.vdim:
+            if grid.get("kind") == "points":
+                self.cg.n[d] = 1
+            elif d < self.vdim:
                 x, w = _f64(grid["nodes"][d]), _f64(grid["weights"][d])
                 k(x); k(w)
                 self.cg.n[d] = len(x)
@@ -126,6 +136,8 @@ class Oracle:
 
     def _nodes(self):
         g = self.grid
+        if g.get("kind") == "points":
+            return np.array(g["points"], dtype=np.float64).reshape(-1, 3), np.array(g["pweights"], dtype=np.float64)
         if self.vdim == 3:
             X, Y, Z = np.meshgrid(*g["nodes"], indexing="ij")
             WX, WY, WZ = np.meshgrid(*g["weights"], indexing="ij")

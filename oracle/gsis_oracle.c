@@ -20,6 +20,7 @@ static const double PI = 3.14159265358979323846;
 
 int32_t oc_nv(const oc_grid *g)
 {
+    if (g->npts > 0) return g->npts;
     return g->vdim == 3 ? g->n[0] * g->n[1] * g->n[2] : g->n[0] * g->n[1];
 }
 
@@ -38,7 +39,10 @@ int32_t oc_threads(void)
 /* velocity node k -> (xi, weight); xi_z = 0 for the reduced grid */
 static void node(const oc_grid *g, int32_t k, double *xi, double *w)
 {
-    if (g->vdim == 3) {
+    if (g->npts > 0) {
+        for (int d = 0; d < 3; ++d) xi[d] = g->pts[3 * k + d];
+        *w = g->pw[k];
+    } else if (g->vdim == 3) {
         int32_t iz = k % g->n[2];
         int32_t iy = (k / g->n[2]) % g->n[1];
         int32_t ix = k / (g->n[2] * g->n[1]);

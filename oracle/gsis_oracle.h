@@ -16,8 +16,9 @@
  * reference distribution reduces to the Shakhov form with Prandtl number
  * Pr = A_tt (Sec. 2, reference distributions and heat-flux mixing).
  *
- * Velocity grids are tensor products.  vdim = 3 stores one function per
- * cell, index k = (ix*ny + iy)*nz + iz.  vdim = 2 stores the reduced pair
+ * Velocity grids are tensor products, or (vdim 3) arbitrary point sets with
+ * their own weights (node k = point k).  vdim = 3 stores one function per
+ * cell, index k = (ix*ny + iy)*nz + iz on a tensor grid.  vdim = 2 stores the reduced pair
  * (phi, psi) = (int f dxi_z, int xi_z^2 f dxi_z) per cell, index
  * k = ix*ny + iy, layout [fun][k].
  *
@@ -54,6 +55,9 @@ typedef struct {
     int32_t n[3];                /* nodes per axis (n[2] ignored for vdim 2) */
     const double *x[3];
     const double *w[3];
+    int32_t npts;                /* > 0: a point set instead of a tensor product (vdim 3) */
+    const double *pts;           /* [npts][3] nodes */
+    const double *pw;            /* [npts] weights */
 } oc_grid;
 
 typedef struct {

@@ -29,7 +29,7 @@ EXPORTS = [
     "gsis_set_velocity_grid", "gsis_case_footprint", "gsis_case_bind", "gsis_set_state", "gsis_kinetic_sweep",
     "gsis_moments", "gsis_n_kinetic", "gsis_update_regions", "gsis_step", "gsis_solve_steady", "gsis_get_vdf",
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
-    "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface",
+    "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
 ]
 
 
@@ -107,6 +107,7 @@ def lib():
             "gsis_sweep_layout": [P, P, P, P],
             "gsis_ns_init": [P, I32, P, P, P],
             "gsis_n_wall_faces": [P, P], "gsis_surface": [P, P, P, P, P],
+            "gsis_set_velocity_points": [P, I32, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -170,18 +171,38 @@ class Mesh:
             self.handle = None
 
 
+def _set_grid(h, grid):
+    """Pass a velocity grid to a case: a tensor grid (dict vdim, nodes, weights)
+    or a point set (dict kind="points", points [nv, 3], pweights [nv]).
+    Returns the host arrays (kept alive by the caller during the call)."""
+    if grid.get("kind") == "points":
+        pts = np.ascontiguousarray(grid["points"], dtype=np.float64).reshape(-1, 3)
+        pw = np.ascontiguousarray(grid["pweights"], dtype=np.float64)
+        _check(lib().gsis_set_velocity_points(h, len(pw), C.c_void_p(pts.ctypes.data), C.c_void_p(pw.ctypes.data)))
+        return (pts, pw)
+    vdim = grid["vdim"]
+    n = (C.c_int32 * 3)(*[len(grid["nodes"][d]) if d < vdim else 1 for d in range(3)])
+    xs_ = [np.ascontiguousarray(grid["nodes"][d] if d < vdim else [0.0], dtype=np.float64) for d in range(3)]
+    ws_ = [np.ascontiguousarray(grid["weights"][d] if d < vdim else [1.0], dtype=np.float64) for d in range(3)]
+    xs = (C.c_void_p * 3)(*[x.ctypes.data for x in xs_])
+    ws = (C.c_void_p * 3)(*[x.ctypes.data for x in ws_])
+    _check(lib().gsis_set_velocity_grid(h, vdim, n, xs, ws))
+    return (xs_, ws_)
+
+
+def grid_nv(grid):
+    """Velocity nodes of a tensor grid or a point set."""
+    if grid.get("kind") == "points":
+        return int(len(grid["pweights"]))
+    return int(np.prod([len(grid["nodes"][d]) for d in range(grid["vdim"])]))
+
+
 def footprint(mesh: Mesh, grid, Kn, dtype=F32, capacity=None, omega=0.5, Pr=2.0 / 3.0):
     """Device bytes a case of this mesh, grid and kinetic capacity binds (no allocation)."""
     h = C.c_void_p()
     _check(lib().gsis_create_case(mesh.handle, C.byref(_Gas(Kn, omega, Pr)), dtype, C.byref(h)))
     try:
-        vdim = grid["vdim"]
-        n = (C.c_int32 * 3)(*[len(grid["nodes"][d]) if d < vdim else 1 for d in range(3)])
-        xs_ = [np.ascontiguousarray(grid["nodes"][d] if d < vdim else [0.0], dtype=np.float64) for d in range(3)]
-        ws_ = [np.ascontiguousarray(grid["weights"][d] if d < vdim else [1.0], dtype=np.float64) for d in range(3)]
-        xs = (C.c_void_p * 3)(*[x.ctypes.data for x in xs_])
-        ws = (C.c_void_p * 3)(*[x.ctypes.data for x in ws_])
-        _check(lib().gsis_set_velocity_grid(h, vdim, n, xs, ws))
+        _keep = _set_grid(h, grid)
         nbytes = C.c_size_t()
         _check(lib().gsis_case_footprint(h, int(capacity or mesh.n_cells), C.byref(nbytes)))
         return nbytes.value
@@ -201,15 +222,9 @@ class Case:
         h = C.c_void_p()
         _check(lib().gsis_create_case(mesh.handle, C.byref(_Gas(Kn, omega, Pr)), dtype, C.byref(h)))
         self.handle = h
-        n = (C.c_int32 * 3)(*[len(grid["nodes"][d]) if d < self.vdim else 1 for d in range(3)])
-        self._grid = [np.ascontiguousarray(grid["nodes"][d] if d < self.vdim else [0.0], dtype=np.float64)
-                      for d in range(3)]
-        self._wts = [np.ascontiguousarray(grid["weights"][d] if d < self.vdim else [1.0], dtype=np.float64)
-                     for d in range(3)]
-        xs = (C.c_void_p * 3)(*[x.ctypes.data for x in self._grid])
-        ws = (C.c_void_p * 3)(*[x.ctypes.data for x in self._wts])
-        _check(lib().gsis_set_velocity_grid(h, self.vdim, n, xs, ws))
-        self.nv = int(np.prod([len(grid["nodes"][d]) for d in range(self.vdim)]))
+        self._grid = _set_grid(h, grid)
+        self.points = grid.get("kind") == "points"
+        self.nv = grid_nv(grid)
         self.capacity = int(capacity or mesh.n_cells)
         nbytes = C.c_size_t()
         _check(lib().gsis_case_footprint(h, self.capacity, C.byref(nbytes)))

@@ -72,6 +72,8 @@ struct gsis_case_s {
     int32_t dtype = GSIS_F32;
     int32_t vdim = 0, n[3] = {0, 0, 0}, nv = 0;
     double xv[3][MAXA], wv[3][MAXA];
+    std::vector<double> vpt;    // point-set grid: [nv][4] = xi (3), w
+    bool points = false;
     bool grid_set = false, bound = false, state_set = false;
     int32_t capacity = 0, tile = 0, ntile = 0, row = 0;
     unsigned char *ws = nullptr;
@@ -386,6 +388,32 @@ extern "C" gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const i
             }
     }
     c->nv = (int32_t)nv;
+    c->points = false;
+    c->vpt.clear();
+    c->grid_set = true;
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_set_velocity_points(gsis_case c, int32_t np, const double *xi, const double *w)
+{
+    if (!c || !xi || !w) return fail(GSIS_E_ARG, "null argument");
+    if (c->bound) return fail(GSIS_E_STATE, "velocity grid must be set before binding");
+    if (np < 1 || np > (1 << 24)) return fail(GSIS_E_ARG, "%d points (need 1..2^24)", np);
+    c->vpt.assign(4 * (size_t)np, 0.0);
+    for (int k = 0; k < np; ++k) {
+        for (int d = 0; d < 3; ++d) {
+            if (!std::isfinite(xi[3 * (size_t)k + d])) return fail(GSIS_E_ARG, "point %d: non-finite node", k);
+            c->vpt[4 * (size_t)k + d] = xi[3 * (size_t)k + d];
+        }
+        if (!(w[k] > 0) || !std::isfinite(w[k])) return fail(GSIS_E_ARG, "point %d: weight must be positive", k);
+        c->vpt[4 * (size_t)k + 3] = w[k];
+    }
+    c->vdim = 3;
+    std::memset(c->xv, 0, sizeof c->xv);
+    std::memset(c->wv, 0, sizeof c->wv);
+    for (int d = 0; d < 3; ++d) c->n[d] = 1;
+    c->nv = np;
+    c->points = true;
     c->grid_set = true;
     return GSIS_OK;
 }
@@ -394,7 +422,7 @@ namespace {
 
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
-        face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, flags, slot, kin, nkin, newc, nnew, scan,
+        face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, flags, slot, kin, nkin, newc, nnew, scan,
         status, prow, grow, gslot, gcell, ngh, axtab, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
@@ -418,7 +446,7 @@ TileChoice choose_tile(const gsis_case_s *c, int64_t cap)
     if (env) target = std::atoi(env);
     if (target < BLOCK) target = BLOCK;
     const char *gen = std::getenv("GSIS_GENERIC_SWEEP");
-    const bool allow_fast = !(gen && gen[0] == '1');
+    const bool allow_fast = !(gen && gen[0] == '1') && !c->points;
     const int nx = c->n[0], ny = c->n[1], nz = c->n[2];
     TileChoice t{};
     if (allow_fast && c->vdim == 3 && BLOCK % nz == 0 && (ny * nz) % BLOCK == 0) {
@@ -494,6 +522,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.wallf = S.take(4 * std::max<size_t>(1, m->wall_faces.size()));
     L.xv = S.take(8 * 3 * MAXA);
     L.wv = S.take(8 * 3 * MAXA);
+    L.vpt = S.take(8 * std::max<size_t>(4, c->vpt.size()));
     L.flags = S.take(4 * nc);
     L.slot = S.take(4 * nc);
     L.kin = S.take(4 * (size_t)cap);
@@ -646,6 +675,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     h.n_wall = (int32_t)m->wall_faces.size();
     P(const double *, xv, xv);
     P(const double *, wv, wv);
+    P(const double *, vpt, vpt);
+    h.points = c->points ? 1 : 0;
     P(int32_t *, flags, flags);
     P(int32_t *, slot_of_cell, slot);
     P(int32_t *, kin_cell, kin);
@@ -719,6 +750,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(put(L.wallf, m->wall_faces.data(), 4 * m->wall_faces.size()));
     HIPCHK(put(L.xv, c->xv, sizeof c->xv));
     HIPCHK(put(L.wv, c->wv, sizeof c->wv));
+    HIPCHK(put(L.vpt, c->vpt.data(), 8 * c->vpt.size()));
     HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.flags, 0, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.status, 0, 16, s));
@@ -846,8 +878,8 @@ gsis_status check_batch(gsis_case const *cases, int n)
         gsis_status st = check_ready(cases[j]);
         if (st) return st;
         if (cases[j]->dtype != cases[0]->dtype || cases[j]->vdim != cases[0]->vdim ||
-            cases[j]->hv.fast != cases[0]->hv.fast)
-            return fail(GSIS_E_ARG, "batched cases must share dtype, vdim and sweep layout");
+            cases[j]->hv.fast != cases[0]->hv.fast || cases[j]->points != cases[0]->points)
+            return fail(GSIS_E_ARG, "batched cases must share dtype, vdim, grid kind and sweep layout");
         for (int d = 0; d < 3; ++d)
             if (cases[j]->n[d] > cases[0]->n[d] && j > 0) {
                 // LDS is sized from the first case: put the largest grid first

@@ -96,6 +96,8 @@ struct CaseView {
     int32_t n_wall, pad_w;
     const double *xv;           // [3][MAXA] nodes
     const double *wv;           // [3][MAXA] weights
+    const double *vpt;          // point-set grids: [nv][4] node (3) and weight
+    int32_t points, pad_p;      // 1: the velocity grid is the point set vpt
     // region
     int32_t *flags;             // [n_cells] 1 = kinetic
     int32_t *slot_of_cell;      // [n_cells], -1 for NS cells
@@ -173,6 +175,33 @@ struct MBatch {
     int32_t n;
     int32_t nfmax;
 };
+
+// velocity node k and its weight: tensor grids (k = (ix n1 + iy) n2 + iz, or
+// ix n1 + iy reduced) or point sets
+__device__ __forceinline__ void vnode(const CaseView &C, int k, double *xi, double &w)
+{
+    if (C.points) {
+        const double *q = C.vpt + 4 * (size_t)k;
+        xi[0] = q[0];
+        xi[1] = q[1];
+        xi[2] = q[2];
+        w = q[3];
+        return;
+    }
+    int ix, iy, iz = 0;
+    if (C.vdim == 3) {
+        iz = k % C.n[2];
+        iy = (k / C.n[2]) % C.n[1];
+        ix = k / (C.n[2] * C.n[1]);
+    } else {
+        iy = k % C.n[1];
+        ix = k / C.n[1];
+    }
+    xi[0] = C.xv[ix];
+    xi[1] = C.xv[MAXA + iy];
+    xi[2] = (C.vdim == 3) ? C.xv[2 * MAXA + iz] : 0.0;
+    w = C.wv[ix] * C.wv[MAXA + iy] * ((C.vdim == 3) ? C.wv[2 * MAXA + iz] : 1.0);
+}
 
 // --- launch wrappers (gsis_kinetic.hip) ---------------------------------------
 hipError_t launch_wall_den(const CaseView *cv, const CaseView &h, hipStream_t s);

@@ -187,6 +187,94 @@ __device__ int solve_dense(int n, double *A, double *b)
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// point-set grids: the conservation fix-up from direct FP64 sums over the
+// nodes, one block per item.  The target is E S(c) (a0 + a.c + b c^2) with
+// E = exp(-c^2 / T) and S the Shakhov factor (or 1); its discrete moments
+// {1, c, c^2} must equal (rho, 0, 3 rho T / 2) in the frame u.
+//   mode 0: the relaxation target of ParamRec (rho from the moments)
+//   mode 1: the Maxwellians of W_new and W_half (FeqRec 0 and 1)
+//   mode 2: the Maxwellian of W (FeqRec 0, initial fill)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_fix_pts(const CaseView *__restrict__ cvp, const int32_t *list, int mode)
+{
+    const CaseView &C = *cvp;
+    const int cell = list[blockIdx.x];
+    const int slot = C.slot_of_cell[cell];
+    __shared__ double red[(BLOCK / 64) * 15];
+    const int nrun = (mode == 1) ? 2 : 1;
+    for (int which = 0; which < nrun; ++which) {
+        double u[3], it, rho, kq[3] = {0.0, 0.0, 0.0};
+        double *fx;
+        if (mode == 0) {
+            ParamRec &P = C.param[slot];
+            for (int d = 0; d < 3; ++d) u[d] = P.u[d], kq[d] = P.kq[d];
+            it = P.it;
+            rho = C.mom[(size_t)slot * (GSIS_NMOM + MAXW)];
+            fx = P.fx;
+        } else {
+            FeqRec &F = C.feq[2 * (size_t)slot + which];
+            for (int d = 0; d < 3; ++d) u[d] = F.u[d];
+            it = F.it;
+            const double *W = (mode == 2) ? C.W + 5 * (size_t)cell
+                                          : ((which == 0 ? C.Wn : C.Wh) + 5 * (size_t)cell);
+            rho = W[0];
+            fx = F.fx;
+        }
+        double acc[15];
+        for (int a = 0; a < 15; ++a) acc[a] = 0.0;
+        for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
+            double xi[3], w;
+            vnode(C, k, xi, w);
+            const double c0 = xi[0] - u[0], c1 = xi[1] - u[1], c2 = xi[2] - u[2];
+            const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+            double g = w * exp(-cc * it);
+            if (mode == 0) g *= 1.0 + (kq[0] * c0 + kq[1] * c1 + kq[2] * c2) * (cc * it - 2.5);
+            const double b[5] = {1.0, c0, c1, c2, cc};
+            int m = 0;
+            for (int a = 0; a < 5; ++a)
+                for (int c = a; c < 5; ++c) acc[m++] += g * b[a] * b[c];
+        }
+        // fixed-order block reduction
+        for (int m = 0; m < 15; ++m) {
+            double v = acc[m];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * 15 + m] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double S[15];
+            for (int m = 0; m < 15; ++m) {
+                S[m] = 0.0;
+                for (int wv = 0; wv < BLOCK / 64; ++wv) S[m] += red[wv * 15 + m];
+            }
+            double A[25], bb[5];
+            int m = 0;
+            for (int a = 0; a < 5; ++a)
+                for (int c = a; c < 5; ++c) {
+                    A[a * 5 + c] = S[m];
+                    A[c * 5 + a] = S[m];
+                    ++m;
+                }
+            const double T = 1.0 / it;
+            bb[0] = rho;
+            bb[1] = bb[2] = bb[3] = 0.0;
+            bb[4] = 1.5 * rho * T;
+            if (solve_dense(5, A, bb)) atomicOr(C.status, 1);
+            for (int a = 0; a < 5; ++a) fx[a] = bb[a];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_fix_pts(const CaseView *cv, const CaseView &h, int n_items, const int32_t *list, int mode,
+                          hipStream_t s)
+{
+    if (!h.points || n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fix_pts, dim3(n_items), dim3(BLOCK), 0, s, cv, list, mode);
+    return hipGetLastError();
+}
+
 // Multiplier (a0, a, b) of the unit-amplitude target E * S(c) (S = Shakhov
 // factor, or 1 when kq == nullptr) so that its discrete mass, momentum and
 // energy in the frame u equal (rho, 0, 3 rho T / 2).
@@ -255,11 +343,8 @@ __global__ __launch_bounds__(BLOCK) void k_wall_den(const CaseView *__restrict__
         double amp = (C.vdim == 3) ? pow(M_PI * T, -1.5) : 1.0 / (M_PI * T);
         double acc = 0.0;
         for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
-            int ix, iy, iz = 0;
-            if (C.vdim == 3) { iz = k % C.n[2]; iy = (k / C.n[2]) % C.n[1]; ix = k / (C.n[2] * C.n[1]); }
-            else { iy = k % C.n[1]; ix = k / C.n[1]; }
-            double xi[3] = {C.xv[ix], C.xv[MAXA + iy], (C.vdim == 3) ? C.xv[2 * MAXA + iz] : 0.0};
-            double w = C.wv[ix] * C.wv[MAXA + iy] * ((C.vdim == 3) ? C.wv[2 * MAXA + iz] : 1.0);
+            double xi[3], w;
+            vnode(C, k, xi, w);
             double a = xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2];
             if (a < 0) {
                 double c2 = 0.0;
@@ -389,7 +474,8 @@ __global__ void k_param(const CaseView *__restrict__ cvp, int n_kin)
     double K = 0.8 * (1.0 - C.Pr) / (rho * T * T);
     for (int d = 0; d < 3; ++d) P.kq[d] = K * mom[11 + d];
     if (C.vdim == 2) P.kq[2] = 0.0;
-    if (fixup_coefs(C, P.u, T, rho, P.kq, P.fx)) atomicOr(C.status, 1);
+    // point-set grids: k_fix_pts forms the multiplier from direct sums
+    if (!C.points && fixup_coefs(C, P.u, T, rho, P.kq, P.fx)) atomicOr(C.status, 1);
     // wall densities from the outgoing half-range mass flux of f^n
     int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1];
     for (int w = 0; w < MAXW; ++w) P.rw[w] = 0.0;
@@ -405,7 +491,7 @@ hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStr
 {
     if (n_kin <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_param, dim3((n_kin + 63) / 64), dim3(64), 0, s, cv, n_kin);
-    return hipGetLastError();
+    return launch_fix_pts(cv, h, n_kin, h.kin_cell, 0, s);
 }
 
 // conservation-fixed Maxwellians of W_new (Wn) and W_half (Wh) per kinetic
@@ -455,7 +541,7 @@ __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const in
         if (C.vdim == 2) F.u[2] = 0.0;
         F.it = 1.0 / W[4];
         F.Th = 0.5 * W[4];
-        if (fixup_coefs(C, F.u, W[4], W[0], nullptr, F.fx)) atomicOr(C.status, 1);
+        if (!C.points && fixup_coefs(C, F.u, W[4], W[0], nullptr, F.fx)) atomicOr(C.status, 1);
         C.feq[2 * (size_t)slot + which] = F;
     }
 }
@@ -464,7 +550,7 @@ hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipSt
 {
     if (n_kin <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_feqpar, dim3((n_kin + 63) / 64), dim3(64), 0, s, cv, n_kin, h.kin_cell, 0);
-    return hipGetLastError();
+    return launch_fix_pts(cv, h, n_kin, h.kin_cell, 1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,7 +604,7 @@ struct FaceS {
     int kind, wall, tab;
 };
 
-template <typename T, int VD>
+template <typename T, int VD, bool PTS>
 __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -610,8 +696,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
         }
         fs[l] = F;
     }
-    // node / weight tables
-    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+    // node / weight tables (tensor grids; a point set reads its nodes per point)
+    for (int j = threadIdx.x; j < (PTS ? 0 : NA3); j += BLOCK) {
         int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
         int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
         xs[j] = (T)C.xv[d * MAXA + jj];
@@ -623,7 +709,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
     __syncthreads();
     // separable Gaussian factors exp(-(x_j - u_d)^2 / T), evaluated in FP64:
     // table 0 = own target, 1 + l = face l
-    for (int idx = threadIdx.x; idx < (1 + nf) * NA3; idx += BLOCK) {
+    for (int idx = threadIdx.x; idx < (PTS ? 0 : (1 + nf) * NA3); idx += BLOCK) {
         int src = idx / NA3, j = idx - src * NA3;
         int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
         int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
@@ -658,15 +744,41 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
     int k = k0 + threadIdx.x;
-    VIdx vi = vidx_init<VD>(k, n1, (VD == 3) ? n2 : 1);
+    VIdx vi = vidx_init<VD>(PTS ? 0 : k, n1, (VD == 3) ? n2 : 1);
     const T *tx = tabs, *ty = tabs + n0, *tz = tabs + n0 + n1;
     for (; k < kend; k += BLOCK) {
-        const T x0 = xs[vi.ix], x1 = xs[n0 + vi.iy];
-        const T x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
-        const T w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
-        const T c0 = cs[vi.ix], c1 = cs[n0 + vi.iy], c2 = (VD == 3) ? cs[n0 + n1 + vi.iz] : (T)0;
+        T x0, x1, x2, w, c0, c1, c2, E;
+        double wd, d0, d1, d2;
+        if constexpr (PTS) {
+            // point set: the node and its Gaussian factor (one exp per node)
+            const double *q = C.vpt + 4 * (size_t)k;
+            d0 = q[0] - P.u[0];
+            d1 = q[1] - P.u[1];
+            d2 = q[2] - P.u[2];
+            wd = q[3];
+            x0 = (T)q[0];
+            x1 = (T)q[1];
+            x2 = (T)q[2];
+            w = (T)wd;
+            c0 = (T)d0;
+            c1 = (T)d1;
+            c2 = (T)d2;
+        } else {
+            x0 = xs[vi.ix];
+            x1 = xs[n0 + vi.iy];
+            x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
+            w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
+            c0 = cs[vi.ix];
+            c1 = cs[n0 + vi.iy];
+            c2 = (VD == 3) ? cs[n0 + n1 + vi.iz] : (T)0;
+            wd = wsd[vi.ix] * wsd[n0 + vi.iy] * ((VD == 3) ? wsd[n0 + n1 + vi.iz] : 1.0);
+            d0 = csd[vi.ix];
+            d1 = csd[n0 + vi.iy];
+            d2 = (VD == 3) ? csd[n0 + n1 + vi.iz] : 0.0;
+        }
         const T cc = c0 * c0 + c1 * c1 + c2 * c2;
-        const T E = tx[vi.ix] * ty[vi.iy] * ((VD == 3) ? tz[vi.iz] : (T)1);
+        if constexpr (PTS) E = exp(-cc * it);
+        else E = tx[vi.ix] * ty[vi.iy] * ((VD == 3) ? tz[vi.iz] : (T)1);
         const T kqc = kq0 * c0 + kq1 * c1 + kq2 * c2;
         T Pf, g0, g1 = (T)0;
         if (VD == 3) {
@@ -694,8 +806,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
                     v0 = F.nb[k];
                     if (VD == 2) v1 = F.nb[nvp + k];
                 } else {
-                    const T *tb = tabs + F.tab * NA3;
-                    const T Es = F.A * tb[vi.ix] * tb[n0 + vi.iy] * ((VD == 3) ? tb[n0 + n1 + vi.iz] : (T)1);
+                    T Es;
+                    if constexpr (PTS) {
+                        const T e0 = x0 - F.u[0], e1 = x1 - F.u[1], e2 = x2 - F.u[2];
+                        Es = F.A * exp(-(e0 * e0 + e1 * e1 + e2 * e2) * F.it);
+                    } else {
+                        const T *tb = tabs + F.tab * NA3;
+                        Es = F.A * tb[vi.ix] * tb[n0 + vi.iy] * ((VD == 3) ? tb[n0 + n1 + vi.iz] : (T)1);
+                    }
                     if (F.kind == K_GHOST) {
                         const T d0 = x0 - F.u[0], d1 = x1 - F.u[1], d2 = (VD == 3) ? x2 - F.u[2] : (T)0;
                         const T dd = d0 * d0 + d1 * d1 + d2 * d2;
@@ -726,8 +844,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
             n1v = num1 * rden;
             fn[nvp + k] = n1v;
         }
-        const double wd = wsd[vi.ix] * wsd[n0 + vi.iy] * ((VD == 3) ? wsd[n0 + n1 + vi.iz] : 1.0);
-        const double d0 = csd[vi.ix], d1 = csd[n0 + vi.iy], d2 = (VD == 3) ? csd[n0 + n1 + vi.iz] : 0.0;
         const double dcc = d0 * d0 + d1 * d1 + d2 * d2;
         acc_moments<double, VD>(acc, wd, (double)n0v, (double)n1v, d0, d1, d2, dcc);
         // moment balance at the old iterate: w (num - den f_old) (1, c, c^2 [+psi])
@@ -745,7 +861,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
             const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
             if (a > (T)0) acc[S_WALL + F.wall] += wd * (double)(a * n0v);
         }
-        vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
+        if constexpr (!PTS) vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
     block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
 }
@@ -753,9 +869,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
 template <typename T, int VD>
 static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
+    if (VD == 3 && h0.points) {
+        hipLaunchKernelGGL((k_sweep<T, 3, true>), dim3(total), dim3(BLOCK), 0, s, b);
+        return hipGetLastError();
+    }
     int NA3 = h0.n[0] + h0.n[1] + (VD == 3 ? h0.n[2] : 0);
     size_t lds = sizeof(double) * (size_t)NA3 * 2 + sizeof(T) * (size_t)NA3 * (3 + 1 + MAXF);
-    hipLaunchKernelGGL((k_sweep<T, VD>), dim3(total), dim3(BLOCK), lds, s, b);
+    hipLaunchKernelGGL((k_sweep<T, VD, false>), dim3(total), dim3(BLOCK), lds, s, b);
     return hipGetLastError();
 }
 
@@ -773,7 +893,7 @@ hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total, hipStream
 // GSIS correction (first eq. updatef): f += f_eq(W_new) - f_eq(W_half), in
 // place, with the moment epilogue of the corrected f
 // ---------------------------------------------------------------------------
-template <typename T, int VD>
+template <typename T, int VD, bool PTS>
 __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -803,14 +923,14 @@ __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ 
             }
         s_nw = nw;
     }
-    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+    for (int j = threadIdx.x; j < (PTS ? 0 : NA3); j += BLOCK) {
         int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
         int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
         xs[j] = (T)C.xv[d * MAXA + jj];
         ws[j] = (T)C.wv[d * MAXA + jj];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 3 * NA3; idx += BLOCK) {
+    for (int idx = threadIdx.x; idx < (PTS ? 0 : 3 * NA3); idx += BLOCK) {
         int src = idx / NA3, j = idx - src * NA3;
         int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
         int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
@@ -837,17 +957,47 @@ __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ 
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
     int k = k0 + threadIdx.x;
-    VIdx vi = vidx_init<VD>(k, n1, (VD == 3) ? n2 : 1);
+    VIdx vi = vidx_init<VD>(PTS ? 0 : k, n1, (VD == 3) ? n2 : 1);
     const T *ta = tabs, *tb = tabs + NA3;
+    const T ita = (T)Fa.it, itb = (T)Fb.it;
     for (; k < kend; k += BLOCK) {
-        const T x0 = xs[vi.ix], x1 = xs[n0 + vi.iy];
-        const T x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
-        const T w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
-        const T Ea = ta[vi.ix] * ta[n0 + vi.iy] * ((VD == 3) ? ta[n0 + n1 + vi.iz] : (T)1);
-        const T Eb = tb[vi.ix] * tb[n0 + vi.iy] * ((VD == 3) ? tb[n0 + n1 + vi.iz] : (T)1);
-        const T *ca = cts, *cb = cts + NA3, *cr = cts + 2 * NA3;
-        const T da0 = ca[vi.ix], da1 = ca[n0 + vi.iy], da2 = (VD == 3) ? ca[n0 + n1 + vi.iz] : (T)0;
-        const T db0 = cb[vi.ix], db1 = cb[n0 + vi.iy], db2 = (VD == 3) ? cb[n0 + n1 + vi.iz] : (T)0;
+        T x0, x1, x2, w, Ea, Eb, da0, da1, da2, db0, db1, db2, c0, c1, c2;
+        if constexpr (PTS) {
+            // point set: offsets formed in FP64, one exp per node and Maxwellian
+            const double *q = C.vpt + 4 * (size_t)k;
+            x0 = (T)q[0];
+            x1 = (T)q[1];
+            x2 = (T)q[2];
+            w = (T)q[3];
+            da0 = (T)(q[0] - Fa.u[0]);
+            da1 = (T)(q[1] - Fa.u[1]);
+            da2 = (T)(q[2] - Fa.u[2]);
+            db0 = (T)(q[0] - Fb.u[0]);
+            db1 = (T)(q[1] - Fb.u[1]);
+            db2 = (T)(q[2] - Fb.u[2]);
+            Ea = exp(-(da0 * da0 + da1 * da1 + da2 * da2) * ita);
+            Eb = exp(-(db0 * db0 + db1 * db1 + db2 * db2) * itb);
+            c0 = (T)(q[0] - P.u[0]);
+            c1 = (T)(q[1] - P.u[1]);
+            c2 = (T)(q[2] - P.u[2]);
+        } else {
+            x0 = xs[vi.ix];
+            x1 = xs[n0 + vi.iy];
+            x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
+            w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
+            Ea = ta[vi.ix] * ta[n0 + vi.iy] * ((VD == 3) ? ta[n0 + n1 + vi.iz] : (T)1);
+            Eb = tb[vi.ix] * tb[n0 + vi.iy] * ((VD == 3) ? tb[n0 + n1 + vi.iz] : (T)1);
+            const T *ca = cts, *cb = cts + NA3, *cr = cts + 2 * NA3;
+            da0 = ca[vi.ix];
+            da1 = ca[n0 + vi.iy];
+            da2 = (VD == 3) ? ca[n0 + n1 + vi.iz] : (T)0;
+            db0 = cb[vi.ix];
+            db1 = cb[n0 + vi.iy];
+            db2 = (VD == 3) ? cb[n0 + n1 + vi.iz] : (T)0;
+            c0 = cr[vi.ix];
+            c1 = cr[n0 + vi.iy];
+            c2 = (VD == 3) ? cr[n0 + n1 + vi.iz] : (T)0;
+        }
         T Pa, Pb;
         if (VD == 3) {
             Pa = a0 + a1 * da0 + a2 * da1 + a3 * da2 + a4 * (da0 * da0 + da1 * da1 + da2 * da2);
@@ -864,14 +1014,13 @@ __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ 
             v1 = fr[nvp + k] + (tha * ma - thb * mb);
             fr[nvp + k] = v1;
         }
-        const T c0 = cr[vi.ix], c1 = cr[n0 + vi.iy], c2 = (VD == 3) ? cr[n0 + n1 + vi.iz] : (T)0;
         const T cc = c0 * c0 + c1 * c1 + c2 * c2;
         acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
         for (int j = 0; j < nw; ++j) {
             const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
             if (a > (T)0) acc[S_WALL + s_wi[j]] += w * a * v0;
         }
-        vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
+        if constexpr (!PTS) vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
     double v[NSUM];
 #pragma unroll
@@ -885,14 +1034,19 @@ hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int 
     if (h.fast) return launch_correct_fast(cv, h, n_kin, cur, s);
     int NA3 = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
     dim3 g(n_kin * h.ntile);
+    if (h.points) {
+        if (h.dtype == GSIS_F32) hipLaunchKernelGGL((k_correct<float, 3, true>), g, dim3(BLOCK), 0, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct<double, 3, true>), g, dim3(BLOCK), 0, s, cv, n_kin, cur);
+        return hipGetLastError();
+    }
     if (h.dtype == GSIS_F32) {
         size_t lds = sizeof(float) * NA3 * 7;
-        if (h.vdim == 3) hipLaunchKernelGGL((k_correct<float, 3>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
-        else hipLaunchKernelGGL((k_correct<float, 2>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        if (h.vdim == 3) hipLaunchKernelGGL((k_correct<float, 3, false>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct<float, 2, false>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
     } else {
         size_t lds = sizeof(double) * NA3 * 7;
-        if (h.vdim == 3) hipLaunchKernelGGL((k_correct<double, 3>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
-        else hipLaunchKernelGGL((k_correct<double, 2>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        if (h.vdim == 3) hipLaunchKernelGGL((k_correct<double, 3, false>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct<double, 2, false>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
     }
     return hipGetLastError();
 }
@@ -902,7 +1056,7 @@ hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int 
 // fixed Maxwellian of W, FeqRec slot 0; mode 1: Grad-13 of ghost[cell]) and
 // write their moment sums relative to u_ref = source velocity
 // ---------------------------------------------------------------------------
-template <typename T, int VD>
+template <typename T, int VD, bool PTS>
 __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp, const int32_t *list, int n_items,
                                                 int mode, int cur)
 {
@@ -957,7 +1111,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
             }
         s_nw = nw;
     }
-    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+    for (int j = threadIdx.x; j < (PTS ? 0 : NA3); j += BLOCK) {
         int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
         int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
         xs[j] = (T)C.xv[d * MAXA + jj];
@@ -965,7 +1119,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
     }
     __syncthreads();
     T *cs = tabs + NA3;
-    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+    for (int j = threadIdx.x; j < (PTS ? 0 : NA3); j += BLOCK) {
         int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
         int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
         double c = C.xv[d * MAXA + jj] - u[d];
@@ -981,15 +1135,31 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
     int k = k0 + threadIdx.x;
-    VIdx vi = vidx_init<VD>(k, n1, (VD == 3) ? n2 : 1);
+    VIdx vi = vidx_init<VD>(PTS ? 0 : k, n1, (VD == 3) ? n2 : 1);
     const int nw = (mode == 3) ? 0 : s_nw;
     const T Tg = (T)(2.0 * Th);
     for (; k < kend; k += BLOCK) {
-        const T x0 = xs[vi.ix], x1 = xs[n0 + vi.iy];
-        const T x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
-        const T w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
-        const T E = tabs[vi.ix] * tabs[n0 + vi.iy] * ((VD == 3) ? tabs[n0 + n1 + vi.iz] : (T)1);
-        const T c0 = cs[vi.ix], c1 = cs[n0 + vi.iy], c2 = (VD == 3) ? cs[n0 + n1 + vi.iz] : (T)0;
+        T x0, x1, x2, w, E, c0, c1, c2;
+        if constexpr (PTS) {
+            const double *q = C.vpt + 4 * (size_t)k;
+            x0 = (T)q[0];
+            x1 = (T)q[1];
+            x2 = (T)q[2];
+            w = (T)q[3];
+            c0 = (T)(q[0] - u[0]);
+            c1 = (T)(q[1] - u[1]);
+            c2 = (T)(q[2] - u[2]);
+            E = exp(-(c0 * c0 + c1 * c1 + c2 * c2) * (T)it);
+        } else {
+            x0 = xs[vi.ix];
+            x1 = xs[n0 + vi.iy];
+            x2 = (VD == 3) ? xs[n0 + n1 + vi.iz] : (T)0;
+            w = ws[vi.ix] * ws[n0 + vi.iy] * ((VD == 3) ? ws[n0 + n1 + vi.iz] : (T)1);
+            E = tabs[vi.ix] * tabs[n0 + vi.iy] * ((VD == 3) ? tabs[n0 + n1 + vi.iz] : (T)1);
+            c0 = cs[vi.ix];
+            c1 = cs[n0 + vi.iy];
+            c2 = (VD == 3) ? cs[n0 + n1 + vi.iz] : (T)0;
+        }
         const T cc = c0 * c0 + c1 * c1 + c2 * c2;
         T v0, v1 = (T)0;
         if (mode == 2) {
@@ -1021,7 +1191,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
             const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
             if (a > (T)0) acc[S_WALL + s_wi[j]] += w * a * v0;
         }
-        vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
+        if constexpr (!PTS) vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
     // zero the padding of this row once
     if (vt == 0 && mode != 2)
@@ -1042,17 +1212,27 @@ hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_it
     const int32_t *list = (mode == 1) ? h.new_cell : ((mode == 3) ? h.ghost_cell : h.kin_cell);
     if (mode == 0) {
         hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, list, 1);
+        hipError_t e = launch_fix_pts(cv, h, n_items, list, 2, s);
+        if (e != hipSuccess) return e;
     }
     int NA3 = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
     dim3 g(n_items * h.ntile);
+    if (h.points) {
+        if (h.dtype == GSIS_F32)
+            hipLaunchKernelGGL((k_fill<float, 3, true>), g, dim3(BLOCK), 0, s, cv, list, n_items, mode, cur);
+        else hipLaunchKernelGGL((k_fill<double, 3, true>), g, dim3(BLOCK), 0, s, cv, list, n_items, mode, cur);
+        return hipGetLastError();
+    }
     if (h.dtype == GSIS_F32) {
         size_t lds = sizeof(float) * NA3 * 4;
-        if (h.vdim == 3) hipLaunchKernelGGL((k_fill<float, 3>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
-        else hipLaunchKernelGGL((k_fill<float, 2>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+        if (h.vdim == 3)
+            hipLaunchKernelGGL((k_fill<float, 3, false>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+        else hipLaunchKernelGGL((k_fill<float, 2, false>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
     } else {
         size_t lds = sizeof(double) * NA3 * 4;
-        if (h.vdim == 3) hipLaunchKernelGGL((k_fill<double, 3>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
-        else hipLaunchKernelGGL((k_fill<double, 2>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+        if (h.vdim == 3)
+            hipLaunchKernelGGL((k_fill<double, 3, false>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
+        else hipLaunchKernelGGL((k_fill<double, 2, false>), g, dim3(BLOCK), lds, s, cv, list, n_items, mode, cur);
     }
     return hipGetLastError();
 }
@@ -1077,17 +1257,10 @@ __global__ void k_patch_rows(const CaseView *__restrict__ cvp)
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nvp; k += gridDim.x * blockDim.x) {
         double v = 0.0;
         if (k < C.nv) {
-            int ix, iy, iz = 0;
-            if (C.vdim == 3) {
-                iz = k % C.n[2];
-                iy = (k / C.n[2]) % C.n[1];
-                ix = k / (C.n[2] * C.n[1]);
-            } else {
-                iy = k % C.n[1];
-                ix = k / C.n[1];
-            }
-            double c0 = C.xv[ix] - ps[1], c1 = C.xv[MAXA + iy] - ps[2];
-            double c2 = (C.vdim == 3) ? C.xv[2 * MAXA + iz] - ps[3] : 0.0;
+            double xi[3], w;
+            vnode(C, k, xi, w);
+            double c0 = xi[0] - ps[1], c1 = xi[1] - ps[2];
+            double c2 = (C.vdim == 3) ? xi[2] - ps[3] : 0.0;
             v = amp * exp(-(c0 * c0 + c1 * c1 + c2 * c2) * it);
         }
         r[k] = (T)v;

@@ -847,17 +847,9 @@ __global__ __launch_bounds__(256) void k_surface(const CaseView *__restrict__ cv
     double acc[NSS];
     for (int a = 0; a < NSS; ++a) acc[a] = 0.0;
     for (int k = threadIdx.x; k < C.nv; k += 256) {
-        int ix, iy, iz = 0;
-        if (vd == 3) {
-            iz = k % C.n[2];
-            iy = (k / C.n[2]) % C.n[1];
-            ix = k / (C.n[2] * C.n[1]);
-        } else {
-            iy = k % C.n[1];
-            ix = k / C.n[1];
-        }
-        const double w = C.wv[ix] * C.wv[MAXA + iy] * ((vd == 3) ? C.wv[2 * MAXA + iz] : 1.0);
-        double c[3] = {C.xv[ix] - ps[1], C.xv[MAXA + iy] - ps[2], (vd == 3) ? C.xv[2 * MAXA + iz] - ps[3] : 0.0};
+        double xi[3], w;
+        vnode(C, k, xi, w);
+        double c[3] = {xi[0] - ps[1], xi[1] - ps[2], (vd == 3) ? xi[2] - ps[3] : 0.0};
         const double a = c[0] * n[0] + c[1] * n[1] + c[2] * n[2];
         const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
         if (a > 0.0) {

@@ -74,7 +74,7 @@ class _Active:
 
     def key(self):
         c, r = self.case, self.req
-        return (c.dtype, c.vdim, c.sweep_layout()[0], r.mode, r.cfl, r.layers)
+        return (c.dtype, c.vdim, c.points, c.sweep_layout()[0], r.mode, r.cfl, r.layers)
 
 
 class Server:
@@ -202,7 +202,7 @@ class Server:
                 for j0 in range(0, len(grp), 16):
                     part = grp[j0:j0 + 16]
                     try:
-                        eps = step([a.case for a in part], self._params(key[3], key[4], key[5]))
+                        eps = step([a.case for a in part], self._params(key[4], key[5], key[6]))
                         err = None
                     except GsisError as e:
                         eps, err = e.eps, e

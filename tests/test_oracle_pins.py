@@ -564,6 +564,58 @@ def test_grad13_limiter_keeps_rows_positive_near_thermal_speeds(oracle_mod):
 
 
 # ---------------------------------------------------------------------------
+# non-tensor (point-set) velocity grids
+# ---------------------------------------------------------------------------
+def _as_points(g):
+    xi, w = gi.node_velocities(g)
+    return {"vdim": 3, "kind": "points", "points": xi, "pweights": w}
+
+
+def test_point_set_equals_tensor_grid(oracle_mod):
+    """A tensor grid given as a point set (every node with its product weight)
+    gives the same moments, relaxation target and sweep as the tensor form."""
+    m = gi.couette_1d(8, 0.1)
+    g = gi.velocity_grid(3, 10, 5.0)
+    Ot = oracle_mod.Oracle(m, g, Kn=0.1)
+    Op = oracle_mod.Oracle(m, _as_points(g), Kn=0.1)
+    W = gi.random_W(8, seed=2, u_scale=0.2)
+    f = gi.gaussian_rows(g, W, seed=3, dtype=np.float64)
+    assert np.array_equal(Ot.xi, Op.xi) and np.array_equal(Ot.w, Op.w)
+    assert np.abs(Ot.moments(f) - Op.moments(f)).max() < 1e-14
+    mom = Ot.moments(f)[3]
+    assert np.abs(Ot.equilibrium(mom) - Op.equilibrium(mom)).max() < 1e-14
+    kin = np.arange(8)
+    ft = Ot.sweep(f, kin, kin)
+    fp = Op.sweep(f, kin, kin)
+    assert np.abs(ft - fp).max() <= 1e-13 * np.abs(ft).max()
+
+
+def test_ball_grid_quadrature_and_conservation(oracle_mod):
+    """The tensor grid cropped to a ball (42% of its nodes) integrates a
+    Maxwellian to its closed-form moments within the quadrature error, the
+    fixed relaxation target conserves mass, momentum and energy to round-off,
+    and a gas at rest between walls at its temperature is a fixed point of the
+    sweep."""
+    gb = gi.ball_grid(16, 5.0)
+    assert len(gb["pweights"]) < 0.45 * 16 ** 3
+    m = gi.couette_1d(6, 0.0)
+    O = oracle_mod.Oracle(m, gb, Kn=0.1)
+    rho, u, T = 1.2, np.array([0.3, -0.1, 0.2]), 1.1
+    mom = O.moments(gauss(O.xi, rho, u, T)[None])
+    assert abs(mom[0] / rho - 1) < 1e-7 and np.abs(mom[1:4] - u).max() < 1e-7 and abs(mom[4] / T - 1) < 1e-7
+    rng = gi.rng_of(5)
+    f = gauss(O.xi, 1.0, [0.2, 0.0, -0.1], 0.9) * (1 + 0.05 * rng.uniform(-1, 1, len(O.w)))
+    mf = O.moments(f[None])
+    g = O.equilibrium(mf)[0]
+    psi = np.stack([np.ones_like(O.w), O.xi[:, 0], O.xi[:, 1], O.xi[:, 2], np.sum(O.xi ** 2, axis=1)])
+    cons = psi @ (O.w * (g - f))
+    assert np.abs(cons).max() < 1e-13 * np.abs(psi @ (O.w * f)).max()
+    f0 = np.stack([gauss(O.xi, 1.0, [0, 0, 0], 1.0)[None]] * 6)
+    f1 = O.sweep(f0, np.arange(6), np.arange(6))
+    assert np.abs(f1 - f0).max() < 1e-8 * f0.max()
+
+
+# ---------------------------------------------------------------------------
 # P10: least squares, Kn_Gll, compaction
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("make", [lambda: gi.quad_cavity_2d(6, 5), lambda: gi.cylinder_tri_2d(n_theta=40, n_rings=10)])
