@@ -422,7 +422,7 @@ namespace {
 
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
-        face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, flags, slot, kin, nkin, newc, nnew, scan,
+        face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
         status, prow, grow, gslot, gcell, ngh, axtab, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
@@ -523,6 +523,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.xv = S.take(8 * 3 * MAXA);
     L.wv = S.take(8 * 3 * MAXA);
     L.vpt = S.take(8 * std::max<size_t>(4, c->vpt.size()));
+    L.vptf = S.take(4 * std::max<size_t>(4, c->vpt.size()));
     L.flags = S.take(4 * nc);
     L.slot = S.take(4 * nc);
     L.kin = S.take(4 * (size_t)cap);
@@ -676,6 +677,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(const double *, xv, xv);
     P(const double *, wv, wv);
     P(const double *, vpt, vpt);
+    P(const float *, vptf, vptf);
     h.points = c->points ? 1 : 0;
     P(int32_t *, flags, flags);
     P(int32_t *, slot_of_cell, slot);
@@ -751,6 +753,11 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(put(L.xv, c->xv, sizeof c->xv));
     HIPCHK(put(L.wv, c->wv, sizeof c->wv));
     HIPCHK(put(L.vpt, c->vpt.data(), 8 * c->vpt.size()));
+    {
+        std::vector<float> vf(c->vpt.begin(), c->vpt.end());
+        HIPCHK(put(L.vptf, vf.data(), 4 * vf.size()));
+        HIPCHK(hipStreamSynchronize(s));   // vf is a host temporary of the async copy
+    }
     HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.flags, 0, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.status, 0, 16, s));
@@ -836,7 +843,7 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
         HIPCHK(launch_ghost(c->cv, h, h.W, s));
-        if (h.fast) HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
+        if (h.fast || h.points) HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
     }
     return GSIS_OK;
 }

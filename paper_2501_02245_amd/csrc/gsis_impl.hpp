@@ -97,6 +97,7 @@ struct CaseView {
     const double *xv;           // [3][MAXA] nodes
     const double *wv;           // [3][MAXA] weights
     const double *vpt;          // point-set grids: [nv][4] node (3) and weight
+    const float *vptf;          // the same rounded to FP32 (node tables of the FP32 kernels)
     int32_t points, pad_p;      // 1: the velocity grid is the point set vpt
     // region
     int32_t *flags;             // [n_cells] 1 = kinetic

@@ -222,6 +222,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_pts(const CaseView *__restrict__ 
             fx = F.fx;
         }
         double acc[15];
+#pragma unroll
         for (int a = 0; a < 15; ++a) acc[a] = 0.0;
         for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
             double xi[3], w;
@@ -231,11 +232,13 @@ __global__ __launch_bounds__(BLOCK) void k_fix_pts(const CaseView *__restrict__ 
             double g = w * exp(-cc * it);
             if (mode == 0) g *= 1.0 + (kq[0] * c0 + kq[1] * c1 + kq[2] * c2) * (cc * it - 2.5);
             const double b[5] = {1.0, c0, c1, c2, cc};
-            int m = 0;
+#pragma unroll
             for (int a = 0; a < 5; ++a)
-                for (int c = a; c < 5; ++c) acc[m++] += g * b[a] * b[c];
+#pragma unroll
+                for (int c = a; c < 5; ++c) acc[a * 5 - a * (a - 1) / 2 + (c - a)] += g * b[a] * b[c];
         }
         // fixed-order block reduction
+#pragma unroll
         for (int m = 0; m < 15; ++m) {
             double v = acc[m];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -737,9 +740,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
     T *fn = fnew + (size_t)slot * C.row;
     const int nvp = C.row / ((VD == 3) ? 1 : 2);   // padded length of one function
 
-    double acc[NSUM];
+    double acc[NSUM], wj[MAXW];
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
 
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
@@ -855,14 +860,152 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
         double re = r0 * dcc;
         if (VD == 2) re += wd * (double)(num1 - den * o1);
         acc[S_RES + 4] += re;
-        // outgoing mass flux through wall faces (numerator of the next rho_w)
-        for (int j = 0; j < nw; ++j) {
-            const FaceS<T> &F = fs[s_wl[j]];
-            const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
-            if (a > (T)0) acc[S_WALL + F.wall] += wd * (double)(a * n0v);
-        }
+        // outgoing mass flux through wall faces (numerator of the next rho_w),
+        // per wall face in registers (a runtime index would put acc in scratch)
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < nw) {
+                const FaceS<T> &F = fs[s_wl[j]];
+                const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
+                if (a > (T)0) wj[j] += wd * (double)(a * n0v);
+            }
         if constexpr (!PTS) vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j)
+#pragma unroll
+        for (int w = 0; w < MAXW; ++w) acc[S_WALL + w] += (j < nw && fs[s_wl[j]].wall == w) ? wj[j] : 0.0;
+    block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+}
+
+// ---------------------------------------------------------------------------
+// the kinetic sweep on point-set grids, faces as rows: every face reads one
+// row -- a kinetic neighbour's VDF, the Grad-13 ghost row of an NS neighbour
+// (built once per sweep) or the patch row of a wall (times rho_w) or the far
+// field -- so the per-node work is the own target (one exp), NF loads and the
+// upwind sums.  Faces are wave-uniform (row bases in SGPRs); the NF loads of a
+// node are issued before they are used; the moment sums are FP64 per thread
+// and block-reduced in a fixed order into the per-(slot, tile) partials.
+// ---------------------------------------------------------------------------
+template <typename P>
+__device__ __forceinline__ P wave_uniform(P p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
+{
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    const int nb = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, nb);
+    int ci = 0;
+    while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
+    const CaseView &C = *B.cv[ci];
+    const int cur = B.cur[ci];
+    const int item = b - B.start[ci];
+    const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
+    const int vt = item / n_kin;
+    const int t = item - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const size_t row = (size_t)C.row;
+    const T *fold = (const T *)C.f[cur];
+    const T *fo = wave_uniform(fold + (size_t)slot * row);
+    T *fn = wave_uniform((T *)C.f[cur ^ 1] + (size_t)slot * row);
+    // faces: row base, scale (rho_w on walls), n S / V, wall-sum index
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    const T *fnb[NF];
+    T fsc[NF], fnx[NF], fny[NF], fnz[NF];
+    int fwall[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fnb[l] = fo;
+        fsc[l] = fnx[l] = fny[l] = fnz[l] = (T)0;
+        fwall[l] = -1;
+        if (l < nf) {
+            const int e = e0 + l;
+            const int oth = C.cf_other[e];
+            fnx[l] = (T)C.cf_nsv[3 * e];
+            fny[l] = (T)C.cf_nsv[3 * e + 1];
+            fnz[l] = (T)C.cf_nsv[3 * e + 2];
+            fsc[l] = (T)1;
+            if (oth >= 0) {
+                const int so = C.slot_of_cell[oth];
+                fnb[l] = (so >= 0) ? fold + (size_t)so * row : (const T *)C.grow + (size_t)C.ghost_slot[oth] * row;
+            } else {
+                fnb[l] = (const T *)C.prow + (size_t)(-1 - oth) * row;
+                fwall[l] = C.cf_wall[e];
+                if (fwall[l] >= 0) fsc[l] = (T)P.rw[fwall[l]];
+            }
+        }
+        fnb[l] = wave_uniform(fnb[l]);
+    }
+    const double u0 = P.u[0], u1 = P.u[1], u2 = P.u[2];
+    const T it = (T)P.it, itau = (T)P.itau, idt = (T)C.inv_dt;
+    const T kq0 = (T)P.kq[0], kq1 = (T)P.kq[1], kq2 = (T)P.kq[2];
+    const T fx0 = (T)P.fx[0], fx1 = (T)P.fx[1], fx2 = (T)P.fx[2], fx3 = (T)P.fx[3], fx4 = (T)P.fx[4];
+    const T tu0 = (T)u0, tu1 = (T)u1, tu2 = (T)u2;
+    double acc[NSUM], wacc[NF];
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) wacc[l] = 0.0;
+    const int k0 = vt * C.tile;
+    const int kend = min(k0 + C.tile, C.nv);
+    for (int k = k0 + (int)threadIdx.x; k < kend; k += BLOCK) {
+        T v[NF];
+#pragma unroll
+        for (int l = 0; l < NF; ++l) v[l] = fnb[l][k];
+        const T o = fo[k];
+        T x0, x1, x2, w;
+        if constexpr (sizeof(T) == 4) {
+            const float4 q = reinterpret_cast<const float4 *>(C.vptf)[k];
+            x0 = q.x, x1 = q.y, x2 = q.z, w = q.w;
+        } else {
+            const double *q = C.vpt + 4 * (size_t)k;
+            x0 = q[0], x1 = q[1], x2 = q[2], w = q[3];
+        }
+        const T c0 = x0 - tu0, c1 = x1 - tu1, c2 = x2 - tu2;
+        const T cc = c0 * c0 + c1 * c1 + c2 * c2;
+        const T g = exp(-cc * it) * (fx0 + fx1 * c0 + fx2 * c1 + fx3 * c2 + fx4 * cc) *
+                    ((T)1 + (kq0 * c0 + kq1 * c1 + kq2 * c2) * (cc * it - (T)2.5));
+        T num = itau * g + idt * o;
+        T den = itau + idt;
+        T ap[NF];
+#pragma unroll
+        for (int l = 0; l < NF; ++l) {
+            const T a = x0 * fnx[l] + x1 * fny[l] + x2 * fnz[l];
+            ap[l] = fmax(a, (T)0);
+            den += ap[l];
+            num -= fmin(a, (T)0) * fsc[l] * v[l];
+        }
+        const T fnv = num / den;
+        fn[k] = fnv;
+        // moment sums relative to u_ref, FP64
+        const double wd = (double)w;
+        const double d0 = (double)x0 - u0, d1 = (double)x1 - u1, d2 = (double)x2 - u2;
+        const double dcc = d0 * d0 + d1 * d1 + d2 * d2;
+        acc_moments<double, 3>(acc, wd, (double)fnv, 0.0, d0, d1, d2, dcc);
+        const double r0 = wd * (double)(num - den * o);
+        acc[S_RES] += r0;
+        acc[S_RES + 1] += r0 * d0;
+        acc[S_RES + 2] += r0 * d1;
+        acc[S_RES + 3] += r0 * d2;
+        acc[S_RES + 4] += r0 * dcc;
+#pragma unroll
+        for (int l = 0; l < NF; ++l) wacc[l] += wd * (double)(ap[l] * fnv);
+    }
+    // outgoing wall sums into their wall slots (static indices: the sums stay in registers)
+#pragma unroll
+    for (int l = 0; l < NF; ++l)
+#pragma unroll
+        for (int w = 0; w < MAXW; ++w) acc[S_WALL + w] += (fwall[l] == w) ? wacc[l] : 0.0;
     block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
 }
 
@@ -870,7 +1013,8 @@ template <typename T, int VD>
 static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
     if (VD == 3 && h0.points) {
-        hipLaunchKernelGGL((k_sweep<T, 3, true>), dim3(total), dim3(BLOCK), 0, s, b);
+        if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_prow<T, 4>), dim3(total), dim3(BLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_sweep_prow<T, MAXF>), dim3(total), dim3(BLOCK), 0, s, b);
         return hipGetLastError();
     }
     int NA3 = h0.n[0] + h0.n[1] + (VD == 3 ? h0.n[2] : 0);
@@ -951,9 +1095,11 @@ __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ 
     const int nw = s_nw;
     T *fr = (T *)C.f[cur] + (size_t)slot * C.row;
     const int nvp = C.row / ((VD == 3) ? 1 : 2);
-    T acc[NSUM];
+    T acc[NSUM], wj[MAXW];
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) acc[i] = (T)0;
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wj[j] = (T)0;
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
     int k = k0 + threadIdx.x;
@@ -1016,12 +1162,18 @@ __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ 
         }
         const T cc = c0 * c0 + c1 * c1 + c2 * c2;
         acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
-        for (int j = 0; j < nw; ++j) {
-            const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
-            if (a > (T)0) acc[S_WALL + s_wi[j]] += w * a * v0;
-        }
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < nw) {
+                const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
+                if (a > (T)0) wj[j] += w * a * v0;
+            }
         if constexpr (!PTS) vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j)
+#pragma unroll
+        for (int ww = 0; ww < MAXW; ++ww) acc[S_WALL + ww] += (j < nw && s_wi[j] == ww) ? wj[j] : (T)0;
     double v[NSUM];
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) v[i] = (double)acc[i];
@@ -1129,9 +1281,11 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
     __syncthreads();
     T *fr = (T *)((mode == 3) ? C.grow : C.f[cur]) + (size_t)slot * C.row;
     const int nvp = C.row / ((VD == 3) ? 1 : 2);
-    T acc[NSUM];
+    T acc[NSUM], wj[MAXW];
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) acc[i] = (T)0;
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wj[j] = (T)0;
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
     int k = k0 + threadIdx.x;
@@ -1187,12 +1341,18 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
             if (VD == 2) fr[nvp + k] = v1;
         }
         acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
-        for (int j = 0; j < nw; ++j) {
-            const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
-            if (a > (T)0) acc[S_WALL + s_wi[j]] += w * a * v0;
-        }
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < nw) {
+                const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
+                if (a > (T)0) wj[j] += w * a * v0;
+            }
         if constexpr (!PTS) vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j)
+#pragma unroll
+        for (int ww = 0; ww < MAXW; ++ww) acc[S_WALL + ww] += (j < nw && s_wi[j] == ww) ? wj[j] : (T)0;
     // zero the padding of this row once
     if (vt == 0 && mode != 2)
         for (int kp = C.nv + threadIdx.x; kp < nvp; kp += BLOCK) {
