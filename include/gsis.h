@@ -117,7 +117,7 @@ gsis_status gsis_destroy_case(gsis_case c);
 gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const int32_t n[3],
                                    const double *const nodes[3], const double *const weights[3]);
 
-/* Non-tensor velocity quadrature (Sec. 4.3 and 5: unstructured / hybrid
+/* Non-tensor velocity quadrature (Sec. 4.3 hybrid and Sec. 4.4 unstructured
  * velocity space): n_points nodes xi [n_points][3] with their own positive
  * weights w [n_points] (host arrays, copied), full 3D velocity space, node k
  * = point k.  Every kinetic kernel then evaluates the Gaussian and Grad-13
