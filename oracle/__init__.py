@@ -49,7 +49,8 @@ class _Grid(C.Structure):
 
 
 class _Gas(C.Structure):
-    _fields_ = [("Kn", C.c_double), ("omega", C.c_double), ("Pr", C.c_double), ("inv_dt", C.c_double)]
+    _fields_ = [("Kn", C.c_double), ("omega", C.c_double), ("Pr", C.c_double), ("inv_dt", C.c_double),
+                ("damp2", C.c_double)]
 
 
 _lib = None
@@ -77,6 +78,11 @@ def lib():
         _lib.oc_macro_residual.argtypes = [P, P, P, P, P]
         _lib.oc_kinetic_residual.restype = C.c_int32
         _lib.oc_kinetic_residual.argtypes = [P, P, C.c_int32, P, P, P, P, P]
+        for name in ("oc_kinetic_slopes", "oc_sweep2", "oc_kinetic_residual2"):
+            getattr(_lib, name).restype = C.c_int32
+        _lib.oc_kinetic_slopes.argtypes = [P, P, C.c_int32, P, P, P, P]
+        _lib.oc_sweep2.argtypes = [P, P, P, C.c_int32, P, P, P, P, P, P]
+        _lib.oc_kinetic_residual2.argtypes = [P, P, C.c_int32, P, P, P, P, P, P]
     return _lib
 
 
@@ -89,10 +95,18 @@ def _f64(a):
 
 
 class Oracle:
-    """Plain FP64 implementation of one steady problem (mesh + gas + grid)."""
+    """Plain FP64 implementation of one steady problem (mesh + gas + grid).
 
-    def __init__(self, mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, inv_dt=0.0):
+    order 2: second-order face values (limited least-squares slopes of every
+    discrete-velocity value, deferred correction of the first-order implicit
+    sweep) with the pseudo-time factor damp2 of that iteration.
+    """
+
+    def __init__(self, mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, inv_dt=0.0, order=1, damp2=2.0):
         L = lib()
+        if order not in (1, 2):
+            raise ValueError("spatial order must be 1 or 2")
+        self.order = order
         self.mesh, self.grid = mesh, grid
         self.vdim = grid["vdim"]
         self.nfun = 1 if self.vdim == 3 else 2
@@ -129,7 +143,7 @@ class Oracle:
             else:
                 self.cg.n[d] = 1
         self.nv = L.oc_nv(C.byref(self.cg))
-        self.gas = _Gas(Kn, omega, Pr, inv_dt)
+        self.gas = _Gas(Kn, omega, Pr, inv_dt, damp2)
         self.Kn, self.omega, self.Pr = Kn, omega, Pr
         # per-node velocities and weights (for tests and diagnostics)
         self.xi, self.w = self._nodes()
@@ -219,11 +233,22 @@ class Oracle:
         if ghost is None:
             ghost = np.zeros((self.mesh["n_cells"], NMOM))
         gh = _f64(ghost)
-        r = lib().oc_sweep(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc), _p(kc), _p(sc),
-                           _p(f_old), _p(gh), _p(f_new))
+        sl = self.slopes(f_old, kc, sc) if self.order == 2 else None
+        r = lib().oc_sweep2(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc), _p(kc), _p(sc),
+                            _p(f_old), _p(gh), _p(sl), _p(f_new))
         if r != 0:
             raise FloatingPointError("oracle sweep failed (%d)" % r)
         return f_new
+
+    def slopes(self, f, kin_cell, slot_of_cell):
+        """Limited least-squares slopes of every discrete-velocity value of the
+        kinetic cells (second-order face values): [n_slots, nfun, nv, 3]."""
+        f = _f64(f)
+        out = np.zeros(f.shape + (3,))
+        kc = np.ascontiguousarray(kin_cell, dtype=np.int32)
+        sc = np.ascontiguousarray(slot_of_cell, dtype=np.int32)
+        lib().oc_kinetic_slopes(C.byref(self.cm), C.byref(self.cg), len(kc), _p(kc), _p(sc), _p(f), _p(out))
+        return out
 
     def lsq(self, phi, bnd):
         """LSQ gradients (Sec. 3.4 Step 2). phi [n_cells, nvar], bnd [n_patches, nvar]."""
@@ -426,7 +451,9 @@ class Oracle:
         sc = np.ascontiguousarray(slot_of_cell, dtype=np.int32)
         gh = _f64(ghost if ghost is not None else np.zeros((self.mesh["n_cells"], NMOM)))
         out = np.zeros((self.mesh["n_cells"], 5))
-        lib().oc_kinetic_residual(C.byref(self.cm), C.byref(self.cg), len(kc), _p(kc), _p(sc), _p(f), _p(gh), _p(out))
+        sl = self.slopes(f, kc, sc) if self.order == 2 else None
+        lib().oc_kinetic_residual2(C.byref(self.cm), C.byref(self.cg), len(kc), _p(kc), _p(sc), _p(f), _p(gh),
+                                   _p(sl), _p(out))
         return out
 
     # --- drivers -------------------------------------------------------------

@@ -339,8 +339,12 @@ static void build_adjacency(const oc_mesh *m, int32_t **ptr_out, int32_t **idx_o
  * its state (Sec. 3.2); diffuse wall -> rho_w M(u_w, T_w) with rho_w from a
  * zero discrete mass flux of f_i^n; far field -> M(rho, u, T) of the patch.
  * ------------------------------------------------------------------------ */
-static double wall_density(const oc_grid *g, const double *fcell, const double *n,
-                           const double *uw, double Tw, double *Mw)
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* scell (nullable): slopes of fcell; the outgoing values at the face are then
+ * the second-order ones fcell + scell . r, r = x_face - x_cell */
+static double wall_density(const oc_grid *g, const double *fcell, const double *scell, const double *r,
+                           const double *n, const double *uw, double Tw, double *Mw)
 {
     /* Mw receives M(1, uw, Tw) at the nodes */
     int32_t nv = oc_nv(g);
@@ -349,7 +353,7 @@ static double wall_density(const oc_grid *g, const double *fcell, const double *
     for (int32_t k = 0; k < nv; ++k) {
         node(g, k, xi, &w);
         double xn = xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2];
-        if (xn > 0) out += w * xn * fcell[k];
+        if (xn > 0) out += w * xn * (fcell[k] + (scell ? dot3(scell + 3 * (size_t)k, r) : 0.0));
         else if (xn < 0) in += w * (-xn) * Mw[k];
     }
     return out / in;
@@ -357,10 +361,12 @@ static double wall_density(const oc_grid *g, const double *fcell, const double *
 
 /* Upwind source rows for the faces of kinetic cell i, all at iterate n:
  * srcp[l] points at the values on the far side of local face l; nrm[4l..]
- * holds the outward unit normal and S/V.  `scratch` has room for nf rows. */
+ * holds the outward unit normal and S/V.  `scratch` has room for nf rows.
+ * si (nullable): slopes of fi, for the second-order outgoing values that fix
+ * the wall densities. */
 static void face_sources(const oc_mesh *m, const oc_grid *g, const int32_t *cptr, const int32_t *cidx,
                          int32_t i, const int32_t *slot_of_cell, const double *f_old, const double *ghost,
-                         const double *fi, double *scratch, double *nrm, const double **srcp)
+                         const double *fi, const double *si, double *scratch, double *nrm, const double **srcp)
 {
     size_t row = (size_t)oc_nfun(g) * oc_nv(g);
     int32_t nf = cptr[i + 1] - cptr[i];
@@ -383,7 +389,9 @@ static void face_sources(const oc_mesh *m, const oc_grid *g, const int32_t *cptr
             int32_t p = -1 - nb;
             const double *ps = m->patch_state + 5 * p;
             if (m->patch_kind[p] == OC_WALL) {
-                double rw = wall_density(g, fi, nrm + 4 * l, ps + 1, ps[4], s);
+                double r[3];
+                for (int d = 0; d < 3; ++d) r[d] = m->face_center[3 * f + d] - m->cell_center[3 * i + d];
+                double rw = wall_density(g, fi, si, r, nrm + 4 * l, ps + 1, ps[4], s);
                 for (size_t k = 0; k < row; ++k) s[k] *= rw;
             } else {
                 oc_maxwellian(g, ps[0], ps + 1, ps[4], s);
@@ -393,9 +401,131 @@ static void face_sources(const oc_mesh *m, const oc_grid *g, const int32_t *cptr
     }
 }
 
-int32_t oc_sweep(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
-                 int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
-                 const double *f_old, const double *ghost, double *f_new)
+/* ------------------------------------------------------------------------
+ * Second-order face values (Sec. 3: the kinetic equation is discretised by
+ * a second-order finite-volume scheme whose details the paper leaves to its
+ * references).  Readings:
+ *  - each discrete-velocity value of a kinetic cell gets a least-squares
+ *    gradient over the cell's kinetic neighbours (weights 1/|dx|^2, the first
+ *    `dim` components; zero when those neighbours do not span `dim`
+ *    dimensions: det(A) <= 1e-12 (tr A / dim)^dim);
+ *  - the gradient is scaled by the Barth-Jespersen factor phi in [0, 1], the
+ *    largest for which every face value f_i + phi g.(x_f - x_i) on a face to a
+ *    kinetic neighbour lies between the smallest and largest of f_i and its
+ *    kinetic neighbours' values;
+ *  - a face value is reconstructed wherever its upwind side is a kinetic
+ *    cell: the outgoing values of every face of a kinetic cell (walls, far
+ *    field and NS interfaces included) and the incoming values from kinetic
+ *    neighbours; incoming wall, far-field and Grad-13 ghost values are the
+ *    face values themselves;
+ *  - the wall density makes the net mass flux of the reconstructed outgoing
+ *    and the wall's incoming values zero.
+ * slope[n_slots][nfun * nv][3] = phi g, components beyond dim zero.
+ * ------------------------------------------------------------------------ */
+static int lsq_singular(int dim, const double *A)
+{
+    double tr = 0, det;
+    for (int d = 0; d < dim; ++d) tr += A[d * dim + d];
+    if (dim == 1) det = A[0];
+    else if (dim == 2) det = A[0] * A[3] - A[1] * A[2];
+    else
+        det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+              A[2] * (A[3] * A[7] - A[4] * A[6]);
+    return !(tr > 0) || det <= 1e-12 * pow(tr / dim, dim);
+}
+
+int32_t oc_kinetic_slopes(const oc_mesh *m, const oc_grid *g, int32_t n_kin, const int32_t *kin_cell,
+                          const int32_t *slot_of_cell, const double *f, double *slope)
+{
+    int32_t nv = oc_nv(g), nfun = oc_nfun(g);
+    size_t row = (size_t)nfun * nv;
+    int dim = m->dim;
+    int32_t *cptr, *cidx;
+    build_adjacency(m, &cptr, &cidx);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t t = 0; t < n_kin; ++t) {
+        int32_t i = kin_cell[t];
+        const double *fi = f + (size_t)slot_of_cell[i] * row;
+        double *si = slope + (size_t)slot_of_cell[i] * row * 3;
+        memset(si, 0, sizeof(double) * row * 3);
+        /* kinetic neighbours: centre offsets and face-centre offsets */
+        int32_t nk = 0;
+        int32_t nbr[64];
+        double dx[64][3], rf[64][3], A[9] = {0};
+        for (int32_t l = cptr[i]; l < cptr[i + 1]; ++l) {
+            int32_t fc = cidx[l];
+            int32_t own = m->face_cells[2 * fc], oth = m->face_cells[2 * fc + 1];
+            int32_t nb = (own == i) ? oth : own;
+            if (nb < 0 || slot_of_cell[nb] < 0 || nk == 64) continue;
+            nbr[nk] = nb;
+            for (int d = 0; d < 3; ++d) {
+                dx[nk][d] = m->cell_center[3 * nb + d] - m->cell_center[3 * i + d];
+                rf[nk][d] = m->face_center[3 * fc + d] - m->cell_center[3 * i + d];
+            }
+            double r2 = 0;
+            for (int d = 0; d < dim; ++d) r2 += dx[nk][d] * dx[nk][d];
+            for (int a = 0; a < dim; ++a)
+                for (int c = 0; c < dim; ++c) A[a * dim + c] += dx[nk][a] * dx[nk][c] / r2;
+            ++nk;
+        }
+        if (nk == 0 || lsq_singular(dim, A)) continue;
+        for (size_t k = 0; k < row; ++k) {
+            double b[3] = {0, 0, 0}, Ak[9];
+            double dmax = 0, dmin = 0;
+            for (int32_t j = 0; j < nk; ++j) {
+                double df = f[(size_t)slot_of_cell[nbr[j]] * row + k] - fi[k];
+                double r2 = 0;
+                for (int d = 0; d < dim; ++d) r2 += dx[j][d] * dx[j][d];
+                for (int d = 0; d < dim; ++d) b[d] += dx[j][d] * df / r2;
+                if (df > dmax) dmax = df;
+                if (df < dmin) dmin = df;
+            }
+            memcpy(Ak, A, sizeof A);
+            if (solve_small(dim, Ak, b) != 0) continue;
+            /* Barth-Jespersen factor over the faces to kinetic neighbours */
+            double phi = 1.0;
+            for (int32_t j = 0; j < nk; ++j) {
+                double ext = 0;
+                for (int d = 0; d < dim; ++d) ext += b[d] * rf[j][d];
+                if (ext > 0) phi = fmin(phi, dmax / ext);
+                else if (ext < 0) phi = fmin(phi, dmin / ext);
+            }
+            for (int d = 0; d < dim; ++d) si[k * 3 + d] = phi * b[d];
+        }
+    }
+    free(cptr);
+    free(cidx);
+    return 0;
+}
+
+/* face-centre offset r_own = x_face - x_i of local face l of cell i; for a
+ * kinetic neighbour also r_nb = x_face - x_nb and its slot (else -1) */
+static int32_t face_offsets(const oc_mesh *m, const int32_t *cptr, const int32_t *cidx, int32_t i, int32_t l,
+                            const int32_t *slot_of_cell, double *r_own, double *r_nb)
+{
+    int32_t f = cidx[cptr[i] + l];
+    int32_t own = m->face_cells[2 * f], oth = m->face_cells[2 * f + 1];
+    int32_t nb = (own == i) ? oth : own;
+    for (int d = 0; d < 3; ++d) r_own[d] = m->face_center[3 * f + d] - m->cell_center[3 * i + d];
+    if (nb < 0 || slot_of_cell[nb] < 0) return -1;
+    for (int d = 0; d < 3; ++d) r_nb[d] = m->face_center[3 * f + d] - m->cell_center[3 * nb + d];
+    return slot_of_cell[nb];
+}
+
+/* The sweep below with second-order face values when slope is non-null:
+ * the first-order implicit operator is kept, and the difference between the
+ * reconstructed and first-order face fluxes, evaluated at iterate n, moves to
+ * the right-hand side (deferred correction):
+ *   outflow face (a > 0), any face:           num -= a (s_i . r_i)
+ *   inflow face (a < 0) from a kinetic cell:  num += |a| (f_j + s_j . r_j)
+ * with r = x_face - x_cell of the cell whose slope is used.  The point-Jacobi
+ * iteration of this operator diverges without damping (its explicit
+ * second-order terms couple downwind); a cell-wise pseudo-time term
+ * (f_i^{n+1/2} - f_i^n)/dt_i, sized by the cell's largest outflow rate, makes
+ * it converge and leaves its fixed point unchanged. */
+static int32_t sweep_body(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                          int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                          const double *f_old, const double *ghost, const double *slope, double *f_new)
 {
     int32_t nv = oc_nv(g), nfun = oc_nfun(g);
     size_t row = (size_t)nfun * nv;
@@ -417,26 +547,76 @@ int32_t oc_sweep(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
         double *nrm = (double *)malloc(sizeof(double) * 4 * (size_t)(nf > 0 ? nf : 1));
         const double **srcp = (const double **)malloc(sizeof(double *) * (size_t)(nf > 0 ? nf : 1));
         if (oc_equilibrium(g, gas, mom, geq) != 0) err = -7;
-        face_sources(m, g, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, src, nrm, srcp);
+        const double *si = slope ? slope + (size_t)slot_of_cell[i] * row * 3 : NULL;
+        face_sources(m, g, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, si, src, nrm, srcp);
+        /* pseudo-time step of the deferred-correction iteration (reading):
+         * 1/dt_i = damp2 * max_k sum_{a_k > 0} a_k, the largest outflow rate
+         * of the cell over the velocity grid; it vanishes at convergence */
+        double inv_dt2 = 0.0;
+        if (si) {
+            double xk[3], wk;
+            for (int32_t k = 0; k < nv; ++k) {
+                node(g, k, xk, &wk);
+                double out = 0.0;
+                for (int32_t l = 0; l < nf; ++l) {
+                    double a = (xk[0] * nrm[4 * l] + xk[1] * nrm[4 * l + 1] + xk[2] * nrm[4 * l + 2]) * nrm[4 * l + 3];
+                    if (a > 0) out += a;
+                }
+                if (out > inv_dt2) inv_dt2 = out;
+            }
+            inv_dt2 *= gas->damp2;
+        }
+        int32_t *kslot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nf > 0 ? nf : 1));
+        double *rown = (double *)malloc(sizeof(double) * 6 * (size_t)(nf > 0 ? nf : 1));
+        for (int32_t l = 0; l < nf; ++l)
+            kslot[l] = face_offsets(m, cptr, cidx, i, l, slot_of_cell, rown + 6 * l, rown + 6 * l + 3);
         double xi[3], w;
         for (int32_t k = 0; k < nv; ++k) {
             node(g, k, xi, &w);
             double den = gas->inv_dt + 1.0 / tau;
             double num[2];
             for (int32_t q = 0; q < nfun; ++q) num[q] = gas->inv_dt * fi[q * nv + k] + geq[q * nv + k] / tau;
+            if (si) {
+                den += inv_dt2;
+                for (int32_t q = 0; q < nfun; ++q) num[q] += inv_dt2 * fi[q * nv + k];
+            }
             for (int32_t l = 0; l < nf; ++l) {
                 double a = (xi[0] * nrm[4 * l] + xi[1] * nrm[4 * l + 1] + xi[2] * nrm[4 * l + 2]) * nrm[4 * l + 3];
-                if (a > 0) den += a;
-                else if (a < 0)
+                if (a > 0) {
+                    den += a;
+                    if (si)
+                        for (int32_t q = 0; q < nfun; ++q)
+                            num[q] -= a * dot3(si + ((size_t)q * nv + k) * 3, rown + 6 * l);
+                } else if (a < 0) {
                     for (int32_t q = 0; q < nfun; ++q) num[q] += -a * srcp[l][q * nv + k];
+                    if (si && kslot[l] >= 0) {
+                        const double *sj = slope + (size_t)kslot[l] * row * 3;
+                        for (int32_t q = 0; q < nfun; ++q)
+                            num[q] += -a * dot3(sj + ((size_t)q * nv + k) * 3, rown + 6 * l + 3);
+                    }
+                }
             }
             for (int32_t q = 0; q < nfun; ++q) fo[q * nv + k] = num[q] / den;
         }
-        free(geq); free(src); free(nrm); free(srcp);
+        free(geq); free(src); free(nrm); free(srcp); free(kslot); free(rown);
     }
     free(cptr);
     free(cidx);
     return err;
+}
+
+int32_t oc_sweep(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                 int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                 const double *f_old, const double *ghost, double *f_new)
+{
+    return sweep_body(m, g, gas, n_kin, kin_cell, slot_of_cell, f_old, ghost, NULL, f_new);
+}
+
+int32_t oc_sweep2(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                  int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                  const double *f_old, const double *ghost, const double *slope, double *f_new)
+{
+    return sweep_body(m, g, gas, n_kin, kin_cell, slot_of_cell, f_old, ghost, slope, f_new);
 }
 
 /* ------------------------------------------------------------------------
@@ -447,9 +627,9 @@ int32_t oc_sweep(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
  * with the same upwind values as the sweep.  R[n_cells][5] = (mass,
  * momentum, energy) per unit volume; rows of non-kinetic cells are zero.
  * ------------------------------------------------------------------------ */
-int32_t oc_kinetic_residual(const oc_mesh *m, const oc_grid *g,
-                            int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
-                            const double *f_old, const double *ghost, double *R)
+static int32_t residual_body(const oc_mesh *m, const oc_grid *g,
+                             int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                             const double *f_old, const double *ghost, const double *slope, double *R)
 {
     int32_t nv = oc_nv(g), nfun = oc_nfun(g);
     size_t row = (size_t)nfun * nv;
@@ -464,15 +644,25 @@ int32_t oc_kinetic_residual(const oc_mesh *m, const oc_grid *g,
         double *src = (double *)malloc(sizeof(double) * row * (size_t)(nf > 0 ? nf : 1));
         double *nrm = (double *)malloc(sizeof(double) * 4 * (size_t)(nf > 0 ? nf : 1));
         const double **srcp = (const double **)malloc(sizeof(double *) * (size_t)(nf > 0 ? nf : 1));
-        face_sources(m, g, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, src, nrm, srcp);
+        const double *si = slope ? slope + (size_t)slot_of_cell[i] * row * 3 : NULL;
+        face_sources(m, g, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, si, src, nrm, srcp);
         double acc[5] = {0, 0, 0, 0, 0}, xi[3], w;
         for (int32_t l = 0; l < nf; ++l) {
+            double rr[6];
+            int32_t ks = face_offsets(m, cptr, cidx, i, l, slot_of_cell, rr, rr + 3);
             for (int32_t k = 0; k < nv; ++k) {
                 node(g, k, xi, &w);
                 double a = (xi[0] * nrm[4 * l] + xi[1] * nrm[4 * l + 1] + xi[2] * nrm[4 * l + 2]) * nrm[4 * l + 3];
                 const double *up = (a > 0) ? fi : srcp[l];
                 double fphi = up[k];
                 double fpsi = (nfun == 2) ? up[nv + k] : 0.0;
+                if (si && (a > 0 || ks >= 0)) {
+                    /* reconstructed value of a kinetic upwind side */
+                    const double *su = (a > 0) ? si : slope + (size_t)ks * row * 3;
+                    const double *r = (a > 0) ? rr : rr + 3;
+                    fphi += dot3(su + (size_t)k * 3, r);
+                    if (nfun == 2) fpsi += dot3(su + ((size_t)nv + k) * 3, r);
+                }
                 double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
                 acc[0] -= w * a * fphi;
                 for (int d = 0; d < 3; ++d) acc[1 + d] -= w * a * xi[d] * fphi;
@@ -485,6 +675,20 @@ int32_t oc_kinetic_residual(const oc_mesh *m, const oc_grid *g,
     free(cptr);
     free(cidx);
     return 0;
+}
+
+int32_t oc_kinetic_residual(const oc_mesh *m, const oc_grid *g,
+                            int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                            const double *f_old, const double *ghost, double *R)
+{
+    return residual_body(m, g, n_kin, kin_cell, slot_of_cell, f_old, ghost, NULL, R);
+}
+
+int32_t oc_kinetic_residual2(const oc_mesh *m, const oc_grid *g,
+                             int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                             const double *f_old, const double *ghost, const double *slope, double *R)
+{
+    return residual_body(m, g, n_kin, kin_cell, slot_of_cell, f_old, ghost, slope, R);
 }
 
 /* ------------------------------------------------------------------------

@@ -65,6 +65,7 @@ typedef struct {
     double omega;   /* viscosity index, mu ~ T^omega */
     double Pr;      /* A_tt of the monatomic gas = Prandtl number */
     double inv_dt;  /* 1/dt of the kinetic update; 0 = steady iteration */
+    double damp2;   /* second-order sweeps: pseudo-time 1/dt_i = damp2 max_k sum_{a_k>0} a_k */
 } oc_gas;
 
 int32_t oc_nv(const oc_grid *g);
@@ -105,12 +106,30 @@ int32_t oc_sweep(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
                  int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
                  const double *f_old, const double *ghost, double *f_new);
 
+/* Limited least-squares slopes of every discrete-velocity value of the
+ * kinetic cells (second-order face values; the readings are stated in the
+ * source).  slope[n_slots][nfun * nv][3], addressed by slot_of_cell. */
+int32_t oc_kinetic_slopes(const oc_mesh *m, const oc_grid *g, int32_t n_kin, const int32_t *kin_cell,
+                          const int32_t *slot_of_cell, const double *f, double *slope);
+
+/* oc_sweep with second-order face values on faces between kinetic cells,
+ * as a deferred correction of the first-order implicit operator; slope from
+ * oc_kinetic_slopes of f_old (NULL: first order, the same as oc_sweep). */
+int32_t oc_sweep2(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                  int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                  const double *f_old, const double *ghost, const double *slope, double *f_new);
+
 /* Moment balance of the kinetic scheme at f (per unit volume): R[n_cells][5]
  * = -sum_faces (S/V) sum_k w (xi.n) (1, xi, |xi|^2) f_upwind; zero rows for
  * non-kinetic cells. */
 int32_t oc_kinetic_residual(const oc_mesh *m, const oc_grid *g,
                             int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
                             const double *f_old, const double *ghost, double *R);
+
+/* The same balance with the second-order face values of oc_sweep2. */
+int32_t oc_kinetic_residual2(const oc_mesh *m, const oc_grid *g,
+                             int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                             const double *f_old, const double *ghost, const double *slope, double *R);
 
 /* Least-squares cell gradients of nvar fields phi[n_cells][nvar];
  * bnd[n_patches][nvar] holds boundary values (NaN = use the cell value).
