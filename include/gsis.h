@@ -126,6 +126,25 @@ gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const int32_t n[3]
  * correction kernels run.  1..2^24 points. */
 gsis_status gsis_set_velocity_points(gsis_case c, int32_t n_points, const double *xi, const double *w);
 
+/* Spatial order of the kinetic face values (Sec. 3: second-order finite
+ * volumes; the paper leaves the scheme to its references).  order 1
+ * (default): first-order upwind.  order 2: every discrete-velocity value of a
+ * kinetic cell gets a least-squares slope over the cell's kinetic neighbours
+ * (zero when they do not span the mesh dimension), scaled by the
+ * Barth-Jespersen factor that keeps the face values to kinetic neighbours
+ * within the range of the cell and those neighbours; every face whose upwind
+ * side is a kinetic cell takes the reconstructed value, as a deferred
+ * correction of the first-order implicit operator, and the wall densities
+ * zero the net mass flux of the reconstructed outgoing values.  The sweep
+ * then adds the pseudo-time term (f^{n+1/2} - f^n)/dt_i with 1/dt_i = damp *
+ * max_k sum_{a_k > 0} a_k (the cell's largest outflow rate; damp >= 0,
+ * typically 2): without it the point-Jacobi iteration of the corrected
+ * operator diverges; it vanishes at convergence.  Order 2 uses the generic
+ * (non-plane) sweep kernel and adds a slope array of dim * (VDF row) per
+ * kinetic slot to the footprint.  Call before gsis_case_footprint / bind
+ * (E_STATE once bound); E_ARG for order not 1 or 2 or a bad damp. */
+gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double damp);
+
 /* Device bytes needed to bind the case with room for `kinetic_capacity`
  * kinetic cells (VDF double buffer, per-cell sums and parameters, mesh and
  * macroscopic arrays). */
@@ -154,6 +173,7 @@ gsis_status gsis_set_state(gsis_case c, const double *W_dev, const void *vdf_dev
  * stream syncs) each case's VDF is f^{n+1/2} and its W holds the moments on
  * kinetic cells. */
 gsis_status gsis_kinetic_sweep(gsis_case const *cases, int32_t n_cases, int32_t n_sweeps, void *stream);
+/* (Batched cases must also share the spatial order.) */
 
 /* Moments of the current VDF (Sec. 2 eq. getmoment): out_dev [n_kin][14]
  * FP64 in ascending cell id (may be null when there is no kinetic cell);
@@ -263,7 +283,8 @@ gsis_status gsis_macro_solve(gsis_case c, double *W_dev, const double *hot_dev, 
                              int32_t n_inner, double cfl, void *stream);
 
 /* Duration in ms of the last kinetic-sweep kernel launched on this case
- * (HIP events on the launch stream; synchronises). */
+ * (HIP events on the launch stream; synchronises).  At spatial order 2 the
+ * interval also covers the slope kernels launched just before the sweep. */
 gsis_status gsis_last_sweep_ms(gsis_case c, float *ms);
 
 /* Sweep layout chosen at bind (all outputs host, nullable): *fast = 1 when the

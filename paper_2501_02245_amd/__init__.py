@@ -30,6 +30,7 @@ EXPORTS = [
     "gsis_moments", "gsis_n_kinetic", "gsis_update_regions", "gsis_step", "gsis_solve_steady", "gsis_get_vdf",
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
     "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
+    "gsis_set_spatial_order",
 ]
 
 
@@ -108,6 +109,7 @@ def lib():
             "gsis_ns_init": [P, I32, P, P, P],
             "gsis_n_wall_faces": [P, P], "gsis_surface": [P, P, P, P, P],
             "gsis_set_velocity_points": [P, I32, P, P],
+            "gsis_set_spatial_order": [P, I32, D],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -213,7 +215,10 @@ def footprint(mesh: Mesh, grid, Kn, dtype=F32, capacity=None, omega=0.5, Pr=2.0 
 class Case:
     """One steady problem bound to a torch-allocated device workspace."""
 
-    def __init__(self, mesh: Mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, dtype=F32, capacity=None):
+    def __init__(self, mesh: Mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, dtype=F32, capacity=None,
+                 order=1, damp2=2.0):
+        """order 2: second-order face values with pseudo-time factor damp2
+        (gsis_set_spatial_order)."""
         import torch
         self.mesh = mesh
         self.dtype = dtype
@@ -223,6 +228,8 @@ class Case:
         _check(lib().gsis_create_case(mesh.handle, C.byref(_Gas(Kn, omega, Pr)), dtype, C.byref(h)))
         self.handle = h
         self._grid = _set_grid(h, grid)
+        self.order = int(order)
+        _check(lib().gsis_set_spatial_order(h, self.order, C.c_double(damp2)))
         self.points = grid.get("kind") == "points"
         self.nv = grid_nv(grid)
         self.capacity = int(capacity or mesh.n_cells)

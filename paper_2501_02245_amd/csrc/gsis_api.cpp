@@ -74,6 +74,8 @@ struct gsis_case_s {
     double xv[3][MAXA], wv[3][MAXA];
     std::vector<double> vpt;    // point-set grid: [nv][4] = xi (3), w
     bool points = false;
+    int32_t order = 1;          // spatial order of the kinetic face values
+    double damp2 = 2.0;         // pseudo-time factor of the order-2 iteration
     bool grid_set = false, bound = false, state_set = false;
     int32_t capacity = 0, tile = 0, ntile = 0, row = 0;
     unsigned char *ws = nullptr;
@@ -418,12 +420,23 @@ extern "C" gsis_status gsis_set_velocity_points(gsis_case c, int32_t np, const d
     return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double damp)
+{
+    if (!c) return fail(GSIS_E_ARG, "null case");
+    if (c->bound) return fail(GSIS_E_STATE, "spatial order must be set before binding");
+    if (order != 1 && order != 2) return fail(GSIS_E_ARG, "spatial order must be 1 or 2");
+    if (!(damp >= 0.0) || !std::isfinite(damp)) return fail(GSIS_E_ARG, "damp must be finite and >= 0");
+    c->order = order;
+    c->damp2 = damp;
+    return GSIS_OK;
+}
+
 namespace {
 
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
-        status, prow, grow, gslot, gcell, ngh, axtab, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
+        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
 
@@ -446,7 +459,7 @@ TileChoice choose_tile(const gsis_case_s *c, int64_t cap)
     if (env) target = std::atoi(env);
     if (target < BLOCK) target = BLOCK;
     const char *gen = std::getenv("GSIS_GENERIC_SWEEP");
-    const bool allow_fast = !(gen && gen[0] == '1') && !c->points;
+    const bool allow_fast = !(gen && gen[0] == '1') && !c->points && c->order == 1;
     const int nx = c->n[0], ny = c->n[1], nz = c->n[2];
     TileChoice t{};
     if (allow_fast && c->vdim == 3 && BLOCK % nz == 0 && (ny * nz) % BLOCK == 0) {
@@ -539,6 +552,10 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.gcell = S.take(4 * gcap);
     L.ngh = S.take(16);
     L.axtab = S.take(es * (size_t)cap * axtab_len(c));
+    const bool o2 = c->order == 2;
+    L.slope = S.take(o2 ? es * (size_t)cap * m->dim * (*row) : 0);
+    L.amax = S.take(o2 ? 8 * nc : 0);
+    L.wsl = S.take(o2 ? 8 * (size_t)cap * (*ntile) * MAXW : 0);
     L.f0 = S.take(es * (size_t)cap * (*row));
     L.f1 = S.take(es * (size_t)cap * (*row));
     L.param = S.take(sizeof(ParamRec) * (size_t)cap);
@@ -704,6 +721,13 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
         const char *renv = std::getenv("GSIS_SWEEP_ROT");
         h.rot = renv ? std::max(0, std::atoi(renv)) : 0;
     }
+    h.sorder = c->order;
+    h.damp2 = c->damp2;
+    if (c->order == 2) {
+        P(void *, slope, slope);
+        P(double *, amax, amax);
+        P(double *, wsl, wsl);
+    }
     P(ParamRec *, param, param);
     P(FeqRec *, feq, feq);
     P(double *, partial, partial);
@@ -771,6 +795,10 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(hipMemsetAsync(B + L.f1, 0, L.param - L.f1, s));
     HIPCHK(launch_wall_den(c->cv, h, s));
     HIPCHK(launch_patch_rows(c->cv, h, s));
+    if (c->order == 2) {
+        HIPCHK(hipMemsetAsync(B + L.wsl, 0, L.f0 - L.wsl, s));
+        HIPCHK(launch_amax(c->cv, h, s));
+    }
     if (!c->ev0) {
         HIPCHK(hipEventCreate(&c->ev0));
         HIPCHK(hipEventCreate(&c->ev1));
@@ -868,6 +896,12 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         b.group = cases[i0]->hv.group;
         b.rot = cases[i0]->hv.rot;
         if (timed && i0 == 0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
+        // order 2: limited slopes of every case's f^n (the sweep reads its own
+        // and its neighbours')
+        for (int j = 0; j < m; ++j) {
+            gsis_case c = cases[i0 + j];
+            if (c->order == 2) HIPCHK(launch_slope(c->cv, c->hv, c->n_kin, c->cur, s));
+        }
         HIPCHK(launch_sweep(b, cases[i0]->hv, b.start[m], s));
         if (timed && i0 + MAX_BATCH >= n) HIPCHK(hipEventRecord(cases[0]->ev1, s));
     }
@@ -885,8 +919,9 @@ gsis_status check_batch(gsis_case const *cases, int n)
         gsis_status st = check_ready(cases[j]);
         if (st) return st;
         if (cases[j]->dtype != cases[0]->dtype || cases[j]->vdim != cases[0]->vdim ||
-            cases[j]->hv.fast != cases[0]->hv.fast || cases[j]->points != cases[0]->points)
-            return fail(GSIS_E_ARG, "batched cases must share dtype, vdim, grid kind and sweep layout");
+            cases[j]->hv.fast != cases[0]->hv.fast || cases[j]->points != cases[0]->points ||
+            cases[j]->order != cases[0]->order)
+            return fail(GSIS_E_ARG, "batched cases must share dtype, vdim, grid kind, spatial order and sweep layout");
         for (int d = 0; d < 3; ++d)
             if (cases[j]->n[d] > cases[0]->n[d] && j > 0) {
                 // LDS is sized from the first case: put the largest grid first

@@ -122,6 +122,15 @@ struct CaseView {
     int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major,
                                 // 2 = groups of `group` cells, tile-major inside a group
     int32_t group, rot;
+    // spatial order 2 (second-order face values): slopes [capacity][dim][row]
+    // in the case dtype, each cell's largest outflow rate amax [n_cells], and
+    // per (slot, tile) sums over the wall faces wsl [capacity][ntile][MAXW]
+    // of sum_{a>0} w a (s . r) (the slope part of the next wall densities)
+    int32_t sorder, pad_o;
+    double damp2;
+    void *slope;
+    double *amax;
+    double *wsl;
     // kinetic state
     void *f[2];                 // VDF double buffer [capacity][row]
     ParamRec *param;            // [capacity]
@@ -216,6 +225,9 @@ hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total_items, hip
 // (gsis_sweep.hip) tensor grids whose fastest axis divides the block
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
 hipError_t launch_axtab(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+// spatial order 2: largest outflow rate per cell (at bind), limited slopes of f[cur]
+hipError_t launch_amax(const CaseView *cv, const CaseView &h, hipStream_t s);
+hipError_t launch_slope(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_patch_rows(const CaseView *cv, const CaseView &h, hipStream_t s);

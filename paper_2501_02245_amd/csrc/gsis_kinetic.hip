@@ -557,6 +557,223 @@ hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipSt
 }
 
 // ---------------------------------------------------------------------------
+// second-order face values (Sec. 3 second-order finite volumes; the scheme is
+// left to the paper's references).  Slope of every discrete-velocity value of
+// a kinetic cell: least squares over the kinetic neighbours (weights
+// 1/|dx|^2, the mesh's `dim` components; zero when the neighbours do not span
+// them: det A <= 1e-12 (tr A / dim)^dim), times the Barth-Jespersen factor
+// that keeps every face value to a kinetic neighbour inside the range of the
+// cell and those neighbours.  One block per (kinetic cell, velocity tile), the
+// geometry of the cell's stencil formed once in FP64 by one thread (the
+// inverse normal matrix folded into per-neighbour coefficient vectors), then
+// one lane per velocity node: 1 + n_k row reads (the neighbour rows are the
+// ones the sweep reads next), dim stores.  The block also sums, per wall face,
+// sum_{a>0} w a (s . r_w) of the first function: the slope part of the
+// outgoing mass flux that fixes the next wall density.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cvp, int n_kin, int cur)
+{
+    const CaseView &C = *cvp;
+    __shared__ T s_c[MAXF][3], s_r[MAXF][3];
+    __shared__ int s_nb[MAXF];
+    __shared__ double s_wn[MAXW][3];
+    __shared__ T s_wr[MAXW][3];
+    __shared__ int s_ww[MAXW];
+    __shared__ int s_nk, s_nw;
+    __shared__ double red[(BLOCK / 64) * MAXW];
+    // set-up work arrays of thread 0 (in LDS: runtime-indexed registers would spill)
+    __shared__ double dx[MAXF][3], iw[MAXF], A[9], I[9];
+    const int vt = blockIdx.x / n_kin;
+    const int t = blockIdx.x - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const int D = C.dim;
+    if (threadIdx.x == 0) {
+        const int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1];
+        const double *xc = C.cell_center + 3 * (size_t)cell;
+        for (int i = 0; i < 9; ++i) A[i] = I[i] = 0.0;
+        int nk = 0, nw = 0;
+        for (int e = e0; e < e1; ++e) {
+            const int oth = C.cf_other[e];
+            const double *fc = C.face_center + 3 * (size_t)C.cf_face[e];
+            if (C.cf_wall[e] >= 0 && nw < MAXW) {
+                s_ww[nw] = C.cf_wall[e];
+                for (int d = 0; d < 3; ++d) {
+                    s_wn[nw][d] = C.cf_nsv[3 * (size_t)e + d];
+                    s_wr[nw][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
+                }
+                ++nw;
+            }
+            if (oth < 0 || C.slot_of_cell[oth] < 0) continue;
+            const double *xo = C.cell_center + 3 * (size_t)oth;
+            double r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                dx[nk][d] = (d < D) ? xo[d] - xc[d] : 0.0;
+                r2 += dx[nk][d] * dx[nk][d];
+            }
+            iw[nk] = 1.0 / r2;
+            for (int a = 0; a < D; ++a)
+                for (int b = 0; b < D; ++b) A[a * D + b] += dx[nk][a] * dx[nk][b] * iw[nk];
+            s_nb[nk] = C.slot_of_cell[oth];
+            for (int d = 0; d < 3; ++d) s_r[nk][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
+            ++nk;
+        }
+        double tr = 0.0, det;
+        for (int d = 0; d < D; ++d) tr += A[d * D + d];
+        if (D == 1) {
+            det = A[0];
+            I[0] = 1.0 / A[0];
+        } else if (D == 2) {
+            det = A[0] * A[3] - A[1] * A[2];
+            I[0] = A[3] / det;
+            I[1] = -A[1] / det;
+            I[2] = -A[2] / det;
+            I[3] = A[0] / det;
+        } else {
+            const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+            det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+            I[0] = c00 / det;
+            I[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+            I[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+            I[3] = c01 / det;
+            I[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+            I[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+            I[6] = c02 / det;
+            I[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+            I[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+        }
+        const bool singular = nk == 0 || !(tr > 0.0) || det <= 1e-12 * pow(tr / D, (double)D);
+        if (singular) nk = 0;
+        for (int j = 0; j < nk; ++j)
+            for (int d = 0; d < 3; ++d) {
+                double c = 0.0;
+                if (d < D)
+                    for (int b = 0; b < D; ++b) c += I[d * D + b] * dx[j][b] * iw[j];
+                s_c[j][d] = (T)c;
+            }
+        s_nk = nk;
+        s_nw = nw;
+    }
+    __syncthreads();
+    const int nk = s_nk, nw = s_nw;
+    const T *__restrict__ fo = (const T *)C.f[cur];
+    T *__restrict__ sl = (T *)C.slope;
+    const size_t row = (size_t)C.row;
+    const int nvp = C.row / C.nfun;
+    const T *fi_row = fo + (size_t)slot * row;
+    T *so = sl + (size_t)slot * D * row;
+    const int k0 = vt * C.tile;
+    const int kend = min(k0 + C.tile, C.nv);
+    double wacc[MAXW];
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wacc[j] = 0.0;
+    for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
+        T w0 = (T)0, w1 = (T)0, w2 = (T)0;   // slope of the first function
+        for (int q = 0; q < C.nfun; ++q) {
+            const size_t kk = (size_t)q * nvp + k;
+            const T fi = fi_row[kk];
+            T g0 = (T)0, g1 = (T)0, g2 = (T)0, dmax = (T)0, dmin = (T)0;
+            for (int j = 0; j < nk; ++j) {
+                const T d = fo[(size_t)s_nb[j] * row + kk] - fi;
+                g0 += s_c[j][0] * d;
+                g1 += s_c[j][1] * d;
+                g2 += s_c[j][2] * d;
+                dmax = fmax(dmax, d);
+                dmin = fmin(dmin, d);
+            }
+            T phi = (T)1;
+            for (int j = 0; j < nk; ++j) {
+                const T ext = g0 * s_r[j][0] + g1 * s_r[j][1] + g2 * s_r[j][2];
+                if (ext > (T)0) phi = fmin(phi, dmax / ext);
+                else if (ext < (T)0) phi = fmin(phi, dmin / ext);
+            }
+            g0 *= phi;
+            g1 *= phi;
+            g2 *= phi;
+            so[kk] = g0;
+            if (D > 1) so[row + kk] = g1;
+            if (D > 2) so[2 * row + kk] = g2;
+            if (q == 0) {
+                w0 = g0;
+                w1 = g1;
+                w2 = g2;
+            }
+        }
+        if (nw > 0) {
+            double xi[3], wd;
+            vnode(C, k, xi, wd);
+#pragma unroll
+            for (int j = 0; j < MAXW; ++j)
+                if (j < nw) {
+                    const double a = xi[0] * s_wn[j][0] + xi[1] * s_wn[j][1] + xi[2] * s_wn[j][2];
+                    if (a > 0.0) wacc[j] += wd * a * (double)(w0 * s_wr[j][0] + w1 * s_wr[j][1] + w2 * s_wr[j][2]);
+                }
+        }
+    }
+    // per wall index (static selects keep the sums in registers)
+    double wsum[MAXW];
+#pragma unroll
+    for (int w = 0; w < MAXW; ++w) {
+        wsum[w] = 0.0;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j) wsum[w] += (j < nw && s_ww[j] == w) ? wacc[j] : 0.0;
+    }
+    block_reduce_store<MAXW>(wsum, C.wsl + ((size_t)slot * C.ntile + vt) * MAXW, red);
+}
+
+hipError_t launch_slope(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    const int blocks = n_kin * h.ntile;
+    if (h.dtype == GSIS_F32) hipLaunchKernelGGL(k_slope<float>, dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+    else hipLaunchKernelGGL(k_slope<double>, dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+    return hipGetLastError();
+}
+
+// each cell's largest outflow rate over the velocity grid,
+// amax = max_k sum_{a_k > 0} a_k (a = xi.n S/V): the pseudo-time scale of the
+// second-order iteration (one block per cell, FP64)
+__global__ __launch_bounds__(BLOCK) void k_amax(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    __shared__ double nsv[MAXF][3];
+    __shared__ double red[BLOCK / 64];
+    const int cell = blockIdx.x;
+    const int e0 = C.cf_ptr[cell], nf = C.cf_ptr[cell + 1] - e0;
+    if (threadIdx.x < nf)
+        for (int d = 0; d < 3; ++d) nsv[threadIdx.x][d] = C.cf_nsv[3 * (size_t)(e0 + threadIdx.x) + d];
+    __syncthreads();
+    double mx = 0.0;
+    for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
+        double xi[3], wd;
+        vnode(C, k, xi, wd);
+        double out = 0.0;
+        for (int l = 0; l < nf; ++l) {
+            const double a = xi[0] * nsv[l][0] + xi[1] * nsv[l][1] + xi[2] * nsv[l][2];
+            if (a > 0.0) out += a;
+        }
+        mx = fmax(mx, out);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < BLOCK / 64; ++w) m = fmax(m, red[w]);
+        C.amax[cell] = m;
+    }
+}
+
+hipError_t launch_amax(const CaseView *cv, const CaseView &h, hipStream_t s)
+{
+    if (h.n_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_amax, dim3(h.n_cells), dim3(BLOCK), 0, s, cv);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // shared epilogue: moment sums of the produced f relative to u_ref
 // ---------------------------------------------------------------------------
 template <typename A, int VD>
@@ -600,6 +817,8 @@ __device__ __forceinline__ void acc_moments(A (&s)[NSUM], A w, A f0, A f1, A c0,
 template <typename T>
 struct FaceS {
     const T *nb;      // upwind row of a kinetic neighbour
+    const T *nbs;     // order 2: the neighbour's slopes
+    T r[3], rb[3];    // order 2: x_face - x_cell, x_face - x_neighbour
     T n[3];           // outward n S / V
     T A, Th, it;      // Gaussian source: amplitude, psi factor, 1/T
     T u[3];
@@ -607,7 +826,7 @@ struct FaceS {
     int kind, wall, tab;
 };
 
-template <typename T, int VD, bool PTS>
+template <typename T, int VD, bool PTS, bool O2>
 __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -660,6 +879,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
         F.wall = C.cf_wall[e];
         F.tab = 1 + l;
         F.nb = nullptr;
+        F.nbs = nullptr;
+        const double *fcen = C.face_center + 3 * (size_t)C.cf_face[e];
+        const double *xcen = C.cell_center + 3 * (size_t)cell;
+        for (int d = 0; d < 3; ++d) {
+            F.r[d] = (T)((O2 && d < C.dim) ? fcen[d] - xcen[d] : 0.0);
+            F.rb[d] = (T)0;
+        }
         F.A = F.Th = F.it = (T)0;
         for (int d = 0; d < 3; ++d) F.u[d] = (T)0, F.q[d] = (T)0;
         for (int d = 0; d < 6; ++d) F.s[d] = (T)0;
@@ -668,6 +894,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
             if (so >= 0) {
                 F.kind = K_KIN;
                 F.nb = fold + (size_t)so * C.row;
+                if (O2) {
+                    F.nbs = (const T *)C.slope + (size_t)so * C.dim * C.row;
+                    const double *xo = C.cell_center + 3 * (size_t)oth;
+                    for (int d = 0; d < 3; ++d) F.rb[d] = (T)(d < C.dim ? fcen[d] - xo[d] : 0.0);
+                }
             } else {
                 // Grad-13 ghost of the NS neighbour (Sec. 3.2)
                 F.kind = K_GHOST;
@@ -687,7 +918,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
             double amp = (VD == 3) ? pow(M_PI * Tp, -1.5) : 1.0 / (M_PI * Tp);
             if (C.patch_kind[pi] == GSIS_PATCH_WALL) {
                 F.kind = K_WALL;
-                amp *= P.rw[F.wall];
+                double rw = P.rw[F.wall];
+                if (O2) {
+                    // slope part of the outgoing mass flux of f^n (from the slope kernel)
+                    double ws = 0.0;
+                    for (int tl = 0; tl < C.ntile; ++tl) ws += C.wsl[((size_t)slot * C.ntile + tl) * MAXW + F.wall];
+                    rw += ws / C.wall_den[e];
+                }
+                amp *= rw;
             } else {
                 F.kind = K_FAR;
                 amp *= ps[0];
@@ -734,11 +972,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
     const T it = (T)P.it, Th = (T)P.Th, itau = (T)P.itau;
     const T kq0 = (T)P.kq[0], kq1 = (T)P.kq[1], kq2 = (T)P.kq[2];
     const T fx0 = (T)P.fx[0], fx1 = (T)P.fx[1], fx2 = (T)P.fx[2], fx3 = (T)P.fx[3], fx4 = (T)P.fx[4];
-    const T inv_dt = (T)C.inv_dt;
+    // order 2: the pseudo-time term damp * amax joins the diagonal
+    const T inv_dt = (T)(C.inv_dt + (O2 ? C.damp2 * C.amax[cell] : 0.0));
     const int nw = s_nw;
     const T *fo = fold + (size_t)slot * C.row;
     T *fn = fnew + (size_t)slot * C.row;
     const int nvp = C.row / ((VD == 3) ? 1 : 2);   // padded length of one function
+    const int Dm = C.dim;
+    const size_t srow = (size_t)C.row;
+    const T *si = O2 ? (const T *)C.slope + (size_t)slot * Dm * srow : nullptr;
 
     double acc[NSUM], wj[MAXW];
 #pragma unroll
@@ -797,6 +1039,18 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
         }
         const T o0 = fo[k];
         const T o1 = (VD == 2) ? fo[nvp + k] : (T)0;
+        // order 2: own slopes of both functions
+        T s00 = (T)0, s01 = (T)0, s02 = (T)0, s10 = (T)0, s11 = (T)0, s12 = (T)0;
+        if constexpr (O2) {
+            s00 = si[k];
+            if (Dm > 1) s01 = si[srow + k];
+            if (Dm > 2) s02 = si[2 * srow + k];
+            if (VD == 2) {
+                s10 = si[nvp + k];
+                if (Dm > 1) s11 = si[srow + nvp + k];
+                if (Dm > 2) s12 = si[2 * srow + nvp + k];
+            }
+        }
         T den = inv_dt + itau;
         T num0 = itau * g0 + inv_dt * o0;
         T num1 = (VD == 2) ? itau * g1 + inv_dt * o1 : (T)0;
@@ -805,11 +1059,30 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
             const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
             if (a > (T)0) {
                 den += a;
+                if constexpr (O2) {
+                    // deferred correction of the outgoing value: f_i + s_i . r
+                    num0 -= a * (s00 * F.r[0] + s01 * F.r[1] + s02 * F.r[2]);
+                    if (VD == 2) num1 -= a * (s10 * F.r[0] + s11 * F.r[1] + s12 * F.r[2]);
+                }
             } else if (a < (T)0) {
                 T v0, v1 = (T)0;
                 if (F.kind == K_KIN) {
                     v0 = F.nb[k];
                     if (VD == 2) v1 = F.nb[nvp + k];
+                    if constexpr (O2) {
+                        // reconstructed incoming value f_j + s_j . r_j
+                        const T *sj = F.nbs;
+                        T c0 = sj[k] * F.rb[0];
+                        if (Dm > 1) c0 += sj[srow + k] * F.rb[1];
+                        if (Dm > 2) c0 += sj[2 * srow + k] * F.rb[2];
+                        v0 += c0;
+                        if (VD == 2) {
+                            T c1 = sj[nvp + k] * F.rb[0];
+                            if (Dm > 1) c1 += sj[srow + nvp + k] * F.rb[1];
+                            if (Dm > 2) c1 += sj[2 * srow + nvp + k] * F.rb[2];
+                            v1 += c1;
+                        }
+                    }
                 } else {
                     T Es;
                     if constexpr (PTS) {
@@ -1012,14 +1285,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
 template <typename T, int VD>
 static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
-    if (VD == 3 && h0.points) {
+    if (VD == 3 && h0.points && h0.sorder != 2) {
         if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_prow<T, 4>), dim3(total), dim3(BLOCK), 0, s, b);
         else hipLaunchKernelGGL((k_sweep_prow<T, MAXF>), dim3(total), dim3(BLOCK), 0, s, b);
         return hipGetLastError();
     }
     int NA3 = h0.n[0] + h0.n[1] + (VD == 3 ? h0.n[2] : 0);
     size_t lds = sizeof(double) * (size_t)NA3 * 2 + sizeof(T) * (size_t)NA3 * (3 + 1 + MAXF);
-    hipLaunchKernelGGL((k_sweep<T, VD, false>), dim3(total), dim3(BLOCK), lds, s, b);
+    if (h0.sorder == 2) {
+        // second-order face values: the generic kernel (also for point sets)
+        if (VD == 3 && h0.points) hipLaunchKernelGGL((k_sweep<T, 3, true, true>), dim3(total), dim3(BLOCK), lds, s, b);
+        else hipLaunchKernelGGL((k_sweep<T, VD, false, true>), dim3(total), dim3(BLOCK), lds, s, b);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_sweep<T, VD, false, false>), dim3(total), dim3(BLOCK), lds, s, b);
     return hipGetLastError();
 }
 
