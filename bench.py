@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-sweep", action="store_true")
     ap.add_argument("--no-point-grid", action="store_true", help="skip the non-tensor velocity-grid sweep leg")
+    ap.add_argument("--no-order2", action="store_true", help="skip the second-order sweep leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
     ap.add_argument("--serve-requests", type=int, default=12, help="requests in the serving leg (0: skip)")
@@ -207,6 +208,32 @@ def point_grid_sweep(g, torch, M, nv1d, W, flags, steps=3):
     return out
 
 
+def order2_sweep(g, torch, M, grid, W, flags, dim, steps=3):
+    """Second-order face values on the same region and tensor grid (FP32):
+    per sweep the slope kernel (reads f, writes dim slopes per value) and the
+    generic sweep with the deferred correction (reads f and its slopes,
+    writes f).  Algorithmic bytes per cell-velocity: 4 (1 + dim) + 4 (2 + dim)."""
+    cap = int(flags.sum()) + 64
+    case = g.Case(M, grid, KN, dtype=g.F32, capacity=cap, order=2)
+    case.set_state(W, flags=flags)
+    case.sweep(1)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        case.sweep(1)
+        ms.append(case.last_sweep_ms())
+    torch.cuda.synchronize()
+    n, nv = case.n_kin, case.nv
+    kms = float(np.mean(ms))
+    bpp = 4.0 * (1 + dim) + 4.0 * (2 + dim)
+    out = {"kinetic_cells": n, "velocities": nv, "slope_plus_sweep_ms": kms,
+           "updates_per_s": n * nv / (kms / 1e3), "bytes_per_update": bpp,
+           "achieved_gbs": bpp * n * nv / (kms / 1e3) / 1e9,
+           "frac": bpp * n * nv / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, "damp2": 2.0}
+    case.close()
+    return out
+
+
 def surface_leg(g, torch, case, mesh, es):
     """Surface quantities on the sphere (stress, pressure, heat flux per wall face,
     force and heat totals) at the state after the timed steps: kernel time over
@@ -235,8 +262,7 @@ def surface_leg(g, torch, case, mesh, es):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (DESIGN.md describes how "
-              "the sweep would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2501_02245_amd as g
@@ -311,6 +337,10 @@ def main():
     if not a.no_point_grid and not a.sweep_only:
         points = point_grid_sweep(g, torch, M, a.nv1d, W, flags)
         log("point-grid sweep", points)
+    order2 = None
+    if not a.no_order2 and not a.sweep_only and dtype == g.F32:
+        order2 = order2_sweep(g, torch, M, grid, W, flags, mesh["dim"])
+        log("second-order sweep", order2)
 
     out = {
         "metric": "kinetic cell-velocity updates/s",
@@ -336,6 +366,7 @@ def main():
         "sweep_updates_per_s": n_kin_mean * nv / sweep_s,
         "fp64_sweep": fp64,
         "point_grid_sweep": points,
+        "order2_sweep": order2,
         "surface": surface,
         "setup_s": setup_s,
     }

@@ -140,8 +140,10 @@ gsis_status gsis_set_velocity_points(gsis_case c, int32_t n_points, const double
  * max_k sum_{a_k > 0} a_k (the cell's largest outflow rate; damp >= 0,
  * typically 2): without it the point-Jacobi iteration of the corrected
  * operator diverges; it vanishes at convergence.  Order 2 uses the generic
- * (non-plane) sweep kernel and adds a slope array of dim * (VDF row) per
- * kinetic slot to the footprint.  Call before gsis_case_footprint / bind
+ * (non-plane) sweep: faces as rows on 3D grids (GSIS_ORDER2_GENERIC=1 in the
+ * environment at launch selects the generic kernel instead), the generic
+ * kernel on reduced 2D grids; it adds a slope array of four values per VDF
+ * value (three components and padding) to the footprint.  Call before gsis_case_footprint / bind
  * (E_STATE once bound); E_ARG for order not 1 or 2 or a bad damp. */
 gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double damp);
 

@@ -491,6 +491,32 @@ int axtab_len(const gsis_case_s *c)
     return (4 * NA + 5 * c->n[0] + 63) / 64 * 64;
 }
 
+// doubles of the per-node table [nv][4] (node, weight): the point set itself,
+// or for a 3D tensor grid at spatial order 2 (whose sweep reads the nodes per
+// point, faces as rows) the tensor nodes in row order
+size_t node_table_len(const gsis_case_s *c)
+{
+    if (c->points) return c->vpt.size();
+    if (c->order == 2 && c->vdim == 3) return 4 * (size_t)c->nv;
+    return 0;
+}
+
+std::vector<double> node_table(const gsis_case_s *c)
+{
+    if (c->points) return c->vpt;
+    std::vector<double> t(node_table_len(c));
+    if (t.empty()) return t;
+    const int n1 = c->n[1], n2 = c->n[2];
+    for (int k = 0; k < c->nv; ++k) {
+        const int iz = k % n2, iy = (k / n2) % n1, ix = k / (n2 * n1);
+        t[4 * (size_t)k + 0] = c->xv[0][ix];
+        t[4 * (size_t)k + 1] = c->xv[1][iy];
+        t[4 * (size_t)k + 2] = c->xv[2][iz];
+        t[4 * (size_t)k + 3] = c->wv[0][ix] * c->wv[1][iy] * c->wv[2][iz];
+    }
+    return t;
+}
+
 // rows reserved for the Grad-13 ghosts of NS cells next to the kinetic region
 size_t ghost_capacity(int64_t n_cells, int64_t cap)
 {
@@ -535,8 +561,8 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.wallf = S.take(4 * std::max<size_t>(1, m->wall_faces.size()));
     L.xv = S.take(8 * 3 * MAXA);
     L.wv = S.take(8 * 3 * MAXA);
-    L.vpt = S.take(8 * std::max<size_t>(4, c->vpt.size()));
-    L.vptf = S.take(4 * std::max<size_t>(4, c->vpt.size()));
+    L.vpt = S.take(8 * std::max<size_t>(4, node_table_len(c)));
+    L.vptf = S.take(4 * std::max<size_t>(4, node_table_len(c)));
     L.flags = S.take(4 * nc);
     L.slot = S.take(4 * nc);
     L.kin = S.take(4 * (size_t)cap);
@@ -553,7 +579,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.ngh = S.take(16);
     L.axtab = S.take(es * (size_t)cap * axtab_len(c));
     const bool o2 = c->order == 2;
-    L.slope = S.take(o2 ? es * (size_t)cap * m->dim * (*row) : 0);
+    L.slope = S.take(o2 ? es * 4 * (size_t)cap * (*row) : 0);
     L.amax = S.take(o2 ? 8 * nc : 0);
     L.wsl = S.take(o2 ? 8 * (size_t)cap * (*ntile) * MAXW : 0);
     L.f0 = S.take(es * (size_t)cap * (*row));
@@ -776,11 +802,12 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(put(L.wallf, m->wall_faces.data(), 4 * m->wall_faces.size()));
     HIPCHK(put(L.xv, c->xv, sizeof c->xv));
     HIPCHK(put(L.wv, c->wv, sizeof c->wv));
-    HIPCHK(put(L.vpt, c->vpt.data(), 8 * c->vpt.size()));
     {
-        std::vector<float> vf(c->vpt.begin(), c->vpt.end());
+        const std::vector<double> vt = node_table(c);
+        std::vector<float> vf(vt.begin(), vt.end());
+        HIPCHK(put(L.vpt, vt.data(), 8 * vt.size()));
         HIPCHK(put(L.vptf, vf.data(), 4 * vf.size()));
-        HIPCHK(hipStreamSynchronize(s));   // vf is a host temporary of the async copy
+        HIPCHK(hipStreamSynchronize(s));   // vt, vf are host temporaries of the async copies
     }
     HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.flags, 0, 4 * nc, s));
@@ -871,7 +898,7 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
         HIPCHK(launch_ghost(c->cv, h, h.W, s));
-        if (h.fast || h.points) HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
+        if (h.fast || h.points || (h.sorder == 2 && h.vdim == 3)) HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
     }
     return GSIS_OK;
 }

@@ -122,8 +122,8 @@ struct CaseView {
     int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major,
                                 // 2 = groups of `group` cells, tile-major inside a group
     int32_t group, rot;
-    // spatial order 2 (second-order face values): slopes [capacity][dim][row]
-    // in the case dtype, each cell's largest outflow rate amax [n_cells], and
+    // spatial order 2 (second-order face values): slopes [capacity][row][4]
+    // in the case dtype (s_x, s_y, s_z, 0 per VDF value), each cell's largest outflow rate amax [n_cells], and
     // per (slot, tile) sums over the wall faces wsl [capacity][ntile][MAXW]
     // of sum_{a>0} w a (s . r) (the slope part of the next wall densities)
     int32_t sorder, pad_o;

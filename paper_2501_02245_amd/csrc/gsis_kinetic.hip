@@ -18,6 +18,8 @@
 // a point's equilibrium costs three LDS reads and two multiplies, no exp.
 #include <math.h>
 
+#include <cstdlib>
+
 #include "gsis_impl.hpp"
 
 namespace gsis {
@@ -571,7 +573,49 @@ hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipSt
 // sum_{a>0} w a (s . r_w) of the first function: the slope part of the
 // outgoing mass flux that fixes the next wall density.
 // ---------------------------------------------------------------------------
+// a wave-uniform pointer held in SGPRs (the value is the same in every lane)
+template <typename P>
+__device__ __forceinline__ P wave_uniform(P p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P)(((uint64_t)hi << 32) | lo);
+}
+
 template <typename T>
+__device__ __forceinline__ T ratio_lim(T num, T den);
+template <>
+__device__ __forceinline__ float ratio_lim(float num, float den)
+{
+    return num * __builtin_amdgcn_rcpf(den);
+}
+template <>
+__device__ __forceinline__ double ratio_lim(double num, double den)
+{
+    return num / den;
+}
+
+#ifndef SLOPE_U
+#define SLOPE_U 4
+#endif
+
+// slopes are stored interleaved, one 4-vector (s_x, s_y, s_z, 0) per VDF
+// value: a reader gets a value's whole slope with one wide load
+template <typename T>
+struct Slope4;
+template <>
+struct Slope4<float> {
+    using type = float4;
+};
+template <>
+struct Slope4<double> {
+    using type = double4;
+};
+template <typename T>
+using S4 = typename Slope4<T>::type;
+
+template <typename T, int NK>
 __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
     const CaseView &C = *cvp;
@@ -657,58 +701,99 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
     }
     __syncthreads();
     const int nk = s_nk, nw = s_nw;
-    const T *__restrict__ fo = (const T *)C.f[cur];
-    T *__restrict__ sl = (T *)C.slope;
+    const T *fo = (const T *)C.f[cur];
     const size_t row = (size_t)C.row;
     const int nvp = C.row / C.nfun;
-    const T *fi_row = fo + (size_t)slot * row;
-    T *so = sl + (size_t)slot * D * row;
+    const T *fi_row = wave_uniform(fo + (size_t)slot * row);
+    S4<T> *so = wave_uniform((S4<T> *)C.slope + (size_t)slot * row);
+    // the stencil in registers: absent neighbours read the cell's own row
+    // with zero coefficients and offsets (they change nothing)
+    const T *nbr[NK];
+    T c0[NK], c1[NK], c2[NK], r0[NK], r1[NK], r2[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const bool on = j < nk;
+        nbr[j] = wave_uniform(on ? fo + (size_t)s_nb[j] * row : fi_row);
+        c0[j] = on ? s_c[j][0] : (T)0;
+        c1[j] = on ? s_c[j][1] : (T)0;
+        c2[j] = on ? s_c[j][2] : (T)0;
+        r0[j] = on ? s_r[j][0] : (T)0;
+        r1[j] = on ? s_r[j][1] : (T)0;
+        r2[j] = on ? s_r[j][2] : (T)0;
+    }
     const int k0 = vt * C.tile;
     const int kend = min(k0 + C.tile, C.nv);
     double wacc[MAXW];
 #pragma unroll
     for (int j = 0; j < MAXW; ++j) wacc[j] = 0.0;
-    for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
-        T w0 = (T)0, w1 = (T)0, w2 = (T)0;   // slope of the first function
+    // SLOPE_U nodes per lane per pass: all their loads are issued before any
+    // is used (the kernel is bound by load latency, not by bandwidth)
+    for (int kb = k0 + threadIdx.x; kb < kend; kb += SLOPE_U * BLOCK) {
+        T w0[SLOPE_U], w1[SLOPE_U], w2[SLOPE_U];   // slopes of the first function
         for (int q = 0; q < C.nfun; ++q) {
-            const size_t kk = (size_t)q * nvp + k;
-            const T fi = fi_row[kk];
-            T g0 = (T)0, g1 = (T)0, g2 = (T)0, dmax = (T)0, dmin = (T)0;
-            for (int j = 0; j < nk; ++j) {
-                const T d = fo[(size_t)s_nb[j] * row + kk] - fi;
-                g0 += s_c[j][0] * d;
-                g1 += s_c[j][1] * d;
-                g2 += s_c[j][2] * d;
-                dmax = fmax(dmax, d);
-                dmin = fmin(dmin, d);
+            T v[SLOPE_U][NK], fi[SLOPE_U];
+#pragma unroll
+            for (int u = 0; u < SLOPE_U; ++u) {
+                const int k = kb + u * BLOCK;
+                const size_t kk = (size_t)q * nvp + (k < kend ? k : kb);   // in-range address for idle nodes
+#pragma unroll
+                for (int j = 0; j < NK; ++j) v[u][j] = nbr[j][kk];
+                fi[u] = fi_row[kk];
             }
-            T phi = (T)1;
-            for (int j = 0; j < nk; ++j) {
-                const T ext = g0 * s_r[j][0] + g1 * s_r[j][1] + g2 * s_r[j][2];
-                if (ext > (T)0) phi = fmin(phi, dmax / ext);
-                else if (ext < (T)0) phi = fmin(phi, dmin / ext);
-            }
-            g0 *= phi;
-            g1 *= phi;
-            g2 *= phi;
-            so[kk] = g0;
-            if (D > 1) so[row + kk] = g1;
-            if (D > 2) so[2 * row + kk] = g2;
-            if (q == 0) {
-                w0 = g0;
-                w1 = g1;
-                w2 = g2;
+#pragma unroll
+            for (int u = 0; u < SLOPE_U; ++u) {
+                const int k = kb + u * BLOCK;
+                T g0 = (T)0, g1 = (T)0, g2 = (T)0, dmax = (T)0, dmin = (T)0;
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    const T d = v[u][j] - fi[u];
+                    g0 += c0[j] * d;
+                    g1 += c1[j] * d;
+                    g2 += c2[j] * d;
+                    dmax = fmax(dmax, d);
+                    dmin = fmin(dmin, d);
+                }
+                // Barth-Jespersen: phi = min over faces of min(1, bound / ext)
+                T phi = (T)1;
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    const T ext = g0 * r0[j] + g1 * r1[j] + g2 * r2[j];
+                    if (ext > dmax) phi = fmin(phi, ratio_lim(dmax, ext));
+                    else if (ext < dmin) phi = fmin(phi, ratio_lim(dmin, ext));
+                }
+                g0 *= phi;
+                g1 *= phi;
+                g2 *= phi;
+                if (k < kend) {
+                    S4<T> sv;
+                    sv.x = g0;
+                    sv.y = g1;
+                    sv.z = g2;
+                    sv.w = (T)0;
+                    so[(size_t)q * nvp + k] = sv;
+                }
+                if (q == 0) {
+                    w0[u] = g0;
+                    w1[u] = g1;
+                    w2[u] = g2;
+                }
             }
         }
         if (nw > 0) {
-            double xi[3], wd;
-            vnode(C, k, xi, wd);
 #pragma unroll
-            for (int j = 0; j < MAXW; ++j)
-                if (j < nw) {
-                    const double a = xi[0] * s_wn[j][0] + xi[1] * s_wn[j][1] + xi[2] * s_wn[j][2];
-                    if (a > 0.0) wacc[j] += wd * a * (double)(w0 * s_wr[j][0] + w1 * s_wr[j][1] + w2 * s_wr[j][2]);
-                }
+            for (int u = 0; u < SLOPE_U; ++u) {
+                const int k = kb + u * BLOCK;
+                if (k >= kend) break;
+                double xi[3], wd;
+                vnode(C, k, xi, wd);
+#pragma unroll
+                for (int j = 0; j < MAXW; ++j)
+                    if (j < nw) {
+                        const double a = xi[0] * s_wn[j][0] + xi[1] * s_wn[j][1] + xi[2] * s_wn[j][2];
+                        if (a > 0.0)
+                            wacc[j] += wd * a * (double)(w0[u] * s_wr[j][0] + w1[u] * s_wr[j][1] + w2[u] * s_wr[j][2]);
+                    }
+            }
         }
     }
     // per wall index (static selects keep the sums in registers)
@@ -726,8 +811,14 @@ hipError_t launch_slope(const CaseView *cv, const CaseView &h, int n_kin, int cu
 {
     if (n_kin <= 0) return hipSuccess;
     const int blocks = n_kin * h.ntile;
-    if (h.dtype == GSIS_F32) hipLaunchKernelGGL(k_slope<float>, dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
-    else hipLaunchKernelGGL(k_slope<double>, dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+    const bool f4 = h.nfmax <= 4;
+    if (h.dtype == GSIS_F32) {
+        if (f4) hipLaunchKernelGGL((k_slope<float, 4>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_slope<float, MAXF>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+    } else {
+        if (f4) hipLaunchKernelGGL((k_slope<double, 4>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_slope<double, MAXF>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+    }
     return hipGetLastError();
 }
 
@@ -817,7 +908,7 @@ __device__ __forceinline__ void acc_moments(A (&s)[NSUM], A w, A f0, A f1, A c0,
 template <typename T>
 struct FaceS {
     const T *nb;      // upwind row of a kinetic neighbour
-    const T *nbs;     // order 2: the neighbour's slopes
+    const S4<T> *nbs; // order 2: the neighbour's slopes
     T r[3], rb[3];    // order 2: x_face - x_cell, x_face - x_neighbour
     T n[3];           // outward n S / V
     T A, Th, it;      // Gaussian source: amplitude, psi factor, 1/T
@@ -895,7 +986,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
                 F.kind = K_KIN;
                 F.nb = fold + (size_t)so * C.row;
                 if (O2) {
-                    F.nbs = (const T *)C.slope + (size_t)so * C.dim * C.row;
+                    F.nbs = (const S4<T> *)C.slope + (size_t)so * C.row;
                     const double *xo = C.cell_center + 3 * (size_t)oth;
                     for (int d = 0; d < 3; ++d) F.rb[d] = (T)(d < C.dim ? fcen[d] - xo[d] : 0.0);
                 }
@@ -980,7 +1071,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
     const int nvp = C.row / ((VD == 3) ? 1 : 2);   // padded length of one function
     const int Dm = C.dim;
     const size_t srow = (size_t)C.row;
-    const T *si = O2 ? (const T *)C.slope + (size_t)slot * Dm * srow : nullptr;
+    const S4<T> *si = O2 ? (const S4<T> *)C.slope + (size_t)slot * srow : nullptr;
 
     double acc[NSUM], wj[MAXW];
 #pragma unroll
@@ -1042,13 +1133,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
         // order 2: own slopes of both functions
         T s00 = (T)0, s01 = (T)0, s02 = (T)0, s10 = (T)0, s11 = (T)0, s12 = (T)0;
         if constexpr (O2) {
-            s00 = si[k];
-            if (Dm > 1) s01 = si[srow + k];
-            if (Dm > 2) s02 = si[2 * srow + k];
+            const S4<T> a0 = si[k];
+            s00 = a0.x;
+            s01 = a0.y;
+            s02 = a0.z;
             if (VD == 2) {
-                s10 = si[nvp + k];
-                if (Dm > 1) s11 = si[srow + nvp + k];
-                if (Dm > 2) s12 = si[2 * srow + nvp + k];
+                const S4<T> a1 = si[nvp + k];
+                s10 = a1.x;
+                s11 = a1.y;
+                s12 = a1.z;
             }
         }
         T den = inv_dt + itau;
@@ -1071,16 +1164,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
                     if (VD == 2) v1 = F.nb[nvp + k];
                     if constexpr (O2) {
                         // reconstructed incoming value f_j + s_j . r_j
-                        const T *sj = F.nbs;
-                        T c0 = sj[k] * F.rb[0];
-                        if (Dm > 1) c0 += sj[srow + k] * F.rb[1];
-                        if (Dm > 2) c0 += sj[2 * srow + k] * F.rb[2];
-                        v0 += c0;
+                        const S4<T> sj = F.nbs[k];
+                        v0 += sj.x * F.rb[0] + sj.y * F.rb[1] + sj.z * F.rb[2];
                         if (VD == 2) {
-                            T c1 = sj[nvp + k] * F.rb[0];
-                            if (Dm > 1) c1 += sj[srow + nvp + k] * F.rb[1];
-                            if (Dm > 2) c1 += sj[2 * srow + nvp + k] * F.rb[2];
-                            v1 += c1;
+                            const S4<T> sj1 = F.nbs[nvp + k];
+                            v1 += sj1.x * F.rb[0] + sj1.y * F.rb[1] + sj1.z * F.rb[2];
                         }
                     }
                 } else {
@@ -1160,16 +1248,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
 // node are issued before they are used; the moment sums are FP64 per thread
 // and block-reduced in a fixed order into the per-(slot, tile) partials.
 // ---------------------------------------------------------------------------
-template <typename P>
-__device__ __forceinline__ P wave_uniform(P p)
-{
-    const uint64_t v = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (P)(((uint64_t)hi << 32) | lo);
-}
 
-template <typename T, int NF>
+template <typename T, int NF, bool O2>
 __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
 {
     __shared__ double red[(BLOCK / 64) * NSUM];
@@ -1196,10 +1276,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
     const T *fnb[NF];
     T fsc[NF], fnx[NF], fny[NF], fnz[NF];
     int fwall[NF];
+    // order 2: slope rows (component 0; component d at + d row) of the cell
+    // and of each kinetic neighbour, offsets x_face - x_cell (r*) and
+    // x_face - x_neighbour (q*; zero unless the neighbour is kinetic)
+    const int Dm = C.dim;
+    const S4<T> *sl0 = O2 ? (const S4<T> *)C.slope : nullptr;
+    const S4<T> *sio = O2 ? wave_uniform(sl0 + (size_t)slot * row) : nullptr;
+    const S4<T> *snb[NF];
+    T rx[NF], ry[NF], rz[NF], qx[NF], qy[NF], qz[NF];
+    const double *xcen = C.cell_center + 3 * (size_t)cell;
 #pragma unroll
     for (int l = 0; l < NF; ++l) {
         fnb[l] = fo;
+        snb[l] = sio;
         fsc[l] = fnx[l] = fny[l] = fnz[l] = (T)0;
+        rx[l] = ry[l] = rz[l] = qx[l] = qy[l] = qz[l] = (T)0;
         fwall[l] = -1;
         if (l < nf) {
             const int e = e0 + l;
@@ -1208,19 +1299,44 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
             fny[l] = (T)C.cf_nsv[3 * e + 1];
             fnz[l] = (T)C.cf_nsv[3 * e + 2];
             fsc[l] = (T)1;
+            const double *fcen = C.face_center + 3 * (size_t)C.cf_face[e];
+            if (O2) {
+                rx[l] = (T)(fcen[0] - xcen[0]);
+                ry[l] = (T)(Dm > 1 ? fcen[1] - xcen[1] : 0.0);
+                rz[l] = (T)(Dm > 2 ? fcen[2] - xcen[2] : 0.0);
+            }
             if (oth >= 0) {
                 const int so = C.slot_of_cell[oth];
                 fnb[l] = (so >= 0) ? fold + (size_t)so * row : (const T *)C.grow + (size_t)C.ghost_slot[oth] * row;
+                if (O2 && so >= 0) {
+                    const double *xo = C.cell_center + 3 * (size_t)oth;
+                    snb[l] = sl0 + (size_t)so * row;
+                    qx[l] = (T)(fcen[0] - xo[0]);
+                    qy[l] = (T)(Dm > 1 ? fcen[1] - xo[1] : 0.0);
+                    qz[l] = (T)(Dm > 2 ? fcen[2] - xo[2] : 0.0);
+                }
             } else {
                 fnb[l] = (const T *)C.prow + (size_t)(-1 - oth) * row;
                 fwall[l] = C.cf_wall[e];
-                if (fwall[l] >= 0) fsc[l] = (T)P.rw[fwall[l]];
+                if (fwall[l] >= 0) {
+                    double rw = P.rw[fwall[l]];
+                    if (O2) {
+                        // slope part of the outgoing mass flux of f^n (slope kernel)
+                        double ws = 0.0;
+                        for (int tl = 0; tl < C.ntile; ++tl)
+                            ws += C.wsl[((size_t)slot * C.ntile + tl) * MAXW + fwall[l]];
+                        rw += ws / C.wall_den[e];
+                    }
+                    fsc[l] = (T)rw;
+                }
             }
         }
         fnb[l] = wave_uniform(fnb[l]);
+        if (O2) snb[l] = wave_uniform(snb[l]);
     }
     const double u0 = P.u[0], u1 = P.u[1], u2 = P.u[2];
-    const T it = (T)P.it, itau = (T)P.itau, idt = (T)C.inv_dt;
+    // order 2: the pseudo-time term damp * amax joins the diagonal
+    const T it = (T)P.it, itau = (T)P.itau, idt = (T)(C.inv_dt + (O2 ? C.damp2 * C.amax[cell] : 0.0));
     const T kq0 = (T)P.kq[0], kq1 = (T)P.kq[1], kq2 = (T)P.kq[2];
     const T fx0 = (T)P.fx[0], fx1 = (T)P.fx[1], fx2 = (T)P.fx[2], fx3 = (T)P.fx[3], fx4 = (T)P.fx[4];
     const T tu0 = (T)u0, tu1 = (T)u1, tu2 = (T)u2;
@@ -1236,6 +1352,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
 #pragma unroll
         for (int l = 0; l < NF; ++l) v[l] = fnb[l][k];
         const T o = fo[k];
+        // order 2: own slopes, and each face's incoming value reconstructed
+        // from its kinetic neighbour (q = 0 elsewhere)
+        T s0 = (T)0, s1 = (T)0, s2 = (T)0;
+        if constexpr (O2) {
+            const S4<T> a = sio[k];
+            s0 = a.x;
+            s1 = a.y;
+            s2 = a.z;
+#pragma unroll
+            for (int l = 0; l < NF; ++l) {
+                const S4<T> b = snb[l][k];
+                v[l] += b.x * qx[l] + b.y * qy[l] + b.z * qz[l];
+            }
+        }
         T x0, x1, x2, w;
         if constexpr (sizeof(T) == 4) {
             const float4 q = reinterpret_cast<const float4 *>(C.vptf)[k];
@@ -1251,13 +1381,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
         T num = itau * g + idt * o;
         T den = itau + idt;
         T ap[NF];
+        T ar0 = (T)0, ar1 = (T)0, ar2 = (T)0;   // order 2: sum_{a>0} a r
 #pragma unroll
         for (int l = 0; l < NF; ++l) {
             const T a = x0 * fnx[l] + x1 * fny[l] + x2 * fnz[l];
             ap[l] = fmax(a, (T)0);
             den += ap[l];
             num -= fmin(a, (T)0) * fsc[l] * v[l];
+            if constexpr (O2) {
+                ar0 += ap[l] * rx[l];
+                ar1 += ap[l] * ry[l];
+                ar2 += ap[l] * rz[l];
+            }
         }
+        // deferred correction of the outgoing values f_i + s_i . r
+        if constexpr (O2) num -= s0 * ar0 + s1 * ar1 + s2 * ar2;
         const T fnv = num / den;
         fn[k] = fnv;
         // moment sums relative to u_ref, FP64
@@ -1285,17 +1423,26 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
 template <typename T, int VD>
 static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
-    if (VD == 3 && h0.points && h0.sorder != 2) {
-        if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_prow<T, 4>), dim3(total), dim3(BLOCK), 0, s, b);
-        else hipLaunchKernelGGL((k_sweep_prow<T, MAXF>), dim3(total), dim3(BLOCK), 0, s, b);
+    const char *o2g = std::getenv("GSIS_ORDER2_GENERIC");
+    if (VD == 3 && (h0.points || (h0.sorder == 2 && !(o2g && o2g[0] == '1')))) {
+        // faces as rows: point sets, and 3D tensor grids at order 2 (their
+        // node table is filled at bind)
+        if (h0.sorder == 2) {
+            if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_prow<T, 4, true>), dim3(total), dim3(BLOCK), 0, s, b);
+            else hipLaunchKernelGGL((k_sweep_prow<T, MAXF, true>), dim3(total), dim3(BLOCK), 0, s, b);
+        } else {
+            if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_prow<T, 4, false>), dim3(total), dim3(BLOCK), 0, s, b);
+            else hipLaunchKernelGGL((k_sweep_prow<T, MAXF, false>), dim3(total), dim3(BLOCK), 0, s, b);
+        }
         return hipGetLastError();
     }
     int NA3 = h0.n[0] + h0.n[1] + (VD == 3 ? h0.n[2] : 0);
     size_t lds = sizeof(double) * (size_t)NA3 * 2 + sizeof(T) * (size_t)NA3 * (3 + 1 + MAXF);
     if (h0.sorder == 2) {
-        // second-order face values: the generic kernel (also for point sets)
-        if (VD == 3 && h0.points) hipLaunchKernelGGL((k_sweep<T, 3, true, true>), dim3(total), dim3(BLOCK), lds, s, b);
-        else hipLaunchKernelGGL((k_sweep<T, VD, false, true>), dim3(total), dim3(BLOCK), lds, s, b);
+        // second-order face values on tensor grids: the generic kernel (its
+        // per-face branches load neighbour slopes only for incoming values,
+        // which measured faster than the row form's unconditional loads)
+        hipLaunchKernelGGL((k_sweep<T, VD, false, true>), dim3(total), dim3(BLOCK), lds, s, b);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_sweep<T, VD, false, false>), dim3(total), dim3(BLOCK), lds, s, b);

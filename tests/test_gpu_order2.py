@@ -71,6 +71,28 @@ def test_order2_one_sweep(g, oracle_mod, name, dtype):
         assert v < TOL[dtype], (k, v)
 
 
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_order2_generic_kernel_3d(g, oracle_mod, dtype, monkeypatch):
+    """The generic kernel's second-order path on a 3D grid (selected by
+    GSIS_ORDER2_GENERIC=1) against the oracle, on the sphere's partial region."""
+    monkeypatch.setenv("GSIS_ORDER2_GENERIC", "1")
+    m, grid, Kn, W, flags = workload("sphere_small")
+    O = oracle_mod.Oracle(m, grid, Kn, order=2)
+    kin, slot, _ = oracle_mod.regions_from_flags(flags)
+    f0 = gi.gaussian_rows(grid, W[kin], seed=5, amp=0.2,
+                          dtype=np.float32 if dtype == g.F32 else np.float64).astype(np.float64)
+    W = W.copy()
+    W[kin] = O.moments(f0)[:, :5]
+    case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype, order=2)
+    case.set_state(W, vdf=f0, flags=flags)
+    ghost = O.ghost_params(case.get_state()[0].cpu().numpy())
+    fo = O.sweep(f0, kin, slot, ghost)
+    case.sweep(1)
+    ef = f_error(case.get_vdf().cpu().numpy(), fo, O.w)
+    print("order2 generic 3D", dtype, ef, flush=True)
+    assert ef < TOL[dtype]
+
+
 @pytest.mark.parametrize("name", ["couette", "cavity"])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_order2_two_sweeps(g, oracle_mod, name, dtype):
