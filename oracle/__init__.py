@@ -50,7 +50,8 @@ class _Grid(C.Structure):
 
 class _Gas(C.Structure):
     _fields_ = [("Kn", C.c_double), ("omega", C.c_double), ("Pr", C.c_double), ("inv_dt", C.c_double),
-                ("damp2", C.c_double)]
+                ("damp2", C.c_double),
+                ("dr", C.c_double), ("Zr", C.c_double), ("A", C.c_double * 4)]
 
 
 _lib = None
@@ -78,8 +79,11 @@ def lib():
         _lib.oc_macro_residual.argtypes = [P, P, P, P, P]
         _lib.oc_kinetic_residual.restype = C.c_int32
         _lib.oc_kinetic_residual.argtypes = [P, P, C.c_int32, P, P, P, P, P]
-        for name in ("oc_kinetic_slopes", "oc_sweep2", "oc_kinetic_residual2"):
+        for name in ("oc_kinetic_slopes", "oc_sweep2", "oc_kinetic_residual2", "oc_poly_target", "oc_sweep_poly"):
             getattr(_lib, name).restype = C.c_int32
+        _lib.oc_moments_poly.argtypes = [P, C.c_double, P, P]
+        _lib.oc_poly_target.argtypes = [P, P, P, P]
+        _lib.oc_sweep_poly.argtypes = [P, P, P, C.c_int32, P, P, P, P, P]
         _lib.oc_kinetic_slopes.argtypes = [P, P, C.c_int32, P, P, P, P]
         _lib.oc_sweep2.argtypes = [P, P, P, C.c_int32, P, P, P, P, P, P]
         _lib.oc_kinetic_residual2.argtypes = [P, P, C.c_int32, P, P, P, P, P, P]
@@ -100,9 +104,14 @@ class Oracle:
     order 2: second-order face values (limited least-squares slopes of every
     discrete-velocity value, deferred correction of the first-order implicit
     sweep) with the pseudo-time factor damp2 of that iteration.
+
+    dr > 0: the polyatomic two-VDF gas (Sec. 2) with internal collision number
+    Zr and heat-flux matrix A = (A_tt, A_tr, A_rt, A_rr); rows are (f0, f1) on
+    a 3D velocity grid and moments carry T_r and q_r after the 14 of f0.
     """
 
-    def __init__(self, mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, inv_dt=0.0, order=1, damp2=2.0):
+    def __init__(self, mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, inv_dt=0.0, order=1, damp2=2.0,
+                 dr=0.0, Zr=1.0, A=None):
         L = lib()
         if order not in (1, 2):
             raise ValueError("spatial order must be 1 or 2")
@@ -143,8 +152,15 @@ class Oracle:
             else:
                 self.cg.n[d] = 1
         self.nv = L.oc_nv(C.byref(self.cg))
-        self.gas = _Gas(Kn, omega, Pr, inv_dt, damp2)
+        self.poly = dr > 0
+        if self.poly and (self.vdim != 3 or order != 1):
+            raise ValueError("the polyatomic gas needs a 3D velocity grid and first-order face values")
+        if self.poly:
+            self.nfun = 2
+        Av = (C.c_double * 4)(*([Pr, 0.0, 0.0, 1.0] if A is None else [float(a) for a in A]))
+        self.gas = _Gas(Kn, omega, Pr, inv_dt, damp2, dr, Zr, Av)
         self.Kn, self.omega, self.Pr = Kn, omega, Pr
+        self.dr, self.Zr = dr, Zr
         # per-node velocities and weights (for tests and diagnostics)
         self.xi, self.w = self._nodes()
 
@@ -169,15 +185,28 @@ class Oracle:
         return (self.nfun, self.nv)
 
     def moments(self, f):
-        """Moments of rows f[..., nfun, nv] -> [..., 14] (Sec. 2, getmoment)."""
+        """Moments of rows f[..., nfun, nv] -> [..., 14] (Sec. 2, getmoment);
+        polyatomic: [..., 18] with T_r, q_r appended (T and q are T_t, q_t)."""
         f = _f64(f)
         lead = f.shape[:-2]
         fr = f.reshape(-1, self.nfun * self.nv)
-        out = np.empty((fr.shape[0], NMOM))
+        nm = NMOM + 4 if self.poly else NMOM
+        out = np.empty((fr.shape[0], nm))
         for i in range(fr.shape[0]):
             row = np.ascontiguousarray(fr[i])
-            lib().oc_moments(C.byref(self.cg), _p(row), _p(out[i]))
-        return out.reshape(*lead, NMOM)
+            if self.poly:
+                lib().oc_moments_poly(C.byref(self.cg), float(self.dr), _p(row), _p(out[i]))
+            else:
+                lib().oc_moments(C.byref(self.cg), _p(row), _p(out[i]))
+        return out.reshape(*lead, nm)
+
+    def poly_target(self, mom):
+        """Polyatomic relaxation targets (G0, G1) with the conservation fix-up, [2, nv]."""
+        out = np.empty((2, self.nv))
+        m = _f64(mom)
+        if lib().oc_poly_target(C.byref(self.cg), C.byref(self.gas), _p(m), _p(out)) != 0:
+            raise FloatingPointError("fix-up system singular")
+        return out
 
     def maxwellian(self, rho, u, T):
         out = np.empty(self.row_shape())
@@ -208,10 +237,14 @@ class Oracle:
         return out
 
     def feq(self, W5):
+        """Conservation-fixed Maxwellian of W (Sec. 3.2); polyatomic: f1 =
+        (d_r T / 4) f0, the internal modes in equilibrium at T."""
         out = np.empty(self.row_shape())
         w = _f64(W5)
         if lib().oc_feq(C.byref(self.cg), _p(w), _p(out)) != 0:
             raise FloatingPointError("fix-up system singular")
+        if self.poly:
+            out[1] = 0.25 * self.dr * w[4] * out[0]
         return out
 
     def g13(self, mom):
@@ -233,6 +266,12 @@ class Oracle:
         if ghost is None:
             ghost = np.zeros((self.mesh["n_cells"], NMOM))
         gh = _f64(ghost)
+        if self.poly:
+            r = lib().oc_sweep_poly(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc), _p(kc),
+                                    _p(sc), _p(f_old), _p(gh), _p(f_new))
+            if r != 0:
+                raise FloatingPointError("oracle sweep failed (%d)" % r)
+            return f_new
         sl = self.slopes(f_old, kc, sc) if self.order == 2 else None
         r = lib().oc_sweep2(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc), _p(kc), _p(sc),
                             _p(f_old), _p(gh), _p(sl), _p(f_new))

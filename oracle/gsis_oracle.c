@@ -1015,3 +1015,185 @@ int32_t oc_macro(const oc_mesh *m, const oc_gas *gas, const double *hot, const d
     free(U); free(R); free(D); free(pv); free(gr); free(bv);
     return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Polyatomic gas: the two-VDF kinetic model of Sec. 2 (eq. general_model,
+ * reference distributions g_0t, g_0r, g_1t, g_1r, heat-flux mixing q_0, q_1
+ * through A, tau = mu(T_t) / p_t), 3D velocity space, scaled units
+ * (R T -> T/2).  f1 is measured in rho0 / v_m so that
+ *   sum w f1 = d_r rho T_r / 4        ((d_r/2) rho R T_r)
+ *   q_r = 2 sum w c f1               (q_r / (rho0 R T0 v_m)).
+ * Scaled reference distributions:
+ *   g0t = M_t [1 + (4/15) q_t.c / (T_t p_t) (c^2/T_t - 5/2)],  M_t = rho (pi T_t)^-3/2 e^{-c^2/T_t}
+ *   g0r = M_r [1 + (4/15) q_0.c / (T p) (c^2/T - 5/2)],        M_r = rho (pi T)^-3/2 e^{-c^2/T}
+ *   g1t = (d_r T_r / 4) g0t + (pi T_t)^-3/2 (q_r.c / T_t) e^{-c^2/T_t}
+ *   g1r = (d_r T / 4) g0r + (pi T)^-3/2 (q_1.c / T) e^{-c^2/T}
+ * with T = (3 T_t + d_r T_r)/(3 + d_r), p_t = rho T_t, p = rho T.
+ * ------------------------------------------------------------------------ */
+void oc_moments_poly(const oc_grid *g, double d_r, const double *f, double *mom)
+{
+    int32_t nv = oc_nv(g);
+    oc_moments(g, f, mom);   /* f0: rho, u, T_t, sigma, q_t */
+    double xi[3], w, e1 = 0, qr[3] = {0, 0, 0};
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        e1 += w * f[nv + k];
+        for (int d = 0; d < 3; ++d) qr[d] += 2.0 * w * (xi[d] - mom[1 + d]) * f[nv + k];
+    }
+    mom[14] = (d_r > 0) ? 4.0 * e1 / (d_r * mom[0]) : mom[4];
+    for (int d = 0; d < 3; ++d) mom[15 + d] = qr[d];
+}
+
+int32_t oc_poly_target(const oc_grid *g, const oc_gas *gas, const double *mom, double *out)
+{
+    int32_t nv = oc_nv(g);
+    const double dr = gas->dr, Zr = gas->Zr;
+    const double Att = gas->A[0], Atr = gas->A[1], Art = gas->A[2], Arr = gas->A[3];
+    const double rho = mom[0], Tt = mom[4], Tr = mom[14];
+    const double *u = mom + 1, *qt = mom + 11, *qr = mom + 15;
+    const double T = (3.0 * Tt + dr * Tr) / (3.0 + dr), pt = rho * Tt, p = rho * T;
+    double q0[3], q1[3];
+    for (int d = 0; d < 3; ++d) {
+        q0[d] = ((2.0 - 3.0 * Att) * Zr + 1.0) * qt[d] - 3.0 * Atr * Zr * qr[d];
+        q1[d] = -Art * Zr * qt[d] + (1.0 - Arr * Zr) * qr[d];
+    }
+    double xi[3], w;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c[3], c2 = 0, qtc = 0, q0c = 0, qrc = 0, q1c = 0;
+        for (int d = 0; d < 3; ++d) {
+            c[d] = xi[d] - u[d];
+            c2 += c[d] * c[d];
+            qtc += qt[d] * c[d];
+            q0c += q0[d] * c[d];
+            qrc += qr[d] * c[d];
+            q1c += q1[d] * c[d];
+        }
+        double Et = pow(PI * Tt, -1.5) * exp(-c2 / Tt), Er = pow(PI * T, -1.5) * exp(-c2 / T);
+        double g0t = rho * Et * (1.0 + (4.0 / 15.0) * qtc / (Tt * pt) * (c2 / Tt - 2.5));
+        double g0r = rho * Er * (1.0 + (4.0 / 15.0) * q0c / (T * p) * (c2 / T - 2.5));
+        double g1t = 0.25 * dr * Tr * g0t + Et * qrc / Tt;
+        double g1r = 0.25 * dr * T * g0r + Er * q1c / T;
+        out[k] = g0t + (g0r - g0t) / Zr;
+        out[nv + k] = g1t + (g1r - g1t) / Zr;
+    }
+    /* conservation fix-up: P(c) = a0 + a.c + b c^2 on both targets, with
+     * sum w P G0 = rho, sum w c P G0 = 0, sum w (c^2 G0 + 2 G1) P =
+     * (3/2) rho T_t + (d_r/2) rho T_r (the discrete moments of f) */
+    double M[25] = {0}, b[5] = {0};
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c[3], c2 = 0;
+        for (int d = 0; d < 3; ++d) { c[d] = xi[d] - u[d]; c2 += c[d] * c[d]; }
+        double ph[5] = {1.0, c[0], c[1], c[2], c2};
+        double G0 = out[k], G1 = out[nv + k];
+        for (int a = 0; a < 5; ++a) {
+            double t = (a < 4) ? ph[a] * G0 : c2 * G0 + 2.0 * G1;
+            for (int bb = 0; bb < 5; ++bb) M[a * 5 + bb] += w * t * ph[bb];
+        }
+    }
+    b[0] = rho;
+    b[4] = 1.5 * rho * Tt + 0.5 * dr * rho * Tr;
+    if (solve_small(5, M, b) != 0) return -1;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c2 = 0, P = b[0];
+        for (int d = 0; d < 3; ++d) {
+            double c = xi[d] - u[d];
+            c2 += c * c;
+            P += b[1 + d] * c;
+        }
+        P += b[4] * c2;
+        out[k] *= P;
+        out[nv + k] *= P;
+    }
+    return 0;
+}
+
+/* Upwind rows of the faces of kinetic cell i for the two-VDF gas (as
+ * face_sources, rows of 2 nv; f1 on boundary and NS faces = (d_r T_b/4) f0). */
+static void face_sources_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *gas, const int32_t *cptr,
+                              const int32_t *cidx, int32_t i, const int32_t *slot_of_cell, const double *f_old,
+                              const double *ghost, const double *fi, double *scratch, double *nrm,
+                              const double **srcp)
+{
+    int32_t nv = oc_nv(g);
+    size_t row = 2 * (size_t)nv;
+    int32_t nf = cptr[i + 1] - cptr[i];
+    for (int32_t l = 0; l < nf; ++l) {
+        int32_t f = cidx[cptr[i] + l];
+        int32_t own = m->face_cells[2 * f], oth = m->face_cells[2 * f + 1];
+        double sgn = (own == i) ? 1.0 : -1.0;
+        int32_t nb = (own == i) ? oth : own;
+        for (int d = 0; d < 3; ++d) nrm[4 * l + d] = sgn * m->face_normal[3 * f + d];
+        nrm[4 * l + 3] = m->face_area[f] / m->cell_volume[i];
+        double *s = scratch + (size_t)l * row;
+        double Tb;
+        if (nb >= 0 && slot_of_cell[nb] >= 0) {
+            srcp[l] = f_old + (size_t)slot_of_cell[nb] * row;
+            continue;
+        }
+        if (nb >= 0) {
+            oc_g13(g, ghost + (size_t)nb * OC_NMOM, s);
+            Tb = ghost[(size_t)nb * OC_NMOM + 4];
+        } else {
+            int32_t p = -1 - nb;
+            const double *ps = m->patch_state + 5 * p;
+            Tb = ps[4];
+            if (m->patch_kind[p] == OC_WALL) {
+                double rw = wall_density(g, fi, NULL, NULL, nrm + 4 * l, ps + 1, ps[4], s);
+                for (int32_t k = 0; k < nv; ++k) s[k] *= rw;
+            } else {
+                oc_maxwellian(g, ps[0], ps + 1, ps[4], s);
+            }
+        }
+        for (int32_t k = 0; k < nv; ++k) s[nv + k] = 0.25 * gas->dr * Tb * s[k];
+        srcp[l] = s;
+    }
+}
+
+int32_t oc_sweep_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                      int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                      const double *f_old, const double *ghost, double *f_new)
+{
+    if (g->vdim != 3) return -1;
+    int32_t nv = oc_nv(g);
+    size_t row = 2 * (size_t)nv;
+    int32_t *cptr, *cidx;
+    build_adjacency(m, &cptr, &cidx);
+    int32_t err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : err)
+    for (int32_t t = 0; t < n_kin; ++t) {
+        int32_t i = kin_cell[t];
+        const double *fi = f_old + (size_t)slot_of_cell[i] * row;
+        double *fo = f_new + (size_t)slot_of_cell[i] * row;
+        int32_t nf = cptr[i + 1] - cptr[i];
+        double mom[OC_NMOM_POLY];
+        oc_moments_poly(g, gas->dr, fi, mom);
+        double tau = oc_tau(gas, mom[0], mom[4]);   /* tau = mu(T_t) / p_t */
+        double *G = (double *)malloc(sizeof(double) * row);
+        double *src = (double *)malloc(sizeof(double) * row * (size_t)(nf > 0 ? nf : 1));
+        double *nrm = (double *)malloc(sizeof(double) * 4 * (size_t)(nf > 0 ? nf : 1));
+        const double **srcp = (const double **)malloc(sizeof(double *) * (size_t)(nf > 0 ? nf : 1));
+        if (oc_poly_target(g, gas, mom, G) != 0) err = -7;
+        face_sources_poly(m, g, gas, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, src, nrm, srcp);
+        double xi[3], w;
+        for (int32_t k = 0; k < nv; ++k) {
+            node(g, k, xi, &w);
+            double den = gas->inv_dt + 1.0 / tau;
+            double num[2];
+            for (int q = 0; q < 2; ++q) num[q] = gas->inv_dt * fi[q * nv + k] + G[q * nv + k] / tau;
+            for (int32_t l = 0; l < nf; ++l) {
+                double a = (xi[0] * nrm[4 * l] + xi[1] * nrm[4 * l + 1] + xi[2] * nrm[4 * l + 2]) * nrm[4 * l + 3];
+                if (a > 0) den += a;
+                else if (a < 0)
+                    for (int q = 0; q < 2; ++q) num[q] += -a * srcp[l][q * nv + k];
+            }
+            for (int q = 0; q < 2; ++q) fo[q * nv + k] = num[q] / den;
+        }
+        free(G); free(src); free(nrm); free(srcp);
+    }
+    free(cptr);
+    free(cidx);
+    return err;
+}

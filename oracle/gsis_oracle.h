@@ -66,6 +66,9 @@ typedef struct {
     double Pr;      /* A_tt of the monatomic gas = Prandtl number */
     double inv_dt;  /* 1/dt of the kinetic update; 0 = steady iteration */
     double damp2;   /* second-order sweeps: pseudo-time 1/dt_i = damp2 max_k sum_{a_k>0} a_k */
+    double dr;      /* polyatomic gas: internal degrees of freedom d_r (0: monatomic) */
+    double Zr;      /* internal collision number */
+    double A[4];    /* heat-flux relaxation matrix (A_tt, A_tr, A_rt, A_rr) */
 } oc_gas;
 
 int32_t oc_nv(const oc_grid *g);
@@ -153,6 +156,29 @@ int32_t oc_macro_residual(const oc_mesh *m, const oc_gas *gas, const double *hot
  * Returns 0, or -7 on a non-positive density/temperature. */
 int32_t oc_macro(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *src,
                  int32_t n_inner, double cfl, double *W);
+
+/* ------------------------------------------------------------------------
+ * Polyatomic gas (Sec. 2, the two-VDF model with d_r > 0), 3D velocity grids.
+ * Rows [2][nv] = (f0, f1); f1 is scaled so that sum w f1 = d_r rho T_r / 4 and
+ * q_r = 2 sum w c f1.  Moment vector OC_NMOM_POLY = OC_NMOM (from f0: T is T_t,
+ * q is q_t) followed by T_r, q_r[3].
+ * ------------------------------------------------------------------------ */
+#define OC_NMOM_POLY 18
+
+void oc_moments_poly(const oc_grid *g, double d_r, const double *f, double *mom);
+
+/* Relaxation targets G0 = g0t + (g0r - g0t)/Z_r and G1 = g1t + (g1r - g1t)/Z_r
+ * from the moments, times the conservation fix-up (a0 + a.c + b c^2) that makes
+ * their discrete mass, momentum and total energy those of the moments.
+ * out [2][nv].  Returns 0 or -1 (singular fix-up). */
+int32_t oc_poly_target(const oc_grid *g, const oc_gas *gas, const double *mom, double *out);
+
+/* One point-Jacobi sweep of both VDFs (rows [n_slots][2][nv]).  Boundary and
+ * NS-interface values of f1 are (d_r T_b / 4) times those of f0 (internal
+ * modes in equilibrium at the boundary temperature T_b). */
+int32_t oc_sweep_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                      int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                      const double *f_old, const double *ghost, double *f_new);
 
 #ifdef __cplusplus
 }
