@@ -126,6 +126,31 @@ gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const int32_t n[3]
  * correction kernels run.  1..2^24 points. */
 gsis_status gsis_set_velocity_points(gsis_case c, int32_t n_points, const double *xi, const double *w);
 
+/* Polyatomic gas (Sec. 2: the two-VDF model, eq. general_model, with d_r
+ * internal degrees of freedom, internal collision number Z_r >= 1 and the
+ * heat-flux relaxation matrix A = {A_tt, A_tr, A_rt, A_rr}; the gas of Sec. 4
+ * is d_r = 2, Z_r = 2.667, omega = 0.74, A = {0.786, -0.201, -0.059, 0.842}).
+ * d_r = 0 (default) is the monatomic gas.  With d_r > 0 each kinetic cell
+ * holds two rows, f0 and f1 (layout [fun][k] as the reduced pair), f1 scaled
+ * so that sum w f1 = d_r rho T_r / 4 and q_r = 2 sum w c f1; the relaxation
+ * targets are g_0t + (g_0r - g_0t)/Z_r and g_1t + (g_1r - g_1t)/Z_r with the
+ * heat-flux mixing of q_0, q_1 through A, times a conservation fix-up of mass,
+ * momentum and total (translational + internal) energy; tau = mu(T_t)/p_t
+ * with mu = T_t^omega.  Wall, far-field and NS-interface values of f1 are
+ * (d_r T_b / 4) times those of f0.  Supported: 3D tensor velocity grids,
+ * spatial order 1, kinetic sweeps, moments (gsis_moments gives T_t and q_t,
+ * gsis_internal_moments T_r and q_r) and DVM-mode steps; the GSIS modes,
+ * region updates, correction and surface calls return E_ARG (the synthetic
+ * solve has no internal-energy equation).  Gas Pr is not used.  Call before
+ * gsis_case_footprint / bind (E_STATE once bound); E_ARG for d_r < 0, Z_r < 1
+ * or non-finite A. */
+gsis_status gsis_set_internal_dof(gsis_case c, double d_r, double Z_r, const double *A);
+
+/* Polyatomic gas: T_r and q_r (x, y, z) of the current f1 per kinetic cell,
+ * out_dev [n_kin][4] FP64 in ascending cell id (may be null when there is no
+ * kinetic cell).  E_ARG for a monatomic case. */
+gsis_status gsis_internal_moments(gsis_case c, double *out_dev, void *stream);
+
 /* Spatial order of the kinetic face values (Sec. 3: second-order finite
  * volumes; the paper leaves the scheme to its references).  order 1
  * (default): first-order upwind.  order 2: every discrete-velocity value of a

@@ -30,7 +30,7 @@ EXPORTS = [
     "gsis_moments", "gsis_n_kinetic", "gsis_update_regions", "gsis_step", "gsis_solve_steady", "gsis_get_vdf",
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
     "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
-    "gsis_set_spatial_order",
+    "gsis_set_spatial_order", "gsis_set_internal_dof", "gsis_internal_moments",
 ]
 
 
@@ -110,6 +110,7 @@ def lib():
             "gsis_n_wall_faces": [P, P], "gsis_surface": [P, P, P, P, P],
             "gsis_set_velocity_points": [P, I32, P, P],
             "gsis_set_spatial_order": [P, I32, D],
+            "gsis_set_internal_dof": [P, D, D, P], "gsis_internal_moments": [P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -216,9 +217,10 @@ class Case:
     """One steady problem bound to a torch-allocated device workspace."""
 
     def __init__(self, mesh: Mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, dtype=F32, capacity=None,
-                 order=1, damp2=2.0):
+                 order=1, damp2=2.0, dr=0.0, Zr=1.0, A=None):
         """order 2: second-order face values with pseudo-time factor damp2
-        (gsis_set_spatial_order)."""
+        (gsis_set_spatial_order); dr > 0: the polyatomic gas with Zr and the
+        heat-flux matrix A (gsis_set_internal_dof)."""
         import torch
         self.mesh = mesh
         self.dtype = dtype
@@ -230,6 +232,11 @@ class Case:
         self._grid = _set_grid(h, grid)
         self.order = int(order)
         _check(lib().gsis_set_spatial_order(h, self.order, C.c_double(damp2)))
+        self.poly = dr > 0
+        if self.poly:
+            Av = np.ascontiguousarray(A if A is not None else (Pr, 0.0, 0.0, 1.0), dtype=np.float64)
+            _check(lib().gsis_set_internal_dof(h, C.c_double(dr), C.c_double(Zr), C.c_void_p(Av.ctypes.data)))
+            self.nfun = 2
         self.points = grid.get("kind") == "points"
         self.nv = grid_nv(grid)
         self.capacity = int(capacity or mesh.n_cells)
@@ -274,6 +281,13 @@ class Case:
         kc = torch.empty(n, dtype=torch.int32, device="cuda")
         _check(lib().gsis_moments(self.handle, _ptr(out), _ptr(kc), _stream()))
         return out, kc
+
+    def internal_moments(self):
+        """Polyatomic gas: T_r and q_r per kinetic cell [n_kin, 4] (device, FP64)."""
+        import torch
+        out = torch.empty((self.n_kin, 4), dtype=torch.float64, device="cuda")
+        _check(lib().gsis_internal_moments(self.handle, _ptr(out), _stream()))
+        return out
 
     def get_vdf(self):
         import torch

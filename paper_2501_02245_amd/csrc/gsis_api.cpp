@@ -76,6 +76,7 @@ struct gsis_case_s {
     bool points = false;
     int32_t order = 1;          // spatial order of the kinetic face values
     double damp2 = 2.0;         // pseudo-time factor of the order-2 iteration
+    double dr = 0.0, Zr = 1.0, A[4] = {0, 0, 0, 0};   // polyatomic gas (dr > 0)
     bool grid_set = false, bound = false, state_set = false;
     int32_t capacity = 0, tile = 0, ntile = 0, row = 0;
     unsigned char *ws = nullptr;
@@ -420,6 +421,20 @@ extern "C" gsis_status gsis_set_velocity_points(gsis_case c, int32_t np, const d
     return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_set_internal_dof(gsis_case c, double d_r, double Z_r, const double *A)
+{
+    if (!c || !A) return fail(GSIS_E_ARG, "null argument");
+    if (c->bound) return fail(GSIS_E_STATE, "internal degrees of freedom must be set before binding");
+    if (!(d_r >= 0.0) || !std::isfinite(d_r)) return fail(GSIS_E_ARG, "d_r must be finite and >= 0");
+    if (!(Z_r >= 1.0) || !std::isfinite(Z_r)) return fail(GSIS_E_ARG, "Z_r must be finite and >= 1");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(A[i])) return fail(GSIS_E_ARG, "A must be finite");
+    c->dr = d_r;
+    c->Zr = Z_r;
+    for (int i = 0; i < 4; ++i) c->A[i] = A[i];
+    return GSIS_OK;
+}
+
 extern "C" gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double damp)
 {
     if (!c) return fail(GSIS_E_ARG, "null case");
@@ -436,7 +451,7 @@ namespace {
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
-        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
+        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
 
@@ -459,7 +474,7 @@ TileChoice choose_tile(const gsis_case_s *c, int64_t cap)
     if (env) target = std::atoi(env);
     if (target < BLOCK) target = BLOCK;
     const char *gen = std::getenv("GSIS_GENERIC_SWEEP");
-    const bool allow_fast = !(gen && gen[0] == '1') && !c->points && c->order == 1;
+    const bool allow_fast = !(gen && gen[0] == '1') && !c->points && c->order == 1 && !(c->dr > 0);
     const int nx = c->n[0], ny = c->n[1], nz = c->n[2];
     TileChoice t{};
     if (allow_fast && c->vdim == 3 && BLOCK % nz == 0 && (ny * nz) % BLOCK == 0) {
@@ -528,7 +543,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
 {
     const gsis_mesh_s *m = c->mesh;
     const size_t nc = m->n_cells, nf = m->n_faces, nnz = m->nnz, np = std::max(1, m->n_patches);
-    const int nfun = (c->vdim == 3) ? 1 : 2;
+    const int nfun = (c->vdim == 3 && !(c->dr > 0)) ? 1 : 2;
     const int nvp = (c->nv + 63) / 64 * 64;
     *row = nfun * nvp;
     TileChoice tc = choose_tile(c, cap);
@@ -582,12 +597,15 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.slope = S.take(o2 ? es * 4 * (size_t)cap * (*row) : 0);
     L.amax = S.take(o2 ? 8 * nc : 0);
     L.wsl = S.take(o2 ? 8 * (size_t)cap * (*ntile) * MAXW : 0);
+    const bool poly = c->dr > 0;
+    L.prec = S.take(poly ? sizeof(PolyRec) * (size_t)cap : 0);
+    L.psum = S.take(poly ? 32 * (size_t)cap * (*ntile) : 0);
     L.f0 = S.take(es * (size_t)cap * (*row));
     L.f1 = S.take(es * (size_t)cap * (*row));
     L.param = S.take(sizeof(ParamRec) * (size_t)cap);
     L.feq = S.take(2 * sizeof(FeqRec) * (size_t)cap);
     L.partial = S.take(8 * (size_t)cap * (*ntile) * NSUM);
-    L.mom = S.take(8 * (size_t)cap * (GSIS_NMOM + MAXW));
+    L.mom = S.take(8 * (size_t)cap * MOMS);
     L.W = S.take(40 * nc);
     L.Wh = S.take(40 * nc);
     L.Wn = S.take(40 * nc);
@@ -645,11 +663,28 @@ gsis_status read_counts(gsis_case c, hipStream_t s, int *n_new)
 
 }  // namespace
 
+namespace {
+// combinations of grid, order and gas the kernels support
+gsis_status check_config(const gsis_case_s *c)
+{
+    if (c->dr > 0 && (c->vdim != 3 || c->points || c->order != 1))
+        return fail(GSIS_E_ARG, "the polyatomic gas needs a 3D tensor velocity grid and spatial order 1");
+    return GSIS_OK;
+}
+
+gsis_status refuse_poly(gsis_case c, const char *what)
+{
+    if (c && c->dr > 0) return fail(GSIS_E_ARG, "%s: the polyatomic gas supports kinetic sweeps, moments and DVM steps only", what);
+    return GSIS_OK;
+}
+}  // namespace
+
 extern "C" gsis_status gsis_case_footprint(gsis_case c, int64_t cap, size_t *bytes)
 {
     if (!c || !bytes) return fail(GSIS_E_ARG, "null argument");
     if (!c->grid_set) return fail(GSIS_E_STATE, "velocity grid not set");
     if (cap <= 0 || cap > c->mesh->n_cells) return fail(GSIS_E_ARG, "capacity must be in 1..n_cells");
+    if (gsis_status st = check_config(c)) return st;
     int tile, ntile, row;
     *bytes = make_layout(c, cap, &tile, &ntile, &row).total;
     return GSIS_OK;
@@ -661,6 +696,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     if (!c->grid_set) return fail(GSIS_E_STATE, "velocity grid not set");
     if (cap <= 0 || cap > c->mesh->n_cells) return fail(GSIS_E_ARG, "capacity must be in 1..n_cells");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GSIS_E_ARG, "workspace must be 256-byte aligned");
+    if (gsis_status st = check_config(c)) return st;
     int tile, ntile, row, fast, xp;
     Layout L = make_layout(c, cap, &tile, &ntile, &row, &fast, &xp);
     if (bytes < L.total) return fail(GSIS_E_NOMEM, "workspace of %zu bytes < footprint %zu", bytes, L.total);
@@ -682,7 +718,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     h.dim = m->dim;
     h.nnz = m->nnz;
     h.vdim = c->vdim;
-    h.nfun = (c->vdim == 3) ? 1 : 2;
+    h.nfun = (c->vdim == 3 && !(c->dr > 0)) ? 1 : 2;
     for (int d = 0; d < 3; ++d) h.n[d] = c->n[d];
     h.nv = c->nv;
     h.row = row;
@@ -749,6 +785,14 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     }
     h.sorder = c->order;
     h.damp2 = c->damp2;
+    h.poly = c->dr > 0 ? 1 : 0;
+    h.dr = c->dr;
+    h.Zr = c->Zr;
+    for (int i = 0; i < 4; ++i) h.A[i] = c->A[i];
+    if (h.poly) {
+        P(PolyRec *, prec, prec);
+        P(double *, psum, psum);
+    }
     if (c->order == 2) {
         P(void *, slope, slope);
         P(double *, amax, amax);
@@ -947,8 +991,8 @@ gsis_status check_batch(gsis_case const *cases, int n)
         if (st) return st;
         if (cases[j]->dtype != cases[0]->dtype || cases[j]->vdim != cases[0]->vdim ||
             cases[j]->hv.fast != cases[0]->hv.fast || cases[j]->points != cases[0]->points ||
-            cases[j]->order != cases[0]->order)
-            return fail(GSIS_E_ARG, "batched cases must share dtype, vdim, grid kind, spatial order and sweep layout");
+            cases[j]->order != cases[0]->order || (cases[j]->dr > 0) != (cases[0]->dr > 0))
+            return fail(GSIS_E_ARG, "batched cases must share dtype, vdim, grid kind, spatial order, gas kind and sweep layout");
         for (int d = 0; d < 3; ++d)
             if (cases[j]->n[d] > cases[0]->n[d] && j > 0) {
                 // LDS is sized from the first case: put the largest grid first
@@ -1000,6 +1044,16 @@ extern "C" gsis_status gsis_last_sweep_ms(gsis_case c, float *ms)
     return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_internal_moments(gsis_case c, double *out, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!(c->dr > 0)) return fail(GSIS_E_ARG, "the gas has no internal degrees of freedom");
+    if (!out && c->n_kin > 0) return fail(GSIS_E_ARG, "null output");
+    HIPCHK(launch_internal_out(c->cv, c->hv, c->n_kin, out, (hipStream_t)stream));
+    return GSIS_OK;
+}
+
 extern "C" gsis_status gsis_moments(gsis_case c, double *out, int32_t *kc, void *stream)
 {
     gsis_status st = check_ready(c);
@@ -1035,6 +1089,7 @@ extern "C" gsis_status gsis_update_regions(gsis_case c, double Kn_ref, int32_t l
 {
     gsis_status st = check_ready(c);
     if (st) return st;
+    if ((st = refuse_poly(c, "gsis_update_regions"))) return st;
     if (!(Kn_ref >= 0) || layers < 0) return fail(GSIS_E_ARG, "bad Kn_ref or layers");
     hipStream_t s = (hipStream_t)stream;
     CaseView &h = c->hv;
@@ -1210,6 +1265,7 @@ extern "C" gsis_status gsis_step(gsis_case const *cases, int32_t n, const gsis_s
     gsis_status st = check_batch(cases, n);
     if (st) return st;
     if ((st = check_params(p))) return st;
+    if (p->mode != GSIS_MODE_DVM && (st = refuse_poly(cases[0], "gsis_step (GSIS modes)"))) return st;
     hipStream_t s = (hipStream_t)stream;
     for (int j = 0; j < n; ++j)
         if ((st = prepare_sweep(cases[j], s))) return st;
@@ -1250,6 +1306,7 @@ extern "C" gsis_status gsis_correct(gsis_case c, const double *W_new, void *stre
 {
     gsis_status st = check_ready(c);
     if (st) return st;
+    if ((st = refuse_poly(c, "gsis_correct"))) return st;
     if (!W_new) return fail(GSIS_E_ARG, "null W_new");
     hipStream_t s = (hipStream_t)stream;
     CaseView &h = c->hv;
@@ -1274,6 +1331,7 @@ extern "C" gsis_status gsis_surface(gsis_case c, int32_t *face_dev, double *out,
 {
     gsis_status st = check_ready(c);
     if (st) return st;
+    if ((st = refuse_poly(c, "gsis_surface"))) return st;
     if (!out) return fail(GSIS_E_ARG, "null output");
     hipStream_t s = (hipStream_t)stream;
     CaseView &h = c->hv;
@@ -1303,6 +1361,8 @@ extern "C" gsis_status gsis_ns_init(gsis_case const *cases, int32_t n, const gsi
     gsis_status st;
     if ((st = check_params(p))) return st;
     if (p->mode != GSIS_MODE_AGSIS) return fail(GSIS_E_ARG, "the NS start belongs to aGSIS");
+    for (int j = 0; j < n; ++j)
+        if ((st = refuse_poly(cases[j], "gsis_ns_init"))) return st;
     for (int j = 0; j < n; ++j) {
         if ((st = check_ready(cases[j]))) return st;
         for (int i = 0; i < j; ++i)
@@ -1363,6 +1423,7 @@ extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p
     if (st) return st;
     if ((st = check_params(p))) return st;
     if (!r) return fail(GSIS_E_ARG, "null result");
+    if (p->mode != GSIS_MODE_DVM && (st = refuse_poly(c, "gsis_solve_steady (GSIS modes)"))) return st;
     const bool ns_init = p->mode == GSIS_MODE_AGSIS && p->ns_init;
     if (!(p->tol > 0) || p->max_iter < 0 || (p->max_iter == 0 && !ns_init))
         return fail(GSIS_E_ARG, "bad tol or max_iter");

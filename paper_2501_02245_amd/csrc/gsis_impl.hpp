@@ -19,6 +19,10 @@ constexpr int MAXW = GSIS_MAX_WALL_FACES;
 constexpr int MAXA = GSIS_MAX_AXIS;
 constexpr int NSUM = 24;               // per (slot, tile) partial sums, see below
 constexpr int MAX_BATCH = 16;          // cases per batched launch
+// per-slot moment record: the GSIS_NMOM moments, the MAXW outgoing wall
+// fluxes, then (polyatomic gas) T_r and q_r
+constexpr int MOMS = GSIS_NMOM + MAXW + 4;
+constexpr int MOM_INT = GSIS_NMOM + MAXW;
 
 // Partial sums written by every kernel that produces a VDF (init, sweep,
 // correction), per (slot, velocity tile), relative to the slot's reference
@@ -43,6 +47,24 @@ struct ParamRec {
     double fx[5];     // fix-up multiplier (a0, a_x, a_y, [a_z], b), amplitude folded in
     double rw[MAXW];  // densities of the diffuse-wall faces (Jacobi: from f^n)
     double pad[3];
+};
+
+// Polyatomic gas (Sec. 2 two-VDF model): per-slot coefficients of the targets
+//   G0 = P(c) [at Et (1 + kt.c (c^2/T_t - 5/2)) + ar Er (1 + k0.c (c^2/T - 5/2))]
+//   G1 = P(c) [tht at Et (...) + Et bt.c + thr ar Er (...) + Er br.c]
+// with Et = exp(-c^2/T_t), Er = exp(-c^2/T), c = xi - u and the fix-up
+// P(c) = fx0 + fx.c + fx4 c^2; the (1 - 1/Z_r) and 1/Z_r weights are folded
+// into at, bt and ar, br.
+struct PolyRec {
+    double u[3];
+    double itt, it;      // 1 / T_t, 1 / T
+    double itau;         // 1 / tau, tau = mu(T_t) / p_t
+    double at, ar;       // rho (pi T_t)^-3/2 (1 - 1/Z_r), rho (pi T)^-3/2 / Z_r
+    double kt[3], k0[3]; // (4/15) q_t / (T_t p_t), (4/15) q_0 / (T p)
+    double tht, thr;     // d_r T_r / 4, d_r T / 4
+    double bt[3], br[3]; // (pi T_t)^-3/2 (1 - 1/Z_r) q_r / T_t, (pi T)^-3/2 q_1 / (T Z_r)
+    double fx[5];
+    double rw[MAXW];     // wall densities (Jacobi: from f0^n)
 };
 
 // Conservation-fixed Maxwellian f_eq(W) (Sec. 3.2): amplitude-folded
@@ -128,6 +150,12 @@ struct CaseView {
     // of sum_{a>0} w a (s . r) (the slope part of the next wall densities)
     int32_t sorder, pad_o;
     double damp2;
+    // polyatomic gas (d_r > 0): rows hold (f0, f1); per-slot target records and
+    // per (slot, tile) sums of the second function: sum w f1, sum w c f1 (3)
+    int32_t poly, pad_p2;
+    double dr, Zr, A[4];
+    PolyRec *prec;
+    double *psum;
     void *slope;
     double *amax;
     double *wsl;
@@ -136,7 +164,7 @@ struct CaseView {
     ParamRec *param;            // [capacity]
     FeqRec *feq;                // [capacity][2] (new, half)
     double *partial;            // [capacity][ntile][NSUM]
-    double *mom;                // [capacity][GSIS_NMOM + MAXW]
+    double *mom;                // [capacity][MOMS]
     // macroscopic state (FP64, every cell)
     double *W;                  // [n_cells][5] current W^n
     double *Wh;                 // [n_cells][5] W^{n+1/2}
@@ -259,6 +287,8 @@ hipError_t launch_set_flags(const CaseView *cv, const CaseView &h, const uint8_t
 hipError_t launch_get_flags(const CaseView *cv, const CaseView &h, uint8_t *flags, hipStream_t s);
 hipError_t launch_moments_out(const CaseView *cv, const CaseView &h, int n_kin, double *out, int32_t *kc,
                               hipStream_t s);
+// polyatomic gas: T_r, q_r per kinetic cell [n_kin][4]
+hipError_t launch_internal_out(const CaseView *cv, const CaseView &h, int n_kin, double *out, hipStream_t s);
 hipError_t launch_W_from_mom(const CaseView *cv, const CaseView &h, int n_kin, double *W, hipStream_t s);
 // surface quantities of the wall faces (GSIS_NSURF per face) and optional totals
 hipError_t launch_surface(const CaseView *cv, const CaseView &h, int cur, double *out, double *totals, hipStream_t s);

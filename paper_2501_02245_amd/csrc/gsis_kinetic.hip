@@ -212,7 +212,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_pts(const CaseView *__restrict__ 
             ParamRec &P = C.param[slot];
             for (int d = 0; d < 3; ++d) u[d] = P.u[d], kq[d] = P.kq[d];
             it = P.it;
-            rho = C.mom[(size_t)slot * (GSIS_NMOM + MAXW)];
+            rho = C.mom[(size_t)slot * MOMS];
             fx = P.fx;
         } else {
             FeqRec &F = C.feq[2 * (size_t)slot + which];
@@ -393,7 +393,7 @@ __global__ void k_reduce(const CaseView *__restrict__ cvp, int n_kin, int with_r
     for (int tl = 0; tl < C.ntile; ++tl)
         for (int i = 0; i < NSUM; ++i) S[i] += P[tl * NSUM + i];
     const double *ur = C.param[slot].u;
-    double *mom = C.mom + (size_t)slot * (GSIS_NMOM + MAXW);
+    double *mom = C.mom + (size_t)slot * MOMS;
     double rho = S[0];
     double dl[3] = {S[1] / rho, S[2] / rho, (C.vdim == 3) ? S[3] / rho : 0.0};
     double c2[3][3];
@@ -437,6 +437,16 @@ __global__ void k_reduce(const CaseView *__restrict__ cvp, int n_kin, int with_r
     mom[10] = 2.0 * c2[1][2];
     for (int d = 0; d < 3; ++d) mom[11 + d] = q[d];
     for (int w = 0; w < MAXW; ++w) mom[GSIS_NMOM + w] = S[S_WALL + w];
+    if (C.poly) {
+        // second function: T_r = 4 sum w f1 / (d_r rho), q_r = 2 sum w c f1
+        double Q[4] = {0, 0, 0, 0};
+        const double *ps = C.psum + (size_t)slot * C.ntile * 4;
+        for (int tl = 0; tl < C.ntile; ++tl)
+            for (int i = 0; i < 4; ++i) Q[i] += ps[tl * 4 + i];
+        mom[MOM_INT] = 4.0 * Q[0] / (C.dr * rho);
+        for (int d = 0; d < 3; ++d) mom[MOM_INT + 1 + d] = 2.0 * (Q[1 + d] - dl[d] * Q[0]);
+        if (!(mom[MOM_INT] > 0.0)) atomicOr(C.status, 1);
+    }
     int bad = !(rho > 0.0) || !(p > 0.0) || !isfinite(q[0] + q[1] + q[2] + mom[5] + mom[8]);
     if (bad) atomicOr(C.status, 1);
     if (with_res) {
@@ -469,7 +479,7 @@ __global__ void k_param(const CaseView *__restrict__ cvp, int n_kin)
     if (t >= n_kin) return;
     int cell = C.kin_cell[t];
     int slot = C.slot_of_cell[cell];
-    const double *mom = C.mom + (size_t)slot * (GSIS_NMOM + MAXW);
+    const double *mom = C.mom + (size_t)slot * MOMS;
     ParamRec P;
     double rho = mom[0], T = mom[4];
     for (int d = 0; d < 3; ++d) P.u[d] = mom[1 + d];
@@ -492,9 +502,12 @@ __global__ void k_param(const CaseView *__restrict__ cvp, int n_kin)
     C.param[slot] = P;
 }
 
+hipError_t launch_param_poly(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
+
 hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
 {
     if (n_kin <= 0) return hipSuccess;
+    if (h.poly) return launch_param_poly(cv, h, n_kin, s);
     hipLaunchKernelGGL(k_param, dim3((n_kin + 63) / 64), dim3(64), 0, s, cv, n_kin);
     return launch_fix_pts(cv, h, n_kin, h.kin_cell, 0, s);
 }
@@ -1420,6 +1433,434 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
     block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
 }
 
+
+// ---------------------------------------------------------------------------
+// polyatomic gas: the two-VDF model of Sec. 2 (eq. general_model; reference
+// distributions g_0t, g_0r, g_1t, g_1r; heat-flux mixing q_0, q_1 through A;
+// tau = mu(T_t)/p_t), 3D tensor grids.  Rows hold (f0, f1), f1 scaled so that
+// sum w f1 = d_r rho T_r / 4 and q_r = 2 sum w c f1.  Boundary and NS-interface
+// values of f1 are (d_r T_b / 4) times those of f0.
+// ---------------------------------------------------------------------------
+__global__ void k_param_poly(const CaseView *__restrict__ cvp, int n_kin)
+{
+    const CaseView &C = *cvp;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_kin) return;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const double *mom = C.mom + (size_t)slot * MOMS;
+    const double rho = mom[0], Tt = mom[4], Tr = mom[MOM_INT];
+    const double *qt = mom + 11, *qr = mom + MOM_INT + 1;
+    const double dr = C.dr, Zr = C.Zr;
+    const double T = (3.0 * Tt + dr * Tr) / (3.0 + dr), pt = rho * Tt, p = rho * T;
+    const double wt = 1.0 - 1.0 / Zr, wr = 1.0 / Zr;
+    const double ct = pow(M_PI * Tt, -1.5), cr = pow(M_PI * T, -1.5);
+    PolyRec R;
+    for (int d = 0; d < 3; ++d) R.u[d] = mom[1 + d];
+    R.itt = 1.0 / Tt;
+    R.it = 1.0 / T;
+    R.itau = rho * pow(Tt, 1.0 - C.omega) * sqrt(M_PI) / (2.0 * C.Kn);
+    R.at = rho * ct * wt;
+    R.ar = rho * cr * wr;
+    for (int d = 0; d < 3; ++d) {
+        const double q0 = ((2.0 - 3.0 * C.A[0]) * Zr + 1.0) * qt[d] - 3.0 * C.A[1] * Zr * qr[d];
+        const double q1 = -C.A[2] * Zr * qt[d] + (1.0 - C.A[3] * Zr) * qr[d];
+        R.kt[d] = (4.0 / 15.0) * qt[d] / (Tt * pt);
+        R.k0[d] = (4.0 / 15.0) * q0 / (T * p);
+        R.bt[d] = ct * wt * qr[d] / Tt;
+        R.br[d] = cr * wr * q1 / T;
+    }
+    R.tht = 0.25 * dr * Tr;
+    R.thr = 0.25 * dr * T;
+    R.fx[0] = 1.0;
+    for (int d = 1; d < 5; ++d) R.fx[d] = 0.0;
+    for (int w = 0; w < MAXW; ++w) R.rw[w] = 0.0;
+    for (int e = C.cf_ptr[cell]; e < C.cf_ptr[cell + 1]; ++e) {
+        const int wi = C.cf_wall[e];
+        if (wi >= 0) R.rw[wi] = mom[GSIS_NMOM + wi] / C.wall_den[e];
+    }
+    if (!(rho > 0.0) || !(Tt > 0.0) || !(Tr > 0.0)) atomicOr(C.status, 1);
+    C.prec[slot] = R;
+    // the sums of the next sweep are taken relative to u
+    for (int d = 0; d < 3; ++d) C.param[slot].u[d] = R.u[d];
+}
+
+// conservation fix-up of the polyatomic targets: P(c) = a0 + a.c + b c^2 on
+// both, with sum w P G0 = rho, sum w c P G0 = 0 and
+// sum w (c^2 G0 + 2 G1) P = (3/2) rho T_t + (d_r/2) rho T_r, from direct FP64
+// sums over the nodes (one block per kinetic cell)
+__global__ __launch_bounds__(BLOCK) void k_fix_poly(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    __shared__ double red[(BLOCK / 64) * 25];
+    __shared__ double M[25];
+    const int cell = C.kin_cell[blockIdx.x];
+    const int slot = C.slot_of_cell[cell];
+    const PolyRec R = C.prec[slot];
+    double acc[25];
+#pragma unroll
+    for (int i = 0; i < 25; ++i) acc[i] = 0.0;
+    for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
+        double xi[3], w;
+        vnode(C, k, xi, w);
+        const double c0 = xi[0] - R.u[0], c1 = xi[1] - R.u[1], c2 = xi[2] - R.u[2];
+        const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+        const double Et = exp(-cc * R.itt), Er = exp(-cc * R.it);
+        const double ht = R.at * Et * (1.0 + (R.kt[0] * c0 + R.kt[1] * c1 + R.kt[2] * c2) * (cc * R.itt - 2.5));
+        const double hr = R.ar * Er * (1.0 + (R.k0[0] * c0 + R.k0[1] * c1 + R.k0[2] * c2) * (cc * R.it - 2.5));
+        const double G0 = ht + hr;
+        const double G1 = R.tht * ht + Et * (R.bt[0] * c0 + R.bt[1] * c1 + R.bt[2] * c2) + R.thr * hr +
+                          Er * (R.br[0] * c0 + R.br[1] * c1 + R.br[2] * c2);
+        const double ph[5] = {1.0, c0, c1, c2, cc};
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            const double tv = (a < 4) ? ph[a] * G0 : cc * G0 + 2.0 * G1;
+#pragma unroll
+            for (int b = 0; b < 5; ++b) acc[a * 5 + b] += w * tv * ph[b];
+        }
+    }
+    block_reduce_store<25>(acc, M, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double *mom = C.mom + (size_t)slot * MOMS;
+        const double rho = mom[0], Tt = mom[4], Tr = mom[MOM_INT];
+        double A[25], b[5] = {rho, 0.0, 0.0, 0.0, 1.5 * rho * Tt + 0.5 * C.dr * rho * Tr};
+        for (int i = 0; i < 25; ++i) A[i] = M[i];
+        bool ok = true;
+        for (int col = 0; col < 5 && ok; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < 5; ++r)
+                if (fabs(A[r * 5 + col]) > fabs(A[piv * 5 + col])) piv = r;
+            if (!(fabs(A[piv * 5 + col]) > 0.0)) {
+                ok = false;
+                break;
+            }
+            if (piv != col) {
+                for (int j = 0; j < 5; ++j) {
+                    const double tmp = A[col * 5 + j];
+                    A[col * 5 + j] = A[piv * 5 + j];
+                    A[piv * 5 + j] = tmp;
+                }
+                const double tmp = b[col];
+                b[col] = b[piv];
+                b[piv] = tmp;
+            }
+            for (int r = col + 1; r < 5; ++r) {
+                const double fac = A[r * 5 + col] / A[col * 5 + col];
+                for (int j = col; j < 5; ++j) A[r * 5 + j] -= fac * A[col * 5 + j];
+                b[r] -= fac * b[col];
+            }
+        }
+        if (ok) {
+            for (int r = 4; r >= 0; --r) {
+                double sum = b[r];
+                for (int j = r + 1; j < 5; ++j) sum -= A[r * 5 + j] * b[j];
+                b[r] = sum / A[r * 5 + r];
+            }
+            for (int d = 0; d < 5; ++d) C.prec[slot].fx[d] = b[d];
+        } else {
+            atomicOr(C.status, 1);
+        }
+    }
+}
+
+// rows of the polyatomic gas and their sums: mode 0 fills f0 with the
+// conservation-fixed Maxwellian of W (FeqRec) and f1 = (d_r T / 4) f0; mode 2
+// keeps the rows; both write the partial sums of f0 and f1
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict__ cvp, const int32_t *list,
+                                                     int n_items, int mode, int cur)
+{
+    const CaseView &C = *cvp;
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    __shared__ double wn[MAXW][3];
+    __shared__ int s_wi[MAXW], s_nw;
+    const int vt = blockIdx.x / n_items, t = blockIdx.x - vt * n_items;
+    const int cell = list[t];
+    const int slot = C.slot_of_cell[cell];
+    double u[3], it = 1.0, fx[5] = {0, 0, 0, 0, 0};
+    if (mode == 0) {
+        const FeqRec &F = C.feq[2 * (size_t)slot];
+        for (int d = 0; d < 3; ++d) u[d] = F.u[d];
+        it = F.it;
+        for (int d = 0; d < 5; ++d) fx[d] = F.fx[d];
+    } else {
+        for (int d = 0; d < 3; ++d) u[d] = C.W[5 * (size_t)cell + 1 + d];
+    }
+    const double th = 0.25 * C.dr / it;
+    if (threadIdx.x == 0) {
+        if (vt == 0)
+            for (int d = 0; d < 3; ++d) C.param[slot].u[d] = u[d];
+        int nw = 0;
+        for (int e = C.cf_ptr[cell]; e < C.cf_ptr[cell + 1]; ++e)
+            if (C.cf_wall[e] >= 0) {
+                for (int d = 0; d < 3; ++d) wn[nw][d] = C.cf_nsv[3 * (size_t)e + d];
+                s_wi[nw++] = C.cf_wall[e];
+            }
+        s_nw = nw;
+    }
+    __syncthreads();
+    const int nw = s_nw;
+    const int nvp = C.row / 2;
+    T *fr = (T *)C.f[cur] + (size_t)slot * C.row;
+    double acc[NSUM], wj[MAXW], ps[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
+    const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
+    for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
+        double xi[3], w;
+        vnode(C, k, xi, w);
+        const double c0 = xi[0] - u[0], c1 = xi[1] - u[1], c2 = xi[2] - u[2];
+        const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+        T v0, v1;
+        if (mode == 0) {
+            const double f0 = exp(-cc * it) * (fx[0] + fx[1] * c0 + fx[2] * c1 + fx[3] * c2 + fx[4] * cc);
+            v0 = (T)f0;
+            v1 = (T)(th * f0);
+            fr[k] = v0;
+            fr[nvp + k] = v1;
+        } else {
+            v0 = fr[k];
+            v1 = fr[nvp + k];
+        }
+        acc_moments<double, 3>(acc, w, (double)v0, 0.0, c0, c1, c2, cc);
+        const double h1 = w * (double)v1;
+        ps[0] += h1;
+        ps[1] += h1 * c0;
+        ps[2] += h1 * c1;
+        ps[3] += h1 * c2;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < nw) {
+                const double a = xi[0] * wn[j][0] + xi[1] * wn[j][1] + xi[2] * wn[j][2];
+                if (a > 0.0) wj[j] += w * a * (double)v0;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j)
+#pragma unroll
+        for (int ww = 0; ww < MAXW; ++ww) acc[S_WALL + ww] += (j < nw && s_wi[j] == ww) ? wj[j] : 0.0;
+    if (vt == 0 && mode == 0)
+        for (int kp = C.nv + threadIdx.x; kp < nvp; kp += BLOCK) {
+            fr[kp] = (T)0;
+            fr[nvp + kp] = (T)0;
+        }
+    block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+    __syncthreads();
+    block_reduce_store<4>(ps, C.psum + ((size_t)slot * C.ntile + vt) * 4, red);
+}
+
+// the point-Jacobi sweep of both VDFs: one block per (kinetic cell, velocity
+// tile); every Gaussian is evaluated per node (the own targets need two, at
+// T_t and at T)
+template <typename T>
+struct FaceP {
+    const T *nb;
+    T n[3];
+    T A, it, th;       // Gaussian amplitude, 1/T_b, d_r T_b / 4
+    T u[3];
+    T s[6], q[3];      // Grad-13 coefficients (ghost)
+    int kind, wall;
+};
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
+{
+    __shared__ FaceP<T> fs[MAXF];
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    __shared__ int s_nf, s_nw, s_wl[MAXW];
+    const int nb = gridDim.x;
+    const int b = xcd_remap(blockIdx.x, nb);
+    int ci = 0;
+    while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
+    const CaseView &C = *B.cv[ci];
+    const int cur = B.cur[ci];
+    const int item = b - B.start[ci];
+    const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
+    const int vt = item / n_kin;
+    const int t = item - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const T *fold = (const T *)C.f[cur];
+    const PolyRec &R = C.prec[slot];
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    if (threadIdx.x == 0) {
+        s_nf = nf;
+        int nw = 0;
+        for (int l = 0; l < nf; ++l)
+            if (C.cf_wall[e0 + l] >= 0) s_wl[nw++] = l;
+        s_nw = nw;
+    }
+    if (threadIdx.x < nf) {
+        const int l = threadIdx.x, e = e0 + l;
+        const int oth = C.cf_other[e];
+        FaceP<T> F;
+        for (int d = 0; d < 3; ++d) F.n[d] = (T)C.cf_nsv[3 * (size_t)e + d];
+        F.wall = C.cf_wall[e];
+        F.nb = nullptr;
+        F.A = F.it = F.th = (T)0;
+        for (int d = 0; d < 3; ++d) F.u[d] = F.q[d] = (T)0;
+        for (int d = 0; d < 6; ++d) F.s[d] = (T)0;
+        if (oth >= 0 && C.slot_of_cell[oth] >= 0) {
+            F.kind = K_KIN;
+            F.nb = fold + (size_t)C.slot_of_cell[oth] * C.row;
+        } else if (oth >= 0) {
+            // Grad-13 ghost of the NS neighbour for f0; f1 = (d_r T/4) f0
+            F.kind = K_GHOST;
+            const double *g = C.ghost + (size_t)oth * GSIS_NMOM;
+            const double rho = g[0], Tg = g[4], p = rho * Tg;
+            F.A = (T)(rho * pow(M_PI * Tg, -1.5));
+            for (int d = 0; d < 3; ++d) F.u[d] = (T)g[1 + d];
+            F.it = (T)(1.0 / Tg);
+            F.th = (T)(0.25 * C.dr * Tg);
+            for (int d = 0; d < 6; ++d) F.s[d] = (T)(g[5 + d] / (p * Tg));
+            for (int d = 0; d < 3; ++d) F.q[d] = (T)(2.0 * g[11 + d] / (p * Tg));
+        } else {
+            const int pi = -1 - oth;
+            const double *ps = C.patch_state + 5 * pi;
+            const double Tp = ps[4];
+            double amp = pow(M_PI * Tp, -1.5);
+            if (C.patch_kind[pi] == GSIS_PATCH_WALL) {
+                F.kind = K_WALL;
+                amp *= R.rw[F.wall];
+            } else {
+                F.kind = K_FAR;
+                amp *= ps[0];
+            }
+            F.A = (T)amp;
+            for (int d = 0; d < 3; ++d) F.u[d] = (T)ps[1 + d];
+            F.it = (T)(1.0 / Tp);
+            F.th = (T)(0.25 * C.dr * Tp);
+        }
+        fs[l] = F;
+    }
+    __syncthreads();
+    const T itt = (T)R.itt, it = (T)R.it, itau = (T)R.itau, inv_dt = (T)C.inv_dt;
+    const T at = (T)R.at, ar = (T)R.ar, tht = (T)R.tht, thr = (T)R.thr;
+    const T kt0 = (T)R.kt[0], kt1 = (T)R.kt[1], kt2 = (T)R.kt[2];
+    const T k00 = (T)R.k0[0], k01 = (T)R.k0[1], k02 = (T)R.k0[2];
+    const T bt0 = (T)R.bt[0], bt1 = (T)R.bt[1], bt2 = (T)R.bt[2];
+    const T br0 = (T)R.br[0], br1 = (T)R.br[1], br2 = (T)R.br[2];
+    const T fx0 = (T)R.fx[0], fx1 = (T)R.fx[1], fx2 = (T)R.fx[2], fx3 = (T)R.fx[3], fx4 = (T)R.fx[4];
+    const double u0 = R.u[0], u1 = R.u[1], u2 = R.u[2];
+    const int nw = s_nw;
+    const int nvp = C.row / 2;
+    const T *fo = fold + (size_t)slot * C.row;
+    T *fn = (T *)C.f[cur ^ 1] + (size_t)slot * C.row;
+    double acc[NSUM], wj[MAXW], ps[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
+    const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
+    for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
+        double xi[3], wd;
+        vnode(C, k, xi, wd);
+        const T x0 = (T)xi[0], x1 = (T)xi[1], x2 = (T)xi[2];
+        const double d0 = xi[0] - u0, d1 = xi[1] - u1, d2 = xi[2] - u2;
+        const T c0 = (T)d0, c1 = (T)d1, c2 = (T)d2;
+        const T cc = c0 * c0 + c1 * c1 + c2 * c2;
+        const T Et = exp(-cc * itt), Er = exp(-cc * it);
+        const T ht = at * Et * ((T)1 + (kt0 * c0 + kt1 * c1 + kt2 * c2) * (cc * itt - (T)2.5));
+        const T hr = ar * Er * ((T)1 + (k00 * c0 + k01 * c1 + k02 * c2) * (cc * it - (T)2.5));
+        const T P = fx0 + fx1 * c0 + fx2 * c1 + fx3 * c2 + fx4 * cc;
+        const T G0 = P * (ht + hr);
+        const T G1 = P * (tht * ht + Et * (bt0 * c0 + bt1 * c1 + bt2 * c2) + thr * hr +
+                          Er * (br0 * c0 + br1 * c1 + br2 * c2));
+        const T o0 = fo[k], o1 = fo[nvp + k];
+        T den = inv_dt + itau;
+        T num0 = itau * G0 + inv_dt * o0;
+        T num1 = itau * G1 + inv_dt * o1;
+        for (int l = 0; l < s_nf; ++l) {
+            const FaceP<T> &F = fs[l];
+            const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
+            if (a > (T)0) {
+                den += a;
+            } else if (a < (T)0) {
+                T v0, v1;
+                if (F.kind == K_KIN) {
+                    v0 = F.nb[k];
+                    v1 = F.nb[nvp + k];
+                } else {
+                    const T e0 = x0 - F.u[0], e1 = x1 - F.u[1], e2 = x2 - F.u[2];
+                    const T ee = e0 * e0 + e1 * e1 + e2 * e2;
+                    v0 = F.A * exp(-ee * F.it);
+                    if (F.kind == K_GHOST) {
+                        const T Q2 = F.s[0] * e0 * e0 + F.s[1] * e1 * e1 + F.s[2] * e2 * e2 +
+                                     (T)2 * (F.s[3] * e0 * e1 + F.s[4] * e0 * e2 + F.s[5] * e1 * e2);
+                        const T qd = F.q[0] * e0 + F.q[1] * e1 + F.q[2] * e2;
+                        v0 *= (T)1 + Q2 + qd * ((T)0.4 * ee * F.it - (T)1);
+                    }
+                    v1 = F.th * v0;
+                }
+                num0 -= a * v0;
+                num1 -= a * v1;
+            }
+        }
+        const T rden = (T)1 / den;
+        const T n0v = num0 * rden, n1v = num1 * rden;
+        fn[k] = n0v;
+        fn[nvp + k] = n1v;
+        const double dcc = d0 * d0 + d1 * d1 + d2 * d2;
+        acc_moments<double, 3>(acc, wd, (double)n0v, 0.0, d0, d1, d2, dcc);
+        const double h1 = wd * (double)n1v;
+        ps[0] += h1;
+        ps[1] += h1 * d0;
+        ps[2] += h1 * d1;
+        ps[3] += h1 * d2;
+        // moment balance at the old iterate (energy: c^2 f0 + 2 f1)
+        const double r0 = wd * (double)(num0 - den * o0);
+        acc[S_RES] += r0;
+        acc[S_RES + 1] += r0 * d0;
+        acc[S_RES + 2] += r0 * d1;
+        acc[S_RES + 3] += r0 * d2;
+        acc[S_RES + 4] += r0 * dcc + 2.0 * wd * (double)(num1 - den * o1);
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < nw) {
+                const FaceP<T> &F = fs[s_wl[j]];
+                const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
+                if (a > (T)0) wj[j] += wd * (double)(a * n0v);
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j)
+#pragma unroll
+        for (int w = 0; w < MAXW; ++w) acc[S_WALL + w] += (j < nw && fs[s_wl[j]].wall == w) ? wj[j] : 0.0;
+    block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+    __syncthreads();
+    block_reduce_store<4>(ps, C.psum + ((size_t)slot * C.ntile + vt) * 4, red);
+}
+
+hipError_t launch_param_poly(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_param_poly, dim3((n_kin + 63) / 64), dim3(64), 0, s, cv, n_kin);
+    hipLaunchKernelGGL(k_fix_poly, dim3(n_kin), dim3(BLOCK), 0, s, cv);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_poly(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (mode == 0) hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, h.kin_cell, 1);
+    dim3 g(n_items * h.ntile);
+    if (h.dtype == GSIS_F32)
+        hipLaunchKernelGGL((k_fill_poly<float>), g, dim3(BLOCK), 0, s, cv, h.kin_cell, n_items, mode, cur);
+    else hipLaunchKernelGGL((k_fill_poly<double>), g, dim3(BLOCK), 0, s, cv, h.kin_cell, n_items, mode, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_poly(const Batch &b, const CaseView &h0, int total, hipStream_t s)
+{
+    if (h0.dtype == GSIS_F32) hipLaunchKernelGGL((k_sweep_poly<float>), dim3(total), dim3(BLOCK), 0, s, b);
+    else hipLaunchKernelGGL((k_sweep_poly<double>), dim3(total), dim3(BLOCK), 0, s, b);
+    return hipGetLastError();
+}
+
 template <typename T, int VD>
 static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
@@ -1452,6 +1893,7 @@ static hipError_t launch_sweep_t(const Batch &b, const CaseView &h0, int total, 
 hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
+    if (h0.poly) return launch_sweep_poly(b, h0, total, s);
     if (h0.fast) return launch_sweep_fast(b, h0, total, s);
     // all cases of a batch share dtype and vdim; LDS is sized for the largest axes
     if (h0.dtype == GSIS_F32)
@@ -1792,9 +2234,12 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
     block_reduce_store<NSUM>(v, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
 }
 
+hipError_t launch_fill_poly(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s);
+
 hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
+    if (h.poly && (mode == 0 || mode == 2)) return launch_fill_poly(cv, h, mode, n_items, cur, s);
     const int32_t *list = (mode == 1) ? h.new_cell : ((mode == 3) ? h.ghost_cell : h.kin_cell);
     if (mode == 0) {
         hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, list, 1);

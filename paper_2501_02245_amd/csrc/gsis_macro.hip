@@ -346,7 +346,7 @@ __global__ void k_hot(const CaseView *__restrict__ cvp)
         for (int c = 0; c < 9; ++c) h[c] = 0.0;
         return;
     }
-    const double *mom = C.mom + (size_t)slot * (GSIS_NMOM + MAXW);
+    const double *mom = C.mom + (size_t)slot * MOMS;
     double s[6], q[3];
     cell_nsf(C, i, C.Wh[5 * (size_t)i + 4], s, q);
     for (int c = 0; c < 6; ++c) h[c] = mom[5 + c] - s[c];
@@ -366,7 +366,7 @@ __global__ void k_whalf(const CaseView *__restrict__ cvp)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= C.n_cells) return;
     int slot = C.slot_of_cell[i];
-    const double *src = (slot >= 0) ? C.mom + (size_t)slot * (GSIS_NMOM + MAXW) : C.W + 5 * (size_t)i;
+    const double *src = (slot >= 0) ? C.mom + (size_t)slot * MOMS : C.W + 5 * (size_t)i;
     for (int c = 0; c < 5; ++c) C.Wh[5 * (size_t)i + c] = src[c];
 }
 
@@ -1248,7 +1248,7 @@ __global__ void k_moments_out(const CaseView *__restrict__ cvp, int n_kin, doubl
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_kin) return;
     int cell = C.kin_cell[t];
-    const double *m = C.mom + (size_t)C.slot_of_cell[cell] * (GSIS_NMOM + MAXW);
+    const double *m = C.mom + (size_t)C.slot_of_cell[cell] * MOMS;
     for (int c = 0; c < GSIS_NMOM; ++c) out[(size_t)t * GSIS_NMOM + c] = m[c];
     if (kc) kc[t] = cell;
 }
@@ -1261,13 +1261,29 @@ hipError_t launch_moments_out(const CaseView *cv, const CaseView &h, int n_kin, 
     return hipGetLastError();
 }
 
+__global__ void k_internal_out(const CaseView *__restrict__ cvp, int n_kin, double *out)
+{
+    const CaseView &C = *cvp;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_kin) return;
+    const double *m = C.mom + (size_t)C.slot_of_cell[C.kin_cell[t]] * MOMS + MOM_INT;
+    for (int c = 0; c < 4; ++c) out[4 * (size_t)t + c] = m[c];
+}
+
+hipError_t launch_internal_out(const CaseView *cv, const CaseView &h, int n_kin, double *out, hipStream_t s)
+{
+    if (n_kin <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_internal_out, dim3((n_kin + 127) / 128), dim3(128), 0, s, cv, n_kin, out);
+    return hipGetLastError();
+}
+
 __global__ void k_W_from_mom(const CaseView *__restrict__ cvp, int n_kin, double *W)
 {
     const CaseView &C = *cvp;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_kin) return;
     int cell = C.kin_cell[t];
-    const double *m = C.mom + (size_t)C.slot_of_cell[cell] * (GSIS_NMOM + MAXW);
+    const double *m = C.mom + (size_t)C.slot_of_cell[cell] * MOMS;
     for (int c = 0; c < 5; ++c) W[5 * (size_t)cell + c] = m[c];
 }
 
