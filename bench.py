@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-fp64-sweep", action="store_true")
     ap.add_argument("--no-point-grid", action="store_true", help="skip the non-tensor velocity-grid sweep leg")
     ap.add_argument("--no-order2", action="store_true", help="skip the second-order sweep leg")
+    ap.add_argument("--no-poly", action="store_true", help="skip the polyatomic-gas sweep leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
     ap.add_argument("--serve-requests", type=int, default=12, help="requests in the serving leg (0: skip)")
@@ -234,6 +235,32 @@ def order2_sweep(g, torch, M, grid, W, flags, dim, steps=3):
     return out
 
 
+def poly_sweep(g, torch, M, grid, W, flags, steps=3):
+    """The polyatomic gas (two VDFs, nitrogen parameters: d_r 2, Z_r 2.667,
+    omega 0.74, the A matrix of the thermal relaxation rates) on the same
+    region and grid, FP32: sweeps of (f0, f1) with per-node Gaussians at T_t
+    and T.  Algorithmic bytes per cell-velocity: 2 x (4 read + 4 write)."""
+    cap = int(flags.sum()) + 64
+    case = g.Case(M, grid, KN, omega=0.74, Pr=0.786, dtype=g.F32, capacity=cap,
+                  dr=2.0, Zr=2.667, A=(0.786, -0.201, -0.059, 0.842))
+    case.set_state(W, flags=flags)
+    case.sweep(1)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        case.sweep(1)
+        ms.append(case.last_sweep_ms())
+    torch.cuda.synchronize()
+    n, nv = case.n_kin, case.nv
+    kms = float(np.mean(ms))
+    out = {"kinetic_cells": n, "velocities": nv, "kernel_ms": kms, "updates_per_s": n * nv / (kms / 1e3),
+           "bytes_per_update": 16.0, "achieved_gbs": 16.0 * n * nv / (kms / 1e3) / 1e9,
+           "frac": 16.0 * n * nv / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "gas": "N2: d_r 2, Z_r 2.667, omega 0.74, A (0.786, -0.201, -0.059, 0.842)"}
+    case.close()
+    return out
+
+
 def surface_leg(g, torch, case, mesh, es):
     """Surface quantities on the sphere (stress, pressure, heat flux per wall face,
     force and heat totals) at the state after the timed steps: kernel time over
@@ -341,6 +368,10 @@ def main():
     if not a.no_order2 and not a.sweep_only and dtype == g.F32:
         order2 = order2_sweep(g, torch, M, grid, W, flags, mesh["dim"])
         log("second-order sweep", order2)
+    poly = None
+    if not a.no_poly and not a.sweep_only and dtype == g.F32:
+        poly = poly_sweep(g, torch, M, grid, W, flags)
+        log("polyatomic sweep", poly)
 
     out = {
         "metric": "kinetic cell-velocity updates/s",
@@ -367,6 +398,7 @@ def main():
         "fp64_sweep": fp64,
         "point_grid_sweep": points,
         "order2_sweep": order2,
+        "poly_sweep": poly,
         "surface": surface,
         "setup_s": setup_s,
     }

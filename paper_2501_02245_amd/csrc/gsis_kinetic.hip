@@ -1494,18 +1494,33 @@ __global__ __launch_bounds__(BLOCK) void k_fix_poly(const CaseView *__restrict__
     const CaseView &C = *cvp;
     __shared__ double red[(BLOCK / 64) * 25];
     __shared__ double M[25];
+    // per-axis offsets c_d = x_j - u_d, weights and Gaussian factors at T_t and T
+    __shared__ double tc[3 * MAXA], tw[3 * MAXA], tet[3 * MAXA], ter[3 * MAXA];
     const int cell = C.kin_cell[blockIdx.x];
     const int slot = C.slot_of_cell[cell];
     const PolyRec R = C.prec[slot];
+    const int n0 = C.n[0], n1 = C.n[1], n2 = C.n[2], NA3 = n0 + n1 + n2;
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        const int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        const int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        const double c = C.xv[d * MAXA + jj] - R.u[d];
+        tc[j] = c;
+        tw[j] = C.wv[d * MAXA + jj];
+        tet[j] = exp(-c * c * R.itt);
+        ter[j] = exp(-c * c * R.it);
+    }
+    __syncthreads();
     double acc[25];
 #pragma unroll
     for (int i = 0; i < 25; ++i) acc[i] = 0.0;
+    VIdx vi = vidx_init<3>(threadIdx.x, n1, n2);
     for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
-        double xi[3], w;
-        vnode(C, k, xi, w);
-        const double c0 = xi[0] - R.u[0], c1 = xi[1] - R.u[1], c2 = xi[2] - R.u[2];
+        const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
+        vidx_step<3>(vi, n1, n2);
+        const double w = tw[jx] * tw[jy] * tw[jz];
+        const double c0 = tc[jx], c1 = tc[jy], c2 = tc[jz];
         const double cc = c0 * c0 + c1 * c1 + c2 * c2;
-        const double Et = exp(-cc * R.itt), Er = exp(-cc * R.it);
+        const double Et = tet[jx] * tet[jy] * tet[jz], Er = ter[jx] * ter[jy] * ter[jz];
         const double ht = R.at * Et * (1.0 + (R.kt[0] * c0 + R.kt[1] * c1 + R.kt[2] * c2) * (cc * R.itt - 2.5));
         const double hr = R.ar * Er * (1.0 + (R.k0[0] * c0 + R.k0[1] * c1 + R.k0[2] * c2) * (cc * R.it - 2.5));
         const double G0 = ht + hr;
@@ -1671,6 +1686,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
     __shared__ FaceP<T> fs[MAXF];
     __shared__ double red[(BLOCK / 64) * NSUM];
     __shared__ int s_nf, s_nw, s_wl[MAXW];
+    // per-axis node tables: FP64 offsets c_d = x_j - u_d and weights (for the
+    // sums), nodes and Gaussian factors at T_t and T in the case dtype
+    __shared__ double tcd[3 * MAXA], twd[3 * MAXA];
+    __shared__ T tx[3 * MAXA], tet[3 * MAXA], ter[3 * MAXA];
     const int nb = gridDim.x;
     const int b = xcd_remap(blockIdx.x, nb);
     int ci = 0;
@@ -1737,6 +1756,17 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
         }
         fs[l] = F;
     }
+    const int n0 = C.n[0], n1 = C.n[1], n2 = C.n[2], NA3 = n0 + n1 + n2;
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        const int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        const int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        const double x = C.xv[d * MAXA + jj], c = x - R.u[d];
+        tcd[j] = c;
+        twd[j] = C.wv[d * MAXA + jj];
+        tx[j] = (T)x;
+        tet[j] = (T)exp(-c * c * R.itt);
+        ter[j] = (T)exp(-c * c * R.it);
+    }
     __syncthreads();
     const T itt = (T)R.itt, it = (T)R.it, itau = (T)R.itau, inv_dt = (T)C.inv_dt;
     const T at = (T)R.at, ar = (T)R.ar, tht = (T)R.tht, thr = (T)R.thr;
@@ -1745,7 +1775,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
     const T bt0 = (T)R.bt[0], bt1 = (T)R.bt[1], bt2 = (T)R.bt[2];
     const T br0 = (T)R.br[0], br1 = (T)R.br[1], br2 = (T)R.br[2];
     const T fx0 = (T)R.fx[0], fx1 = (T)R.fx[1], fx2 = (T)R.fx[2], fx3 = (T)R.fx[3], fx4 = (T)R.fx[4];
-    const double u0 = R.u[0], u1 = R.u[1], u2 = R.u[2];
     const int nw = s_nw;
     const int nvp = C.row / 2;
     const T *fo = fold + (size_t)slot * C.row;
@@ -1756,14 +1785,16 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
 #pragma unroll
     for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
     const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
+    VIdx vi = vidx_init<3>(k0 + threadIdx.x, n1, n2);
     for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
-        double xi[3], wd;
-        vnode(C, k, xi, wd);
-        const T x0 = (T)xi[0], x1 = (T)xi[1], x2 = (T)xi[2];
-        const double d0 = xi[0] - u0, d1 = xi[1] - u1, d2 = xi[2] - u2;
+        const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
+        vidx_step<3>(vi, n1, n2);
+        const double wd = twd[jx] * twd[jy] * twd[jz];
+        const T x0 = tx[jx], x1 = tx[jy], x2 = tx[jz];
+        const double d0 = tcd[jx], d1 = tcd[jy], d2 = tcd[jz];
         const T c0 = (T)d0, c1 = (T)d1, c2 = (T)d2;
         const T cc = c0 * c0 + c1 * c1 + c2 * c2;
-        const T Et = exp(-cc * itt), Er = exp(-cc * it);
+        const T Et = tet[jx] * tet[jy] * tet[jz], Er = ter[jx] * ter[jy] * ter[jz];
         const T ht = at * Et * ((T)1 + (kt0 * c0 + kt1 * c1 + kt2 * c2) * (cc * itt - (T)2.5));
         const T hr = ar * Er * ((T)1 + (k00 * c0 + k01 * c1 + k02 * c2) * (cc * it - (T)2.5));
         const T P = fx0 + fx1 * c0 + fx2 * c1 + fx3 * c2 + fx4 * cc;
