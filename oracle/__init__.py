@@ -257,8 +257,11 @@ class Oracle:
         return lib().oc_tau(C.byref(self.gas), float(rho), float(T))
 
     # --- field-level pieces -------------------------------------------------
-    def sweep(self, f_old, kin_cell, slot_of_cell, ghost=None):
-        """One point-Jacobi kinetic sweep (Sec. 3.1).  f_old [n_slots, nfun, nv]."""
+    def sweep(self, f_old, kin_cell, slot_of_cell, ghost=None, slope=None):
+        """One point-Jacobi kinetic sweep (Sec. 3.1).  f_old [n_slots, nfun, nv].
+        Order 2: `slope` [n_slots, nfun, nv, 3] (default: the slopes of f_old over
+        kin_cell; pass them to sweep a subset of cells whose neighbours' slopes
+        come from a larger list)."""
         f_old = _f64(f_old)
         f_new = np.zeros_like(f_old)
         kc = np.ascontiguousarray(kin_cell, dtype=np.int32)
@@ -272,7 +275,9 @@ class Oracle:
             if r != 0:
                 raise FloatingPointError("oracle sweep failed (%d)" % r)
             return f_new
-        sl = self.slopes(f_old, kc, sc) if self.order == 2 else None
+        sl = None
+        if self.order == 2:
+            sl = self.slopes(f_old, kc, sc) if slope is None else np.ascontiguousarray(slope, dtype=np.float64)
         r = lib().oc_sweep2(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc), _p(kc), _p(sc),
                             _p(f_old), _p(gh), _p(sl), _p(f_new))
         if r != 0:

@@ -2,6 +2,8 @@
 times: Mach-5 sphere, 192,445 tetrahedra, 32^3 stretched velocities, FP32,
 capacity 0.7 n_cells (one whole-row tile per kinetic cell, plane kernel,
 4-face template).  About 45% of the cells are kinetic (87k rows, 11 GB).
+The second-order and polyatomic legs are checked the same way in their own
+launch configuration (capacity n_kin + 64).
 
 The oracle cannot sweep 2.8e9 points in a test, so one sweep is compared on
 48 sampled kinetic cells (random ones, wall cells, cells next to the NS
@@ -148,3 +150,112 @@ def test_fullsize_correction_property(g, big):
     err_T = np.abs(mg[:, 4] / Wk[:, 4] - 1).max()
     print("correction property: rho", err_rho, "u", err_u, "T", err_T, flush=True)
     assert err_rho < 1e-5 and err_u < 1e-5 and err_T < 1e-5
+
+
+def _need_for(mesh, flags, cells):
+    """Kinetic cells whose rows the oracle needs to sweep `cells`: the cells,
+    their kinetic neighbours, and the kinetic neighbours of their NS neighbours
+    (whose moments enter the ghosts' gradients)."""
+    nb = _neighbours(mesh, cells)
+    ns_nb = nb[flags[nb] == 0]
+    need = np.union1d(np.union1d(cells, nb[flags[nb] == 1]), _neighbours(mesh, ns_nb))
+    return need[flags[need] == 1]
+
+
+def test_fullsize_order2_sweep_sampled(g, oracle_mod, big):
+    """Second-order face values at the benchmark size: one sweep (slope kernel
+    and faces-as-rows sweep) on the sampled cells.  The oracle's slopes of the
+    sample and of its kinetic neighbours come from their full stencils."""
+    import torch
+    mesh, grid, W, flags, kin = (big[k] for k in ("mesh", "grid", "W", "flags", "kin"))
+    sample = _sample(mesh, flags, kin, seed=6)
+    pos = np.searchsorted(kin, sample)
+    nb = _neighbours(mesh, sample)
+    slope_cells = np.union1d(sample, nb[flags[nb] == 1])
+    need = np.union1d(_need_for(mesh, flags, sample), _need_for(mesh, flags, slope_cells))
+    print("order 2: sampled", len(sample), "cells,", len(need), "rows", flush=True)
+    case = g.Case(g.Mesh(mesh), grid, KN, dtype=g.F32, capacity=len(kin) + 64, order=2)
+    ax, ay, az = gi.separable_row_factors(grid, W, kin, seed=SEED_ROWS)
+    tx, ty, tz = (torch.from_numpy(a).cuda() for a in (ax, ay, az))
+    rows = ((tx[:, :, None, None] * ty[:, None, :, None]) * tz[:, None, None, :]).reshape(len(kin), 1, -1)
+    case.set_state(W, vdf=rows, flags=flags)
+    del rows, tx, ty, tz
+    torch.cuda.empty_cache()
+    rows32 = gi.assemble_separable_rows(*gi.separable_row_factors(grid, W, need, seed=SEED_ROWS))
+    O = oracle_mod.Oracle(mesh, grid, KN, order=2)
+    f = rows32.astype(np.float64)
+    Wo = W.copy()
+    Wo[need] = O.moments(f)[:, :5]
+    ghost = O.ghost_params(Wo)
+    slot = -np.ones(mesh["n_cells"], np.int32)
+    slot[need] = np.arange(len(need), dtype=np.int32)
+    sl = O.slopes(f, slope_cells, slot)
+    fo = O.sweep(f, sample, slot, ghost, slope=sl)[slot[sample]]
+    case.sweep(1)
+    fg = case.get_vdf()
+    fs = fg[torch.from_numpy(pos).cuda()].cpu().numpy()
+    del fg
+    mg, _ = case.moments()
+    ms = mg.cpu().numpy()[pos]
+    case.close()
+    del case
+    torch.cuda.empty_cache()
+    ef = f_error(fs, fo, O.w)
+    em = moment_errors(ms, O.moments(fo), u_scale=1.0)
+    print("full size order 2: f", ef, "moments", em, flush=True)
+    assert ef < 1e-5
+    for k, v in em.items():
+        assert v < 1e-5, (k, v)
+
+
+def test_fullsize_poly_sweep_sampled(g, oracle_mod, big):
+    """The polyatomic gas (nitrogen) at the benchmark size: one sweep of
+    (f0, f1) on the sampled cells, f1 = theta_i f0 with a per-cell factor
+    (internal modes at 0.8 T), formed in FP32 on both sides."""
+    import torch
+    mesh, grid, W, flags, kin = (big[k] for k in ("mesh", "grid", "W", "flags", "kin"))
+    sample = _sample(mesh, flags, kin, seed=7)
+    pos = np.searchsorted(kin, sample)
+    need = _need_for(mesh, flags, sample)
+    print("poly: sampled", len(sample), "cells,", len(need), "rows", flush=True)
+    A = (0.786, -0.201, -0.059, 0.842)
+    case = g.Case(g.Mesh(mesh), grid, KN, omega=0.74, Pr=A[0], dtype=g.F32, capacity=len(kin) + 64,
+                  dr=2.0, Zr=2.667, A=A)
+    theta = (0.25 * 2.0 * 0.8 * W[:, 4]).astype(np.float32)
+    ax, ay, az = gi.separable_row_factors(grid, W, kin, seed=SEED_ROWS)
+    tx, ty, tz = (torch.from_numpy(a).cuda() for a in (ax, ay, az))
+    r0 = ((tx[:, :, None, None] * ty[:, None, :, None]) * tz[:, None, None, :]).reshape(len(kin), 1, -1)
+    th = torch.from_numpy(theta[kin]).cuda()
+    rows = torch.cat([r0, r0 * th[:, None, None]], dim=1)
+    del r0, tx, ty, tz
+    case.set_state(W, vdf=rows, flags=flags)
+    del rows
+    torch.cuda.empty_cache()
+    f0 = gi.assemble_separable_rows(*gi.separable_row_factors(grid, W, need, seed=SEED_ROWS))[:, 0]
+    f1 = f0 * theta[need][:, None]
+    f = np.stack([f0, f1], axis=1).astype(np.float64)
+    O = oracle_mod.Oracle(mesh, grid, KN, omega=0.74, Pr=A[0], dr=2.0, Zr=2.667, A=A)
+    Wo = W.copy()
+    Wo[need] = O.moments(f)[:, :5]
+    ghost = O.ghost_params(Wo)
+    slot = -np.ones(mesh["n_cells"], np.int32)
+    slot[need] = np.arange(len(need), dtype=np.int32)
+    fo = O.sweep(f, sample, slot, ghost)[slot[sample]]
+    case.sweep(1)
+    fg = case.get_vdf()
+    fs = fg[torch.from_numpy(pos).cuda()].cpu().numpy()
+    del fg
+    mg, _ = case.moments()
+    ms = mg.cpu().numpy()[pos]
+    ig = case.internal_moments().cpu().numpy()[pos]
+    case.close()
+    del case
+    torch.cuda.empty_cache()
+    mo = O.moments(fo)
+    ef = f_error(fs, fo, O.w)
+    em = moment_errors(ms, mo[:, :14], u_scale=1.0)
+    eTr = np.abs(ig[:, 0] - mo[:, 14]).max() / np.abs(mo[:, 14]).max()
+    print("full size poly: f", ef, "moments", em, "T_r", eTr, flush=True)
+    assert ef < 1e-5 and eTr < 1e-5
+    for k, v in em.items():
+        assert v < 1e-5, (k, v)
