@@ -227,7 +227,8 @@ typedef struct {
     double Kn_ref;               /* Sec. 3.2 reference Knudsen number (aGSIS) */
     double tol;                  /* stop when max(eps) < tol (Sec. 4, default 1e-6) */
     int32_t max_iter;
-    int32_t region_update_every; /* aGSIS: re-flag every k iterations (0 = never) */
+    int32_t region_update_every; /* aGSIS: k > 0 re-flag every k iterations; k < 0 re-flag once,
+                                    after |k| iterations (Sec. 3.4 Step 3: k = -5); 0 = never */
     int32_t n_macro_inner;       /* pseudo-time steps per synthetic solve */
     double cfl;                  /* > 0 local steps; < 0 one global (conservative) step */
     int32_t force_wall_layers;

@@ -605,7 +605,9 @@ class SteadySolver:
 
     mode 'dvm'  : f^{n+1} = f^{n+1/2} (conventional iteration, no synthetic step)
     mode 'gsis' : every cell kinetic; Sec. 3.1 synthetic step and correction
-    mode 'agsis': kinetic cells chosen by Kn_Gll >= Kn_ref (Sec. 3.2), NS elsewhere
+    mode 'agsis': kinetic cells chosen by Kn_Gll >= Kn_ref (Sec. 3.2), NS elsewhere;
+                  region_every k > 0 re-flags every k iterations, k < 0 once after
+                  |k| iterations (Sec. 3.4 Step 3 takes five GSIS iterations first)
 
     State: W [n_cells, 5] primitive (rho, u, T) on every cell; flags; kinetic
     list and slots; f [n_slots, nfun, nv] for the kinetic cells.
@@ -713,7 +715,8 @@ class SteadySolver:
         self.W = W_new
         self.it += 1
         self.last_mom = mom_half
-        if self.mode == "agsis" and self.region_every > 0 and self.it % self.region_every == 0:
+        k = self.region_every
+        if self.mode == "agsis" and ((k > 0 and self.it % k == 0) or (k < 0 and self.it == -k)):
             self.update_regions()
         return eps
 

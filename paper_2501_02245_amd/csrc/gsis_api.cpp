@@ -1283,7 +1283,8 @@ extern "C" gsis_status gsis_step(gsis_case const *cases, int32_t n, const gsis_s
         gsis_case c = cases[j];
         c->iter++;
         st = GSIS_OK;
-        if (p->mode == GSIS_MODE_AGSIS && p->region_update_every > 0 && c->iter % p->region_update_every == 0)
+        const int k = p->region_update_every;
+        if (p->mode == GSIS_MODE_AGSIS && ((k > 0 && c->iter % k == 0) || (k < 0 && c->iter == -k)))
             st = gsis_update_regions(c, p->Kn_ref, p->force_wall_layers, nullptr, stream);
         double e[3] = {NAN, NAN, NAN};
         if (!st && eps_host) {

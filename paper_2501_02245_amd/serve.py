@@ -238,7 +238,7 @@ class Server:
 
 def params_for(mode, cfl, layers, Kn_ref=0.01, tol=1e-6, n_inner=400, **kw):
     return SolveParams(mode=MODE_AGSIS if mode == "agsis" else MODE_GSIS, Kn_ref=Kn_ref, tol=tol,
-                       n_macro_inner=n_inner, cfl=cfl, region_update_every=1, force_wall_layers=layers, **kw)
+                       n_macro_inner=n_inner, cfl=cfl, region_update_every=-5, force_wall_layers=layers, **kw)
 
 
 def start_case(r: Request, dtype, Kn_ref=0.01, tol=1e-6, n_inner=400, ns_chunks=50):

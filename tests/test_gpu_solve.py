@@ -180,3 +180,29 @@ def test_agsis_steps(g, oracle_mod, name, dtype):
         assert np.array_equal(fl, S.flags)
         assert max(err.values()) < tol
         assert np.allclose(eg, eo, rtol=1e-3 if dtype == g.F32 else 1e-7)
+
+
+def test_agsis_region_schedule_once(g, oracle_mod):
+    """The schedule of Sec. 3.4 Step 3 (re-flag once, after a number of GSIS
+    iterations; region_update_every < 0): with -2 the region changes after the
+    second iteration only, flags and fields as the oracle's (FP64)."""
+    m, grid, Kn, W, flags = workload("cylinder_small")
+    O = oracle_mod.Oracle(m, grid, Kn)
+    S = oracle_mod.SteadySolver(O, mode="agsis", Kn_ref=0.01, n_inner=60, cfl=0.5, region_every=-2,
+                                force_wall_layers=2)
+    case = make_case(g, "cylinder_small", m, grid, Kn, g.F64)
+    S.set_state(W, flags=flags)
+    case.set_state(W, flags=flags)
+    p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, n_macro_inner=60, cfl=0.5, region_update_every=-2,
+                      force_wall_layers=2)
+    counts = []
+    for it in range(4):
+        S.step()
+        case.step(p)
+        Wg, fl = case.get_state()
+        fl = fl.cpu().numpy()
+        assert np.array_equal(fl, S.flags)
+        assert max(_fields_err(Wg.cpu().numpy(), S.W, 1.0).values()) < 1e-9
+        counts.append(case.n_kin)
+    print("kinetic cells per iteration", counts, flush=True)
+    assert counts[0] == len(np.nonzero(flags)[0]) and counts[2] == counts[3] == counts[1]
