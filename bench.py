@@ -211,9 +211,10 @@ def point_grid_sweep(g, torch, M, nv1d, W, flags, steps=3):
 
 def order2_sweep(g, torch, M, grid, W, flags, dim, steps=3):
     """Second-order face values on the same region and tensor grid (FP32):
-    per sweep the slope kernel (reads f, writes dim slopes per value) and the
-    generic sweep with the deferred correction (reads f and its slopes,
-    writes f).  Algorithmic bytes per cell-velocity: 4 (1 + dim) + 4 (2 + dim)."""
+    per sweep the slope kernel and the row sweep with the deferred correction.
+    Algorithmic bytes per cell-velocity, counted for a slope of dim components:
+    slope kernel 4 (read f) + 4 dim (write), sweep 4 (read f) + 4 dim (own
+    slope) + 4 (write f); the library stores one increment per face instead."""
     cap = int(flags.sum()) + 64
     case = g.Case(M, grid, KN, dtype=g.F32, capacity=cap, order=2)
     case.set_state(W, flags=flags)

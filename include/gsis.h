@@ -167,8 +167,9 @@ gsis_status gsis_internal_moments(gsis_case c, double *out_dev, void *stream);
  * operator diverges; it vanishes at convergence.  Order 2 uses the generic
  * (non-plane) sweep: faces as rows on 3D grids (GSIS_ORDER2_GENERIC=1 in the
  * environment at launch selects the generic kernel instead), the generic
- * kernel on reduced 2D grids; it adds a slope array of four values per VDF
- * value (three components and padding) to the footprint.  Call before gsis_case_footprint / bind
+ * kernel on reduced 2D grids; it adds the reconstruction increments of every
+ * face (the mesh's largest face count per cell times the VDF row, per kinetic
+ * slot) to the footprint.  Call before gsis_case_footprint / bind
  * (E_STATE once bound); E_ARG for order not 1 or 2 or a bad damp. */
 gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double damp);
 

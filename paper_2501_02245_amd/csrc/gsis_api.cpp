@@ -56,6 +56,7 @@ struct Segment {
 struct gsis_mesh_s {
     int32_t dim, n_cells, n_faces, n_patches, nnz, max_faces = 0;
     std::vector<int32_t> face_cells, cf_ptr, cf_face, cf_other, cf_wall, patch_kind;
+    std::vector<int32_t> cf_back;      // [nnz] local index of the face in the neighbour's list, -1 on boundaries
     std::vector<int32_t> wall_faces;   // boundary faces on diffuse-wall patches, ascending id
     std::vector<double> face_normal, face_area, face_center, cell_volume, cell_center, cf_nsv, face_dist,
         patch_state;
@@ -262,6 +263,7 @@ extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
     m->cf_face.assign(m->nnz, 0);
     m->cf_other.assign(m->nnz, 0);
     m->cf_wall.assign(m->nnz, -1);
+    m->cf_back.assign(m->nnz, -1);
     m->cf_nsv.assign(3 * (size_t)m->nnz, 0.0);
     std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
     for (int f = 0; f < nf; ++f) {
@@ -271,7 +273,10 @@ extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
         m->cf_other[e] = b;
         for (int k = 0; k < 3; ++k) m->cf_nsv[3 * e + k] = m->face_normal[3 * f + k] * m->face_area[f] / m->cell_volume[a];
         if (b >= 0) {
+            const int ea = e;
             e = pos[b]++;
+            m->cf_back[ea] = e - cnt[b];
+            m->cf_back[e] = ea - cnt[a];
             m->cf_face[e] = f;
             m->cf_other[e] = a;
             for (int k = 0; k < 3; ++k)
@@ -451,7 +456,7 @@ namespace {
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
-        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
+        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, cf_back, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
     size_t total;
 };
 
@@ -594,9 +599,10 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.ngh = S.take(16);
     L.axtab = S.take(es * (size_t)cap * axtab_len(c));
     const bool o2 = c->order == 2;
-    L.slope = S.take(o2 ? es * 4 * (size_t)cap * (*row) : 0);
+    L.slope = S.take(o2 ? es * (size_t)m->max_faces * (size_t)cap * (*row) : 0);
     L.amax = S.take(o2 ? 8 * nc : 0);
     L.wsl = S.take(o2 ? 8 * (size_t)cap * (*ntile) * MAXW : 0);
+    L.cf_back = S.take(o2 ? 4 * nnz : 0);
     const bool poly = c->dr > 0;
     L.prec = S.take(poly ? sizeof(PolyRec) * (size_t)cap : 0);
     L.psum = S.take(poly ? 32 * (size_t)cap * (*ntile) : 0);
@@ -797,6 +803,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
         P(void *, slope, slope);
         P(double *, amax, amax);
         P(double *, wsl, wsl);
+        P(const int32_t *, cf_back, cf_back);
     }
     P(ParamRec *, param, param);
     P(FeqRec *, feq, feq);
@@ -867,7 +874,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(launch_wall_den(c->cv, h, s));
     HIPCHK(launch_patch_rows(c->cv, h, s));
     if (c->order == 2) {
-        HIPCHK(hipMemsetAsync(B + L.wsl, 0, L.f0 - L.wsl, s));
+        HIPCHK(put(L.cf_back, m->cf_back.data(), 4 * nnz));
+        HIPCHK(hipMemsetAsync(B + L.wsl, 0, L.cf_back - L.wsl, s));
         HIPCHK(launch_amax(c->cv, h, s));
     }
     if (!c->ev0) {

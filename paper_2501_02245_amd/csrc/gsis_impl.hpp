@@ -144,10 +144,13 @@ struct CaseView {
     int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major,
                                 // 2 = groups of `group` cells, tile-major inside a group
     int32_t group, rot;
-    // spatial order 2 (second-order face values): slopes [capacity][row][4]
-    // in the case dtype (s_x, s_y, s_z, 0 per VDF value), each cell's largest outflow rate amax [n_cells], and
-    // per (slot, tile) sums over the wall faces wsl [capacity][ntile][MAXW]
-    // of sum_{a>0} w a (s . r) (the slope part of the next wall densities)
+    // spatial order 2 (second-order face values): the reconstruction increments
+    // of every face of every kinetic cell, slope [capacity][nfmax][row] in the
+    // case dtype (delta_l = phi g . (x_face_l - x_cell) per VDF value), each
+    // cell's largest outflow rate amax [n_cells], per (slot, tile) sums over the
+    // wall faces wsl [capacity][ntile][MAXW] of sum_{a>0} w a delta (the
+    // reconstruction part of the next wall densities), and cf_back [nnz], the
+    // local index of each face in the neighbour's face list (-1 on boundaries)
     int32_t sorder, pad_o;
     double damp2;
     // polyatomic gas (d_r > 0): rows hold (f0, f1); per-slot target records and
@@ -159,6 +162,7 @@ struct CaseView {
     void *slope;
     double *amax;
     double *wsl;
+    const int32_t *cf_back;
     // kinetic state
     void *f[2];                 // VDF double buffer [capacity][row]
     ParamRec *param;            // [capacity]

@@ -578,13 +578,16 @@ hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipSt
 // 1/|dx|^2, the mesh's `dim` components; zero when the neighbours do not span
 // them: det A <= 1e-12 (tr A / dim)^dim), times the Barth-Jespersen factor
 // that keeps every face value to a kinetic neighbour inside the range of the
-// cell and those neighbours.  One block per (kinetic cell, velocity tile), the
-// geometry of the cell's stencil formed once in FP64 by one thread (the
-// inverse normal matrix folded into per-neighbour coefficient vectors), then
-// one lane per velocity node: 1 + n_k row reads (the neighbour rows are the
-// ones the sweep reads next), dim stores.  The block also sums, per wall face,
-// sum_{a>0} w a (s . r_w) of the first function: the slope part of the
-// outgoing mass flux that fixes the next wall density.
+// cell and those neighbours.  What is stored is the reconstruction increment
+// delta_l = phi g . (x_face_l - x_cell) of every face l of the cell: a sweep then
+// reads one value per face, its own for outgoing values and the neighbour's on
+// the shared face for incoming ones.  One block per (kinetic cell, velocity
+// tile), the stencil's geometry formed once in FP64 by one thread (the inverse
+// normal matrix folded into per-neighbour coefficient vectors), then one lane
+// per velocity node with the loads of SLOPE_U nodes issued before use.  The
+// block also sums, per wall face, sum_{a>0} w a delta of the first function:
+// the reconstruction part of the outgoing mass flux that fixes the next wall
+// density.
 // ---------------------------------------------------------------------------
 // a wave-uniform pointer held in SGPRs (the value is the same in every lane)
 template <typename P>
@@ -610,34 +613,19 @@ __device__ __forceinline__ double ratio_lim(double num, double den)
 }
 
 #ifndef SLOPE_U
-#define SLOPE_U 4
+#define SLOPE_U 2
 #endif
-
-// slopes are stored interleaved, one 4-vector (s_x, s_y, s_z, 0) per VDF
-// value: a reader gets a value's whole slope with one wide load
-template <typename T>
-struct Slope4;
-template <>
-struct Slope4<float> {
-    using type = float4;
-};
-template <>
-struct Slope4<double> {
-    using type = double4;
-};
-template <typename T>
-using S4 = typename Slope4<T>::type;
 
 template <typename T, int NK>
 __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
     const CaseView &C = *cvp;
-    __shared__ T s_c[MAXF][3], s_r[MAXF][3];
+    __shared__ T s_c[MAXF][3], s_r[MAXF][3], s_ra[MAXF][3];
     __shared__ int s_nb[MAXF];
     __shared__ double s_wn[MAXW][3];
     __shared__ T s_wr[MAXW][3];
     __shared__ int s_ww[MAXW];
-    __shared__ int s_nk, s_nw;
+    __shared__ int s_nk, s_nw, s_nf;
     __shared__ double red[(BLOCK / 64) * MAXW];
     // set-up work arrays of thread 0 (in LDS: runtime-indexed registers would spill)
     __shared__ double dx[MAXF][3], iw[MAXF], A[9], I[9];
@@ -651,9 +639,11 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
         const double *xc = C.cell_center + 3 * (size_t)cell;
         for (int i = 0; i < 9; ++i) A[i] = I[i] = 0.0;
         int nk = 0, nw = 0;
+        s_nf = e1 - e0;
         for (int e = e0; e < e1; ++e) {
             const int oth = C.cf_other[e];
             const double *fc = C.face_center + 3 * (size_t)C.cf_face[e];
+            for (int d = 0; d < 3; ++d) s_ra[e - e0][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
             if (C.cf_wall[e] >= 0 && nw < MAXW) {
                 s_ww[nw] = C.cf_wall[e];
                 for (int d = 0; d < 3; ++d) {
@@ -713,12 +703,22 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
         s_nw = nw;
     }
     __syncthreads();
-    const int nk = s_nk, nw = s_nw;
+    const int nk = s_nk, nw = s_nw, nfa = s_nf;
     const T *fo = (const T *)C.f[cur];
     const size_t row = (size_t)C.row;
     const int nvp = C.row / C.nfun;
     const T *fi_row = wave_uniform(fo + (size_t)slot * row);
-    S4<T> *so = wave_uniform((S4<T> *)C.slope + (size_t)slot * row);
+    // increments of the cell's faces: delta_l at (slot nfmax + l) row
+    T *so[NK];
+    T a0[NK], a1[NK], a2[NK];
+#pragma unroll
+    for (int l = 0; l < NK; ++l) {
+        const bool on = l < nfa;
+        so[l] = wave_uniform((T *)C.slope + ((size_t)slot * C.nfmax + (on ? l : 0)) * row);
+        a0[l] = on ? s_ra[l][0] : (T)0;
+        a1[l] = on ? s_ra[l][1] : (T)0;
+        a2[l] = on ? s_ra[l][2] : (T)0;
+    }
     // the stencil in registers: absent neighbours read the cell's own row
     // with zero coefficients and offsets (they change nothing)
     const T *nbr[NK];
@@ -778,12 +778,10 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
                 g1 *= phi;
                 g2 *= phi;
                 if (k < kend) {
-                    S4<T> sv;
-                    sv.x = g0;
-                    sv.y = g1;
-                    sv.z = g2;
-                    sv.w = (T)0;
-                    so[(size_t)q * nvp + k] = sv;
+                    const size_t kk = (size_t)q * nvp + k;
+#pragma unroll
+                    for (int l = 0; l < NK; ++l)
+                        if (l < nfa) so[l][kk] = g0 * a0[l] + g1 * a1[l] + g2 * a2[l];
                 }
                 if (q == 0) {
                     w0[u] = g0;
@@ -921,8 +919,8 @@ __device__ __forceinline__ void acc_moments(A (&s)[NSUM], A w, A f0, A f1, A c0,
 template <typename T>
 struct FaceS {
     const T *nb;      // upwind row of a kinetic neighbour
-    const S4<T> *nbs; // order 2: the neighbour's slopes
-    T r[3], rb[3];    // order 2: x_face - x_cell, x_face - x_neighbour
+    const T *od;      // order 2: the cell's reconstruction increments on this face
+    const T *nd;      // order 2: the kinetic neighbour's increments on this face (or null)
     T n[3];           // outward n S / V
     T A, Th, it;      // Gaussian source: amplitude, psi factor, 1/T
     T u[3];
@@ -983,13 +981,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
         F.wall = C.cf_wall[e];
         F.tab = 1 + l;
         F.nb = nullptr;
-        F.nbs = nullptr;
-        const double *fcen = C.face_center + 3 * (size_t)C.cf_face[e];
-        const double *xcen = C.cell_center + 3 * (size_t)cell;
-        for (int d = 0; d < 3; ++d) {
-            F.r[d] = (T)((O2 && d < C.dim) ? fcen[d] - xcen[d] : 0.0);
-            F.rb[d] = (T)0;
-        }
+        F.od = O2 ? (const T *)C.slope + ((size_t)slot * C.nfmax + l) * C.row : nullptr;
+        F.nd = nullptr;
         F.A = F.Th = F.it = (T)0;
         for (int d = 0; d < 3; ++d) F.u[d] = (T)0, F.q[d] = (T)0;
         for (int d = 0; d < 6; ++d) F.s[d] = (T)0;
@@ -998,11 +991,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
             if (so >= 0) {
                 F.kind = K_KIN;
                 F.nb = fold + (size_t)so * C.row;
-                if (O2) {
-                    F.nbs = (const S4<T> *)C.slope + (size_t)so * C.row;
-                    const double *xo = C.cell_center + 3 * (size_t)oth;
-                    for (int d = 0; d < 3; ++d) F.rb[d] = (T)(d < C.dim ? fcen[d] - xo[d] : 0.0);
-                }
+                if (O2) F.nd = (const T *)C.slope + ((size_t)so * C.nfmax + C.cf_back[e]) * C.row;
             } else {
                 // Grad-13 ghost of the NS neighbour (Sec. 3.2)
                 F.kind = K_GHOST;
@@ -1082,9 +1071,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
     const T *fo = fold + (size_t)slot * C.row;
     T *fn = fnew + (size_t)slot * C.row;
     const int nvp = C.row / ((VD == 3) ? 1 : 2);   // padded length of one function
-    const int Dm = C.dim;
-    const size_t srow = (size_t)C.row;
-    const S4<T> *si = O2 ? (const S4<T> *)C.slope + (size_t)slot * srow : nullptr;
 
     double acc[NSUM], wj[MAXW];
 #pragma unroll
@@ -1143,20 +1129,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
         }
         const T o0 = fo[k];
         const T o1 = (VD == 2) ? fo[nvp + k] : (T)0;
-        // order 2: own slopes of both functions
-        T s00 = (T)0, s01 = (T)0, s02 = (T)0, s10 = (T)0, s11 = (T)0, s12 = (T)0;
-        if constexpr (O2) {
-            const S4<T> a0 = si[k];
-            s00 = a0.x;
-            s01 = a0.y;
-            s02 = a0.z;
-            if (VD == 2) {
-                const S4<T> a1 = si[nvp + k];
-                s10 = a1.x;
-                s11 = a1.y;
-                s12 = a1.z;
-            }
-        }
         T den = inv_dt + itau;
         T num0 = itau * g0 + inv_dt * o0;
         T num1 = (VD == 2) ? itau * g1 + inv_dt * o1 : (T)0;
@@ -1166,9 +1138,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
             if (a > (T)0) {
                 den += a;
                 if constexpr (O2) {
-                    // deferred correction of the outgoing value: f_i + s_i . r
-                    num0 -= a * (s00 * F.r[0] + s01 * F.r[1] + s02 * F.r[2]);
-                    if (VD == 2) num1 -= a * (s10 * F.r[0] + s11 * F.r[1] + s12 * F.r[2]);
+                    // deferred correction of the outgoing value: f_i + delta_i
+                    num0 -= a * F.od[k];
+                    if (VD == 2) num1 -= a * F.od[nvp + k];
                 }
             } else if (a < (T)0) {
                 T v0, v1 = (T)0;
@@ -1176,13 +1148,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(Batch B)
                     v0 = F.nb[k];
                     if (VD == 2) v1 = F.nb[nvp + k];
                     if constexpr (O2) {
-                        // reconstructed incoming value f_j + s_j . r_j
-                        const S4<T> sj = F.nbs[k];
-                        v0 += sj.x * F.rb[0] + sj.y * F.rb[1] + sj.z * F.rb[2];
-                        if (VD == 2) {
-                            const S4<T> sj1 = F.nbs[nvp + k];
-                            v1 += sj1.x * F.rb[0] + sj1.y * F.rb[1] + sj1.z * F.rb[2];
-                        }
+                        // reconstructed incoming value f_j + delta_j on this face
+                        v0 += F.nd[k];
+                        if (VD == 2) v1 += F.nd[nvp + k];
                     }
                 } else {
                     T Es;
@@ -1289,21 +1257,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
     const T *fnb[NF];
     T fsc[NF], fnx[NF], fny[NF], fnz[NF];
     int fwall[NF];
-    // order 2: slope rows (component 0; component d at + d row) of the cell
-    // and of each kinetic neighbour, offsets x_face - x_cell (r*) and
-    // x_face - x_neighbour (q*; zero unless the neighbour is kinetic)
-    const int Dm = C.dim;
-    const S4<T> *sl0 = O2 ? (const S4<T> *)C.slope : nullptr;
-    const S4<T> *sio = O2 ? wave_uniform(sl0 + (size_t)slot * row) : nullptr;
-    const S4<T> *snb[NF];
-    T rx[NF], ry[NF], rz[NF], qx[NF], qy[NF], qz[NF];
-    const double *xcen = C.cell_center + 3 * (size_t)cell;
+    // order 2: the cell's reconstruction increments per face (dio) and each
+    // kinetic neighbour's increments on the shared face (dnb, weighted by qk =
+    // 1; other faces read the cell's first row with weight 0)
+    const T *dl0 = O2 ? (const T *)C.slope : nullptr;
+    const T *dio[NF];
+    const T *dnb[NF];
+    T qk[NF];
 #pragma unroll
     for (int l = 0; l < NF; ++l) {
         fnb[l] = fo;
-        snb[l] = sio;
+        dio[l] = O2 ? dl0 + ((size_t)slot * C.nfmax + (l < nf ? l : 0)) * row : nullptr;
+        dnb[l] = dio[l];
+        qk[l] = (T)0;
         fsc[l] = fnx[l] = fny[l] = fnz[l] = (T)0;
-        rx[l] = ry[l] = rz[l] = qx[l] = qy[l] = qz[l] = (T)0;
         fwall[l] = -1;
         if (l < nf) {
             const int e = e0 + l;
@@ -1312,21 +1279,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
             fny[l] = (T)C.cf_nsv[3 * e + 1];
             fnz[l] = (T)C.cf_nsv[3 * e + 2];
             fsc[l] = (T)1;
-            const double *fcen = C.face_center + 3 * (size_t)C.cf_face[e];
-            if (O2) {
-                rx[l] = (T)(fcen[0] - xcen[0]);
-                ry[l] = (T)(Dm > 1 ? fcen[1] - xcen[1] : 0.0);
-                rz[l] = (T)(Dm > 2 ? fcen[2] - xcen[2] : 0.0);
-            }
             if (oth >= 0) {
                 const int so = C.slot_of_cell[oth];
                 fnb[l] = (so >= 0) ? fold + (size_t)so * row : (const T *)C.grow + (size_t)C.ghost_slot[oth] * row;
                 if (O2 && so >= 0) {
-                    const double *xo = C.cell_center + 3 * (size_t)oth;
-                    snb[l] = sl0 + (size_t)so * row;
-                    qx[l] = (T)(fcen[0] - xo[0]);
-                    qy[l] = (T)(Dm > 1 ? fcen[1] - xo[1] : 0.0);
-                    qz[l] = (T)(Dm > 2 ? fcen[2] - xo[2] : 0.0);
+                    dnb[l] = dl0 + ((size_t)so * C.nfmax + C.cf_back[e]) * row;
+                    qk[l] = (T)1;
                 }
             } else {
                 fnb[l] = (const T *)C.prow + (size_t)(-1 - oth) * row;
@@ -1345,7 +1303,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
             }
         }
         fnb[l] = wave_uniform(fnb[l]);
-        if (O2) snb[l] = wave_uniform(snb[l]);
+        if (O2) {
+            dio[l] = wave_uniform(dio[l]);
+            dnb[l] = wave_uniform(dnb[l]);
+        }
     }
     const double u0 = P.u[0], u1 = P.u[1], u2 = P.u[2];
     // order 2: the pseudo-time term damp * amax joins the diagonal
@@ -1365,18 +1326,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
 #pragma unroll
         for (int l = 0; l < NF; ++l) v[l] = fnb[l][k];
         const T o = fo[k];
-        // order 2: own slopes, and each face's incoming value reconstructed
-        // from its kinetic neighbour (q = 0 elsewhere)
-        T s0 = (T)0, s1 = (T)0, s2 = (T)0;
+        // order 2: the cell's increments per face, and each face's incoming
+        // value reconstructed by its kinetic neighbour
+        T di[NF];
         if constexpr (O2) {
-            const S4<T> a = sio[k];
-            s0 = a.x;
-            s1 = a.y;
-            s2 = a.z;
 #pragma unroll
             for (int l = 0; l < NF; ++l) {
-                const S4<T> b = snb[l][k];
-                v[l] += b.x * qx[l] + b.y * qy[l] + b.z * qz[l];
+                di[l] = dio[l][k];
+                v[l] += qk[l] * dnb[l][k];
             }
         }
         T x0, x1, x2, w;
@@ -1394,21 +1351,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
         T num = itau * g + idt * o;
         T den = itau + idt;
         T ap[NF];
-        T ar0 = (T)0, ar1 = (T)0, ar2 = (T)0;   // order 2: sum_{a>0} a r
 #pragma unroll
         for (int l = 0; l < NF; ++l) {
             const T a = x0 * fnx[l] + x1 * fny[l] + x2 * fnz[l];
             ap[l] = fmax(a, (T)0);
             den += ap[l];
             num -= fmin(a, (T)0) * fsc[l] * v[l];
-            if constexpr (O2) {
-                ar0 += ap[l] * rx[l];
-                ar1 += ap[l] * ry[l];
-                ar2 += ap[l] * rz[l];
-            }
+            // deferred correction of the outgoing value f_i + delta_i
+            if constexpr (O2) num -= ap[l] * di[l];
         }
-        // deferred correction of the outgoing values f_i + s_i . r
-        if constexpr (O2) num -= s0 * ar0 + s1 * ar1 + s2 * ar2;
         const T fnv = num / den;
         fn[k] = fnv;
         // moment sums relative to u_ref, FP64
