@@ -950,7 +950,8 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
         HIPCHK(launch_ghost(c->cv, h, h.W, s));
-        if (h.fast || h.points || (h.sorder == 2 && h.vdim == 3)) HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
+        if (h.fast || h.points || (h.sorder == 2 && h.vdim == 3) || h.poly)
+            HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
     }
     return GSIS_OK;
 }

@@ -1619,24 +1619,15 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
 }
 
 // the point-Jacobi sweep of both VDFs: one block per (kinetic cell, velocity
-// tile); every Gaussian is evaluated per node (the own targets need two, at
-// T_t and at T)
-template <typename T>
-struct FaceP {
-    const T *nb;
-    T n[3];
-    T A, it, th;       // Gaussian amplitude, 1/T_b, d_r T_b / 4
-    T u[3];
-    T s[6], q[3];      // Grad-13 coefficients (ghost)
-    int kind, wall;
-};
-
-template <typename T>
+// tile), faces as rows with wave-uniform bases -- a kinetic neighbour's
+// (f0, f1) rows, or the Grad-13 ghost row of an NS neighbour or the patch row
+// of a wall (times rho_w) or far field for f0 with f1 = (d_r T_b / 4) f0; the
+// own targets from per-axis Gaussian tables at T_t and T; the loads of a node
+// are issued before they are used; FP64 moment sums of both VDFs
+template <typename T, int NF>
 __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
 {
-    __shared__ FaceP<T> fs[MAXF];
     __shared__ double red[(BLOCK / 64) * NSUM];
-    __shared__ int s_nf, s_nw, s_wl[MAXW];
     // per-axis node tables: FP64 offsets c_d = x_j - u_d and weights (for the
     // sums), nodes and Gaussian factors at T_t and T in the case dtype
     __shared__ double tcd[3 * MAXA], twd[3 * MAXA];
@@ -1653,59 +1644,46 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
     const int t = item - vt * n_kin;
     const int cell = C.kin_cell[t];
     const int slot = C.slot_of_cell[cell];
-    const T *fold = (const T *)C.f[cur];
     const PolyRec &R = C.prec[slot];
+    const size_t row = (size_t)C.row;
+    const int nvp = C.row / 2;
+    const T *fold = (const T *)C.f[cur];
+    const T *fo = wave_uniform(fold + (size_t)slot * row);
+    T *fn = wave_uniform((T *)C.f[cur ^ 1] + (size_t)slot * row);
+    // faces: row base, scale (rho_w on walls), n S / V, f1 rule (kinetic row
+    // or d_r T_b / 4 times f0), wall-sum index
     const int e0 = C.cf_ptr[cell];
     const int nf = C.cf_ptr[cell + 1] - e0;
-    if (threadIdx.x == 0) {
-        s_nf = nf;
-        int nw = 0;
-        for (int l = 0; l < nf; ++l)
-            if (C.cf_wall[e0 + l] >= 0) s_wl[nw++] = l;
-        s_nw = nw;
-    }
-    if (threadIdx.x < nf) {
-        const int l = threadIdx.x, e = e0 + l;
-        const int oth = C.cf_other[e];
-        FaceP<T> F;
-        for (int d = 0; d < 3; ++d) F.n[d] = (T)C.cf_nsv[3 * (size_t)e + d];
-        F.wall = C.cf_wall[e];
-        F.nb = nullptr;
-        F.A = F.it = F.th = (T)0;
-        for (int d = 0; d < 3; ++d) F.u[d] = F.q[d] = (T)0;
-        for (int d = 0; d < 6; ++d) F.s[d] = (T)0;
-        if (oth >= 0 && C.slot_of_cell[oth] >= 0) {
-            F.kind = K_KIN;
-            F.nb = fold + (size_t)C.slot_of_cell[oth] * C.row;
-        } else if (oth >= 0) {
-            // Grad-13 ghost of the NS neighbour for f0; f1 = (d_r T/4) f0
-            F.kind = K_GHOST;
-            const double *g = C.ghost + (size_t)oth * GSIS_NMOM;
-            const double rho = g[0], Tg = g[4], p = rho * Tg;
-            F.A = (T)(rho * pow(M_PI * Tg, -1.5));
-            for (int d = 0; d < 3; ++d) F.u[d] = (T)g[1 + d];
-            F.it = (T)(1.0 / Tg);
-            F.th = (T)(0.25 * C.dr * Tg);
-            for (int d = 0; d < 6; ++d) F.s[d] = (T)(g[5 + d] / (p * Tg));
-            for (int d = 0; d < 3; ++d) F.q[d] = (T)(2.0 * g[11 + d] / (p * Tg));
-        } else {
-            const int pi = -1 - oth;
-            const double *ps = C.patch_state + 5 * pi;
-            const double Tp = ps[4];
-            double amp = pow(M_PI * Tp, -1.5);
-            if (C.patch_kind[pi] == GSIS_PATCH_WALL) {
-                F.kind = K_WALL;
-                amp *= R.rw[F.wall];
+    const T *fnb[NF];
+    T fsc[NF], fnx[NF], fny[NF], fnz[NF], fkin[NF], fth[NF];
+    int fwall[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fnb[l] = fo;
+        fsc[l] = fnx[l] = fny[l] = fnz[l] = fkin[l] = fth[l] = (T)0;
+        fwall[l] = -1;
+        if (l < nf) {
+            const int e = e0 + l;
+            const int oth = C.cf_other[e];
+            fnx[l] = (T)C.cf_nsv[3 * e];
+            fny[l] = (T)C.cf_nsv[3 * e + 1];
+            fnz[l] = (T)C.cf_nsv[3 * e + 2];
+            fsc[l] = (T)1;
+            if (oth >= 0 && C.slot_of_cell[oth] >= 0) {
+                fnb[l] = fold + (size_t)C.slot_of_cell[oth] * row;
+                fkin[l] = (T)1;
+            } else if (oth >= 0) {
+                fnb[l] = (const T *)C.grow + (size_t)C.ghost_slot[oth] * row;
+                fth[l] = (T)(0.25 * C.dr * C.ghost[(size_t)oth * GSIS_NMOM + 4]);
             } else {
-                F.kind = K_FAR;
-                amp *= ps[0];
+                const int pi = -1 - oth;
+                fnb[l] = (const T *)C.prow + (size_t)pi * row;
+                fth[l] = (T)(0.25 * C.dr * C.patch_state[5 * pi + 4]);
+                fwall[l] = C.cf_wall[e];
+                if (fwall[l] >= 0) fsc[l] = (T)R.rw[fwall[l]];
             }
-            F.A = (T)amp;
-            for (int d = 0; d < 3; ++d) F.u[d] = (T)ps[1 + d];
-            F.it = (T)(1.0 / Tp);
-            F.th = (T)(0.25 * C.dr * Tp);
         }
-        fs[l] = F;
+        fnb[l] = wave_uniform(fnb[l]);
     }
     const int n0 = C.n[0], n1 = C.n[1], n2 = C.n[2], NA3 = n0 + n1 + n2;
     for (int j = threadIdx.x; j < NA3; j += BLOCK) {
@@ -1726,18 +1704,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
     const T bt0 = (T)R.bt[0], bt1 = (T)R.bt[1], bt2 = (T)R.bt[2];
     const T br0 = (T)R.br[0], br1 = (T)R.br[1], br2 = (T)R.br[2];
     const T fx0 = (T)R.fx[0], fx1 = (T)R.fx[1], fx2 = (T)R.fx[2], fx3 = (T)R.fx[3], fx4 = (T)R.fx[4];
-    const int nw = s_nw;
-    const int nvp = C.row / 2;
-    const T *fo = fold + (size_t)slot * C.row;
-    T *fn = (T *)C.f[cur ^ 1] + (size_t)slot * C.row;
-    double acc[NSUM], wj[MAXW], ps[4] = {0, 0, 0, 0};
+    double acc[NSUM], wacc[NF], ps[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
 #pragma unroll
-    for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
+    for (int l = 0; l < NF; ++l) wacc[l] = 0.0;
     const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
     VIdx vi = vidx_init<3>(k0 + threadIdx.x, n1, n2);
     for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
+        T v0[NF], v1[NF];
+#pragma unroll
+        for (int l = 0; l < NF; ++l) {
+            v0[l] = fnb[l][k];
+            v1[l] = fnb[l][nvp + k];
+        }
+        const T o0 = fo[k], o1 = fo[nvp + k];
         const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
         vidx_step<3>(vi, n1, n2);
         const double wd = twd[jx] * twd[jy] * twd[jz];
@@ -1752,35 +1733,18 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
         const T G0 = P * (ht + hr);
         const T G1 = P * (tht * ht + Et * (bt0 * c0 + bt1 * c1 + bt2 * c2) + thr * hr +
                           Er * (br0 * c0 + br1 * c1 + br2 * c2));
-        const T o0 = fo[k], o1 = fo[nvp + k];
         T den = inv_dt + itau;
         T num0 = itau * G0 + inv_dt * o0;
         T num1 = itau * G1 + inv_dt * o1;
-        for (int l = 0; l < s_nf; ++l) {
-            const FaceP<T> &F = fs[l];
-            const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
-            if (a > (T)0) {
-                den += a;
-            } else if (a < (T)0) {
-                T v0, v1;
-                if (F.kind == K_KIN) {
-                    v0 = F.nb[k];
-                    v1 = F.nb[nvp + k];
-                } else {
-                    const T e0 = x0 - F.u[0], e1 = x1 - F.u[1], e2 = x2 - F.u[2];
-                    const T ee = e0 * e0 + e1 * e1 + e2 * e2;
-                    v0 = F.A * exp(-ee * F.it);
-                    if (F.kind == K_GHOST) {
-                        const T Q2 = F.s[0] * e0 * e0 + F.s[1] * e1 * e1 + F.s[2] * e2 * e2 +
-                                     (T)2 * (F.s[3] * e0 * e1 + F.s[4] * e0 * e2 + F.s[5] * e1 * e2);
-                        const T qd = F.q[0] * e0 + F.q[1] * e1 + F.q[2] * e2;
-                        v0 *= (T)1 + Q2 + qd * ((T)0.4 * ee * F.it - (T)1);
-                    }
-                    v1 = F.th * v0;
-                }
-                num0 -= a * v0;
-                num1 -= a * v1;
-            }
+        T ap[NF];
+#pragma unroll
+        for (int l = 0; l < NF; ++l) {
+            const T a = x0 * fnx[l] + x1 * fny[l] + x2 * fnz[l];
+            ap[l] = fmax(a, (T)0);
+            den += ap[l];
+            const T m = fmin(a, (T)0) * fsc[l];
+            num0 -= m * v0[l];
+            num1 -= m * (fkin[l] * v1[l] + fth[l] * v0[l]);
         }
         const T rden = (T)1 / den;
         const T n0v = num0 * rden, n1v = num1 * rden;
@@ -1801,17 +1765,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
         acc[S_RES + 3] += r0 * d2;
         acc[S_RES + 4] += r0 * dcc + 2.0 * wd * (double)(num1 - den * o1);
 #pragma unroll
-        for (int j = 0; j < MAXW; ++j)
-            if (j < nw) {
-                const FaceP<T> &F = fs[s_wl[j]];
-                const T a = x0 * F.n[0] + x1 * F.n[1] + x2 * F.n[2];
-                if (a > (T)0) wj[j] += wd * (double)(a * n0v);
-            }
+        for (int l = 0; l < NF; ++l) wacc[l] += wd * (double)(ap[l] * n0v);
     }
 #pragma unroll
-    for (int j = 0; j < MAXW; ++j)
+    for (int l = 0; l < NF; ++l)
 #pragma unroll
-        for (int w = 0; w < MAXW; ++w) acc[S_WALL + w] += (j < nw && fs[s_wl[j]].wall == w) ? wj[j] : 0.0;
+        for (int w = 0; w < MAXW; ++w) acc[S_WALL + w] += (fwall[l] == w) ? wacc[l] : 0.0;
     block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
     __syncthreads();
     block_reduce_store<4>(ps, C.psum + ((size_t)slot * C.ntile + vt) * 4, red);
@@ -1838,8 +1797,14 @@ hipError_t launch_fill_poly(const CaseView *cv, const CaseView &h, int mode, int
 
 hipError_t launch_sweep_poly(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
-    if (h0.dtype == GSIS_F32) hipLaunchKernelGGL((k_sweep_poly<float>), dim3(total), dim3(BLOCK), 0, s, b);
-    else hipLaunchKernelGGL((k_sweep_poly<double>), dim3(total), dim3(BLOCK), 0, s, b);
+    const bool f4 = b.nfmax <= 4;
+    if (h0.dtype == GSIS_F32) {
+        if (f4) hipLaunchKernelGGL((k_sweep_poly<float, 4>), dim3(total), dim3(BLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_sweep_poly<float, MAXF>), dim3(total), dim3(BLOCK), 0, s, b);
+    } else {
+        if (f4) hipLaunchKernelGGL((k_sweep_poly<double, 4>), dim3(total), dim3(BLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_sweep_poly<double, MAXF>), dim3(total), dim3(BLOCK), 0, s, b);
+    }
     return hipGetLastError();
 }
 
