@@ -1063,91 +1063,171 @@ hipError_t launch_flags(const CaseView *cv, const CaseView &h, double Kn_ref, in
 }
 
 // ---------------------------------------------------------------------------
-// compaction (single block, deterministic): new flags in scan_tmp[0..n);
+// compaction (deterministic, multi-block): new flags in scan_tmp[0..n); the
 // kinetic list in ascending cell id; staying cells keep their slot; freed
-// slots are reused lowest-first by new cells in ascending cell id.
+// slots are reused lowest-first by new cells in ascending cell id.  Every list
+// is a prefix sum: per-block counts, one block scans the block totals, then
+// each block writes its items at its offset (block-local order by a scan).
+// scan_tmp layout: flags [n] | used [cap] | free list [cap] | block sums.
 // ---------------------------------------------------------------------------
+constexpr int CB = 256;   // items per block of the compaction kernels
+
+// 1024-thread exclusive scan of one int per thread; returns the prefix, sm[1024] = total
 __device__ int block_excl_scan(int v, int *sm)
 {
-    // 1024-thread exclusive scan of one int per thread; returns the prefix, sm[1024] = total
-    int tid = threadIdx.x;
+    const int tid = threadIdx.x;
     sm[tid] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        int x = (tid >= off) ? sm[tid - off] : 0;
+        const int x = (tid >= off) ? sm[tid - off] : 0;
         __syncthreads();
         sm[tid] += x;
         __syncthreads();
     }
-    int incl = sm[tid];
-    int total = sm[1023];
+    const int incl = sm[tid];
+    const int total = sm[1023];
     __syncthreads();
     if (tid == 0) sm[1024] = total;
     __syncthreads();
     return incl - v;
 }
 
-__global__ __launch_bounds__(1024) void k_compact(const CaseView *__restrict__ cvp)
+// exclusive scan of one int per thread over a 256-thread block; *total = sum
+__device__ int block_excl_scan256(int v, int *sm, int *total)
+{
+    const int tid = threadIdx.x;
+    sm[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < CB; off <<= 1) {
+        const int x = (tid >= off) ? sm[tid - off] : 0;
+        __syncthreads();
+        sm[tid] += x;
+        __syncthreads();
+    }
+    const int incl = sm[tid];
+    *total = sm[CB - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_used_clear(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < C.capacity) C.scan_tmp[C.n_cells + s] = 0;
+}
+
+// slots of staying cells; per-block counts of kinetic and new cells
+__global__ __launch_bounds__(CB) void k_compact_count(const CaseView *__restrict__ cvp, int nbc)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[CB];
+    const int n = C.n_cells, cap = C.capacity;
+    int32_t *used = C.scan_tmp + n;
+    int32_t *bsum = C.scan_tmp + n + 2 * cap;     // [2 nbc] kinetic, new; then [nbs] free slots
+    const int i = blockIdx.x * CB + threadIdx.x;
+    int kin = 0, nw = 0;
+    if (i < n) {
+        kin = C.scan_tmp[i] != 0;
+        const int old = C.slot_of_cell[i];
+        if (kin && old >= 0) used[old] = 1;
+        nw = kin && old < 0;
+    }
+    int tk, tn;
+    block_excl_scan256(kin, sm, &tk);
+    block_excl_scan256(nw, sm, &tn);
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = tk;
+        bsum[nbc + blockIdx.x] = tn;
+    }
+}
+
+// per-block counts of free slots (after every staying cell has marked its slot)
+__global__ __launch_bounds__(CB) void k_free_count(const CaseView *__restrict__ cvp, int nbc)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[CB];
+    const int n = C.n_cells, cap = C.capacity;
+    const int s = blockIdx.x * CB + threadIdx.x;
+    const int f = (s < cap) ? !C.scan_tmp[n + s] : 0;
+    int tf;
+    block_excl_scan256(f, sm, &tf);
+    if (threadIdx.x == 0) C.scan_tmp[n + 2 * cap + 2 * nbc + blockIdx.x] = tf;
+}
+
+// exclusive scans of the block totals (one block; three lists), totals to the device counters
+__global__ __launch_bounds__(1024) void k_block_offsets(const CaseView *__restrict__ cvp, int nbc, int nbs)
 {
     const CaseView &C = *cvp;
     __shared__ int sm[1025];
     const int n = C.n_cells, cap = C.capacity;
-    const int32_t *fl = C.scan_tmp;              // new flags (bit 0 kinetic, bit 1 wall band)
-    int32_t *used = C.scan_tmp + n;              // [cap] slot still used by a staying cell
-    int32_t *freelist = C.scan_tmp + n + cap;    // [cap]
-    const int tid = threadIdx.x;
-    for (int s = tid; s < cap; s += 1024) used[s] = 0;
-    __syncthreads();
-    for (int i = tid; i < n; i += 1024) {
-        int kin = fl[i] != 0;
-        int old = C.slot_of_cell[i];
-        if (kin && old >= 0) used[old] = 1;
+    int32_t *bsum = C.scan_tmp + n + 2 * cap;
+    for (int list = 0; list < 3; ++list) {
+        int32_t *b = bsum + list * nbc;
+        const int m = (list < 2) ? nbc : nbs;
+        int carry = 0;
+        for (int base = 0; base < m; base += 1024) {
+            const int j = base + threadIdx.x;
+            const int v = (j < m) ? b[j] : 0;
+            const int ex = block_excl_scan(v, sm);
+            const int tot = sm[1024];
+            if (j < m) b[j] = carry + ex;
+            carry += tot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (list == 0) {
+                *C.n_kin_dev = carry;
+                if (carry > cap) C.status[1] = 1;
+            } else if (list == 1) {
+                *C.n_new_dev = carry;
+            }
+        }
     }
-    __syncthreads();
-    // free slots, ascending
-    int chunk = (cap + 1023) / 1024;
-    int lo = tid * chunk, hi = min(lo + chunk, cap), cnt = 0;
-    for (int s = lo; s < hi; ++s) cnt += !used[s];
-    int base = block_excl_scan(cnt, sm);
-    for (int s = lo; s < hi; ++s)
-        if (!used[s]) freelist[base++] = s;
-    __syncthreads();
-    // kinetic list and new cells, ascending cell id
-    chunk = (n + 1023) / 1024;
-    lo = tid * chunk;
-    hi = min(lo + chunk, n);
-    int ck = 0, cn = 0;
-    for (int i = lo; i < hi; ++i) {
-        int kin = fl[i] != 0;
-        ck += kin;
-        cn += kin && C.slot_of_cell[i] < 0;
+}
+
+__global__ __launch_bounds__(CB) void k_free_scatter(const CaseView *__restrict__ cvp, int nbc)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[CB];
+    const int n = C.n_cells, cap = C.capacity;
+    const int s = blockIdx.x * CB + threadIdx.x;
+    const int f = (s < cap) ? !C.scan_tmp[n + s] : 0;
+    int tf;
+    const int ex = block_excl_scan256(f, sm, &tf);
+    if (f) C.scan_tmp[n + cap + C.scan_tmp[n + 2 * cap + 2 * nbc + blockIdx.x] + ex] = s;
+}
+
+__global__ __launch_bounds__(CB) void k_compact_scatter(const CaseView *__restrict__ cvp, int nbc)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[CB];
+    const int n = C.n_cells, cap = C.capacity;
+    const int32_t *freelist = C.scan_tmp + n + cap;
+    const int32_t *bsum = C.scan_tmp + n + 2 * cap;
+    if (*C.n_kin_dev > cap) return;   // capacity exceeded: the lists stay as they were (block-uniform)
+    const int i = blockIdx.x * CB + threadIdx.x;
+    int kin = 0, old = -1;
+    if (i < n) {
+        kin = C.scan_tmp[i] != 0;
+        old = C.slot_of_cell[i];
     }
-    int bk = block_excl_scan(ck, sm);
-    int total_k = sm[1024];
-    int bn = block_excl_scan(cn, sm);
-    int total_n = sm[1024];
-    if (total_k > cap) {
-        if (tid == 0) C.status[1] = 1;
-        return;
-    }
-    for (int i = lo; i < hi; ++i) {
-        int kin = fl[i] != 0;
-        int old = C.slot_of_cell[i];
+    const int nw = kin && old < 0;
+    int tk, tn;
+    const int ek = block_excl_scan256(kin, sm, &tk);
+    const int en = block_excl_scan256(nw, sm, &tn);
+    if (i < n) {
         if (kin) {
-            C.kin_cell[bk++] = i;
-            if (old < 0) {
-                C.new_cell[bn] = i;
-                C.slot_of_cell[i] = freelist[bn];
-                ++bn;
+            C.kin_cell[bsum[blockIdx.x] + ek] = i;
+            if (nw) {
+                const int q = bsum[nbc + blockIdx.x] + en;
+                C.new_cell[q] = i;
+                C.slot_of_cell[i] = freelist[q];
             }
         } else {
             C.slot_of_cell[i] = -1;
         }
         C.flags[i] = kin;
-    }
-    if (tid == 0) {
-        *C.n_kin_dev = total_k;
-        *C.n_new_dev = total_n;
     }
 }
 
@@ -1166,38 +1246,73 @@ __global__ void k_ghost_mark(const CaseView *__restrict__ cvp)
     C.scan_tmp[i] = g;
 }
 
-// marked cells in ascending id -> rows of grow (single block, deterministic)
-__global__ __launch_bounds__(1024) void k_ghost_list(const CaseView *__restrict__ cvp)
+// marked cells in ascending id -> rows of grow: per-block counts, one block
+// scans them, each block writes its rows
+__global__ __launch_bounds__(CB) void k_ghost_count(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[CB];
+    const int i = blockIdx.x * CB + threadIdx.x;
+    const int g = (i < C.n_cells) ? C.scan_tmp[i] : 0;
+    int t;
+    block_excl_scan256(g, sm, &t);
+    if (threadIdx.x == 0) C.scan_tmp[C.n_cells + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void k_ghost_offsets(const CaseView *__restrict__ cvp, int nb)
 {
     const CaseView &C = *cvp;
     __shared__ int sm[1025];
-    const int n = C.n_cells, tid = threadIdx.x;
-    const int chunk = (n + 1023) / 1024;
-    const int lo = tid * chunk, hi = min(lo + chunk, n);
-    int cnt = 0;
-    for (int i = lo; i < hi; ++i) cnt += C.scan_tmp[i];
-    int base = block_excl_scan(cnt, sm);
-    const int total = sm[1024];
-    if (total > C.gcap) {
-        if (tid == 0) C.status[1] = 1;
-        return;
+    int32_t *b = C.scan_tmp + C.n_cells;
+    int carry = 0;
+    for (int base = 0; base < nb; base += 1024) {
+        const int j = base + threadIdx.x;
+        const int v = (j < nb) ? b[j] : 0;
+        const int ex = block_excl_scan(v, sm);
+        const int tot = sm[1024];
+        if (j < nb) b[j] = carry + ex;
+        carry += tot;
+        __syncthreads();
     }
-    for (int i = lo; i < hi; ++i) {
-        if (C.scan_tmp[i]) {
-            C.ghost_cell[base] = i;
-            C.ghost_slot[i] = base++;
+    if (threadIdx.x == 0) {
+        *C.n_ghost_dev = carry;
+        if (carry > C.gcap) C.status[1] = 1;
+    }
+}
+
+__global__ __launch_bounds__(CB) void k_ghost_scatter(const CaseView *__restrict__ cvp)
+{
+    const CaseView &C = *cvp;
+    __shared__ int sm[CB];
+    if (*C.n_ghost_dev > C.gcap) return;
+    const int i = blockIdx.x * CB + threadIdx.x;
+    const int g = (i < C.n_cells) ? C.scan_tmp[i] : 0;
+    int t;
+    const int ex = block_excl_scan256(g, sm, &t);
+    if (i < C.n_cells) {
+        if (g) {
+            const int r = C.scan_tmp[C.n_cells + blockIdx.x] + ex;
+            C.ghost_cell[r] = i;
+            C.ghost_slot[i] = r;
         } else {
             C.ghost_slot[i] = -1;
         }
     }
-    if (tid == 0) *C.n_ghost_dev = total;
 }
 
 hipError_t launch_compact(const CaseView *cv, const CaseView &h, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, cv);
-    hipLaunchKernelGGL(k_ghost_mark, dim3((h.n_cells + 255) / 256), dim3(256), 0, s, cv);
-    hipLaunchKernelGGL(k_ghost_list, dim3(1), dim3(1024), 0, s, cv);
+    const int nbc = (h.n_cells + CB - 1) / CB, nbs = (h.capacity + CB - 1) / CB;
+    hipLaunchKernelGGL(k_used_clear, dim3(nbs), dim3(CB), 0, s, cv);
+    hipLaunchKernelGGL(k_compact_count, dim3(nbc), dim3(CB), 0, s, cv, nbc);
+    hipLaunchKernelGGL(k_free_count, dim3(nbs), dim3(CB), 0, s, cv, nbc);
+    hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(1024), 0, s, cv, nbc, nbs);
+    hipLaunchKernelGGL(k_free_scatter, dim3(nbs), dim3(CB), 0, s, cv, nbc);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nbc), dim3(CB), 0, s, cv, nbc);
+    hipLaunchKernelGGL(k_ghost_mark, dim3(nbc), dim3(CB), 0, s, cv);
+    hipLaunchKernelGGL(k_ghost_count, dim3(nbc), dim3(CB), 0, s, cv);
+    hipLaunchKernelGGL(k_ghost_offsets, dim3(1), dim3(1024), 0, s, cv, nbc);
+    hipLaunchKernelGGL(k_ghost_scatter, dim3(nbc), dim3(CB), 0, s, cv);
     return hipGetLastError();
 }
 
