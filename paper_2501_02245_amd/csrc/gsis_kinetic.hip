@@ -582,7 +582,8 @@ hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipSt
 // delta_l = phi g . (x_face_l - x_cell) of every face l of the cell: a sweep then
 // reads one value per face, its own for outgoing values and the neighbour's on
 // the shared face for incoming ones.  One block per (kinetic cell, velocity
-// tile), the stencil's geometry formed once in FP64 by one thread (the inverse
+// tile), blocks remapped so that each XCD walks a contiguous run of cells,
+// the stencil's geometry formed once in FP64 by one thread (the inverse
 // normal matrix folded into per-neighbour coefficient vectors), then one lane
 // per velocity node with the loads of SLOPE_U nodes issued before use.  The
 // block also sums, per wall face, sum_{a>0} w a delta of the first function:
@@ -629,8 +630,10 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
     __shared__ double red[(BLOCK / 64) * MAXW];
     // set-up work arrays of thread 0 (in LDS: runtime-indexed registers would spill)
     __shared__ double dx[MAXF][3], iw[MAXF], A[9], I[9];
-    const int vt = blockIdx.x / n_kin;
-    const int t = blockIdx.x - vt * n_kin;
+    // XCD-contiguous runs of cells: neighbour rows meet in the XCD's L2
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int vt = b / n_kin;
+    const int t = b - vt * n_kin;
     const int cell = C.kin_cell[t];
     const int slot = C.slot_of_cell[cell];
     const int D = C.dim;
@@ -1438,54 +1441,110 @@ __global__ void k_param_poly(const CaseView *__restrict__ cvp, int n_kin)
 
 // conservation fix-up of the polyatomic targets: P(c) = a0 + a.c + b c^2 on
 // both, with sum w P G0 = rho, sum w c P G0 = 0 and
-// sum w (c^2 G0 + 2 G1) P = (3/2) rho T_t + (d_r/2) rho T_r, from direct FP64
-// sums over the nodes (one block per kinetic cell)
-__global__ __launch_bounds__(BLOCK) void k_fix_poly(const CaseView *__restrict__ cvp)
+// sum w (c^2 G0 + 2 G1) P = (3/2) rho T_t + (d_r/2) rho T_r.  On a tensor grid
+// every sum needed is a combination of sums of w E c^alpha over the nodes,
+// E one of the two Gaussians exp(-c^2/T_t), exp(-c^2/T), and each of those
+// factorises into three 1D sums: S[g][d][m] = sum_j w_dj e_g(c_dj) c_dj^m,
+// m <= 7.  So the block forms 2 x 3 x 8 one-dimensional FP64 sums (O(n) work
+// instead of O(n^3)), their 2 x 8^3 products, and one thread per matrix entry
+// assembles it from those.
+// One block of 64 threads per kinetic cell.
+constexpr int FIXP_THREADS = 64;
+
+// sum_nodes w E_g c^alpha (c.c)^n, n <= 3, from the products of 1D sums
+// P[(p0 8 + p1) 8 + p2] = S[g][0][p0] S[g][1][p1] S[g][2][p2]: (c.c)^n expanded
+// by the multinomial theorem, sum over i + j + k = n of n!/(i! j! k!)
+// c0^2i c1^2j c2^2k
+__device__ __forceinline__ int fact3(int x)
+{
+    return x < 2 ? 1 : (x == 2 ? 2 : 6);
+}
+
+__device__ __forceinline__ double gmom(const double *P, int a0, int a1, int a2, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i <= n; ++i)
+        for (int j = 0; i + j <= n; ++j) {
+            const int k = n - i - j;
+            const int coef = fact3(n) / (fact3(i) * fact3(j) * fact3(k));
+            s += (double)coef * P[((a0 + 2 * i) * 8 + a1 + 2 * j) * 8 + a2 + 2 * k];
+        }
+    return s;
+}
+
+// sum w E_g (1 + (kap.c)(c^2 iT - 5/2)) c^alpha (c.c)^n
+__device__ __forceinline__ double gshak(const double *P, const double *kap, double iT, int a0, int a1, int a2,
+                                        int n)
+{
+    double s = gmom(P, a0, a1, a2, n);
+    for (int i = 0; i < 3; ++i) {
+        const int b0 = a0 + (i == 0), b1 = a1 + (i == 1), b2 = a2 + (i == 2);
+        s += kap[i] * (iT * gmom(P, b0, b1, b2, n + 1) - 2.5 * gmom(P, b0, b1, b2, n));
+    }
+    return s;
+}
+
+// sum w E_g (bet.c) c^alpha (c.c)^n
+__device__ __forceinline__ double glin(const double *P, const double *bet, int a0, int a1, int a2, int n)
+{
+    return bet[0] * gmom(P, a0 + 1, a1, a2, n) + bet[1] * gmom(P, a0, a1 + 1, a2, n) +
+           bet[2] * gmom(P, a0, a1, a2 + 1, n);
+}
+
+__global__ __launch_bounds__(FIXP_THREADS) void k_fix_poly(const CaseView *__restrict__ cvp)
 {
     const CaseView &C = *cvp;
-    __shared__ double red[(BLOCK / 64) * 25];
     __shared__ double M[25];
     // per-axis offsets c_d = x_j - u_d, weights and Gaussian factors at T_t and T
-    __shared__ double tc[3 * MAXA], tw[3 * MAXA], tet[3 * MAXA], ter[3 * MAXA];
+    __shared__ double tc[3 * MAXA], tw[3 * MAXA], te[2][3 * MAXA];
+    __shared__ double S[2][3][8];
+    __shared__ double P[2][512];
     const int cell = C.kin_cell[blockIdx.x];
     const int slot = C.slot_of_cell[cell];
-    const PolyRec R = C.prec[slot];
+    const PolyRec &R = C.prec[slot];
     const int n0 = C.n[0], n1 = C.n[1], n2 = C.n[2], NA3 = n0 + n1 + n2;
-    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+    for (int j = threadIdx.x; j < NA3; j += FIXP_THREADS) {
         const int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
         const int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
         const double c = C.xv[d * MAXA + jj] - R.u[d];
         tc[j] = c;
         tw[j] = C.wv[d * MAXA + jj];
-        tet[j] = exp(-c * c * R.itt);
-        ter[j] = exp(-c * c * R.it);
+        te[0][j] = exp(-c * c * R.itt);
+        te[1][j] = exp(-c * c * R.it);
     }
     __syncthreads();
-    double acc[25];
-#pragma unroll
-    for (int i = 0; i < 25; ++i) acc[i] = 0.0;
-    VIdx vi = vidx_init<3>(threadIdx.x, n1, n2);
-    for (int k = threadIdx.x; k < C.nv; k += BLOCK) {
-        const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
-        vidx_step<3>(vi, n1, n2);
-        const double w = tw[jx] * tw[jy] * tw[jz];
-        const double c0 = tc[jx], c1 = tc[jy], c2 = tc[jz];
-        const double cc = c0 * c0 + c1 * c1 + c2 * c2;
-        const double Et = tet[jx] * tet[jy] * tet[jz], Er = ter[jx] * ter[jy] * ter[jz];
-        const double ht = R.at * Et * (1.0 + (R.kt[0] * c0 + R.kt[1] * c1 + R.kt[2] * c2) * (cc * R.itt - 2.5));
-        const double hr = R.ar * Er * (1.0 + (R.k0[0] * c0 + R.k0[1] * c1 + R.k0[2] * c2) * (cc * R.it - 2.5));
-        const double G0 = ht + hr;
-        const double G1 = R.tht * ht + Et * (R.bt[0] * c0 + R.bt[1] * c1 + R.bt[2] * c2) + R.thr * hr +
-                          Er * (R.br[0] * c0 + R.br[1] * c1 + R.br[2] * c2);
-        const double ph[5] = {1.0, c0, c1, c2, cc};
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            const double tv = (a < 4) ? ph[a] * G0 : cc * G0 + 2.0 * G1;
-#pragma unroll
-            for (int b = 0; b < 5; ++b) acc[a * 5 + b] += w * tv * ph[b];
+    if (threadIdx.x < 48) {
+        const int g = threadIdx.x / 24, d = (threadIdx.x / 8) % 3, m = threadIdx.x % 8;
+        const int j0 = (d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1), nd = C.n[d];
+        double s = 0.0;
+        for (int j = j0; j < j0 + nd; ++j) {
+            double pw = tw[j] * te[g][j];
+            for (int r = 0; r < m; ++r) pw *= tc[j];
+            s += pw;
         }
+        S[g][d][m] = s;
     }
-    block_reduce_store<25>(acc, M, red);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 1024; i += FIXP_THREADS) {
+        const int g = i >> 9, r = i & 511;
+        P[g][r] = S[g][0][r >> 6] * S[g][1][(r >> 3) & 7] * S[g][2][r & 7];
+    }
+    __syncthreads();
+    if (threadIdx.x < 25) {
+        // entry (a, b): sum w ph_a ph_b G0 for a < 4, sum w ph_b (c^2 G0 + 2 G1)
+        // for a = 4, with ph = (1, c0, c1, c2, c^2): ph_a ph_b = c^alpha (c.c)^n
+        const int a = threadIdx.x / 5, b = threadIdx.x % 5;
+        const int al0 = (a == 1) + (b == 1), al1 = (a == 2) + (b == 2), al2 = (a == 3) + (b == 3);
+        const int n = (a == 4) + (b == 4);
+        double v = R.at * gshak(P[0], R.kt, R.itt, al0, al1, al2, n) + R.ar * gshak(P[1], R.k0, R.it, al0, al1, al2, n);
+        if (a == 4) {
+            const int m0 = (b == 1), m1 = (b == 2), m2 = (b == 3), nb = (b == 4);
+            const double g1 = R.tht * R.at * gshak(P[0], R.kt, R.itt, m0, m1, m2, nb) + glin(P[0], R.bt, m0, m1, m2, nb) +
+                              R.thr * R.ar * gshak(P[1], R.k0, R.it, m0, m1, m2, nb) + glin(P[1], R.br, m0, m1, m2, nb);
+            v += 2.0 * g1;
+        }
+        M[threadIdx.x] = v;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const double *mom = C.mom + (size_t)slot * MOMS;
@@ -1780,7 +1839,7 @@ hipError_t launch_param_poly(const CaseView *cv, const CaseView &h, int n_kin, h
 {
     if (n_kin <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_param_poly, dim3((n_kin + 63) / 64), dim3(64), 0, s, cv, n_kin);
-    hipLaunchKernelGGL(k_fix_poly, dim3(n_kin), dim3(BLOCK), 0, s, cv);
+    hipLaunchKernelGGL(k_fix_poly, dim3(n_kin), dim3(FIXP_THREADS), 0, s, cv);
     return hipGetLastError();
 }
 

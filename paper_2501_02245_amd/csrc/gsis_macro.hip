@@ -39,11 +39,24 @@ __device__ __forceinline__ double bfield(const CaseView &C, int p, int v)
     return sqrt(ps[1] * ps[1] + ps[2] * ps[2] + ps[3] * ps[3]);
 }
 
+// Logical block index of the cell and face kernels.  Workgroups are
+// dispatched round-robin over the 8 XCDs; this gives XCD x the contiguous
+// range [x q + min(x, rem), ...) of blocks, so that the cells and faces of a
+// locality-ordered mesh handled on one XCD share its L2.  A bijection on
+// [0, gridDim.x); blocks keep their cells and faces, so results do not change.
+__device__ __forceinline__ int mblk()
+{
+    const int X = 8, b = blockIdx.x, nb = gridDim.x;
+    const int x = b % X, r = b / X, q = nb / X, rem = nb % X;
+    return x * q + min(x, rem) + r;
+}
+
 // case of a block in a batched launch (block-uniform)
 __device__ __forceinline__ int mb_case(const int32_t *start, int n)
 {
+    const int b = mblk();
     int j = 0;
-    while (j + 1 < n && (int)blockIdx.x >= start[j + 1]) ++j;
+    while (j + 1 < n && b >= start[j + 1]) ++j;
     return j;
 }
 
@@ -103,7 +116,7 @@ __global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
     const MLoc ML = mb_loc(B, PK_CELL);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
-    const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
+    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     const size_t nnz = (size_t)C.nnz;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_lsq_q(BT B)
     const MLoc ML = mb_loc(B, PK_GROUP);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
-    const int i = ((int)blockIdx.x - ML.base) * MCELLS_Q + (int)threadIdx.x / G;
+    const int i = (mblk() - ML.base) * MCELLS_Q + (int)threadIdx.x / G;
     const int l = (int)threadIdx.x % G;
     if (i >= C.n_cells) return;   // whole groups leave together
     const size_t nnz = (size_t)C.nnz;
@@ -404,7 +417,7 @@ __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
     const double *__restrict__ hot = ML.hot;
-    const int f = ((int)blockIdx.x - ML.base) * MBLOCK_F + (int)threadIdx.x;
+    const int f = (mblk() - ML.base) * MBLOCK_F + (int)threadIdx.x;
     if (f >= C.n_faces) return;
     int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
     const double *n = C.face_normal + 3 * (size_t)f;
@@ -549,7 +562,7 @@ __global__ __launch_bounds__(MBLOCK) void k_cons(BT B)
     const MLoc ML = mb_loc(B, PK_CELL);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
-    const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
+    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     const double *P = W + 5 * (size_t)i;
     double *U = C.U + 5 * (size_t)i;
@@ -567,7 +580,7 @@ __global__ __launch_bounds__(MBLOCK) void k_dloc(BT B)
     const MLoc ML = mb_loc(B, PK_CELL);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
-    const int blk = (int)blockIdx.x - ML.base;
+    const int blk = mblk() - ML.base;
     const int i = blk * MBLOCK + (int)threadIdx.x;
     __shared__ double sm[MBLOCK];
     double v = INFINITY;
@@ -609,7 +622,7 @@ __global__ __launch_bounds__(MBLOCK) void k_update(BT B, double cfl)
     const CaseView &C = *ML.cv;
     double *__restrict__ W = ML.W;
     const double *__restrict__ src = ML.src;
-    const int i = ((int)blockIdx.x - ML.base) * MBLOCK + (int)threadIdx.x;
+    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
     if (i >= C.n_cells) return;
     double *Wi = W + 5 * (size_t)i;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
@@ -686,7 +699,7 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
     const CaseView &C = *ML.cv;
     double *__restrict__ W = ML.W;
     const double *__restrict__ src = ML.src;
-    const int i = ((int)blockIdx.x - ML.base) * MCELLS_Q + (int)threadIdx.x / G;
+    const int i = (mblk() - ML.base) * MCELLS_Q + (int)threadIdx.x / G;
     const int l = (int)threadIdx.x % G;
     if (i >= C.n_cells) return;   // whole groups leave together
     double *Wi = W + 5 * (size_t)i;
