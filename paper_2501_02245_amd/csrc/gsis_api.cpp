@@ -59,7 +59,7 @@ struct gsis_mesh_s {
     std::vector<int32_t> cf_back;      // [nnz] local index of the face in the neighbour's list, -1 on boundaries
     std::vector<int32_t> wall_faces;   // boundary faces on diffuse-wall patches, ascending id
     std::vector<double> face_normal, face_area, face_center, cell_volume, cell_center, cf_nsv, face_dist,
-        patch_state;
+        face_dx, patch_state;
     // geometry-only factors of the macroscopic kernels
     std::vector<double> lsq;      // [2][nnz][3] least-squares coefficients: all faces / no wall faces
     std::vector<double> cf_fs;    // [nnz] -S (owner) or +S: the face's sign and area in the cell balance
@@ -307,12 +307,16 @@ extern "C" gsis_status gsis_create_mesh(const gsis_mesh_desc *d, gsis_mesh *out)
         }
     }
     m->face_dist.assign(nf, 0.0);
+    m->face_dx.assign(3 * (size_t)nf, 0.0);
     for (int f = 0; f < nf; ++f) {
         int a = m->face_cells[2 * f], b = m->face_cells[2 * f + 1];
         double dd = 0;
         if (b >= 0) {
             // normal distance between the centroids
-            for (int k = 0; k < 3; ++k) dd += (m->cell_center[3 * b + k] - m->cell_center[3 * a + k]) * m->face_normal[3 * f + k];
+            for (int k = 0; k < 3; ++k) {
+                m->face_dx[3 * (size_t)f + k] = m->cell_center[3 * b + k] - m->cell_center[3 * a + k];
+                dd += m->face_dx[3 * (size_t)f + k] * m->face_normal[3 * f + k];
+            }
         } else {
             for (int k = 0; k < 3; ++k) dd += (m->face_center[3 * f + k] - m->cell_center[3 * a + k]) * m->face_normal[3 * f + k];
             dd *= 2.0;
@@ -455,8 +459,8 @@ namespace {
 
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
-        face_dist, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
-        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, cf_back, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, dloc, red, eps;
+        face_dist, face_dx, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
+        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, cf_back, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, hface, dloc, red, eps;
     size_t total;
 };
 
@@ -574,6 +578,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.face_area = S.take(8 * nf);
     L.face_center = S.take(24 * nf);
     L.face_dist = S.take(8 * nf);
+    L.face_dx = S.take(24 * nf);
     L.cell_volume = S.take(8 * nc);
     L.cell_center = S.take(24 * nc);
     L.patch_kind = S.take(4 * np);
@@ -623,6 +628,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.Rk = S.take(40 * nc);
     L.Rm = S.take(40 * nc);
     L.fflux = S.take(40 * std::max<size_t>(nf, 1));
+    L.hface = S.take(32 * std::max<size_t>(nf, 1));
     L.dloc = S.take(8 * nc);
     L.red = S.take(8 * std::max<size_t>(8192, 8 + 6 * (nc / 256 + 2) + 256));
     L.eps = S.take(64);
@@ -753,6 +759,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(const double *, face_area, face_area);
     P(const double *, face_center, face_center);
     P(const double *, face_dist, face_dist);
+    P(const double *, face_dx, face_dx);
     P(const double *, cell_volume, cell_volume);
     P(const double *, cell_center, cell_center);
     P(const int32_t *, patch_kind, patch_kind);
@@ -820,6 +827,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(double *, Rk, Rk);
     P(double *, Rm, Rm);
     P(double *, fflux, fflux);
+    P(double *, hface, hface);
     P(double *, dloc, dloc);
     P(double *, red, red);
     P(double *, eps, eps);
@@ -846,6 +854,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(put(L.face_area, m->face_area.data(), 8 * nf));
     HIPCHK(put(L.face_center, m->face_center.data(), 24 * nf));
     HIPCHK(put(L.face_dist, m->face_dist.data(), 8 * nf));
+    HIPCHK(put(L.face_dx, m->face_dx.data(), 24 * nf));
     HIPCHK(put(L.cell_volume, m->cell_volume.data(), 8 * nc));
     HIPCHK(put(L.cell_center, m->cell_center.data(), 24 * nc));
     HIPCHK(put(L.patch_kind, m->patch_kind.data(), 4 * m->n_patches));

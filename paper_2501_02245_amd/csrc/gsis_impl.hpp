@@ -110,6 +110,7 @@ struct CaseView {
     const double *face_center;  // [n_faces][3]
     const double *face_dist;    // [n_faces] normal distance between centroids (interior) or twice
                                 // the centroid-face normal distance (boundary)
+    const double *face_dx;      // [n_faces][3] x_R - x_L between the centroids (interior faces), 0 on boundaries
     const double *cell_volume;
     const double *cell_center;  // [n_cells][3]
     const int32_t *patch_kind;
@@ -181,6 +182,7 @@ struct CaseView {
     double *Rk;                 // [n_cells][5] kinetic moment balance per unit volume
     double *Rm;                 // [n_cells][5]
     double *fflux;              // [n_faces][5]
+    double *hface;              // [n_faces][4] face means of the high-order terms: sigma.n (3), q.n (1)
     double *dloc;               // [n_cells]
     double *red;                // [1024 * 8] reduction scratch
     double *eps;                // [8]

@@ -410,13 +410,41 @@ __device__ void half_flux(const double *P, const double *n, double sgn, double *
     F[4] = rho * (m3 + (ut2 + T) * m1);
 }
 
+// The high-order terms are frozen during a macroscopic solve, and enter the
+// interior face flux only through their face means projected on the normal:
+// hface = (0.5 (sigma_L + sigma_R).n, 0.5 (q_L + q_R).n), formed once per solve
+// (zero on boundary faces and without high-order terms).
+template <class BT>
+__global__ __launch_bounds__(MBLOCK_F) void k_hot_face(BT B)
+{
+    const MLoc ML = mb_loc(B, PK_FACE);
+    const CaseView &C = *ML.cv;
+    const double *__restrict__ hot = ML.hot;
+    const int f = (mblk() - ML.base) * MBLOCK_F + (int)threadIdx.x;
+    if (f >= C.n_faces) return;
+    const int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
+    double o[4] = {0.0, 0.0, 0.0, 0.0};
+    if (Rc >= 0 && hot) {
+        const double *n = C.face_normal + 3 * (size_t)f;
+        const double *hL = hot + 9 * (size_t)L, *hR = hot + 9 * (size_t)Rc;
+        double sg[6], q[3];
+        for (int c = 0; c < 6; ++c) sg[c] = 0.5 * (hL[c] + hR[c]);
+        for (int c = 0; c < 3; ++c) q[c] = 0.5 * (hL[6 + c] + hR[6 + c]);
+        o[0] = sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2];
+        o[1] = sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2];
+        o[2] = sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2];
+        o[3] = q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+    }
+    double *hf = C.hface + 4 * (size_t)f;
+    for (int c = 0; c < 4; ++c) hf[c] = o[c];
+}
+
 template <class BT>
 __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
 {
     const MLoc ML = mb_loc(B, PK_FACE);
     const CaseView &C = *ML.cv;
     const double *__restrict__ W = ML.W;
-    const double *__restrict__ hot = ML.hot;
     const int f = (mblk() - ML.base) * MBLOCK_F + (int)threadIdx.x;
     if (f >= C.n_faces) return;
     int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
@@ -432,9 +460,7 @@ __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
         if (Rc >= 0) {
             // mean gradient corrected along n so that its projection on the
             // centroid difference equals the jump (exact for linear fields)
-            const double *xL = C.cell_center + 3 * (size_t)L, *xR = C.cell_center + 3 * (size_t)Rc;
-            double dx[3];
-            for (int d = 0; d < 3; ++d) dx[d] = xR[d] - xL[d];
+            const double *dx = C.face_dx + 3 * (size_t)f;
             const double dn = C.face_dist[f];
             double G[4][3];
             const double *gL = C.grad + (size_t)L * 18, *gR = C.grad + (size_t)Rc * 18;
@@ -453,14 +479,14 @@ __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
             double Gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
             double sg[6], q[3];
             nsf(C, Tf, Gu, G[3], sg, q);
-            const double *hL = hot + 9 * (size_t)L, *hR = hot + 9 * (size_t)Rc;
-            for (int c = 0; c < 6; ++c) sg[c] += 0.5 * (hL[c] + hR[c]);
-            for (int c = 0; c < 3; ++c) q[c] += 0.5 * (hL[6 + c] + hR[6 + c]);
-            double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2], sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
-                            sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+            // plus the face means of the frozen high-order terms (projected once per solve)
+            const double *hf = C.hface + 4 * (size_t)f;
+            double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2] + hf[0],
+                            sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2] + hf[1],
+                            sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2] + hf[2]};
             double uf[3] = {0.5 * (PL[1] + PR[1]), 0.5 * (PL[2] + PR[2]), 0.5 * (PL[3] + PR[3])};
             for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
-            F[4] += sn[0] * uf[0] + sn[1] * uf[1] + sn[2] * uf[2] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+            F[4] += sn[0] * uf[0] + sn[1] * uf[1] + sn[2] * uf[2] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2] + hf[3];
         }
     } else {
         // isothermal no-slip wall: pressure plus the NSF viscous flux from
@@ -517,7 +543,10 @@ hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const do
     if (e != hipSuccess) return e;
     MBatch b{};
     mbatch_add(b, cv, h, const_cast<double *>(W), hot, nullptr);
-    if (b.bf[1] > 0) hipLaunchKernelGGL(k_face_flux<MOne>, dim3(b.bf[1]), dim3(MBLOCK_F), 0, s, mone_of(b));
+    if (b.bf[1] > 0) {
+        hipLaunchKernelGGL(k_hot_face<MOne>, dim3(b.bf[1]), dim3(MBLOCK_F), 0, s, mone_of(b));
+        hipLaunchKernelGGL(k_face_flux<MOne>, dim3(b.bf[1]), dim3(MBLOCK_F), 0, s, mone_of(b));
+    }
     hipLaunchKernelGGL(k_residual_cells, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, Rout);
     return hipGetLastError();
 }
@@ -765,6 +794,7 @@ static void macro_steps_t(const BT &bt, const MBatch &b, int n_inner, double cfl
 {
     const dim3 gc(b.bc[b.n]), gf(b.bf[b.n]);
     hipLaunchKernelGGL(k_cons<BT>, gc, dim3(MBLOCK), 0, s, bt);
+    if (b.bf[b.n] > 0) hipLaunchKernelGGL(k_hot_face<BT>, gf, dim3(MBLOCK_F), 0, s, bt);
     const bool lanes = macro_lanes();
     const dim3 gq(b.bq[b.n]);
     for (int it = 0; it < n_inner; ++it) {
