@@ -106,6 +106,14 @@ void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, con
     b.n = j + 1;
 }
 
+// Gradient storage: the (u, T) rows of every cell, [n_cells][4][3], then the
+// (rho, |u|) rows, [n_cells][2][3].  The synthetic iteration reads only the
+// first block, which stays dense (96 B per cell).
+__device__ __forceinline__ double *grad_row(const CaseView &C, int i, int v)
+{
+    return (v < 4) ? C.grad + 12 * (size_t)i + 3 * v : C.grad + 12 * (size_t)C.n_cells + 6 * (size_t)i + 3 * (v - 4);
+}
+
 // least-squares gradients (Sec. 3.4 Step 2) from the per-face coefficients
 // built with the mesh: grad_v = sum_e c_e (phi_e - phi_i); the density uses
 // the coefficients without wall faces.  Variables: 0..2 u, 3 T [, 4 rho, 5 |u|].
@@ -146,9 +154,9 @@ __global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
         }
     }
     const double *Wi = W + 5 * (size_t)i;
-    double *go = C.grad + (size_t)i * 18;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
+        double *go = grad_row(C, i, v);
         const double fi = field(Wi, v);
         double g0 = 0.0, g1 = 0.0, g2 = 0.0;
 #pragma unroll
@@ -160,9 +168,9 @@ __global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
             g1 += cc[1] * d;
             g2 += cc[2] * d;
         }
-        go[3 * v] = g0;
-        go[3 * v + 1] = g1;
-        go[3 * v + 2] = g2;
+        go[0] = g0;
+        go[1] = g1;
+        go[2] = g2;
     }
 }
 
@@ -221,12 +229,13 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_lsq_q(BT B)
 #pragma unroll
             for (int d = 0; d < 3; ++d) g[v][d] += __shfl_xor(g[v][d], off, G);
     // every lane holds the sums: lane l writes the variables v = l (mod G)
-    double *go = C.grad + (size_t)i * 18;
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-        if (v % G == l)
+        if (v % G == l) {
+            double *go = grad_row(C, i, v);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) go[3 * v + d] = g[v][d];
+            for (int d = 0; d < 3; ++d) go[d] = g[v][d];
+        }
 }
 
 template <class BT>
@@ -305,7 +314,7 @@ __device__ void nsf(const CaseView &C, double T, const double *Gu, const double 
 
 __device__ __forceinline__ void cell_nsf(const CaseView &C, int i, double T, double *s, double *q)
 {
-    const double *g = C.grad + (size_t)i * 18;   // rows u_x, u_y, u_z, T (each d/dx_j)
+    const double *g = grad_row(C, i, 0);   // rows u_x, u_y, u_z, T (each d/dx_j)
     double Gu[9];
     for (int a = 0; a < 9; ++a) Gu[a] = g[a];
     nsf(C, T, Gu, g + 9, s, q);
@@ -463,7 +472,7 @@ __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
             const double *dx = C.face_dx + 3 * (size_t)f;
             const double dn = C.face_dist[f];
             double G[4][3];
-            const double *gL = C.grad + (size_t)L * 18, *gR = C.grad + (size_t)Rc * 18;
+            const double *gL = grad_row(C, L, 0), *gR = grad_row(C, Rc, 0);
             for (int v = 0; v < 4; ++v) {
                 double gx = 0.0;
                 for (int d = 0; d < 3; ++d) {
@@ -493,7 +502,7 @@ __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
         // one-sided gradients towards (u_w, T_w)
         const double *ps = C.patch_state + 5 * (-1 - Rc);
         const double dn = 0.5 * C.face_dist[f];
-        const double *gL = C.grad + (size_t)L * 18;
+        const double *gL = grad_row(C, L, 0);
         double pL = PL[0] * PL[4];
         for (int d = 0; d < 3; ++d) F[1 + d] = 0.5 * pL * n[d];
         double G[4][3];
@@ -857,7 +866,7 @@ __global__ __launch_bounds__(256) void k_surface(const CaseView *__restrict__ cv
         if (threadIdx.x != 0) return;
         const double *PL = C.W + 5 * (size_t)L;
         const double dn = 0.5 * C.face_dist[f];
-        const double *gL = C.grad + (size_t)L * 18;
+        const double *gL = grad_row(C, L, 0);
         double G[4][3];
         for (int v = 0; v < 4; ++v) {
             double gn = gL[3 * v] * n[0] + gL[3 * v + 1] * n[1] + gL[3 * v + 2] * n[2];
@@ -1048,13 +1057,13 @@ __global__ void k_kn_flags(const CaseView *__restrict__ cvp, double Kn_ref, int 
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= C.n_cells) return;
     const double *W = C.W + 5 * (size_t)i;
-    const double *g = C.grad + (size_t)i * 18;
+    const double *g = grad_row(C, i, 0);
     double rho = W[0], T = W[4];
     double U = sqrt(W[1] * W[1] + W[2] * W[2] + W[3] * W[3]);
     double a = sqrt(5.0 * T / 6.0);
     double lam = C.Kn * pow(T, C.omega - 0.5) / rho;
     auto nrm = [](const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
-    double kn = lam * fmax(fmax(nrm(g + 12) / rho, nrm(g + 15) / fmax(U, a)), nrm(g + 9) / T);
+    double kn = lam * fmax(fmax(nrm(grad_row(C, i, 4)) / rho, nrm(grad_row(C, i, 5)) / fmax(U, a)), nrm(g + 9) / T);
     int flag = kn >= Kn_ref;
     if (layers > 0)
         for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
