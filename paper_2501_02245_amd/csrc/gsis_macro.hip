@@ -188,8 +188,12 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_lsq_q(BT B)
     const int l = (int)threadIdx.x % G;
     if (i >= C.n_cells) return;   // whole groups leave together
     const size_t nnz = (size_t)C.nnz;
-    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
+    // the cell's own values are loaded with its face range (independent loads)
     const double *Wi = W + 5 * (size_t)i;
+    double fi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fi[v] = field(Wi, v);
+    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
     double g[NV][3];
 #pragma unroll
     for (int v = 0; v < NV; ++v) g[v][0] = g[v][1] = g[v][2] = 0.0;
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_lsq_q(BT B)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             if (v == 4 && wall) continue;
-            const double d = fo[v] - field(Wi, v);
+            const double d = fo[v] - fi[v];
             const double *cc = (v == 4) ? cr : c;
             g[v][0] = cc[0] * d;
             g[v][1] = cc[1] * d;
@@ -741,6 +745,16 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
     const int l = (int)threadIdx.x % G;
     if (i >= C.n_cells) return;   // whole groups leave together
     double *Wi = W + 5 * (size_t)i;
+    double *U = C.U + 5 * (size_t)i;
+    // the cell's own data first: these loads do not wait for its face range
+    double Wc[5], Uc[5], Sc[5] = {0, 0, 0, 0, 0};
+    for (int c = 0; c < 5; ++c) {
+        Wc[c] = Wi[c];
+        Uc[c] = U[c];
+        if (src) Sc[c] = src[5 * (size_t)i + c];
+    }
+    const double V = C.cell_volume[i];
+    const double sS0 = C.cell_sS[2 * (size_t)i], sS1 = C.cell_sS[2 * (size_t)i + 1];
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
     double R[5] = {0, 0, 0, 0, 0}, un = 0.0;
     if (l < nf) {
@@ -750,7 +764,7 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
         for (int c = 0; c < 5; ++c) R[c] = F[c] * fs;
         if (cfl >= 0) {
             const double *n = C.cf_nsv + 3 * (size_t)e;
-            un = fabs(Wi[1] * n[0] + Wi[2] * n[1] + Wi[3] * n[2]);
+            un = fabs(Wc[1] * n[0] + Wc[2] * n[1] + Wc[3] * n[2]);
         }
     }
 #pragma unroll
@@ -760,25 +774,22 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
         un += __shfl_xor(un, off, G);
     }
     if (l != 0) return;
-    const double V = C.cell_volume[i];
     if (src)
-        for (int c = 0; c < 5; ++c) R[c] += src[5 * (size_t)i + c] * V;
+        for (int c = 0; c < 5; ++c) R[c] += Sc[c] * V;
     double k;
     if (cfl < 0) {
         k = (-cfl * C.red[0]) / V;
     } else {
-        const double a = sqrt(5.0 / 3.0 * Wi[4] / 2.0);
-        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wi[4], C.omega) / (sqrt(M_PI) * Wi[0]);
-        const double *sS = C.cell_sS + 2 * (size_t)i;
-        k = cfl / (V * un + a * sS[0] + 2.0 * nu * sS[1]);
+        const double a = sqrt(5.0 / 3.0 * Wc[4] / 2.0);
+        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wc[4], C.omega) / (sqrt(M_PI) * Wc[0]);
+        k = cfl / (V * un + a * sS0 + 2.0 * nu * sS1);
     }
-    double *U = C.U + 5 * (size_t)i;
     // positivity safeguard: halve this cell's increment (at most ten times)
     // while the new density or temperature would not be positive
     double Un[5], Pn[5];
     bool ok = false;
     for (int h = 0; h <= 10 && !ok; ++h) {
-        for (int c = 0; c < 5; ++c) Un[c] = U[c] + k * R[c];
+        for (int c = 0; c < 5; ++c) Un[c] = Uc[c] + k * R[c];
         Pn[0] = Un[0];
         double u2 = 0.0;
         for (int d = 0; d < 3; ++d) {
@@ -795,7 +806,8 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
             Wi[c] = Pn[c];
         }
     }
-    if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4])) atomicOr(C.status, 1);
+    const double *Wf = ok ? Pn : Wc;
+    if (!isfinite(Wf[0] + Wf[1] + Wf[2] + Wf[3] + Wf[4])) atomicOr(C.status, 1);
 }
 
 template <class BT>
