@@ -1494,32 +1494,22 @@ __device__ __forceinline__ double glin(const double *P, const double *bet, int a
 __global__ __launch_bounds__(FIXP_THREADS) void k_fix_poly(const CaseView *__restrict__ cvp)
 {
     const CaseView &C = *cvp;
-    __shared__ double M[25];
-    // per-axis offsets c_d = x_j - u_d, weights and Gaussian factors at T_t and T
-    __shared__ double tc[3 * MAXA], tw[3 * MAXA], te[2][3 * MAXA];
+    __shared__ double M[25], Bv[5];
     __shared__ double S[2][3][8];
     __shared__ double P[2][512];
     const int cell = C.kin_cell[blockIdx.x];
     const int slot = C.slot_of_cell[cell];
     const PolyRec &R = C.prec[slot];
-    const int n0 = C.n[0], n1 = C.n[1], n2 = C.n[2], NA3 = n0 + n1 + n2;
-    for (int j = threadIdx.x; j < NA3; j += FIXP_THREADS) {
-        const int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
-        const int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
-        const double c = C.xv[d * MAXA + jj] - R.u[d];
-        tc[j] = c;
-        tw[j] = C.wv[d * MAXA + jj];
-        te[0][j] = exp(-c * c * R.itt);
-        te[1][j] = exp(-c * c * R.it);
-    }
-    __syncthreads();
     if (threadIdx.x < 48) {
+        // one 1D sum per lane, straight from the axis nodes and weights (no
+        // LDS tables: the block's small LDS footprint keeps more cells in flight)
         const int g = threadIdx.x / 24, d = (threadIdx.x / 8) % 3, m = threadIdx.x % 8;
-        const int j0 = (d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1), nd = C.n[d];
+        const double u = R.u[d], iT = g ? R.it : R.itt;
         double s = 0.0;
-        for (int j = j0; j < j0 + nd; ++j) {
-            double pw = tw[j] * te[g][j];
-            for (int r = 0; r < m; ++r) pw *= tc[j];
+        for (int j = 0; j < C.n[d]; ++j) {
+            const double c = C.xv[d * MAXA + j] - u;
+            double pw = C.wv[d * MAXA + j] * exp(-c * c * iT);
+            for (int r = 0; r < m; ++r) pw *= c;
             s += pw;
         }
         S[g][d][m] = s;
@@ -1549,8 +1539,12 @@ __global__ __launch_bounds__(FIXP_THREADS) void k_fix_poly(const CaseView *__res
     if (threadIdx.x == 0) {
         const double *mom = C.mom + (size_t)slot * MOMS;
         const double rho = mom[0], Tt = mom[4], Tr = mom[MOM_INT];
-        double A[25], b[5] = {rho, 0.0, 0.0, 0.0, 1.5 * rho * Tt + 0.5 * C.dr * rho * Tr};
-        for (int i = 0; i < 25; ++i) A[i] = M[i];
+        // elimination in place in LDS (row swaps index at run time: private
+        // arrays would live in scratch memory)
+        double *A = M, *b = Bv;
+        b[0] = rho;
+        b[1] = b[2] = b[3] = 0.0;
+        b[4] = 1.5 * rho * Tt + 0.5 * C.dr * rho * Tr;
         bool ok = true;
         for (int col = 0; col < 5 && ok; ++col) {
             int piv = col;
