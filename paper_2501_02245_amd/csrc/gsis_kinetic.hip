@@ -2208,13 +2208,15 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
             fr[k] = v0;
             if (VD == 2) fr[nvp + k] = v1;
         }
-        acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
+        if (mode != 3) {   // ghost rows carry no sums
+            acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
 #pragma unroll
-        for (int j = 0; j < MAXW; ++j)
-            if (j < nw) {
-                const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
-                if (a > (T)0) wj[j] += w * a * v0;
-            }
+            for (int j = 0; j < MAXW; ++j)
+                if (j < nw) {
+                    const T a = x0 * wn[j][0] + x1 * wn[j][1] + x2 * wn[j][2];
+                    if (a > (T)0) wj[j] += w * a * v0;
+                }
+        }
         if constexpr (!PTS) vidx_step<VD>(vi, n1, (VD == 3) ? n2 : 1);
     }
 #pragma unroll
