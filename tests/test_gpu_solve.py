@@ -102,16 +102,20 @@ def test_correction_alone(g, oracle_mod):
     assert np.abs(mo[:, 4] / Wn[:, 4] - 1).max() < 1e-12
 
 
-def test_macro_solve_alone(g, oracle_mod):
-    """Synthetic macroscopic solve with high-order terms and a source (Mach-5 cylinder, FP64)."""
-    m, grid, Kn, W, flags = workload("cylinder_small")
+@pytest.mark.parametrize("name", ["cylinder_small", "sphere_small"])
+def test_macro_solve_alone(g, oracle_mod, name):
+    """Synthetic macroscopic solve with high-order terms and a source, FP64:
+    the Mach-5 cylinder (planar) and the Mach-5 sphere (3D: every HoT
+    component, walls and far field)."""
+    m, grid, Kn, W, flags = workload(name)
     O = oracle_mod.Oracle(m, grid, Kn)
     n = m["n_cells"]
     rng = gi.rng_of(21)
     hot = 1e-3 * rng.uniform(-1, 1, (n, 9))
-    hot[:, [4, 5, 8]] = 0.0                      # planar flow: no xz, yz stress, no q_z
     src = 1e-2 * rng.uniform(-1, 1, (n, 5))
-    src[:, 3] = 0.0
+    if m["dim"] == 2:
+        hot[:, [4, 5, 8]] = 0.0                  # planar flow: no xz, yz stress, no q_z
+        src[:, 3] = 0.0
     case = g.Case(g.Mesh(m), grid, Kn, dtype=g.F64)
     for cfl, steps in ((0.5, 60), (-0.4, 20)):
         Wo = O.macro(W, hot, steps, cfl, src)
