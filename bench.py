@@ -287,6 +287,28 @@ def surface_leg(g, torch, case, mesh, es):
             "state": "after the timed steps (not converged)"}
 
 
+def synthetic_leg(torch, case, mesh, n_inner, reps=2):
+    """The synthetic macroscopic solve alone (eq. macro, FP64): n_inner
+    pseudo-time steps over every cell from the state after the timed steps,
+    zero HoT and source, local steps (cfl 0.5).  Timed with events on the
+    stream the library launches on; one untimed solve first."""
+    Wd, _ = case.get_state()
+    n = mesh["n_cells"]
+    hot = torch.zeros((n, 9), dtype=torch.float64, device="cuda")
+    Ws = [Wd.clone() for _ in range(reps + 1)]
+    case.macro_solve(Ws[0], hot, None, n_inner, 0.5)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        case.macro_solve(Ws[1 + r], hot, None, n_inner, 0.5)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"cells": n, "faces": int(len(mesh["face_cells"])), "inner_steps": n_inner, "ms": ms,
+            "us_per_inner_step": 1e3 * ms / n_inner, "cell_steps_per_s": n * n_inner / (ms / 1e3)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -345,6 +367,8 @@ def main():
     traffic = measured_traffic(n_kin_mean, nv) if dtype == g.F32 else None
     surface = surface_leg(g, torch, case, mesh, es)
     log("surface", surface)
+    synthetic = None if a.sweep_only else synthetic_leg(torch, case, mesh, a.n_inner)
+    log("synthetic solve", synthetic)
     case.close()
 
     if a.calibrate_copy > 0:
@@ -401,6 +425,7 @@ def main():
         "order2_sweep": order2,
         "poly_sweep": poly,
         "surface": surface,
+        "synthetic_solve": synthetic,
         "setup_s": setup_s,
     }
     if a.serve_requests > 0 and not a.sweep_only:
