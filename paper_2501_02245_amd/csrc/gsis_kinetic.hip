@@ -784,7 +784,7 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
                     const size_t kk = (size_t)q * nvp + k;
 #pragma unroll
                     for (int l = 0; l < NK; ++l)
-                        if (l < nfa) so[l][kk] = g0 * a0[l] + g1 * a1[l] + g2 * a2[l];
+                        if (l < nfa) __builtin_nontemporal_store(g0 * a0[l] + g1 * a1[l] + g2 * a2[l], &so[l][kk]);
                 }
                 if (q == 0) {
                     w0[u] = g0;
@@ -1364,7 +1364,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_prow(Batch B)
             if constexpr (O2) num -= ap[l] * di[l];
         }
         const T fnv = num / den;
-        fn[k] = fnv;
+        __builtin_nontemporal_store(fnv, &fn[k]);
         // moment sums relative to u_ref, FP64
         const double wd = (double)w;
         const double d0 = (double)x0 - u0, d1 = (double)x1 - u1, d2 = (double)x2 - u2;
@@ -1801,8 +1801,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
         }
         const T rden = (T)1 / den;
         const T n0v = num0 * rden, n1v = num1 * rden;
-        fn[k] = n0v;
-        fn[nvp + k] = n1v;
+        __builtin_nontemporal_store(n0v, &fn[k]);
+        __builtin_nontemporal_store(n1v, &fn[nvp + k]);
         const double dcc = d0 * d0 + d1 * d1 + d2 * d2;
         acc_moments<double, 3>(acc, wd, (double)n0v, 0.0, d0, d1, d2, dcc);
         const double h1 = wd * (double)n1v;

@@ -78,7 +78,9 @@ __device__ __forceinline__ T ldb(gcptr<T> p, uint32_t off)
 template <typename T>
 __device__ __forceinline__ void stb(gptr<T> p, uint32_t off, T v)
 {
-    *(gptr<T>)((__attribute__((address_space(1))) char *)p + off) = v;
+    // streaming store: the written row is not read again by this launch, so
+    // it should not displace neighbour rows from L2
+    __builtin_nontemporal_store(v, (gptr<T>)((__attribute__((address_space(1))) char *)p + off));
 }
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
