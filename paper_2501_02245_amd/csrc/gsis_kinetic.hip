@@ -2204,9 +2204,9 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
                 v1 = (T)Th * Es * ((T)1 + Q2 + (T)1.5 * Tg * (T)sg[2] + qd * ((T)0.4 * cc * (T)it - (T)0.4));
             }
         }
-        if (mode != 2) {
-            fr[k] = v0;
-            if (VD == 2) fr[nvp + k] = v1;
+        if (mode != 2) {   // rows read by the next launches only: streaming stores
+            __builtin_nontemporal_store(v0, &fr[k]);
+            if (VD == 2) __builtin_nontemporal_store(v1, &fr[nvp + k]);
         }
         if (mode != 3) {   // ghost rows carry no sums
             acc_moments<T, VD>(acc, w, v0, v1, c0, c1, c2, cc);
