@@ -173,6 +173,26 @@ gsis_status gsis_internal_moments(gsis_case c, double *out_dev, void *stream);
  * (E_STATE once bound); E_ARG for order not 1 or 2 or a bad damp. */
 gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double damp);
 
+/* Range limit of the Grad-13 distributions (Sec. 3.2 eq. G13_VDF) that NS
+ * cells next to the kinetic region present to it and that newly kinetic
+ * cells start from.  The paper builds them from the NS stress and heat flux
+ * without a limit; here, with r = max(max_ij |sigma_ij| / p, |q| / (p
+ * sqrt(T))), p = rho T, the pair (sigma, q) is scaled by min(1, rmax / r) so
+ * that the polynomial factor stays of order one at thermal speeds.  rmax <= 0
+ * disables the limit (the paper's form); the default is 0.5.  Call before
+ * binding (E_STATE once bound); E_ARG for a non-finite rmax. */
+gsis_status gsis_set_g13_limit(gsis_case c, double rmax);
+
+/* Activity of the two limiters since the last bind or gsis_set_state:
+ * out[6] (host) = {Grad-13 ghost rows built, of which limited; new-cell
+ * Grad-13 rows built, of which limited; GSIS corrections applied (kinetic
+ * cell-iterations), of which cut by the correction limiter (the conserved
+ * change from W^{n+1/2} to W^{n+1} is halved until density and temperature
+ * stay within a factor 2, dropped after ten halvings)}.  The counts are
+ * cumulative; take differences between calls for one step.  Synchronises
+ * `stream`. */
+gsis_status gsis_limiter_stats(gsis_case c, int64_t *out, void *stream);
+
 /* Device bytes needed to bind the case with room for `kinetic_capacity`
  * kinetic cells (VDF double buffer, per-cell sums and parameters, mesh and
  * macroscopic arrays). */

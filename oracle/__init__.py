@@ -111,8 +111,11 @@ class Oracle:
     """
 
     def __init__(self, mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, inv_dt=0.0, order=1, damp2=2.0,
-                 dr=0.0, Zr=1.0, A=None):
+                 dr=0.0, Zr=1.0, A=None, g13_rmax=0.5):
         L = lib()
+        # range limit of the Grad-13 rows (reading; None: unlimited)
+        self.g13_rmax = g13_rmax
+        self.last_g13_limited = None
         if order not in (1, 2):
             raise ValueError("spatial order must be 1 or 2")
         self.order = order
@@ -334,21 +337,26 @@ class Oracle:
             out[i, 6:] = q
         return out
 
-    G13_RMAX = 0.5
-
     def ghost_params(self, W, grad=None):
         """Grad-13 parameters (rho, u, T, sigma_NSF, q_NSF) per cell (Sec. 3.2).
 
         Reading: the Grad expansion is used inside its range of validity.  With
         r = max(max_ij |sigma_ij| / p, |q| / (p sqrt(T))), p = rho T, the pair
-        (sigma, q) is scaled by min(1, 0.5 / r), so that the polynomial factor
-        of the Grad-13 distribution stays of order one at thermal speeds (an
-        unlimited one from a strongly sheared NS field is negative over much
-        of velocity space)."""
+        (sigma, q) is scaled by min(1, rmax / r), rmax = g13_rmax (0.5 by
+        default, None: no limit), so that the polynomial factor of the Grad-13
+        distribution stays of order one at thermal speeds (an unlimited one
+        from a strongly sheared NS field is negative over much of velocity
+        space).  The cells whose pair was scaled are left in
+        ``last_g13_limited`` (bool per cell)."""
         nsf = self.nsf_field(W, grad)
         p = W[:, 0] * W[:, 4]
         r = np.maximum(np.abs(nsf[:, :6]).max(axis=1) / p, np.linalg.norm(nsf[:, 6:9], axis=1) / (p * np.sqrt(W[:, 4])))
-        theta = np.where(r > self.G13_RMAX, self.G13_RMAX / np.where(r > 0, r, 1.0), 1.0)
+        rmax = self.g13_rmax
+        if rmax is None:
+            theta = np.ones(len(W))
+        else:
+            theta = np.where(r > rmax, rmax / np.where(r > 0, r, 1.0), 1.0)
+        self.last_g13_limited = theta < 1.0
         gh = np.zeros((len(W), NMOM))
         gh[:, 0:5] = W
         gh[:, 5:11] = nsf[:, :6] * theta[:, None]
@@ -582,22 +590,25 @@ def _prim(U):
     return np.array([rho, u[0], u[1], u[2], (U[4] - rho * np.dot(u, u)) / (1.5 * rho)])
 
 
-def limit_correction(Wh, Wn, factor=2.0, halvings=10):
+def limit_correction(Wh, Wn, factor=2.0, halvings=10, with_theta=False):
     """Limiter of the GSIS correction (reading; inactive at convergence).
 
     The conserved-variable change from W^{n+1/2} to W^{n+1} of a kinetic cell
     is halved (at most ten times, then dropped) until the new density and
     temperature lie within a factor 2 of those of W^{n+1/2}, so that the
     corrected distribution stays resolvable on the velocity grid.
+    with_theta: also return the fraction of the change kept (1 = inactive,
+    0 = dropped).
     """
     Uh, Un = _cons(Wh), _cons(Wn)
     th = 1.0
     for _ in range(halvings + 1):
         W = _prim(Uh + th * (Un - Uh))
         if (Wh[0] / factor <= W[0] <= Wh[0] * factor) and (Wh[4] / factor <= W[4] <= Wh[4] * factor):
-            return W
+            return (W, th) if with_theta else W
         th *= 0.5
-    return np.array(Wh, dtype=np.float64)
+    W = np.array(Wh, dtype=np.float64)
+    return (W, 0.0) if with_theta else W
 
 
 class SteadySolver:
@@ -621,6 +632,11 @@ class SteadySolver:
         self.n = O.mesh["n_cells"]
         self.capacity = capacity if capacity is not None else self.n
         self.it = 0
+        # limiter activity of the last step and region update (readings R19b, R24):
+        # Grad-13 ghost rows and new-cell rows whose (sigma, q) were scaled, and
+        # kinetic cells whose correction was cut
+        self.stats = {"g13_ghost_limited": 0, "g13_ghosts": 0, "g13_new_limited": 0, "g13_new": 0,
+                      "corrections_limited": 0}
 
     # -- initial state ---------------------------------------------------------
     def set_state(self, W, f=None, flags=None):
@@ -672,8 +688,21 @@ class SteadySolver:
         gh = O.ghost_params(self.W, grad)
         for c in new:
             self.f[slot[c]] = O.g13(gh[c])
+        self.stats["g13_new"] = len(new)
+        self.stats["g13_new_limited"] = int(O.last_g13_limited[new].sum()) if len(new) else 0
         self.flags, self.kin, self.slot = fl, kin, slot
         return len(kin)
+
+    def ghost_cells(self):
+        """NS cells with a kinetic face neighbour (the cells whose Grad-13 rows a sweep reads)."""
+        fc = self.O.mesh["face_cells"]
+        inner = fc[:, 1] >= 0
+        a, b = fc[inner, 0], fc[inner, 1]
+        k = self.flags.astype(bool)
+        mark = np.zeros(self.n, dtype=bool)
+        mark[a[k[b] & ~k[a]]] = True
+        mark[b[k[a] & ~k[b]]] = True
+        return np.nonzero(mark)[0]
 
     # -- one outer iteration ---------------------------------------------------
     def step(self):
@@ -681,6 +710,10 @@ class SteadySolver:
         kin, slot = self.kin, self.slot
         rows = slot[kin]
         ghost = O.ghost_params(self.W) if self.mode == "agsis" else None
+        if ghost is not None:
+            gc = self.ghost_cells()
+            self.stats["g13_ghosts"] = len(gc)
+            self.stats["g13_ghost_limited"] = int(O.last_g13_limited[gc].sum())
         if self.mode != "dvm":
             Rk = O.kinetic_residual(self.f, kin, slot, ghost)
         f_half = O.sweep(self.f, kin, slot, ghost)
@@ -707,9 +740,12 @@ class SteadySolver:
             W_new = O.macro(W_old, hot, self.n_inner, self.cfl, src)
             # GSIS correction (first eq. updatef), with the change of the
             # conserved moments limited on each kinetic cell
+            cut = 0
             for c in kin:
-                W_new[c] = limit_correction(W_half[c], W_new[c])
+                W_new[c], th = limit_correction(W_half[c], W_new[c], with_theta=True)
+                cut += th < 1.0
                 f_half[slot[c]] += O.feq(W_new[c]) - O.feq(W_half[c])
+            self.stats["corrections_limited"] = int(cut)
             self.f = f_half
         eps = O.residual(W_new, W_old)
         self.W = W_new

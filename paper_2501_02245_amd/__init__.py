@@ -31,6 +31,7 @@ EXPORTS = [
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
     "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
     "gsis_set_spatial_order", "gsis_set_internal_dof", "gsis_internal_moments",
+    "gsis_set_g13_limit", "gsis_limiter_stats",
 ]
 
 
@@ -111,6 +112,7 @@ def lib():
             "gsis_set_velocity_points": [P, I32, P, P],
             "gsis_set_spatial_order": [P, I32, D],
             "gsis_set_internal_dof": [P, D, D, P], "gsis_internal_moments": [P, P, P],
+            "gsis_set_g13_limit": [P, D], "gsis_limiter_stats": [P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -217,10 +219,11 @@ class Case:
     """One steady problem bound to a torch-allocated device workspace."""
 
     def __init__(self, mesh: Mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, dtype=F32, capacity=None,
-                 order=1, damp2=2.0, dr=0.0, Zr=1.0, A=None):
+                 order=1, damp2=2.0, dr=0.0, Zr=1.0, A=None, g13_rmax=0.5):
         """order 2: second-order face values with pseudo-time factor damp2
         (gsis_set_spatial_order); dr > 0: the polyatomic gas with Zr and the
-        heat-flux matrix A (gsis_set_internal_dof)."""
+        heat-flux matrix A (gsis_set_internal_dof); g13_rmax: range limit of
+        the Grad-13 rows (gsis_set_g13_limit; None or <= 0: unlimited)."""
         import torch
         self.mesh = mesh
         self.dtype = dtype
@@ -237,6 +240,7 @@ class Case:
             Av = np.ascontiguousarray(A if A is not None else (Pr, 0.0, 0.0, 1.0), dtype=np.float64)
             _check(lib().gsis_set_internal_dof(h, C.c_double(dr), C.c_double(Zr), C.c_void_p(Av.ctypes.data)))
             self.nfun = 2
+        _check(lib().gsis_set_g13_limit(h, C.c_double(0.0 if g13_rmax is None else g13_rmax)))
         self.points = grid.get("kind") == "points"
         self.nv = grid_nv(grid)
         self.capacity = int(capacity or mesh.n_cells)
@@ -288,6 +292,14 @@ class Case:
         out = torch.empty((self.n_kin, 4), dtype=torch.float64, device="cuda")
         _check(lib().gsis_internal_moments(self.handle, _ptr(out), _stream()))
         return out
+
+    def limiter_stats(self):
+        """Cumulative limiter activity since bind / set_state (gsis_limiter_stats)."""
+        v = (C.c_int64 * 6)()
+        _check(lib().gsis_limiter_stats(self.handle, v, _stream()))
+        keys = ("g13_ghosts", "g13_ghost_limited", "g13_new", "g13_new_limited", "corrections",
+                "corrections_limited")
+        return dict(zip(keys, [int(x) for x in v]))
 
     def get_vdf(self):
         import torch

@@ -78,6 +78,7 @@ struct gsis_case_s {
     int32_t order = 1;          // spatial order of the kinetic face values
     double damp2 = 2.0;         // pseudo-time factor of the order-2 iteration
     double dr = 0.0, Zr = 1.0, A[4] = {0, 0, 0, 0};   // polyatomic gas (dr > 0)
+    double g13_rmax = 0.5;      // range limit of the Grad-13 rows (<= 0: none)
     bool grid_set = false, bound = false, state_set = false;
     int32_t capacity = 0, tile = 0, ntile = 0, row = 0;
     unsigned char *ws = nullptr;
@@ -444,6 +445,27 @@ extern "C" gsis_status gsis_set_internal_dof(gsis_case c, double d_r, double Z_r
     return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_set_g13_limit(gsis_case c, double rmax)
+{
+    if (!c) return fail(GSIS_E_ARG, "null case");
+    if (c->bound) return fail(GSIS_E_STATE, "the Grad-13 limit must be set before binding");
+    if (!std::isfinite(rmax)) return fail(GSIS_E_ARG, "rmax must be finite");
+    c->g13_rmax = rmax;
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_limiter_stats(gsis_case c, int64_t *out, void *stream)
+{
+    if (!c || !out) return fail(GSIS_E_ARG, "null argument");
+    if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
+    unsigned long long v[6];
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(v, c->hv.lim, sizeof v, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < 6; ++i) out[i] = (int64_t)v[i];
+    return GSIS_OK;
+}
+
 extern "C" gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double damp)
 {
     if (!c) return fail(GSIS_E_ARG, "null case");
@@ -460,7 +482,7 @@ namespace {
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, face_dx, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
-        status, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, cf_back, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, hface, dloc, red, eps;
+        status, lim, g13th, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, cf_back, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, hface, dloc, red, eps;
     size_t total;
 };
 
@@ -596,6 +618,8 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.nnew = S.take(16);
     L.scan = S.take(4 * (2 * nc + 2 * (size_t)cap + 1024));
     L.status = S.take(16);
+    L.lim = S.take(64);
+    L.g13th = S.take(8 * nc);
     const size_t gcap = ghost_capacity(m->n_cells, cap);
     L.prow = S.take(es * np * (*row));
     L.grow = S.take(es * gcap * (*row));
@@ -779,6 +803,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     P(int32_t *, n_new_dev, nnew);
     P(int32_t *, scan_tmp, scan);
     P(int32_t *, status, status);
+    P(unsigned long long *, lim, lim);
+    P(double *, g13_th, g13th);
     P(void *, prow, prow);
     P(void *, grow, grow);
     P(int32_t *, ghost_slot, gslot);
@@ -798,6 +824,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     }
     h.sorder = c->order;
     h.damp2 = c->damp2;
+    h.g13_rmax = c->g13_rmax;
     h.poly = c->dr > 0 ? 1 : 0;
     h.dr = c->dr;
     h.Zr = c->Zr;
@@ -872,6 +899,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.flags, 0, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.status, 0, 16, s));
+    HIPCHK(hipMemsetAsync(B + L.lim, 0, 64, s));
     HIPCHK(hipMemsetAsync(B + L.gslot, 0xff, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.ngh, 0, 16, s));
     HIPCHK(hipMemsetAsync(B + L.prow, 0, L.gslot - L.prow, s));
@@ -911,6 +939,7 @@ extern "C" gsis_status gsis_set_state(gsis_case c, const double *W_dev, const vo
     CaseView &h = c->hv;
     c->state_set = false;
     HIPCHK(hipMemsetAsync(h.status, 0, 16, s));
+    HIPCHK(hipMemsetAsync(h.lim, 0, 64, s));
     HIPCHK(launch_copy_W(h.W, W_dev, h.n_cells, s));
     HIPCHK(launch_check_W(c->cv, h, h.W, s));
     HIPCHK(hipMemsetAsync(h.slot_of_cell, 0xff, 4 * (size_t)h.n_cells, s));
@@ -959,6 +988,7 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
         HIPCHK(launch_ghost(c->cv, h, h.W, s));
+        HIPCHK(launch_count_g13(c->cv, h.ghost_cell, c->n_ghost, 0, s));
         if (h.fast || h.points || (h.sorder == 2 && h.vdim == 3) || h.poly)
             HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
     }
@@ -1118,6 +1148,7 @@ extern "C" gsis_status gsis_update_regions(gsis_case c, double Kn_ref, int32_t l
     if (n_new > 0) {
         // Grad-13 of the current W (gradients of u, T are in grad after launch_flags)
         HIPCHK(launch_ghost(c->cv, h, h.W, s));
+        HIPCHK(launch_count_g13(c->cv, h.new_cell, n_new, 1, s));
         HIPCHK(launch_fill(c->cv, h, 1, n_new, c->cur, s));
     }
     HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));

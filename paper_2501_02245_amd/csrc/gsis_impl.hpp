@@ -186,6 +186,14 @@ struct CaseView {
     double *dloc;               // [n_cells]
     double *red;                // [1024 * 8] reduction scratch
     double *eps;                // [8]
+    // range limit of the Grad-13 rows (<= 0: unlimited), the factor each cell's
+    // (sigma, q) was scaled by at the last Grad-13 build [n_cells], and the
+    // cumulative limiter counters (see gsis_limiter_stats): rows built and rows
+    // limited for ghosts [0, 1] and new cells [2, 3], corrections applied and
+    // cut [4, 5]
+    double g13_rmax;
+    double *g13_th;
+    unsigned long long *lim;
 };
 
 struct Batch {
@@ -272,6 +280,9 @@ hipError_t launch_gather_vdf(const CaseView *cv, const CaseView &h, int n_kin, i
 // --- launch wrappers (gsis_macro.hip) ----------------------------------------
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s);
 hipError_t launch_ghost(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s);
+// add to the limiter counters lim[2 which], lim[2 which + 1] the n cells of
+// list and those whose Grad-13 pair was scaled (list and n from the host)
+hipError_t launch_count_g13(const CaseView *cv, const int32_t *list, int n, int which, hipStream_t s);
 hipError_t launch_hot(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 hipError_t launch_whalf(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 hipError_t launch_macro_residual(const CaseView *cv, const CaseView &h, const double *W, const double *hot,

@@ -518,10 +518,10 @@ __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const in
 {
     const CaseView &C = *cvp;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_items) return;
-    int cell = list[t];
-    int slot = C.slot_of_cell[cell];
-    if (mode == 0) {
+    const bool live = t < n_items;
+    const int cell = live ? list[t] : 0;
+    bool cut = false;
+    if (mode == 0 && live) {
         // limiter of the correction: halve the conserved-variable change from
         // W_half to W_new (at most ten times, then drop it) until density and
         // temperature stay within a factor 2 of W_half; W_new takes the result
@@ -538,7 +538,8 @@ __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const in
         for (int c = 0; c < 5; ++c) Ud[c] -= Uh[c];
         double th = 1.0, Wl[5];
         bool ok = false;
-        for (int h = 0; h <= 10 && !ok; ++h) {
+        int h = 0;
+        for (; h <= 10 && !ok; ++h) {
             double U0 = Uh[0] + th * Ud[0];
             double u2 = 0.0;
             Wl[0] = U0;
@@ -550,8 +551,17 @@ __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const in
             ok = (wh[0] / 2.0 <= Wl[0]) && (Wl[0] <= 2.0 * wh[0]) && (wh[4] / 2.0 <= Wl[4]) && (Wl[4] <= 2.0 * wh[4]);
             th *= 0.5;
         }
+        cut = !ok || h > 1;
         for (int c = 0; c < 5; ++c) wn[c] = ok ? Wl[c] : wh[c];
     }
+    if (mode == 0) {
+        // limiter counters (one atomic per wave)
+        const unsigned long long m = __ballot(cut);
+        if ((threadIdx.x & 63) == 0 && m) atomicAdd(&C.lim[5], (unsigned long long)__popcll(m));
+        if (t == 0) atomicAdd(&C.lim[4], (unsigned long long)n_items);
+    }
+    if (!live) return;
+    int slot = C.slot_of_cell[cell];
     for (int which = 0; which < (mode == 0 ? 2 : 1); ++which) {
         const double *W = (mode == 0) ? ((which == 0 ? C.Wn : C.Wh) + 5 * (size_t)cell) : (C.W + 5 * (size_t)cell);
         FeqRec F;

@@ -325,7 +325,6 @@ __device__ __forceinline__ void cell_nsf(const CaseView &C, int i, double T, dou
 }
 
 // Grad-13 parameters of every cell from W and the gradients of W
-constexpr double G13_RMAX = 0.5;
 
 __global__ void k_ghost(const CaseView *__restrict__ cvp, const double *__restrict__ W)
 {
@@ -337,13 +336,15 @@ __global__ void k_ghost(const CaseView *__restrict__ cvp, const double *__restri
     for (int c = 0; c < 5; ++c) g[c] = Wi[c];
     double s[6], q[3];
     cell_nsf(C, i, Wi[4], s, q);
-    // Grad expansion inside its range: (sigma, q) scaled by min(1, 0.5 / r),
-    // r = max(max |sigma_ij| / p, |q| / (p sqrt T)), p = rho T
+    // Grad expansion inside its range: (sigma, q) scaled by min(1, rmax / r),
+    // r = max(max |sigma_ij| / p, |q| / (p sqrt T)), p = rho T (rmax <= 0: no limit)
     const double p = Wi[0] * Wi[4];
     double smax = 0.0;
     for (int c = 0; c < 6; ++c) smax = fmax(smax, fabs(s[c]));
     const double r = fmax(smax / p, sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (p * sqrt(Wi[4])));
-    const double th = (r > G13_RMAX) ? G13_RMAX / r : 1.0;
+    const double rmax = C.g13_rmax;
+    const double th = (rmax > 0.0 && r > rmax) ? rmax / r : 1.0;
+    C.g13_th[i] = th;
     for (int c = 0; c < 6; ++c) g[5 + c] = s[c] * th;
     for (int c = 0; c < 3; ++c) g[11 + c] = q[c] * th;
     if (C.vdim == 2) {
@@ -356,6 +357,25 @@ __global__ void k_ghost(const CaseView *__restrict__ cvp, const double *__restri
 hipError_t launch_ghost(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s)
 {
     hipLaunchKernelGGL(k_ghost, dim3((h.n_cells + 127) / 128), dim3(128), 0, s, cv, W);
+    return hipGetLastError();
+}
+
+// limiter counters: cells of a list, and those whose Grad-13 pair was scaled
+// (one atomic per wave; the integer sums do not depend on the order)
+__global__ void k_count_g13(const CaseView *__restrict__ cvp, const int32_t *__restrict__ list, int n, int which)
+{
+    const CaseView &C = *cvp;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool lim = (t < n) && C.g13_th[list[t]] < 1.0;
+    const unsigned long long m = __ballot(lim);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&C.lim[2 * which + 1], (unsigned long long)__popcll(m));
+    if (t == 0) atomicAdd(&C.lim[2 * which], (unsigned long long)n);
+}
+
+hipError_t launch_count_g13(const CaseView *cv, const int32_t *list, int n, int which, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_g13, dim3((n + 255) / 256), dim3(256), 0, s, cv, list, n, which);
     return hipGetLastError();
 }
 

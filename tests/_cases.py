@@ -92,15 +92,24 @@ def workload(name):
 
 
 def f_error(fg, fo, w):
-    """max over cells of the quadrature-weighted L2 error of the rows, relative."""
+    """Relative error of the rows, the larger of two measures, maxed over cells:
+    the quadrature-weighted L2 error of the cell's rows over their L2 norm, and
+    the element-wise max |g - o| over the cell's largest |o| (so that an error
+    on low-weight tail nodes cannot hide in the L2 norm)."""
     fg = np.asarray(fg, dtype=np.float64).reshape(fo.shape)
     num = np.sqrt(np.einsum("k,ijk->i", w, (fg - fo) ** 2))
     den = np.sqrt(np.einsum("k,ijk->i", w, fo ** 2))
-    return float(np.max(num / den))
+    cells = fo.reshape(fo.shape[0], -1)
+    pw = np.abs(fg.reshape(cells.shape) - cells).max(axis=1) / np.abs(cells).max(axis=1)
+    return float(max(np.max(num / den), np.max(pw)))
 
 
 def moment_errors(mg, mo, u_scale=0.0):
-    """Per-field error max_i |g - o| / max_i |o| (u divided by max(max|u|, u_scale))."""
+    """Per-field error max_i |g - o| / max_i |o| (u divided by max(max|u|, u_scale)),
+    and per cell ("*_cell"): rho and T relative to the cell's value, u to the
+    cell's thermal speed sqrt(T), sigma to its pressure p = rho T and q to
+    p sqrt(T), maxed over cells (a field that is small somewhere is still held
+    to its physical scale there)."""
     mg = np.asarray(mg)
     out = {}
     for name, sl in (("rho", [0]), ("u", [1, 2, 3]), ("T", [4]), ("sigma", list(range(5, 11))),
@@ -110,4 +119,9 @@ def moment_errors(mg, mo, u_scale=0.0):
         if name == "u":
             s = max(s, u_scale)
         out[name] = d / s if s > 0 else d
+    rho, T = mo[:, 0], mo[:, 4]
+    p = rho * T
+    for name, sl, scale in (("rho_cell", [0], rho), ("u_cell", [1, 2, 3], np.sqrt(T)), ("T_cell", [4], T),
+                            ("sigma_cell", list(range(5, 11)), p), ("q_cell", [11, 12, 13], p * np.sqrt(T))):
+        out[name] = float((np.abs(mg[:, sl] - mo[:, sl]).max(axis=1) / scale).max())
     return out

@@ -23,7 +23,7 @@ def g():
 
 def test_exports_match_header(g):
     hdr = open(os.path.join(ROOT, "include", "gsis.h")).read()
-    declared = set(re.findall(r"\b(gsis_[a-z_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(gsis_[a-z0-9_]+)\s*\(", hdr))
     assert declared == set(g.EXPORTS)
     L = g.lib()
     for name in declared:

@@ -98,8 +98,7 @@ def test_largest_axis(g, oracle_mod, vdim):
     case = make_case(g, "largest", m, grid, Kn, g.F32)
     assert case.sweep_layout()[0] == 1
     case.set_state(W, vdf=f0, flags=flags)
-    Wg = case.get_state()[0].cpu().numpy()
-    ghost = O.ghost_params(Wg)
+    ghost = O.ghost_params(W)
     fo = O.sweep(f0, kin, slot, ghost)
     case.sweep(1)
     fg = case.get_vdf().cpu().numpy()

@@ -9,7 +9,8 @@ The oracle cannot sweep 2.8e9 points in a test, so one sweep is compared on
 48 sampled kinetic cells (random ones, wall cells, cells next to the NS
 region and to the far field), each recomputed from exactly the same FP32
 input rows; the GSIS correction is checked by a property that holds at any
-size (the conserved moments of the corrected VDF are the new W).
+size (the conserved moments of the corrected VDF are the new W) and on
+sampled cells against the oracle.
 """
 import numpy as np
 import pytest
@@ -128,22 +129,56 @@ def test_fullsize_sweep_sampled(g, oracle_mod, big):
         assert v < 1e-5, (k, v)
 
 
-def test_fullsize_correction_property(g, big):
-    """f += f_eq(W_new) - f_eq(W_half) with fixed-up Maxwellians: the conserved
-    moments of the result are W_new on every kinetic cell (FP32 storage)."""
+def test_fullsize_correction_sampled(g, oracle_mod, big):
+    """GSIS correction at the benchmark size, in the benchmark's launch
+    configuration: f += f_eq(W_new) - f_eq(W_half) with fixed-up Maxwellians
+    and the correction limiter, from the generator's rows.  The sampled cells
+    are recomputed by the oracle from the same FP32 rows and the same W_new;
+    on every kinetic cell the conserved moments of the result are W_new (FP32
+    storage)."""
     import torch
-    mesh, flags, kin, case = (big[k] for k in ("mesh", "flags", "kin", "case"))
-    Wh, _ = case.get_state()
-    Wh = Wh.cpu().numpy()
+    mesh, grid, W, flags, kin, case = (big[k] for k in ("mesh", "grid", "W", "flags", "kin", "case"))
+    # reset to the generator's rows (earlier tests swept them)
+    ax, ay, az = gi.separable_row_factors(grid, W, kin, seed=SEED_ROWS)
+    tx, ty, tz = (torch.from_numpy(a).cuda() for a in (ax, ay, az))
+    rows = ((tx[:, :, None, None] * ty[:, None, :, None]) * tz[:, None, None, :]).reshape(len(kin), 1, -1)
+    case.set_state(W, vdf=rows, flags=flags)
+    del rows, tx, ty, tz
+    torch.cuda.empty_cache()
     n = mesh["n_cells"]
     ph = np.arange(n, dtype=np.float64)
-    Wn = Wh.copy()
+    Wn = W.copy()
     Wn[:, 0] *= 1.0 + 0.01 * np.sin(ph)
     Wn[:, 1:4] += 0.01 * np.cos(ph)[:, None]
     Wn[:, 4] *= 1.0 + 0.01 * np.cos(0.7 * ph)
     case.correct(Wn)
     mg, kc = case.moments()
     mg = mg.cpu().numpy()
+    sample = _sample(mesh, flags, kin, seed=8)
+    pos = np.searchsorted(kin, sample)
+    fg = case.get_vdf()
+    fs = fg[torch.from_numpy(pos).cuda()].cpu().numpy()
+    del fg
+    torch.cuda.empty_cache()
+    # oracle: the same rows, its own W_half, the same W_new through its limiter
+    O = oracle_mod.Oracle(mesh, grid, KN)
+    f = gi.assemble_separable_rows(*gi.separable_row_factors(grid, W, sample, seed=SEED_ROWS)).astype(np.float64)
+    Wh = O.moments(f)[:, :5]
+    fo = np.empty_like(f)
+    Wk = np.empty((len(sample), 5))
+    cut = 0
+    for j, c in enumerate(sample):
+        Wk[j], th = oracle_mod.limit_correction(Wh[j], Wn[c], with_theta=True)
+        cut += th < 1.0
+        fo[j] = f[j] + O.feq(Wk[j]) - O.feq(Wh[j])
+    ef = f_error(fs, fo, O.w)
+    em = moment_errors(mg[pos], O.moments(fo), u_scale=1.0)
+    print("full size correction: f", ef, "moments", em, "limited", cut, flush=True)
+    assert ef < 1e-5
+    for k, v in em.items():
+        assert v < 1e-5, (k, v)
+    # every kinetic cell: the conserved moments are W_new (none is limited here)
+    assert cut == 0
     Wk = Wn[kin]
     err_rho = np.abs(mg[:, 0] / Wk[:, 0] - 1).max()
     err_u = np.abs(mg[:, 1:4] - Wk[:, 1:4]).max()

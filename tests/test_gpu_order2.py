@@ -53,8 +53,7 @@ def test_order2_one_sweep(g, oracle_mod, name, dtype):
     case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype, order=2)
     assert case.sweep_layout()[0] == 0
     case.set_state(W, vdf=f0, flags=flags)
-    Wg = case.get_state()[0].cpu().numpy()
-    ghost = O.ghost_params(Wg) if len(kin) < m["n_cells"] else None
+    ghost = O.ghost_params(W) if len(kin) < m["n_cells"] else None
     fo = O.sweep(f0, kin, slot, ghost)
     case.sweep(1)
     fg = case.get_vdf().cpu().numpy()
@@ -85,7 +84,7 @@ def test_order2_generic_kernel_3d(g, oracle_mod, dtype, monkeypatch):
     W[kin] = O.moments(f0)[:, :5]
     case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype, order=2)
     case.set_state(W, vdf=f0, flags=flags)
-    ghost = O.ghost_params(case.get_state()[0].cpu().numpy())
+    ghost = O.ghost_params(W)
     fo = O.sweep(f0, kin, slot, ghost)
     case.sweep(1)
     ef = f_error(case.get_vdf().cpu().numpy(), fo, O.w)

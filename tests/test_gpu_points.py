@@ -49,8 +49,7 @@ def test_points_one_sweep(g, oracle_mod, name, dtype):
     case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype)
     assert case.sweep_layout()[0] == 0 and case.nv == len(grid["pweights"])
     case.set_state(W, vdf=f0, flags=flags)
-    Wg = case.get_state()[0].cpu().numpy()
-    ghost = O.ghost_params(Wg) if len(kin) < m["n_cells"] else None
+    ghost = O.ghost_params(W) if len(kin) < m["n_cells"] else None
     fo = O.sweep(f0, kin, slot, ghost)
     case.sweep(1)
     fg = case.get_vdf().cpu().numpy()

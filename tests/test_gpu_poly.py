@@ -62,8 +62,7 @@ def test_poly_one_sweep(g, oracle_mod, name, dtype):
     mg0, _ = case.moments()
     ig0 = case.internal_moments().cpu().numpy()
     assert np.abs(ig0[:, 0] / mo[:, 14] - 1).max() < TOL[dtype]
-    Wg = case.get_state()[0].cpu().numpy()
-    ghost = O.ghost_params(Wg) if len(kin) < m["n_cells"] else None
+    ghost = O.ghost_params(W) if len(kin) < m["n_cells"] else None
     fo = O.sweep(f0, kin, slot, ghost)
     case.sweep(1)
     fg = case.get_vdf().cpu().numpy()
@@ -74,12 +73,17 @@ def test_poly_one_sweep(g, oracle_mod, name, dtype):
     em = moment_errors(mg.cpu().numpy(), m_o[:, :14], u_scale=1.0)
     ig = case.internal_moments().cpu().numpy()
     eTr = np.abs(ig[:, 0] - m_o[:, 14]).max() / np.abs(m_o[:, 14]).max()
-    eqr = np.abs(ig[:, 1:] - m_o[:, 15:]).max() / np.abs(m_o[:, 15:]).max()
+    # q_r = 2 sum w c f1 is a first moment of f1 about u, a small difference of
+    # terms of size rho T_r sqrt(T) (the internal energy carried at the thermal
+    # speed): each cell's error is measured on that scale, as sigma and q are
+    # on p and p sqrt(T)
+    scale = m_o[:, 0] * m_o[:, 14] * np.sqrt(m_o[:, 4])
+    eqr = float((np.abs(ig[:, 1:] - m_o[:, 15:]).max(axis=1) / scale).max())
     print("poly", name, dtype, "f", ef, "moments", em, "T_r", eTr, "q_r", eqr, flush=True)
     assert ef < TOL[dtype]
     for k, v in em.items():
         assert v < TOL[dtype], (k, v)
-    assert eTr < TOL[dtype] and eqr < 10 * TOL[dtype]
+    assert eTr < TOL[dtype] and eqr < TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [0, 1])

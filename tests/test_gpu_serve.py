@@ -64,6 +64,7 @@ def test_served_matches_oracle(g, oracle_mod):
             e = S.step()
             if np.max(e[list(r.fields)]) < 1e-6:
                 break
+        assert np.max(e[list(r.fields)]) < 1e-6, ("oracle did not converge", r.rid, e)
         err = {"rho": np.abs(out.W[:, 0] - S.W[:, 0]).max() / np.abs(S.W[:, 0]).max(),
                "u": np.abs(out.W[:, 1:4] - S.W[:, 1:4]).max() / max(np.abs(S.W[:, 1:4]).max(), 0.1),
                "T": np.abs(out.W[:, 4] - S.W[:, 4]).max() / np.abs(S.W[:, 4]).max()}

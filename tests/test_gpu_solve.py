@@ -173,6 +173,7 @@ def test_agsis_steps(g, oracle_mod, name, dtype):
     p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, n_macro_inner=100, cfl=0.5, region_update_every=1,
                       force_wall_layers=2)
     tol = 1e-9 if dtype == g.F64 else 1e-4
+    last = case.limiter_stats()
     for it in range(4):
         eo = S.step()
         eg = case.step(p)
@@ -180,10 +181,17 @@ def test_agsis_steps(g, oracle_mod, name, dtype):
         Wg = Wg.cpu().numpy()
         fl = fl.cpu().numpy()
         err = _fields_err(Wg, S.W, 1.0)
-        print(it, "eps", eo, eg, "n_kin", len(S.kin), case.n_kin, "err", err, flush=True)
+        # limiter activity of this step (Grad-13 range limit, correction limit)
+        now = case.limiter_stats()
+        d = {k: now[k] - last[k] for k in now}
+        last = now
+        print(it, "eps", eo, eg, "n_kin", len(S.kin), case.n_kin, "err", err, "limiters", d, S.stats, flush=True)
         assert np.array_equal(fl, S.flags)
         assert max(err.values()) < tol
         assert np.allclose(eg, eo, rtol=1e-3 if dtype == g.F32 else 1e-7)
+        assert d["g13_ghosts"] == S.stats["g13_ghosts"] and d["g13_ghost_limited"] == S.stats["g13_ghost_limited"]
+        assert d["g13_new"] == S.stats["g13_new"] and d["g13_new_limited"] == S.stats["g13_new_limited"]
+        assert d["corrections_limited"] == S.stats["corrections_limited"]
 
 
 def test_agsis_region_schedule_once(g, oracle_mod):
