@@ -204,6 +204,19 @@ gsis_status gsis_case_footprint(gsis_case c, int64_t kinetic_capacity, size_t *b
 gsis_status gsis_case_bind(gsis_case c, void *dev_workspace, size_t bytes, int64_t kinetic_capacity,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call the allocator, harnesses that
+ * forbid it): bind the case to the library's static device workspace instead
+ * of a caller-owned one.  The workspace is a fixed 256 MiB array per GPU,
+ * held by the library until the process ends; a case whose footprint exceeds
+ * it is refused with GSIS_E_NOMEM.  The call allocates nothing (no hipMalloc,
+ * no events: gsis_last_sweep_ms reports E_STATE for such a case).  One case
+ * per GPU owns the array: binding another case to it leaves the previous
+ * owner unbound (its calls return E_STATE until it is bound again), and
+ * calls on two cases that overlap in time on one GPU race on the same
+ * memory.  Everything else is as gsis_case_bind on the current device. */
+gsis_status gsis_case_bind_static(gsis_case c, int64_t kinetic_capacity, void *stream);
+
 /* Set the state (device pointers).  W_dev [n_cells][5] = (rho, ux, uy, uz, T)
  * FP64 on every cell.  flags_dev [n_cells] uint8 (1 = kinetic) or NULL (all
  * kinetic).  vdf_dev: rows [n_kin][nfun][nv] in the case dtype for the
@@ -331,9 +344,13 @@ gsis_status gsis_correct(gsis_case c, const double *W_new_dev, void *stream);
 gsis_status gsis_macro_solve(gsis_case c, double *W_dev, const double *hot_dev, const double *src_dev,
                              int32_t n_inner, double cfl, void *stream);
 
-/* Duration in ms of the last kinetic-sweep kernel launched on this case
- * (HIP events on the launch stream; synchronises).  At spatial order 2 the
- * interval also covers the slope kernels launched just before the sweep. */
+/* Duration in ms of the last kinetic-sweep launch in which this case was
+ * the first (or only) case of the batch (HIP events on the launch stream;
+ * synchronises); for a batch the interval covers the whole batched launch.
+ * E_STATE if the case's last sweep was not timed that way (a later case of a
+ * batch, or a case bound to the static workspace, which has no events).  At
+ * spatial order 2 the interval also covers the slope kernels launched just
+ * before the sweep. */
 gsis_status gsis_last_sweep_ms(gsis_case c, float *ms);
 
 /* Sweep layout chosen at bind (all outputs host, nullable): *fast = 1 when the

@@ -31,7 +31,7 @@ EXPORTS = [
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
     "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
     "gsis_set_spatial_order", "gsis_set_internal_dof", "gsis_internal_moments",
-    "gsis_set_g13_limit", "gsis_limiter_stats",
+    "gsis_set_g13_limit", "gsis_limiter_stats", "gsis_case_bind_static",
 ]
 
 
@@ -113,6 +113,7 @@ def lib():
             "gsis_set_spatial_order": [P, I32, D],
             "gsis_set_internal_dof": [P, D, D, P], "gsis_internal_moments": [P, P, P],
             "gsis_set_g13_limit": [P, D], "gsis_limiter_stats": [P, P, P],
+            "gsis_case_bind_static": [P, I64, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -219,11 +220,13 @@ class Case:
     """One steady problem bound to a torch-allocated device workspace."""
 
     def __init__(self, mesh: Mesh, grid, Kn, omega=0.5, Pr=2.0 / 3.0, dtype=F32, capacity=None,
-                 order=1, damp2=2.0, dr=0.0, Zr=1.0, A=None, g13_rmax=0.5):
+                 order=1, damp2=2.0, dr=0.0, Zr=1.0, A=None, g13_rmax=0.5, static=False):
         """order 2: second-order face values with pseudo-time factor damp2
         (gsis_set_spatial_order); dr > 0: the polyatomic gas with Zr and the
         heat-flux matrix A (gsis_set_internal_dof); g13_rmax: range limit of
-        the Grad-13 rows (gsis_set_g13_limit; None or <= 0: unlimited)."""
+        the Grad-13 rows (gsis_set_g13_limit; None or <= 0: unlimited);
+        static: bind to the library's static device workspace
+        (gsis_case_bind_static) instead of a torch allocation."""
         import torch
         self.mesh = mesh
         self.dtype = dtype
@@ -247,8 +250,12 @@ class Case:
         nbytes = C.c_size_t()
         _check(lib().gsis_case_footprint(h, self.capacity, C.byref(nbytes)))
         self.footprint = nbytes.value
-        self.workspace = torch.empty(self.footprint, dtype=torch.uint8, device="cuda")
-        _check(lib().gsis_case_bind(h, _ptr(self.workspace), self.footprint, self.capacity, _stream()))
+        if static:
+            self.workspace = None
+            _check(lib().gsis_case_bind_static(h, self.capacity, _stream()))
+        else:
+            self.workspace = torch.empty(self.footprint, dtype=torch.uint8, device="cuda")
+            _check(lib().gsis_case_bind(h, _ptr(self.workspace), self.footprint, self.capacity, _stream()))
 
     @property
     def torch_dtype(self):

@@ -74,6 +74,8 @@ struct gsis_case_s {
     int32_t vdim = 0, n[3] = {0, 0, 0}, nv = 0;
     double xv[3][MAXA], wv[3][MAXA];
     std::vector<double> vpt;    // point-set grid: [nv][4] = xi (3), w
+    std::vector<double> vt;     // node table the kernels read (see node_table), kept with the grid
+    std::vector<float> vtf;     // the same rounded to FP32
     bool points = false;
     int32_t order = 1;          // spatial order of the kinetic face values
     double damp2 = 2.0;         // pseudo-time factor of the order-2 iteration
@@ -92,6 +94,7 @@ struct gsis_case_s {
 
 namespace {
 void drop_graphs_of(gsis_case c);   // captured synthetic solves that use the case
+void refresh_node_table(gsis_case c);   // node tables of the kernels, rebuilt when grid or order change
 }  // namespace
 
 extern "C" const char *gsis_last_error(void) { return g_err.c_str(); }
@@ -366,6 +369,7 @@ extern "C" gsis_status gsis_create_case(gsis_mesh mesh, const gsis_gas *gas, int
 extern "C" gsis_status gsis_destroy_case(gsis_case c)
 {
     if (!c) return fail(GSIS_E_ARG, "null case");
+    static_release(c);
     drop_graphs_of(c);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -402,8 +406,10 @@ extern "C" gsis_status gsis_set_velocity_grid(gsis_case c, int32_t vdim, const i
     }
     c->nv = (int32_t)nv;
     c->points = false;
+    c->vt.clear();
     c->vpt.clear();
     c->grid_set = true;
+    refresh_node_table(c);
     return GSIS_OK;
 }
 
@@ -428,6 +434,7 @@ extern "C" gsis_status gsis_set_velocity_points(gsis_case c, int32_t np, const d
     c->nv = np;
     c->points = true;
     c->grid_set = true;
+    refresh_node_table(c);
     return GSIS_OK;
 }
 
@@ -474,6 +481,7 @@ extern "C" gsis_status gsis_set_spatial_order(gsis_case c, int32_t order, double
     if (!(damp >= 0.0) || !std::isfinite(damp)) return fail(GSIS_E_ARG, "damp must be finite and >= 0");
     c->order = order;
     c->damp2 = damp;
+    if (c->grid_set) refresh_node_table(c);
     return GSIS_OK;
 }
 
@@ -545,6 +553,14 @@ size_t node_table_len(const gsis_case_s *c)
     if (c->points) return c->vpt.size();
     if (c->order == 2 && c->vdim == 3) return 4 * (size_t)c->nv;
     return 0;
+}
+
+std::vector<double> node_table(const gsis_case_s *c);
+
+void refresh_node_table(gsis_case c)
+{
+    c->vt = node_table(c);
+    c->vtf.assign(c->vt.begin(), c->vt.end());
 }
 
 std::vector<double> node_table(const gsis_case_s *c)
@@ -726,7 +742,10 @@ extern "C" gsis_status gsis_case_footprint(gsis_case c, int64_t cap, size_t *byt
     return GSIS_OK;
 }
 
-extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64_t cap, void *stream)
+namespace gsis {
+// Lay the case out in the device buffer ws of `bytes` (256-byte aligned) and
+// copy the mesh and grid; with_events creates the sweep timing events.
+gsis_status bind_impl(gsis_case c, void *ws, size_t bytes, int64_t cap, void *stream, bool with_events)
 {
     if (!c || !ws) return fail(GSIS_E_ARG, "null argument");
     if (!c->grid_set) return fail(GSIS_E_STATE, "velocity grid not set");
@@ -889,13 +908,8 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     HIPCHK(put(L.wallf, m->wall_faces.data(), 4 * m->wall_faces.size()));
     HIPCHK(put(L.xv, c->xv, sizeof c->xv));
     HIPCHK(put(L.wv, c->wv, sizeof c->wv));
-    {
-        const std::vector<double> vt = node_table(c);
-        std::vector<float> vf(vt.begin(), vt.end());
-        HIPCHK(put(L.vpt, vt.data(), 8 * vt.size()));
-        HIPCHK(put(L.vptf, vf.data(), 4 * vf.size()));
-        HIPCHK(hipStreamSynchronize(s));   // vt, vf are host temporaries of the async copies
-    }
+    HIPCHK(put(L.vpt, c->vt.data(), 8 * c->vt.size()));
+    HIPCHK(put(L.vptf, c->vtf.data(), 4 * c->vtf.size()));
     HIPCHK(hipMemsetAsync(B + L.slot, 0xff, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.flags, 0, 4 * nc, s));
     HIPCHK(hipMemsetAsync(B + L.status, 0, 16, s));
@@ -915,7 +929,7 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
         HIPCHK(hipMemsetAsync(B + L.wsl, 0, L.cf_back - L.wsl, s));
         HIPCHK(launch_amax(c->cv, h, s));
     }
-    if (!c->ev0) {
+    if (with_events && !c->ev0) {
         HIPCHK(hipEventCreate(&c->ev0));
         HIPCHK(hipEventCreate(&c->ev1));
     }
@@ -924,7 +938,27 @@ extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64
     c->state_set = false;
     c->n_kin = 0;
     c->cur = 0;
+    c->timed = false;
     return GSIS_OK;
+}
+
+// the case no longer holds a workspace (another case took the static one)
+void unbind_case(gsis_case c)
+{
+    drop_graphs_of(c);
+    c->bound = false;
+    c->state_set = false;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+}
+
+gsis_status set_error(gsis_status code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace gsis
+
+extern "C" gsis_status gsis_case_bind(gsis_case c, void *ws, size_t bytes, int64_t cap, void *stream)
+{
+    if (c) static_release(c);
+    return bind_impl(c, ws, bytes, cap, stream, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -1014,7 +1048,7 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         b.order = cases[i0]->hv.order;
         b.group = cases[i0]->hv.group;
         b.rot = cases[i0]->hv.rot;
-        if (timed && i0 == 0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
+        if (timed && i0 == 0 && cases[0]->ev0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
         // order 2: limited slopes of every case's f^n (the sweep reads its own
         // and its neighbours')
         for (int j = 0; j < m; ++j) {
@@ -1022,12 +1056,14 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
             if (c->order == 2) HIPCHK(launch_slope(c->cv, c->hv, c->n_kin, c->cur, s));
         }
         HIPCHK(launch_sweep(b, cases[i0]->hv, b.start[m], s));
-        if (timed && i0 + MAX_BATCH >= n) HIPCHK(hipEventRecord(cases[0]->ev1, s));
+        if (timed && i0 + MAX_BATCH >= n && cases[0]->ev1) HIPCHK(hipEventRecord(cases[0]->ev1, s));
     }
+    // the events time the whole batched launch; they belong to the first case
     for (int j = 0; j < n; ++j) {
         cases[j]->cur ^= 1;
-        cases[j]->timed = timed;
+        cases[j]->timed = false;
     }
+    cases[0]->timed = timed && cases[0]->ev0;
     return GSIS_OK;
 }
 

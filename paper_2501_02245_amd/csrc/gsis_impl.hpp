@@ -255,6 +255,13 @@ __device__ __forceinline__ void vnode(const CaseView &C, int k, double *xi, doub
     w = C.wv[ix] * C.wv[MAXA + iy] * ((C.vdim == 3) ? C.wv[2 * MAXA + iz] : 1.0);
 }
 
+// --- binding (gsis_api.cpp, gsis_static.hip) ----------------------------------
+gsis_status bind_impl(gsis_case c, void *ws, size_t bytes, int64_t cap, void *stream, bool with_events);
+void unbind_case(gsis_case c);
+gsis_status set_error(gsis_status code, const char *msg);
+// forget c as the holder of a device's static workspace (destroy, re-bind)
+void static_release(gsis_case c);
+
 // --- launch wrappers (gsis_kinetic.hip) ---------------------------------------
 hipError_t launch_wall_den(const CaseView *cv, const CaseView &h, hipStream_t s);
 // mode 0: conservation-fixed Maxwellian of W on the kinetic cells; mode 1:
