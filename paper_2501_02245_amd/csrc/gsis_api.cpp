@@ -1048,6 +1048,18 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         b.order = cases[i0]->hv.order;
         b.group = cases[i0]->hv.group;
         b.rot = cases[i0]->hv.rot;
+        // 16-byte rows when every case's (y, z) plane fits (GSIS_SWEEP_V4=0 keeps 4-byte rows)
+        {
+            const bool v4_on = [] {
+                const char *e = std::getenv("GSIS_SWEEP_V4");
+                return !(e && e[0] == '0');
+            }();
+            b.v4 = v4_on;
+            for (int j = 0; j < m; ++j) {
+                const CaseView &hj = cases[i0 + j]->hv;
+                if (!(hj.fast && hj.vdim == 3 && !hj.poly && sweep_v4_fits(hj.n[1], hj.n[2]))) b.v4 = 0;
+            }
+        }
         if (timed && i0 == 0 && cases[0]->ev0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
         // order 2: limited slopes of every case's f^n (the sweep reads its own
         // and its neighbours')

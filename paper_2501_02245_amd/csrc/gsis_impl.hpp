@@ -208,6 +208,7 @@ struct Batch {
                                     // 2: groups of `group` consecutive cells, tile-major inside each group
     int32_t group;
     int32_t rot;                    // plane kernel: start plane advances every `rot` blocks per XCD (0: plane 0)
+    int32_t v4;                     // 3D plane layout read as 16-byte rows (every case fits sweep_v4_fits)
 };
 
 // Cases of one batched macroscopic launch: each case owns whole blocks
@@ -273,6 +274,7 @@ hipError_t launch_feqpar(const CaseView *cv, const CaseView &h, int n_kin, hipSt
 hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
 // (gsis_sweep.hip) tensor grids whose fastest axis divides the block
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
+bool sweep_v4_fits(int ny, int nz);
 hipError_t launch_axtab(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 // spatial order 2: largest outflow rate per cell (at bind), limited slopes of f[cur]
 hipError_t launch_amax(const CaseView *cv, const CaseView &h, hipStream_t s);

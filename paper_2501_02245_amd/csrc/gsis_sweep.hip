@@ -520,6 +520,464 @@ k_sweep_fast(Batch B)
 }
 
 // ---------------------------------------------------------------------------
+// The same sweep on 3D tensor grids whose (y, z) plane splits into 64..256
+// lanes of four consecutive z nodes (n_z % 4 == 0, 64 <= n_y n_z / 4 <= 256,
+// and n_y n_z / 4 divides 256): the row layout of the plane kernel above, read
+// and written as 16-byte vectors (four nodes per lane), with the lane's four
+// (y, z) nodes fixed for the whole row and the x-planes looped over.
+//
+// Per lane, everything that depends on (y, z) only is formed once in FP64:
+// the Gaussian factor exp(-(c_y^2 + c_z^2)/T)/tau, the (y, z) parts of the
+// fix-up and Shakhov polynomials, and each face's (n_y c_y + n_z c_z + u.n) S/V.
+// Per x-plane, the block reads one record from LDS (c_x, its Gaussian, fix-up
+// and Shakhov parts, c_x^2/T and the weighted powers w_x c_x^a); the moment
+// and balance sums of a node are then four FMAs each.  A face whose
+// (xi.n) S/V is >= 0 on every node of a wave's patch of the plane brings
+// nothing in: the wave skips its row load and arithmetic (exactly: its
+// min(a, 0) is 0 on every node).  Lanes keep FP32 sums over the planes per
+// node; the epilogue forms each lane's partial sums in FP64 with its (y, z)
+// offsets and weights and reduces them over the block in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec4T;
+template <>
+struct Vec4T<float> {
+    typedef float v __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec4T<double> {
+    typedef double v __attribute__((ext_vector_type(4)));
+};
+
+// per-x-plane record of the v4 sweep (LDS): c, E, P, K, c^2/T, w, w c, w c^2, w c^3
+constexpr int XREC = 12;
+
+// one DPP lane move of an FP64 value (both halves; ctrl selects the pattern)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over each 16-lane row, left in every lane of the row: pairs (quad_perm
+// 1,0,3,2), quads (2,3,0,1), half rows (row_half_mirror), rows (row_mirror).
+// Partners add the same two values, so every lane of a group holds the same
+// bits at each level and the order of the additions is fixed.
+__device__ __forceinline__ double row_sum16(double x)
+{
+    x += dpp_f64<0xB1>(x);
+    x += dpp_f64<0x4E>(x);
+    x += dpp_f64<0x141>(x);
+    x += dpp_f64<0x140>(x);
+    return x;
+}
+
+__device__ __forceinline__ float wave_min(float x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ __forceinline__ double wave_min(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+    return x;
+}
+
+// a value equal in every lane, moved to scalar registers
+__device__ __forceinline__ float to_uniform(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double to_uniform(double x)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// waves per SIMD of the FP32 16-byte-row sweep (up to 4 faces per cell: 150
+// VGPRs without spills at 3; 8 faces take 2)
+#ifndef SWEEP_V4_WAVES
+#define SWEEP_V4_WAVES 3
+#endif
+#ifndef SWEEP_V4_U
+#define SWEEP_V4_U 2
+#endif
+template <typename T, int NF, int U>
+__global__ __launch_bounds__(BLOCK) __attribute__((
+    amdgpu_waves_per_eu(sizeof(T) == 4 ? (NF <= 4 ? SWEEP_V4_WAVES : 2) : 1))) void k_sweep_v4(Batch B)
+{
+    typedef typename Vec4T<T>::v V4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // ---- locate the work item (as the plane kernel) -------------------------
+    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    int ci = 0;
+    while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
+    const CaseView &C = *B.cv[ci];
+    const int cur = B.cur[ci];
+    const int item = b - B.start[ci];
+    const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
+    int vt, t;
+    if (B.order == 2) {
+        const int G = B.group;
+        const int gi = item / (G * C.ntile);
+        const int r = item - gi * G * C.ntile;
+        const int gc = min(G, n_kin - gi * G);
+        vt = r / gc;
+        t = gi * G + (r - vt * gc);
+    } else if (B.order) {
+        t = item / C.ntile;
+        vt = item - t * C.ntile;
+    } else {
+        vt = item / n_kin;
+        t = item - vt * n_kin;
+    }
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
+    const size_t row = (size_t)C.row;
+    gcptr<T> fold = (gcptr<T>)C.f[cur];
+    gptr<T> fn = (gptr<T>)C.f[cur ^ 1] + (size_t)slot * row;
+    gcptr<T> fo = fold + (size_t)slot * row;
+
+    // lane -> (x group, y, first of four z nodes)
+    const int Q = nz >> 2, PL = ny * Q, G = BLOCK / PL;
+    const int xg = threadIdx.x / PL, pr = threadIdx.x - xg * PL;
+    const int iy = pr / Q, iz0 = 4 * (pr - iy * Q);
+
+    // ---- LDS: per-plane records, from the slot's axis tables ----------------
+    // (offset c, Gaussian factor, fix-up and Shakhov parts, each formed in FP64
+    // and rounded once per sweep) and the weighted powers of c
+    const int NA = nx + ny + nz;
+    gcptr<T> tb = (gcptr<T>)C.axtab + (size_t)slot * C.tabp;
+    T *xr = (T *)smem_raw;
+    double *red = (double *)(smem_raw + red_offset<T>((size_t)XREC * nx));
+    {
+        const double ux = P.u[0], it = P.it;
+        for (int j = threadIdx.x; j < nx; j += BLOCK) {
+            const double c = C.xv[j] - ux, w = C.wv[j];
+            T *r = xr + XREC * j;
+            r[0] = tb[j];
+            r[1] = tb[NA + j];
+            r[2] = tb[2 * NA + j];
+            r[3] = tb[3 * NA + j];
+            r[4] = (T)(c * c * it);
+            r[5] = (T)w;
+            r[6] = (T)(w * c);
+            r[7] = (T)(w * c * c);
+            r[8] = (T)(w * c * c * c);
+        }
+    }
+
+    // ---- faces: row bases (wave-uniform), scales, normals ------------------
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    int fwall[NF];
+    T fnx[NF], fsc[NF];
+    double fny[NF], fnz[NF], fun[NF];
+    gcptr<T> fnb[NF];
+    int nw = 0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fwall[l] = -1;
+        fnx[l] = (T)0;
+        fny[l] = fnz[l] = fun[l] = 0.0;
+        fsc[l] = (T)0;
+        fnb[l] = fo;
+        if (l < nf) {
+            const int e = e0 + l;
+            const int oth = C.cf_other[e];
+            const double n0 = C.cf_nsv[3 * e], n1 = C.cf_nsv[3 * e + 1], n2 = C.cf_nsv[3 * e + 2];
+            fnx[l] = (T)n0;
+            fny[l] = n1;
+            fnz[l] = n2;
+            fun[l] = P.u[0] * n0 + P.u[1] * n1 + P.u[2] * n2;   // xi.n S/V = c.n S/V + u.n S/V
+            fwall[l] = C.cf_wall[e];
+            nw += (fwall[l] >= 0);
+            fsc[l] = (T)1;
+            if (oth >= 0) {
+                const int so = C.slot_of_cell[oth];
+                fnb[l] = (so >= 0) ? fold + (size_t)so * row : (gcptr<T>)C.grow + (size_t)C.ghost_slot[oth] * row;
+            } else {
+                const int pi = -1 - oth;
+                fnb[l] = (gcptr<T>)C.prow + (size_t)pi * row;
+                if (fwall[l] >= 0) fsc[l] = (T)P.rw[fwall[l]];
+            }
+        }
+    }
+
+    // ---- lane constants (FP64, rounded once) --------------------------------
+    const double it = P.it;
+    const double cyd = C.xv[MAXA + iy] - P.u[1];
+    const T Ey = tb[NA + nx + iy], Py = tb[2 * NA + nx + iy], Ky = tb[3 * NA + nx + iy];
+    T Eyz[4], Pyz[4], Kyz[4], Ayz[4], wz[4], cz[4], BL[NF];
+    T amin[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) BL[l] = (T)(fny[l] * cyd + fun[l]);
+#pragma unroll
+    for (int l = 0; l < NF; ++l) amin[l] = (T)0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double czd = C.xv[2 * MAXA + iz0 + j] - P.u[2];
+        const double r2 = cyd * cyd + czd * czd;
+        const int jz = nx + ny + iz0 + j;
+        Eyz[j] = ((T)P.itau * Ey) * tb[NA + jz];
+        Pyz[j] = Py + tb[2 * NA + jz];
+        Kyz[j] = Ky + tb[3 * NA + jz];
+        Ayz[j] = (T)(r2 * it - 2.5);
+        wz[j] = (T)C.wv[2 * MAXA + iz0 + j];
+        cz[j] = (T)czd;
+    }
+    // a = (xi.n) S/V = n_x c_x + (n_y c_y + u.n) + n_z c_z: the middle term per
+    // lane, n_z and n_x per face (uniform)
+    T fnzT[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fnzT[l] = (T)fnz[l];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const T a = fma(fnzT[l], cz[j], BL[l]);
+            amin[l] = (j == 0) ? a : fmin(amin[l], a);
+        }
+    }
+    // smallest (y, z) part of each face's a over the wave: with n_x c_x of the
+    // plane it bounds a from below on the wave's whole patch
+#pragma unroll
+    for (int l = 0; l < NF; ++l) amin[l] = to_uniform(wave_min(amin[l]));
+    __syncthreads();
+
+    const T idt = (T)C.inv_dt;
+    const T den0 = (T)P.itau + idt;   // 1/dt + 1/tau (the diagonal, with - sum_{a<0} a, as the closed cell allows)
+    T S0[4], S1[4], S2[4], S3[4], R0[4], R1[4], R2[4];
+    T Wf[NF];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S0[j] = S1[j] = S2[j] = S3[j] = R0[j] = R1[j] = R2[j] = (T)0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) Wf[l] = (T)0;
+
+    const int ix0 = vt * C.xp, ix1 = min(ix0 + C.xp, nx);
+    const uint32_t plane_bytes = (uint32_t)(ny * nz * sizeof(T));
+    const uint32_t lane_bytes = (uint32_t)(4 * pr * sizeof(T));
+    gcptr<V4> fo_u = (gcptr<V4>)uniform_ptr(fo);
+    gptr<V4> fn_u = (gptr<V4>)uniform_ptr(fn);
+    gcptr<V4> fnb_u[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) fnb_u[l] = (gcptr<V4>)uniform_ptr(fnb[l]);
+
+    // U x-planes per load round in the common case; cells with a wall face
+    // (a few percent) carry the wall sums and take one plane per round
+    auto planes = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+        constexpr int UU = WALLS ? 1 : U;
+        for (int ixr = ix0 + xg; ixr < ix1; ixr += UU * G) {
+            // ---- loads of the round: own rows, and the faces that bring values in
+            // A face that brings nothing in on the wave's patch reads the own row
+            // instead (the same cache lines as the own load: no extra traffic) and
+            // its min(a, 0) is 0 on every node, so the code stays branch-free.
+            V4 o[UU], v[UU][NF];
+            bool live[UU];
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int ix = ixr + u * G;
+                live[u] = ix < ix1;
+                const int ixc = min(ix, ix1 - 1);
+                const uint32_t off = (uint32_t)ixc * plane_bytes + lane_bytes;
+                const T cx = xr[XREC * ixc];
+                o[u] = ldb(fo_u, off);
+#pragma unroll
+                for (int l = 0; l < NF; ++l) {
+                    // some node may bring a value in: the lower bound of a on the wave's
+                    // patch, with a margin that covers the rounding of a itself
+                    const T ax = fnx[l] * cx;
+                    const int nd = (ax + amin[l] < (T)1e-5 * (fabs(ax) + fabs(amin[l])));
+                    const bool need = __builtin_amdgcn_readfirstlane(nd);
+                    v[u][l] = ldb(need ? fnb_u[l] : fo_u, off);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                if (!live[u]) break;
+                const int ix = ixr + u * G;
+                const T *rx = xr + XREC * ix;
+                const T cx = rx[0], Ex = rx[1], Px = rx[2], Kx = rx[3], cx2 = rx[4];
+                const T wx = rx[5], wx1 = rx[6], wx2 = rx[7], wx3 = rx[8];
+                T AX[NF];
+#pragma unroll
+                for (int l = 0; l < NF; ++l) AX[l] = fnx[l] * cx + BL[l];
+                V4 outv;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T oj = o[u][j];
+                    // relaxation target (1/tau folded into Eyz)
+                    const T g = Ex * Eyz[j] * (Px + Pyz[j]) * ((Kx + Kyz[j]) * (cx2 + Ayz[j]) + (T)1);
+                    T num = g + idt * oj;
+                    T den = den0;
+                    T aw[NF];
+#pragma unroll
+                    for (int l = 0; l < NF; ++l) {
+                        const T a = fma(fnzT[l], cz[j], AX[l]);
+                        const T mn = fmin(a, (T)0);
+                        den -= mn;
+                        if constexpr (WALLS) {
+                            aw[l] = a - mn;     // max(a, 0)
+                            num -= (mn * fsc[l]) * v[u][l][j];
+                        } else {
+                            num -= mn * v[u][l][j];
+                        }
+                    }
+                    const T f = num * fast_rcp(den);
+                    outv[j] = f;
+                    S0[j] = fma(wx, f, S0[j]);
+                    S1[j] = fma(wx1, f, S1[j]);
+                    S2[j] = fma(wx2, f, S2[j]);
+                    S3[j] = fma(wx3, f, S3[j]);
+                    const T tr = num - den * oj;
+                    R0[j] = fma(wx, tr, R0[j]);
+                    R1[j] = fma(wx1, tr, R1[j]);
+                    R2[j] = fma(wx2, tr, R2[j]);
+                    if constexpr (WALLS) {
+                        // outgoing wall flux sums, weight w_x w_z here and w_y at the end
+                        const T hw = (wx * wz[j]) * f;
+#pragma unroll
+                        for (int l = 0; l < NF; ++l)
+                            if (fwall[l] >= 0) Wf[l] = fma(hw, aw[l], Wf[l]);
+                    }
+                }
+                stb(fn_u, (uint32_t)ix * plane_bytes + lane_bytes, outv);
+            }
+        }
+    };
+    auto epilogue = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+        // the sums leave the loop as they are: without this the compiler
+        // materialises the zero-trip values of their FP64 conversions before
+        // the loop and keeps them live across it (64 registers)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            asm volatile("" : "+v"(S0[j]), "+v"(S1[j]), "+v"(S2[j]), "+v"(S3[j]));
+            asm volatile("" : "+v"(R0[j]), "+v"(R1[j]), "+v"(R2[j]));
+        }
+        if (WALLS) {
+#pragma unroll
+            for (int l = 0; l < NF; ++l) asm volatile("" : "+v"(Wf[l]));
+        }
+        // ---- epilogue: the lane's FP64 partial sums, one at a time, each
+        // reduced over the wave in a fixed order; then the waves in order
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const double wyd = C.wv[MAXA + iy];
+        double wj[4], czj[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            czj[j] = C.xv[2 * MAXA + iz0 + j] - P.u[2];
+            wj[j] = wyd * C.wv[2 * MAXA + iz0 + j];
+        }
+        // row sums (DPP) of 16 lanes, written by the first lane of each row;
+        // the 16 rows of the block are added in order below
+        auto put = [&](int i, double x) {
+            x = row_sum16(x);
+            if ((lane & 15) == 0) red[(wave * 4 + (lane >> 4)) * NSUM + i] = x;
+        };
+        double a, b2, c2, d;
+        // mass, and the y moments that are lane constants times it
+        a = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a += wj[j] * (double)S0[j];
+        put(0, a);
+        put(2, cyd * a);
+        put(5, cyd * cyd * a);
+        // x moments
+        b2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b2 += wj[j] * (double)S1[j];
+        put(1, b2);
+        put(7, cyd * b2);
+        c2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c2 += wj[j] * (double)S2[j];
+        put(4, c2);
+        // z moments
+        a = 0.0;
+        d = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a += wj[j] * czj[j] * (double)S0[j];
+            d += wj[j] * czj[j] * czj[j] * (double)S0[j];
+        }
+        put(3, a);
+        put(9, cyd * a);
+        put(6, d);
+        a = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a += wj[j] * czj[j] * (double)S1[j];
+        put(8, a);
+        // heat-flux sums c^2 c_d
+        a = 0.0;
+        d = 0.0;
+        b2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double yz2 = cyd * cyd + czj[j] * czj[j];
+            const double e2 = wj[j] * ((double)S2[j] + yz2 * (double)S0[j]);
+            a += wj[j] * ((double)S3[j] + yz2 * (double)S1[j]);
+            d += e2;
+            b2 += czj[j] * e2;
+        }
+        put(10, a);
+        put(11, cyd * d);
+        put(12, b2);
+        // moment balance
+        a = 0.0;
+        d = 0.0;
+        b2 = 0.0;
+        c2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double yz2 = cyd * cyd + czj[j] * czj[j];
+            a += wj[j] * (double)R0[j];
+            d += wj[j] * (double)R1[j];
+            b2 += wj[j] * czj[j] * (double)R0[j];
+            c2 += wj[j] * ((double)R2[j] + yz2 * (double)R0[j]);
+        }
+        put(S_RES, a);
+        put(S_RES + 1, d);
+        put(S_RES + 2, cyd * a);
+        put(S_RES + 3, b2);
+        put(S_RES + 4, c2);
+        // outgoing wall fluxes (weights w_x w_z in the sums, w_y here)
+#pragma unroll
+        for (int q2 = 0; q2 < MAXW; ++q2) {
+            double sw = 0.0;
+            if (WALLS) {
+#pragma unroll
+                for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? (double)Wf[l] : 0.0;
+            }
+            put(S_WALL + q2, wyd * sw);
+        }
+        for (int i = S_WALL + MAXW; i < NSUM; ++i) put(i, 0.0);
+        __syncthreads();
+        if (threadIdx.x < NSUM) {
+            double acc = 0.0;
+            for (int r = 0; r < BLOCK / 16; ++r) acc += red[r * NSUM + threadIdx.x];
+            C.partial[((size_t)slot * C.ntile + vt) * NSUM + threadIdx.x] = acc;
+        }
+    };
+    if (nw > 0) {
+        planes(std::true_type{});
+        epilogue(std::true_type{});
+    } else {
+        planes(std::false_type{});
+        epilogue(std::false_type{});
+    }
+}
+
+// ---------------------------------------------------------------------------
 // GSIS correction (Sec. 3.1): f += f_eq(W^{n+1}) - f_eq(W^{n+1/2}) on the plane
 // layout, with the same fused moment and wall sums as the sweep.  Both f_eq
 // are conservation-fixed Maxwellians, separable per axis: E = E_x E_y E_z and
@@ -826,8 +1284,30 @@ void launch_nf(const Batch &b, const CaseView &h0, size_t lds, int total, hipStr
     else launch_u<T, VD, 1>(b, lds, total, s);
 }
 
+// the 16-byte-row sweep covers 3D grids with n_z % 4 == 0 and a (y, z) plane
+// of 64..256 four-node lanes that divides the block
+bool sweep_v4_fits(int ny, int nz)
+{
+    if (nz % 4) return false;
+    const int P = ny * nz / 4;
+    return P >= 64 && P <= BLOCK && BLOCK % P == 0;
+}
+
+template <typename T>
+void launch_v4(const Batch &b, const CaseView &h0, int total, hipStream_t s)
+{
+    const size_t lds = red_offset<T>((size_t)XREC * h0.n[0]) + sizeof(double) * (BLOCK / 16) * NSUM;
+    if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_v4<T, 4, SWEEP_V4_U>), dim3(total), dim3(BLOCK), lds, s, b);
+    else hipLaunchKernelGGL((k_sweep_v4<T, MAXF, 1>), dim3(total), dim3(BLOCK), lds, s, b);
+}
+
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total, hipStream_t s)
 {
+    if (b.v4) {
+        if (h0.dtype == GSIS_F32) launch_v4<float>(b, h0, total, s);
+        else launch_v4<double>(b, h0, total, s);
+        return hipGetLastError();
+    }
     if (h0.dtype == GSIS_F32) {
         const size_t lds = sweep_fast_tab(h0);
         if (h0.vdim == 3) launch_nf<float, 3>(b, h0, lds, total, s);
