@@ -82,6 +82,13 @@ def lib():
         for name in ("oc_kinetic_slopes", "oc_sweep2", "oc_kinetic_residual2", "oc_poly_target", "oc_sweep_poly"):
             getattr(_lib, name).restype = C.c_int32
         _lib.oc_moments_poly.argtypes = [P, C.c_double, P, P]
+        _lib.oc_g13_poly.argtypes = [P, C.c_double, P, P]
+        _lib.oc_nsf_poly.argtypes = [P, C.c_double, P, P, P, P, P, P]
+        for name in ("oc_kinetic_residual_poly", "oc_macro_residual_poly", "oc_macro_poly"):
+            getattr(_lib, name).restype = C.c_int32
+        _lib.oc_kinetic_residual_poly.argtypes = [P, P, P, C.c_int32, P, P, P, P, P]
+        _lib.oc_macro_residual_poly.argtypes = [P, P, P, P, P]
+        _lib.oc_macro_poly.argtypes = [P, P, P, P, C.c_int32, C.c_double, P]
         _lib.oc_poly_target.argtypes = [P, P, P, P]
         _lib.oc_sweep_poly.argtypes = [P, P, P, C.c_int32, P, P, P, P, P]
         _lib.oc_kinetic_slopes.argtypes = [P, P, C.c_int32, P, P, P, P]
@@ -240,20 +247,27 @@ class Oracle:
         return out
 
     def feq(self, W5):
-        """Conservation-fixed Maxwellian of W (Sec. 3.2); polyatomic: f1 =
-        (d_r T / 4) f0, the internal modes in equilibrium at T."""
+        """Conservation-fixed Maxwellian of W (Sec. 3.2) at (rho, u, T).
+        Polyatomic, W = (rho, u, T_t, T_r): f0 at T_t, and f1 = (d_r T_r / 4) f0
+        (f_eq,1 = (d_r/2) R T_r f_eq); a five-component W uses T_r = T_t."""
         out = np.empty(self.row_shape())
         w = _f64(W5)
-        if lib().oc_feq(C.byref(self.cg), _p(w), _p(out)) != 0:
+        if lib().oc_feq(C.byref(self.cg), _p(np.ascontiguousarray(w[:5])), _p(out)) != 0:
             raise FloatingPointError("fix-up system singular")
         if self.poly:
-            out[1] = 0.25 * self.dr * w[4] * out[0]
+            Tr = w[5] if len(w) > 5 else w[4]
+            out[1] = 0.25 * self.dr * Tr * out[0]
         return out
 
     def g13(self, mom):
+        """Grad-13 rows (Sec. 3.2 eq. G13_VDF) of parameters mom; polyatomic:
+        the 18 parameters of ghost_params (T_r and q_r last)."""
         out = np.empty(self.row_shape())
         m = _f64(mom)
-        lib().oc_g13(C.byref(self.cg), _p(m), _p(out))
+        if self.poly:
+            lib().oc_g13_poly(C.byref(self.cg), float(self.dr), _p(m), _p(out))
+        else:
+            lib().oc_g13(C.byref(self.cg), _p(m), _p(out))
         return out
 
     def tau(self, rho, T):
@@ -270,7 +284,7 @@ class Oracle:
         kc = np.ascontiguousarray(kin_cell, dtype=np.int32)
         sc = np.ascontiguousarray(slot_of_cell, dtype=np.int32)
         if ghost is None:
-            ghost = np.zeros((self.mesh["n_cells"], NMOM))
+            ghost = np.zeros((self.mesh["n_cells"], NMOM + 4 if self.poly else NMOM))
         gh = _f64(ghost)
         if self.poly:
             r = lib().oc_sweep_poly(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc), _p(kc),
@@ -315,21 +329,39 @@ class Oracle:
         return s, q
 
     def primitive_gradients(self, W):
-        """LSQ gradients of (ux, uy, uz, T, rho, |u|) with patch values at faces."""
-        phi = np.concatenate([W[:, 1:5], W[:, :1], np.linalg.norm(W[:, 1:4], axis=1)[:, None]], 1)
-        bnd = np.full((len(self.mesh["patches"]), 6), np.nan)
+        """LSQ gradients of (ux, uy, uz, T, rho, |u|) with patch values at faces;
+        polyatomic W (6 columns): a seventh row, the gradient of T_r (patch
+        value T)."""
+        cols = [W[:, 1:5], W[:, :1], np.linalg.norm(W[:, 1:4], axis=1)[:, None]]
+        poly = W.shape[1] > 5
+        if poly:
+            cols.append(W[:, 5:6])
+        phi = np.concatenate(cols, 1)
+        bnd = np.full((len(self.mesh["patches"]), phi.shape[1]), np.nan)
         for p, pt in enumerate(self.mesh["patches"]):
             bnd[p, 0:3] = pt["u"]
             bnd[p, 3] = pt["T"]
             bnd[p, 5] = np.linalg.norm(pt["u"])
+            if poly:
+                bnd[p, 6] = pt["T"]
             if pt["kind"] == "far":
                 bnd[p, 4] = pt["rho"]
         return self.lsq(phi, bnd)
 
     def nsf_field(self, W, grad=None):
-        """sigma_NSF, q_NSF on every cell from LSQ gradients of W (Sec. 2 NSF_constitutive)."""
+        """sigma_NSF, q_NSF on every cell from LSQ gradients of W (Sec. 2
+        NSF_constitutive); polyatomic W: [n, 12] = sigma, q_t, q_r (eq. mu_kappa)."""
         if grad is None:
             grad = self.primitive_gradients(W)
+        if W.shape[1] > 5:
+            out = np.zeros((len(W), 12))
+            for i in range(len(W)):
+                s, qt, qr = np.zeros(6), np.zeros(3), np.zeros(3)
+                gu = _f64(grad[i, 0:3, :]).reshape(9)
+                lib().oc_nsf_poly(C.byref(self.gas), float(W[i, 4]), _p(gu), _p(_f64(grad[i, 3, :])),
+                                  _p(_f64(grad[i, 6, :])), _p(s), _p(qt), _p(qr))
+                out[i, :6], out[i, 6:9], out[i, 9:] = s, qt, qr
+            return out
         out = np.zeros((len(W), 9))
         for i in range(len(W)):
             s, q = self.nsf(W[i, 4], grad[i, 0:3, :], grad[i, 3, :])
@@ -348,19 +380,30 @@ class Oracle:
         from a strongly sheared NS field is negative over much of velocity
         space).  The cells whose pair was scaled are left in
         ``last_g13_limited`` (bool per cell)."""
+        if self.poly and W.shape[1] == 5:
+            W = np.concatenate([W, W[:, 4:5]], 1)   # internal modes at T_t
         nsf = self.nsf_field(W, grad)
         p = W[:, 0] * W[:, 4]
         r = np.maximum(np.abs(nsf[:, :6]).max(axis=1) / p, np.linalg.norm(nsf[:, 6:9], axis=1) / (p * np.sqrt(W[:, 4])))
+        if W.shape[1] > 5:
+            # two-VDF gas: the q_r term of f1 (q_r.c/(rho T_t) M at thermal
+            # speed sqrt(T_t)) relative to its equilibrium part (d_r T_r/4) M
+            r = np.maximum(r, 4.0 * np.linalg.norm(nsf[:, 9:12], axis=1) /
+                           (self.dr * W[:, 0] * W[:, 5] * np.sqrt(W[:, 4])))
         rmax = self.g13_rmax
         if rmax is None:
             theta = np.ones(len(W))
         else:
             theta = np.where(r > rmax, rmax / np.where(r > 0, r, 1.0), 1.0)
         self.last_g13_limited = theta < 1.0
-        gh = np.zeros((len(W), NMOM))
-        gh[:, 0:5] = W
+        poly = W.shape[1] > 5
+        gh = np.zeros((len(W), NMOM + 4 if poly else NMOM))
+        gh[:, 0:5] = W[:, :5]
         gh[:, 5:11] = nsf[:, :6] * theta[:, None]
-        gh[:, 11:14] = nsf[:, 6:] * theta[:, None]
+        gh[:, 11:14] = nsf[:, 6:9] * theta[:, None]
+        if poly:
+            gh[:, 14] = W[:, 5]
+            gh[:, 15:18] = nsf[:, 9:12] * theta[:, None]
         if self.vdim == 2:
             gh[:, 3] = 0.0
             gh[:, 9:11] = 0.0
@@ -409,21 +452,26 @@ class Oracle:
         return (k | self.wall_layers(force_wall_layers)).astype(np.uint8)
 
     def macro(self, W, hot, n_inner, cfl=0.5, src=None):
-        """Synthetic macroscopic solve (Sec. 3.1 eq. macro); see oc_macro for the reading."""
+        """Synthetic macroscopic solve (Sec. 3.1 eq. macro); see oc_macro for
+        the reading.  Polyatomic: W [n, 6], hot [n, 12], src [n, 6] (oc_macro_poly,
+        with the internal-energy equation of Sec. 2 eq. macroscopic_equation_2)."""
         Wio = _f64(W).copy()
         h = _f64(hot)
         sr = _f64(src) if src is not None else None
-        r = lib().oc_macro(C.byref(self.cm), C.byref(self.gas), _p(h), _p(sr), int(n_inner), float(cfl), _p(Wio))
+        fn = lib().oc_macro_poly if self.poly else lib().oc_macro
+        r = fn(C.byref(self.cm), C.byref(self.gas), _p(h), _p(sr), int(n_inner), float(cfl), _p(Wio))
         if r != 0:
             raise FloatingPointError("macro solve produced a non-positive state")
         return Wio
 
     def macro_residual(self, W, hot):
-        """Per-unit-volume residual of the synthetic equations at W (no source)."""
+        """Per-unit-volume residual of the synthetic equations at W (monatomic:
+        no source; polyatomic: with the internal relaxation source)."""
         Wc = _f64(W)
         h = _f64(hot)
-        out = np.zeros((len(Wc), 5))
-        if lib().oc_macro_residual(C.byref(self.cm), C.byref(self.gas), _p(h), _p(Wc), _p(out)) != 0:
+        out = np.zeros((len(Wc), 6 if self.poly else 5))
+        fn = lib().oc_macro_residual_poly if self.poly else lib().oc_macro_residual
+        if fn(C.byref(self.cm), C.byref(self.gas), _p(h), _p(Wc), _p(out)) != 0:
             raise FloatingPointError("non-positive state")
         return out
 
@@ -497,10 +545,19 @@ class Oracle:
         return faces, out
 
     def kinetic_residual(self, f, kin_cell, slot_of_cell, ghost=None):
-        """Moment balance (mass, momentum, energy per unit volume) of the kinetic scheme at f."""
+        """Moment balance (mass, momentum, energy per unit volume) of the kinetic
+        scheme at f; polyatomic: [n, 6] with the internal energy (face fluxes and
+        the exchange term of the sweep's targets)."""
         f = _f64(f)
         kc = np.ascontiguousarray(kin_cell, dtype=np.int32)
         sc = np.ascontiguousarray(slot_of_cell, dtype=np.int32)
+        if self.poly:
+            gh = _f64(ghost if ghost is not None else np.zeros((self.mesh["n_cells"], NMOM + 4)))
+            out = np.zeros((self.mesh["n_cells"], 6))
+            if lib().oc_kinetic_residual_poly(C.byref(self.cm), C.byref(self.cg), C.byref(self.gas), len(kc),
+                                              _p(kc), _p(sc), _p(f), _p(gh), _p(out)) != 0:
+                raise FloatingPointError("fix-up system singular")
+            return out
         gh = _f64(ghost if ghost is not None else np.zeros((self.mesh["n_cells"], NMOM)))
         out = np.zeros((self.mesh["n_cells"], 5))
         sl = self.slopes(f, kc, sc) if self.order == 2 else None
@@ -579,18 +636,27 @@ def one_cell_mesh():
             "cell_volume": np.ones(1), "cell_center": np.zeros((1, 3)), "patches": []}
 
 
-def _cons(W):
+def _cons(W, dr=0.0):
+    """Conserved variables of W = (rho, u, T[, T_r]): (rho, rho u, E[, rho e_r]),
+    E = rho |u|^2 + (3/2) rho T (+ rho e_r, rho e_r = (d_r/2) rho T_r)."""
     rho = W[0]
-    return np.array([rho, rho * W[1], rho * W[2], rho * W[3], rho * (W[1] ** 2 + W[2] ** 2 + W[3] ** 2) + 1.5 * rho * W[4]])
+    E = rho * (W[1] ** 2 + W[2] ** 2 + W[3] ** 2) + 1.5 * rho * W[4]
+    if len(W) > 5:
+        er = 0.5 * dr * rho * W[5]
+        return np.array([rho, rho * W[1], rho * W[2], rho * W[3], E + er, er])
+    return np.array([rho, rho * W[1], rho * W[2], rho * W[3], E])
 
 
-def _prim(U):
+def _prim(U, dr=0.0):
     rho = U[0]
     u = U[1:4] / rho
+    if len(U) > 5:
+        return np.array([rho, u[0], u[1], u[2], (U[4] - rho * np.dot(u, u) - U[5]) / (1.5 * rho),
+                         U[5] / (0.5 * dr * rho)])
     return np.array([rho, u[0], u[1], u[2], (U[4] - rho * np.dot(u, u)) / (1.5 * rho)])
 
 
-def limit_correction(Wh, Wn, factor=2.0, halvings=10, with_theta=False):
+def limit_correction(Wh, Wn, factor=2.0, halvings=10, with_theta=False, dr=0.0):
     """Limiter of the GSIS correction (reading; inactive at convergence).
 
     The conserved-variable change from W^{n+1/2} to W^{n+1} of a kinetic cell
@@ -598,13 +664,17 @@ def limit_correction(Wh, Wn, factor=2.0, halvings=10, with_theta=False):
     temperature lie within a factor 2 of those of W^{n+1/2}, so that the
     corrected distribution stays resolvable on the velocity grid.
     with_theta: also return the fraction of the change kept (1 = inactive,
-    0 = dropped).
+    0 = dropped).  Two-VDF gas (six-component W, d_r = dr): the conserved
+    variables include rho e_r, and T_r is held to the same range.
     """
-    Uh, Un = _cons(Wh), _cons(Wn)
+    Uh, Un = _cons(Wh, dr), _cons(Wn, dr)
     th = 1.0
     for _ in range(halvings + 1):
-        W = _prim(Uh + th * (Un - Uh))
-        if (Wh[0] / factor <= W[0] <= Wh[0] * factor) and (Wh[4] / factor <= W[4] <= Wh[4] * factor):
+        W = _prim(Uh + th * (Un - Uh), dr)
+        ok = (Wh[0] / factor <= W[0] <= Wh[0] * factor) and (Wh[4] / factor <= W[4] <= Wh[4] * factor)
+        if len(W) > 5:
+            ok = ok and (Wh[5] / factor <= W[5] <= Wh[5] * factor)
+        if ok:
             return (W, th) if with_theta else W
         th *= 0.5
     W = np.array(Wh, dtype=np.float64)
@@ -639,11 +709,21 @@ class SteadySolver:
                       "corrections_limited": 0}
 
     # -- initial state ---------------------------------------------------------
+    def _W_of(self, mom):
+        """W of kinetic cells from their moments: (rho, u, T[_t]) [, T_r]."""
+        if self.O.poly:
+            return np.concatenate([mom[:, :5], mom[:, 14:15]], 1)
+        return mom[:, :5]
+
     def set_state(self, W, f=None, flags=None):
-        """W on all cells; f (rows for the kinetic cells in ascending id) or
-        None to start kinetic cells from the conservation-fixed Maxwellian of W."""
+        """W on all cells ((rho, u, T); two-VDF gas: (rho, u, T_t, T_r), a
+        missing T_r is taken equal to T_t); f (rows for the kinetic cells in
+        ascending id) or None to start kinetic cells from the
+        conservation-fixed Maxwellian of W."""
         O = self.O
         self.W = np.array(W, dtype=np.float64)
+        if O.poly and self.W.shape[1] == 5:
+            self.W = np.concatenate([self.W, self.W[:, 4:5]], 1)
         if flags is None:
             flags = np.ones(self.n, np.uint8)
         self.flags = np.asarray(flags, dtype=np.uint8).copy()
@@ -655,7 +735,8 @@ class SteadySolver:
         else:
             self.f[self.slot[self.kin]] = np.asarray(f, dtype=np.float64)
         # W on kinetic cells is the moments of their distribution
-        self.W[self.kin] = O.moments(self.f[self.slot[self.kin]])[:, :5]
+        if len(self.kin):
+            self.W[self.kin] = self._W_of(O.moments(self.f[self.slot[self.kin]]))
 
     def ns_init(self, tol=1e-6, chunk=None, max_chunks=1000):
         """Step 1 (Sec. 3.4): every cell NS, the macroscopic (NSF) solve alone,
@@ -665,7 +746,7 @@ class SteadySolver:
         self.flags = np.zeros(self.n, np.uint8)
         self.kin, self.slot, _ = regions_from_flags(self.flags)
         chunk = chunk or self.n_inner
-        hot = np.zeros((self.n, 9))
+        hot = np.zeros((self.n, 12 if O.poly else 9))
         k, eps = max_chunks, None
         for j in range(max_chunks):
             Wn = O.macro(self.W, hot, chunk, self.cfl)
@@ -720,29 +801,32 @@ class SteadySolver:
         mom_half = O.moments(f_half[rows])
         W_old = self.W
         W_half = W_old.copy()
-        W_half[kin] = mom_half[:, :5]
+        W_half[kin] = self._W_of(mom_half)
         if self.mode == "dvm":
             W_new = W_half
             self.f = f_half
         else:
             # high-order terms on kinetic cells (eq. full_constitutive)
             nsf = O.nsf_field(W_half)
-            hot = np.zeros((self.n, 9))
+            hot = np.zeros((self.n, nsf.shape[1]))
             hot[kin, :6] = mom_half[:, 5:11] - nsf[kin, :6]
-            hot[kin, 6:] = mom_half[:, 11:14] - nsf[kin, 6:]
+            hot[kin, 6:9] = mom_half[:, 11:14] - nsf[kin, 6:9]
+            if O.poly:
+                # HoT of the internal heat flux (eq. full_constitutive, third line)
+                hot[kin, 9:12] = mom_half[:, 15:18] - nsf[kin, 9:12]
             # Source Q of eq. macro (reading): on kinetic cells, the kinetic
             # scheme's own moment balance at f^n minus the synthetic residual
             # at W^n.  The synthetic solve then starts from W^n and acts as a
             # Newton-like corrector of the conserved moments, and its fixed
             # point is the fixed point of the kinetic iteration.
-            src = np.zeros((self.n, 5))
+            src = np.zeros((self.n, W_old.shape[1]))
             src[kin] = Rk[kin] - O.macro_residual(W_old, hot)[kin]
             W_new = O.macro(W_old, hot, self.n_inner, self.cfl, src)
             # GSIS correction (first eq. updatef), with the change of the
             # conserved moments limited on each kinetic cell
             cut = 0
             for c in kin:
-                W_new[c], th = limit_correction(W_half[c], W_new[c], with_theta=True)
+                W_new[c], th = limit_correction(W_half[c], W_new[c], with_theta=True, dr=O.dr)
                 cut += th < 1.0
                 f_half[slot[c]] += O.feq(W_new[c]) - O.feq(W_half[c])
             self.stats["corrections_limited"] = int(cut)

@@ -1134,8 +1134,10 @@ static void face_sources_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *
             continue;
         }
         if (nb >= 0) {
-            oc_g13(g, ghost + (size_t)nb * OC_NMOM, s);
-            Tb = ghost[(size_t)nb * OC_NMOM + 4];
+            /* NS neighbour: the two-VDF Grad-13 rows (eq. G13_VDF) */
+            oc_g13_poly(g, gas->dr, ghost + (size_t)nb * OC_NMOM_POLY, s);
+            srcp[l] = s;
+            continue;
         } else {
             int32_t p = -1 - nb;
             const double *ps = m->patch_state + 5 * p;
@@ -1196,4 +1198,364 @@ int32_t oc_sweep_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
     free(cptr);
     free(cidx);
     return err;
+}
+
+/* ------------------------------------------------------------------------
+ * Grad-13 rows of the two-VDF gas (Sec. 3.2 eq. G13_VDF) in scaled units:
+ * f0 is the monatomic Grad-13 row at T_t; f1 = (d_r T_r/4) f0 plus the
+ * internal heat-flux term q_r.c/(rho T_t) times the Maxwellian at T_t (the
+ * scaled form of the paper's q_r.c/(rho T_t) f_eq: with q_r = 2 sum w c f1
+ * its first moment is q_r, and the Grad bracket of f0 has none).
+ * ------------------------------------------------------------------------ */
+void oc_g13_poly(const oc_grid *g, double d_r, const double *prm, double *out)
+{
+    int32_t nv = oc_nv(g);
+    oc_g13(g, prm, out);
+    const double rho = prm[0], Tt = prm[4], Tr = prm[14];
+    const double *u = prm + 1, *qr = prm + 15;
+    double xi[3], w;
+    for (int32_t k = 0; k < nv; ++k) {
+        node(g, k, xi, &w);
+        double c2 = 0, qc = 0;
+        for (int d = 0; d < 3; ++d) {
+            double c = xi[d] - u[d];
+            c2 += c * c;
+            qc += qr[d] * c;
+        }
+        double M = rho * pow(PI * Tt, -1.5) * exp(-c2 / Tt);
+        out[nv + k] = 0.25 * d_r * Tr * out[k] + qc / (rho * Tt) * M;
+    }
+}
+
+/* thermal-conduction factors [k_t, k_r] = (1/2) A^{-1} [5, d_r] (eq. mu_kappa,
+ * kappa = k mu R) */
+static void conduction_factors(const oc_gas *gas, double *kt, double *kr)
+{
+    const double a = gas->A[0], b = gas->A[1], c = gas->A[2], d = gas->A[3];
+    const double det = a * d - b * c;
+    *kt = 0.5 * (d * 5.0 - b * gas->dr) / det;
+    *kr = 0.5 * (-c * 5.0 + a * gas->dr) / det;
+}
+
+void oc_nsf_poly(const oc_gas *gas, double Tt, const double *grad_u, const double *grad_Tt, const double *grad_Tr,
+                 double *sigma6, double *qt3, double *qr3)
+{
+    double mu = pow(Tt, gas->omega);
+    double cs = -2.0 * gas->Kn / sqrt(PI) * mu;
+    double kt, kr;
+    conduction_factors(gas, &kt, &kr);
+    double div = grad_u[0] + grad_u[4] + grad_u[8];
+    sigma6[0] = cs * (2.0 * grad_u[0] - 2.0 / 3.0 * div);
+    sigma6[1] = cs * (2.0 * grad_u[4] - 2.0 / 3.0 * div);
+    sigma6[2] = cs * (2.0 * grad_u[8] - 2.0 / 3.0 * div);
+    sigma6[3] = cs * (grad_u[1] + grad_u[3]);
+    sigma6[4] = cs * (grad_u[2] + grad_u[6]);
+    sigma6[5] = cs * (grad_u[5] + grad_u[7]);
+    for (int d = 0; d < 3; ++d) {
+        qt3[d] = -kt * gas->Kn / sqrt(PI) * mu * grad_Tt[d];
+        qr3[d] = -kr * gas->Kn / sqrt(PI) * mu * grad_Tr[d];
+    }
+}
+
+int32_t oc_kinetic_residual_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                                 int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                                 const double *f_old, const double *ghost, double *R)
+{
+    int32_t nv = oc_nv(g);
+    size_t row = 2 * (size_t)nv;
+    int32_t *cptr, *cidx;
+    build_adjacency(m, &cptr, &cidx);
+    memset(R, 0, sizeof(double) * 6 * (size_t)m->n_cells);
+    int32_t err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : err)
+    for (int32_t t = 0; t < n_kin; ++t) {
+        int32_t i = kin_cell[t];
+        const double *fi = f_old + (size_t)slot_of_cell[i] * row;
+        int32_t nf = cptr[i + 1] - cptr[i];
+        double *src = (double *)malloc(sizeof(double) * row * (size_t)(nf > 0 ? nf : 1));
+        double *nrm = (double *)malloc(sizeof(double) * 4 * (size_t)(nf > 0 ? nf : 1));
+        const double **srcp = (const double **)malloc(sizeof(double *) * (size_t)(nf > 0 ? nf : 1));
+        double *G = (double *)malloc(sizeof(double) * row);
+        face_sources_poly(m, g, gas, cptr, cidx, i, slot_of_cell, f_old, ghost, fi, src, nrm, srcp);
+        double acc[6] = {0, 0, 0, 0, 0, 0}, xi[3], w;
+        for (int32_t l = 0; l < nf; ++l) {
+            for (int32_t k = 0; k < nv; ++k) {
+                node(g, k, xi, &w);
+                double a = (xi[0] * nrm[4 * l] + xi[1] * nrm[4 * l + 1] + xi[2] * nrm[4 * l + 2]) * nrm[4 * l + 3];
+                const double *up = (a > 0) ? fi : srcp[l];
+                double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+                acc[0] -= w * a * up[k];
+                for (int d = 0; d < 3; ++d) acc[1 + d] -= w * a * xi[d] * up[k];
+                acc[4] -= w * a * (x2 * up[k] + 2.0 * up[nv + k]);
+                acc[5] -= w * a * 2.0 * up[nv + k];
+            }
+        }
+        /* exchange with the translational modes: the collision term of f1 */
+        double mom[OC_NMOM_POLY];
+        oc_moments_poly(g, gas->dr, fi, mom);
+        if (oc_poly_target(g, gas, mom, G) != 0) err = -7;
+        double tau = oc_tau(gas, mom[0], mom[4]);
+        for (int32_t k = 0; k < nv; ++k) {
+            node(g, k, xi, &w);
+            acc[5] += 2.0 * w * (G[nv + k] - fi[nv + k]) / tau;
+        }
+        for (int c = 0; c < 6; ++c) R[6 * i + c] = acc[c];
+        free(src); free(nrm); free(srcp); free(G);
+    }
+    free(cptr);
+    free(cidx);
+    return err;
+}
+
+/* ------------------------------------------------------------------------
+ * Synthetic equations of the two-VDF gas.  Readings (in addition to those
+ * of the monatomic synthetic solve above, which carry over):
+ *   conserved U = (rho, rho u, E, rho e_r), E = rho |u|^2 + (3/2) rho T_t +
+ *   rho e_r, rho e_r = (d_r/2) rho T_r (scaled units, energy / (rho0 R T0));
+ *   convective flux: the kinetic splitting at T_t, with the internal energy
+ *   e_r = (d_r/2) T_r of each side carried by its half-range mass flux
+ *   (internal modes in local equilibrium);
+ *   viscous flux: NSF of oc_nsf_poly at the face T_t plus the mean HoT of
+ *   sigma, q_t and q_r; energy flux sigma.u + (q_t + q_r).n, internal-energy
+ *   flux q_r.n;
+ *   walls: isothermal no-slip for T_t and T_r alike; far field: the patch
+ *   state with T_r = T;
+ *   internal relaxation source S_r = (d_r/2) rho (T - T_r)/(Z_r tau),
+ *   tau = mu(T_t)/p_t, T = (3 T_t + d_r T_r)/(3 + d_r).  In the pseudo-time
+ *   iteration it is taken implicitly (backward Euler in rho e_r with tau of
+ *   the old state and T of the new total energy, which the exchange leaves
+ *   unchanged), so that stiff exchange stays stable and the steady state is
+ *   that of the explicit residual;
+ *   local step: D_i = sum_f S_f (|u_n| + a + 2 nu / d_f), a = sqrt(gamma T/2),
+ *   gamma = (5 + d_r)/(3 + d_r), nu = max(4/3, 2 k_t/3, 2 k_r/d_r) Kn
+ *   T_t^omega / (sqrt(pi) rho);
+ *   positivity: rho, T_t and T_r.
+ * ------------------------------------------------------------------------ */
+static void prim_from_cons_poly(const double *U, double dr, double *P)
+{
+    double rho = U[0], u2 = 0;
+    P[0] = rho;
+    for (int d = 0; d < 3; ++d) { P[1 + d] = U[1 + d] / rho; u2 += P[1 + d] * P[1 + d]; }
+    P[5] = U[5] / (0.5 * dr * rho);
+    P[4] = (U[4] - rho * u2 - U[5]) / (1.5 * rho);
+}
+
+static void cons_from_prim_poly(const double *P, double dr, double *U)
+{
+    double u2 = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
+    U[0] = P[0];
+    for (int d = 0; d < 3; ++d) U[1 + d] = P[0] * P[1 + d];
+    U[5] = 0.5 * dr * P[0] * P[5];
+    U[4] = P[0] * u2 + 1.5 * P[0] * P[4] + U[5];
+}
+
+static void half_flux_poly(const double *P, const double *n, double sgn, double dr, double *F)
+{
+    half_flux(P, n, sgn, F);           /* translational part at T_t = P[4] */
+    double er = 0.5 * dr * P[5];
+    F[4] += er * F[0];
+    F[5] = er * F[0];
+}
+
+static double relax_source(const oc_gas *gas, const double *P)
+{
+    double T = (3.0 * P[4] + gas->dr * P[5]) / (3.0 + gas->dr);
+    return 0.5 * gas->dr * P[0] * (T - P[5]) / (gas->Zr * oc_tau(gas, P[0], P[4]));
+}
+
+/* R (not divided by V) of the flux balance, plus V S_r when with_src; D the
+ * local-step denominators.  pv[n][5] = (u, T_t, T_r), gr[n][5][3]. */
+static int32_t macro_residual_poly(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *W,
+                                   int with_src, double *R, double *D, double *pv, double *gr, const double *bv)
+{
+    int32_t nc = m->n_cells, nfc = m->n_faces;
+    const double dr = gas->dr, gam = (5.0 + dr) / (3.0 + dr);
+    double kt, kr;
+    conduction_factors(gas, &kt, &kr);
+    const double nuf = fmax(4.0 / 3.0, fmax(2.0 * kt / 3.0, 2.0 * kr / dr));
+    for (int32_t i = 0; i < nc; ++i) {
+        const double *Pi = W + 6 * i;
+        if (!(Pi[0] > 0) || !(Pi[4] > 0) || !(Pi[5] > 0)) return -7;
+        for (int c = 0; c < 5; ++c) pv[5 * i + c] = Pi[1 + c];
+    }
+    oc_lsq_gradients(m, 5, pv, bv, gr);
+    memset(R, 0, sizeof(double) * 6 * (size_t)nc);
+    memset(D, 0, sizeof(double) * (size_t)nc);
+    for (int32_t f = 0; f < nfc; ++f) {
+        int32_t L = m->face_cells[2 * f], Rc = m->face_cells[2 * f + 1];
+        const double *n = m->face_normal + 3 * f;
+        double S = m->face_area[f];
+        const double *PL = W + 6 * L;
+        double F[6] = {0, 0, 0, 0, 0, 0};
+        double dL, dR = 0;
+        int kindB = -1;
+        const double *PR = NULL;
+        double Pfar[6];
+        if (Rc >= 0) {
+            PR = W + 6 * Rc;
+        } else {
+            int32_t p = -1 - Rc;
+            kindB = m->patch_kind[p];
+            if (kindB == OC_FAR) {
+                for (int c = 0; c < 5; ++c) Pfar[c] = m->patch_state[5 * p + c];
+                Pfar[5] = Pfar[4];
+                PR = Pfar;
+            }
+        }
+        if (PR) {
+            double FL[6], FR[6];
+            half_flux_poly(PL, n, 1.0, dr, FL);
+            half_flux_poly(PR, n, -1.0, dr, FR);
+            for (int c = 0; c < 6; ++c) F[c] = FL[c] + FR[c];
+        }
+        if (Rc >= 0) {
+            double dx[3], dd = 0;
+            for (int d = 0; d < 3; ++d) { dx[d] = m->cell_center[3 * Rc + d] - m->cell_center[3 * L + d]; dd += dx[d] * n[d]; }
+            double G[5][3];
+            for (int v = 0; v < 5; ++v) {
+                double gx = 0;
+                for (int d = 0; d < 3; ++d) { G[v][d] = 0.5 * (gr[15 * L + 3 * v + d] + gr[15 * Rc + 3 * v + d]); gx += G[v][d] * dx[d]; }
+                double alpha = (pv[5 * Rc + v] - pv[5 * L + v] - gx) / dd;
+                for (int d = 0; d < 3; ++d) G[v][d] += alpha * n[d];
+            }
+            double Tf = 0.5 * (PL[4] + PR[4]);
+            double gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+            double sg[6], qt[3], qr[3];
+            oc_nsf_poly(gas, Tf, gu, G[3], G[4], sg, qt, qr);
+            for (int c = 0; c < 6; ++c) sg[c] += 0.5 * (hot[12 * L + c] + hot[12 * Rc + c]);
+            for (int c = 0; c < 3; ++c) {
+                qt[c] += 0.5 * (hot[12 * L + 6 + c] + hot[12 * Rc + 6 + c]);
+                qr[c] += 0.5 * (hot[12 * L + 9 + c] + hot[12 * Rc + 9 + c]);
+            }
+            double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2],
+                            sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                            sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+            double uf[3] = {0.5 * (PL[1] + PR[1]), 0.5 * (PL[2] + PR[2]), 0.5 * (PL[3] + PR[3])};
+            double qtn = qt[0] * n[0] + qt[1] * n[1] + qt[2] * n[2], qrn = qr[0] * n[0] + qr[1] * n[1] + qr[2] * n[2];
+            for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
+            F[4] += sn[0] * uf[0] + sn[1] * uf[1] + sn[2] * uf[2] + qtn + qrn;
+            F[5] += qrn;
+            dL = dd; dR = dd;
+        } else if (kindB == OC_WALL) {
+            const double *ps = m->patch_state + 5 * (-1 - Rc);
+            double dn = 0;
+            for (int d = 0; d < 3; ++d) dn += (m->face_center[3 * f + d] - m->cell_center[3 * L + d]) * n[d];
+            dL = 2.0 * dn;
+            double pL = PL[0] * PL[4];
+            for (int d = 0; d < 3; ++d) F[1 + d] = 0.5 * pL * n[d];
+            double G[5][3], wv[5] = {ps[1], ps[2], ps[3], ps[4], ps[4]};
+            for (int v = 0; v < 5; ++v) {
+                double gn = 0;
+                for (int d = 0; d < 3; ++d) gn += gr[15 * L + 3 * v + d] * n[d];
+                double jump = (wv[v] - pv[5 * L + v]) / dn;
+                for (int d = 0; d < 3; ++d) G[v][d] = gr[15 * L + 3 * v + d] + (jump - gn) * n[d];
+            }
+            double gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+            double sg[6], qt[3], qr[3];
+            oc_nsf_poly(gas, ps[4], gu, G[3], G[4], sg, qt, qr);
+            double sn[3] = {sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2],
+                            sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                            sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+            double qtn = qt[0] * n[0] + qt[1] * n[1] + qt[2] * n[2], qrn = qr[0] * n[0] + qr[1] * n[1] + qr[2] * n[2];
+            for (int d = 0; d < 3; ++d) F[1 + d] += 0.5 * sn[d];
+            F[4] += sn[0] * ps[1] + sn[1] * ps[2] + sn[2] * ps[3] + qtn + qrn;
+            F[5] += qrn;
+        } else {
+            double dn = 0;
+            for (int d = 0; d < 3; ++d) dn += (m->face_center[3 * f + d] - m->cell_center[3 * L + d]) * n[d];
+            dL = 2.0 * dn;
+        }
+        for (int c = 0; c < 6; ++c) R[6 * L + c] -= F[c] * S;
+        if (Rc >= 0)
+            for (int c = 0; c < 6; ++c) R[6 * Rc + c] += F[c] * S;
+        double TL = (3.0 * PL[4] + dr * PL[5]) / (3.0 + dr);
+        double unL = PL[1] * n[0] + PL[2] * n[1] + PL[3] * n[2];
+        double nuL = nuf * gas->Kn * pow(PL[4], gas->omega) / (sqrt(PI) * PL[0]);
+        D[L] += S * (fabs(unL) + sqrt(gam * TL / 2.0) + 2.0 * nuL / dL);
+        if (Rc >= 0) {
+            double TR = (3.0 * PR[4] + dr * PR[5]) / (3.0 + dr);
+            double unR = PR[1] * n[0] + PR[2] * n[1] + PR[3] * n[2];
+            double nuR = nuf * gas->Kn * pow(PR[4], gas->omega) / (sqrt(PI) * PR[0]);
+            D[Rc] += S * (fabs(unR) + sqrt(gam * TR / 2.0) + 2.0 * nuR / dR);
+        }
+    }
+    if (with_src)
+        for (int32_t i = 0; i < nc; ++i) R[6 * i + 5] += m->cell_volume[i] * relax_source(gas, W + 6 * i);
+    return 0;
+}
+
+static void patch_values_poly(const oc_mesh *m, double *bv)
+{
+    for (int32_t p = 0; p < m->n_patches; ++p) {
+        for (int c = 0; c < 4; ++c) bv[5 * p + c] = m->patch_state[5 * p + 1 + c];
+        bv[5 * p + 4] = m->patch_state[5 * p + 4];
+    }
+}
+
+int32_t oc_macro_residual_poly(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *W,
+                               double *Rv)
+{
+    int32_t nc = m->n_cells;
+    double *D = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *pv = (double *)malloc(sizeof(double) * 5 * (size_t)nc);
+    double *gr = (double *)malloc(sizeof(double) * 15 * (size_t)nc);
+    double *bv = (double *)malloc(sizeof(double) * 5 * (size_t)(m->n_patches > 0 ? m->n_patches : 1));
+    patch_values_poly(m, bv);
+    int32_t st = macro_residual_poly(m, gas, hot, W, 1, Rv, D, pv, gr, bv);
+    if (st == 0)
+        for (int32_t i = 0; i < nc; ++i)
+            for (int c = 0; c < 6; ++c) Rv[6 * i + c] /= m->cell_volume[i];
+    free(D); free(pv); free(gr); free(bv);
+    return st;
+}
+
+int32_t oc_macro_poly(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *src,
+                      int32_t n_inner, double cfl, double *W)
+{
+    int32_t nc = m->n_cells;
+    const double dr = gas->dr;
+    double *U = (double *)malloc(sizeof(double) * 6 * (size_t)nc);
+    double *R = (double *)malloc(sizeof(double) * 6 * (size_t)nc);
+    double *D = (double *)malloc(sizeof(double) * (size_t)nc);
+    double *pv = (double *)malloc(sizeof(double) * 5 * (size_t)nc);
+    double *gr = (double *)malloc(sizeof(double) * 15 * (size_t)nc);
+    double *bv = (double *)malloc(sizeof(double) * 5 * (size_t)(m->n_patches > 0 ? m->n_patches : 1));
+    patch_values_poly(m, bv);
+    for (int32_t i = 0; i < nc; ++i) cons_from_prim_poly(W + 6 * i, dr, U + 6 * i);
+    int32_t status = 0;
+    for (int32_t it = 0; it < n_inner && status == 0; ++it) {
+        status = macro_residual_poly(m, gas, hot, W, 0, R, D, pv, gr, bv);
+        if (status) break;
+        if (src)
+            for (int32_t i = 0; i < nc; ++i)
+                for (int c = 0; c < 6; ++c) R[6 * i + c] += src[6 * i + c] * m->cell_volume[i];
+        double gdt = INFINITY;
+        if (cfl < 0)
+            for (int32_t i = 0; i < nc; ++i) gdt = fmin(gdt, -cfl * m->cell_volume[i] / D[i]);
+        for (int32_t i = 0; i < nc; ++i) {
+            double k = (cfl < 0) ? gdt / m->cell_volume[i] : cfl / D[i];
+            const double *Po = W + 6 * i;
+            double x0 = m->cell_volume[i] / (gas->Zr * oc_tau(gas, Po[0], Po[4]));   /* dt/(Z_r tau) = k x0 */
+            double Un[6], Pn[6];
+            int ok = 0;
+            for (int h = 0; h <= 10 && !ok; ++h) {
+                for (int c = 0; c < 6; ++c) Un[c] = U[6 * i + c] + k * R[6 * i + c];
+                /* internal relaxation, backward Euler at the new total temperature */
+                double u2 = (Un[1] * Un[1] + Un[2] * Un[2] + Un[3] * Un[3]) / (Un[0] * Un[0]);
+                double T = (Un[4] - Un[0] * u2) / (0.5 * (3.0 + dr) * Un[0]);
+                double x = k * x0;
+                Un[5] = (Un[5] + x * 0.5 * dr * Un[0] * T) / (1.0 + x);
+                prim_from_cons_poly(Un, dr, Pn);
+                ok = (Pn[0] > 0) && (Pn[4] > 0) && (Pn[5] > 0);
+                k *= 0.5;
+            }
+            if (ok)
+                for (int c = 0; c < 6; ++c) U[6 * i + c] = Un[c];
+        }
+        for (int32_t i = 0; i < nc; ++i) prim_from_cons_poly(U + 6 * i, dr, W + 6 * i);
+    }
+    for (int32_t i = 0; i < nc && status == 0; ++i)
+        if (!(W[6 * i] > 0) || !(W[6 * i + 4] > 0) || !(W[6 * i + 5] > 0)) status = -7;
+    free(U); free(R); free(D); free(pv); free(gr); free(bv);
+    return status;
 }

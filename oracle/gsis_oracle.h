@@ -173,12 +173,45 @@ void oc_moments_poly(const oc_grid *g, double d_r, const double *f, double *mom)
  * out [2][nv].  Returns 0 or -1 (singular fix-up). */
 int32_t oc_poly_target(const oc_grid *g, const oc_gas *gas, const double *mom, double *out);
 
-/* One point-Jacobi sweep of both VDFs (rows [n_slots][2][nv]).  Boundary and
- * NS-interface values of f1 are (d_r T_b / 4) times those of f0 (internal
- * modes in equilibrium at the boundary temperature T_b). */
+/* One point-Jacobi sweep of both VDFs (rows [n_slots][2][nv]).  Wall and
+ * far-field values of f1 are (d_r T_b / 4) times those of f0 (internal modes
+ * in equilibrium at the boundary temperature T_b); NS neighbours present the
+ * Grad-13 rows of oc_g13_poly of ghost [n_cells][OC_NMOM_POLY]. */
 int32_t oc_sweep_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
                       int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
                       const double *f_old, const double *ghost, double *f_new);
+
+/* Grad-13 rows of an NS cell for the two-VDF gas (Sec. 3.2 eq. G13_VDF):
+ * f0 = the monatomic Grad-13 row of (rho, u, T_t, sigma, q_t) and
+ * f1 = (d_r T_r / 4) f0 + (pi T_t)^(-3/2) (q_r.c / T_t) e^{-c^2/T_t}, so that
+ * 2 sum w c f1 = q_r.  prm[OC_NMOM_POLY] = (rho, u, T_t, sigma, q_t, T_r, q_r). */
+void oc_g13_poly(const oc_grid *g, double d_r, const double *prm, double *out);
+
+/* NSF laws of the two-VDF gas (Sec. 2 eqs. NSF_constitutive, mu_kappa) in
+ * scaled units: sigma = -(2 Kn/sqrt(pi)) mu (grad u + grad u^T - (2/3) div u I),
+ * q_t = -(k_t Kn/sqrt(pi)) mu grad T_t, q_r = -(k_r Kn/sqrt(pi)) mu grad T_r,
+ * mu = T_t^omega, [k_t, k_r] = (1/2) A^{-1} [5, d_r]. */
+void oc_nsf_poly(const oc_gas *gas, double Tt, const double *grad_u, const double *grad_Tt, const double *grad_Tr,
+                 double *sigma6, double *qt3, double *qr3);
+
+/* Moment balance of the two-VDF kinetic scheme at f, per unit volume:
+ * R[n_cells][6] = mass, momentum, total energy sum w (xi^2 f0 + 2 f1) of the
+ * upwind face fluxes, and the internal energy 2 sum w f1: its face fluxes
+ * plus the collision term 2 sum w (G1 - f1) / tau of the sweep's targets.
+ * ghost [n_cells][OC_NMOM_POLY]. */
+int32_t oc_kinetic_residual_poly(const oc_mesh *m, const oc_grid *g, const oc_gas *gas,
+                                 int32_t n_kin, const int32_t *kin_cell, const int32_t *slot_of_cell,
+                                 const double *f_old, const double *ghost, double *R);
+
+/* Synthetic equations of the two-VDF gas (Sec. 2 eq. macroscopic_equation_2
+ * with the internal-energy equation, Sec. 3.1 eqs. full_constitutive, macro).
+ * W[n_cells][6] = (rho, u, T_t, T_r); hot[n_cells][12] = HoT of sigma (6),
+ * q_t (3), q_r (3).  The residual includes the internal relaxation source
+ * (d_r/2) rho (T - T_r) / (Z_r tau), T = (3 T_t + d_r T_r)/(3 + d_r). */
+int32_t oc_macro_residual_poly(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *W,
+                               double *Rv);
+int32_t oc_macro_poly(const oc_mesh *m, const oc_gas *gas, const double *hot, const double *src,
+                      int32_t n_inner, double cfl, double *W);
 
 #ifdef __cplusplus
 }

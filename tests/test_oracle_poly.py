@@ -139,3 +139,123 @@ def test_poly_upwind_transport_free_molecular(oracle_mod):
     for q in (0, 1):
         assert np.abs(f1[1:, q, pos] - f[:-1, q, pos]).max() <= 1e-12 * f.max()
         assert np.abs(f1[:-1, q, neg] - f[1:, q, neg]).max() <= 1e-12 * f.max()
+
+
+# ---------------------------------------------------------------------------
+# the synthetic side of the two-VDF gas (Sec. 2 eq. macroscopic_equation_2,
+# last line; Sec. 3.1 eqs. full_constitutive, macro; Sec. 3.2 eq. G13_VDF)
+# ---------------------------------------------------------------------------
+def test_poly_g13_rows_reproduce_their_parameters(oracle_mod):
+    """The two-VDF Grad-13 rows of an NS cell (eq. G13_VDF, f1 line with its
+    q_r term) have the moments they are built from: rho, u, T_t, sigma, q_t,
+    T_r and q_r, to quadrature accuracy; and they equal the rows written out
+    independently in numpy."""
+    O = _oracle(oracle_mod, oracle_mod.one_cell_mesh())
+    rho, u, Tt, Tr = 1.1, (0.2, -0.3, 0.1), 1.2, 0.9
+    sig, qt, qr = (0.04, -0.02, -0.02, 0.03, -0.01, 0.015), (0.03, -0.02, 0.01), (-0.015, 0.02, 0.01)
+    # without stress and translational heat flux the bracket is 1: the rows
+    # written out in numpy
+    prm0 = np.array([rho, *u, Tt, *np.zeros(9), Tr, *qr])
+    rows0 = O.g13(prm0)
+    assert np.abs(rows0 - _rows(O, rho, u, Tt, Tr, (0, 0, 0), qr)).max() < 1e-13 * np.abs(rows0).max()
+    prm = np.array([rho, *u, Tt, *sig, *qt, Tr, *qr])
+    rows = O.g13(prm)
+    m = O.moments(rows)
+    assert abs(m[0] - rho) < 1e-9 and np.allclose(m[1:4], u, atol=1e-9)
+    assert abs(m[4] - Tt) < 1e-8 and abs(m[14] - Tr) < 1e-8
+    assert np.allclose(m[5:11], sig, atol=1e-8) and np.allclose(m[11:14], qt, atol=1e-8)
+    assert np.allclose(m[15:18], qr, atol=1e-8)
+
+
+def test_poly_synthetic_exchange_matches_kinetic_exchange(oracle_mod):
+    """Uniform gas with T_t = 1.3, T_r = 0.7 in a slab: on interior cells the
+    face fluxes cancel, so the kinetic balance of the internal energy is the
+    collision term 2 sum w (G1 - f1)/tau of the model's targets, and the
+    synthetic residual is the paper's exchange source (d_r/2) rho (T - T_r) /
+    (Z_r tau) with T = (3 T_t + d_r T_r)/(3 + d_r).  The two agree to
+    quadrature accuracy; mass, momentum and total energy do not change.
+    Advanced in pseudo-time, the synthetic solve keeps rho, u and the total
+    energy and relaxes T_t and T_r to the common T."""
+    n = 13
+    m = gi.slab_1d(n, gi._patch("far", rho=1.0, u=(0.1, 0.0, 0.0), T=1.0),
+                   gi._patch("far", rho=1.0, u=(0.1, 0.0, 0.0), T=1.0))
+    O = _oracle(oracle_mod, m, n=24, V=7.0, Kn=0.05)
+    W = np.tile([1.0, 0.1, 0.0, 0.0, 1.3, 0.7], (n, 1))
+    S = oracle_mod.SteadySolver(O, mode="gsis")
+    S.set_state(W)
+    Rk = O.kinetic_residual(S.f, S.kin, S.slot)
+    Rm = O.macro_residual(S.W, np.zeros((n, 12)))
+    inner = np.arange(2, n - 2)
+    T = (3 * 1.3 + 2 * 0.7) / 5.0
+    src = 0.5 * 2.0 * 1.0 * (T - 0.7) / (2.667 * O.tau(1.0, 1.3))
+    assert np.allclose(Rm[inner, 5], src, rtol=1e-12)
+    assert np.allclose(Rk[inner, 5], src, rtol=1e-8)
+    assert np.abs(Rk[inner, :5]).max() < 1e-9 and np.abs(Rm[inner, :5]).max() < 1e-12
+    # two pseudo-time steps (the far-field boundaries do not reach the middle
+    # cell): rho, u, the total energy and T are kept, and T_t, T_r move
+    # towards T by the same fraction
+    Wm = O.macro(S.W, np.zeros((n, 12)), 2, cfl=-0.5)
+    mid = n // 2
+    E0 = 1.0 * 0.01 + 1.5 * 1.3 + 0.5 * 2.0 * 0.7
+    E1 = Wm[mid, 0] * (Wm[mid, 1] ** 2) + 1.5 * Wm[mid, 0] * Wm[mid, 4] + Wm[mid, 0] * Wm[mid, 5]
+    assert abs(E1 - E0) < 1e-13 and abs(Wm[mid, 0] - 1.0) < 1e-14 and abs(Wm[mid, 1] - 0.1) < 1e-14
+    a_t, a_r = (Wm[mid, 4] - T) / (1.3 - T), (Wm[mid, 5] - T) / (0.7 - T)
+    assert 0.0 < a_r < 1.0 and abs(a_t - a_r) < 1e-12
+
+
+def test_poly_continuum_limit_fixes_the_conductivities(oracle_mod):
+    """Nitrogen between diffuse walls at T = 1 (moving -0.1) and T = 2 (moving
+    +0.1), Kn = 0.01, converged by GSIS: away from the Knudsen layers the
+    kinetic stress and both heat fluxes obey the NSF laws of Sec. 2 with
+    mu ~ T_t^omega and the conductivities of eq. mu_kappa,
+    [kappa_t, kappa_r] = (mu R / 2) A^{-1} [5, d_r], i.e. in scaled units
+    q_t = -(k_t Kn/sqrt(pi)) mu dT_t/dx and q_r = -(k_r Kn/sqrt(pi)) mu dT_r/dx
+    with (k_t, k_r) = (3.548, 1.436) for the paper's A (Eucken factors 2.365,
+    1.436).  The heat-flux mixing of the targets through A is what produces
+    these conductivities; a wrong entry of A or of the mixing fails here."""
+    n, Kn = 30, 0.01
+    m = gi.slab_1d(n, gi._patch("wall", u=(0.0, -0.1, 0.0), T=1.0), gi._patch("wall", u=(0.0, 0.1, 0.0), T=2.0))
+    g = gi.velocity_grid(3, 14, 6.0)
+    O = oracle_mod.Oracle(m, g, Kn, omega=N2["omega"], Pr=N2["A"][0], dr=N2["dr"], Zr=N2["Zr"], A=N2["A"])
+    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=0.5)
+    W0 = gi.uniform_W(n)
+    W0[:, 4] = 1.0 + m["cell_center"][:, 0]
+    S.set_state(W0)
+    it, eps = S.solve(tol=1e-9, max_iter=600)
+    assert eps.max() < 1e-9
+    kt, kr = oracle_mod.conductivities(np.array(N2["A"]).reshape(2, 2), N2["dr"])
+    assert abs(kt - 3.548) < 1e-3 and abs(kr - 1.436) < 1e-3
+    mom = O.moments(S.f[S.slot[S.kin]])
+    x = m["cell_center"][:, 0]
+    uy, Tt, sxy, qt, Tr, qr = mom[:, 2], mom[:, 4], mom[:, 8], mom[:, 11], mom[:, 14], mom[:, 15]
+    i = np.arange(n)[(x > 0.2) & (x < 0.8)]
+
+    def d(v):
+        return (v[i + 1] - v[i - 1]) / (x[i + 1] - x[i - 1])
+    mu = Tt[i] ** N2["omega"]
+    c = Kn / np.sqrt(np.pi)
+    assert np.abs(sxy[i] / (-2 * c * mu * d(uy)) - 1).max() < 1e-2
+    assert np.abs(qt[i] / (-kt * c * mu * d(Tt)) - 1).max() < 1e-2
+    assert np.abs(qr[i] / (-kr * c * mu * d(Tr)) - 1).max() < 1e-2
+
+
+def test_poly_gsis_fixed_point_is_dvm_fixed_point(oracle_mod):
+    """Converged GSIS for nitrogen (the internal-energy equation in the
+    synthetic solve, its exchange source, HoT of q_r, rho e_r in the
+    correction) is converged plain DVM on the open slab of the monatomic pin,
+    in far fewer iterations."""
+    m = gi.slab_1d(16, gi._patch("wall", u=(0.0, 0.1, 0.0), T=1.1),
+                   gi._patch("far", rho=1.0, u=(0.0, 0.0, 0.0), T=1.0))
+    g = gi.velocity_grid(3, 12, 5.0)
+    O = oracle_mod.Oracle(m, g, 0.05, omega=N2["omega"], Pr=N2["A"][0], dr=N2["dr"], Zr=N2["Zr"], A=N2["A"])
+    W0 = gi.couette_initial_W(16, seed=1)
+    D = oracle_mod.SteadySolver(O, mode="dvm")
+    D.set_state(W0)
+    it_d, _ = D.solve(tol=1e-12, max_iter=20000)
+    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=0.5)
+    S.set_state(W0)
+    it_s, _ = S.solve(tol=1e-12, max_iter=2000)
+    assert it_s < it_d / 5
+    assert np.abs(S.W - D.W).max() < 1e-9
+    fd = D.f[D.slot[D.kin]]
+    assert np.abs(S.f[S.slot[S.kin]] - fd).max() < 1e-9 * np.abs(fd).max()
