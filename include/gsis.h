@@ -137,19 +137,35 @@ gsis_status gsis_set_velocity_points(gsis_case c, int32_t n_points, const double
  * heat-flux mixing of q_0, q_1 through A, times a conservation fix-up of mass,
  * momentum and total (translational + internal) energy; tau = mu(T_t)/p_t
  * with mu = T_t^omega.  Wall, far-field and NS-interface values of f1 are
- * (d_r T_b / 4) times those of f0.  Supported: 3D tensor velocity grids,
- * spatial order 1, kinetic sweeps, moments (gsis_moments gives T_t and q_t,
- * gsis_internal_moments T_r and q_r) and DVM-mode steps; the GSIS modes,
- * region updates, correction and surface calls return E_ARG (the synthetic
- * solve has no internal-energy equation).  Gas Pr is not used.  Call before
- * gsis_case_footprint / bind (E_STATE once bound); E_ARG for d_r < 0, Z_r < 1
- * or non-finite A. */
+ * (d_r T_b / 4) times those of f0; on NS-interface faces f1 is the two-VDF
+ * Grad-13 row of Sec. 3.2 eq. G13_VDF: (d_r T_r / 4) times the f0 row plus
+ * q_r.c / (rho T_t) times the Maxwellian at T_t.  The synthetic solve of the
+ * GSIS modes adds the internal-energy equation of Sec. 2 eq.
+ * macroscopic_equation_2 (rho e_r = (d_r/2) rho T_r, exchange source
+ * (d_r/2) rho (T - T_r)/(Z_r tau), T = (3 T_t + d_r T_r)/(3 + d_r), taken
+ * backward-Euler in pseudo-time; Fourier laws with the conductivities
+ * (k_t, k_r) = (1/2) A^-1 (5, d_r) of eq. mu_kappa; HoT of q_r), and the
+ * correction moves f1 by (d_r/4)(T_r^{n+1} f_eq(W^{n+1}) - T_r^{n+1/2}
+ * f_eq(W^{n+1/2})).  W passed to and read from the library stays (rho, u,
+ * T_t); T_r of every cell is read with gsis_get_internal_temperature and
+ * starts at T_t on every cell (set_state), the kinetic cells then taking that
+ * of their f1.  Supported: 3D tensor velocity grids, spatial order 1, every
+ * mode of gsis_step / gsis_solve_steady, gsis_ns_init, gsis_update_regions;
+ * gsis_correct, gsis_surface and gsis_macro_solve return E_ARG.  Gas Pr is
+ * not used.  Call before gsis_case_footprint / bind (E_STATE once bound);
+ * E_ARG for d_r < 0, Z_r < 1 or non-finite A. */
 gsis_status gsis_set_internal_dof(gsis_case c, double d_r, double Z_r, const double *A);
 
 /* Polyatomic gas: T_r and q_r (x, y, z) of the current f1 per kinetic cell,
  * out_dev [n_kin][4] FP64 in ascending cell id (may be null when there is no
  * kinetic cell).  E_ARG for a monatomic case. */
 gsis_status gsis_internal_moments(gsis_case c, double *out_dev, void *stream);
+
+/* Polyatomic gas: the internal temperature T_r of every cell of the current
+ * state (kinetic cells: that of f1 after the last step; NS cells: that of the
+ * synthetic solve), out_dev [n_cells] FP64 device memory, on `stream`.  E_ARG
+ * for a monatomic case or a null output; E_STATE before set_state. */
+gsis_status gsis_get_internal_temperature(gsis_case c, double *out_dev, void *stream);
 
 /* Spatial order of the kinetic face values (Sec. 3: second-order finite
  * volumes; the paper leaves the scheme to its references).  order 1

@@ -31,7 +31,7 @@ EXPORTS = [
     "gsis_get_state", "gsis_correct", "gsis_macro_solve", "gsis_last_sweep_ms",
     "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
     "gsis_set_spatial_order", "gsis_set_internal_dof", "gsis_internal_moments",
-    "gsis_set_g13_limit", "gsis_limiter_stats", "gsis_case_bind_static",
+    "gsis_set_g13_limit", "gsis_limiter_stats", "gsis_case_bind_static", "gsis_get_internal_temperature",
 ]
 
 
@@ -112,6 +112,7 @@ def lib():
             "gsis_set_velocity_points": [P, I32, P, P],
             "gsis_set_spatial_order": [P, I32, D],
             "gsis_set_internal_dof": [P, D, D, P], "gsis_internal_moments": [P, P, P],
+            "gsis_get_internal_temperature": [P, P, P],
             "gsis_set_g13_limit": [P, D], "gsis_limiter_stats": [P, P, P],
             "gsis_case_bind_static": [P, I64, P],
         }
@@ -298,6 +299,13 @@ class Case:
         import torch
         out = torch.empty((self.n_kin, 4), dtype=torch.float64, device="cuda")
         _check(lib().gsis_internal_moments(self.handle, _ptr(out), _stream()))
+        return out
+
+    def internal_temperature(self):
+        """Polyatomic gas: T_r of every cell [n_cells] (device, FP64)."""
+        import torch
+        out = torch.empty(self.mesh.n_cells, dtype=torch.float64, device="cuda")
+        _check(lib().gsis_get_internal_temperature(self.handle, _ptr(out), _stream()))
         return out
 
     def limiter_stats(self):

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libgsis.so")
-SOURCES = ["gsis_api.cpp", "gsis_kinetic.hip", "gsis_sweep.hip", "gsis_macro.hip", "gsis_static.hip"]
+SOURCES = ["gsis_api.cpp", "gsis_kinetic.hip", "gsis_sweep.hip", "gsis_macro.hip", "gsis_poly.hip",
+           "gsis_static.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 (v_pk_*) instructions anywhere in the device code

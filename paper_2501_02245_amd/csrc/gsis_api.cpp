@@ -490,7 +490,8 @@ namespace {
 struct Layout {
     size_t cv, cf_ptr, cf_face, cf_other, cf_wall, cf_nsv, lsq, cf_fs, cell_sS, wall_den, face_cells, face_normal, face_area, face_center,
         face_dist, face_dx, cell_volume, cell_center, patch_kind, patch_state, wallf, xv, wv, vpt, vptf, flags, slot, kin, nkin, newc, nnew, scan,
-        status, lim, g13th, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, cf_back, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, hface, dloc, red, eps;
+        status, lim, g13th, prow, grow, gslot, gcell, ngh, axtab, slope, amax, wsl, cf_back, prec, psum, f0, f1, param, feq, partial, mom, W, Wh, Wn, U, grad, ghost, hot, src, Rk, Rm, fflux, hface, dloc, red, eps,
+        Tr, Trh, Trn, Ur, srcr, Rkr, Rmr, fr, hfr, hotr, gTr, ghr;
     size_t total;
 };
 
@@ -650,7 +651,7 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.cf_back = S.take(o2 ? 4 * nnz : 0);
     const bool poly = c->dr > 0;
     L.prec = S.take(poly ? sizeof(PolyRec) * (size_t)cap : 0);
-    L.psum = S.take(poly ? 32 * (size_t)cap * (*ntile) : 0);
+    L.psum = S.take(poly ? 8 * PSUM * (size_t)cap * (*ntile) : 0);
     L.f0 = S.take(es * (size_t)cap * (*row));
     L.f1 = S.take(es * (size_t)cap * (*row));
     L.param = S.take(sizeof(ParamRec) * (size_t)cap);
@@ -672,6 +673,20 @@ Layout make_layout(const gsis_case_s *c, int64_t cap, int *tile, int *ntile, int
     L.dloc = S.take(8 * nc);
     L.red = S.take(8 * std::max<size_t>(8192, 8 + 6 * (nc / 256 + 2) + 256));
     L.eps = S.take(64);
+    // two-VDF gas, synthetic side
+    const size_t pc = poly ? nc : 0, pf = poly ? std::max<size_t>(nf, 1) : 0;
+    L.Tr = S.take(8 * pc);
+    L.Trh = S.take(8 * pc);
+    L.Trn = S.take(8 * pc);
+    L.Ur = S.take(8 * pc);
+    L.srcr = S.take(8 * pc);
+    L.Rkr = S.take(8 * pc);
+    L.Rmr = S.take(8 * pc);
+    L.fr = S.take(8 * pf);
+    L.hfr = S.take(8 * pf);
+    L.hotr = S.take(24 * pc);
+    L.gTr = S.take(24 * pc);
+    L.ghr = S.take(32 * pc);
     L.total = S.off;
     return L;
 }
@@ -726,7 +741,7 @@ gsis_status check_config(const gsis_case_s *c)
 
 gsis_status refuse_poly(gsis_case c, const char *what)
 {
-    if (c && c->dr > 0) return fail(GSIS_E_ARG, "%s: the polyatomic gas supports kinetic sweeps, moments and DVM steps only", what);
+    if (c && c->dr > 0) return fail(GSIS_E_ARG, "%s: not available for the two-VDF (polyatomic) gas", what);
     return GSIS_OK;
 }
 }  // namespace
@@ -851,6 +866,18 @@ gsis_status bind_impl(gsis_case c, void *ws, size_t bytes, int64_t cap, void *st
     if (h.poly) {
         P(PolyRec *, prec, prec);
         P(double *, psum, psum);
+        P(double *, Tr, Tr);
+        P(double *, Trh, Trh);
+        P(double *, Trn, Trn);
+        P(double *, Ur, Ur);
+        P(double *, srcr, srcr);
+        P(double *, Rkr, Rkr);
+        P(double *, Rmr, Rmr);
+        P(double *, fr, fr);
+        P(double *, hfr, hfr);
+        P(double *, hotr, hotr);
+        P(double *, gTr, gTr);
+        P(double *, ghr, ghr);
     }
     if (c->order == 2) {
         P(void *, slope, slope);
@@ -919,6 +946,7 @@ gsis_status bind_impl(gsis_case c, void *ws, size_t bytes, int64_t cap, void *st
     HIPCHK(hipMemsetAsync(B + L.prow, 0, L.gslot - L.prow, s));
     HIPCHK(hipMemsetAsync(B + L.wall_den, 0, 8 * nnz, s));
     HIPCHK(hipMemsetAsync(B + L.hot, 0, 72 * nc, s));
+    if (h.poly) HIPCHK(hipMemsetAsync(B + L.hotr, 0, 24 * nc, s));
     // padding of the VDF rows stays zero
     HIPCHK(hipMemsetAsync(B + L.f0, 0, L.f1 - L.f0, s));
     HIPCHK(hipMemsetAsync(B + L.f1, 0, L.param - L.f1, s));
@@ -982,6 +1010,8 @@ extern "C" gsis_status gsis_set_state(gsis_case c, const double *W_dev, const vo
     gsis_status st = read_counts(c, s, nullptr);
     if (st) return st;
     c->cur = 0;
+    // two-VDF gas: the internal temperature starts at T_t on every cell
+    if (h.poly) HIPCHK(launch_tt_copy(c->cv, h, h.Tr, s));
     if (vdf_dev) {
         HIPCHK(launch_gather_vdf(c->cv, h, c->n_kin, 0, const_cast<void *>(vdf_dev), 1, s));
         HIPCHK(launch_fill(c->cv, h, 2, c->n_kin, 0, s));
@@ -989,8 +1019,9 @@ extern "C" gsis_status gsis_set_state(gsis_case c, const double *W_dev, const vo
         HIPCHK(launch_fill(c->cv, h, 0, c->n_kin, 0, s));
     }
     HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
-    // W on kinetic cells = moments of the VDF
+    // W (and T_r) on kinetic cells = moments of the VDF
     HIPCHK(launch_W_from_mom(c->cv, h, c->n_kin, h.W, s));
+    if (h.poly) HIPCHK(launch_tr_half(c->cv, h, h.Tr, s));
     st = sync_status(c, s);
     if (st) return st;
     c->state_set = true;
@@ -1021,7 +1052,8 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
     if (h.fast) HIPCHK(launch_axtab(c->cv, h, c->n_kin, s));
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
-        HIPCHK(launch_ghost(c->cv, h, h.W, s));
+        if (h.poly) HIPCHK(launch_ghost_poly(c->cv, h, h.W, h.Tr, s));
+        else HIPCHK(launch_ghost(c->cv, h, h.W, s));
         HIPCHK(launch_count_g13(c->cv, h.ghost_cell, c->n_ghost, 0, s));
         if (h.fast || h.points || (h.sorder == 2 && h.vdim == 3) || h.poly)
             HIPCHK(launch_ghost_rows(c->cv, h, c->n_ghost, s));
@@ -1116,6 +1148,7 @@ extern "C" gsis_status gsis_kinetic_sweep(gsis_case const *cases, int32_t n_case
             gsis_case c = cases[j];
             HIPCHK(launch_reduce(c->cv, c->hv, c->n_kin, 1, s));
             HIPCHK(launch_W_from_mom(c->cv, c->hv, c->n_kin, c->hv.W, s));
+            if (c->hv.poly) HIPCHK(launch_tr_half(c->cv, c->hv, c->hv.Tr, s));
         }
     }
     return GSIS_OK;
@@ -1147,6 +1180,16 @@ extern "C" gsis_status gsis_internal_moments(gsis_case c, double *out, void *str
     if (!(c->dr > 0)) return fail(GSIS_E_ARG, "the gas has no internal degrees of freedom");
     if (!out && c->n_kin > 0) return fail(GSIS_E_ARG, "null output");
     HIPCHK(launch_internal_out(c->cv, c->hv, c->n_kin, out, (hipStream_t)stream));
+    return GSIS_OK;
+}
+
+extern "C" gsis_status gsis_get_internal_temperature(gsis_case c, double *out, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!(c->dr > 0)) return fail(GSIS_E_ARG, "the gas has no internal degrees of freedom");
+    if (!out) return fail(GSIS_E_ARG, "null output");
+    HIPCHK(launch_copy_d(out, c->hv.Tr, c->hv.n_cells, (hipStream_t)stream));
     return GSIS_OK;
 }
 
@@ -1185,7 +1228,6 @@ extern "C" gsis_status gsis_update_regions(gsis_case c, double Kn_ref, int32_t l
 {
     gsis_status st = check_ready(c);
     if (st) return st;
-    if ((st = refuse_poly(c, "gsis_update_regions"))) return st;
     if (!(Kn_ref >= 0) || layers < 0) return fail(GSIS_E_ARG, "bad Kn_ref or layers");
     hipStream_t s = (hipStream_t)stream;
     CaseView &h = c->hv;
@@ -1195,7 +1237,8 @@ extern "C" gsis_status gsis_update_regions(gsis_case c, double Kn_ref, int32_t l
     if ((st = read_counts(c, s, &n_new))) return st;
     if (n_new > 0) {
         // Grad-13 of the current W (gradients of u, T are in grad after launch_flags)
-        HIPCHK(launch_ghost(c->cv, h, h.W, s));
+        if (h.poly) HIPCHK(launch_ghost_poly(c->cv, h, h.W, h.Tr, s));
+        else HIPCHK(launch_ghost(c->cv, h, h.W, s));
         HIPCHK(launch_count_g13(c->cv, h.new_cell, n_new, 1, s));
         HIPCHK(launch_fill(c->cv, h, 1, n_new, c->cur, s));
     }
@@ -1219,15 +1262,24 @@ gsis_status pre_macro(gsis_case c, const gsis_solve_params *p, hipStream_t s)
     if (p->mode == GSIS_MODE_DVM) {
         HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
         HIPCHK(launch_W_from_mom(c->cv, h, c->n_kin, h.Wn, s));
+        if (h.poly) HIPCHK(launch_tr_half(c->cv, h, h.Trn, s));
         return GSIS_OK;
     }
     HIPCHK(launch_whalf(c->cv, h, c->n_kin, s));
+    if (h.poly) HIPCHK(launch_tr_half(c->cv, h, h.Trh, s));
     // high-order terms from f^{n+1/2} and gradients of W^{n+1/2}
     HIPCHK(launch_lsq(c->cv, h, h.Wh, 4, s));
-    HIPCHK(launch_hot(c->cv, h, c->n_kin, s));
+    if (h.poly) HIPCHK(launch_hot_poly(c->cv, h, s));
+    else HIPCHK(launch_hot(c->cv, h, c->n_kin, s));
     // source: kinetic moment balance at f^n minus synthetic residual at W^n
-    HIPCHK(launch_macro_residual(c->cv, h, h.W, h.hot, h.Rm, s));
-    HIPCHK(launch_src(c->cv, h, c->n_kin, s));
+    if (h.poly) {
+        HIPCHK(launch_macro_residual_poly(c->cv, h, h.W, h.Tr, h.hot, h.Rm, h.Rmr, s));
+        HIPCHK(launch_src_poly(c->cv, h, s));
+        HIPCHK(launch_copy_d(h.Trn, h.Tr, h.n_cells, s));
+    } else {
+        HIPCHK(launch_macro_residual(c->cv, h, h.W, h.hot, h.Rm, s));
+        HIPCHK(launch_src(c->cv, h, c->n_kin, s));
+    }
     HIPCHK(launch_copy_W(h.Wn, h.W, h.n_cells, s));
     return GSIS_OK;
 }
@@ -1283,7 +1335,7 @@ gsis_status run_macro_batch(gsis_case const *cases, int n, int n_inner, double c
     MBatch b{};
     for (int j = 0; j < n; ++j) {
         CaseView &h = cases[j]->hv;
-        mbatch_add(b, cases[j]->cv, h, h.Wn, h.hot, with_src ? h.src : nullptr);
+        mbatch_add(b, cases[j]->cv, h, h.Wn, h.hot, with_src ? h.src : nullptr, h.poly ? h.Trn : nullptr);
     }
     if (!graphs_enabled() || n_inner <= 0) {
         HIPCHK(launch_macro_steps_batch(b, n_inner, cfl, s));
@@ -1342,6 +1394,7 @@ gsis_status post_macro(gsis_case c, const gsis_solve_params *p, hipStream_t s)
     }
     HIPCHK(launch_eps(c->cv, h, h.Wn, h.W, s));
     HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+    if (h.poly) HIPCHK(launch_copy_d(h.Tr, h.Trn, h.n_cells, s));
     return GSIS_OK;
 }
 
@@ -1362,7 +1415,6 @@ extern "C" gsis_status gsis_step(gsis_case const *cases, int32_t n, const gsis_s
     gsis_status st = check_batch(cases, n);
     if (st) return st;
     if ((st = check_params(p))) return st;
-    if (p->mode != GSIS_MODE_DVM && (st = refuse_poly(cases[0], "gsis_step (GSIS modes)"))) return st;
     hipStream_t s = (hipStream_t)stream;
     for (int j = 0; j < n; ++j)
         if ((st = prepare_sweep(cases[j], s))) return st;
@@ -1445,6 +1497,7 @@ extern "C" gsis_status gsis_macro_solve(gsis_case c, double *W, const double *ho
     if (!c || !W || !hot) return fail(GSIS_E_ARG, "null argument");
     if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
     if (n_inner < 0 || cfl == 0 || !std::isfinite(cfl)) return fail(GSIS_E_ARG, "bad n_inner or cfl");
+    if (c->dr > 0) return fail(GSIS_E_ARG, "gsis_macro_solve: the two-VDF gas's synthetic solve runs inside gsis_step");
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipMemsetAsync(c->hv.status, 0, 16, s));
     HIPCHK(launch_check_W(c->cv, c->hv, W, s));
@@ -1459,8 +1512,6 @@ extern "C" gsis_status gsis_ns_init(gsis_case const *cases, int32_t n, const gsi
     gsis_status st;
     if ((st = check_params(p))) return st;
     if (p->mode != GSIS_MODE_AGSIS) return fail(GSIS_E_ARG, "the NS start belongs to aGSIS");
-    for (int j = 0; j < n; ++j)
-        if ((st = refuse_poly(cases[j], "gsis_ns_init"))) return st;
     for (int j = 0; j < n; ++j) {
         if ((st = check_ready(cases[j]))) return st;
         for (int i = 0; i < j; ++i)
@@ -1476,6 +1527,7 @@ extern "C" gsis_status gsis_ns_init(gsis_case const *cases, int32_t n, const gsi
         HIPCHK(launch_compact(c->cv, h, s));
         if ((st = read_counts(c, s, nullptr))) return st;
         HIPCHK(hipMemsetAsync(h.hot, 0, 72 * (size_t)h.n_cells, s));
+        if (h.poly) HIPCHK(hipMemsetAsync(h.hotr, 0, 24 * (size_t)h.n_cells, s));
         if (chunks) chunks[j] = 0;
     }
     std::vector<gsis_case> active(cases, cases + n);
@@ -1483,7 +1535,10 @@ extern "C" gsis_status gsis_ns_init(gsis_case const *cases, int32_t n, const gsi
     for (int j = 0; j < n; ++j) idx[j] = j;
     const int max_chunks = p->ns_init_max_chunks > 0 ? p->ns_init_max_chunks : 1000;
     for (int k = 0; k < max_chunks && !active.empty(); ++k) {
-        for (gsis_case c : active) HIPCHK(launch_copy_W(c->hv.Wn, c->hv.W, c->hv.n_cells, s));
+        for (gsis_case c : active) {
+            HIPCHK(launch_copy_W(c->hv.Wn, c->hv.W, c->hv.n_cells, s));
+            if (c->hv.poly) HIPCHK(launch_copy_d(c->hv.Trn, c->hv.Tr, c->hv.n_cells, s));
+        }
         for (size_t j0 = 0; j0 < active.size(); j0 += MAX_BATCH)
             if ((st = run_macro_batch(active.data() + j0, (int)std::min<size_t>(MAX_BATCH, active.size() - j0),
                                       p->n_macro_inner, p->cfl, false, s)))
@@ -1493,6 +1548,7 @@ extern "C" gsis_status gsis_ns_init(gsis_case const *cases, int32_t n, const gsi
             CaseView &h = active[j]->hv;
             HIPCHK(launch_eps(active[j]->cv, h, h.Wn, h.W, s));
             HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+            if (h.poly) HIPCHK(launch_copy_d(h.Tr, h.Trn, h.n_cells, s));
             HIPCHK(hipMemcpyAsync(&e[3 * j], h.eps, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         }
         HIPCHK(hipStreamSynchronize(s));
@@ -1521,7 +1577,6 @@ extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p
     if (st) return st;
     if ((st = check_params(p))) return st;
     if (!r) return fail(GSIS_E_ARG, "null result");
-    if (p->mode != GSIS_MODE_DVM && (st = refuse_poly(c, "gsis_solve_steady (GSIS modes)"))) return st;
     const bool ns_init = p->mode == GSIS_MODE_AGSIS && p->ns_init;
     if (!(p->tol > 0) || p->max_iter < 0 || (p->max_iter == 0 && !ns_init))
         return fail(GSIS_E_ARG, "bad tol or max_iter");

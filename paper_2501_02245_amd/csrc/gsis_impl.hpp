@@ -35,6 +35,7 @@ constexpr int MOM_INT = GSIS_NMOM + MAXW;
 //       sum w D (f_new - f_old) (1, c_x, c_y, c_z, c^2 [+ psi]) (sweep only)
 //   [18..21] sum_{a > 0} w a phi per wall face of the cell (a = xi.n S/V)
 enum { S_RES = 13, S_WALL = 18 };
+constexpr int PSUM = 5;                // per (slot, tile) sums of the second function (two-VDF gas)
 
 // Per-slot parameters of the relaxation target (FP64; Sec. 2 reference
 // distribution specialised to d_r = 0, with the conservation fix-up).
@@ -155,7 +156,8 @@ struct CaseView {
     int32_t sorder, pad_o;
     double damp2;
     // polyatomic gas (d_r > 0): rows hold (f0, f1); per-slot target records and
-    // per (slot, tile) sums of the second function: sum w f1, sum w c f1 (3)
+    // per (slot, tile) sums of the second function [PSUM]: sum w f1, sum w c f1
+    // (3), and (sweep only) the balance sum w D (f1_new - f1_old) at the old iterate
     int32_t poly, pad_p2;
     double dr, Zr, A[4];
     PolyRec *prec;
@@ -194,6 +196,14 @@ struct CaseView {
     double g13_rmax;
     double *g13_th;
     unsigned long long *lim;
+    // two-VDF gas, synthetic side (Sec. 2 eq. macroscopic_equation_2, last line):
+    // the internal temperature T_r of W^n, W^{n+1/2} and W^{n+1} [n_cells] each,
+    // rho e_r during the pseudo-time steps, its source, kinetic and synthetic
+    // balances [n_cells], face fluxes and HoT face means of rho e_r [n_faces],
+    // HoT of q_r [n_cells][3], the gradient of T_r [n_cells][3] and the Grad-13
+    // parameters T_r, q_r of every cell [n_cells][4]
+    double *Tr, *Trh, *Trn, *Ur, *srcr, *Rkr, *Rmr;
+    double *fr, *hfr, *hotr, *gTr, *ghr;
 };
 
 struct Batch {
@@ -220,6 +230,7 @@ constexpr int MCELLS_Q = 64;     // cells per block of the lane-per-face kernels
 struct MBatch {
     const CaseView *cv[MAX_BATCH];
     double *W[MAX_BATCH];            // state advanced by the pseudo-time steps
+    double *Tr[MAX_BATCH];           // two-VDF gas: its internal temperature (else null)
     const double *hot[MAX_BATCH];    // [n_cells][9] high-order terms
     const double *src[MAX_BATCH];    // [n_cells][5] sources per unit volume, or null
     int32_t bc[MAX_BATCH + 1];       // prefix of cell blocks
@@ -227,6 +238,7 @@ struct MBatch {
     int32_t bq[MAX_BATCH + 1];       // prefix of cell-group blocks (MCELLS_Q cells, one lane per face)
     int32_t n;
     int32_t nfmax;
+    int32_t poly;                    // the cases are two-VDF gases (synthetic equations with rho e_r)
 };
 
 // velocity node k and its weight: tensor grids (k = (ix n1 + iy) n2 + iz, or
@@ -288,6 +300,7 @@ hipError_t launch_gather_vdf(const CaseView *cv, const CaseView &h, int n_kin, i
 
 // --- launch wrappers (gsis_macro.hip) ----------------------------------------
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s);
+hipError_t launch_lsq_batch(const MBatch &b, int nvar, hipStream_t s);
 hipError_t launch_ghost(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s);
 // add to the limiter counters lim[2 which], lim[2 which + 1] the n cells of
 // list and those whose Grad-13 pair was scaled (list and n from the host)
@@ -300,7 +313,8 @@ hipError_t launch_src(const CaseView *cv, const CaseView &h, int n_kin, hipStrea
 // n_inner pseudo-time steps for every case of a batch (cfl > 0 local steps,
 // cfl < 0 one global step per case)
 hipError_t launch_macro_steps_batch(const MBatch &b, int n_inner, double cfl, hipStream_t s);
-void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src);
+void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src,
+                double *Tr = nullptr);
 hipError_t launch_macro_steps(const CaseView *cv, const CaseView &h, double *W, const double *hot,
                               const double *src, int n_inner, double cfl, hipStream_t s);
 hipError_t launch_eps(const CaseView *cv, const CaseView &h, const double *Wnew, const double *Wold,
@@ -319,5 +333,22 @@ hipError_t launch_W_from_mom(const CaseView *cv, const CaseView &h, int n_kin, d
 // surface quantities of the wall faces (GSIS_NSURF per face) and optional totals
 hipError_t launch_surface(const CaseView *cv, const CaseView &h, int cur, double *out, double *totals, hipStream_t s);
 hipError_t launch_check_W(const CaseView *cv, const CaseView &h, const double *W, hipStream_t s);
+
+// --- two-VDF gas, synthetic side (gsis_poly.hip) -----------------------------
+// Grad-13 parameters (ghost, ghr) of every cell from W, Tr and their gradients
+// (grad rows of W from launch_lsq, the T_r gradient computed here)
+hipError_t launch_ghost_poly(const CaseView *cv, const CaseView &h, const double *W, const double *Tr, hipStream_t s);
+// HoT of sigma, q_t (hot) and q_r (hotr) on kinetic cells at W^{n+1/2}
+hipError_t launch_hot_poly(const CaseView *cv, const CaseView &h, hipStream_t s);
+// out = T_r of the moments on kinetic cells, Tr elsewhere (out may be Tr)
+hipError_t launch_tr_half(const CaseView *cv, const CaseView &h, double *out, hipStream_t s);
+// synthetic residual per unit volume at (W, Tr), with the exchange source
+hipError_t launch_macro_residual_poly(const CaseView *cv, const CaseView &h, const double *W, const double *Tr,
+                                      const double *hot, double *Rout, double *Rrout, hipStream_t s);
+hipError_t launch_src_poly(const CaseView *cv, const CaseView &h, hipStream_t s);
+hipError_t launch_macro_steps_poly(const MBatch &b, int n_inner, double cfl, hipStream_t s);
+hipError_t launch_copy_d(double *dst, const double *src, int n, hipStream_t s);
+// out[i] = T_t of W (every cell)
+hipError_t launch_tt_copy(const CaseView *cv, const CaseView &h, double *out, hipStream_t s);
 
 }  // namespace gsis

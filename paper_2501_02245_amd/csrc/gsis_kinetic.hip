@@ -439,13 +439,15 @@ __global__ void k_reduce(const CaseView *__restrict__ cvp, int n_kin, int with_r
     for (int w = 0; w < MAXW; ++w) mom[GSIS_NMOM + w] = S[S_WALL + w];
     if (C.poly) {
         // second function: T_r = 4 sum w f1 / (d_r rho), q_r = 2 sum w c f1
-        double Q[4] = {0, 0, 0, 0};
-        const double *ps = C.psum + (size_t)slot * C.ntile * 4;
+        double Q[PSUM] = {0, 0, 0, 0, 0};
+        const double *ps = C.psum + (size_t)slot * C.ntile * PSUM;
         for (int tl = 0; tl < C.ntile; ++tl)
-            for (int i = 0; i < 4; ++i) Q[i] += ps[tl * 4 + i];
+            for (int i = 0; i < PSUM; ++i) Q[i] += ps[tl * PSUM + i];
         mom[MOM_INT] = 4.0 * Q[0] / (C.dr * rho);
         for (int d = 0; d < 3; ++d) mom[MOM_INT + 1 + d] = 2.0 * (Q[1 + d] - dl[d] * Q[0]);
         if (!(mom[MOM_INT] > 0.0)) atomicOr(C.status, 1);
+        // kinetic balance of rho e_r = 2 sum w f1 (flux and exchange)
+        if (with_res) C.Rkr[cell] = 2.0 * Q[4];
     }
     int bad = !(rho > 0.0) || !(p > 0.0) || !isfinite(q[0] + q[1] + q[2] + mom[5] + mom[8]);
     if (bad) atomicOr(C.status, 1);
@@ -513,7 +515,9 @@ hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStr
 }
 
 // conservation-fixed Maxwellians of W_new (Wn) and W_half (Wh) per kinetic
-// slot (mode 0, GSIS correction), or of W (mode 1, initial fill)
+// slot (mode 0, GSIS correction), or of W (mode 1, initial fill); Th is the
+// factor of the second function (T/2 of the reduced pair, d_r T_r/4 of the
+// two-VDF gas)
 __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const int32_t *list, int mode)
 {
     const CaseView &C = *cvp;
@@ -525,18 +529,24 @@ __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const in
         // limiter of the correction: halve the conserved-variable change from
         // W_half to W_new (at most ten times, then drop it) until density and
         // temperature stay within a factor 2 of W_half; W_new takes the result
+        // (two-VDF gas: the conserved variables include rho e_r = (d_r/2) rho T_r,
+        // and T_r is held to the same range)
         double *wn = C.Wn + 5 * (size_t)cell;
         const double *wh = C.Wh + 5 * (size_t)cell;
-        double Uh[5], Ud[5];
+        const bool poly = C.poly != 0;
+        const double trh = poly ? C.Trh[cell] : 0.0, trn = poly ? C.Trn[cell] : 0.0;
+        double Uh[6], Ud[6];
         for (int s = 0; s < 2; ++s) {
             const double *w = s ? wn : wh;
             double *U = s ? Ud : Uh;
+            const double er = poly ? 0.5 * C.dr * w[0] * (s ? trn : trh) : 0.0;
             U[0] = w[0];
             for (int d = 0; d < 3; ++d) U[1 + d] = w[0] * w[1 + d];
-            U[4] = w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) + 1.5 * w[0] * w[4];
+            U[4] = w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) + 1.5 * w[0] * w[4] + er;
+            U[5] = er;
         }
-        for (int c = 0; c < 5; ++c) Ud[c] -= Uh[c];
-        double th = 1.0, Wl[5];
+        for (int c = 0; c < 6; ++c) Ud[c] -= Uh[c];
+        double th = 1.0, Wl[5], Trl = 0.0;
         bool ok = false;
         int h = 0;
         for (; h <= 10 && !ok; ++h) {
@@ -547,12 +557,18 @@ __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const in
                 Wl[1 + d] = (Uh[1 + d] + th * Ud[1 + d]) / U0;
                 u2 += Wl[1 + d] * Wl[1 + d];
             }
-            Wl[4] = (Uh[4] + th * Ud[4] - U0 * u2) / (1.5 * U0);
+            const double er = Uh[5] + th * Ud[5];
+            Wl[4] = (Uh[4] + th * Ud[4] - U0 * u2 - er) / (1.5 * U0);
             ok = (wh[0] / 2.0 <= Wl[0]) && (Wl[0] <= 2.0 * wh[0]) && (wh[4] / 2.0 <= Wl[4]) && (Wl[4] <= 2.0 * wh[4]);
+            if (poly) {
+                Trl = er / (0.5 * C.dr * U0);
+                ok = ok && (trh / 2.0 <= Trl) && (Trl <= 2.0 * trh);
+            }
             th *= 0.5;
         }
         cut = !ok || h > 1;
         for (int c = 0; c < 5; ++c) wn[c] = ok ? Wl[c] : wh[c];
+        if (poly) C.Trn[cell] = ok ? Trl : trh;
     }
     if (mode == 0) {
         // limiter counters (one atomic per wave)
@@ -569,6 +585,11 @@ __global__ void k_feqpar(const CaseView *__restrict__ cvp, int n_items, const in
         if (C.vdim == 2) F.u[2] = 0.0;
         F.it = 1.0 / W[4];
         F.Th = 0.5 * W[4];
+        if (C.poly) {
+            // f_eq,1 = (d_r T_r / 4) f_eq,0
+            const double *Trs = (mode == 0) ? (which == 0 ? C.Trn : C.Trh) : C.Tr;
+            F.Th = 0.25 * C.dr * Trs[cell];
+        }
         if (!C.points && fixup_coefs(C, F.u, W[4], W[0], nullptr, F.fx)) atomicOr(C.status, 1);
         C.feq[2 * (size_t)slot + which] = F;
     }
@@ -1594,8 +1615,12 @@ __global__ __launch_bounds__(FIXP_THREADS) void k_fix_poly(const CaseView *__res
 }
 
 // rows of the polyatomic gas and their sums: mode 0 fills f0 with the
-// conservation-fixed Maxwellian of W (FeqRec) and f1 = (d_r T / 4) f0; mode 2
-// keeps the rows; both write the partial sums of f0 and f1
+// conservation-fixed Maxwellian of W (FeqRec) and f1 = Th f0 (Th = d_r T_r/4);
+// mode 1 (new kinetic cells) and mode 3 (Grad-13 ghost rows of NS cells, no
+// sums) the two-VDF Grad-13 rows of the cell's parameters (ghost, ghr):
+// f0 = the monatomic row at T_t, f1 = (d_r T_r/4) f0 + (q_r.c/(rho T_t)) M_t
+// (Sec. 3.2 eq. G13_VDF, scaled); mode 2 keeps the rows.  Modes 0-2 write the
+// partial sums of f0 and f1.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict__ cvp, const int32_t *list,
                                                      int n_items, int mode, int cur)
@@ -1606,20 +1631,128 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
     __shared__ int s_wi[MAXW], s_nw;
     const int vt = blockIdx.x / n_items, t = blockIdx.x - vt * n_items;
     const int cell = list[t];
-    const int slot = C.slot_of_cell[cell];
-    double u[3], it = 1.0, fx[5] = {0, 0, 0, 0, 0};
+    const int slot = (mode == 3) ? C.ghost_slot[cell] : C.slot_of_cell[cell];
+    double u[3], it = 1.0, th = 0.0, fx[5] = {0, 0, 0, 0, 0};
+    double A = 0.0, sg[6] = {0, 0, 0, 0, 0, 0}, qg[3] = {0, 0, 0}, qr[3] = {0, 0, 0};
     if (mode == 0) {
         const FeqRec &F = C.feq[2 * (size_t)slot];
         for (int d = 0; d < 3; ++d) u[d] = F.u[d];
         it = F.it;
+        th = F.Th;
         for (int d = 0; d < 5; ++d) fx[d] = F.fx[d];
-    } else {
+    } else if (mode == 2) {
         for (int d = 0; d < 3; ++d) u[d] = C.W[5 * (size_t)cell + 1 + d];
+    } else {
+        const double *g = C.ghost + (size_t)cell * GSIS_NMOM;
+        const double *gr = C.ghr + 4 * (size_t)cell;
+        const double rho = g[0], Tg = g[4], p = rho * Tg;
+        for (int d = 0; d < 3; ++d) u[d] = g[1 + d];
+        it = 1.0 / Tg;
+        th = 0.25 * C.dr * gr[0];
+        A = rho * pow(M_PI * Tg, -1.5);
+        for (int d = 0; d < 6; ++d) sg[d] = g[5 + d] / (p * Tg);
+        for (int d = 0; d < 3; ++d) {
+            qg[d] = 2.0 * g[11 + d] / (p * Tg);
+            qr[d] = gr[1 + d] / p;   // q_r / (rho T_t)
+        }
     }
-    const double th = 0.25 * C.dr / it;
     if (threadIdx.x == 0) {
-        if (vt == 0)
+        if (vt == 0 && mode != 3)
             for (int d = 0; d < 3; ++d) C.param[slot].u[d] = u[d];
+        int nw = 0;
+        if (mode != 3)
+            for (int e = C.cf_ptr[cell]; e < C.cf_ptr[cell + 1]; ++e)
+                if (C.cf_wall[e] >= 0) {
+                    for (int d = 0; d < 3; ++d) wn[nw][d] = C.cf_nsv[3 * (size_t)e + d];
+                    s_wi[nw++] = C.cf_wall[e];
+                }
+        s_nw = nw;
+    }
+    __syncthreads();
+    const int nw = s_nw;
+    const int nvp = C.row / 2;
+    T *fr = (T *)((mode == 3) ? C.grow : C.f[cur]) + (size_t)slot * C.row;
+    double acc[NSUM], wj[MAXW], ps[PSUM] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
+    const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
+    for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
+        double xi[3], w;
+        vnode(C, k, xi, w);
+        const double c0 = xi[0] - u[0], c1 = xi[1] - u[1], c2 = xi[2] - u[2];
+        const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+        T v0, v1;
+        if (mode == 2) {
+            v0 = fr[k];
+            v1 = fr[nvp + k];
+        } else {
+            double f0, f1;
+            if (mode == 0) {
+                f0 = exp(-cc * it) * (fx[0] + fx[1] * c0 + fx[2] * c1 + fx[3] * c2 + fx[4] * cc);
+                f1 = th * f0;
+            } else {
+                const double Q2 = sg[0] * c0 * c0 + sg[1] * c1 * c1 + sg[2] * c2 * c2 +
+                                  2.0 * (sg[3] * c0 * c1 + sg[4] * c0 * c2 + sg[5] * c1 * c2);
+                const double qd = qg[0] * c0 + qg[1] * c1 + qg[2] * c2;
+                const double M = A * exp(-cc * it);
+                f0 = M * (1.0 + Q2 + qd * (0.4 * cc * it - 1.0));
+                f1 = th * f0 + (qr[0] * c0 + qr[1] * c1 + qr[2] * c2) * M;
+            }
+            v0 = (T)f0;
+            v1 = (T)f1;
+            fr[k] = v0;
+            fr[nvp + k] = v1;
+        }
+        if (mode == 3) continue;
+        acc_moments<double, 3>(acc, w, (double)v0, 0.0, c0, c1, c2, cc);
+        const double h1 = w * (double)v1;
+        ps[0] += h1;
+        ps[1] += h1 * c0;
+        ps[2] += h1 * c1;
+        ps[3] += h1 * c2;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j)
+            if (j < nw) {
+                const double a = xi[0] * wn[j][0] + xi[1] * wn[j][1] + xi[2] * wn[j][2];
+                if (a > 0.0) wj[j] += w * a * (double)v0;
+            }
+    }
+    if (vt == 0 && mode != 2)
+        for (int kp = C.nv + threadIdx.x; kp < nvp; kp += BLOCK) {
+            fr[kp] = (T)0;
+            fr[nvp + kp] = (T)0;
+        }
+    if (mode == 3) return;   // ghost rows carry no sums (block-uniform exit)
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j)
+#pragma unroll
+        for (int ww = 0; ww < MAXW; ++ww) acc[S_WALL + ww] += (j < nw && s_wi[j] == ww) ? wj[j] : 0.0;
+    block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
+    __syncthreads();
+    block_reduce_store<PSUM>(ps, C.psum + ((size_t)slot * C.ntile + vt) * PSUM, red);
+}
+
+// GSIS correction of both VDFs (first eq. updatef): f0 += f_eq(W_new) -
+// f_eq(W_half), f1 += Th_new f_eq(W_new) - Th_half f_eq(W_half), in place,
+// with the partial sums of the corrected rows (relative to the slot's
+// reference velocity)
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restrict__ cvp, int n_kin, int cur)
+{
+    const CaseView &C = *cvp;
+    __shared__ double red[(BLOCK / 64) * NSUM];
+    __shared__ double wn[MAXW][3];
+    __shared__ int s_wi[MAXW], s_nw;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int vt = b / n_kin, t = b - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const FeqRec &Fa = C.feq[2 * (size_t)slot];
+    const FeqRec &Fb = C.feq[2 * (size_t)slot + 1];
+    const double *ur = C.param[slot].u;
+    if (threadIdx.x == 0) {
         int nw = 0;
         for (int e = C.cf_ptr[cell]; e < C.cf_ptr[cell + 1]; ++e)
             if (C.cf_wall[e] >= 0) {
@@ -1632,7 +1765,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
     const int nw = s_nw;
     const int nvp = C.row / 2;
     T *fr = (T *)C.f[cur] + (size_t)slot * C.row;
-    double acc[NSUM], wj[MAXW], ps[4] = {0, 0, 0, 0};
+    double acc[NSUM], wj[MAXW], ps[PSUM] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
 #pragma unroll
@@ -1641,19 +1774,17 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
     for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
         double xi[3], w;
         vnode(C, k, xi, w);
-        const double c0 = xi[0] - u[0], c1 = xi[1] - u[1], c2 = xi[2] - u[2];
+        const double a0 = xi[0] - Fa.u[0], a1 = xi[1] - Fa.u[1], a2 = xi[2] - Fa.u[2];
+        const double b0 = xi[0] - Fb.u[0], b1 = xi[1] - Fb.u[1], b2 = xi[2] - Fb.u[2];
+        const double aa = a0 * a0 + a1 * a1 + a2 * a2, bb = b0 * b0 + b1 * b1 + b2 * b2;
+        const double ma = exp(-aa * Fa.it) * (Fa.fx[0] + Fa.fx[1] * a0 + Fa.fx[2] * a1 + Fa.fx[3] * a2 + Fa.fx[4] * aa);
+        const double mb = exp(-bb * Fb.it) * (Fb.fx[0] + Fb.fx[1] * b0 + Fb.fx[2] * b1 + Fb.fx[3] * b2 + Fb.fx[4] * bb);
+        const T v0 = (T)((double)fr[k] + (ma - mb));
+        const T v1 = (T)((double)fr[nvp + k] + (Fa.Th * ma - Fb.Th * mb));
+        fr[k] = v0;
+        fr[nvp + k] = v1;
+        const double c0 = xi[0] - ur[0], c1 = xi[1] - ur[1], c2 = xi[2] - ur[2];
         const double cc = c0 * c0 + c1 * c1 + c2 * c2;
-        T v0, v1;
-        if (mode == 0) {
-            const double f0 = exp(-cc * it) * (fx[0] + fx[1] * c0 + fx[2] * c1 + fx[3] * c2 + fx[4] * cc);
-            v0 = (T)f0;
-            v1 = (T)(th * f0);
-            fr[k] = v0;
-            fr[nvp + k] = v1;
-        } else {
-            v0 = fr[k];
-            v1 = fr[nvp + k];
-        }
         acc_moments<double, 3>(acc, w, (double)v0, 0.0, c0, c1, c2, cc);
         const double h1 = w * (double)v1;
         ps[0] += h1;
@@ -1671,14 +1802,9 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
     for (int j = 0; j < MAXW; ++j)
 #pragma unroll
         for (int ww = 0; ww < MAXW; ++ww) acc[S_WALL + ww] += (j < nw && s_wi[j] == ww) ? wj[j] : 0.0;
-    if (vt == 0 && mode == 0)
-        for (int kp = C.nv + threadIdx.x; kp < nvp; kp += BLOCK) {
-            fr[kp] = (T)0;
-            fr[nvp + kp] = (T)0;
-        }
     block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
     __syncthreads();
-    block_reduce_store<4>(ps, C.psum + ((size_t)slot * C.ntile + vt) * 4, red);
+    block_reduce_store<PSUM>(ps, C.psum + ((size_t)slot * C.ntile + vt) * PSUM, red);
 }
 
 // the point-Jacobi sweep of both VDFs: one block per (kinetic cell, velocity
@@ -1736,8 +1862,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
                 fnb[l] = fold + (size_t)C.slot_of_cell[oth] * row;
                 fkin[l] = (T)1;
             } else if (oth >= 0) {
+                // the two-VDF Grad-13 rows of the NS neighbour (f0, f1)
                 fnb[l] = (const T *)C.grow + (size_t)C.ghost_slot[oth] * row;
-                fth[l] = (T)(0.25 * C.dr * C.ghost[(size_t)oth * GSIS_NMOM + 4]);
+                fkin[l] = (T)1;
             } else {
                 const int pi = -1 - oth;
                 fnb[l] = (const T *)C.prow + (size_t)pi * row;
@@ -1767,7 +1894,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
     const T bt0 = (T)R.bt[0], bt1 = (T)R.bt[1], bt2 = (T)R.bt[2];
     const T br0 = (T)R.br[0], br1 = (T)R.br[1], br2 = (T)R.br[2];
     const T fx0 = (T)R.fx[0], fx1 = (T)R.fx[1], fx2 = (T)R.fx[2], fx3 = (T)R.fx[3], fx4 = (T)R.fx[4];
-    double acc[NSUM], wacc[NF], ps[4] = {0, 0, 0, 0};
+    double acc[NSUM], wacc[NF], ps[PSUM] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < NSUM; ++i) acc[i] = 0.0;
 #pragma unroll
@@ -1826,7 +1953,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
         acc[S_RES + 1] += r0 * d0;
         acc[S_RES + 2] += r0 * d1;
         acc[S_RES + 3] += r0 * d2;
-        acc[S_RES + 4] += r0 * dcc + 2.0 * wd * (double)(num1 - den * o1);
+        const double r1 = wd * (double)(num1 - den * o1);
+        acc[S_RES + 4] += r0 * dcc + 2.0 * r1;
+        ps[4] += r1;
 #pragma unroll
         for (int l = 0; l < NF; ++l) wacc[l] += wd * (double)(ap[l] * n0v);
     }
@@ -1836,7 +1965,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
         for (int w = 0; w < MAXW; ++w) acc[S_WALL + w] += (fwall[l] == w) ? wacc[l] : 0.0;
     block_reduce_store<NSUM>(acc, C.partial + ((size_t)slot * C.ntile + vt) * NSUM, red);
     __syncthreads();
-    block_reduce_store<4>(ps, C.psum + ((size_t)slot * C.ntile + vt) * 4, red);
+    block_reduce_store<PSUM>(ps, C.psum + ((size_t)slot * C.ntile + vt) * PSUM, red);
 }
 
 hipError_t launch_param_poly(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
@@ -1850,11 +1979,12 @@ hipError_t launch_param_poly(const CaseView *cv, const CaseView &h, int n_kin, h
 hipError_t launch_fill_poly(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
-    if (mode == 0) hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, h.kin_cell, 1);
+    const int32_t *list = (mode == 1) ? h.new_cell : ((mode == 3) ? h.ghost_cell : h.kin_cell);
+    if (mode == 0) hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, list, 1);
     dim3 g(n_items * h.ntile);
     if (h.dtype == GSIS_F32)
-        hipLaunchKernelGGL((k_fill_poly<float>), g, dim3(BLOCK), 0, s, cv, h.kin_cell, n_items, mode, cur);
-    else hipLaunchKernelGGL((k_fill_poly<double>), g, dim3(BLOCK), 0, s, cv, h.kin_cell, n_items, mode, cur);
+        hipLaunchKernelGGL((k_fill_poly<float>), g, dim3(BLOCK), 0, s, cv, list, n_items, mode, cur);
+    else hipLaunchKernelGGL((k_fill_poly<double>), g, dim3(BLOCK), 0, s, cv, list, n_items, mode, cur);
     return hipGetLastError();
 }
 
@@ -2061,6 +2191,12 @@ __global__ __launch_bounds__(BLOCK) void k_correct(const CaseView *__restrict__ 
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
 {
     if (n_kin <= 0) return hipSuccess;
+    if (h.poly) {
+        const dim3 g(n_kin * h.ntile);
+        if (h.dtype == GSIS_F32) hipLaunchKernelGGL((k_correct_poly<float>), g, dim3(BLOCK), 0, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct_poly<double>), g, dim3(BLOCK), 0, s, cv, n_kin, cur);
+        return hipGetLastError();
+    }
     if (h.fast) return launch_correct_fast(cv, h, n_kin, cur, s);
     int NA3 = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
     dim3 g(n_kin * h.ntile);
@@ -2251,7 +2387,7 @@ hipError_t launch_fill_poly(const CaseView *cv, const CaseView &h, int mode, int
 hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
-    if (h.poly && (mode == 0 || mode == 2)) return launch_fill_poly(cv, h, mode, n_items, cur, s);
+    if (h.poly) return launch_fill_poly(cv, h, mode, n_items, cur, s);
     const int32_t *list = (mode == 1) ? h.new_cell : ((mode == 3) ? h.ghost_cell : h.kin_cell);
     if (mode == 0) {
         hipLaunchKernelGGL(k_feqpar, dim3((n_items + 63) / 64), dim3(64), 0, s, cv, n_items, list, 1);

@@ -91,12 +91,14 @@ __device__ __forceinline__ MLoc mb_loc(const MOne &B, int) { return {B.cv, B.W, 
 
 static MOne mone_of(const MBatch &b) { return {b.cv[0], b.W[0], b.hot[0], b.src[0]}; }
 
-void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src)
+void mbatch_add(MBatch &b, const CaseView *cv, const CaseView &h, double *W, const double *hot, const double *src,
+                double *Tr)
 {
     const int j = b.n;
-    if (j == 0) b.bc[0] = b.bf[0] = b.bq[0] = 0, b.nfmax = 0;
+    if (j == 0) b.bc[0] = b.bf[0] = b.bq[0] = 0, b.nfmax = 0, b.poly = h.poly;
     b.cv[j] = cv;
     b.W[j] = W;
+    b.Tr[j] = Tr;
     b.hot[j] = hot;
     b.src[j] = src;
     b.bc[j + 1] = b.bc[j] + (h.n_cells + MBLOCK - 1) / MBLOCK;
@@ -289,6 +291,12 @@ static void launch_lsq_b(const MBatch &b, int nvar, hipStream_t s)
     else launch_lsq_t(b, g, b.nfmax, nvar, s);
 }
 
+
+hipError_t launch_lsq_batch(const MBatch &b, int nvar, hipStream_t s)
+{
+    launch_lsq_b(b, nvar, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, int nvar, hipStream_t s)
 {
@@ -860,6 +868,7 @@ static void macro_steps_t(const BT &bt, const MBatch &b, int n_inner, double cfl
 hipError_t launch_macro_steps_batch(const MBatch &b, int n_inner, double cfl, hipStream_t s)
 {
     if (b.n <= 0) return hipSuccess;
+    if (b.poly) return launch_macro_steps_poly(b, n_inner, cfl, s);
     if (b.n == 1) macro_steps_t(mone_of(b), b, n_inner, cfl, s);
     else macro_steps_t(b, b, n_inner, cfl, s);
     return hipGetLastError();
