@@ -49,15 +49,17 @@ def parse():
     ap.add_argument("--no-fp64-sweep", action="store_true")
     ap.add_argument("--no-point-grid", action="store_true", help="skip the non-tensor velocity-grid sweep leg")
     ap.add_argument("--no-order2", action="store_true", help="skip the second-order sweep leg")
-    ap.add_argument("--no-poly", action="store_true", help="skip the polyatomic-gas sweep leg")
+    ap.add_argument("--no-poly", action="store_true", help="skip the polyatomic-gas (nitrogen) aGSIS leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the Couette, cavity and cylinder legs")
+    ap.add_argument("--poly-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
-    ap.add_argument("--serve-requests", type=int, default=12, help="requests in the serving leg (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving leg (1/s)")
-    ap.add_argument("--serve-max-iter", type=int, default=150)
-    ap.add_argument("--serve-tol", type=float, default=1e-4,
-                    help="served solves stop at this residual (the explicit synthetic solver converges slowly in "
-                         "transitional closed boxes)")
+    ap.add_argument("--serve-requests", type=int, default=60, help="requests per arrival rate (0: skip serving)")
+    ap.add_argument("--serve-rates", default="5,20,80", help="Poisson arrival rates of the serving leg (1/s)")
+    ap.add_argument("--serve-max-iter", type=int, default=300)
+    ap.add_argument("--serve-tol", type=float, default=1e-6, help="served solves stop at this residual (Sec. 4)")
+    ap.add_argument("--serve-fp64-check", type=int, default=16,
+                    help="requests of the middle rate also solved alone by the FP64 per-case path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain streaming kernel over MIB MiB (scale for HBM counters)")
     return ap.parse_args()
@@ -72,6 +74,12 @@ def workload(nv1d):
     import gsis_inputs as gi
     mesh, grid, W = gi.sphere_workload(nv1d, MACH)
     return mesh, grid, W, np.zeros(mesh["n_cells"], np.uint8)
+
+
+def sweep_kernel_name():
+    """The plane sweep kernel the library launches for this workload's 32^3
+    tensor grid: 16-byte rows (k_sweep_v4) unless GSIS_SWEEP_V4=0."""
+    return "k_sweep_fast" if os.environ.get("GSIS_SWEEP_V4", "1") == "0" else "k_sweep_v4"
 
 
 def sweep_source_hash():
@@ -94,14 +102,26 @@ def measured_traffic(n_kin_mean, nv):
     return float(t["bytes_per_point"]) * n_kin_mean * nv
 
 
-def cpu_baseline(mesh, grid, W, flags, seconds):
-    """Oracle (FP64, OpenMP) sweep + moments of a chunk of kinetic cells, with
-    their kinetic neighbours' rows present, repeated for `seconds`."""
+def cpu_model():
+    """The host CPU's model name and logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def _oracle_sample(O, mesh, grid, W, flags, n_cells, seconds):
+    """Repeated oracle sweeps + moments of the first n_cells kinetic cells
+    (their kinetic neighbours' rows present) for `seconds`: (updates/s, text)."""
     import gsis_inputs as gi
-    import oracle
-    O = oracle.Oracle(mesh, grid, KN)
     kin = np.nonzero(flags)[0]
-    chunk = kin[: min(64, len(kin))]
+    chunk = kin[: min(n_cells, len(kin))]
     fc = mesh["face_cells"].reshape(-1, 2)
     inchunk = np.zeros(mesh["n_cells"], bool)
     inchunk[chunk] = True
@@ -122,45 +142,104 @@ def cpu_baseline(mesh, grid, W, flags, seconds):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    nv = O.nv
-    return {"value": reps * len(chunk) * nv / el, "unit": "updates/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": "%d x (FP64 oracle sweep + moments of %d kinetic cells of this workload, "
-                      "%d velocities, kinetic neighbours' rows present) in %.1f s" % (reps, len(chunk), nv, el)}
+    return reps * len(chunk) * O.nv / el, "%d x (sweep + moments of %d cells) in %.1f s" % (reps, len(chunk), el)
 
 
-def serving(g, n, rate, max_iter, tol, seed=7):
-    """Continuous-batching FP32 server on a seeded request stream, against the
-    same requests solved one after another by the plain per-case FP64 path."""
+def _oracle_sweep_ms(O, f, n):
+    """Median of 3 oracle sweeps of every cell (all kinetic), ms."""
+    kin = np.arange(n, dtype=np.int32)
+    ts = []
+    for _ in range(3):
+        t = time.perf_counter()
+        O.sweep(f, kin, kin)
+        ts.append(time.perf_counter() - t)
+    return 1e3 * float(np.median(ts))
+
+
+def cpu_baseline(mesh, grid, W, flags, seconds):
+    """The oracle (FP64, OpenMP) on this host: a bounded sample of the sphere
+    workload with every thread and with one, one oracle sweep of C1 and C2
+    (every cell kinetic), and the time of a C1 GSIS outer iteration."""
+    import gsis_inputs as gi
+    import oracle
+    model, ncpu = cpu_model()
+    O = oracle.Oracle(mesh, grid, KN)
+    nt = oracle.threads()
+    v, txt = _oracle_sample(O, mesh, grid, W, flags, 256, seconds)
+    oracle.set_threads(1)
+    v1, txt1 = _oracle_sample(O, mesh, grid, W, flags, 16, max(2.0, seconds / 4))
+    oracle.set_threads(nt)
+    out = {"value": v, "unit": "updates/s", "cores": nt, "kind": "oracle",
+           "sample": "FP64 oracle on the sphere workload (%d velocities, the kinetic region after the NS "
+                     "start): %s" % (O.nv, txt),
+           "cpu_model": model, "logical_cpus": ncpu,
+           "one_core": {"value": v1, "unit": "updates/s", "sample": txt1}}
+    # C1 and C2: one sweep of every cell
+    m1 = gi.couette_1d(64, 0.1)
+    g1 = gi.velocity_grid(3, 16, 5.0)
+    O1 = oracle.Oracle(m1, g1, 0.1)
+    W1 = gi.couette_initial_W(64, seed=0)
+    f1 = np.stack([O1.feq(w) for w in W1])
+    ms1 = _oracle_sweep_ms(O1, f1, 64)
+    m2 = gi.quad_cavity_2d(64, 64, 0.1)
+    g2 = gi.velocity_grid(2, 32, 6.0, "stretched")
+    O2 = oracle.Oracle(m2, g2, 0.1)
+    f2 = gi.gaussian_rows(g2, gi.uniform_W(m2["n_cells"]), seed=4, dtype=np.float64)
+    ms2 = _oracle_sweep_ms(O2, f2, m2["n_cells"])
+    S = oracle.SteadySolver(O1, mode="gsis", n_inner=400, cfl=0.5)
+    S.set_state(W1)
+    t = time.perf_counter()
+    for _ in range(10):
+        S.step()
+    c1 = (time.perf_counter() - t) / 10
+    out["configs"] = {"C1_sweep_ms": ms1, "C1_updates_per_s": 64 * O1.nv / (ms1 / 1e3),
+                      "C2_sweep_ms": ms2, "C2_updates_per_s": m2["n_cells"] * O2.nv / (ms2 / 1e3),
+                      "C1_gsis_ms_per_iteration": 1e3 * c1,
+                      "note": "C1 GSIS: 10 oracle iterations timed (the GPU leg gives the iterations to 1e-8); "
+                              "full C2-C4 solves are not timed on the CPU (minutes to hours)"}
+    return out
+
+
+def serving(g, n, rates, max_iter, tol, n_check, seed=7):
+    """Continuous-batching FP32 server on seeded request streams, one per
+    Poisson arrival rate (the same seed: the same requests, arriving faster),
+    and `n_check` requests of the middle rate solved one after another by the
+    plain per-case FP64 path (the same steps and stopping rule)."""
     import gsis_inputs as gi
     import paper_2501_02245_amd.serve as sv
-    reqs = [sv.Request.from_spec(d) for d in gi.serving_requests(n, rate, seed=seed)]
-    budget = 64 << 30
-    srv = sv.Server(budget, dtype=g.F32, max_iter=max_iter, tol=tol)
-    t = time.perf_counter()
-    res = srv.run(reqs, log=log)
-    wall = time.perf_counter() - t
-    out = sv.summarize(res, wall)
-    out.update({"wall_s": wall, "peak_active": srv.peak_active, "peak_bytes": srv.peak_bytes,
-                "requeued": srv.requeued, "dtype": "f32", "tol": srv.tol, "max_iter": max_iter,
-                "mix": "seed %d: %d requests, Poisson rate %g/s, 1D Couette/Fourier 32-512 cells 16^3/32^3, "
-                       "2D cylinder 2k-20k cells 32^2/64^2, Kn log-uniform [1e-3, 1], Mach [1, 8], Kn_ref 0.01"
-                       % (seed, n, rate)})
-    # the plain per-case FP64 path on the same requests, one at a time
-    t = time.perf_counter()
-    base, diff = [], []
-    for r, rr in zip(reqs, res):
-        it, eps, nk, W, status = sv.solve_alone(r, g.F64, max_iter=max_iter, tol=tol)
-        base.append(status)
-        if status == "ok" and rr.status == "ok":
-            scale = np.maximum(np.abs(W).max(axis=0), 1e-3)
-            diff.append(float((np.abs(W - rr.W).max(axis=0) / scale).max()))
-        log("fp64 alone: request %d %s after %d iterations" % (r.rid, status, it))
-    wall64 = time.perf_counter() - t
-    n64 = sum(1 for b in base if b == "ok")
-    out["fp64_per_case"] = {"solved": n64, "wall_s": wall64, "solves_per_s": n64 / wall64}
-    out["speedup_vs_fp64_per_case"] = out["solves_per_s"] / (n64 / wall64) if n64 else None
-    out["max_field_diff_vs_fp64"] = max(diff) if diff else None
+    out = {"dtype": "f32", "tol": tol, "max_iter": max_iter,
+           "mix": "seed %d: %d requests per rate, 1D Couette/Fourier 32-512 cells 16^3/32^3 (GSIS), 2D cylinder "
+                  "2k-20k cells 32^2/64^2 (aGSIS from the NS start), Kn log-uniform [1e-3, 1], Mach [1, 8], "
+                  "Kn_ref 0.01" % (seed, n), "rates": []}
+    mid = sorted(rates)[len(rates) // 2]
+    for rate in rates:
+        reqs = [sv.Request.from_spec(d) for d in gi.serving_requests(n, rate, seed=seed)]
+        srv = sv.Server(64 << 30, dtype=g.F32, max_iter=max_iter, tol=tol)
+        t = time.perf_counter()
+        res = srv.run(reqs, log=log)
+        wall = time.perf_counter() - t
+        r = sv.summarize(res, wall)
+        r.update({"rate_per_s": rate, "wall_s": wall, "peak_active": srv.peak_active,
+                  "peak_bytes": srv.peak_bytes, "requeued": srv.requeued})
+        log("serving rate %g: %d of %d solved in %.1f s, p50 %.3f s p99 %.3f s" % (
+            rate, r["solved"], r["requests"], wall, r["p50_s"], r["p99_s"]))
+        if rate == mid and n_check > 0:
+            t = time.perf_counter()
+            n64, diff = 0, []
+            for q, rr in list(zip(reqs, res))[:n_check]:
+                it, eps, nk, W, status = sv.solve_alone(q, g.F64, max_iter=max_iter, tol=tol)
+                if status == "ok":
+                    n64 += 1
+                if status == "ok" and rr.status == "ok":
+                    scale = np.maximum(np.abs(W).max(axis=0), 1e-3)
+                    diff.append(float((np.abs(W - rr.W).max(axis=0) / scale).max()))
+                log("fp64 alone: request %d %s after %d iterations" % (q.rid, status, it))
+            wall64 = time.perf_counter() - t
+            r["fp64_per_case"] = {"requests": n_check, "solved": n64, "wall_s": wall64,
+                                  "solves_per_s": n64 / wall64 if wall64 > 0 else 0.0}
+            r["served_fields_vs_fp64_max"] = max(diff) if diff else None
+            r["served_fields_vs_fp64_compared"] = len(diff)
+        out["rates"].append(r)
     return out
 
 
@@ -236,27 +315,138 @@ def order2_sweep(g, torch, M, grid, W, flags, dim, steps=3):
     return out
 
 
-def poly_sweep(g, torch, M, grid, W, flags, steps=3):
-    """The polyatomic gas (two VDFs, nitrogen parameters: d_r 2, Z_r 2.667,
-    omega 0.74, the A matrix of the thermal relaxation rates) on the same
-    region and grid, FP32: sweeps of (f0, f1) with per-node Gaussians at T_t
-    and T.  Algorithmic bytes per cell-velocity: 2 x (4 read + 4 write)."""
-    cap = int(flags.sum()) + 64
+def _timed_steps(torch, case, params, steps, warmup=1):
+    """warmup + timed outer iterations; returns (ms per step, mean sweep ms,
+    mean kinetic cells, last eps)."""
+    for _ in range(warmup):
+        case.step(params)
+    torch.cuda.synchronize()
+    kin, sw = [], []
+    e = None
+    t = time.perf_counter()
+    for _ in range(steps):
+        kin.append(case.n_kin)
+        e = case.step(params)
+        sw.append(case.last_sweep_ms())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    return 1e3 * dt / steps, float(np.mean(sw)), float(np.mean(kin)), e
+
+
+def c1_couette(g, torch):
+    """C1: 1D planar Couette (64 cells on [0,1], walls at T 1 moving -+0.1,
+    16^3 uniform velocities on [-5,5], Kn 0.1, hard spheres, density
+    perturbation 1e-3 N(0,1) from seed 0), FP64, full-kinetic: the plain
+    iteration (DVM) and GSIS, each to eps < 1e-8."""
+    import gsis_inputs as gi
+    m = gi.couette_1d(64, 0.1)
+    grid = gi.velocity_grid(3, 16, 5.0)
+    W = gi.couette_initial_W(64, seed=0)
+    out = {}
+    for name, mode in (("dvm", g.MODE_DVM), ("gsis", g.MODE_GSIS)):
+        case = g.Case(g.Mesh(m), grid, 0.1, dtype=g.F64)
+        case.set_state(W)
+        p = g.SolveParams(mode=mode, tol=1e-8, max_iter=20000, n_macro_inner=400, cfl=0.5)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it, eps, _ = case.solve(p, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        sweep_ms = case.last_sweep_ms()
+        out[name] = {"iterations": int(it), "eps": [float(x) for x in eps], "converged": bool(max(eps) < 1e-8),
+                     "solve_s": dt, "ms_per_iteration": 1e3 * dt / max(it, 1), "sweep_ms": sweep_ms,
+                     "sweep_updates_per_s": 64 * case.nv / (sweep_ms / 1e3)}
+        case.close()
+    return out
+
+
+def c2_cavity(g, torch):
+    """C2: lid-driven cavity (64x64 quads as an unstructured mesh, lid +0.1,
+    walls at T 1), reduced 2D distributions on a 32^2 stretched grid on
+    [-6,6]^2, uniform start, FP32, full-kinetic GSIS at Kn 0.01, 0.1 and 1:
+    per-sweep time (the plane kernel) and time per GSIS outer iteration."""
+    import gsis_inputs as gi
+    m = gi.quad_cavity_2d(64, 64, 0.1)
+    grid = gi.velocity_grid(2, 32, 6.0, "stretched")
+    W = gi.uniform_W(m["n_cells"])
+    M = g.Mesh(m)
+    out = {}
+    for Kn in (0.01, 0.1, 1.0):
+        case = g.Case(M, grid, Kn, dtype=g.F32)
+        case.set_state(W)
+        case.sweep(1)
+        ms = []
+        for _ in range(5):
+            case.sweep(1)
+            ms.append(case.last_sweep_ms())
+        case.set_state(W)
+        p = g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=400, cfl=0.5)
+        step_ms, _, nk, e = _timed_steps(torch, case, p, 5)
+        kms = float(np.median(ms))
+        pts = nk * case.nv * 2
+        out["Kn=%g" % Kn] = {"sweep_ms": kms, "sweep_updates_per_s": nk * case.nv / (kms / 1e3),
+                             "achieved_gbs": 8.0 * pts / (kms / 1e3) / 1e9, "ms_per_gsis_iteration": step_ms,
+                             "eps_after_6": [float(x) for x in e], "layout": list(case.sweep_layout())}
+        case.close()
+    return out
+
+
+def c3_cylinder(g, torch, steps=5):
+    """C3: Mach-5 flow past a unit cylinder (seeded Delaunay, ~20k
+    triangles), reduced 2D distributions on a 64^2 stretched grid on
+    [-15,15]^2, Kn 0.01, aGSIS with Kn_ref 0.01 and two forced wall layers
+    from the NS start, FP32: time per outer iteration, per sweep, kinetic
+    cells."""
+    import gsis_inputs as gi
+    u = MACH * np.sqrt(5.0 / 6.0)
+    m = gi.cylinder_tri_2d(free=(1.0, (u, 0.0, 0.0), 1.0))
+    grid = gi.velocity_grid(2, 64, 15.0, "stretched")
+    W = gi.hypersonic_field(m)
+    W[:, 3] = 0.0
+    n = m["n_cells"]
+    case = g.Case(g.Mesh(m), grid, 0.01, dtype=g.F32, capacity=int(0.6 * n))
+    case.set_state(W, flags=np.zeros(n, np.uint8))
+    t = time.perf_counter()
+    case.solve(g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=KN_REF, tol=1e-6, max_iter=0, n_macro_inner=400, cfl=0.5,
+                             force_wall_layers=2, ns_init=1, ns_init_max_chunks=50))
+    torch.cuda.synchronize()
+    ns_s = time.perf_counter() - t
+    p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=KN_REF, n_macro_inner=400, cfl=0.5, region_update_every=1,
+                      force_wall_layers=2)
+    step_ms, kms, nk, e = _timed_steps(torch, case, p, steps)
+    pts = nk * case.nv * 2
+    out = {"cells": n, "velocities": case.nv, "ns_start_s": ns_s, "kinetic_cells_mean": nk,
+           "kinetic_fraction": nk / n, "ms_per_step": step_ms, "sweep_ms": kms,
+           "sweep_updates_per_s": nk * case.nv / (kms / 1e3), "achieved_gbs": 8.0 * pts / (kms / 1e3) / 1e9,
+           "eps_last": [float(x) for x in e], "layout": list(case.sweep_layout())}
+    case.close()
+    return out
+
+
+def poly_agsis(g, torch, M, grid, W0, cap, steps):
+    """The paper's own gas on the sphere workload: nitrogen as a two-VDF gas
+    (d_r 2, Z_r 2.667, omega 0.74, A = (0.786, -0.201, -0.059, 0.842)), FP32,
+    aGSIS from the NS start (synthetic equations with the internal energy):
+    time per outer iteration, per sweep of (f0, f1) (kernel k_sweep_poly,
+    algorithmic bytes per cell-velocity 2 x (4 read + 4 write)), kinetic
+    cells."""
     case = g.Case(M, grid, KN, omega=0.74, Pr=0.786, dtype=g.F32, capacity=cap,
                   dr=2.0, Zr=2.667, A=(0.786, -0.201, -0.059, 0.842))
-    case.set_state(W, flags=flags)
-    case.sweep(1)
+    case.set_state(W0, flags=np.zeros(M.n_cells, np.uint8))
+    t = time.perf_counter()
+    case.solve(g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=KN_REF, tol=1e-6, max_iter=0, n_macro_inner=400, cfl=0.5,
+                             force_wall_layers=2, ns_init=1, ns_init_max_chunks=100))
     torch.cuda.synchronize()
-    ms = []
-    for _ in range(steps):
-        case.sweep(1)
-        ms.append(case.last_sweep_ms())
-    torch.cuda.synchronize()
-    n, nv = case.n_kin, case.nv
-    kms = float(np.mean(ms))
-    out = {"kinetic_cells": n, "velocities": nv, "kernel_ms": kms, "updates_per_s": n * nv / (kms / 1e3),
-           "bytes_per_update": 16.0, "achieved_gbs": 16.0 * n * nv / (kms / 1e3) / 1e9,
-           "frac": 16.0 * n * nv / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+    ns_s = time.perf_counter() - t
+    p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=KN_REF, n_macro_inner=400, cfl=0.5, region_update_every=1,
+                      force_wall_layers=2)
+    step_ms, kms, nk, e = _timed_steps(torch, case, p, steps)
+    nv = case.nv
+    gbs = 16.0 * nk * nv / (kms / 1e3) / 1e9
+    out = {"kinetic_cells_mean": nk, "velocities": nv, "ns_start_s": ns_s, "ms_per_step": step_ms,
+           "sweep_ms": kms, "sweep_updates_per_s": nk * nv / (kms / 1e3), "bytes_per_update": 16.0,
+           "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS, "kernel": "k_sweep_poly",
+           "eps_last": [float(x) for x in e], "limiters": case.limiter_stats(),
            "gas": "N2: d_r 2, Z_r 2.667, omega 0.74, A (0.786, -0.201, -0.059, 0.842)"}
     case.close()
     return out
@@ -319,6 +509,7 @@ def main():
 
     t0 = time.time()
     mesh, grid, W, flags = workload(a.nv1d)
+    W_start = W.copy()
     n_cells = mesh["n_cells"]
     dtype = g.F32 if a.dtype == "f32" else g.F64
     cap = min(n_cells, int(a.capacity * n_cells))
@@ -395,8 +586,17 @@ def main():
         log("second-order sweep", order2)
     poly = None
     if not a.no_poly and not a.sweep_only and dtype == g.F32:
-        poly = poly_sweep(g, torch, M, grid, W, flags)
-        log("polyatomic sweep", poly)
+        poly = poly_agsis(g, torch, M, grid, W_start, cap, a.poly_steps)
+        log("nitrogen aGSIS", poly)
+    configs = None
+    if not a.no_configs and not a.sweep_only:
+        configs = {}
+        configs["C1_couette_fp64"] = c1_couette(g, torch)
+        log("C1", configs["C1_couette_fp64"])
+        configs["C2_cavity_fp32"] = c2_cavity(g, torch)
+        log("C2", configs["C2_cavity_fp32"])
+        configs["C3_cylinder_fp32"] = c3_cylinder(g, torch)
+        log("C3", configs["C3_cylinder_fp32"])
 
     out = {
         "metric": "kinetic cell-velocity updates/s",
@@ -417,20 +617,22 @@ def main():
                    "start": "NS solve to eps<1e-6, then Kn_Gll flagging", "n_macro_inner": a.n_inner,
                    "sweep_only": bool(a.sweep_only)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_sweep_fast",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": sweep_kernel_name(),
                      "kernel_ms": 1e3 * sweep_s},
         "sweep_updates_per_s": n_kin_mean * nv / sweep_s,
         "fp64_sweep": fp64,
         "point_grid_sweep": points,
         "order2_sweep": order2,
-        "poly_sweep": poly,
+        "nitrogen_agsis": poly,
+        "configs": configs,
         "surface": surface,
         "synthetic_solve": synthetic,
         "setup_s": setup_s,
     }
     if a.serve_requests > 0 and not a.sweep_only:
         t1 = time.time()
-        out["serving"] = serving(g, a.serve_requests, a.serve_rate, a.serve_max_iter, a.serve_tol)
+        rates = [float(x) for x in a.serve_rates.split(",") if x]
+        out["serving"] = serving(g, a.serve_requests, rates, a.serve_max_iter, a.serve_tol, a.serve_fp64_check)
         log("serving leg %.1f s" % (time.time() - t1))
     if not a.no_cpu_baseline:
         t1 = time.time()

@@ -586,6 +586,11 @@ def threads():
     return int(lib().oc_threads())
 
 
+def set_threads(n):
+    """Threads of the oracle's parallel loops from now on (n >= 1)."""
+    lib().oc_set_threads(int(n))
+
+
 def regions_from_flags(flags, old_slot_of_cell=None):
     """Compacted kinetic list (ascending cell id) and slot assignment.
 

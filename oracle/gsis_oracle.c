@@ -36,6 +36,17 @@ int32_t oc_threads(void)
 #endif
 }
 
+/* set the threads of the oracle's OpenMP loops (timing on one core); n <= 0
+ * leaves the count unchanged */
+void oc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads((int)n);
+#else
+    (void)n;
+#endif
+}
+
 /* velocity node k -> (xi, weight); xi_z = 0 for the reduced grid */
 static void node(const oc_grid *g, int32_t k, double *xi, double *w)
 {

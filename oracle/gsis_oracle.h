@@ -74,6 +74,7 @@ typedef struct {
 int32_t oc_nv(const oc_grid *g);
 int32_t oc_nfun(const oc_grid *g);
 int32_t oc_threads(void);
+void oc_set_threads(int32_t n);
 
 /* Moments of one cell's distribution(s) f[nfun][nv] -> mom[OC_NMOM]. */
 void oc_moments(const oc_grid *g, const double *f, double *mom);
