@@ -1629,6 +1629,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
     __shared__ double red[(BLOCK / 64) * NSUM];
     __shared__ double wn[MAXW][3];
     __shared__ int s_wi[MAXW], s_nw;
+    __shared__ double t_c[3 * MAXA], t_e[3 * MAXA], t_x[3 * MAXA], t_w[3 * MAXA];
     const int vt = blockIdx.x / n_items, t = blockIdx.x - vt * n_items;
     const int cell = list[t];
     const int slot = (mode == 3) ? C.ghost_slot[cell] : C.slot_of_cell[cell];
@@ -1668,6 +1669,19 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
                 }
         s_nw = nw;
     }
+    // per axis node j (axes concatenated): the offset c = x - u, the 1D
+    // Gaussian factor exp(-c^2/T), the node and its weight (a node's Gaussian
+    // is the product of its three factors)
+    const int n0 = C.n[0], n1 = C.n[1], n2 = C.n[2], NA3 = n0 + n1 + n2;
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        const int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        const int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        const double x = C.xv[d * MAXA + jj], c = x - u[d];
+        t_c[j] = c;
+        t_e[j] = exp(-c * c * it);
+        t_x[j] = x;
+        t_w[j] = C.wv[d * MAXA + jj];
+    }
     __syncthreads();
     const int nw = s_nw;
     const int nvp = C.row / 2;
@@ -1678,11 +1692,15 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
 #pragma unroll
     for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
     const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
+    VIdx vi = vidx_init<3>(k0 + threadIdx.x, n1, n2);
     for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
-        double xi[3], w;
-        vnode(C, k, xi, w);
-        const double c0 = xi[0] - u[0], c1 = xi[1] - u[1], c2 = xi[2] - u[2];
+        const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
+        vidx_step<3>(vi, n1, n2);
+        const double xi[3] = {t_x[jx], t_x[jy], t_x[jz]};
+        const double w = t_w[jx] * t_w[jy] * t_w[jz];
+        const double c0 = t_c[jx], c1 = t_c[jy], c2 = t_c[jz];
         const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+        const double E = t_e[jx] * t_e[jy] * t_e[jz];
         T v0, v1;
         if (mode == 2) {
             v0 = fr[k];
@@ -1690,13 +1708,13 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
         } else {
             double f0, f1;
             if (mode == 0) {
-                f0 = exp(-cc * it) * (fx[0] + fx[1] * c0 + fx[2] * c1 + fx[3] * c2 + fx[4] * cc);
+                f0 = E * (fx[0] + fx[1] * c0 + fx[2] * c1 + fx[3] * c2 + fx[4] * cc);
                 f1 = th * f0;
             } else {
                 const double Q2 = sg[0] * c0 * c0 + sg[1] * c1 * c1 + sg[2] * c2 * c2 +
                                   2.0 * (sg[3] * c0 * c1 + sg[4] * c0 * c2 + sg[5] * c1 * c2);
                 const double qd = qg[0] * c0 + qg[1] * c1 + qg[2] * c2;
-                const double M = A * exp(-cc * it);
+                const double M = A * E;
                 f0 = M * (1.0 + Q2 + qd * (0.4 * cc * it - 1.0));
                 f1 = th * f0 + (qr[0] * c0 + qr[1] * c1 + qr[2] * c2) * M;
             }
@@ -1737,7 +1755,10 @@ __global__ __launch_bounds__(BLOCK) void k_fill_poly(const CaseView *__restrict_
 // GSIS correction of both VDFs (first eq. updatef): f0 += f_eq(W_new) -
 // f_eq(W_half), f1 += Th_new f_eq(W_new) - Th_half f_eq(W_half), in place,
 // with the partial sums of the corrected rows (relative to the slot's
-// reference velocity)
+// reference velocity).  Tensor grid: both Gaussians factorise per axis, so the
+// block forms FP64 tables of the offsets and 1D Gaussian factors of the two
+// Maxwellians (and the offsets of the reference frame) and a node takes two
+// products per Maxwellian, no exp.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
@@ -1745,6 +1766,11 @@ __global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restri
     __shared__ double red[(BLOCK / 64) * NSUM];
     __shared__ double wn[MAXW][3];
     __shared__ int s_wi[MAXW], s_nw;
+    // per axis node j (axes concatenated): offsets and Gaussian factors of
+    // f_eq(W_new) (a) and f_eq(W_half) (b), the reference-frame offset, the
+    // node and its weight
+    __shared__ double t_ca[3 * MAXA], t_ea[3 * MAXA], t_cb[3 * MAXA], t_eb[3 * MAXA], t_cr[3 * MAXA],
+        t_x[3 * MAXA], t_w[3 * MAXA];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int vt = b / n_kin, t = b - vt * n_kin;
     const int cell = C.kin_cell[t];
@@ -1752,6 +1778,7 @@ __global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restri
     const FeqRec &Fa = C.feq[2 * (size_t)slot];
     const FeqRec &Fb = C.feq[2 * (size_t)slot + 1];
     const double *ur = C.param[slot].u;
+    const int n0 = C.n[0], n1 = C.n[1], n2 = C.n[2], NA3 = n0 + n1 + n2;
     if (threadIdx.x == 0) {
         int nw = 0;
         for (int e = C.cf_ptr[cell]; e < C.cf_ptr[cell + 1]; ++e)
@@ -1760,6 +1787,19 @@ __global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restri
                 s_wi[nw++] = C.cf_wall[e];
             }
         s_nw = nw;
+    }
+    for (int j = threadIdx.x; j < NA3; j += BLOCK) {
+        const int d = (j < n0) ? 0 : ((j < n0 + n1) ? 1 : 2);
+        const int jj = j - ((d == 0) ? 0 : ((d == 1) ? n0 : n0 + n1));
+        const double x = C.xv[d * MAXA + jj];
+        const double ca = x - Fa.u[d], cb = x - Fb.u[d];
+        t_ca[j] = ca;
+        t_cb[j] = cb;
+        t_ea[j] = exp(-ca * ca * Fa.it);
+        t_eb[j] = exp(-cb * cb * Fb.it);
+        t_cr[j] = x - ur[d];
+        t_x[j] = x;
+        t_w[j] = C.wv[d * MAXA + jj];
     }
     __syncthreads();
     const int nw = s_nw;
@@ -1771,19 +1811,23 @@ __global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restri
 #pragma unroll
     for (int j = 0; j < MAXW; ++j) wj[j] = 0.0;
     const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
+    VIdx vi = vidx_init<3>(k0 + threadIdx.x, n1, n2);
     for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
-        double xi[3], w;
-        vnode(C, k, xi, w);
-        const double a0 = xi[0] - Fa.u[0], a1 = xi[1] - Fa.u[1], a2 = xi[2] - Fa.u[2];
-        const double b0 = xi[0] - Fb.u[0], b1 = xi[1] - Fb.u[1], b2 = xi[2] - Fb.u[2];
+        const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
+        vidx_step<3>(vi, n1, n2);
+        const double a0 = t_ca[jx], a1 = t_ca[jy], a2 = t_ca[jz];
+        const double b0 = t_cb[jx], b1 = t_cb[jy], b2 = t_cb[jz];
         const double aa = a0 * a0 + a1 * a1 + a2 * a2, bb = b0 * b0 + b1 * b1 + b2 * b2;
-        const double ma = exp(-aa * Fa.it) * (Fa.fx[0] + Fa.fx[1] * a0 + Fa.fx[2] * a1 + Fa.fx[3] * a2 + Fa.fx[4] * aa);
-        const double mb = exp(-bb * Fb.it) * (Fb.fx[0] + Fb.fx[1] * b0 + Fb.fx[2] * b1 + Fb.fx[3] * b2 + Fb.fx[4] * bb);
+        const double ma = (t_ea[jx] * t_ea[jy] * t_ea[jz]) *
+                          (Fa.fx[0] + Fa.fx[1] * a0 + Fa.fx[2] * a1 + Fa.fx[3] * a2 + Fa.fx[4] * aa);
+        const double mb = (t_eb[jx] * t_eb[jy] * t_eb[jz]) *
+                          (Fb.fx[0] + Fb.fx[1] * b0 + Fb.fx[2] * b1 + Fb.fx[3] * b2 + Fb.fx[4] * bb);
         const T v0 = (T)((double)fr[k] + (ma - mb));
         const T v1 = (T)((double)fr[nvp + k] + (Fa.Th * ma - Fb.Th * mb));
         fr[k] = v0;
         fr[nvp + k] = v1;
-        const double c0 = xi[0] - ur[0], c1 = xi[1] - ur[1], c2 = xi[2] - ur[2];
+        const double w = t_w[jx] * t_w[jy] * t_w[jz];
+        const double c0 = t_cr[jx], c1 = t_cr[jy], c2 = t_cr[jz];
         const double cc = c0 * c0 + c1 * c1 + c2 * c2;
         acc_moments<double, 3>(acc, w, (double)v0, 0.0, c0, c1, c2, cc);
         const double h1 = w * (double)v1;
@@ -1794,7 +1838,7 @@ __global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restri
 #pragma unroll
         for (int j = 0; j < MAXW; ++j)
             if (j < nw) {
-                const double a = xi[0] * wn[j][0] + xi[1] * wn[j][1] + xi[2] * wn[j][2];
+                const double a = t_x[jx] * wn[j][0] + t_x[jy] * wn[j][1] + t_x[jz] * wn[j][2];
                 if (a > 0.0) wj[j] += w * a * (double)v0;
             }
     }
