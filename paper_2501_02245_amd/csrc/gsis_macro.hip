@@ -120,14 +120,9 @@ __device__ __forceinline__ double *grad_row(const CaseView &C, int i, int v)
 // built with the mesh: grad_v = sum_e c_e (phi_e - phi_i); the density uses
 // the coefficients without wall faces.  Variables: 0..2 u, 3 T [, 4 rho, 5 |u|].
 // NF bounds the faces per cell: all loads of a cell are issued first.
-template <int NV, int NF, class BT>
-__global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
+template <int NV, int NF>
+__device__ __forceinline__ void lsq_cell(const CaseView &C, const double *__restrict__ W, int i)
 {
-    const MLoc ML = mb_loc(B, PK_CELL);
-    const CaseView &C = *ML.cv;
-    const double *__restrict__ W = ML.W;
-    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
-    if (i >= C.n_cells) return;
     const size_t nnz = (size_t)C.nnz;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
     int oth[NF];
@@ -174,6 +169,15 @@ __global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
         go[1] = g1;
         go[2] = g2;
     }
+}
+
+template <int NV, int NF, class BT>
+__global__ __launch_bounds__(MBLOCK) void k_lsq(BT B)
+{
+    const MLoc ML = mb_loc(B, PK_CELL);
+    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
+    if (i >= ML.cv->n_cells) return;
+    lsq_cell<NV, NF>(*ML.cv, ML.W, i);
 }
 
 // The same gradients with one lane per face: G lanes (G >= the cell's faces)
@@ -455,14 +459,8 @@ __device__ void half_flux(const double *P, const double *n, double sgn, double *
 // interior face flux only through their face means projected on the normal:
 // hface = (0.5 (sigma_L + sigma_R).n, 0.5 (q_L + q_R).n), formed once per solve
 // (zero on boundary faces and without high-order terms).
-template <class BT>
-__global__ __launch_bounds__(MBLOCK_F) void k_hot_face(BT B)
+__device__ __forceinline__ void hot_face_one(const CaseView &C, const double *__restrict__ hot, int f)
 {
-    const MLoc ML = mb_loc(B, PK_FACE);
-    const CaseView &C = *ML.cv;
-    const double *__restrict__ hot = ML.hot;
-    const int f = (mblk() - ML.base) * MBLOCK_F + (int)threadIdx.x;
-    if (f >= C.n_faces) return;
     const int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
     double o[4] = {0.0, 0.0, 0.0, 0.0};
     if (Rc >= 0 && hot) {
@@ -481,13 +479,16 @@ __global__ __launch_bounds__(MBLOCK_F) void k_hot_face(BT B)
 }
 
 template <class BT>
-__global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
+__global__ __launch_bounds__(MBLOCK_F) void k_hot_face(BT B)
 {
     const MLoc ML = mb_loc(B, PK_FACE);
-    const CaseView &C = *ML.cv;
-    const double *__restrict__ W = ML.W;
     const int f = (mblk() - ML.base) * MBLOCK_F + (int)threadIdx.x;
-    if (f >= C.n_faces) return;
+    if (f >= ML.cv->n_faces) return;
+    hot_face_one(*ML.cv, ML.hot, f);
+}
+
+__device__ __forceinline__ void face_flux_one(const CaseView &C, const double *__restrict__ W, int f)
+{
     int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
     const double *n = C.face_normal + 3 * (size_t)f;
     const double *PL = W + 5 * (size_t)L;
@@ -553,6 +554,15 @@ __global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
         F[4] += sn[0] * ps[1] + sn[1] * ps[2] + sn[2] * ps[3] + q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
     }
     for (int c = 0; c < 5; ++c) C.fflux[5 * (size_t)f + c] = F[c];
+}
+
+template <class BT>
+__global__ __launch_bounds__(MBLOCK_F) void k_face_flux(BT B)
+{
+    const MLoc ML = mb_loc(B, PK_FACE);
+    const int f = (mblk() - ML.base) * MBLOCK_F + (int)threadIdx.x;
+    if (f >= ML.cv->n_faces) return;
+    face_flux_one(*ML.cv, ML.W, f);
 }
 
 // per-cell flux balance R_i = -sum_f (+-F_f) S_f (deterministic order over the cell's faces)
@@ -626,20 +636,23 @@ __device__ double cell_D(const CaseView &C, int i, const double *Wi)
     return C.cell_volume[i] * un + a * sS[0] + 2.0 * nu * sS[1];
 }
 
-template <class BT>
-__global__ __launch_bounds__(MBLOCK) void k_cons(BT B)
+__device__ __forceinline__ void cons_cell(const CaseView &C, const double *__restrict__ W, int i)
 {
-    const MLoc ML = mb_loc(B, PK_CELL);
-    const CaseView &C = *ML.cv;
-    const double *__restrict__ W = ML.W;
-    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
-    if (i >= C.n_cells) return;
     const double *P = W + 5 * (size_t)i;
     double *U = C.U + 5 * (size_t)i;
     double u2 = P[1] * P[1] + P[2] * P[2] + P[3] * P[3];
     U[0] = P[0];
     for (int d = 0; d < 3; ++d) U[1 + d] = P[0] * P[1 + d];
     U[4] = P[0] * u2 + 1.5 * P[0] * P[4];
+}
+
+template <class BT>
+__global__ __launch_bounds__(MBLOCK) void k_cons(BT B)
+{
+    const MLoc ML = mb_loc(B, PK_CELL);
+    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
+    if (i >= ML.cv->n_cells) return;
+    cons_cell(*ML.cv, ML.W, i);
 }
 
 // dloc_i = V_i / D_i, then a two-level min reduction into red[0]
@@ -685,15 +698,10 @@ __global__ __launch_bounds__(256) void k_min_final(MBatch B)
 // U_i += k_i (R_i + V_i src_i), k_i = cfl / D_i (local) or |cfl| min V/D / V_i
 // (global), halved while the new state is not positive; W = prim(U).  NF
 // bounds the faces per cell: the face data of a cell is loaded first.
-template <int NF, class BT>
-__global__ __launch_bounds__(MBLOCK) void k_update(BT B, double cfl)
+template <int NF>
+__device__ __forceinline__ void update_cell(const CaseView &C, double *__restrict__ W, const double *__restrict__ src,
+                                            int i, double cfl)
 {
-    const MLoc ML = mb_loc(B, PK_CELL);
-    const CaseView &C = *ML.cv;
-    double *__restrict__ W = ML.W;
-    const double *__restrict__ src = ML.src;
-    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
-    if (i >= C.n_cells) return;
     double *Wi = W + 5 * (size_t)i;
     const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
     int fc[NF];
@@ -756,6 +764,15 @@ __global__ __launch_bounds__(MBLOCK) void k_update(BT B, double cfl)
         }
     }
     if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4])) atomicOr(C.status, 1);
+}
+
+template <int NF, class BT>
+__global__ __launch_bounds__(MBLOCK) void k_update(BT B, double cfl)
+{
+    const MLoc ML = mb_loc(B, PK_CELL);
+    const int i = (mblk() - ML.base) * MBLOCK + (int)threadIdx.x;
+    if (i >= ML.cv->n_cells) return;
+    update_cell<NF>(*ML.cv, ML.W, ML.src, i, cfl);
 }
 
 // The update with one lane per face: each of the G lanes of a cell loads one
@@ -865,12 +882,92 @@ static void macro_steps_t(const BT &bt, const MBatch &b, int n_inner, double cfl
     }
 }
 
+// Small cases (at most SMALL_CELLS cells) run all their pseudo-time steps in
+// one workgroup each: the cell and face loops of a step are strided over the
+// block's lanes with a barrier between the phases, so a 64-cell box pays one
+// launch per solve instead of three per step.  The per-cell and per-face
+// arithmetic is that of the one-thread-per-cell kernels (lsq_cell,
+// face_flux_one, update_cell); a case takes this path by its size alone, so
+// its results do not depend on the batch it runs in.
+constexpr int SMALL_T = 512;
+constexpr int SMALL_CELLS = 1024;
+
+template <int NF>
+__global__ __launch_bounds__(SMALL_T) void k_macro_small(MBatch B, int n_inner, double cfl)
+{
+    const int j = blockIdx.x;
+    const CaseView &C = *B.cv[j];
+    double *__restrict__ W = B.W[j];
+    const double *__restrict__ hot = B.hot[j];
+    const double *__restrict__ src = B.src[j];
+    const int nc = C.n_cells, nfc = C.n_faces;
+    const int t = threadIdx.x;
+    __shared__ double sm[SMALL_T];
+    for (int i = t; i < nc; i += SMALL_T) cons_cell(C, W, i);
+    for (int f = t; f < nfc; f += SMALL_T) hot_face_one(C, hot, f);
+    __syncthreads();
+    for (int it = 0; it < n_inner; ++it) {
+        for (int i = t; i < nc; i += SMALL_T) lsq_cell<4, NF>(C, W, i);
+        __syncthreads();
+        for (int f = t; f < nfc; f += SMALL_T) face_flux_one(C, W, f);
+        if (cfl < 0) {
+            // one global step: min over the cells of V / D (exact in any order)
+            double v = INFINITY;
+            for (int i = t; i < nc; i += SMALL_T) v = fmin(v, C.cell_volume[i] / cell_D(C, i, W + 5 * (size_t)i));
+            sm[t] = v;
+            __syncthreads();
+            for (int st = SMALL_T / 2; st > 0; st >>= 1) {
+                if (t < st) sm[t] = fmin(sm[t], sm[t + st]);
+                __syncthreads();
+            }
+            if (t == 0) C.red[0] = sm[0];
+        }
+        __syncthreads();
+        for (int i = t; i < nc; i += SMALL_T) update_cell<NF>(C, W, src, i, cfl);
+        __syncthreads();
+    }
+}
+
+bool macro_small_on()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GSIS_MACRO_SMALL");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+// case j of batch b appended to batch o (prefixes rebuilt from j's block counts)
+static void mbatch_take(MBatch &o, const MBatch &b, int j)
+{
+    const int k = o.n;
+    if (k == 0) o.bc[0] = o.bf[0] = o.bq[0] = 0, o.nfmax = b.nfmax, o.poly = b.poly;
+    o.cv[k] = b.cv[j];
+    o.W[k] = b.W[j];
+    o.Tr[k] = b.Tr[j];
+    o.hot[k] = b.hot[j];
+    o.src[k] = b.src[j];
+    o.bc[k + 1] = o.bc[k] + (b.bc[j + 1] - b.bc[j]);
+    o.bf[k + 1] = o.bf[k] + (b.bf[j + 1] - b.bf[j]);
+    o.bq[k + 1] = o.bq[k] + (b.bq[j + 1] - b.bq[j]);
+    o.n = k + 1;
+}
+
 hipError_t launch_macro_steps_batch(const MBatch &b, int n_inner, double cfl, hipStream_t s)
 {
     if (b.n <= 0) return hipSuccess;
     if (b.poly) return launch_macro_steps_poly(b, n_inner, cfl, s);
-    if (b.n == 1) macro_steps_t(mone_of(b), b, n_inner, cfl, s);
-    else macro_steps_t(b, b, n_inner, cfl, s);
+    MBatch small{}, large{};
+    for (int j = 0; j < b.n; ++j) {
+        const bool sm = macro_small_on() && (b.bc[j + 1] - b.bc[j]) * MBLOCK <= SMALL_CELLS;
+        mbatch_take(sm ? small : large, b, j);
+    }
+    if (small.n > 0 && n_inner > 0) {
+        if (small.nfmax <= 4) hipLaunchKernelGGL(k_macro_small<4>, dim3(small.n), dim3(SMALL_T), 0, s, small, n_inner, cfl);
+        else hipLaunchKernelGGL(k_macro_small<MAXF>, dim3(small.n), dim3(SMALL_T), 0, s, small, n_inner, cfl);
+    }
+    if (large.n == 1) macro_steps_t(mone_of(large), large, n_inner, cfl, s);
+    else if (large.n > 1) macro_steps_t(large, large, n_inner, cfl, s);
     return hipGetLastError();
 }
 

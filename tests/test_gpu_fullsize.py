@@ -219,12 +219,8 @@ def test_fullsize_order2_sweep_sampled(g, oracle_mod, big):
     rows32 = gi.assemble_separable_rows(*gi.separable_row_factors(grid, W, need, seed=SEED_ROWS))
     O = oracle_mod.Oracle(mesh, grid, KN, order=2)
     f = rows32.astype(np.float64)
-    # T_r of every cell as the library holds it: T_t on NS cells, that of f1
-    # on kinetic ones (it enters the NS ghosts' T_r gradients)
-    Wo = np.concatenate([W, W[:, 4:5]], 1)
-    mf = O.moments(f)
-    Wo[need, :5] = mf[:, :5]
-    Wo[need, 5] = mf[:, 14]
+    Wo = W.copy()
+    Wo[need] = O.moments(f)[:, :5]
     ghost = O.ghost_params(Wo)
     slot = -np.ones(mesh["n_cells"], np.int32)
     slot[need] = np.arange(len(need), dtype=np.int32)
