@@ -12,8 +12,9 @@
  *
  * Units: lengths / L, velocities / sqrt(2 R T0), T / T0, rho / rho0; the
  * Maxwellian is rho (pi T)^(-3/2) exp(-|xi - u|^2 / T).  The gas is
- * monatomic (the two-VDF model of Sec. 2 with d_r = 0, which is the Shakhov
- * model with Prandtl number A_tt).
+ * monatomic by default (the two-VDF model of Sec. 2 with d_r = 0, which is
+ * the Shakhov model with Prandtl number A_tt); gsis_set_internal_dof selects
+ * the two-VDF gas with internal degrees of freedom (the nitrogen of Sec. 4).
  *
  * Conventions
  *  - Every call returns gsis_status; GSIS_OK == 0.  On failure,
@@ -347,6 +348,17 @@ gsis_status gsis_get_state(gsis_case c, double *W_dev, uint8_t *flags_dev, void 
 #define GSIS_NSURF 9
 gsis_status gsis_n_wall_faces(gsis_case c, int32_t *n_wall);
 gsis_status gsis_surface(gsis_case c, int32_t *face_dev, double *out_dev, double *totals_dev, void *stream);
+
+/* Force and heat coefficients (Sec. 4.3) from surface totals, host only:
+ * totals [4] = (sum tau S (3), sum q S) as gsis_surface writes them (copied to
+ * the host), the free stream (rho_inf, u_inf[3]) and the reference area.
+ * out [3] = C_d = F.e / (rho |u|^2 A) along the free-stream direction e,
+ * C_l = F.e_l / (rho |u|^2 A) along e_l = (-e_y, e_x, 0), and
+ * C_h = Q / (rho |u|^3 A); the dynamic pressure rho |u|^2 / 2 is rho |u|^2
+ * in units rho0 R T0.  E_ARG for null pointers, |u_inf| = 0, rho_inf <= 0 or
+ * area <= 0. */
+gsis_status gsis_force_coefficients(const double *totals, double rho_inf, const double *u_inf, double area,
+                                    double *out);
 
 /* GSIS correction alone (Sec. 3.1, first eq. updatef) on the current VDF:
  * f += f_eq(W_new) - f_eq(W_half) on kinetic cells, where W_half are the

@@ -32,21 +32,19 @@ EXPORTS = [
     "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
     "gsis_set_spatial_order", "gsis_set_internal_dof", "gsis_internal_moments",
     "gsis_set_g13_limit", "gsis_limiter_stats", "gsis_case_bind_static", "gsis_get_internal_temperature",
+    "gsis_force_coefficients",
 ]
 
 
 def force_coefficients(totals, rho_inf, u_inf, area):
-    """Drag and lift coefficients (Sec. 4.3) from surface totals [Fx, Fy, Fz, Q]:
-    C_d = F.e / (rho u^2 A) along the free stream e, C_l the same for the
-    in-plane normal of e (the dynamic pressure rho |u|^2 / 2 is rho u^2 in units
-    rho0 R T0); C_h = Q / (rho |u|^3 A) (heat, units rho0 R T0 v_m)."""
-    t = np.asarray(totals, dtype=np.float64)
-    u = np.asarray(u_inf, dtype=np.float64)
-    U = float(np.linalg.norm(u))
-    e = u / U
-    el = np.array([-e[1], e[0], 0.0])
-    q = rho_inf * U * U * area
-    return {"C_d": float(t[:3] @ e) / q, "C_l": float(t[:3] @ el) / q, "C_h": float(t[3]) / (q * U)}
+    """Drag, lift and heat coefficients (Sec. 4.3) from surface totals
+    [Fx, Fy, Fz, Q] (gsis_force_coefficients)."""
+    t = np.ascontiguousarray(np.asarray(totals, dtype=np.float64)[:4])
+    u = np.ascontiguousarray(np.asarray(u_inf, dtype=np.float64)[:3])
+    out = np.zeros(3)
+    _check(lib().gsis_force_coefficients(C.c_void_p(t.ctypes.data), C.c_double(rho_inf), C.c_void_p(u.ctypes.data),
+                                         C.c_double(area), C.c_void_p(out.ctypes.data)))
+    return {"C_d": float(out[0]), "C_l": float(out[1]), "C_h": float(out[2])}
 
 
 class GsisError(RuntimeError):
@@ -113,6 +111,7 @@ def lib():
             "gsis_set_spatial_order": [P, I32, D],
             "gsis_set_internal_dof": [P, D, D, P], "gsis_internal_moments": [P, P, P],
             "gsis_get_internal_temperature": [P, P, P],
+            "gsis_force_coefficients": [P, D, P, D, P],
             "gsis_set_g13_limit": [P, D], "gsis_limiter_stats": [P, P, P],
             "gsis_case_bind_static": [P, I64, P],
         }

@@ -1491,6 +1491,22 @@ extern "C" gsis_status gsis_surface(gsis_case c, int32_t *face_dev, double *out,
     return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_force_coefficients(const double *totals, double rho_inf, const double *u_inf, double area,
+                                               double *out)
+{
+    if (!totals || !u_inf || !out) return fail(GSIS_E_ARG, "null argument");
+    const double U = std::sqrt(u_inf[0] * u_inf[0] + u_inf[1] * u_inf[1] + u_inf[2] * u_inf[2]);
+    if (!(U > 0) || !(rho_inf > 0) || !(area > 0) || !std::isfinite(U))
+        return fail(GSIS_E_ARG, "bad free stream or reference area");
+    const double e[3] = {u_inf[0] / U, u_inf[1] / U, u_inf[2] / U};
+    const double el[3] = {-e[1], e[0], 0.0};
+    const double q = rho_inf * U * U * area;
+    out[0] = (totals[0] * e[0] + totals[1] * e[1] + totals[2] * e[2]) / q;
+    out[1] = (totals[0] * el[0] + totals[1] * el[1] + totals[2] * el[2]) / q;
+    out[2] = totals[3] / (q * U);
+    return GSIS_OK;
+}
+
 extern "C" gsis_status gsis_macro_solve(gsis_case c, double *W, const double *hot, const double *src, int32_t n_inner,
                                         double cfl, void *stream)
 {

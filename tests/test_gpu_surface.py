@@ -85,3 +85,19 @@ def test_surface_after_step(g, oracle_mod):
     case.set_state(W, flags=flags)
     case.step(g.SolveParams(mode=g.MODE_AGSIS, n_macro_inner=20, cfl=0.5, force_wall_layers=2))
     _compare(O, case, m)
+
+
+def test_force_coefficients_hand_computed(g):
+    """gsis_force_coefficients on totals with known answers: free stream along
+    (3, 4, 0)/5 at rho 2, area 0.5, so rho |u|^2 A = 25 and C_h divides by 125:
+    F = (3, 4, 0) gives C_d = 5/25 and C_l = 0; F = (-4, 3, 7) gives C_d = 0,
+    C_l = 5/25 (F_z plays no part); Q = 10 gives C_h = 10/125; bad inputs are
+    refused."""
+    u = (3.0, 4.0, 0.0)
+    c = g.force_coefficients([3.0, 4.0, 0.0, 10.0], 2.0, u, 0.5)
+    assert abs(c["C_d"] - 0.2) < 1e-15 and abs(c["C_l"]) < 1e-15 and abs(c["C_h"] - 0.08) < 1e-15
+    c = g.force_coefficients([-4.0, 3.0, 7.0, 0.0], 2.0, u, 0.5)
+    assert abs(c["C_d"]) < 1e-15 and abs(c["C_l"] - 0.2) < 1e-15 and c["C_h"] == 0.0
+    for bad in ((2.0, (0.0, 0.0, 0.0), 0.5), (0.0, u, 0.5), (2.0, u, 0.0)):
+        with pytest.raises(g.GsisError):
+            g.force_coefficients([1.0, 0.0, 0.0, 0.0], *bad)
