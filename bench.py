@@ -477,6 +477,30 @@ def surface_leg(g, torch, case, mesh, es):
             "state": "after the timed steps (not converged)"}
 
 
+def step_graph_leg(g, torch, case, n_inner, steps=4):
+    """Whole outer iterations with the region held (no re-flagging): eager
+    launches, then replays of whole-step HIP graphs (GSIS_STEP_GRAPHS=1; the
+    first two steps capture one graph per buffer parity)."""
+    p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=KN_REF, n_macro_inner=n_inner, cfl=0.5, region_update_every=0,
+                      force_wall_layers=2)
+    out = {}
+    for name, env, warm in (("eager", "0", 1), ("graphs", "1", 2)):
+        os.environ["GSIS_STEP_GRAPHS"] = env
+        try:
+            for _ in range(warm):
+                case.step(p)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                case.step(p)
+            torch.cuda.synchronize()
+            out[name + "_ms_per_step"] = 1e3 * (time.perf_counter() - t) / steps
+        finally:
+            os.environ.pop("GSIS_STEP_GRAPHS", None)
+    out["kinetic_cells"] = case.n_kin
+    return out
+
+
 def synthetic_leg(torch, case, mesh, n_inner, reps=2):
     """The synthetic macroscopic solve alone (eq. macro, FP64): n_inner
     pseudo-time steps over every cell from the state after the timed steps,
@@ -560,6 +584,8 @@ def main():
     log("surface", surface)
     synthetic = None if a.sweep_only else synthetic_leg(torch, case, mesh, a.n_inner)
     log("synthetic solve", synthetic)
+    step_graphs = None if a.sweep_only else step_graph_leg(g, torch, case, a.n_inner)
+    log("whole-step graphs", step_graphs)
     case.close()
 
     if a.calibrate_copy > 0:
@@ -627,6 +653,7 @@ def main():
         "configs": configs,
         "surface": surface,
         "synthetic_solve": synthetic,
+        "step_graphs": step_graphs,
         "setup_s": setup_s,
     }
     if a.serve_requests > 0 and not a.sweep_only:

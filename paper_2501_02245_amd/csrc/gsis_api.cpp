@@ -1314,6 +1314,29 @@ bool graphs_enabled()
     return !(env && env[0] == '0');
 }
 
+// Whole outer iterations from HIP graphs (GSIS_STEP_GRAPHS=1): everything a
+// step launches before its region update -- relaxation parameters, ghosts,
+// the batched sweep, moments, HoT, the synthetic solve, the correction and
+// the residual -- is captured once per batch composition, parameters, kinetic
+// and ghost counts and buffer parity, and replayed while those stay the same
+// (between region updates).  The region update and the residual read-back
+// stay eager.  Sweep timing events are not recorded in this mode.
+struct StepGraph {
+    std::vector<gsis_case> cases;
+    std::vector<int32_t> nk, ng, cur;
+    gsis_solve_params p;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+std::vector<StepGraph> g_step_graphs;
+
+bool step_graphs_enabled()
+{
+    const char *env = std::getenv("GSIS_STEP_GRAPHS");
+    return env && env[0] == '1';
+}
+
 void drop_graphs_of(gsis_case c)
 {
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -1323,6 +1346,16 @@ void drop_graphs_of(gsis_case c)
             (void)hipGraphExecDestroy(G.exec);
             (void)hipGraphDestroy(G.graph);
             g_graphs.erase(g_graphs.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+    for (size_t k = 0; k < g_step_graphs.size();) {
+        StepGraph &G = g_step_graphs[k];
+        if (std::find(G.cases.begin(), G.cases.end(), c) != G.cases.end()) {
+            (void)hipGraphExecDestroy(G.exec);
+            (void)hipGraphDestroy(G.graph);
+            g_step_graphs.erase(g_step_graphs.begin() + k);
         } else {
             ++k;
         }
@@ -1372,13 +1405,25 @@ gsis_status run_macro_batch(gsis_case const *cases, int n, int n_inner, double c
 
 // the synthetic solves of a batch: one launch per kernel and pseudo-time step
 // for all cases (up to 16 per launch)
-gsis_status macro_solves(gsis_case const *cases, int n, const gsis_solve_params *p, hipStream_t s)
+gsis_status macro_solves(gsis_case const *cases, int n, const gsis_solve_params *p, hipStream_t s,
+                         bool capturing = false)
 {
     if (p->mode == GSIS_MODE_DVM) return GSIS_OK;
     gsis_status st;
-    for (int j0 = 0; j0 < n; j0 += MAX_BATCH)
-        if ((st = run_macro_batch(cases + j0, std::min(MAX_BATCH, n - j0), p->n_macro_inner, p->cfl, true, s)))
+    for (int j0 = 0; j0 < n; j0 += MAX_BATCH) {
+        const int m = std::min(MAX_BATCH, n - j0);
+        if (capturing) {
+            // inside a whole-step capture: the launches themselves (no nested graph)
+            MBatch b{};
+            for (int j = 0; j < m; ++j) {
+                CaseView &h = cases[j0 + j]->hv;
+                mbatch_add(b, cases[j0 + j]->cv, h, h.Wn, h.hot, h.src, h.poly ? h.Trn : nullptr);
+            }
+            HIPCHK(launch_macro_steps_batch(b, p->n_macro_inner, p->cfl, s));
+        } else if ((st = run_macro_batch(cases + j0, m, p->n_macro_inner, p->cfl, true, s))) {
             return st;
+        }
+    }
     return GSIS_OK;
 }
 
@@ -1395,6 +1440,79 @@ gsis_status post_macro(gsis_case c, const gsis_solve_params *p, hipStream_t s)
     HIPCHK(launch_eps(c->cv, h, h.Wn, h.W, s));
     HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
     if (h.poly) HIPCHK(launch_copy_d(h.Tr, h.Trn, h.n_cells, s));
+    return GSIS_OK;
+}
+
+// everything one outer iteration launches before its region update
+gsis_status step_body(gsis_case const *cases, int n, const gsis_solve_params *p, hipStream_t s, bool capturing)
+{
+    gsis_status st;
+    for (int j = 0; j < n; ++j)
+        if ((st = prepare_sweep(cases[j], s))) return st;
+    if ((st = batched_sweep(cases, n, s, !capturing))) return st;
+    for (int j = 0; j < n; ++j)
+        if ((st = pre_macro(cases[j], p, s))) return st;
+    if ((st = macro_solves(cases, n, p, s, capturing))) return st;
+    for (int j = 0; j < n; ++j)
+        if ((st = post_macro(cases[j], p, s))) return st;
+    return GSIS_OK;
+}
+
+bool same_params(const gsis_solve_params &a, const gsis_solve_params &b)
+{
+    return a.mode == b.mode && a.n_macro_inner == b.n_macro_inner && a.cfl == b.cfl;
+}
+
+gsis_status step_from_graph(gsis_case const *cases, int n, const gsis_solve_params *p, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    std::vector<gsis_case> key(cases, cases + n);
+    std::vector<int32_t> nk(n), ng(n), cur(n);
+    for (int j = 0; j < n; ++j) {
+        nk[j] = cases[j]->n_kin;
+        ng[j] = cases[j]->n_ghost;
+        cur[j] = cases[j]->cur;
+    }
+    StepGraph *hit = nullptr;
+    for (auto &G : g_step_graphs)
+        if (G.cases == key && G.nk == nk && G.ng == ng && G.cur == cur && same_params(G.p, *p)) hit = &G;
+    if (hit) {
+        hit->last_use = ++g_graph_clock;
+        HIPCHK(hipGraphLaunch(hit->exec, s));
+        // the host bookkeeping of the captured sweep
+        for (int j = 0; j < n; ++j) {
+            cases[j]->cur ^= 1;
+            cases[j]->timed = false;
+        }
+        return GSIS_OK;
+    }
+    if (!g_capture_stream) HIPCHK(hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking));
+    if (g_step_graphs.size() >= MAX_GRAPHS) {
+        auto lru = std::min_element(g_step_graphs.begin(), g_step_graphs.end(),
+                                    [](const StepGraph &a, const StepGraph &c) { return a.last_use < c.last_use; });
+        (void)hipGraphExecDestroy(lru->exec);
+        (void)hipGraphDestroy(lru->graph);
+        g_step_graphs.erase(lru);
+    }
+    StepGraph G{key, nk, ng, cur, *p, nullptr, nullptr, 0};
+    // the capture stream starts after the work already on s
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, s));
+    HIPCHK(hipStreamWaitEvent(g_capture_stream, ev, 0));
+    HIPCHK(hipEventDestroy(ev));
+    HIPCHK(hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal));
+    gsis_status st = step_body(cases, n, p, g_capture_stream, true);
+    hipError_t e2 = hipStreamEndCapture(g_capture_stream, &G.graph);
+    if (st) {
+        if (G.graph) (void)hipGraphDestroy(G.graph);
+        return st;
+    }
+    HIPCHK(e2);
+    HIPCHK(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+    G.last_use = ++g_graph_clock;
+    g_step_graphs.push_back(G);
+    HIPCHK(hipGraphLaunch(G.exec, s));
     return GSIS_OK;
 }
 
@@ -1416,14 +1534,11 @@ extern "C" gsis_status gsis_step(gsis_case const *cases, int32_t n, const gsis_s
     if (st) return st;
     if ((st = check_params(p))) return st;
     hipStream_t s = (hipStream_t)stream;
-    for (int j = 0; j < n; ++j)
-        if ((st = prepare_sweep(cases[j], s))) return st;
-    if ((st = batched_sweep(cases, n, s, true))) return st;
-    for (int j = 0; j < n; ++j)
-        if ((st = pre_macro(cases[j], p, s))) return st;
-    if ((st = macro_solves(cases, n, p, s))) return st;
-    for (int j = 0; j < n; ++j)
-        if ((st = post_macro(cases[j], p, s))) return st;
+    if (step_graphs_enabled()) {
+        if ((st = step_from_graph(cases, n, p, s))) return st;
+    } else if ((st = step_body(cases, n, p, s, false))) {
+        return st;
+    }
     // per-case endings: a case whose region update or state check fails is
     // reported with NaN residuals; the others complete the step
     gsis_status first = GSIS_OK;

@@ -42,3 +42,38 @@ def test_graph_replays_equal_eager(g, name, mode):
             os.environ.pop("GSIS_GRAPHS", None)
     for a, b in zip(out["0"], out["1"]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,mode", [("cylinder_fast", "agsis"), ("couette", "gsis"), ("sphere_fast", "agsis")])
+def test_step_graph_replays_equal_eager(g, name, mode):
+    """Whole outer iterations from HIP graphs (GSIS_STEP_GRAPHS=1): sweep,
+    moments, HoT, synthetic solve, correction and residual captured per batch
+    composition, counts and buffer parity, replayed between region updates
+    (re-flagging once, after two iterations, then a fixed region: the later
+    steps replay the graphs of the same parity).  Eight iterations with host
+    reads between them are bitwise the eager ones."""
+    m, grid, Kn, W, flags = workload(name)
+    out = {}
+    for graphs in ("0", "1"):
+        os.environ["GSIS_STEP_GRAPHS"] = graphs
+        try:
+            case = make_case(g, name, m, grid, Kn, g.F32)
+            if mode == "agsis":
+                case.set_state(W, flags=flags)
+                p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, n_macro_inner=50, cfl=0.5, region_update_every=-2,
+                                  force_wall_layers=2)
+            else:
+                case.set_state(W)
+                p = g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=50, cfl=-0.5)
+            eps, Ws = [], []
+            for _ in range(8):
+                eps.append(case.step(p))
+                Ws.append(case.get_state()[0].cpu().numpy())
+            Wg, fl = case.get_state()
+            out[graphs] = (np.array(eps), np.array(Ws), fl.cpu().numpy(), case.get_vdf().cpu().numpy(),
+                           case.moments()[0].cpu().numpy())
+            case.close()
+        finally:
+            os.environ.pop("GSIS_STEP_GRAPHS", None)
+    for a, b in zip(out["0"], out["1"]):
+        assert np.array_equal(a, b)
