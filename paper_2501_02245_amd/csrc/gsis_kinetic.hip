@@ -504,6 +504,16 @@ __global__ void k_param(const CaseView *__restrict__ cvp, int n_kin)
     C.param[slot] = P;
 }
 
+// GSIS_POLY_VEC=0 keeps one node per lane in the two-VDF sweep
+static bool poly_vec_on()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GSIS_POLY_VEC");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 hipError_t launch_param_poly(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 
 hipError_t launch_param(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s)
@@ -1857,7 +1867,7 @@ __global__ __launch_bounds__(BLOCK) void k_correct_poly(const CaseView *__restri
 // of a wall (times rho_w) or far field for f0 with f1 = (d_r T_b / 4) f0; the
 // own targets from per-axis Gaussian tables at T_t and T; the loads of a node
 // are issued before they are used; FP64 moment sums of both VDFs
-template <typename T, int NF>
+template <typename T, int NF, bool VEC>
 __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
 {
     __shared__ double red[(BLOCK / 64) * NSUM];
@@ -1944,17 +1954,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
 #pragma unroll
     for (int l = 0; l < NF; ++l) wacc[l] = 0.0;
     const int k0 = vt * C.tile, kend = min(k0 + C.tile, C.nv);
-    VIdx vi = vidx_init<3>(k0 + threadIdx.x, n1, n2);
-    for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
-        T v0[NF], v1[NF];
-#pragma unroll
-        for (int l = 0; l < NF; ++l) {
-            v0[l] = fnb[l][k];
-            v1[l] = fnb[l][nvp + k];
-        }
-        const T o0 = fo[k], o1 = fo[nvp + k];
-        const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
-        vidx_step<3>(vi, n1, n2);
+    // one node: the relaxed values of f0 and f1 from the node's own and upwind
+    // values, with its moment, balance and wall sums
+    auto relax = [&](int jx, int jy, int jz, const T *v0, const T *v1, T o0, T o1, T &n0v, T &n1v) {
         const double wd = twd[jx] * twd[jy] * twd[jz];
         const T x0 = tx[jx], x1 = tx[jy], x2 = tx[jz];
         const double d0 = tcd[jx], d1 = tcd[jy], d2 = tcd[jz];
@@ -1981,9 +1983,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
             num1 -= m * (fkin[l] * v1[l] + fth[l] * v0[l]);
         }
         const T rden = (T)1 / den;
-        const T n0v = num0 * rden, n1v = num1 * rden;
-        __builtin_nontemporal_store(n0v, &fn[k]);
-        __builtin_nontemporal_store(n1v, &fn[nvp + k]);
+        n0v = num0 * rden;
+        n1v = num1 * rden;
         const double dcc = d0 * d0 + d1 * d1 + d2 * d2;
         acc_moments<double, 3>(acc, wd, (double)n0v, 0.0, d0, d1, d2, dcc);
         const double h1 = wd * (double)n1v;
@@ -2002,6 +2003,54 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_poly(Batch B)
         ps[4] += r1;
 #pragma unroll
         for (int l = 0; l < NF; ++l) wacc[l] += wd * (double)(ap[l] * n0v);
+    };
+    if (VEC && C.n[2] % 4 == 0 && C.tile % 4 == 0 && C.nv % 4 == 0) {
+        // four consecutive z nodes per lane (16-byte loads and stores of every
+        // row; n_z, the tile and the rows are multiples of 4 nodes)
+        typedef T V4 __attribute__((ext_vector_type(4)));
+        for (int k = k0 + 4 * (int)threadIdx.x; k < kend; k += 4 * BLOCK) {
+            V4 a0[NF], a1[NF];
+#pragma unroll
+            for (int l = 0; l < NF; ++l) {
+                a0[l] = *(const V4 *)(fnb[l] + k);
+                a1[l] = *(const V4 *)(fnb[l] + nvp + k);
+            }
+            const V4 q0 = *(const V4 *)(fo + k), q1 = *(const V4 *)(fo + nvp + k);
+            const int iz = k % n2, r = k / n2, iy = r % n1, ix = r / n1;
+            V4 r0v, r1v;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                T v0[NF], v1[NF];
+#pragma unroll
+                for (int l = 0; l < NF; ++l) {
+                    v0[l] = a0[l][jj];
+                    v1[l] = a1[l][jj];
+                }
+                T n0v, n1v;
+                relax(ix, n0 + iy, n0 + n1 + iz + jj, v0, v1, q0[jj], q1[jj], n0v, n1v);
+                r0v[jj] = n0v;
+                r1v[jj] = n1v;
+            }
+            __builtin_nontemporal_store(r0v, (V4 *)(fn + k));
+            __builtin_nontemporal_store(r1v, (V4 *)(fn + nvp + k));
+        }
+    } else {
+        VIdx vi = vidx_init<3>(k0 + threadIdx.x, n1, n2);
+        for (int k = k0 + threadIdx.x; k < kend; k += BLOCK) {
+            T v0[NF], v1[NF];
+#pragma unroll
+            for (int l = 0; l < NF; ++l) {
+                v0[l] = fnb[l][k];
+                v1[l] = fnb[l][nvp + k];
+            }
+            const T o0 = fo[k], o1 = fo[nvp + k];
+            const int jx = vi.ix, jy = n0 + vi.iy, jz = n0 + n1 + vi.iz;
+            vidx_step<3>(vi, n1, n2);
+            T n0v, n1v;
+            relax(jx, jy, jz, v0, v1, o0, o1, n0v, n1v);
+            __builtin_nontemporal_store(n0v, &fn[k]);
+            __builtin_nontemporal_store(n1v, &fn[nvp + k]);
+        }
     }
 #pragma unroll
     for (int l = 0; l < NF; ++l)
@@ -2036,11 +2085,18 @@ hipError_t launch_sweep_poly(const Batch &b, const CaseView &h0, int total, hipS
 {
     const bool f4 = b.nfmax <= 4;
     if (h0.dtype == GSIS_F32) {
-        if (f4) hipLaunchKernelGGL((k_sweep_poly<float, 4>), dim3(total), dim3(BLOCK), 0, s, b);
-        else hipLaunchKernelGGL((k_sweep_poly<float, MAXF>), dim3(total), dim3(BLOCK), 0, s, b);
+        // 16-byte node groups on the cases whose z axis, tile and node count are
+        // multiples of 4 (the kernel checks each case)
+        if (poly_vec_on()) {
+            if (f4) hipLaunchKernelGGL((k_sweep_poly<float, 4, true>), dim3(total), dim3(BLOCK), 0, s, b);
+            else hipLaunchKernelGGL((k_sweep_poly<float, MAXF, true>), dim3(total), dim3(BLOCK), 0, s, b);
+        } else {
+            if (f4) hipLaunchKernelGGL((k_sweep_poly<float, 4, false>), dim3(total), dim3(BLOCK), 0, s, b);
+            else hipLaunchKernelGGL((k_sweep_poly<float, MAXF, false>), dim3(total), dim3(BLOCK), 0, s, b);
+        }
     } else {
-        if (f4) hipLaunchKernelGGL((k_sweep_poly<double, 4>), dim3(total), dim3(BLOCK), 0, s, b);
-        else hipLaunchKernelGGL((k_sweep_poly<double, MAXF>), dim3(total), dim3(BLOCK), 0, s, b);
+        if (f4) hipLaunchKernelGGL((k_sweep_poly<double, 4, false>), dim3(total), dim3(BLOCK), 0, s, b);
+        else hipLaunchKernelGGL((k_sweep_poly<double, MAXF, false>), dim3(total), dim3(BLOCK), 0, s, b);
     }
     return hipGetLastError();
 }
