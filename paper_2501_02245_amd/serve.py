@@ -81,8 +81,11 @@ class Server:
     """FIFO admission by footprint, one batched outer iteration per tick."""
 
     def __init__(self, budget_bytes, dtype=F32, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400,
-                 ns_chunks=50, max_active=64, keep_fields=True, min_iter=5):
+                 ns_chunks=50, max_active=64, keep_fields=True, min_iter=5, step_graphs=False):
         self.budget = int(budget_bytes)
+        # replay each group's outer iteration from a HIP graph between region
+        # updates (GSIS_STEP_GRAPHS; results are bitwise those of eager launches)
+        self.step_graphs = step_graphs
         self.min_iter = min_iter     # a first small change is not convergence
         self.dtype, self.Kn_ref, self.tol, self.max_iter = dtype, Kn_ref, tol, max_iter
         self.n_inner, self.ns_chunks = n_inner, ns_chunks
@@ -134,6 +137,18 @@ class Server:
         return res
 
     def run(self, requests, log=None):
+        import os
+        old = os.environ.get("GSIS_STEP_GRAPHS")
+        os.environ["GSIS_STEP_GRAPHS"] = "1" if self.step_graphs else "0"
+        try:
+            return self._run(requests, log)
+        finally:
+            if old is None:
+                os.environ.pop("GSIS_STEP_GRAPHS", None)
+            else:
+                os.environ["GSIS_STEP_GRAPHS"] = old
+
+    def _run(self, requests, log=None):
         import torch
         pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         queue, active, results = deque(), [], []
