@@ -310,7 +310,10 @@ gsis_status gsis_step(gsis_case const *cases, int32_t n_cases, const gsis_solve_
  * ns_init_max_chunks chunks) to eps < 1e-6, then the first flagging with
  * Grad-13 rows for every kinetic cell.  The cases' solves share batched
  * launches; a case leaves the batch when it converges.  chunks (host,
- * nullable) receives the chunks each case ran.  Synchronises. */
+ * nullable) receives the chunks each case ran.  If a case's first flagging
+ * fails (E_CAPACITY: a region beyond its capacity), its chunks entry is -1
+ * and it needs gsis_set_state again; the other cases complete, and the call
+ * returns the first error.  Synchronises. */
 gsis_status gsis_ns_init(gsis_case const *cases, int32_t n_cases, const gsis_solve_params *p, int32_t *chunks,
                          void *stream);
 

@@ -391,10 +391,17 @@ def kinetic_sweep(cases, n_sweeps=1):
 
 def ns_init(cases, params: SolveParams):
     """Steps 1-2 (NS start, first flagging) for several aGSIS cases with batched
-    launches; returns the chunks each case ran."""
+    launches; returns the chunks each case ran.  On failure the GsisError
+    carries `chunks`: -1 marks the cases whose first flagging failed; the
+    others completed their start."""
     arr = (C.c_void_p * len(cases))(*[c.handle for c in cases])
     chunks = (C.c_int32 * len(cases))()
-    _check(lib().gsis_ns_init(arr, len(cases), C.byref(params), chunks, _stream()))
+    code = lib().gsis_ns_init(arr, len(cases), C.byref(params), chunks, _stream())
+    try:
+        _check(code)
+    except GsisError as e:
+        e.chunks = list(chunks)
+        raise
     return list(chunks)
 
 

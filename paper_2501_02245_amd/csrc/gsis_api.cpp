@@ -1696,9 +1696,21 @@ extern "C" gsis_status gsis_ns_init(gsis_case const *cases, int32_t n, const gsi
         active.swap(still);
         idx.swap(still_idx);
     }
-    // Step 2: first flagging; every kinetic cell is new and starts from Grad-13
-    for (int j = 0; j < n; ++j)
-        if ((st = gsis_update_regions(cases[j], p->Kn_ref, p->force_wall_layers, nullptr, stream))) return st;
+    // Step 2: first flagging; every kinetic cell is new and starts from Grad-13.
+    // A case whose flagging fails (a region beyond its capacity) is marked with
+    // chunks[j] = -1 and the others complete; the first error is returned.
+    gsis_status first = GSIS_OK;
+    std::string first_msg;
+    for (int j = 0; j < n; ++j) {
+        if ((st = gsis_update_regions(cases[j], p->Kn_ref, p->force_wall_layers, nullptr, stream))) {
+            if (chunks) chunks[j] = -1;
+            if (!first) {
+                first = st;
+                first_msg = "case " + std::to_string(j) + " of the batch: " + g_err;
+            }
+        }
+    }
+    if (first) return fail(first, "%s", first_msg.c_str());
     return GSIS_OK;
 }
 

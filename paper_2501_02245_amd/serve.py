@@ -110,8 +110,9 @@ class Server:
 
     def _ns_starts(self, fresh):
         """Steps 1-2 for newly bound aGSIS cases, batched by launch compatibility;
-        returns [(active, outcome)]: None (started), "retry" (the batched start
-        failed: restart alone), or the error of a start run alone."""
+        returns [(active, outcome)]: None (started), "grow" (its region outgrew
+        the reservation in a batched start), "retry" (the batched start failed:
+        restart alone), or the error of a start run alone."""
         out = []
         groups = defaultdict(list)
         for k, a in enumerate(fresh):
@@ -125,7 +126,13 @@ class Server:
                 ns_init([a.case for a in grp], p)
                 out += [(a, None) for a in grp]
             except GsisError as e:
-                out += [(a, "retry" if len(grp) > 1 else e) for a in grp]
+                ch = getattr(e, "chunks", None)
+                if len(grp) > 1 and ch is not None and min(ch) < 0 and e.code == E_CAPACITY:
+                    # the cases whose first flagging failed restart with a larger
+                    # reservation (alone if they hold the whole mesh); the rest started
+                    out += [(a, None if c >= 0 else "grow") for a, c in zip(grp, ch)]
+                else:
+                    out += [(a, "retry" if len(grp) > 1 else e) for a in grp]
         return out
 
     def _retire(self, a, status, t0):
@@ -190,7 +197,10 @@ class Server:
                 a.case.close()
                 a.case.mesh.close()
                 r = a.req
-                if err == "retry":
+                if err == "grow" and r.capacity < 1.0:
+                    queue.appendleft(dataclasses.replace(r, capacity=min(1.0, 2.0 * r.capacity)))
+                    self.requeued += 1
+                elif err in ("retry", "grow"):
                     queue.appendleft(dataclasses.replace(r, solo=True))
                     self.requeued += 1
                 elif err.code == E_CAPACITY and r.capacity < 1.0:

@@ -70,3 +70,28 @@ def test_served_matches_oracle(g, oracle_mod):
                "T": np.abs(out.W[:, 4] - S.W[:, 4]).max() / np.abs(S.W[:, 4]).max()}
         print(r.rid, r.kind, out.iterations, S.it, err, flush=True)
         assert max(err.values()) < 1e-4
+
+
+def test_batched_ns_start_keeps_the_cases_that_fit(g):
+    """A batched NS start where one case's first flagging outgrows its
+    reservation: that case is marked (chunks -1, E_CAPACITY), the other
+    completes its start and steps on."""
+    from _cases import workload
+    m, grid, Kn, W, _ = workload("cylinder_small")
+    n = m["n_cells"]
+    ok = g.Case(g.Mesh(m), grid, Kn, dtype=g.F32, capacity=n)
+    small = g.Case(g.Mesh(m), grid, Kn, dtype=g.F32, capacity=8)
+    none = np.zeros(n, np.uint8)
+    for c in (ok, small):
+        c.set_state(W, flags=none)
+    p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, n_macro_inner=100, cfl=0.5, force_wall_layers=2,
+                      ns_init_max_chunks=2)
+    with pytest.raises(g.GsisError) as ei:
+        g.ns_init([ok, small], p)
+    assert ei.value.code == g.E_CAPACITY
+    ch = ei.value.chunks
+    print("chunks", ch, "kinetic", ok.n_kin, flush=True)
+    assert ch[0] >= 1 and ch[1] == -1
+    assert ok.n_kin > 8
+    e = ok.step(p)
+    assert np.all(np.isfinite(e))
