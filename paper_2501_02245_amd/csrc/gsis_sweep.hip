@@ -601,6 +601,120 @@ __device__ __forceinline__ double to_uniform(double x)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Epilogue of the 16-byte-row plane kernels.  A lane holds, per node j of its
+// four z nodes, FP32 sums over the x-planes of w_x c_x^a f (a = 0..3) in S0..S3,
+// the sweep's balance sums in R0..R2 (zero for the correction) and, for cells
+// with wall faces, the outgoing wall sums with weight w_x w_z in Wf.  They
+// become FP64 partials with the lane's (y, z) offsets, reduced over the wave
+// with DPP row sums and over the block's rows in a fixed order, and the NSUM
+// partial sums of the (slot, tile) are written to out.
+template <typename T, int NF, bool WALLS>
+__device__ __forceinline__ void v4_partials(const T (&S0)[4], const T (&S1)[4], const T (&S2)[4], const T (&S3)[4],
+                                            const T (&R0)[4], const T (&R1)[4], const T (&R2)[4],
+                                            const T (&Wf)[NF], const int (&fwall)[NF], const CaseView &C,
+                                            double uz, double cyd, int iy, int iz0, double *red, double *out)
+{
+    // ---- epilogue: the lane's FP64 partial sums, one at a time, each
+    // reduced over the wave in a fixed order; then the waves in order
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double wyd = C.wv[MAXA + iy];
+    double wj[4], czj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        czj[j] = C.xv[2 * MAXA + iz0 + j] - uz;
+        wj[j] = wyd * C.wv[2 * MAXA + iz0 + j];
+    }
+    // row sums (DPP) of 16 lanes, written by the first lane of each row;
+    // the 16 rows of the block are added in order below
+    auto put = [&](int i, double x) {
+        x = row_sum16(x);
+        if ((lane & 15) == 0) red[(wave * 4 + (lane >> 4)) * NSUM + i] = x;
+    };
+    double a, b2, c2, d;
+    // mass, and the y moments that are lane constants times it
+    a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a += wj[j] * (double)S0[j];
+    put(0, a);
+    put(2, cyd * a);
+    put(5, cyd * cyd * a);
+    // x moments
+    b2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b2 += wj[j] * (double)S1[j];
+    put(1, b2);
+    put(7, cyd * b2);
+    c2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c2 += wj[j] * (double)S2[j];
+    put(4, c2);
+    // z moments
+    a = 0.0;
+    d = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a += wj[j] * czj[j] * (double)S0[j];
+        d += wj[j] * czj[j] * czj[j] * (double)S0[j];
+    }
+    put(3, a);
+    put(9, cyd * a);
+    put(6, d);
+    a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a += wj[j] * czj[j] * (double)S1[j];
+    put(8, a);
+    // heat-flux sums c^2 c_d
+    a = 0.0;
+    d = 0.0;
+    b2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double yz2 = cyd * cyd + czj[j] * czj[j];
+        const double e2 = wj[j] * ((double)S2[j] + yz2 * (double)S0[j]);
+        a += wj[j] * ((double)S3[j] + yz2 * (double)S1[j]);
+        d += e2;
+        b2 += czj[j] * e2;
+    }
+    put(10, a);
+    put(11, cyd * d);
+    put(12, b2);
+    // moment balance
+    a = 0.0;
+    d = 0.0;
+    b2 = 0.0;
+    c2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double yz2 = cyd * cyd + czj[j] * czj[j];
+        a += wj[j] * (double)R0[j];
+        d += wj[j] * (double)R1[j];
+        b2 += wj[j] * czj[j] * (double)R0[j];
+        c2 += wj[j] * ((double)R2[j] + yz2 * (double)R0[j]);
+    }
+    put(S_RES, a);
+    put(S_RES + 1, d);
+    put(S_RES + 2, cyd * a);
+    put(S_RES + 3, b2);
+    put(S_RES + 4, c2);
+    // outgoing wall fluxes (weights w_x w_z in the sums, w_y here)
+#pragma unroll
+    for (int q2 = 0; q2 < MAXW; ++q2) {
+        double sw = 0.0;
+        if (WALLS) {
+#pragma unroll
+            for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? (double)Wf[l] : 0.0;
+        }
+        put(S_WALL + q2, wyd * sw);
+    }
+    for (int i = S_WALL + MAXW; i < NSUM; ++i) put(i, 0.0);
+    __syncthreads();
+    if (threadIdx.x < NSUM) {
+        double acc = 0.0;
+        for (int r = 0; r < BLOCK / 16; ++r) acc += red[r * NSUM + threadIdx.x];
+        out[threadIdx.x] = acc;
+    }
+}
+
 // waves per SIMD of the FP32 16-byte-row sweep (up to 4 faces per cell: 150
 // VGPRs without spills at 3; 8 faces take 2)
 #ifndef SWEEP_V4_WAVES
@@ -868,105 +982,180 @@ __global__ __launch_bounds__(BLOCK) __attribute__((
 #pragma unroll
             for (int l = 0; l < NF; ++l) asm volatile("" : "+v"(Wf[l]));
         }
-        // ---- epilogue: the lane's FP64 partial sums, one at a time, each
-        // reduced over the wave in a fixed order; then the waves in order
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        const double wyd = C.wv[MAXA + iy];
-        double wj[4], czj[4];
+        v4_partials<T, NF, WALLS>(S0, S1, S2, S3, R0, R1, R2, Wf, fwall, C, P.u[2], cyd, iy, iz0, red,
+                                  C.partial + ((size_t)slot * C.ntile + vt) * NSUM);
+    };
+    if (nw > 0) {
+        planes(std::true_type{});
+        epilogue(std::true_type{});
+    } else {
+        planes(std::false_type{});
+        epilogue(std::false_type{});
+    }
+}
+
+// waves per SIMD of the FP32 16-byte-row correction
+#ifndef CORRECT_V4_WAVES
+#define CORRECT_V4_WAVES 4
+#endif
+// x-planes per load round of the 16-byte-row correction (cells without walls)
+#ifndef CORRECT_V4_U
+#define CORRECT_V4_U 4
+#endif
+
+// ---------------------------------------------------------------------------
+// GSIS correction (Sec. 3.1) in the 16-byte-row plane layout of k_sweep_v4:
+// f += f_eq(W^{n+1}) - f_eq(W^{n+1/2}) in place.  Each f_eq is a
+// conservation-fixed Maxwellian E_x E_y E_z (P_x + P_y + P_z) (a_0 in P_x).  A
+// lane keeps one y node and four z nodes for the whole row: their (y, z)
+// factors E_y E_z and P_y + P_z are formed in FP64 and rounded once; one LDS
+// record per x-plane gives c_x, E_x and P_x of both states and w_x c_x^a.  The
+// moment and outgoing wall sums are those of the sweep (no balance sums).
+// ---------------------------------------------------------------------------
+template <typename T, int NF>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? CORRECT_V4_WAVES : 1))) void
+k_correct_v4(const CaseView *__restrict__ cvp, int n_kin, int cur)
+{
+    typedef typename Vec4T<T>::v V4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const CaseView &C = *cvp;
+    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int vt = b / n_kin, t = b - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const FeqRec &Fa = C.feq[2 * (size_t)slot];       // f_eq(W^{n+1})
+    const FeqRec &Fb = C.feq[2 * (size_t)slot + 1];   // f_eq(W^{n+1/2})
+    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
+    gptr<T> fr = (gptr<T>)C.f[cur] + (size_t)slot * C.row;
+
+    // lane -> (x group, y, first of four z nodes), as in the sweep
+    const int Q = nz >> 2, PL = ny * Q, G = BLOCK / PL;
+    const int xg = threadIdx.x / PL, pr = threadIdx.x - xg * PL;
+    const int iy = pr / Q, iz0 = 4 * (pr - iy * Q);
+
+    // ---- LDS: per x-plane c, E_x and P_x of both states, w c^a ---------------
+    T *xr = (T *)smem_raw;
+    double *red = (double *)(smem_raw + red_offset<T>((size_t)XREC * nx));
+    for (int j = threadIdx.x; j < nx; j += BLOCK) {
+        const double x = C.xv[j], c = x - P.u[0], w = C.wv[j];
+        const double ca = x - Fa.u[0], cb = x - Fb.u[0];
+        T *r = xr + XREC * j;
+        r[0] = (T)c;
+        r[1] = (T)exp(-ca * ca * Fa.it);
+        r[2] = (T)(Fa.fx[0] + Fa.fx[1] * ca + Fa.fx[4] * ca * ca);
+        r[3] = (T)exp(-cb * cb * Fb.it);
+        r[4] = (T)(Fb.fx[0] + Fb.fx[1] * cb + Fb.fx[4] * cb * cb);
+        r[5] = (T)w;
+        r[6] = (T)(w * c);
+        r[7] = (T)(w * c * c);
+        r[8] = (T)(w * c * c * c);
+    }
+
+    // ---- lane constants (FP64, rounded once) ---------------------------------
+    const double yv = C.xv[MAXA + iy];
+    const double cyd = yv - P.u[1];
+    const double ya = yv - Fa.u[1], yb = yv - Fb.u[1];
+    const double Eya = exp(-ya * ya * Fa.it), Pya = Fa.fx[2] * ya + Fa.fx[4] * ya * ya;
+    const double Eyb = exp(-yb * yb * Fb.it), Pyb = Fb.fx[2] * yb + Fb.fx[4] * yb * yb;
+    T EA[4], PA[4], EB[4], PB[4], wz[4], cz[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            czj[j] = C.xv[2 * MAXA + iz0 + j] - P.u[2];
-            wj[j] = wyd * C.wv[2 * MAXA + iz0 + j];
-        }
-        // row sums (DPP) of 16 lanes, written by the first lane of each row;
-        // the 16 rows of the block are added in order below
-        auto put = [&](int i, double x) {
-            x = row_sum16(x);
-            if ((lane & 15) == 0) red[(wave * 4 + (lane >> 4)) * NSUM + i] = x;
-        };
-        double a, b2, c2, d;
-        // mass, and the y moments that are lane constants times it
-        a = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        const double zv = C.xv[2 * MAXA + iz0 + j];
+        const double za = zv - Fa.u[2], zb = zv - Fb.u[2];
+        EA[j] = (T)(Eya * exp(-za * za * Fa.it));
+        PA[j] = (T)(Pya + Fa.fx[3] * za + Fa.fx[4] * za * za);
+        EB[j] = (T)(Eyb * exp(-zb * zb * Fb.it));
+        PB[j] = (T)(Pyb + Fb.fx[3] * zb + Fb.fx[4] * zb * zb);
+        wz[j] = (T)C.wv[2 * MAXA + iz0 + j];
+        cz[j] = (T)(zv - P.u[2]);
+    }
+
+    // ---- wall faces: a = (xi.n) S/V = n_x c_x + (n_y c_y + u.n) + n_z c_z ------
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    int fwall[NF];
+    T fnx[NF], fnzT[NF], BL[NF];
+    int nw = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) a += wj[j] * (double)S0[j];
-        put(0, a);
-        put(2, cyd * a);
-        put(5, cyd * cyd * a);
-        // x moments
-        b2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b2 += wj[j] * (double)S1[j];
-        put(1, b2);
-        put(7, cyd * b2);
-        c2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c2 += wj[j] * (double)S2[j];
-        put(4, c2);
-        // z moments
-        a = 0.0;
-        d = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            a += wj[j] * czj[j] * (double)S0[j];
-            d += wj[j] * czj[j] * czj[j] * (double)S0[j];
-        }
-        put(3, a);
-        put(9, cyd * a);
-        put(6, d);
-        a = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a += wj[j] * czj[j] * (double)S1[j];
-        put(8, a);
-        // heat-flux sums c^2 c_d
-        a = 0.0;
-        d = 0.0;
-        b2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double yz2 = cyd * cyd + czj[j] * czj[j];
-            const double e2 = wj[j] * ((double)S2[j] + yz2 * (double)S0[j]);
-            a += wj[j] * ((double)S3[j] + yz2 * (double)S1[j]);
-            d += e2;
-            b2 += czj[j] * e2;
-        }
-        put(10, a);
-        put(11, cyd * d);
-        put(12, b2);
-        // moment balance
-        a = 0.0;
-        d = 0.0;
-        b2 = 0.0;
-        c2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double yz2 = cyd * cyd + czj[j] * czj[j];
-            a += wj[j] * (double)R0[j];
-            d += wj[j] * (double)R1[j];
-            b2 += wj[j] * czj[j] * (double)R0[j];
-            c2 += wj[j] * ((double)R2[j] + yz2 * (double)R0[j]);
-        }
-        put(S_RES, a);
-        put(S_RES + 1, d);
-        put(S_RES + 2, cyd * a);
-        put(S_RES + 3, b2);
-        put(S_RES + 4, c2);
-        // outgoing wall fluxes (weights w_x w_z in the sums, w_y here)
-#pragma unroll
-        for (int q2 = 0; q2 < MAXW; ++q2) {
-            double sw = 0.0;
-            if (WALLS) {
-#pragma unroll
-                for (int l = 0; l < NF; ++l) sw += (fwall[l] == q2) ? (double)Wf[l] : 0.0;
+    for (int l = 0; l < NF; ++l) {
+        fwall[l] = -1;
+        fnx[l] = fnzT[l] = BL[l] = (T)0;
+        if (l < nf) {
+            const int e = e0 + l;
+            fwall[l] = C.cf_wall[e];
+            if (fwall[l] >= 0) {
+                const double n0 = C.cf_nsv[3 * e], n1 = C.cf_nsv[3 * e + 1], n2 = C.cf_nsv[3 * e + 2];
+                fnx[l] = (T)n0;
+                fnzT[l] = (T)n2;
+                BL[l] = (T)(n1 * cyd + (P.u[0] * n0 + P.u[1] * n1 + P.u[2] * n2));
+                ++nw;
             }
-            put(S_WALL + q2, wyd * sw);
         }
-        for (int i = S_WALL + MAXW; i < NSUM; ++i) put(i, 0.0);
-        __syncthreads();
-        if (threadIdx.x < NSUM) {
-            double acc = 0.0;
-            for (int r = 0; r < BLOCK / 16; ++r) acc += red[r * NSUM + threadIdx.x];
-            C.partial[((size_t)slot * C.ntile + vt) * NSUM + threadIdx.x] = acc;
+    }
+    __syncthreads();
+
+    T S0[4], S1[4], S2[4], S3[4], Z[4], Wf[NF];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S0[j] = S1[j] = S2[j] = S3[j] = Z[j] = (T)0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) Wf[l] = (T)0;
+
+    const int ix0 = vt * C.xp, ix1 = min(ix0 + C.xp, nx);
+    const uint32_t plane_bytes = (uint32_t)(ny * nz * sizeof(T));
+    const uint32_t lane_bytes = (uint32_t)(4 * pr * sizeof(T));
+    gptr<V4> f_u = (gptr<V4>)uniform_ptr(fr);
+
+    auto planes = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+        constexpr int UU = WALLS ? 1 : CORRECT_V4_U;
+        for (int ixr = ix0 + xg; ixr < ix1; ixr += UU * G) {
+            V4 o[UU];
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int ixc = min(ixr + u * G, ix1 - 1);
+                o[u] = ldb(gcptr<V4>(f_u), (uint32_t)ixc * plane_bytes + lane_bytes);
+            }
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int ix = ixr + u * G;
+                if (ix >= ix1) break;
+                const T *rx = xr + XREC * ix;
+                const T cx = rx[0], Exa = rx[1], Pxa = rx[2], Exb = rx[3], Pxb = rx[4];
+                const T wx = rx[5], wx1 = rx[6], wx2 = rx[7], wx3 = rx[8];
+                V4 outv;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T fv = o[u][j] + (Exa * EA[j] * (Pxa + PA[j]) - Exb * EB[j] * (Pxb + PB[j]));
+                    outv[j] = fv;
+                    S0[j] = fma(wx, fv, S0[j]);
+                    S1[j] = fma(wx1, fv, S1[j]);
+                    S2[j] = fma(wx2, fv, S2[j]);
+                    S3[j] = fma(wx3, fv, S3[j]);
+                    if constexpr (WALLS) {
+                        const T hw = (wx * wz[j]) * fv;
+#pragma unroll
+                        for (int l = 0; l < NF; ++l)
+                            if (fwall[l] >= 0) {
+                                const T a = fma(fnzT[l], cz[j], fnx[l] * cx + BL[l]);
+                                Wf[l] = fma(hw, fmax(a, (T)0), Wf[l]);
+                            }
+                    }
+                }
+                stb(f_u, (uint32_t)ix * plane_bytes + lane_bytes, outv);
+            }
         }
+    };
+    auto epilogue = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(S0[j]), "+v"(S1[j]), "+v"(S2[j]), "+v"(S3[j]));
+        if (WALLS) {
+#pragma unroll
+            for (int l = 0; l < NF; ++l) asm volatile("" : "+v"(Wf[l]));
+        }
+        v4_partials<T, NF, WALLS>(S0, S1, S2, S3, Z, Z, Z, Wf, fwall, C, P.u[2], cyd, iy, iz0, red,
+                                  C.partial + ((size_t)slot * C.ntile + vt) * NSUM);
     };
     if (nw > 0) {
         planes(std::true_type{});
@@ -1345,8 +1534,33 @@ void launch_correct_t(const CaseView *cv, const CaseView &h, int n_kin, int cur,
     else launch_correct_u<T, VD, 1>(cv, h, n_kin, cur, s);
 }
 
+// 16-byte rows for the correction where the sweep takes them (GSIS_CORRECT_V4=0
+// keeps 4-byte rows)
+static bool correct_v4_on()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GSIS_CORRECT_V4");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
+template <typename T>
+void launch_correct_v4(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
+{
+    const size_t lds = red_offset<T>((size_t)XREC * h.n[0]) + sizeof(double) * (BLOCK / 16) * NSUM;
+    const dim3 g(n_kin * h.ntile);
+    if (h.nfmax <= 4) hipLaunchKernelGGL((k_correct_v4<T, 4>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+    else hipLaunchKernelGGL((k_correct_v4<T, MAXF>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+}
+
 hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
 {
+    if (h.vdim == 3 && sweep_v4_fits(h.n[1], h.n[2]) && correct_v4_on()) {
+        if (h.dtype == GSIS_F32) launch_correct_v4<float>(cv, h, n_kin, cur, s);
+        else launch_correct_v4<double>(cv, h, n_kin, cur, s);
+        return hipGetLastError();
+    }
     if (h.dtype == GSIS_F32) {
         if (h.vdim == 3) launch_correct_t<float, 3>(cv, h, n_kin, cur, s);
         else launch_correct_t<float, 2>(cv, h, n_kin, cur, s);
