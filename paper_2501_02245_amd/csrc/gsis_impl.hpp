@@ -292,6 +292,7 @@ hipError_t launch_axtab(const CaseView *cv, const CaseView &h, int n_kin, hipStr
 hipError_t launch_amax(const CaseView *cv, const CaseView &h, hipStream_t s);
 hipError_t launch_slope(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
+bool launch_correct_poly_v4(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s);
 hipError_t launch_patch_rows(const CaseView *cv, const CaseView &h, hipStream_t s);
 hipError_t launch_ghost_rows(const CaseView *cv, const CaseView &h, int n_ghost, hipStream_t s);

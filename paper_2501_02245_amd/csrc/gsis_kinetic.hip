@@ -2292,6 +2292,7 @@ hipError_t launch_correct(const CaseView *cv, const CaseView &h, int n_kin, int 
 {
     if (n_kin <= 0) return hipSuccess;
     if (h.poly) {
+        if (launch_correct_poly_v4(cv, h, n_kin, cur, s)) return hipGetLastError();
         const dim3 g(n_kin * h.ntile);
         if (h.dtype == GSIS_F32) hipLaunchKernelGGL((k_correct_poly<float>), g, dim3(BLOCK), 0, s, cv, n_kin, cur);
         else hipLaunchKernelGGL((k_correct_poly<double>), g, dim3(BLOCK), 0, s, cv, n_kin, cur);

@@ -601,6 +601,27 @@ __device__ __forceinline__ double to_uniform(double x)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Block sums of N per-lane FP64 values: DPP row sums of 16 lanes, then the
+// block's rows added in a fixed order by thread i < N into out[i].  red holds
+// (BLOCK / 16) N doubles; it is free again after the call.
+template <int N>
+__device__ __forceinline__ void v4_block_sums(const double (&x)[N], double *red, double *out)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();   // red may still be read by an earlier reduction
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const double v = row_sum16(x[i]);
+        if ((lane & 15) == 0) red[(wave * 4 + (lane >> 4)) * N + i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double acc = 0.0;
+        for (int r = 0; r < BLOCK / 16; ++r) acc += red[r * N + threadIdx.x];
+        out[threadIdx.x] = acc;
+    }
+}
+
 // Epilogue of the 16-byte-row plane kernels.  A lane holds, per node j of its
 // four z nodes, FP32 sums over the x-planes of w_x c_x^a f (a = 0..3) in S0..S3,
 // the sweep's balance sums in R0..R2 (zero for the correction) and, for cells
@@ -1167,6 +1188,189 @@ k_correct_v4(const CaseView *__restrict__ cvp, int n_kin, int cur)
 }
 
 // ---------------------------------------------------------------------------
+// Correction of the two-VDF gas (Sec. 3.1, eq. updatef with rho e_r) in the
+// 16-byte-row plane layout: per node m_a = f_eq(W^{n+1}) and m_b = f_eq(W^{n+1/2})
+// as in k_correct_v4; f0 += m_a - m_b and f1 += th_a m_a - th_b m_b with
+// th = d_r T_r / 4 of each state.  Rows hold (f0, f1) with f1 at nvp = row / 2.
+// Sums: those of f0 as in the sweep, and of f1 sum w f1, sum w c f1 (PSUM, the
+// last entry, the sweep's balance, zero).  A tile must cover whole x-planes.
+// ---------------------------------------------------------------------------
+template <typename T, int NF>
+__global__ __launch_bounds__(BLOCK) __attribute__((
+    amdgpu_waves_per_eu(sizeof(T) == 4 ? (NF <= 4 ? CORRECT_V4_WAVES : 2) : 1))) void k_correct_poly_v4(const CaseView *__restrict__ cvp, int n_kin, int cur)
+{
+    typedef typename Vec4T<T>::v V4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const CaseView &C = *cvp;
+    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int vt = b / n_kin, t = b - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const FeqRec &Fa = C.feq[2 * (size_t)slot];
+    const FeqRec &Fb = C.feq[2 * (size_t)slot + 1];
+    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
+    gptr<T> fr = (gptr<T>)C.f[cur] + (size_t)slot * C.row;
+    const int Q = nz >> 2, PL = ny * Q, G = BLOCK / PL;
+    const int xg = threadIdx.x / PL, pr = threadIdx.x - xg * PL;
+    const int iy = pr / Q, iz0 = 4 * (pr - iy * Q);
+
+    T *xr = (T *)smem_raw;
+    double *red = (double *)(smem_raw + red_offset<T>((size_t)XREC * nx));
+    for (int j = threadIdx.x; j < nx; j += BLOCK) {
+        const double x = C.xv[j], c = x - P.u[0], w = C.wv[j];
+        const double ca = x - Fa.u[0], cb = x - Fb.u[0];
+        T *r = xr + XREC * j;
+        r[0] = (T)c;
+        r[1] = (T)exp(-ca * ca * Fa.it);
+        r[2] = (T)(Fa.fx[0] + Fa.fx[1] * ca + Fa.fx[4] * ca * ca);
+        r[3] = (T)exp(-cb * cb * Fb.it);
+        r[4] = (T)(Fb.fx[0] + Fb.fx[1] * cb + Fb.fx[4] * cb * cb);
+        r[5] = (T)w;
+        r[6] = (T)(w * c);
+        r[7] = (T)(w * c * c);
+        r[8] = (T)(w * c * c * c);
+    }
+    const double yv = C.xv[MAXA + iy];
+    const double cyd = yv - P.u[1];
+    const double ya = yv - Fa.u[1], yb = yv - Fb.u[1];
+    const double Eya = exp(-ya * ya * Fa.it), Pya = Fa.fx[2] * ya + Fa.fx[4] * ya * ya;
+    const double Eyb = exp(-yb * yb * Fb.it), Pyb = Fb.fx[2] * yb + Fb.fx[4] * yb * yb;
+    T EA[4], PA[4], EB[4], PB[4], wz[4], cz[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double zv = C.xv[2 * MAXA + iz0 + j];
+        const double za = zv - Fa.u[2], zb = zv - Fb.u[2];
+        EA[j] = (T)(Eya * exp(-za * za * Fa.it));
+        PA[j] = (T)(Pya + Fa.fx[3] * za + Fa.fx[4] * za * za);
+        EB[j] = (T)(Eyb * exp(-zb * zb * Fb.it));
+        PB[j] = (T)(Pyb + Fb.fx[3] * zb + Fb.fx[4] * zb * zb);
+        wz[j] = (T)C.wv[2 * MAXA + iz0 + j];
+        cz[j] = (T)(zv - P.u[2]);
+    }
+    const T tha = (T)Fa.Th, thb = (T)Fb.Th;
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    int fwall[NF];
+    T fnx[NF], fnzT[NF], BL[NF];
+    int nw = 0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fwall[l] = -1;
+        fnx[l] = fnzT[l] = BL[l] = (T)0;
+        if (l < nf) {
+            const int e = e0 + l;
+            fwall[l] = C.cf_wall[e];
+            if (fwall[l] >= 0) {
+                const double n0 = C.cf_nsv[3 * e], n1 = C.cf_nsv[3 * e + 1], n2 = C.cf_nsv[3 * e + 2];
+                fnx[l] = (T)n0;
+                fnzT[l] = (T)n2;
+                BL[l] = (T)(n1 * cyd + (P.u[0] * n0 + P.u[1] * n1 + P.u[2] * n2));
+                ++nw;
+            }
+        }
+    }
+    __syncthreads();
+
+    T S0[4], S1[4], S2[4], S3[4], Q0[4], Q1[4], Z[4], Wf[NF];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S0[j] = S1[j] = S2[j] = S3[j] = Q0[j] = Q1[j] = Z[j] = (T)0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) Wf[l] = (T)0;
+
+    // the tile's x-planes (tiles cover whole planes)
+    const int P2 = ny * nz;
+    const int ix0 = (vt * C.tile) / P2, ix1 = min(nx, ((vt + 1) * C.tile) / P2);
+    const uint32_t plane_bytes = (uint32_t)(P2 * sizeof(T));
+    const uint32_t lane_bytes = (uint32_t)(4 * pr * sizeof(T));
+    const uint32_t f1_bytes = (uint32_t)((C.row / 2) * sizeof(T));
+    gptr<V4> f_u = (gptr<V4>)uniform_ptr(fr);
+
+    auto planes = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+        constexpr int UU = WALLS ? 1 : 2;
+        for (int ixr = ix0 + xg; ixr < ix1; ixr += UU * G) {
+            V4 o0[UU], o1[UU];
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const uint32_t off = (uint32_t)min(ixr + u * G, ix1 - 1) * plane_bytes + lane_bytes;
+                o0[u] = ldb(gcptr<V4>(f_u), off);
+                o1[u] = ldb(gcptr<V4>(f_u), off + f1_bytes);
+            }
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int ix = ixr + u * G;
+                if (ix >= ix1) break;
+                const T *rx = xr + XREC * ix;
+                const T cx = rx[0], Exa = rx[1], Pxa = rx[2], Exb = rx[3], Pxb = rx[4];
+                const T wx = rx[5], wx1 = rx[6], wx2 = rx[7], wx3 = rx[8];
+                V4 out0, out1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T ma = Exa * EA[j] * (Pxa + PA[j]), mb = Exb * EB[j] * (Pxb + PB[j]);
+                    const T v0 = o0[u][j] + (ma - mb);
+                    const T v1 = o1[u][j] + (tha * ma - thb * mb);
+                    out0[j] = v0;
+                    out1[j] = v1;
+                    S0[j] = fma(wx, v0, S0[j]);
+                    S1[j] = fma(wx1, v0, S1[j]);
+                    S2[j] = fma(wx2, v0, S2[j]);
+                    S3[j] = fma(wx3, v0, S3[j]);
+                    Q0[j] = fma(wx, v1, Q0[j]);
+                    Q1[j] = fma(wx1, v1, Q1[j]);
+                    if constexpr (WALLS) {
+                        const T hw = (wx * wz[j]) * v0;
+#pragma unroll
+                        for (int l = 0; l < NF; ++l)
+                            if (fwall[l] >= 0) {
+                                const T a = fma(fnzT[l], cz[j], fnx[l] * cx + BL[l]);
+                                Wf[l] = fma(hw, fmax(a, (T)0), Wf[l]);
+                            }
+                    }
+                }
+                const uint32_t off = (uint32_t)ix * plane_bytes + lane_bytes;
+                stb(f_u, off, out0);
+                stb(f_u, off + f1_bytes, out1);
+            }
+        }
+    };
+    auto epilogue = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            asm volatile("" : "+v"(S0[j]), "+v"(S1[j]), "+v"(S2[j]), "+v"(S3[j]));
+            asm volatile("" : "+v"(Q0[j]), "+v"(Q1[j]));
+        }
+        if (WALLS) {
+#pragma unroll
+            for (int l = 0; l < NF; ++l) asm volatile("" : "+v"(Wf[l]));
+        }
+        v4_partials<T, NF, WALLS>(S0, S1, S2, S3, Z, Z, Z, Wf, fwall, C, P.u[2], cyd, iy, iz0, red,
+                                  C.partial + ((size_t)slot * C.ntile + vt) * NSUM);
+        // the sums of f1: sum w f1 and sum w c f1, then the balance entry (zero)
+        const double wyd = C.wv[MAXA + iy];
+        double q[PSUM] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double wj = wyd * C.wv[2 * MAXA + iz0 + j];
+            const double czj = C.xv[2 * MAXA + iz0 + j] - P.u[2];
+            q[0] += wj * (double)Q0[j];
+            q[1] += wj * (double)Q1[j];
+            q[3] += wj * czj * (double)Q0[j];
+        }
+        q[2] = cyd * q[0];
+        v4_block_sums<PSUM>(q, red, C.psum + ((size_t)slot * C.ntile + vt) * PSUM);
+    };
+    if (nw > 0) {
+        planes(std::true_type{});
+        epilogue(std::true_type{});
+    } else {
+        planes(std::false_type{});
+        epilogue(std::false_type{});
+    }
+}
+
+// ---------------------------------------------------------------------------
 // GSIS correction (Sec. 3.1): f += f_eq(W^{n+1}) - f_eq(W^{n+1/2}) on the plane
 // layout, with the same fused moment and wall sums as the sweep.  Both f_eq
 // are conservation-fixed Maxwellians, separable per axis: E = E_x E_y E_z and
@@ -1552,6 +1756,25 @@ void launch_correct_v4(const CaseView *cv, const CaseView &h, int n_kin, int cur
     const dim3 g(n_kin * h.ntile);
     if (h.nfmax <= 4) hipLaunchKernelGGL((k_correct_v4<T, 4>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
     else hipLaunchKernelGGL((k_correct_v4<T, MAXF>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+}
+
+// the two-VDF correction in 16-byte rows, where the tile covers whole
+// x-planes; false leaves the case to the per-node kernel
+bool launch_correct_poly_v4(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
+{
+    if (!(h.vdim == 3 && sweep_v4_fits(h.n[1], h.n[2]) && h.tile % (h.n[1] * h.n[2]) == 0 && correct_v4_on()))
+        return false;
+    const dim3 g(n_kin * h.ntile);
+    if (h.dtype == GSIS_F32) {
+        const size_t lds = red_offset<float>((size_t)XREC * h.n[0]) + sizeof(double) * (BLOCK / 16) * NSUM;
+        if (h.nfmax <= 4) hipLaunchKernelGGL((k_correct_poly_v4<float, 4>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct_poly_v4<float, MAXF>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+    } else {
+        const size_t lds = red_offset<double>((size_t)XREC * h.n[0]) + sizeof(double) * (BLOCK / 16) * NSUM;
+        if (h.nfmax <= 4) hipLaunchKernelGGL((k_correct_poly_v4<double, 4>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+        else hipLaunchKernelGGL((k_correct_poly_v4<double, MAXF>), g, dim3(BLOCK), lds, s, cv, n_kin, cur);
+    }
+    return true;
 }
 
 hipError_t launch_correct_fast(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
