@@ -206,6 +206,18 @@ struct CaseView {
     double *fr, *hfr, *hotr, *gTr, *ghr;
 };
 
+// Logical index of workgroup b of nb.  Workgroups are dispatched round-robin
+// over the 8 XCDs; this gives XCD x the contiguous range [x q + min(x, rem), ...)
+// of logical blocks, so that the work of neighbouring blocks (cells of a
+// locality-ordered mesh, their rows and faces) shares that XCD's L2.  A
+// bijection on [0, nb): blocks keep their work, so results do not change.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int X = 8;
+    const int x = b % X, r = b / X, q = nb / X, rem = nb % X;
+    return x * q + min(x, rem) + r;
+}
+
 struct Batch {
     const CaseView *cv[MAX_BATCH];
     int32_t start[MAX_BATCH + 1];   // prefix of work items (blocks) per case

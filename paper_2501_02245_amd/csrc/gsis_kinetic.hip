@@ -26,15 +26,6 @@ namespace gsis {
 
 enum { K_KIN = 0, K_WALL = 1, K_FAR = 2, K_GHOST = 3 };
 
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    // Workgroups are dispatched round-robin over 8 XCDs; give XCD x the
-    // contiguous logical range [x q + min(x, rem), ...).
-    const int X = 8;
-    int x = b % X, r = b / X, q = nb / X, rem = nb % X;
-    return x * q + min(x, rem) + r;
-}
-
 template <int NS>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NS], double *out, double *lds)
 {

@@ -39,17 +39,8 @@ __device__ __forceinline__ double bfield(const CaseView &C, int p, int v)
     return sqrt(ps[1] * ps[1] + ps[2] * ps[2] + ps[3] * ps[3]);
 }
 
-// Logical block index of the cell and face kernels.  Workgroups are
-// dispatched round-robin over the 8 XCDs; this gives XCD x the contiguous
-// range [x q + min(x, rem), ...) of blocks, so that the cells and faces of a
-// locality-ordered mesh handled on one XCD share its L2.  A bijection on
-// [0, gridDim.x); blocks keep their cells and faces, so results do not change.
-__device__ __forceinline__ int mblk()
-{
-    const int X = 8, b = blockIdx.x, nb = gridDim.x;
-    const int x = b % X, r = b / X, q = nb / X, rem = nb % X;
-    return x * q + min(x, rem) + r;
-}
+// logical block index of the cell and face kernels (XCD-contiguous ranges)
+__device__ __forceinline__ int mblk() { return xcd_remap(blockIdx.x, gridDim.x); }
 
 // case of a block in a batched launch (block-uniform)
 __device__ __forceinline__ int mb_case(const int32_t *start, int n)

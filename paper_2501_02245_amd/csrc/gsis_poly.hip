@@ -112,20 +112,31 @@ __device__ double cell_D_poly(const CaseView &C, int i, const double *Wi, double
 
 // least-squares gradient of T_r (the coefficients of the other fields; a
 // boundary face contributes the patch temperature)
-__global__ void k_lsq_tr(const CaseView *__restrict__ cvp, const double *__restrict__ Tr)
+// one lane per face of a cell (G lanes per cell, MCELLS_Q cells per block);
+// the lanes' terms are added in a fixed tree order
+template <int G>
+__global__ __launch_bounds__(MCELLS_Q * G) void k_lsq_tr(const CaseView *__restrict__ cvp, const double *__restrict__ Tr)
 {
     const CaseView &C = *cvp;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= C.n_cells) return;
-    double g[3] = {0.0, 0.0, 0.0};
+    const int i = xcd_remap(blockIdx.x, gridDim.x) * MCELLS_Q + (int)threadIdx.x / G;
+    const int l = (int)threadIdx.x % G;
+    if (i >= C.n_cells) return;   // whole groups leave together
     const double ti = Tr[i];
-    for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
+    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
+    double g[3] = {0.0, 0.0, 0.0};
+    if (l < nf) {
+        const int e = e0 + l;
         const int o = C.cf_other[e];
         const double to = (o >= 0) ? Tr[o] : C.patch_state[5 * (-1 - o) + 4];
         const double *ca = C.lsq + 3 * (size_t)e;
-        for (int d = 0; d < 3; ++d) g[d] += ca[d] * (to - ti);
+        for (int d = 0; d < 3; ++d) g[d] = ca[d] * (to - ti);
     }
-    for (int d = 0; d < 3; ++d) C.gTr[3 * (size_t)i + d] = g[d];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[d] += __shfl_xor(g[d], off, G);
+    if (l == 0)
+        for (int d = 0; d < 3; ++d) C.gTr[3 * (size_t)i + d] = g[d];
 }
 
 // Grad-13 parameters of the two-VDF gas: (rho, u, T_t, sigma, q_t) in ghost,
@@ -226,7 +237,7 @@ __global__ void k_face_flux_p(const CaseView *__restrict__ cvp, const double *__
                               const double *__restrict__ Tr)
 {
     const CaseView &C = *cvp;
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= C.n_faces) return;
     const int L = C.face_cells[2 * f], Rc = C.face_cells[2 * f + 1];
     const double *n = C.face_normal + 3 * (size_t)f;
@@ -396,22 +407,61 @@ __global__ __launch_bounds__(256) void k_min_p(const CaseView *__restrict__ cvp,
 // moments and rho e_r (src: the case's src and srcr, or none), then the
 // exchange backward-Euler at the new total energy; halved (at most ten times)
 // while rho, T_t or T_r would not be positive
-__global__ void k_update_p(const CaseView *__restrict__ cvp, double *__restrict__ W, double *__restrict__ Tr,
-                           const double *__restrict__ src, double cfl)
+// one lane per face of a cell (G lanes, MCELLS_Q cells per block): the flux
+// balance and sum_f |u.n| S/V in a fixed tree order, then lane 0 steps the cell
+template <int G>
+__global__ __launch_bounds__(MCELLS_Q * G) void k_update_p(const CaseView *__restrict__ cvp, double *__restrict__ W,
+                                                           double *__restrict__ Tr, const double *__restrict__ src,
+                                                           double cfl)
 {
     const CaseView &C = *cvp;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= C.n_cells) return;
+    const int i = xcd_remap(blockIdx.x, gridDim.x) * MCELLS_Q + (int)threadIdx.x / G;
+    const int l = (int)threadIdx.x % G;
+    if (i >= C.n_cells) return;   // whole groups leave together
     double *Wi = W + 5 * (size_t)i;
-    double R[6];
-    balance_p(C, i, R);
+    double Wc[5];
+    for (int c = 0; c < 5; ++c) Wc[c] = Wi[c];
+    const double tri = Tr[i];
+    const int e0 = C.cf_ptr[i], nf = C.cf_ptr[i + 1] - e0;
+    double R[6] = {0, 0, 0, 0, 0, 0}, un = 0.0;
+    if (l < nf) {
+        const int e = e0 + l;
+        const int f = C.cf_face[e];
+        const double fs = C.cf_fs[e];   // -S if i owns the face, +S otherwise
+        for (int c = 0; c < 5; ++c) R[c] = C.fflux[5 * (size_t)f + c] * fs;
+        R[5] = C.fr[f] * fs;
+        const double *n = C.cf_nsv + 3 * (size_t)e;
+        un = fabs(Wc[1] * n[0] + Wc[2] * n[1] + Wc[3] * n[2]);
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) R[c] += __shfl_xor(R[c], off, G);
+        un += __shfl_xor(un, off, G);
+    }
+    if (l != 0) return;
     const double V = C.cell_volume[i];
     if (src) {
         for (int c = 0; c < 5; ++c) R[c] += src[5 * (size_t)i + c] * V;
         R[5] += C.srcr[i] * V;
     }
-    double k = (cfl < 0) ? (-cfl * C.red[0]) / V : cfl / cell_D_poly(C, i, Wi, Tr[i]);
-    const double x0 = V / (C.Zr * tau_of(C, Wi[0], Wi[4]));   // dt/(Z_r tau) = k x0
+    double k;
+    if (cfl < 0) {
+        k = (-cfl * C.red[0]) / V;
+    } else {
+        // D_i = sum_f S_f (|u_n| + a + 2 nu / d_f), a = sqrt(gamma T/2), gamma = (5 + d_r)/(3 + d_r),
+        // nu = max(4/3, 2 k_t/3, 2 k_r/d_r) Kn T_t^omega/(sqrt(pi) rho)
+        double kt, kr;
+        cond_factors(C, kt, kr);
+        const double T = (3.0 * Wc[4] + C.dr * tri) / (3.0 + C.dr);
+        const double gam = (5.0 + C.dr) / (3.0 + C.dr);
+        const double a = sqrt(gam * T / 2.0);
+        const double nu = fmax(4.0 / 3.0, fmax(2.0 * kt / 3.0, 2.0 * kr / C.dr)) * C.Kn * pow(Wc[4], C.omega) /
+                          (sqrt(M_PI) * Wc[0]);
+        const double *sS = C.cell_sS + 2 * (size_t)i;
+        k = cfl / (V * un + a * sS[0] + 2.0 * nu * sS[1]);
+    }
+    const double x0 = V / (C.Zr * tau_of(C, Wc[0], Wc[4]));   // dt/(Z_r tau) = k x0
     double *U = C.U + 5 * (size_t)i;
     const double dr = C.dr;
     double Un[6], Pn[5], Trn = 0.0;
@@ -438,7 +488,9 @@ __global__ void k_update_p(const CaseView *__restrict__ cvp, double *__restrict_
         C.Ur[i] = Un[5];
         Tr[i] = Trn;
     }
-    if (!isfinite(Wi[0] + Wi[1] + Wi[2] + Wi[3] + Wi[4] + Tr[i])) atomicOr(C.status, 1);
+    const double *Wf = ok ? Pn : Wc;
+    const double tf = ok ? Trn : tri;
+    if (!isfinite(Wf[0] + Wf[1] + Wf[2] + Wf[3] + Wf[4] + tf)) atomicOr(C.status, 1);
 }
 
 __global__ void k_tt(const CaseView *__restrict__ cvp, double *__restrict__ out)
@@ -452,6 +504,23 @@ __global__ void k_copy_dd(double *d, const double *s, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) d[i] = s[i];
+}
+
+// the lane-per-face cell kernels: blocks of MCELLS_Q cells covering n_cells,
+// G = 4 lanes per cell on tetrahedral meshes, else GSIS_MAX_FACES
+void lsq_tr(const CaseView *cv, int n_cells, int nfmax, const double *Tr, hipStream_t s)
+{
+    const dim3 g((n_cells + MCELLS_Q - 1) / MCELLS_Q);
+    if (nfmax <= 4) hipLaunchKernelGGL((k_lsq_tr<4>), g, dim3(MCELLS_Q * 4), 0, s, cv, Tr);
+    else hipLaunchKernelGGL((k_lsq_tr<MAXF>), g, dim3(MCELLS_Q * MAXF), 0, s, cv, Tr);
+}
+
+void update_p(const CaseView *cv, int n_cells, int nfmax, double *W, double *Tr, const double *src, double cfl,
+              hipStream_t s)
+{
+    const dim3 g((n_cells + MCELLS_Q - 1) / MCELLS_Q);
+    if (nfmax <= 4) hipLaunchKernelGGL((k_update_p<4>), g, dim3(MCELLS_Q * 4), 0, s, cv, W, Tr, src, cfl);
+    else hipLaunchKernelGGL((k_update_p<MAXF>), g, dim3(MCELLS_Q * MAXF), 0, s, cv, W, Tr, src, cfl);
 }
 
 }  // namespace
@@ -472,7 +541,7 @@ hipError_t launch_tt_copy(const CaseView *cv, const CaseView &h, double *out, hi
 hipError_t launch_ghost_poly(const CaseView *cv, const CaseView &h, const double *W, const double *Tr, hipStream_t s)
 {
     const dim3 g((h.n_cells + 127) / 128);
-    hipLaunchKernelGGL(k_lsq_tr, g, dim3(128), 0, s, cv, Tr);
+    lsq_tr(cv, h.n_cells, h.nfmax, Tr, s);
     hipLaunchKernelGGL(k_ghost_p, g, dim3(128), 0, s, cv, W, Tr);
     return hipGetLastError();
 }
@@ -480,7 +549,7 @@ hipError_t launch_ghost_poly(const CaseView *cv, const CaseView &h, const double
 hipError_t launch_hot_poly(const CaseView *cv, const CaseView &h, hipStream_t s)
 {
     const dim3 g((h.n_cells + 127) / 128);
-    hipLaunchKernelGGL(k_lsq_tr, g, dim3(128), 0, s, cv, (const double *)h.Trh);
+    lsq_tr(cv, h.n_cells, h.nfmax, (const double *)h.Trh, s);
     hipLaunchKernelGGL(k_hot_p, g, dim3(128), 0, s, cv);
     return hipGetLastError();
 }
@@ -497,7 +566,7 @@ hipError_t launch_macro_residual_poly(const CaseView *cv, const CaseView &h, con
     hipError_t e = launch_lsq(cv, h, W, 4, s);
     if (e != hipSuccess) return e;
     const dim3 gc((h.n_cells + 127) / 128), gf((h.n_faces + 127) / 128);
-    hipLaunchKernelGGL(k_lsq_tr, gc, dim3(128), 0, s, cv, Tr);
+    lsq_tr(cv, h.n_cells, h.nfmax, Tr, s);
     if (h.n_faces > 0) {
         hipLaunchKernelGGL(k_hot_face_p, gf, dim3(128), 0, s, cv, hot);
         hipLaunchKernelGGL(k_face_flux_p, gf, dim3(128), 0, s, cv, W, Tr);
@@ -539,14 +608,14 @@ hipError_t launch_macro_steps_poly(const MBatch &b, int n_inner, double cfl, hip
         for (int it = 0; it < n_inner; ++it) {
             hipError_t e = launch_lsq_batch(one, 4, s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_lsq_tr, gc, dim3(128), 0, s, cv, (const double *)Tr);
+            lsq_tr(cv, ncb * MBLOCK, b.nfmax, (const double *)Tr, s);
             if (nfb > 0)
                 hipLaunchKernelGGL(k_face_flux_p, gf, dim3(128), 0, s, cv, (const double *)W, (const double *)Tr);
             if (cfl < 0) {
                 hipLaunchKernelGGL(k_dloc_p, dim3(ncb), dim3(MBLOCK), 0, s, cv, (const double *)W, (const double *)Tr);
                 hipLaunchKernelGGL(k_min_p, dim3(1), dim3(256), 0, s, cv, ncb);
             }
-            hipLaunchKernelGGL(k_update_p, gc, dim3(128), 0, s, cv, W, Tr, src, cfl);
+            update_p(cv, ncb * MBLOCK, b.nfmax, W, Tr, src, cfl, s);
         }
     }
     return hipGetLastError();

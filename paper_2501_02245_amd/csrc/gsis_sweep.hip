@@ -51,13 +51,6 @@ using gcptr = const __attribute__((address_space(1))) T *;
 template <typename T>
 using gptr = __attribute__((address_space(1))) T *;
 
-__device__ __forceinline__ int xcd_remap2(int b, int nb)
-{
-    const int X = 8;
-    int x = b % X, r = b / X, q = nb / X, rem = nb % X;
-    return x * q + min(x, rem) + r;
-}
-
 // a wave-uniform pointer held in SGPRs (the value is the same in every lane)
 template <typename P>
 __device__ __forceinline__ P uniform_ptr(P p)
@@ -239,7 +232,7 @@ k_sweep_fast(Batch B)
     extern __shared__ __align__(16) unsigned char smem_raw[];
 
     // ---- locate the work item -------------------------------------------
-    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     int ci = 0;
     while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
     const CaseView &C = *B.cv[ci];
@@ -751,7 +744,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((
     typedef typename Vec4T<T>::v V4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // ---- locate the work item (as the plane kernel) -------------------------
-    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     int ci = 0;
     while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
     const CaseView &C = *B.cv[ci];
@@ -1040,7 +1033,7 @@ k_correct_v4(const CaseView *__restrict__ cvp, int n_kin, int cur)
     typedef typename Vec4T<T>::v V4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const CaseView &C = *cvp;
-    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int vt = b / n_kin, t = b - vt * n_kin;
     const int cell = C.kin_cell[t];
     const int slot = C.slot_of_cell[cell];
@@ -1202,7 +1195,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((
     typedef typename Vec4T<T>::v V4;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const CaseView &C = *cvp;
-    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int vt = b / n_kin, t = b - vt * n_kin;
     const int cell = C.kin_cell[t];
     const int slot = C.slot_of_cell[cell];
@@ -1383,7 +1376,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const CaseView &C = *cvp;
-    const int b = xcd_remap2(blockIdx.x, gridDim.x);
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int vt = b / n_kin, t = b - vt * n_kin;
     const int cell = C.kin_cell[t];
     const int slot = C.slot_of_cell[cell];
