@@ -649,19 +649,119 @@ __device__ __forceinline__ double ratio_lim(double num, double den)
 #define SLOPE_U 2
 #endif
 
+// LDS of the slope kernels' set-up (thread 0): the least-squares stencil of a
+// kinetic cell over its kinetic neighbours (coefficients c_j, face offsets r_j,
+// neighbour slots), the offsets of every face (ra_l) and the wall faces (FP64
+// normals, offsets, wall index); work arrays of the 3x3 solve
+template <typename T>
+struct SlopeSh {
+    T s_c[MAXF][3], s_r[MAXF][3], s_ra[MAXF][3];
+    int s_nb[MAXF];
+    double s_wn[MAXW][3];
+    T s_wr[MAXW][3];
+    int s_ww[MAXW];
+    int s_nk, s_nw, s_nf;
+    double red[(BLOCK / 64) * MAXW];
+    double dx[MAXF][3], iw[MAXF], A[9], I[9];
+};
+
+// thread 0: the stencil of `cell` (a neighbour set that does not span dim
+// gives no stencil: nk = 0, zero slopes)
+template <typename T>
+__device__ void slope_setup(const CaseView &C, int cell, int D, SlopeSh<T> &sh)
+{
+    T(&s_c)[MAXF][3] = sh.s_c;
+    T(&s_r)[MAXF][3] = sh.s_r;
+    T(&s_ra)[MAXF][3] = sh.s_ra;
+    int(&s_nb)[MAXF] = sh.s_nb;
+    double(&s_wn)[MAXW][3] = sh.s_wn;
+    T(&s_wr)[MAXW][3] = sh.s_wr;
+    int(&s_ww)[MAXW] = sh.s_ww;
+    double(&dx)[MAXF][3] = sh.dx;
+    double(&iw)[MAXF] = sh.iw;
+    double(&A)[9] = sh.A;
+    double(&I)[9] = sh.I;
+    const int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1];
+    const double *xc = C.cell_center + 3 * (size_t)cell;
+    for (int i = 0; i < 9; ++i) A[i] = I[i] = 0.0;
+    int nk = 0, nw = 0;
+    sh.s_nf = e1 - e0;
+    for (int e = e0; e < e1; ++e) {
+        const int oth = C.cf_other[e];
+        const double *fc = C.face_center + 3 * (size_t)C.cf_face[e];
+        for (int d = 0; d < 3; ++d) s_ra[e - e0][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
+        if (C.cf_wall[e] >= 0 && nw < MAXW) {
+            s_ww[nw] = C.cf_wall[e];
+            for (int d = 0; d < 3; ++d) {
+                s_wn[nw][d] = C.cf_nsv[3 * (size_t)e + d];
+                s_wr[nw][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
+            }
+            ++nw;
+        }
+        if (oth < 0 || C.slot_of_cell[oth] < 0) continue;
+        const double *xo = C.cell_center + 3 * (size_t)oth;
+        double r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            dx[nk][d] = (d < D) ? xo[d] - xc[d] : 0.0;
+            r2 += dx[nk][d] * dx[nk][d];
+        }
+        iw[nk] = 1.0 / r2;
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) A[a * D + b] += dx[nk][a] * dx[nk][b] * iw[nk];
+        s_nb[nk] = C.slot_of_cell[oth];
+        for (int d = 0; d < 3; ++d) s_r[nk][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
+        ++nk;
+    }
+    double tr = 0.0, det;
+    for (int d = 0; d < D; ++d) tr += A[d * D + d];
+    if (D == 1) {
+        det = A[0];
+        I[0] = 1.0 / A[0];
+    } else if (D == 2) {
+        det = A[0] * A[3] - A[1] * A[2];
+        I[0] = A[3] / det;
+        I[1] = -A[1] / det;
+        I[2] = -A[2] / det;
+        I[3] = A[0] / det;
+    } else {
+        const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+        det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+        I[0] = c00 / det;
+        I[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+        I[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+        I[3] = c01 / det;
+        I[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+        I[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+        I[6] = c02 / det;
+        I[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+        I[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+    }
+    const bool singular = nk == 0 || !(tr > 0.0) || det <= 1e-12 * pow(tr / D, (double)D);
+    if (singular) nk = 0;
+    for (int j = 0; j < nk; ++j)
+        for (int d = 0; d < 3; ++d) {
+            double c = 0.0;
+            if (d < D)
+                for (int b = 0; b < D; ++b) c += I[d * D + b] * dx[j][b] * iw[j];
+            s_c[j][d] = (T)c;
+        }
+    sh.s_nk = nk;
+    sh.s_nw = nw;
+}
+
 template <typename T, int NK>
 __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cvp, int n_kin, int cur)
 {
     const CaseView &C = *cvp;
-    __shared__ T s_c[MAXF][3], s_r[MAXF][3], s_ra[MAXF][3];
-    __shared__ int s_nb[MAXF];
-    __shared__ double s_wn[MAXW][3];
-    __shared__ T s_wr[MAXW][3];
-    __shared__ int s_ww[MAXW];
-    __shared__ int s_nk, s_nw, s_nf;
-    __shared__ double red[(BLOCK / 64) * MAXW];
-    // set-up work arrays of thread 0 (in LDS: runtime-indexed registers would spill)
-    __shared__ double dx[MAXF][3], iw[MAXF], A[9], I[9];
+    __shared__ SlopeSh<T> sh;
+    T(&s_c)[MAXF][3] = sh.s_c;
+    T(&s_r)[MAXF][3] = sh.s_r;
+    T(&s_ra)[MAXF][3] = sh.s_ra;
+    int(&s_nb)[MAXF] = sh.s_nb;
+    double(&s_wn)[MAXW][3] = sh.s_wn;
+    T(&s_wr)[MAXW][3] = sh.s_wr;
+    int(&s_ww)[MAXW] = sh.s_ww;
+    double *red = sh.red;
     // XCD-contiguous runs of cells: neighbour rows meet in the XCD's L2
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int vt = b / n_kin;
@@ -669,76 +769,9 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
     const int cell = C.kin_cell[t];
     const int slot = C.slot_of_cell[cell];
     const int D = C.dim;
-    if (threadIdx.x == 0) {
-        const int e0 = C.cf_ptr[cell], e1 = C.cf_ptr[cell + 1];
-        const double *xc = C.cell_center + 3 * (size_t)cell;
-        for (int i = 0; i < 9; ++i) A[i] = I[i] = 0.0;
-        int nk = 0, nw = 0;
-        s_nf = e1 - e0;
-        for (int e = e0; e < e1; ++e) {
-            const int oth = C.cf_other[e];
-            const double *fc = C.face_center + 3 * (size_t)C.cf_face[e];
-            for (int d = 0; d < 3; ++d) s_ra[e - e0][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
-            if (C.cf_wall[e] >= 0 && nw < MAXW) {
-                s_ww[nw] = C.cf_wall[e];
-                for (int d = 0; d < 3; ++d) {
-                    s_wn[nw][d] = C.cf_nsv[3 * (size_t)e + d];
-                    s_wr[nw][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
-                }
-                ++nw;
-            }
-            if (oth < 0 || C.slot_of_cell[oth] < 0) continue;
-            const double *xo = C.cell_center + 3 * (size_t)oth;
-            double r2 = 0.0;
-            for (int d = 0; d < 3; ++d) {
-                dx[nk][d] = (d < D) ? xo[d] - xc[d] : 0.0;
-                r2 += dx[nk][d] * dx[nk][d];
-            }
-            iw[nk] = 1.0 / r2;
-            for (int a = 0; a < D; ++a)
-                for (int b = 0; b < D; ++b) A[a * D + b] += dx[nk][a] * dx[nk][b] * iw[nk];
-            s_nb[nk] = C.slot_of_cell[oth];
-            for (int d = 0; d < 3; ++d) s_r[nk][d] = (T)(d < D ? fc[d] - xc[d] : 0.0);
-            ++nk;
-        }
-        double tr = 0.0, det;
-        for (int d = 0; d < D; ++d) tr += A[d * D + d];
-        if (D == 1) {
-            det = A[0];
-            I[0] = 1.0 / A[0];
-        } else if (D == 2) {
-            det = A[0] * A[3] - A[1] * A[2];
-            I[0] = A[3] / det;
-            I[1] = -A[1] / det;
-            I[2] = -A[2] / det;
-            I[3] = A[0] / det;
-        } else {
-            const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
-            det = A[0] * c00 + A[1] * c01 + A[2] * c02;
-            I[0] = c00 / det;
-            I[1] = (A[2] * A[7] - A[1] * A[8]) / det;
-            I[2] = (A[1] * A[5] - A[2] * A[4]) / det;
-            I[3] = c01 / det;
-            I[4] = (A[0] * A[8] - A[2] * A[6]) / det;
-            I[5] = (A[2] * A[3] - A[0] * A[5]) / det;
-            I[6] = c02 / det;
-            I[7] = (A[1] * A[6] - A[0] * A[7]) / det;
-            I[8] = (A[0] * A[4] - A[1] * A[3]) / det;
-        }
-        const bool singular = nk == 0 || !(tr > 0.0) || det <= 1e-12 * pow(tr / D, (double)D);
-        if (singular) nk = 0;
-        for (int j = 0; j < nk; ++j)
-            for (int d = 0; d < 3; ++d) {
-                double c = 0.0;
-                if (d < D)
-                    for (int b = 0; b < D; ++b) c += I[d * D + b] * dx[j][b] * iw[j];
-                s_c[j][d] = (T)c;
-            }
-        s_nk = nk;
-        s_nw = nw;
-    }
+    if (threadIdx.x == 0) slope_setup<T>(C, cell, D, sh);
     __syncthreads();
-    const int nk = s_nk, nw = s_nw, nfa = s_nf;
+    const int nk = sh.s_nk, nw = sh.s_nw, nfa = sh.s_nf;
     const T *fo = (const T *)C.f[cur];
     const size_t row = (size_t)C.row;
     const int nvp = C.row / C.nfun;
@@ -853,11 +886,167 @@ __global__ __launch_bounds__(BLOCK) void k_slope(const CaseView *__restrict__ cv
     block_reduce_store<MAXW>(wsum, C.wsl + ((size_t)slot * C.ntile + vt) * MAXW, red);
 }
 
+// The slope kernel on 3D tensor grids in the 16-byte-row plane layout: a lane
+// keeps one y node and four consecutive z nodes and loops over the tile's
+// x-planes, reading its own row and the kinetic neighbours' rows as 16-byte
+// vectors and writing each face's increments the same way.  The per-node
+// arithmetic is that of k_slope; tiles must cover whole x-planes.
+#ifndef SLOPE_V4_U
+#define SLOPE_V4_U 2
+#endif
+template <typename T, int NK>
+__global__ __launch_bounds__(BLOCK) void k_slope_v4(const CaseView *__restrict__ cvp, int n_kin, int cur)
+{
+    typedef T V4 __attribute__((ext_vector_type(4)));
+    const CaseView &C = *cvp;
+    __shared__ SlopeSh<T> sh;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int vt = b / n_kin;
+    const int t = b - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    if (threadIdx.x == 0) slope_setup<T>(C, cell, C.dim, sh);
+    __syncthreads();
+    const int nk = sh.s_nk, nw = sh.s_nw, nfa = sh.s_nf;
+    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
+    const size_t row = (size_t)C.row;
+    const T *fo = (const T *)C.f[cur];
+    const T *fi_row = wave_uniform(fo + (size_t)slot * row);
+    T *so[NK];
+    T a0[NK], a1[NK], a2[NK];
+#pragma unroll
+    for (int l = 0; l < NK; ++l) {
+        const bool on = l < nfa;
+        so[l] = wave_uniform((T *)C.slope + ((size_t)slot * C.nfmax + (on ? l : 0)) * row);
+        a0[l] = on ? sh.s_ra[l][0] : (T)0;
+        a1[l] = on ? sh.s_ra[l][1] : (T)0;
+        a2[l] = on ? sh.s_ra[l][2] : (T)0;
+    }
+    const T *nbr[NK];
+    T c0[NK], c1[NK], c2[NK], r0[NK], r1[NK], r2[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const bool on = j < nk;
+        nbr[j] = wave_uniform(on ? fo + (size_t)sh.s_nb[j] * row : fi_row);
+        c0[j] = on ? sh.s_c[j][0] : (T)0;
+        c1[j] = on ? sh.s_c[j][1] : (T)0;
+        c2[j] = on ? sh.s_c[j][2] : (T)0;
+        r0[j] = on ? sh.s_r[j][0] : (T)0;
+        r1[j] = on ? sh.s_r[j][1] : (T)0;
+        r2[j] = on ? sh.s_r[j][2] : (T)0;
+    }
+    // lane -> (x group, y, first of four z nodes)
+    const int Q = nz >> 2, PL = ny * Q, G = BLOCK / PL;
+    const int xg = threadIdx.x / PL, pr = threadIdx.x - xg * PL;
+    const int iy = pr / Q, iz0 = 4 * (pr - iy * Q);
+    const int P2 = ny * nz;
+    const int ix0 = (vt * C.tile) / P2, ix1 = min(nx, ((vt + 1) * C.tile) / P2);
+    double wacc[MAXW];
+#pragma unroll
+    for (int j = 0; j < MAXW; ++j) wacc[j] = 0.0;
+    for (int ixr = ix0 + xg; ixr < ix1; ixr += SLOPE_V4_U * G) {
+        V4 v[SLOPE_V4_U][NK], fi[SLOPE_V4_U];
+#pragma unroll
+        for (int u = 0; u < SLOPE_V4_U; ++u) {
+            const size_t k = (size_t)min(ixr + u * G, ix1 - 1) * P2 + 4 * pr;   // in-range address for idle planes
+#pragma unroll
+            for (int j = 0; j < NK; ++j) v[u][j] = *(const V4 *)(nbr[j] + k);
+            fi[u] = *(const V4 *)(fi_row + k);
+        }
+#pragma unroll
+        for (int u = 0; u < SLOPE_V4_U; ++u) {
+            const int ix = ixr + u * G;
+            if (ix >= ix1) break;
+            const size_t k = (size_t)ix * P2 + 4 * pr;
+            V4 out[NK];
+            T w0[4], w1[4], w2[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T g0 = (T)0, g1 = (T)0, g2 = (T)0, dmax = (T)0, dmin = (T)0;
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    const T d = v[u][j][q] - fi[u][q];
+                    g0 += c0[j] * d;
+                    g1 += c1[j] * d;
+                    g2 += c2[j] * d;
+                    dmax = fmax(dmax, d);
+                    dmin = fmin(dmin, d);
+                }
+                // Barth-Jespersen: phi = min over faces of min(1, bound / ext)
+                T phi = (T)1;
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    const T ext = g0 * r0[j] + g1 * r1[j] + g2 * r2[j];
+                    if (ext > dmax) phi = fmin(phi, ratio_lim(dmax, ext));
+                    else if (ext < dmin) phi = fmin(phi, ratio_lim(dmin, ext));
+                }
+                g0 *= phi;
+                g1 *= phi;
+                g2 *= phi;
+#pragma unroll
+                for (int l = 0; l < NK; ++l) out[l][q] = g0 * a0[l] + g1 * a1[l] + g2 * a2[l];
+                w0[q] = g0;
+                w1[q] = g1;
+                w2[q] = g2;
+            }
+#pragma unroll
+            for (int l = 0; l < NK; ++l)
+                if (l < nfa) __builtin_nontemporal_store(out[l], (V4 *)(so[l] + k));
+            if (nw > 0) {
+                // the slope part of the outgoing wall fluxes (FP64, rare cells)
+                const double xx = C.xv[ix], yy = C.xv[MAXA + iy];
+                const double wxy = C.wv[ix] * C.wv[MAXA + iy];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double zz = C.xv[2 * MAXA + iz0 + q];
+                    const double wd = wxy * C.wv[2 * MAXA + iz0 + q];
+#pragma unroll
+                    for (int j = 0; j < MAXW; ++j)
+                        if (j < nw) {
+                            const double a = xx * sh.s_wn[j][0] + yy * sh.s_wn[j][1] + zz * sh.s_wn[j][2];
+                            if (a > 0.0)
+                                wacc[j] += wd * a *
+                                           (double)(w0[q] * sh.s_wr[j][0] + w1[q] * sh.s_wr[j][1] +
+                                                    w2[q] * sh.s_wr[j][2]);
+                        }
+                }
+            }
+        }
+    }
+    double wsum[MAXW];
+#pragma unroll
+    for (int w = 0; w < MAXW; ++w) {
+        wsum[w] = 0.0;
+#pragma unroll
+        for (int j = 0; j < MAXW; ++j) wsum[w] += (j < nw && sh.s_ww[j] == w) ? wacc[j] : 0.0;
+    }
+    block_reduce_store<MAXW>(wsum, C.wsl + ((size_t)slot * C.ntile + vt) * MAXW, sh.red);
+}
+
 hipError_t launch_slope(const CaseView *cv, const CaseView &h, int n_kin, int cur, hipStream_t s)
 {
     if (n_kin <= 0) return hipSuccess;
     const int blocks = n_kin * h.ntile;
     const bool f4 = h.nfmax <= 4;
+    // 16-byte rows on 3D tensor grids whose (y, z) plane splits into 64-256
+    // lanes of four z nodes and whose tiles cover whole planes (GSIS_SLOPE_V4=0
+    // keeps the node-per-thread kernel)
+    static const bool v4_on = [] {
+        const char *e = std::getenv("GSIS_SLOPE_V4");
+        return !(e && e[0] == '0');
+    }();
+    const int P2 = h.n[1] * h.n[2];
+    if (v4_on && h.vdim == 3 && !h.points && h.nfun == 1 && h.n[2] % 4 == 0 && P2 / 4 >= 64 && P2 / 4 <= BLOCK &&
+        BLOCK % (P2 / 4) == 0 && h.tile % P2 == 0) {
+        if (h.dtype == GSIS_F32) {
+            if (f4) hipLaunchKernelGGL((k_slope_v4<float, 4>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+            else hipLaunchKernelGGL((k_slope_v4<float, MAXF>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+        } else {
+            if (f4) hipLaunchKernelGGL((k_slope_v4<double, 4>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+            else hipLaunchKernelGGL((k_slope_v4<double, MAXF>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
+        }
+        return hipGetLastError();
+    }
     if (h.dtype == GSIS_F32) {
         if (f4) hipLaunchKernelGGL((k_slope<float, 4>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
         else hipLaunchKernelGGL((k_slope<float, MAXF>), dim3(blocks), dim3(BLOCK), 0, s, cv, n_kin, cur);
