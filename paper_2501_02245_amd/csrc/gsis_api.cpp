@@ -1049,7 +1049,7 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
 {
     CaseView &h = c->hv;
     HIPCHK(launch_param(c->cv, h, c->n_kin, s));
-    if (h.fast) HIPCHK(launch_axtab(c->cv, h, c->n_kin, s));
+    if (h.fast || o2_v4_fits(h)) HIPCHK(launch_axtab(c->cv, h, c->n_kin, s));
     if (has_ns_cells(c)) {
         HIPCHK(launch_lsq(c->cv, h, h.W, 4, s));
         if (h.poly) HIPCHK(launch_ghost_poly(c->cv, h, h.W, h.Tr, s));
@@ -1090,6 +1090,12 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
             for (int j = 0; j < m; ++j) {
                 const CaseView &hj = cases[i0 + j]->hv;
                 if (!(hj.fast && hj.vdim == 3 && !hj.poly && sweep_v4_fits(hj.n[1], hj.n[2]))) b.v4 = 0;
+            }
+            // order 2: the 16-byte-row sweep when every case fits it
+            if (cases[i0]->hv.sorder == 2) {
+                b.v4 = 1;
+                for (int j = 0; j < m; ++j)
+                    if (!o2_v4_fits(cases[i0 + j]->hv)) b.v4 = 0;
             }
         }
         if (timed && i0 == 0 && cases[0]->ev0) HIPCHK(hipEventRecord(cases[0]->ev0, s));

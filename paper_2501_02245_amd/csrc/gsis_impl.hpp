@@ -299,6 +299,8 @@ hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total_items, hip
 // (gsis_sweep.hip) tensor grids whose fastest axis divides the block
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total_items, hipStream_t s);
 bool sweep_v4_fits(int ny, int nz);
+bool o2_v4_fits(const CaseView &h);
+hipError_t launch_sweep_o2v4(const Batch &b, const CaseView &h0, int total, hipStream_t s);
 hipError_t launch_axtab(const CaseView *cv, const CaseView &h, int n_kin, hipStream_t s);
 // spatial order 2: largest outflow rate per cell (at bind), limited slopes of f[cur]
 hipError_t launch_amax(const CaseView *cv, const CaseView &h, hipStream_t s);

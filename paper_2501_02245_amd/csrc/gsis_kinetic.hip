@@ -2315,6 +2315,7 @@ hipError_t launch_sweep(const Batch &b, const CaseView &h0, int total, hipStream
     if (total <= 0) return hipSuccess;
     if (h0.poly) return launch_sweep_poly(b, h0, total, s);
     if (h0.fast) return launch_sweep_fast(b, h0, total, s);
+    if (h0.sorder == 2 && b.v4) return launch_sweep_o2v4(b, h0, total, s);
     // all cases of a batch share dtype and vdim; LDS is sized for the largest axes
     if (h0.dtype == GSIS_F32)
         return h0.vdim == 3 ? launch_sweep_t<float, 3>(b, h0, total, s) : launch_sweep_t<float, 2>(b, h0, total, s);

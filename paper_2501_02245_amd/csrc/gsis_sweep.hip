@@ -1008,6 +1008,269 @@ __global__ __launch_bounds__(BLOCK) __attribute__((
     }
 }
 
+// ---------------------------------------------------------------------------
+// Second-order sweep (Sec. 3, second-order finite volumes, as a deferred
+// correction of the first-order implicit update) in the 16-byte-row plane
+// layout of k_sweep_v4.  Besides the first-order terms, a node takes
+//   - the cell's own increment of every face where the value goes out
+//     (num -= max(a, 0) delta_l),
+//   - on a face to a kinetic neighbour, the neighbour's increment on the
+//     shared face where the value comes in (v = f_nb + delta_nb),
+//   - the pseudo-time term damp amax on the diagonal,
+// and wall faces scale their Maxwellian row by rho_w with the slope part of
+// the outgoing flux.  Per wave and x-plane a face that brings nothing in reads
+// neither the neighbour's row nor its increment, and a face that takes
+// nothing out does not read the cell's increment (exactly: those terms are
+// zero on every node of the wave's patch).  Tiles cover whole x-planes.
+// ---------------------------------------------------------------------------
+template <typename T, int NF>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (NF <= 4 ? 3 : 2) : 1))) void
+k_sweep_o2v4(Batch B)
+{
+    typedef typename Vec4T<T>::v V4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    int ci = 0;
+    while (ci + 1 < B.n && b >= B.start[ci + 1]) ++ci;
+    const CaseView &C = *B.cv[ci];
+    const int cur = B.cur[ci];
+    const int item = b - B.start[ci];
+    const int n_kin = (B.start[ci + 1] - B.start[ci]) / C.ntile;
+    const int vt = item / n_kin;
+    const int t = item - vt * n_kin;
+    const int cell = C.kin_cell[t];
+    const int slot = C.slot_of_cell[cell];
+    const ParamRec &P = C.param[slot];
+    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
+    const size_t row = (size_t)C.row;
+    gcptr<T> fold = (gcptr<T>)C.f[cur];
+    gptr<T> fn = (gptr<T>)C.f[cur ^ 1] + (size_t)slot * row;
+    gcptr<T> fo = fold + (size_t)slot * row;
+    gcptr<T> dl0 = (gcptr<T>)C.slope;
+
+    const int Q = nz >> 2, PL = ny * Q, G = BLOCK / PL;
+    const int xg = threadIdx.x / PL, pr = threadIdx.x - xg * PL;
+    const int iy = pr / Q, iz0 = 4 * (pr - iy * Q);
+
+    const int NA = nx + ny + nz;
+    gcptr<T> tb = (gcptr<T>)C.axtab + (size_t)slot * C.tabp;
+    T *xr = (T *)smem_raw;
+    double *red = (double *)(smem_raw + red_offset<T>((size_t)XREC * nx));
+    {
+        const double ux = P.u[0], it = P.it;
+        for (int j = threadIdx.x; j < nx; j += BLOCK) {
+            const double c = C.xv[j] - ux, w = C.wv[j];
+            T *r = xr + XREC * j;
+            r[0] = tb[j];
+            r[1] = tb[NA + j];
+            r[2] = tb[2 * NA + j];
+            r[3] = tb[3 * NA + j];
+            r[4] = (T)(c * c * it);
+            r[5] = (T)w;
+            r[6] = (T)(w * c);
+            r[7] = (T)(w * c * c);
+            r[8] = (T)(w * c * c * c);
+        }
+    }
+
+    // ---- faces: neighbour rows and increments, own increments, scales -------
+    const int e0 = C.cf_ptr[cell];
+    const int nf = C.cf_ptr[cell + 1] - e0;
+    int fwall[NF];
+    T fnx[NF], fsc[NF], qk[NF];
+    double fny[NF], fnz[NF], fun[NF];
+    gcptr<T> fnb[NF], dnb[NF], dio[NF];
+    int nw = 0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fwall[l] = -1;
+        fnx[l] = fsc[l] = qk[l] = (T)0;
+        fny[l] = fnz[l] = fun[l] = 0.0;
+        fnb[l] = dnb[l] = dio[l] = fo;
+        if (l < nf) {
+            const int e = e0 + l;
+            const int oth = C.cf_other[e];
+            const double n0 = C.cf_nsv[3 * e], n1 = C.cf_nsv[3 * e + 1], n2 = C.cf_nsv[3 * e + 2];
+            fnx[l] = (T)n0;
+            fny[l] = n1;
+            fnz[l] = n2;
+            fun[l] = P.u[0] * n0 + P.u[1] * n1 + P.u[2] * n2;
+            fsc[l] = (T)1;
+            dio[l] = dl0 + ((size_t)slot * C.nfmax + l) * row;
+            if (oth >= 0) {
+                const int so = C.slot_of_cell[oth];
+                if (so >= 0) {
+                    fnb[l] = fold + (size_t)so * row;
+                    dnb[l] = dl0 + ((size_t)so * C.nfmax + C.cf_back[e]) * row;
+                    qk[l] = (T)1;
+                } else {
+                    fnb[l] = (gcptr<T>)C.grow + (size_t)C.ghost_slot[oth] * row;
+                }
+            } else {
+                fnb[l] = (gcptr<T>)C.prow + (size_t)(-1 - oth) * row;
+                fwall[l] = C.cf_wall[e];
+                if (fwall[l] >= 0) {
+                    // rho_w with the slope part of the outgoing mass flux of f^n
+                    double ws = 0.0;
+                    for (int tl = 0; tl < C.ntile; ++tl) ws += C.wsl[((size_t)slot * C.ntile + tl) * MAXW + fwall[l]];
+                    fsc[l] = (T)(P.rw[fwall[l]] + ws / C.wall_den[e]);
+                    ++nw;
+                }
+            }
+        }
+    }
+
+    // ---- lane constants (FP64, rounded once) --------------------------------
+    const double it = P.it;
+    const double cyd = C.xv[MAXA + iy] - P.u[1];
+    const T Ey = tb[NA + nx + iy], Py = tb[2 * NA + nx + iy], Ky = tb[3 * NA + nx + iy];
+    T Eyz[4], Pyz[4], Kyz[4], Ayz[4], wz[4], cz[4], BL[NF], amin[NF], amx[NF], fnzT[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) BL[l] = (T)(fny[l] * cyd + fun[l]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double czd = C.xv[2 * MAXA + iz0 + j] - P.u[2];
+        const double r2 = cyd * cyd + czd * czd;
+        const int jz = nx + ny + iz0 + j;
+        Eyz[j] = ((T)P.itau * Ey) * tb[NA + jz];
+        Pyz[j] = Py + tb[2 * NA + jz];
+        Kyz[j] = Ky + tb[3 * NA + jz];
+        Ayz[j] = (T)(r2 * it - 2.5);
+        wz[j] = (T)C.wv[2 * MAXA + iz0 + j];
+        cz[j] = (T)czd;
+    }
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fnzT[l] = (T)fnz[l];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const T a = fma(fnzT[l], cz[j], BL[l]);
+            amin[l] = (j == 0) ? a : fmin(amin[l], a);
+            amx[l] = (j == 0) ? a : fmax(amx[l], a);
+        }
+    }
+    // the (y, z) part of each face's a over the wave: with n_x c_x of the plane
+    // it bounds a on the wave's whole patch from below and above
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        amin[l] = to_uniform(wave_min(amin[l]));
+        amx[l] = to_uniform(-wave_min(-amx[l]));
+    }
+    __syncthreads();
+
+    const T idt = (T)(C.inv_dt + C.damp2 * C.amax[cell]);
+    const T den0 = (T)P.itau + idt;
+    T S0[4], S1[4], S2[4], S3[4], R0[4], R1[4], R2[4];
+    T Wf[NF];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) S0[j] = S1[j] = S2[j] = S3[j] = R0[j] = R1[j] = R2[j] = (T)0;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) Wf[l] = (T)0;
+
+    const int P2 = ny * nz;
+    const int ix0 = (vt * C.tile) / P2, ix1 = min(nx, ((vt + 1) * C.tile) / P2);
+    const uint32_t plane_bytes = (uint32_t)(P2 * sizeof(T));
+    const uint32_t lane_bytes = (uint32_t)(4 * pr * sizeof(T));
+    gcptr<V4> fo_u = (gcptr<V4>)uniform_ptr(fo);
+    gptr<V4> fn_u = (gptr<V4>)uniform_ptr(fn);
+    gcptr<V4> fnb_u[NF], dnb_u[NF], dio_u[NF];
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        fnb_u[l] = (gcptr<V4>)uniform_ptr(fnb[l]);
+        dnb_u[l] = (gcptr<V4>)uniform_ptr(dnb[l]);
+        dio_u[l] = (gcptr<V4>)uniform_ptr(dio[l]);
+    }
+
+    auto planes = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+        for (int ix = ix0 + xg; ix < ix1; ix += G) {
+            const uint32_t off = (uint32_t)ix * plane_bytes + lane_bytes;
+            const T cx = xr[XREC * ix];
+            const V4 o = ldb(fo_u, off);
+            V4 v[NF], dn[NF], di[NF];
+#pragma unroll
+            for (int l = 0; l < NF; ++l) {
+                const T ax = fnx[l] * cx;
+                const int ni = (ax + amin[l] < (T)1e-5 * (fabs(ax) + fabs(amin[l])));
+                const int no = (ax + amx[l] > (T)-1e-5 * (fabs(ax) + fabs(amx[l])));
+                const bool need_in = __builtin_amdgcn_readfirstlane(ni);
+                const bool need_out = __builtin_amdgcn_readfirstlane(no);
+                v[l] = ldb(need_in ? fnb_u[l] : fo_u, off);
+                dn[l] = ldb(need_in ? dnb_u[l] : fo_u, off);
+                di[l] = ldb(need_out ? dio_u[l] : fo_u, off);
+            }
+            const T *rx = xr + XREC * ix;
+            const T Ex = rx[1], Px = rx[2], Kx = rx[3], cx2 = rx[4];
+            const T wx = rx[5], wx1 = rx[6], wx2 = rx[7], wx3 = rx[8];
+            T AX[NF];
+#pragma unroll
+            for (int l = 0; l < NF; ++l) AX[l] = fnx[l] * cx + BL[l];
+            V4 outv;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T oj = o[j];
+                const T g = Ex * Eyz[j] * (Px + Pyz[j]) * ((Kx + Kyz[j]) * (cx2 + Ayz[j]) + (T)1);
+                T num = g + idt * oj;
+                T den = den0;
+                T aw[NF];
+#pragma unroll
+                for (int l = 0; l < NF; ++l) {
+                    const T a = fma(fnzT[l], cz[j], AX[l]);
+                    const T mn = fmin(a, (T)0);
+                    const T ap = a - mn;   // max(a, 0)
+                    den -= mn;
+                    const T vin = fma(qk[l], dn[l][j], v[l][j]);
+                    if constexpr (WALLS) {
+                        aw[l] = ap;
+                        num -= (mn * fsc[l]) * vin;
+                    } else {
+                        num -= mn * vin;
+                    }
+                    num -= ap * di[l][j];
+                }
+                const T f = num * fast_rcp(den);
+                outv[j] = f;
+                S0[j] = fma(wx, f, S0[j]);
+                S1[j] = fma(wx1, f, S1[j]);
+                S2[j] = fma(wx2, f, S2[j]);
+                S3[j] = fma(wx3, f, S3[j]);
+                const T tr = num - den * oj;
+                R0[j] = fma(wx, tr, R0[j]);
+                R1[j] = fma(wx1, tr, R1[j]);
+                R2[j] = fma(wx2, tr, R2[j]);
+                if constexpr (WALLS) {
+                    const T hw = (wx * wz[j]) * f;
+#pragma unroll
+                    for (int l = 0; l < NF; ++l)
+                        if (fwall[l] >= 0) Wf[l] = fma(hw, aw[l], Wf[l]);
+                }
+            }
+            stb(fn_u, off, outv);
+        }
+    };
+    auto epilogue = [&](auto walls) {
+        constexpr bool WALLS = decltype(walls)::value;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            asm volatile("" : "+v"(S0[j]), "+v"(S1[j]), "+v"(S2[j]), "+v"(S3[j]));
+            asm volatile("" : "+v"(R0[j]), "+v"(R1[j]), "+v"(R2[j]));
+        }
+        if (WALLS) {
+#pragma unroll
+            for (int l = 0; l < NF; ++l) asm volatile("" : "+v"(Wf[l]));
+        }
+        v4_partials<T, NF, WALLS>(S0, S1, S2, S3, R0, R1, R2, Wf, fwall, C, P.u[2], cyd, iy, iz0, red,
+                                  C.partial + ((size_t)slot * C.ntile + vt) * NSUM);
+    };
+    if (nw > 0) {
+        planes(std::true_type{});
+        epilogue(std::true_type{});
+    } else {
+        planes(std::false_type{});
+        epilogue(std::false_type{});
+    }
+}
+
 // waves per SIMD of the FP32 16-byte-row correction
 #ifndef CORRECT_V4_WAVES
 #define CORRECT_V4_WAVES 4
@@ -1685,6 +1948,33 @@ void launch_v4(const Batch &b, const CaseView &h0, int total, hipStream_t s)
     const size_t lds = red_offset<T>((size_t)XREC * h0.n[0]) + sizeof(double) * (BLOCK / 16) * NSUM;
     if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_v4<T, 4, SWEEP_V4_U>), dim3(total), dim3(BLOCK), lds, s, b);
     else hipLaunchKernelGGL((k_sweep_v4<T, MAXF, 1>), dim3(total), dim3(BLOCK), lds, s, b);
+}
+
+// second-order cases the 16-byte-row sweep takes: 3D tensor grids whose (y, z)
+// plane splits into 64-256 lanes of four z nodes and whose tiles cover whole
+// x-planes (GSIS_O2_V4=0 keeps the node-per-thread sweep)
+bool o2_v4_fits(const CaseView &h)
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GSIS_O2_V4");
+        return !(e && e[0] == '0');
+    }();
+    return on && h.sorder == 2 && h.vdim == 3 && !h.points && !h.poly && sweep_v4_fits(h.n[1], h.n[2]) &&
+           h.tile % (h.n[1] * h.n[2]) == 0;
+}
+
+hipError_t launch_sweep_o2v4(const Batch &b, const CaseView &h0, int total, hipStream_t s)
+{
+    const size_t lds_f = red_offset<float>((size_t)XREC * h0.n[0]) + sizeof(double) * (BLOCK / 16) * NSUM;
+    const size_t lds_d = red_offset<double>((size_t)XREC * h0.n[0]) + sizeof(double) * (BLOCK / 16) * NSUM;
+    if (h0.dtype == GSIS_F32) {
+        if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_o2v4<float, 4>), dim3(total), dim3(BLOCK), lds_f, s, b);
+        else hipLaunchKernelGGL((k_sweep_o2v4<float, MAXF>), dim3(total), dim3(BLOCK), lds_f, s, b);
+    } else {
+        if (b.nfmax <= 4) hipLaunchKernelGGL((k_sweep_o2v4<double, 4>), dim3(total), dim3(BLOCK), lds_d, s, b);
+        else hipLaunchKernelGGL((k_sweep_o2v4<double, MAXF>), dim3(total), dim3(BLOCK), lds_d, s, b);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_fast(const Batch &b, const CaseView &h0, int total, hipStream_t s)
