@@ -2666,6 +2666,70 @@ __global__ __launch_bounds__(BLOCK) void k_fill(const CaseView *__restrict__ cvp
 
 hipError_t launch_fill_poly(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s);
 
+// Grad-13 rows of the NS neighbours (mode 3 of k_fill) in the 16-byte-row
+// plane layout: a lane keeps one y node and four z nodes and loops over the
+// tile's x-planes.  f = A e^{-c^2/T} (1 + c.sigma.c/(pT) + (2/5) q.c/(pT)
+// (c^2/T - 5/2)) with c = xi - u; the (y, z) parts of the Gaussian (with A),
+// of c^2, of c.sigma.c and of q.c are lane constants formed in FP64 and
+// rounded once, the x parts come from an LDS table per plane.  Ghost rows
+// carry no sums.  Tiles cover whole x-planes.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_ghost_rows_v4(const CaseView *__restrict__ cvp, int n_items)
+{
+    typedef T V4 __attribute__((ext_vector_type(4)));
+    __shared__ T tcx[MAXA], tex[MAXA];
+    const CaseView &C = *cvp;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int vt = b / n_items, t = b - vt * n_items;
+    const int cell = C.ghost_cell[t];
+    const int slot = C.ghost_slot[cell];
+    const double *g = C.ghost + (size_t)cell * GSIS_NMOM;
+    const double rho = g[0], Tg = g[4], p = rho * Tg, it = 1.0 / Tg;
+    const double A = rho * pow(M_PI * Tg, -1.5);
+    double sg[6], qg[3];
+    for (int d = 0; d < 6; ++d) sg[d] = g[5 + d] / (p * Tg);
+    for (int d = 0; d < 3; ++d) qg[d] = 2.0 * g[11 + d] / (p * Tg);
+    const int nx = C.n[0], ny = C.n[1], nz = C.n[2];
+    for (int j = threadIdx.x; j < nx; j += BLOCK) {
+        const double c = C.xv[j] - g[1];
+        tcx[j] = (T)c;
+        tex[j] = (T)exp(-c * c * it);
+    }
+    const int Q = nz >> 2, PL = ny * Q, G = BLOCK / PL;
+    const int xg = threadIdx.x / PL, pr = threadIdx.x - xg * PL;
+    const int iy = pr / Q, iz0 = 4 * (pr - iy * Q);
+    const double cy = C.xv[MAXA + iy] - g[2];
+    const double ey = A * exp(-cy * cy * it);
+    T Eyz[4], CC[4], QL[4], QM[4], QD[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double cz = C.xv[2 * MAXA + iz0 + j] - g[3];
+        Eyz[j] = (T)(ey * exp(-cz * cz * it));
+        CC[j] = (T)(cy * cy + cz * cz);
+        QL[j] = (T)(sg[1] * cy * cy + sg[2] * cz * cz + 2.0 * sg[5] * cy * cz);
+        QM[j] = (T)(2.0 * (sg[3] * cy + sg[4] * cz));
+        QD[j] = (T)(qg[1] * cy + qg[2] * cz);
+    }
+    const T s0 = (T)sg[0], q0 = (T)qg[0], itT = (T)it;
+    __syncthreads();
+    T *fr = (T *)C.grow + (size_t)slot * C.row;
+    const int P2 = ny * nz;
+    const int ix0 = (vt * C.tile) / P2, ix1 = min(nx, ((vt + 1) * C.tile) / P2);
+    for (int ix = ix0 + xg; ix < ix1; ix += G) {
+        const T c0 = tcx[ix], Ex = tex[ix];
+        const T sc = s0 * c0;
+        V4 out;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const T cc = fma(c0, c0, CC[j]);
+            const T Q2 = fma(sc, c0, fma(QM[j], c0, QL[j]));
+            const T qd = fma(q0, c0, QD[j]);
+            out[j] = (Ex * Eyz[j]) * ((T)1 + Q2 + qd * ((T)0.4 * cc * itT - (T)1));
+        }
+        __builtin_nontemporal_store(out, (V4 *)(fr + (size_t)ix * P2 + 4 * pr));
+    }
+}
+
 hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_items, int cur, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
@@ -2678,6 +2742,20 @@ hipError_t launch_fill(const CaseView *cv, const CaseView &h, int mode, int n_it
     }
     int NA3 = h.n[0] + h.n[1] + (h.vdim == 3 ? h.n[2] : 0);
     dim3 g(n_items * h.ntile);
+    // Grad-13 ghost rows in 16-byte rows on 3D tensor grids whose (y, z) plane
+    // splits into 64-256 lanes of four z nodes and whose tiles cover whole
+    // planes (GSIS_FILL_V4=0 keeps the node-per-thread kernel)
+    static const bool fill_v4 = [] {
+        const char *e = std::getenv("GSIS_FILL_V4");
+        return !(e && e[0] == '0');
+    }();
+    const int P2 = h.n[1] * h.n[2];
+    if (mode == 3 && fill_v4 && h.vdim == 3 && !h.points && h.n[2] % 4 == 0 && P2 / 4 >= 64 && P2 / 4 <= BLOCK &&
+        BLOCK % (P2 / 4) == 0 && h.tile % P2 == 0) {
+        if (h.dtype == GSIS_F32) hipLaunchKernelGGL((k_ghost_rows_v4<float>), g, dim3(BLOCK), 0, s, cv, n_items);
+        else hipLaunchKernelGGL((k_ghost_rows_v4<double>), g, dim3(BLOCK), 0, s, cv, n_items);
+        return hipGetLastError();
+    }
     if (h.points) {
         if (h.dtype == GSIS_F32)
             hipLaunchKernelGGL((k_fill<float, 3, true>), g, dim3(BLOCK), 0, s, cv, list, n_items, mode, cur);
