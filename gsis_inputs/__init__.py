@@ -206,6 +206,52 @@ def fourier_1d(n_cells: int = 64, T_left: float = 1.0, T_right: float = 1.1):
     return slab_1d(n_cells, _patch("wall", T=T_left), _patch("wall", T=T_right))
 
 
+def hex_box_3d(nx: int = 5, ny: int = 5, nz: int = 5, wall_speed: float = 0.2, T_wall: float = 1.0,
+               free=(1.0, (0.5, 0.0, 0.0), 1.0)):
+    """Structured box [0,1]^3 of nx ny nz hexahedra as a face list (six faces per
+    interior cell).  The x = 0 and x = 1 faces are diffuse walls at T_wall moving
+    -wall_speed and +wall_speed in y (patches 0 and 1); the y and z faces are
+    far field at free = (rho, u, T) (patch 2).  Interior face normals point from
+    the lower to the higher cell index along their axis; boundary normals point
+    out of the gas."""
+    n = (nx, ny, nz)
+    h = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+
+    def cid(i, j, k):
+        return (i * ny + j) * nz + k
+
+    fc, nrm, area, fcen = [], [], [], []
+    for ax in range(3):
+        a1, a2 = [d for d in range(3) if d != ax]
+        for idx in np.ndindex(*n):
+            i = idx[ax]
+            cen = [(idx[d] + 0.5) * h[d] for d in range(3)]
+            e = [0.0, 0.0, 0.0]
+            e[ax] = 1.0
+            fa = h[a1] * h[a2]
+            c = cid(*idx)
+            if i == 0:   # lower boundary face of the box on this axis
+                p = 0 if ax == 0 else 2
+                fcx = list(cen); fcx[ax] = 0.0
+                fc.append((c, -1 - p)); nrm.append(tuple(-x for x in e)); area.append(fa); fcen.append(tuple(fcx))
+            if i < n[ax] - 1:
+                nb = list(idx); nb[ax] += 1
+                fcx = list(cen); fcx[ax] = (i + 1) * h[ax]
+                fc.append((c, cid(*nb))); nrm.append(tuple(e)); area.append(fa); fcen.append(tuple(fcx))
+            else:        # upper boundary face
+                p = 1 if ax == 0 else 2
+                fcx = list(cen); fcx[ax] = 1.0
+                fc.append((c, -1 - p)); nrm.append(tuple(e)); area.append(fa); fcen.append(tuple(fcx))
+    ncell = nx * ny * nz
+    cc = np.array([[(i + 0.5) * h[0], (j + 0.5) * h[1], (k + 0.5) * h[2]]
+                   for i in range(nx) for j in range(ny) for k in range(nz)])
+    vol = np.full(ncell, h[0] * h[1] * h[2])
+    rho, u, T = free
+    patches = [_patch("wall", u=(0.0, -wall_speed, 0.0), T=T_wall), _patch("wall", u=(0.0, wall_speed, 0.0), T=T_wall),
+               _patch("far", rho=rho, u=u, T=T)]
+    return _finish(3, fc, nrm, np.asarray(area), fcen, vol, cc, patches)
+
+
 def quad_cavity_2d(nx: int = 64, ny: int = 64, lid_speed: float = 0.1, T_wall: float = 1.0):
     """Lid-driven cavity on [0,1]^2 as an unstructured quad face list.
 

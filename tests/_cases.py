@@ -82,6 +82,12 @@ def workload(name):
         W = gi.hypersonic_field(m)
         fl = gi.synthetic_region(m, 0.2, seed=11)
         return m, g, 0.005, W, fl
+    if name == "hexbox":           # hexahedra (six faces per cell), walls and far field, partial region, 16^3
+        m = gi.hex_box_3d(5, 5, 5)
+        g = gi.velocity_grid(3, 16, 6.0)
+        W = gi.random_W(m["n_cells"], seed=13, u_scale=0.2, dT=0.1, drho=0.1)
+        fl = gi.synthetic_region(m, 0.5, seed=11)
+        return m, g, 0.05, W, fl
     if name == "sphere_small":     # Mach 5 sphere, tetrahedra, partial region
         m = gi.sphere_tet_3d(h_wall=0.25, growth=0.6, h_max=1.5)
         g = gi.velocity_grid(3, 12, 15.0, "stretched")

@@ -41,7 +41,7 @@ def _setup(g, oracle_mod, name, dtype, seed=1):
                                         ("couette_ragged", 0), ("cavity", 0), ("cavity", 1),
                                         ("cavity:generic", 0), ("cylinder_small", 0), ("cylinder_fast", 0),
                                         ("cylinder_fast", 1), ("sphere_small", 0), ("sphere_small", 1),
-                                        ("sphere_fast", 0), ("sphere_fast", 1)])
+                                        ("sphere_fast", 0), ("sphere_fast", 1), ("hexbox", 0), ("hexbox", 1)])
 def test_one_sweep(g, oracle_mod, name, dtype):
     print("case", name, "dtype", dtype, flush=True)
     m, grid, O, W, flags, kin, slot, f0, case = _setup(g, oracle_mod, name, dtype)

@@ -39,7 +39,8 @@ def _load(name):
     return workload(name)
 
 
-@pytest.mark.parametrize("name", ["couette", "couette_ragged", "cavity", "cylinder_small", "sphere_small", "points"])
+@pytest.mark.parametrize("name", ["couette", "couette_ragged", "cavity", "cylinder_small", "sphere_small", "points",
+                                  "hexbox"])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_order2_one_sweep(g, oracle_mod, name, dtype):
     m, grid, Kn, W, flags = _load(name)

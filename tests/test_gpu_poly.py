@@ -49,7 +49,7 @@ def _rows(grid, W, seed, dtype):
     return f.astype(np.float32 if dtype == 0 else np.float64).astype(np.float64)
 
 
-@pytest.mark.parametrize("name", ["couette", "couette_ragged", "sphere_small"])
+@pytest.mark.parametrize("name", ["couette", "couette_ragged", "sphere_small", "hexbox"])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_poly_one_sweep(g, oracle_mod, name, dtype):
     m, grid, Kn, W, flags = workload(name)

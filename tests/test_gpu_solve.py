@@ -152,10 +152,11 @@ def test_region_update(g, oracle_mod):
 
 
 @pytest.mark.parametrize("name,dtype", [("cylinder_small", 1), ("cylinder_small", 0), ("cylinder_fast", 1),
-                                        ("cylinder_fast", 0)])
+                                        ("cylinder_fast", 0), ("hexbox", 1), ("hexbox", 0)])
 def test_agsis_steps(g, oracle_mod, name, dtype):
     """Four aGSIS outer iterations with region updates on the Mach-5 cylinder
-    (24^2 grid: generic sweep kernel; 32^2: plane kernel)."""
+    (24^2 grid: generic sweep kernel; 32^2: plane kernel) and on the hexahedral
+    box (six faces per cell, 16^3: the plane kernels' wide-face variants)."""
     print("case", name, "dtype", dtype, flush=True)
     m, grid, Kn, W, flags = workload(name)
     O = oracle_mod.Oracle(m, grid, Kn)

@@ -25,7 +25,8 @@ def gauss(xi, rho, u, T):
 # inputs: meshes and quadratures
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("make", [lambda: gi.couette_1d(16), lambda: gi.quad_cavity_2d(8, 6),
-                                  lambda: gi.cylinder_tri_2d(n_theta=40, n_rings=12)])
+                                  lambda: gi.cylinder_tri_2d(n_theta=40, n_rings=12),
+                                  lambda: gi.hex_box_3d(4, 3, 5)])
 def test_mesh_closed_and_oriented(make):
     m = make()
     nc = m["n_cells"]
