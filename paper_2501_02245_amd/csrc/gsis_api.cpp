@@ -853,8 +853,6 @@ gsis_status bind_impl(gsis_case c, void *ws, size_t bytes, int64_t cap, void *st
         h.order = env ? std::atoi(env) : 0;
         const char *genv = std::getenv("GSIS_SWEEP_GROUP");
         h.group = genv ? std::max(1, std::atoi(genv)) : 256;
-        const char *renv = std::getenv("GSIS_SWEEP_ROT");
-        h.rot = renv ? std::max(0, std::atoi(renv)) : 0;
     }
     h.sorder = c->order;
     h.damp2 = c->damp2;
@@ -1079,7 +1077,6 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         for (int j = 0; j < m; ++j) b.cur[j] = cases[i0 + j]->cur;
         b.order = cases[i0]->hv.order;
         b.group = cases[i0]->hv.group;
-        b.rot = cases[i0]->hv.rot;
         // 16-byte rows when every case's (y, z) plane fits (GSIS_SWEEP_V4=0 keeps 4-byte rows)
         {
             const bool v4_on = [] {

@@ -145,7 +145,7 @@ struct CaseView {
     void *axtab;
     int32_t tabp, order;        // order: sweep blocks 0 = tile-major, 1 = cell-major,
                                 // 2 = groups of `group` cells, tile-major inside a group
-    int32_t group, rot;
+    int32_t group, pad_g;
     // spatial order 2 (second-order face values): the reconstruction increments
     // of every face of every kinetic cell, slope [capacity][nfmax][row] in the
     // case dtype (delta_l = phi g . (x_face_l - x_cell) per VDF value), each
@@ -229,7 +229,6 @@ struct Batch {
     int32_t order;                  // 0: blocks tile-major, 1: cell-major (all tiles of a cell together),
                                     // 2: groups of `group` consecutive cells, tile-major inside each group
     int32_t group;
-    int32_t rot;                    // plane kernel: start plane advances every `rot` blocks per XCD (0: plane 0)
     int32_t v4;                     // 3D plane layout read as 16-byte rows (every case fits sweep_v4_fits)
 };
 
