@@ -697,10 +697,19 @@ class SteadySolver:
 
     State: W [n_cells, 5] primitive (rho, u, T) on every cell; flags; kinetic
     list and slots; f [n_slots, nfun, nv] for the kinetic cells.
+
+    source_half (monatomic gas): the source of eq. macro is the kinetic
+    balance at f^{n+1/2} minus the synthetic residual at W^{n+1/2}, and the
+    synthetic solve starts from W^{n+1/2}; the synthetic equation is then
+    the usual GSIS one, fed by the sweep's new non-equilibrium moments.
+    Default: the balance at f^n and the residual at W^n, the solve from W^n.
     """
 
     def __init__(self, O, mode="gsis", Kn_ref=0.01, n_inner=400, cfl=0.5,
-                 region_every=1, force_wall_layers=0, capacity=None):
+                 region_every=1, force_wall_layers=0, capacity=None, source_half=False):
+        if source_half and O.poly:
+            raise ValueError("source_half is defined for the monatomic gas")
+        self.source_half = bool(source_half)
         self.O, self.mode = O, mode
         self.Kn_ref, self.n_inner, self.cfl = Kn_ref, n_inner, cfl
         self.region_every, self.layers = region_every, force_wall_layers
@@ -800,7 +809,7 @@ class SteadySolver:
             gc = self.ghost_cells()
             self.stats["g13_ghosts"] = len(gc)
             self.stats["g13_ghost_limited"] = int(O.last_g13_limited[gc].sum())
-        if self.mode != "dvm":
+        if self.mode != "dvm" and not self.source_half:
             Rk = O.kinetic_residual(self.f, kin, slot, ghost)
         f_half = O.sweep(self.f, kin, slot, ghost)
         mom_half = O.moments(f_half[rows])
@@ -825,8 +834,15 @@ class SteadySolver:
             # Newton-like corrector of the conserved moments, and its fixed
             # point is the fixed point of the kinetic iteration.
             src = np.zeros((self.n, W_old.shape[1]))
-            src[kin] = Rk[kin] - O.macro_residual(W_old, hot)[kin]
-            W_new = O.macro(W_old, hot, self.n_inner, self.cfl, src)
+            if self.source_half:
+                # the same at the half step: the sweep's f^{n+1/2} and W^{n+1/2}
+                # (NS cells keep W^n, and their Grad-13 rows are those of the sweep)
+                Rk = O.kinetic_residual(f_half, kin, slot, ghost)
+                src[kin] = Rk[kin] - O.macro_residual(W_half, hot)[kin]
+                W_new = O.macro(W_half, hot, self.n_inner, self.cfl, src)
+            else:
+                src[kin] = Rk[kin] - O.macro_residual(W_old, hot)[kin]
+                W_new = O.macro(W_old, hot, self.n_inner, self.cfl, src)
             # GSIS correction (first eq. updatef), with the change of the
             # conserved moments limited on each kinetic cell
             cut = 0

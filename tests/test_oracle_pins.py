@@ -724,7 +724,8 @@ def test_macro_navier_stokes_couette(oracle_mod, n, Kn):
     assert np.abs(W[:, 1]).max() < 1e-3 * U                 # O(h) splitting dissipation
 
 
-def test_gsis_fixed_point_is_dvm_fixed_point(oracle_mod):
+@pytest.mark.parametrize("source_half", [False, True])
+def test_gsis_fixed_point_is_dvm_fixed_point(oracle_mod, source_half):
     """The synthetic step only accelerates (Sec. 3.1): with the source of eq.
     macro taken as the kinetic scheme's own moment balance, converged GSIS is
     converged plain DVM (the same discrete equations), reached in far fewer
@@ -739,9 +740,10 @@ def test_gsis_fixed_point_is_dvm_fixed_point(oracle_mod):
     D = oracle_mod.SteadySolver(O, mode="dvm")
     D.set_state(W0)
     it_d, _ = D.solve(tol=1e-12, max_iter=20000)
-    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=0.5)
+    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=0.5, source_half=source_half)
     S.set_state(W0)
     it_s, _ = S.solve(tol=1e-12, max_iter=2000)
+    print("source_half", source_half, "GSIS", it_s, "DVM", it_d)
     assert it_s < it_d / 5
     assert np.abs(S.W - D.W).max() < 1e-9
     fd = D.f[D.slot[D.kin]]
