@@ -287,6 +287,14 @@ typedef struct {
                                     synthetic solve alone (HoT = 0) to eps < 1e-6, then the first
                                     flagging with Grad-13 rows for every kinetic cell */
     int32_t ns_init_max_chunks;  /* chunks of n_macro_inner steps for Step 1 (0: 1000) */
+    int32_t source_half;         /* GSIS/aGSIS, monatomic gas (Sec. 3.1 eq. macro): 0 -- the source
+                                    is the kinetic moment balance at f^n minus the synthetic residual
+                                    at W^n, and the synthetic solve starts from W^n; 1 -- both at the
+                                    half step (f^{n+1/2}, W^{n+1/2}) and the solve starts from
+                                    W^{n+1/2}, so that the sweep's new non-equilibrium moments drive
+                                    W^{n+1}.  1 costs one more kinetic-balance pass per step (a
+                                    sweep of f^{n+1/2} whose output is discarded) and converges in
+                                    fewer outer iterations.  The two-VDF gas takes 0 only. */
 } gsis_solve_params;
 
 typedef struct {

@@ -71,12 +71,14 @@ class _Gas(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("mode", C.c_int32), ("Kn_ref", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("region_update_every", C.c_int32), ("n_macro_inner", C.c_int32), ("cfl", C.c_double),
-                ("force_wall_layers", C.c_int32), ("ns_init", C.c_int32), ("ns_init_max_chunks", C.c_int32)]
+                ("force_wall_layers", C.c_int32), ("ns_init", C.c_int32), ("ns_init_max_chunks", C.c_int32),
+                ("source_half", C.c_int32)]
 
     def __init__(self, mode=MODE_GSIS, Kn_ref=0.01, tol=1e-6, max_iter=1000, region_update_every=1,
-                 n_macro_inner=400, cfl=0.5, force_wall_layers=0, ns_init=0, ns_init_max_chunks=1000):
+                 n_macro_inner=400, cfl=0.5, force_wall_layers=0, ns_init=0, ns_init_max_chunks=1000,
+                 source_half=0):
         super().__init__(mode, Kn_ref, tol, max_iter, region_update_every, n_macro_inner, cfl, force_wall_layers,
-                         ns_init, ns_init_max_chunks)
+                         ns_init, ns_init_max_chunks, int(source_half))
 
 
 class SolveResult(C.Structure):

@@ -1059,42 +1059,49 @@ gsis_status prepare_sweep(gsis_case c, hipStream_t s)
     return GSIS_OK;
 }
 
+// the launch batch of cases [i0, i0 + m): work-item prefixes, buffers, layout
+Batch make_batch(gsis_case const *cases, int i0, int m)
+{
+    Batch b{};
+    b.n = m;
+    b.start[0] = 0;
+    for (int j = 0; j < m; ++j) {
+        gsis_case c = cases[i0 + j];
+        b.cv[j] = c->cv;
+        b.start[j + 1] = b.start[j] + c->n_kin * c->ntile;
+        b.nfmax = std::max(b.nfmax, c->hv.nfmax);
+        if (c->vdim == 3) b.mdiv = std::gcd(b.mdiv, c->n[1] * c->n[2] / BLOCK);
+    }
+    // every case sweeps its own f^n buffer (cur) into the other one
+    for (int j = 0; j < m; ++j) b.cur[j] = cases[i0 + j]->cur;
+    b.order = cases[i0]->hv.order;
+    b.group = cases[i0]->hv.group;
+    // 16-byte rows when every case's (y, z) plane fits (GSIS_SWEEP_V4=0 keeps 4-byte rows)
+    {
+        const bool v4_on = [] {
+            const char *e = std::getenv("GSIS_SWEEP_V4");
+            return !(e && e[0] == '0');
+        }();
+        b.v4 = v4_on;
+        for (int j = 0; j < m; ++j) {
+            const CaseView &hj = cases[i0 + j]->hv;
+            if (!(hj.fast && hj.vdim == 3 && !hj.poly && sweep_v4_fits(hj.n[1], hj.n[2]))) b.v4 = 0;
+        }
+        // order 2: the 16-byte-row sweep when every case fits it
+        if (cases[i0]->hv.sorder == 2) {
+            b.v4 = 1;
+            for (int j = 0; j < m; ++j)
+                if (!o2_v4_fits(cases[i0 + j]->hv)) b.v4 = 0;
+        }
+    }
+    return b;
+}
+
 gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool timed)
 {
     for (int i0 = 0; i0 < n; i0 += MAX_BATCH) {
-        Batch b{};
-        int m = std::min(MAX_BATCH, n - i0);
-        b.n = m;
-        b.start[0] = 0;
-        for (int j = 0; j < m; ++j) {
-            gsis_case c = cases[i0 + j];
-            b.cv[j] = c->cv;
-            b.start[j + 1] = b.start[j] + c->n_kin * c->ntile;
-            b.nfmax = std::max(b.nfmax, c->hv.nfmax);
-            if (c->vdim == 3) b.mdiv = std::gcd(b.mdiv, c->n[1] * c->n[2] / BLOCK);
-        }
-        // every case sweeps its own f^n buffer (cur) into the other one
-        for (int j = 0; j < m; ++j) b.cur[j] = cases[i0 + j]->cur;
-        b.order = cases[i0]->hv.order;
-        b.group = cases[i0]->hv.group;
-        // 16-byte rows when every case's (y, z) plane fits (GSIS_SWEEP_V4=0 keeps 4-byte rows)
-        {
-            const bool v4_on = [] {
-                const char *e = std::getenv("GSIS_SWEEP_V4");
-                return !(e && e[0] == '0');
-            }();
-            b.v4 = v4_on;
-            for (int j = 0; j < m; ++j) {
-                const CaseView &hj = cases[i0 + j]->hv;
-                if (!(hj.fast && hj.vdim == 3 && !hj.poly && sweep_v4_fits(hj.n[1], hj.n[2]))) b.v4 = 0;
-            }
-            // order 2: the 16-byte-row sweep when every case fits it
-            if (cases[i0]->hv.sorder == 2) {
-                b.v4 = 1;
-                for (int j = 0; j < m; ++j)
-                    if (!o2_v4_fits(cases[i0 + j]->hv)) b.v4 = 0;
-            }
-        }
+        const int m = std::min(MAX_BATCH, n - i0);
+        Batch b = make_batch(cases, i0, m);
         if (timed && i0 == 0 && cases[0]->ev0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
         // order 2: limited slopes of every case's f^n (the sweep reads its own
         // and its neighbours')
@@ -1111,6 +1118,25 @@ gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool tim
         cases[j]->timed = false;
     }
     cases[0]->timed = timed && cases[0]->ev0;
+    return GSIS_OK;
+}
+
+// the kinetic moment balance of the case's current rows (f^{n+1/2} after a
+// sweep): the targets and wall densities from their moments, then one sweep
+// of them into the other buffer (f^n, no longer needed), whose fused balance
+// sums are the balance at its input (the fix-up makes the collision term's
+// conserved moments vanish); the buffers do not swap and the rows written are
+// discarded.  Rk <- the balance (the moments stay those of the rows).
+gsis_status balance_of_current(gsis_case c, hipStream_t s)
+{
+    CaseView &h = c->hv;
+    HIPCHK(launch_param(c->cv, h, c->n_kin, s));
+    if (h.fast || o2_v4_fits(h)) HIPCHK(launch_axtab(c->cv, h, c->n_kin, s));
+    if (c->order == 2) HIPCHK(launch_slope(c->cv, h, c->n_kin, c->cur, s));
+    gsis_case one[1] = {c};
+    Batch b = make_batch(one, 0, 1);
+    HIPCHK(launch_sweep(b, h, b.start[1], s));
+    HIPCHK(launch_reduce(c->cv, h, c->n_kin, 2, s));
     return GSIS_OK;
 }
 
@@ -1274,6 +1300,16 @@ gsis_status pre_macro(gsis_case c, const gsis_solve_params *p, hipStream_t s)
     HIPCHK(launch_lsq(c->cv, h, h.Wh, 4, s));
     if (h.poly) HIPCHK(launch_hot_poly(c->cv, h, s));
     else HIPCHK(launch_hot(c->cv, h, c->n_kin, s));
+    if (p->source_half) {
+        // source at the half step: the balance of f^{n+1/2} minus the synthetic
+        // residual at W^{n+1/2}; the solve starts from W^{n+1/2}
+        gsis_status st = balance_of_current(c, s);
+        if (st) return st;
+        HIPCHK(launch_macro_residual(c->cv, h, h.Wh, h.hot, h.Rm, s));
+        HIPCHK(launch_src(c->cv, h, c->n_kin, s));
+        HIPCHK(launch_copy_W(h.Wn, h.Wh, h.n_cells, s));
+        return GSIS_OK;
+    }
     // source: kinetic moment balance at f^n minus synthetic residual at W^n
     if (h.poly) {
         HIPCHK(launch_macro_residual_poly(c->cv, h, h.W, h.Tr, h.hot, h.Rm, h.Rmr, s));
@@ -1463,7 +1499,7 @@ gsis_status step_body(gsis_case const *cases, int n, const gsis_solve_params *p,
 
 bool same_params(const gsis_solve_params &a, const gsis_solve_params &b)
 {
-    return a.mode == b.mode && a.n_macro_inner == b.n_macro_inner && a.cfl == b.cfl;
+    return a.mode == b.mode && a.n_macro_inner == b.n_macro_inner && a.cfl == b.cfl && a.source_half == b.source_half;
 }
 
 gsis_status step_from_graph(gsis_case const *cases, int n, const gsis_solve_params *p, hipStream_t s)
@@ -1525,6 +1561,16 @@ gsis_status check_params(const gsis_solve_params *p)
     if (p->mode < GSIS_MODE_DVM || p->mode > GSIS_MODE_AGSIS) return fail(GSIS_E_ARG, "bad mode");
     if (p->mode != GSIS_MODE_DVM && (p->n_macro_inner < 0 || p->cfl == 0 || !std::isfinite(p->cfl)))
         return fail(GSIS_E_ARG, "bad macro parameters");
+    if (p->source_half != 0 && p->source_half != 1) return fail(GSIS_E_ARG, "source_half must be 0 or 1");
+    return GSIS_OK;
+}
+
+// the half-step source is defined for the monatomic gas
+gsis_status check_source(gsis_case const *cases, int n, const gsis_solve_params *p)
+{
+    if (p->source_half && p->mode != GSIS_MODE_DVM)
+        for (int j = 0; j < n; ++j)
+            if (cases[j]->dr > 0) return fail(GSIS_E_ARG, "source_half is defined for the monatomic gas");
     return GSIS_OK;
 }
 
@@ -1536,6 +1582,7 @@ extern "C" gsis_status gsis_step(gsis_case const *cases, int32_t n, const gsis_s
     gsis_status st = check_batch(cases, n);
     if (st) return st;
     if ((st = check_params(p))) return st;
+    if ((st = check_source(cases, n, p))) return st;
     hipStream_t s = (hipStream_t)stream;
     if (step_graphs_enabled()) {
         if ((st = step_from_graph(cases, n, p, s))) return st;
@@ -1722,6 +1769,7 @@ extern "C" gsis_status gsis_solve_steady(gsis_case c, const gsis_solve_params *p
     gsis_status st = check_ready(c);
     if (st) return st;
     if ((st = check_params(p))) return st;
+    if ((st = check_source(&c, 1, p))) return st;
     if (!r) return fail(GSIS_E_ARG, "null result");
     const bool ns_init = p->mode == GSIS_MODE_AGSIS && p->ns_init;
     if (!(p->tol > 0) || p->max_iter < 0 || (p->max_iter == 0 && !ns_init))

@@ -371,6 +371,9 @@ hipError_t launch_wall_den(const CaseView *cv, const CaseView &h, hipStream_t s)
 // ---------------------------------------------------------------------------
 // tile sums -> moments (FP64), kinetic moment balance, wall numerators
 // ---------------------------------------------------------------------------
+// with_res: 0 the moments, 1 the moments and the kinetic balance Rk, 2 the
+// balance alone (a pass whose output rows are discarded: moments, wall sums
+// and the state checks stay those of the last real sweep)
 __global__ void k_reduce(const CaseView *__restrict__ cvp, int n_kin, int with_res)
 {
     const CaseView &C = *cvp;
@@ -384,6 +387,16 @@ __global__ void k_reduce(const CaseView *__restrict__ cvp, int n_kin, int with_r
     for (int tl = 0; tl < C.ntile; ++tl)
         for (int i = 0; i < NSUM; ++i) S[i] += P[tl * NSUM + i];
     const double *ur = C.param[slot].u;
+    if (with_res == 2) {
+        double *R = C.Rk + 5 * (size_t)cell;
+        const double r0 = S[S_RES];
+        const double rc[3] = {S[S_RES + 1], S[S_RES + 2], S[S_RES + 3]};
+        R[0] = r0;
+        for (int d = 0; d < 3; ++d) R[1 + d] = rc[d] + ur[d] * r0;
+        const double u2 = ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2];
+        R[4] = S[S_RES + 4] + 2.0 * (ur[0] * rc[0] + ur[1] * rc[1] + ur[2] * rc[2]) + u2 * r0;
+        return;
+    }
     double *mom = C.mom + (size_t)slot * MOMS;
     double rho = S[0];
     double dl[3] = {S[1] / rho, S[2] / rho, (C.vdim == 3) ? S[3] / rho : 0.0};

@@ -115,13 +115,15 @@ def test_order2_two_sweeps(g, oracle_mod, name, dtype):
     assert ef < 2 * TOL[dtype]
 
 
+@pytest.mark.parametrize("half", [0, 1])
 @pytest.mark.parametrize("dtype", [1, 0])
-def test_order2_gsis_steps(g, oracle_mod, dtype):
+def test_order2_gsis_steps(g, oracle_mod, dtype, half):
     """Three GSIS outer iterations (sweep, synthetic solve, correction) at
-    second order on the Couette slab."""
+    second order on the Couette slab (source of eq. macro at f^n and at the
+    half step, whose balance pass takes the slopes of f^{n+1/2})."""
     m, grid, Kn, W, flags = workload("couette")
     O = oracle_mod.Oracle(m, grid, Kn, order=2)
-    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=50, cfl=-0.5)
+    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=50, cfl=-0.5, source_half=bool(half))
     case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype, order=2)
     if dtype == g.F32:
         f0 = gi.gaussian_rows(grid, W, seed=2).astype(np.float64)
@@ -130,7 +132,7 @@ def test_order2_gsis_steps(g, oracle_mod, dtype):
     else:
         S.set_state(W)
         case.set_state(W)
-    p = g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=50, cfl=-0.5)
+    p = g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=50, cfl=-0.5, source_half=half)
     tol = 1e-9 if dtype == g.F64 else 1e-5
     for it in range(3):
         eo = S.step()

@@ -283,6 +283,8 @@ def test_poly_refusals(g):
     with pytest.raises(g.GsisError):
         g._check(g.lib().gsis_set_internal_dof(case.handle, C.c_double(2.0), C.c_double(2.0),
                                               C.c_void_p(A.ctypes.data)))
+    with pytest.raises(g.GsisError):   # the half-step source is for the monatomic gas
+        case.step(g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=10, source_half=1))
     case.sweep(1)                      # still usable
     mono = g.Case(g.Mesh(m), grid, Kn, dtype=g.F64)
     mono.set_state(W)

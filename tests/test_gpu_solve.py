@@ -55,22 +55,24 @@ def test_dvm_sweeps_fp64(g, oracle_mod):
     assert f_error(case.get_vdf().cpu().numpy(), S.f, O.w) < 1e-10
 
 
+@pytest.mark.parametrize("half", [0, 1])
 @pytest.mark.parametrize("dtype", [1, 0])
-def test_gsis_couette_converged(g, oracle_mod, dtype):
-    """GSIS steady Couette (Kn 0.1): converged fields, FP64 to round-off, FP32 within 1e-4."""
+def test_gsis_couette_converged(g, oracle_mod, dtype, half):
+    """GSIS steady Couette (Kn 0.1): converged fields, FP64 to round-off, FP32
+    within 1e-4; with the source of eq. macro at f^n / W^n and at the half step."""
     m, grid, Kn, W, flags = workload("couette")
     O = oracle_mod.Oracle(m, grid, Kn)
-    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=-0.5)
+    S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=-0.5, source_half=bool(half))
     S.set_state(W)
     it_o, eps_o = S.solve(tol=1e-8, max_iter=2000)
     case = g.Case(g.Mesh(m), grid, Kn, dtype=dtype)
     case.set_state(W)
     tol = 1e-8 if dtype == g.F64 else 1e-6
     it_g, eps_g, _ = case.solve(g.SolveParams(mode=g.MODE_GSIS, tol=tol, max_iter=2000, n_macro_inner=400,
-                                              cfl=-0.5))
+                                              cfl=-0.5, source_half=half))
     Wg = case.get_state()[0].cpu().numpy()
     err = _fields_err(Wg, S.W, 0.1)
-    print("gsis", dtype, "iters", it_o, it_g, "err", err, flush=True)
+    print("gsis", dtype, "half", half, "iters", it_o, it_g, "err", err, flush=True)
     if dtype == g.F64:
         assert abs(it_g - it_o) <= 2
         assert max(err.values()) < 1e-8
@@ -151,17 +153,26 @@ def test_region_update(g, oracle_mod):
     assert max(em.values()) < 1e-10, em
 
 
-@pytest.mark.parametrize("name,dtype", [("cylinder_small", 1), ("cylinder_small", 0), ("cylinder_fast", 1),
-                                        ("cylinder_fast", 0), ("hexbox", 1), ("hexbox", 0)])
-def test_agsis_steps(g, oracle_mod, name, dtype):
+@pytest.mark.parametrize("name,dtype,half", [("cylinder_small", 1, 0), ("cylinder_small", 0, 0),
+                                             ("cylinder_fast", 1, 0), ("cylinder_fast", 0, 0),
+                                             ("hexbox", 1, 0), ("hexbox", 0, 0),
+                                             ("cylinder_fast", 1, 1), ("cylinder_fast", 0, 1),
+                                             ("sphere_fast", 1, 1), ("hexbox", 1, 1)])
+def test_agsis_steps(g, oracle_mod, name, dtype, half):
     """Four aGSIS outer iterations with region updates on the Mach-5 cylinder
     (24^2 grid: generic sweep kernel; 32^2: plane kernel) and on the hexahedral
-    box (six faces per cell, 16^3: the plane kernels' wide-face variants)."""
+    box (six faces per cell, 16^3: the plane kernels' wide-face variants).
+
+    The sphere (16^3, three-dimensional plane kernel) is compared over one
+    step: from the second step on its iterates are ill-conditioned in the
+    oracle itself (a relative change of 1e-12 in W grows to 2e-8 within the
+    second step and to 1e-2 within the third, with identical flags and limiter
+    counts), so agreement there measures rounding, not the method."""
     print("case", name, "dtype", dtype, flush=True)
     m, grid, Kn, W, flags = workload(name)
     O = oracle_mod.Oracle(m, grid, Kn)
     S = oracle_mod.SteadySolver(O, mode="agsis", Kn_ref=0.01, n_inner=100, cfl=0.5, region_every=1,
-                                force_wall_layers=2)
+                                force_wall_layers=2, source_half=bool(half))
     case = make_case(g, name, m, grid, Kn, dtype)
     if dtype == g.F32:
         kin = np.nonzero(flags)[0]
@@ -172,10 +183,10 @@ def test_agsis_steps(g, oracle_mod, name, dtype):
         S.set_state(W, flags=flags)
         case.set_state(W, flags=flags)
     p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, n_macro_inner=100, cfl=0.5, region_update_every=1,
-                      force_wall_layers=2)
+                      force_wall_layers=2, source_half=half)
     tol = 1e-9 if dtype == g.F64 else 1e-4
     last = case.limiter_stats()
-    for it in range(4):
+    for it in range(1 if name == "sphere_fast" else 4):
         eo = S.step()
         eg = case.step(p)
         Wg, fl = case.get_state()
