@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--serve-rates", default="5,20,80", help="Poisson arrival rates of the serving leg (1/s)")
     ap.add_argument("--serve-max-iter", type=int, default=300)
     ap.add_argument("--serve-tol", type=float, default=1e-6, help="served solves stop at this residual (Sec. 4)")
+    ap.add_argument("--serve-source-half", type=int, default=1, choices=[0, 1],
+                    help="served solves take the synthetic source at the half step (0: at f^n, W^n)")
     ap.add_argument("--serve-fp64-check", type=int, default=12,
                     help="requests of the middle rate also solved alone by the FP64 per-case path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -200,7 +202,7 @@ def cpu_baseline(mesh, grid, W, flags, seconds):
     return out
 
 
-def serving(g, n, rates, max_iter, tol, n_check, seed=7):
+def serving(g, n, rates, max_iter, tol, n_check, source_half, seed=7):
     """Continuous-batching FP32 server on seeded request streams, one per
     Poisson arrival rate (the same seed: the same requests, arriving faster),
     and `n_check` requests of the middle rate solved one after another by the
@@ -208,13 +210,14 @@ def serving(g, n, rates, max_iter, tol, n_check, seed=7):
     import gsis_inputs as gi
     import paper_2501_02245_amd.serve as sv
     out = {"dtype": "f32", "tol": tol, "max_iter": max_iter,
+           "synthetic_source": "half step (f^{n+1/2}, W^{n+1/2})" if source_half else "f^n, W^n",
            "mix": "seed %d: %d requests per rate, 1D Couette/Fourier 32-512 cells 16^3/32^3 (GSIS), 2D cylinder "
                   "2k-20k cells 32^2/64^2 (aGSIS from the NS start), Kn log-uniform [1e-3, 1], Mach [1, 8], "
                   "Kn_ref 0.01" % (seed, n), "rates": []}
     mid = sorted(rates)[len(rates) // 2]
     for rate in rates:
         reqs = [sv.Request.from_spec(d) for d in gi.serving_requests(n, rate, seed=seed)]
-        srv = sv.Server(64 << 30, dtype=g.F32, max_iter=max_iter, tol=tol)
+        srv = sv.Server(64 << 30, dtype=g.F32, max_iter=max_iter, tol=tol, source_half=source_half)
         t = time.perf_counter()
         res = srv.run(reqs, log=log)
         wall = time.perf_counter() - t
@@ -227,7 +230,7 @@ def serving(g, n, rates, max_iter, tol, n_check, seed=7):
             t = time.perf_counter()
             n64, diff = 0, []
             for q, rr in list(zip(reqs, res))[:n_check]:
-                it, eps, nk, W, status = sv.solve_alone(q, g.F64, max_iter=max_iter, tol=tol)
+                it, eps, nk, W, status = sv.solve_alone(q, g.F64, max_iter=max_iter, tol=tol, source_half=source_half)
                 if status == "ok":
                     n64 += 1
                 if status == "ok" and rr.status == "ok":
@@ -659,7 +662,8 @@ def main():
     if a.serve_requests > 0 and not a.sweep_only:
         t1 = time.time()
         rates = [float(x) for x in a.serve_rates.split(",") if x]
-        out["serving"] = serving(g, a.serve_requests, rates, a.serve_max_iter, a.serve_tol, a.serve_fp64_check)
+        out["serving"] = serving(g, a.serve_requests, rates, a.serve_max_iter, a.serve_tol, a.serve_fp64_check,
+                                 a.serve_source_half)
         log("serving leg %.1f s" % (time.time() - t1))
     if not a.no_cpu_baseline:
         t1 = time.time()

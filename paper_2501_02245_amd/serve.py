@@ -81,11 +81,14 @@ class Server:
     """FIFO admission by footprint, one batched outer iteration per tick."""
 
     def __init__(self, budget_bytes, dtype=F32, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400,
-                 ns_chunks=50, max_active=64, keep_fields=True, min_iter=5, step_graphs=False):
+                 ns_chunks=50, max_active=64, keep_fields=True, min_iter=5, step_graphs=False, source_half=False):
         self.budget = int(budget_bytes)
         # replay each group's outer iteration from a HIP graph between region
         # updates (GSIS_STEP_GRAPHS; results are bitwise those of eager launches)
         self.step_graphs = step_graphs
+        # source of the synthetic equations at the half step (f^{n+1/2},
+        # W^{n+1/2}) rather than at f^n, W^n: same fixed point, fewer iterations
+        self.source_half = int(bool(source_half))
         self.min_iter = min_iter     # a first small change is not convergence
         self.dtype, self.Kn_ref, self.tol, self.max_iter = dtype, Kn_ref, tol, max_iter
         self.n_inner, self.ns_chunks = n_inner, ns_chunks
@@ -227,7 +230,8 @@ class Server:
                 for j0 in range(0, len(grp), 16):
                     part = grp[j0:j0 + 16]
                     try:
-                        eps = step([a.case for a in part], self._params(key[4], key[5], key[6]))
+                        eps = step([a.case for a in part],
+                                   self._params(key[4], key[5], key[6], source_half=self.source_half))
                         err = None
                     except GsisError as e:
                         eps, err = e.eps, e
@@ -287,7 +291,8 @@ def start_case(r: Request, dtype, Kn_ref=0.01, tol=1e-6, n_inner=400, ns_chunks=
     return case
 
 
-def solve_alone(r: Request, dtype, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400, ns_chunks=50, min_iter=5):
+def solve_alone(r: Request, dtype, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400, ns_chunks=50, min_iter=5,
+                source_half=False):
     """One request on its own, with the same steps, stopping rule and
     reservation doubling as the server."""
     while True:
@@ -298,7 +303,7 @@ def solve_alone(r: Request, dtype, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=
                 r = dataclasses.replace(r, capacity=min(1.0, 2.0 * r.capacity))
                 continue
             return 0, np.full(3, np.inf), 0, None, "error: %s" % e
-        p = params_for(r.mode, r.cfl, r.layers, Kn_ref, tol, n_inner)
+        p = params_for(r.mode, r.cfl, r.layers, Kn_ref, tol, n_inner, source_half=int(bool(source_half)))
         it, eps, status = 0, np.full(3, np.inf), "noconv"
         try:
             while it < max_iter:

@@ -44,14 +44,17 @@ def test_graph_replays_equal_eager(g, name, mode):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name,mode", [("cylinder_fast", "agsis"), ("couette", "gsis"), ("sphere_fast", "agsis")])
-def test_step_graph_replays_equal_eager(g, name, mode):
+@pytest.mark.parametrize("name,mode,half", [("cylinder_fast", "agsis", 0), ("couette", "gsis", 0),
+                                            ("sphere_fast", "agsis", 0), ("cylinder_fast", "agsis", 1),
+                                            ("couette", "gsis", 1)])
+def test_step_graph_replays_equal_eager(g, name, mode, half):
     """Whole outer iterations from HIP graphs (GSIS_STEP_GRAPHS=1): sweep,
     moments, HoT, synthetic solve, correction and residual captured per batch
     composition, counts and buffer parity, replayed between region updates
     (re-flagging once, after two iterations, then a fixed region: the later
     steps replay the graphs of the same parity).  Eight iterations with host
-    reads between them are bitwise the eager ones."""
+    reads between them are bitwise the eager ones, with the synthetic source
+    at f^n, W^n and at the half step (its balance pass captured too)."""
     m, grid, Kn, W, flags = workload(name)
     out = {}
     for graphs in ("0", "1"):
@@ -61,10 +64,10 @@ def test_step_graph_replays_equal_eager(g, name, mode):
             if mode == "agsis":
                 case.set_state(W, flags=flags)
                 p = g.SolveParams(mode=g.MODE_AGSIS, Kn_ref=0.01, n_macro_inner=50, cfl=0.5, region_update_every=-2,
-                                  force_wall_layers=2)
+                                  force_wall_layers=2, source_half=half)
             else:
                 case.set_state(W)
-                p = g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=50, cfl=-0.5)
+                p = g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=50, cfl=-0.5, source_half=half)
             eps, Ws = [], []
             for _ in range(8):
                 eps.append(case.step(p))

@@ -21,10 +21,12 @@ def _requests(n, seed, **kw):
     return [sv.Request.from_spec(d) for d in gi.serving_requests(n, 50.0, seed=seed, **kw)]
 
 
-def test_served_equals_alone(g):
+@pytest.mark.parametrize("half", [0, 1])
+def test_served_equals_alone(g, half):
     """Six requests arriving together (1D boxes of different sizes and grids,
     one small cylinder) share batched launches; every one ends bitwise where it
-    ends alone, after the same number of iterations."""
+    ends alone, after the same number of iterations (synthetic source at f^n,
+    W^n and at the half step)."""
     import paper_2501_02245_amd.serve as sv
     reqs = _requests(5, 3, kinds=("couette", "fourier"), cells_1d=(24, 64), nv_1d=(16, 32),
                      Kn_range=(0.01, 0.5), mach_range=(1.0, 3.0))
@@ -33,32 +35,34 @@ def test_served_equals_alone(g):
     reqs[-1].rid = len(reqs) - 1
     for r in reqs:
         r.arrival = 0.0
-    srv = sv.Server(budget_bytes=8 << 30, max_iter=40)
+    srv = sv.Server(budget_bytes=8 << 30, max_iter=40, source_half=half)
     res = srv.run(reqs, log=lambda m: print(m, flush=True))
     for out in res:
         print("served", out.rid, out.kind, out.status, out.iterations, flush=True)
     assert len(res) == len(reqs)
     assert srv.peak_active == len(reqs)
     for r, out in zip(reqs, res):
-        it, eps, nk, W, status = sv.solve_alone(r, g.F32, max_iter=40)
+        it, eps, nk, W, status = sv.solve_alone(r, g.F32, max_iter=40, source_half=half)
         print(r.rid, r.kind, status, out.status, it, out.iterations, flush=True)
         assert status == out.status and it == out.iterations
         assert np.array_equal(W, out.W)
 
 
-def test_served_matches_oracle(g, oracle_mod):
+@pytest.mark.parametrize("half", [0, 1])
+def test_served_matches_oracle(g, oracle_mod, half):
     """Three 1D requests served in FP32 against the FP64 oracle run with the
     same steps and stopping rule (GSIS, global pseudo-time step, tol 1e-6 on
-    the fields the request converges on): converged fields within 1e-4."""
+    the fields the request converges on, synthetic source at f^n, W^n or at
+    the half step): converged fields within 1e-4."""
     import paper_2501_02245_amd.serve as sv
     reqs = _requests(3, 12, kinds=("couette", "fourier"), cells_1d=(24, 40), nv_1d=(16,), Kn_range=(0.03, 0.12),
                      mach_range=(1.0, 2.0))
-    srv = sv.Server(budget_bytes=4 << 30, max_iter=300)
+    srv = sv.Server(budget_bytes=4 << 30, max_iter=300, source_half=half)
     res = srv.run(reqs)
     for r, out in zip(reqs, res):
         assert out.status == "ok", out.status
         O = oracle_mod.Oracle(r.mesh, r.grid, r.Kn)
-        S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=r.cfl)
+        S = oracle_mod.SteadySolver(O, mode="gsis", n_inner=400, cfl=r.cfl, source_half=bool(half))
         S.set_state(r.W0)
         for _ in range(300):
             e = S.step()
