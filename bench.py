@@ -234,8 +234,13 @@ def serving(g, n, rates, max_iter, tol, n_check, source_half, seed=7):
                 if status == "ok":
                     n64 += 1
                 if status == "ok" and rr.status == "ok":
-                    scale = np.maximum(np.abs(W).max(axis=0), 1e-3)
-                    diff.append(float((np.abs(W - rr.W).max(axis=0) / scale).max()))
+                    # per field, relative to its largest value; u (a vector) to
+                    # max(|u|, 0.1), since the boxes' flows are nearly at rest
+                    d = np.abs(W - rr.W)
+                    diff.append(max(d[:, 0].max() / np.abs(W[:, 0]).max(),
+                                    d[:, 1:4].max() / max(np.abs(W[:, 1:4]).max(), 0.1),
+                                    d[:, 4].max() / np.abs(W[:, 4]).max()))
+                    log("served vs fp64: request %d (%s) %.2e" % (q.rid, q.kind, diff[-1]))
                 log("fp64 alone: request %d %s after %d iterations" % (q.rid, status, it))
             wall64 = time.perf_counter() - t
             r["fp64_per_case"] = {"requests": n_check, "solved": n64, "wall_s": wall64,
