@@ -496,6 +496,12 @@ class Oracle:
         q = q.n with the NSF laws at T_w evaluated on the LSQ cell gradient
         whose normal part is replaced by the one-sided difference to the wall
         values (the wall flux of the synthetic equations).
+
+        Two-VDF gas (W with T_r as a sixth column): the energy carried is
+        |c|^2 f0 + 2 f1 (the total energy of the scaled units), the reflected
+        f1 is (d_r T_w / 4) rho_w M (internal modes in equilibrium with the
+        wall), and an NS wall cell's heat flux is (q_t + q_r).n of the
+        two-temperature NSF laws with T_r also held at T_w.
         """
         m = self.mesh
         fc = m["face_cells"]
@@ -516,12 +522,17 @@ class Oracle:
                 a = c @ n
                 c2 = np.sum(c * c, axis=1)
                 M = self.maxwellian(1.0, uw, Tw).reshape(self.nfun, self.nv)
+                if self.poly:
+                    M[1] = 0.25 * self.dr * Tw * M[0]
                 row = np.asarray(f[s], dtype=np.float64).reshape(self.nfun, self.nv)
                 inc, ref = a > 0, a < 0
                 rho_w = np.sum(self.w[inc] * a[inc] * row[0, inc]) / np.sum(self.w[ref] * -a[ref] * M[0, ref])
                 g = np.where(inc[None, :], row, np.where(ref[None, :], rho_w * M, 0.0))
                 tau = 2.0 * np.sum((self.w * a * g[0])[:, None] * c, axis=0)
-                e = c2 * g[0] + (g[1] if self.nfun == 2 else 0.0)
+                if self.poly:
+                    e = c2 * g[0] + 2.0 * g[1]
+                else:
+                    e = c2 * g[0] + (g[1] if self.nfun == 2 else 0.0)
                 q = np.sum(self.w * a * e)
                 mass = np.sum(self.w * a * g[0])
             else:
@@ -531,7 +542,15 @@ class Oracle:
                 G = grad[L, 0:4, :].copy()
                 for v in range(4):
                     G[v] += ((wall[v] - cellv[v]) / dn - np.dot(G[v], n)) * n
-                sg, qv = self.nsf(Tw, G[0:3], G[3])
+                if self.poly:
+                    Gr = grad[L, 6, :].copy()
+                    Gr += ((Tw - W[L, 5]) / dn - np.dot(Gr, n)) * n
+                    sg, qt, qr = np.zeros(6), np.zeros(3), np.zeros(3)
+                    gu, gt, gr = _f64(G[0:3]).reshape(9).copy(), _f64(G[3]).copy(), _f64(Gr).copy()
+                    lib().oc_nsf_poly(C.byref(self.gas), float(Tw), _p(gu), _p(gt), _p(gr), _p(sg), _p(qt), _p(qr))
+                    qv = qt + qr
+                else:
+                    sg, qv = self.nsf(Tw, G[0:3], G[3])
                 S = np.array([[sg[0], sg[3], sg[4]], [sg[3], sg[1], sg[5]], [sg[4], sg[5], sg[2]]])
                 tau = W[L, 0] * W[L, 4] * n + S @ n
                 q = float(np.dot(qv, n))

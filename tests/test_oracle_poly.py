@@ -259,3 +259,102 @@ def test_poly_gsis_fixed_point_is_dvm_fixed_point(oracle_mod):
     assert np.abs(S.W - D.W).max() < 1e-9
     fd = D.f[D.slot[D.kin]]
     assert np.abs(S.f[S.slot[S.kin]] - fd).max() < 1e-9 * np.abs(fd).max()
+
+
+# ---------------------------------------------------------------------------
+# surface quantities of the two-VDF gas (Sec. 4.2/4.3 with the internal
+# energy of Sec. 2): wall values of f1 are (d_r T_w/4) f0's
+# ---------------------------------------------------------------------------
+def _wall_side(m, faces):
+    return np.sign(m["face_normal"][faces, 0])
+
+
+def test_poly_surface_rest_at_wall_temperature(oracle_mod):
+    """Nitrogen at rest at the walls' temperature with its internal modes in
+    equilibrium (T_r = T_w; rows f0 = M, f1 = (d_r T_w/4) M): the wall stress
+    is the pressure along the normal, no shear, no heat and no net mass flux,
+    on kinetic and on NS wall cells."""
+    m = gi.couette_1d(6, wall_speed=0.0, T_wall=1.2)
+    O = _oracle(oracle_mod, m, n=16, V=5.0, Kn=0.1)
+    M = O.maxwellian(0.9, [0, 0, 0], 1.2)[0]
+    f = np.stack([np.stack([M, 0.25 * N2["dr"] * 1.2 * M])] * 6)
+    W = np.tile([0.9, 0, 0, 0, 1.2, 1.2], (6, 1))
+    kin = np.arange(6)
+    for slot in (kin, -np.ones(6, np.int64)):
+        faces, out = O.surface(f, slot, W)
+        n = m["face_normal"][faces]
+        p = out[:, 3]
+        assert np.allclose(out[:, 0:3], p[:, None] * n, atol=1e-12)
+        assert np.abs(out[:, 4:7]).max() < 1e-12
+        assert np.abs(out[:, 7]).max() < 1e-12 and np.abs(out[:, 8]).max() < 1e-12
+        assert np.allclose(p, 0.9 * 1.2, rtol=1e-6)
+
+
+def test_poly_surface_free_molecular_fourier(oracle_mod):
+    """Free-molecular nitrogen between stationary walls at T_L and T_R: in the
+    discrete steady state the heat into each wall is the gas's total heat
+    flux q_t + q_r (q_r = 2 sum w c f1 carries the internal energy), the two
+    walls' heat sums to zero, and against the continuous closed form each
+    molecule leaving a wall carries (d_r/2) T_w of internal energy besides its
+    translational energy, so q = n_L sqrt(T_L)(T_L - T_R)(1 + d_r/4)/sqrt(pi)
+    to the quadrature error.  A dropped factor 2 on f1 or a reflected f1 at
+    the wrong temperature fails the last check."""
+    TL, TR, n = 1.0, 1.5, 12
+    m = gi.fourier_1d(n, TL, TR)
+    g = gi.velocity_grid(3, (96, 16, 16), (8.0, 6.0, 6.0))
+    O = oracle_mod.Oracle(m, g, Kn=1e14, omega=N2["omega"], Pr=N2["A"][0], dr=N2["dr"], Zr=N2["Zr"], A=N2["A"])
+    f = np.stack([O.feq(np.array([1.0, 0, 0, 0, 1.0]))] * n)
+    kin = np.arange(n)
+    for _ in range(n + 2):
+        f = O.sweep(f, kin, kin)
+    mom = O.moments(f)
+    W = np.concatenate([mom[:, :5], mom[:, 14:15]], 1)
+    faces, out = O.surface(f, kin, W)
+    side = _wall_side(m, faces)
+    R, L = np.nonzero(side > 0)[0][0], np.nonzero(side < 0)[0][0]
+    q = mom[0, 11] + mom[0, 15]
+    assert mom[0, 15] < 0 and q < 0    # heat, internal part included, flows to the cold left wall
+    assert abs(out[L, 7] / -q - 1) < 1e-10
+    assert abs(out[R, 7] / q - 1) < 1e-10
+    assert abs(out[L, 7] + out[R, 7]) < 1e-12 * abs(q)
+    assert np.abs(out[:, 8]).max() < 1e-13
+    xi, w = O.xi, O.w
+    pos, neg = xi[:, 0] > 0, xi[:, 0] < 0
+    wn = w * np.abs(xi[:, 0])
+
+    def gauss(T):
+        return (np.pi * T) ** -1.5 * np.exp(-np.sum(xi * xi, axis=1) / T)
+    nL = np.sum(wn[neg] * gauss(1.0)[neg]) / np.sum(wn[pos] * gauss(TL)[pos])
+    qcf = nL * np.sqrt(TL) * (TL - TR) * (1 + 0.25 * N2["dr"]) / np.sqrt(np.pi)
+    assert abs(out[R, 7] / qcf - 1) < 5e-3
+
+
+def test_poly_surface_ns_wall_linear_fields(oracle_mod):
+    """NS wall cells of nitrogen: with u_y, T_t and T_r linear in x and the
+    walls at the end values (T_r held at T_w as well), the one-sided gradients
+    are exact, so the shear is -(2 Kn/sqrt(pi)) mu du_y/dx n_x and the heat
+    into the wall is (k_t dT_t/dx + k_r dT_r/dx)(Kn/sqrt(pi)) mu (-n_x), with
+    mu = T_w^omega and (k_t, k_r) = (1/2) A^{-1} (5, d_r) (eq. mu_kappa)."""
+    n, a, b, Kn = 10, 0.3, 0.4, 0.05
+    m = gi.couette_1d(n, wall_speed=0.5 * a)
+    for p in m["patches"]:
+        p["T"] = 1.0 + b * (0.0 if p["u"][1] < 0 else 1.0)
+    x = m["cell_center"][:, 0]
+    W = np.zeros((n, 6))
+    W[:, 0] = 1.0
+    W[:, 2] = a * (x - 0.5)
+    W[:, 4] = 1.0 + b * x
+    W[:, 5] = 1.0 + b * x
+    O = _oracle(oracle_mod, m, n=8, V=5.0, Kn=Kn)
+    faces, out = O.surface(np.zeros((n, 2, O.nv)), -np.ones(n, np.int64), W)
+    side = _wall_side(m, faces)
+    A = np.array(N2["A"]).reshape(2, 2)
+    kt, kr = 0.5 * np.linalg.solve(A, [5.0, N2["dr"]])
+    for j, fi in enumerate(faces):
+        Tw = m["patches"][-1 - m["face_cells"][fi, 1]]["T"]
+        mu = Tw ** N2["omega"]
+        L = m["face_cells"][fi, 0]
+        c = Kn / np.sqrt(np.pi) * mu
+        assert abs(out[j, 1] - (-2 * c * a * side[j])) < 1e-12
+        assert abs(out[j, 7] - (-(kt + kr) * c * b * side[j])) < 1e-12
+        assert abs(out[j, 3] - W[L, 0] * W[L, 4]) < 1e-12
