@@ -152,7 +152,7 @@ gsis_status gsis_set_velocity_points(gsis_case c, int32_t n_points, const double
  * starts at T_t on every cell (set_state), the kinetic cells then taking that
  * of their f1.  Supported: 3D tensor velocity grids, spatial order 1, every
  * mode of gsis_step / gsis_solve_steady, gsis_ns_init, gsis_update_regions;
- * gsis_correct, gsis_surface and gsis_macro_solve return E_ARG.  Gas Pr is
+ * gsis_surface; gsis_correct and gsis_macro_solve return E_ARG.  Gas Pr is
  * not used.  Call before gsis_case_footprint / bind (E_STATE once bound);
  * E_ARG for d_r < 0, Z_r < 1 or non-finite A. */
 gsis_status gsis_set_internal_dof(gsis_case c, double d_r, double Z_r, const double *A);
@@ -352,7 +352,10 @@ gsis_status gsis_get_state(gsis_case c, double *W_dev, uint8_t *flags_dev, void 
  * discrete zero-mass-flux condition: tau = 2 sum w c (c.n) f,
  * q = sum w (c.n) |c|^2 f (reduced 2D: |c|^2 phi + psi).  On an NS wall cell
  * tau = rho T n + sigma_NSF.n and q = q_NSF.n with the one-sided wall
- * gradients of the synthetic solve.  face_dev [n_wall] int32 (nullable)
+ * gradients of the synthetic solve.  Two-VDF gas (gsis_set_internal_dof): the
+ * energy carried is |c|^2 f0 + 2 f1, reflected f1 = (d_r T_w / 4) rho_w M, and
+ * an NS wall cell's heat flux is (q_t + q_r).n with T_r also held at T_w (so C_h
+ * includes the internal energy).  face_dev [n_wall] int32 (nullable)
  * receives the face ids; totals_dev [4] (nullable) the integrals
  * sum tau S (3) and sum q S in fixed order.  All device buffers are the
  * caller's; nothing synchronises. */

@@ -1646,7 +1646,6 @@ extern "C" gsis_status gsis_surface(gsis_case c, int32_t *face_dev, double *out,
 {
     gsis_status st = check_ready(c);
     if (st) return st;
-    if ((st = refuse_poly(c, "gsis_surface"))) return st;
     if (!out) return fail(GSIS_E_ARG, "null output");
     hipStream_t s = (hipStream_t)stream;
     CaseView &h = c->hv;

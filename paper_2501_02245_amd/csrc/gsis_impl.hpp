@@ -354,6 +354,7 @@ hipError_t launch_check_W(const CaseView *cv, const CaseView &h, const double *W
 hipError_t launch_ghost_poly(const CaseView *cv, const CaseView &h, const double *W, const double *Tr, hipStream_t s);
 // HoT of sigma, q_t (hot) and q_r (hotr) on kinetic cells at W^{n+1/2}
 hipError_t launch_hot_poly(const CaseView *cv, const CaseView &h, hipStream_t s);
+hipError_t launch_surface_ns_poly(const CaseView *cv, const CaseView &h, double *out, hipStream_t s);
 // out = T_r of the moments on kinetic cells, Tr elsewhere (out may be Tr)
 hipError_t launch_tr_half(const CaseView *cv, const CaseView &h, double *out, hipStream_t s);
 // synthetic residual per unit volume at (W, Tr), with the exchange source

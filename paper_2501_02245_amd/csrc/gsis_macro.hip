@@ -992,7 +992,9 @@ __global__ __launch_bounds__(256) void k_surface(const CaseView *__restrict__ cv
     const int slot = C.slot_of_cell[L];
     double *o = out + (size_t)j * GSIS_NSURF;
     if (slot < 0) {
-        if (threadIdx.x != 0) return;
+        // the two-VDF gas's NS wall cells take the two-temperature NSF laws
+        // (k_surface_ns_p)
+        if (C.poly || threadIdx.x != 0) return;
         const double *PL = C.W + 5 * (size_t)L;
         const double dn = 0.5 * C.face_dist[f];
         const double *gL = grad_row(C, L, 0);
@@ -1034,14 +1036,18 @@ __global__ __launch_bounds__(256) void k_surface(const CaseView *__restrict__ cv
         const double a = c[0] * n[0] + c[1] * n[1] + c[2] * n[2];
         const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
         if (a > 0.0) {
+            // energy carried: |c|^2 f (3D), |c|^2 phi + psi (reduced 2D),
+            // |c|^2 f0 + 2 f1 (two-VDF gas: translational plus internal)
             const double f0 = (double)row[k];
-            const double e = (vd == 3) ? c2 * f0 : c2 * f0 + (double)row[nvp + k];
+            const double e = C.poly ? c2 * f0 + 2.0 * (double)row[nvp + k]
+                                    : ((vd == 3) ? c2 * f0 : c2 * f0 + (double)row[nvp + k]);
             acc[0] += w * a * f0;
             for (int d = 0; d < 3; ++d) acc[1 + d] += w * a * c[d] * f0;
             acc[4] += w * a * e;
         } else if (a < 0.0) {
+            // reflected: the wall Maxwellian, with f1 = (d_r T_w / 4) M for the two-VDF gas
             const double m = amp * exp(-c2 * it);
-            const double e = (vd == 3) ? c2 * m : (c2 + 0.5 * Tw) * m;
+            const double e = C.poly ? (c2 + 0.5 * C.dr * Tw) * m : ((vd == 3) ? c2 * m : (c2 + 0.5 * Tw) * m);
             acc[5] -= w * a * m;
             for (int d = 0; d < 3; ++d) acc[6 + d] += w * a * c[d] * m;
             acc[9] += w * a * e;
@@ -1106,6 +1112,10 @@ hipError_t launch_surface(const CaseView *cv, const CaseView &h, int cur, double
     if (e != hipSuccess) return e;
     if (h.dtype == GSIS_F32) hipLaunchKernelGGL(k_surface<float>, dim3(h.n_wall), dim3(256), 0, s, cv, cur, out);
     else hipLaunchKernelGGL(k_surface<double>, dim3(h.n_wall), dim3(256), 0, s, cv, cur, out);
+    if (h.poly) {
+        e = launch_surface_ns_poly(cv, h, out, s);
+        if (e != hipSuccess) return e;
+    }
     if (totals) hipLaunchKernelGGL(k_surface_totals, dim3(1), dim3(256), 0, s, cv, (const double *)out, totals);
     return hipGetLastError();
 }

@@ -506,6 +506,53 @@ __global__ void k_copy_dd(double *d, const double *s, int n)
     if (i < n) d[i] = s[i];
 }
 
+// surface quantities on the NS wall cells of the two-VDF gas (Sec. 4.2/4.3):
+// the wall flux of its synthetic equations -- pressure rho T_t plus the NSF
+// stress, and the heat flux (q_t + q_r).n, from the LSQ gradients of u, T_t
+// and T_r whose normal parts are replaced by one-sided differences to the
+// wall values (T_r held at T_w like T_t).  One thread per wall face; faces of
+// kinetic cells are left to k_surface.
+__global__ __launch_bounds__(256) void k_surface_ns_p(const CaseView *__restrict__ cvp, double *__restrict__ out)
+{
+    const CaseView &C = *cvp;
+    const int j = blockIdx.x * 256 + (int)threadIdx.x;
+    if (j >= C.n_wall) return;
+    const int f = C.wall_face[j];
+    const int L = C.face_cells[2 * f], p = -1 - C.face_cells[2 * f + 1];
+    if (C.slot_of_cell[L] >= 0) return;
+    const double *ps = C.patch_state + 5 * p;
+    const double *n = C.face_normal + 3 * (size_t)f;
+    const double *PL = C.W + 5 * (size_t)L;
+    const double TrL = C.Tr[L];
+    const double dn = 0.5 * C.face_dist[f];
+    const double *gL = grad_ut(C, L), *tL = C.gTr + 3 * (size_t)L;
+    double G[5][3];
+    for (int v = 0; v < 5; ++v) {
+        const double *gv = (v < 4) ? gL + 3 * v : tL;
+        const double gn = gv[0] * n[0] + gv[1] * n[1] + gv[2] * n[2];
+        const double fl = (v < 3) ? PL[1 + v] : ((v == 3) ? PL[4] : TrL);
+        const double wv = (v < 3) ? ps[1 + v] : ps[4];
+        const double jump = (wv - fl) / dn;
+        for (int d = 0; d < 3; ++d) G[v][d] = gv[d] + (jump - gn) * n[d];
+    }
+    double Gu[9] = {G[0][0], G[0][1], G[0][2], G[1][0], G[1][1], G[1][2], G[2][0], G[2][1], G[2][2]};
+    double sg[6], qt[3], qr[3];
+    nsf_poly(C, ps[4], Gu, G[3], G[4], sg, qt, qr);
+    const double pL = PL[0] * PL[4];
+    const double tau[3] = {pL * n[0] + sg[0] * n[0] + sg[3] * n[1] + sg[4] * n[2],
+                           pL * n[1] + sg[3] * n[0] + sg[1] * n[1] + sg[5] * n[2],
+                           pL * n[2] + sg[4] * n[0] + sg[5] * n[1] + sg[2] * n[2]};
+    const double pn = tau[0] * n[0] + tau[1] * n[1] + tau[2] * n[2];
+    double *o = out + (size_t)j * GSIS_NSURF;
+    for (int d = 0; d < 3; ++d) {
+        o[d] = tau[d];
+        o[4 + d] = tau[d] - pn * n[d];
+    }
+    o[3] = pn;
+    o[7] = (qt[0] + qr[0]) * n[0] + (qt[1] + qr[1]) * n[1] + (qt[2] + qr[2]) * n[2];
+    o[8] = 0.0;
+}
+
 // the lane-per-face cell kernels: blocks of MCELLS_Q cells covering n_cells,
 // G = 4 lanes per cell on tetrahedral meshes, else GSIS_MAX_FACES
 void lsq_tr(const CaseView *cv, int n_cells, int nfmax, const double *Tr, hipStream_t s)
@@ -551,6 +598,16 @@ hipError_t launch_hot_poly(const CaseView *cv, const CaseView &h, hipStream_t s)
     const dim3 g((h.n_cells + 127) / 128);
     lsq_tr(cv, h.n_cells, h.nfmax, (const double *)h.Trh, s);
     hipLaunchKernelGGL(k_hot_p, g, dim3(128), 0, s, cv);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_ns_poly(const CaseView *cv, const CaseView &h, double *out, hipStream_t s)
+{
+    if (h.n_wall <= 0) return hipSuccess;
+    // T_r gradients of the current state (the u, T_t rows come with the
+    // surface launch's own LSQ pass)
+    lsq_tr(cv, h.n_cells, h.nfmax, (const double *)h.Tr, s);
+    hipLaunchKernelGGL(k_surface_ns_p, dim3((h.n_wall + 255) / 256), dim3(256), 0, s, cv, out);
     return hipGetLastError();
 }
 

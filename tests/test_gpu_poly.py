@@ -5,7 +5,8 @@ ragged tail, and on the Mach-5 sphere's partial region (NS neighbours,
 Grad-13 ghosts, far field, walls); the state filled from W; DVM, GSIS and
 aGSIS outer iterations (synthetic solve with the internal-energy equation,
 correction of both VDFs, region updates); the NS start; a converged GSIS
-solution; and the calls the polyatomic gas refuses.
+solution; the surface quantities with the internal energy; and the calls
+the polyatomic gas refuses.
 Tolerances: FP32 1e-5 per sweep, FP64 1e-11; outer iterations FP64 1e-9,
 FP32 1e-4 (the synthetic solve's 100-400 pseudo-time steps amplify the
 sweep's rounding).
@@ -276,8 +277,6 @@ def test_poly_refusals(g):
     with pytest.raises(g.GsisError):
         case.correct(W)
     with pytest.raises(g.GsisError):
-        case.surface()
-    with pytest.raises(g.GsisError):
         case.macro_solve(W, np.zeros((m["n_cells"], 9)), n_inner=10)
     A = np.array(N2["A"])
     with pytest.raises(g.GsisError):
@@ -294,3 +293,57 @@ def test_poly_refusals(g):
         g.Case(g.Mesh(m), gi.ball_grid(8, 4.0), Kn, dtype=g.F64, dr=2.0, Zr=2.0, A=N2["A"])
     with pytest.raises(g.GsisError):   # nor a reduced 2D grid
         g.Case(g.Mesh(m), gi.velocity_grid(2, 8, 4.0), Kn, dtype=g.F64, dr=2.0, Zr=2.0, A=N2["A"])
+
+
+def _wall_cells(m):
+    fc = m["face_cells"]
+    wall = [p for p, pt in enumerate(m["patches"]) if pt["kind"] == "wall"]
+    b = fc[:, 1] < 0
+    return np.unique(fc[b & np.isin(-1 - fc[:, 1], wall), 0])
+
+
+@pytest.mark.parametrize("name", ["couette", "sphere_small", "couette_after_step"])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_poly_surface_matches_oracle(g, oracle_mod, name, dtype):
+    """Surface quantities of the two-VDF gas (Sec. 4.2/4.3 with the internal
+    energy of Sec. 2): kinetic wall cells whose f1 is out of equilibrium
+    (T_r = 0.8 T, q_r != 0) and, on the sphere, NS wall cells beside them
+    (every other wall cell switched to NS, T_r from the library's state); the
+    Couette slab also after one GSIS outer iteration (the rows then sit in the
+    other buffer).  The oracle takes the device's rows, W and T_r, so both
+    sides sum the same numbers in FP64: 1e-10 of each column group's scale."""
+    base = "couette" if name.startswith("couette") else name
+    m, grid, Kn, W, flags = workload(base)
+    flags = flags.copy()
+    wc = _wall_cells(m)
+    if base != "couette":
+        flags[wc[::2]] = 0
+    O, case = _pair(oracle_mod.Oracle, g, m, grid, Kn, dtype)
+    kin = np.nonzero(flags)[0]
+    case.set_state(W, vdf=_rows(grid, W[kin], 5, dtype), flags=flags)
+    if name == "couette_after_step":
+        case.step(g.SolveParams(mode=g.MODE_GSIS, n_macro_inner=20, cfl=0.5))
+    Wg, fl = case.get_state()
+    Wg, fl = Wg.cpu().numpy(), fl.cpu().numpy()
+    Wo = np.concatenate([Wg, case.internal_temperature().cpu().numpy()[:, None]], 1)
+    k = np.nonzero(fl)[0]
+    slot = -np.ones(m["n_cells"], np.int64)
+    slot[k] = np.arange(len(k))
+    rows = case.get_vdf().cpu().numpy().astype(np.float64)
+    faces_o, out_o = O.surface(rows, slot, Wo)
+    faces, out, tot = case.surface()
+    faces, out, tot = faces.cpu().numpy(), out.cpu().numpy(), tot.cpu().numpy()
+    assert np.array_equal(faces, faces_o)
+    scale_p = np.abs(out_o[:, 3]).max()
+    scale_q = max(np.abs(out_o[:, 7]).max(), 1e-300)
+    e_tau = np.abs(out[:, 0:7] - out_o[:, 0:7]).max() / scale_p
+    e_q = np.abs(out[:, 7] - out_o[:, 7]).max() / scale_q
+    e_m = np.abs(out[:, 8] - out_o[:, 8]).max() / scale_p
+    S = m["face_area"][faces_o]
+    tot_o = np.concatenate([(out_o[:, 0:3] * S[:, None]).sum(0), [(out_o[:, 7] * S).sum()]])
+    e_tot = np.abs(tot - tot_o).max() / max(np.abs(tot_o).max(), 1e-300)
+    n_kw = np.isin(wc, k).sum()
+    print("poly surface", name, dtype, "wall cells", len(wc), "kinetic", n_kw, "tau", e_tau, "q", e_q, "mass", e_m,
+          "totals", e_tot, flush=True)
+    assert n_kw > 0 and (base == "couette" or n_kw < len(wc))
+    assert e_tau < 1e-10 and e_q < 1e-10 and e_m < 1e-10 and e_tot < 1e-10
