@@ -152,7 +152,8 @@ gsis_status gsis_set_velocity_points(gsis_case c, int32_t n_points, const double
  * starts at T_t on every cell (set_state), the kinetic cells then taking that
  * of their f1.  Supported: 3D tensor velocity grids, spatial order 1, every
  * mode of gsis_step / gsis_solve_steady, gsis_ns_init, gsis_update_regions;
- * gsis_surface; gsis_correct and gsis_macro_solve return E_ARG.  Gas Pr is
+ * gsis_surface, gsis_correct_internal and gsis_macro_solve_internal (the
+ * monatomic gsis_correct and gsis_macro_solve return E_ARG).  Gas Pr is
  * not used.  Call before gsis_case_footprint / bind (E_STATE once bound);
  * E_ARG for d_r < 0, Z_r < 1 or non-finite A. */
 gsis_status gsis_set_internal_dof(gsis_case c, double d_r, double Z_r, const double *A);
@@ -378,6 +379,29 @@ gsis_status gsis_force_coefficients(const double *totals, double rho_inf, const 
  * f += f_eq(W_new) - f_eq(W_half) on kinetic cells, where W_half are the
  * current moments and W_new_dev [n_cells][5] FP64; W becomes W_new. */
 gsis_status gsis_correct(gsis_case c, const double *W_new_dev, void *stream);
+
+/* GSIS correction of the two-VDF gas alone (Sec. 3.1 eq. updatef with rho e_r
+ * in W): f0 += f_eq(W_new) - f_eq(W_half) and f1 += (d_r/4)(T_r,new
+ * f_eq(W_new) - T_r,half f_eq(W_half)) on kinetic cells, where W_half and
+ * T_r,half are the current rows' moments; W_new_dev [n_cells][5] and
+ * Tr_new_dev [n_cells] FP64 device memory (T_r > 0); W and T_r become the new
+ * ones.  The correction limiter acts as in gsis_step.  E_ARG for a monatomic
+ * case (gsis_correct) or null inputs; E_STATE before set_state. */
+gsis_status gsis_correct_internal(gsis_case c, const double *W_new_dev, const double *Tr_new_dev, void *stream);
+
+/* Synthetic macroscopic solve of the two-VDF gas alone (Sec. 2 eq.
+ * macroscopic_equation_2 with its internal-energy line, eq. macro, FP64):
+ * n_inner pseudo-time steps from W_dev [n_cells][5] and Tr_dev [n_cells]
+ * (both in/out) with high-order terms hot_dev [n_cells][9] (sigma 6, q_t 3)
+ * and hot_r_dev [n_cells][3] (q_r; null: zero), and sources per unit volume
+ * src_dev [n_cells][5] (null: none) and src_r_dev [n_cells] (rho e_r; null:
+ * zero).  The internal-energy exchange of the synthetic equations is part of
+ * the step.  Synchronises `stream`; E_NONFINITE when a state goes non-positive;
+ * E_ARG for a monatomic case (gsis_macro_solve), null W, Tr or hot, or bad
+ * n_inner / cfl. */
+gsis_status gsis_macro_solve_internal(gsis_case c, double *W_dev, double *Tr_dev, const double *hot_dev,
+                                      const double *hot_r_dev, const double *src_dev, const double *src_r_dev,
+                                      int32_t n_inner, double cfl, void *stream);
 
 /* Synthetic macroscopic solve alone (eq. macro, FP64): n_inner pseudo-time
  * steps from W_dev [n_cells][5] (in/out) with high-order terms hot_dev

@@ -32,7 +32,7 @@ EXPORTS = [
     "gsis_sweep_layout", "gsis_ns_init", "gsis_n_wall_faces", "gsis_surface", "gsis_set_velocity_points",
     "gsis_set_spatial_order", "gsis_set_internal_dof", "gsis_internal_moments",
     "gsis_set_g13_limit", "gsis_limiter_stats", "gsis_case_bind_static", "gsis_get_internal_temperature",
-    "gsis_force_coefficients",
+    "gsis_force_coefficients", "gsis_correct_internal", "gsis_macro_solve_internal",
 ]
 
 
@@ -116,6 +116,8 @@ def lib():
             "gsis_force_coefficients": [P, D, P, D, P],
             "gsis_set_g13_limit": [P, D], "gsis_limiter_stats": [P, P, P],
             "gsis_case_bind_static": [P, I64, P],
+            "gsis_correct_internal": [P, P, P, P],
+            "gsis_macro_solve_internal": [P, P, P, P, P, P, P, I32, D, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -364,6 +366,24 @@ class Case:
         import torch
         Wd = _dev(W_new, torch.float64)
         _check(lib().gsis_correct(self.handle, _ptr(Wd), _stream()))
+
+    def correct_internal(self, W_new, Tr_new):
+        """Two-VDF gas: the correction with the internal temperature (gsis_correct_internal)."""
+        import torch
+        Wd = _dev(W_new, torch.float64)
+        Td = _dev(Tr_new, torch.float64)
+        _check(lib().gsis_correct_internal(self.handle, _ptr(Wd), _ptr(Td), _stream()))
+
+    def macro_solve_internal(self, W, Tr, hot, hot_r=None, src=None, src_r=None, n_inner=1, cfl=0.5):
+        """Two-VDF gas: the synthetic solve alone (gsis_macro_solve_internal); returns (W, T_r) on the device."""
+        import torch
+        Wd = _dev(W, torch.float64)
+        Td = _dev(Tr, torch.float64)
+        args = [_dev(a, torch.float64) if a is not None else None for a in (hot, hot_r, src, src_r)]
+        _check(lib().gsis_macro_solve_internal(self.handle, _ptr(Wd), _ptr(Td), *[_ptr(a) if a is not None else None
+                                                                                  for a in args],
+                                               n_inner, cfl, _stream()))
+        return Wd, Td
 
     def macro_solve(self, W, hot, src=None, n_inner=1, cfl=0.5):
         import torch

@@ -1635,6 +1635,28 @@ extern "C" gsis_status gsis_correct(gsis_case c, const double *W_new, void *stre
     return GSIS_OK;
 }
 
+extern "C" gsis_status gsis_correct_internal(gsis_case c, const double *W_new, const double *Tr_new, void *stream)
+{
+    gsis_status st = check_ready(c);
+    if (st) return st;
+    if (!(c->dr > 0)) return fail(GSIS_E_ARG, "gsis_correct_internal: a monatomic case (use gsis_correct)");
+    if (!W_new || !Tr_new) return fail(GSIS_E_ARG, "null W_new or Tr_new");
+    hipStream_t s = (hipStream_t)stream;
+    CaseView &h = c->hv;
+    // W^{n+1/2} and T_r^{n+1/2}: the moments of the current rows on kinetic cells
+    HIPCHK(launch_whalf(c->cv, h, c->n_kin, s));
+    HIPCHK(launch_tr_half(c->cv, h, h.Trh, s));
+    HIPCHK(launch_copy_W(h.Wn, W_new, h.n_cells, s));
+    HIPCHK(launch_copy_d(h.Trn, Tr_new, h.n_cells, s));
+    HIPCHK(launch_check_W(c->cv, h, h.Wn, s));
+    HIPCHK(launch_feqpar(c->cv, h, c->n_kin, s));
+    HIPCHK(launch_correct(c->cv, h, c->n_kin, c->cur, s));
+    HIPCHK(launch_reduce(c->cv, h, c->n_kin, 0, s));
+    HIPCHK(launch_copy_W(h.W, h.Wn, h.n_cells, s));
+    HIPCHK(launch_copy_d(h.Tr, h.Trn, h.n_cells, s));
+    return GSIS_OK;
+}
+
 extern "C" gsis_status gsis_n_wall_faces(gsis_case c, int32_t *n_wall)
 {
     if (!c || !n_wall) return fail(GSIS_E_ARG, "null argument");
@@ -1682,6 +1704,32 @@ extern "C" gsis_status gsis_macro_solve(gsis_case c, double *W, const double *ho
     HIPCHK(hipMemsetAsync(c->hv.status, 0, 16, s));
     HIPCHK(launch_check_W(c->cv, c->hv, W, s));
     HIPCHK(launch_macro_steps(c->cv, c->hv, W, hot, src, n_inner, cfl, s));
+    return sync_status(c, s);
+}
+
+extern "C" gsis_status gsis_macro_solve_internal(gsis_case c, double *W, double *Tr, const double *hot,
+                                                 const double *hot_r, const double *src, const double *src_r,
+                                                 int32_t n_inner, double cfl, void *stream)
+{
+    if (!c || !W || !Tr || !hot) return fail(GSIS_E_ARG, "null argument");
+    if (!c->bound) return fail(GSIS_E_STATE, "case is not bound to a workspace");
+    if (!(c->dr > 0)) return fail(GSIS_E_ARG, "gsis_macro_solve_internal: a monatomic case (use gsis_macro_solve)");
+    if (n_inner < 0 || cfl == 0 || !std::isfinite(cfl)) return fail(GSIS_E_ARG, "bad n_inner or cfl");
+    hipStream_t s = (hipStream_t)stream;
+    CaseView &h = c->hv;
+    const size_t nc = (size_t)h.n_cells;
+    HIPCHK(hipMemsetAsync(h.status, 0, 16, s));
+    HIPCHK(launch_check_W(c->cv, h, W, s));
+    // the q_r high-order terms and the rho e_r source live in the workspace
+    if (hot_r) HIPCHK(hipMemcpyAsync(h.hotr, hot_r, 24 * nc, hipMemcpyDeviceToDevice, s));
+    else HIPCHK(hipMemsetAsync(h.hotr, 0, 24 * nc, s));
+    if (src) {
+        if (src_r) HIPCHK(hipMemcpyAsync(h.srcr, src_r, 8 * nc, hipMemcpyDeviceToDevice, s));
+        else HIPCHK(hipMemsetAsync(h.srcr, 0, 8 * nc, s));
+    }
+    MBatch b{};
+    mbatch_add(b, c->cv, h, W, hot, src, Tr);
+    HIPCHK(launch_macro_steps_poly(b, n_inner, cfl, s));
     return sync_status(c, s);
 }
 

@@ -5,8 +5,9 @@ ragged tail, and on the Mach-5 sphere's partial region (NS neighbours,
 Grad-13 ghosts, far field, walls); the state filled from W; DVM, GSIS and
 aGSIS outer iterations (synthetic solve with the internal-energy equation,
 correction of both VDFs, region updates); the NS start; a converged GSIS
-solution; the surface quantities with the internal energy; and the calls
-the polyatomic gas refuses.
+solution; the surface quantities with the internal energy; the correction
+and the synthetic solve as calls of their own; and the calls the polyatomic
+gas refuses.
 Tolerances: FP32 1e-5 per sweep, FP64 1e-11; outer iterations FP64 1e-9,
 FP32 1e-4 (the synthetic solve's 100-400 pseudo-time steps amplify the
 sweep's rounding).
@@ -289,6 +290,10 @@ def test_poly_refusals(g):
     mono.set_state(W)
     with pytest.raises(g.GsisError):
         mono.internal_moments()
+    with pytest.raises(g.GsisError):   # the two-VDF entry points refuse a monatomic case
+        mono.correct_internal(W, W[:, 4])
+    with pytest.raises(g.GsisError):
+        mono.macro_solve_internal(W, W[:, 4], np.zeros((m["n_cells"], 9)), n_inner=10)
     with pytest.raises(g.GsisError):   # point sets are not supported with d_r > 0
         g.Case(g.Mesh(m), gi.ball_grid(8, 4.0), Kn, dtype=g.F64, dr=2.0, Zr=2.0, A=N2["A"])
     with pytest.raises(g.GsisError):   # nor a reduced 2D grid
@@ -347,3 +352,62 @@ def test_poly_surface_matches_oracle(g, oracle_mod, name, dtype):
           "totals", e_tot, flush=True)
     assert n_kw > 0 and (base == "couette" or n_kw < len(wc))
     assert e_tau < 1e-10 and e_q < 1e-10 and e_m < 1e-10 and e_tot < 1e-10
+
+
+def test_poly_correction_alone(g, oracle_mod):
+    """gsis_correct_internal (Sec. 3.1 eq. updatef with rho e_r in W) on the
+    Couette slab, every cell kinetic, FP64: f0 += f_eq(W_new) - f_eq(W_half)
+    and f1 += (d_r/4)(T_r,new f_eq(W_new) - T_r,half f_eq(W_half)), with the
+    half state the rows' own moments and changes of a few percent (inside the
+    correction limiter's range); rows, W and T_r against the oracle."""
+    m, grid, Kn, W, _ = workload("couette")
+    O, case = _pair(oracle_mod.Oracle, g, m, grid, Kn, g.F64)
+    f0 = _rows(grid, W, 21, g.F64)
+    mo = O.moments(f0)
+    Wh = np.concatenate([mo[:, :5], mo[:, 14:15]], 1)
+    case.set_state(Wh[:, :5], vdf=f0)
+    Wn = Wh.copy()
+    pert = gi.perturbation((len(Wn), 6), seed=22, amp=0.02)
+    Wn[:, 0] *= pert[:, 0]
+    Wn[:, 1:3] += 0.01 * (pert[:, 1:3] - 1)
+    Wn[:, 4] *= pert[:, 4]
+    Wn[:, 5] *= pert[:, 5]
+    case.correct_internal(Wn[:, :5], Wn[:, 5])
+    fo = np.stack([f0[i] + O.feq(Wn[i]) - O.feq(Wh[i]) for i in range(len(Wn))])
+    ef = f_error(case.get_vdf().cpu().numpy(), fo, O.w)
+    Wg = case.get_state()[0].cpu().numpy()
+    Trg = case.internal_temperature().cpu().numpy()
+    print("poly correction", ef, np.abs(Wg - Wn[:, :5]).max(), np.abs(Trg - Wn[:, 5]).max(), flush=True)
+    assert ef < 1e-11
+    # W and T_r become the new state (W_half + theta (W_new - W_half) with theta = 1:
+    # equal up to the rounding of that form)
+    assert np.abs(Wg - Wn[:, :5]).max() < 1e-13 and np.abs(Trg - Wn[:, 5]).max() < 1e-13
+    ig = case.internal_moments().cpu().numpy()
+    assert np.abs(ig[:, 0] - O.moments(fo)[:, 14]).max() < 1e-11
+
+
+@pytest.mark.parametrize("name,cfl", [("sphere_small", 0.5), ("couette", -0.5)])
+def test_poly_macro_solve_alone(g, oracle_mod, name, cfl):
+    """gsis_macro_solve_internal (Sec. 2 eq. macroscopic_equation_2 with the
+    internal-energy line, eq. macro): 60 pseudo-time steps from a field whose
+    internal temperature is out of equilibrium, with seeded high-order terms
+    (sigma, q_t, q_r) and sources, local steps on the sphere (walls, far
+    field) and the global step on the Couette slab; W and T_r against the
+    oracle's solve (FP64, 1e-10)."""
+    m, grid, Kn, W, _ = workload(name)
+    O, case = _pair(oracle_mod.Oracle, g, m, grid, Kn, g.F64)
+    case.set_state(W)
+    n = m["n_cells"]
+    W6 = np.concatenate([W, (W[:, 4] * gi.perturbation((n,), seed=31, amp=0.1))[:, None]], 1)
+    hot = 0.01 * (gi.perturbation((n, 12), seed=32, amp=1.0) - 1.0)
+    src = 0.001 * (gi.perturbation((n, 6), seed=33, amp=1.0) - 1.0)
+    Wo = O.macro(W6, hot, 60, cfl, src)
+    Wg, Trg = case.macro_solve_internal(W6[:, :5], W6[:, 5], hot[:, :9], hot[:, 9:], src[:, :5], src[:, 5],
+                                        n_inner=60, cfl=cfl)
+    Wg, Trg = Wg.cpu().numpy(), Trg.cpu().numpy()
+    err = {"rho": _rel(Wg[:, 0], Wo[:, 0]), "u": _rel(Wg[:, 1:4], Wo[:, 1:4], max(np.abs(Wo[:, 1:4]).max(), 1.0)),
+           "T_t": _rel(Wg[:, 4], Wo[:, 4]), "T_r": _rel(Trg, Wo[:, 5])}
+    moved = np.abs(Wo[:, 5] - W6[:, 5]).max()
+    print("poly macro alone", name, cfl, err, "T_r moved", moved, flush=True)
+    assert moved > 1e-4
+    assert max(err.values()) < 1e-10, err
