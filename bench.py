@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--poly-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="length of the oracle sample")
     ap.add_argument("--sweep-only", action="store_true", help="time kinetic sweeps only (diagnostic)")
-    ap.add_argument("--serve-requests", type=int, default=50, help="requests per arrival rate (0: skip serving)")
+    ap.add_argument("--serve-requests", type=int, default=170,
+                    help="requests per arrival rate (0: skip serving); 170 give about 55 solved per rate for the p99")
     ap.add_argument("--serve-rates", default="5,20,80", help="Poisson arrival rates of the serving leg (1/s)")
     ap.add_argument("--serve-max-iter", type=int, default=300)
     ap.add_argument("--serve-tol", type=float, default=1e-6, help="served solves stop at this residual (Sec. 4)")
