@@ -301,12 +301,19 @@ hipError_t launch_lsq(const CaseView *cv, const CaseView &h, const double *W, in
     return hipGetLastError();
 }
 
+// T^omega of the viscosity law: the square root, correctly rounded, for hard
+// spheres (omega = 1/2), else pow
+__device__ __forceinline__ double t_pow_omega(const CaseView &C, double T)
+{
+    return (C.omega == 0.5) ? sqrt(T) : pow(T, C.omega);
+}
+
 // Newton and Fourier laws (Sec. 2 eq. NSF_constitutive, kappa of eq.
 // mu_kappa with d_r = 0), scaled: sigma = -(2Kn/sqrt(pi)) T^w (G + G^T -
 // 2/3 tr G I), q = -(5 Kn / (2 sqrt(pi) Pr)) T^w grad T; G[i][j] = du_i/dx_j
 __device__ void nsf(const CaseView &C, double T, const double *Gu, const double *GT, double *s, double *q)
 {
-    double mu = pow(T, C.omega);
+    double mu = t_pow_omega(C, T);
     double cs = -2.0 * C.Kn / sqrt(M_PI) * mu;
     double cq = -5.0 * C.Kn / (2.0 * sqrt(M_PI) * C.Pr) * mu;
     double div = Gu[0] + Gu[4] + Gu[8];
@@ -616,7 +623,7 @@ __device__ double cell_D(const CaseView &C, int i, const double *Wi)
 {
     const double gam = 5.0 / 3.0;
     double a = sqrt(gam * Wi[4] / 2.0);
-    double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wi[4], C.omega) / (sqrt(M_PI) * Wi[0]);
+    double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * t_pow_omega(C, Wi[4]) / (sqrt(M_PI) * Wi[0]);
     // sum_f S_f |u.n_f| = V sum_e |u . (n S / V)_e|; the rest from the per-cell sums
     double un = 0.0;
     for (int e = C.cf_ptr[i]; e < C.cf_ptr[i + 1]; ++e) {
@@ -727,7 +734,7 @@ __device__ __forceinline__ void update_cell(const CaseView &C, double *__restric
 #pragma unroll
         for (int l = 0; l < NF; ++l) un += fabs(Wi[1] * ns[l][0] + Wi[2] * ns[l][1] + Wi[3] * ns[l][2]);
         const double a = sqrt(5.0 / 3.0 * Wi[4] / 2.0);
-        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wi[4], C.omega) / (sqrt(M_PI) * Wi[0]);
+        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * t_pow_omega(C, Wi[4]) / (sqrt(M_PI) * Wi[0]);
         const double *sS = C.cell_sS + 2 * (size_t)i;
         k = cfl / (V * un + a * sS[0] + 2.0 * nu * sS[1]);
     }
@@ -817,7 +824,7 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
         k = (-cfl * C.red[0]) / V;
     } else {
         const double a = sqrt(5.0 / 3.0 * Wc[4] / 2.0);
-        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * pow(Wc[4], C.omega) / (sqrt(M_PI) * Wc[0]);
+        const double nu = fmax(4.0 / 3.0, 5.0 / (3.0 * C.Pr)) * C.Kn * t_pow_omega(C, Wc[4]) / (sqrt(M_PI) * Wc[0]);
         k = cfl / (V * un + a * sS0 + 2.0 * nu * sS1);
     }
     // positivity safeguard: halve this cell's increment (at most ten times)
