@@ -314,8 +314,8 @@ __device__ __forceinline__ double t_pow_omega(const CaseView &C, double T)
 __device__ void nsf(const CaseView &C, double T, const double *Gu, const double *GT, double *s, double *q)
 {
     double mu = t_pow_omega(C, T);
-    double cs = -2.0 * C.Kn / sqrt(M_PI) * mu;
-    double cq = -5.0 * C.Kn / (2.0 * sqrt(M_PI) * C.Pr) * mu;
+    double cs = (-2.0 / sqrt(M_PI)) * C.Kn * mu;
+    double cq = (-2.5 / sqrt(M_PI)) * C.Kn / C.Pr * mu;
     double div = Gu[0] + Gu[4] + Gu[8];
     s[0] = cs * (2.0 * Gu[0] - 2.0 / 3.0 * div);
     s[1] = cs * (2.0 * Gu[4] - 2.0 / 3.0 * div);
@@ -444,7 +444,7 @@ __device__ void half_flux(const double *P, const double *n, double sgn, double *
     double ut2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
     double s = un / sT;
     double A = 0.5 * (1.0 + sgn * erf(s));
-    double B = sgn * exp(-s * s) / (2.0 * sqrt(M_PI));
+    double B = sgn * exp(-s * s) * (0.5 / sqrt(M_PI));   // 1/(2 sqrt(pi)), folded at compile time
     double m1 = un * A + sT * B;
     double m2 = (un * un + 0.5 * T) * A + un * sT * B;
     double m3 = (un * un * un + 1.5 * un * T) * A + (un * un + T) * sT * B;
@@ -501,7 +501,7 @@ __device__ __forceinline__ void face_flux_one(const CaseView &C, const double *_
             // mean gradient corrected along n so that its projection on the
             // centroid difference equals the jump (exact for linear fields)
             const double *dx = C.face_dx + 3 * (size_t)f;
-            const double dn = C.face_dist[f];
+            const double idn = 1.0 / C.face_dist[f];
             double G[4][3];
             const double *gL = grad_row(C, L, 0), *gR = grad_row(C, Rc, 0);
             for (int v = 0; v < 4; ++v) {
@@ -512,7 +512,7 @@ __device__ __forceinline__ void face_flux_one(const CaseView &C, const double *_
                 }
                 double fl = (v < 3) ? PL[1 + v] : PL[4];
                 double fr = (v < 3) ? PR[1 + v] : PR[4];
-                double alpha = (fr - fl - gx) / dn;
+                double alpha = (fr - fl - gx) * idn;
                 for (int d = 0; d < 3; ++d) G[v][d] += alpha * n[d];
             }
             double Tf = 0.5 * (PL[4] + PR[4]);
@@ -834,12 +834,13 @@ __global__ __launch_bounds__(MCELLS_Q * G) void k_update_q(BT B, double cfl)
     for (int h = 0; h <= 10 && !ok; ++h) {
         for (int c = 0; c < 5; ++c) Un[c] = Uc[c] + k * R[c];
         Pn[0] = Un[0];
+        const double ir = 1.0 / Un[0];
         double u2 = 0.0;
         for (int d = 0; d < 3; ++d) {
-            Pn[1 + d] = Un[1 + d] / Un[0];
+            Pn[1 + d] = Un[1 + d] * ir;
             u2 += Pn[1 + d] * Pn[1 + d];
         }
-        Pn[4] = (Un[4] - Un[0] * u2) / (1.5 * Un[0]);
+        Pn[4] = (Un[4] - Un[0] * u2) * ((1.0 / 1.5) * ir);
         ok = (Pn[0] > 0.0) && (Pn[4] > 0.0);
         k *= 0.5;
     }
