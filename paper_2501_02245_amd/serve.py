@@ -81,7 +81,7 @@ class Server:
     """FIFO admission by footprint, one batched outer iteration per tick."""
 
     def __init__(self, budget_bytes, dtype=F32, Kn_ref=0.01, tol=1e-6, max_iter=400, n_inner=400,
-                 ns_chunks=50, max_active=64, keep_fields=True, min_iter=5, step_graphs=False, source_half=False):
+                 ns_chunks=50, max_active=256, keep_fields=True, min_iter=5, step_graphs=False, source_half=False):
         self.budget = int(budget_bytes)
         # replay each group's outer iteration from a HIP graph between region
         # updates (GSIS_STEP_GRAPHS; results are bitwise those of eager launches)
