@@ -1099,19 +1099,36 @@ Batch make_batch(gsis_case const *cases, int i0, int m)
 
 gsis_status batched_sweep(gsis_case const *cases, int n, hipStream_t s, bool timed)
 {
-    for (int i0 = 0; i0 < n; i0 += MAX_BATCH) {
-        const int m = std::min(MAX_BATCH, n - i0);
-        Batch b = make_batch(cases, i0, m);
-        if (timed && i0 == 0 && cases[0]->ev0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
-        // order 2: limited slopes of every case's f^n (the sweep reads its own
-        // and its neighbours')
-        for (int j = 0; j < m; ++j) {
-            gsis_case c = cases[i0 + j];
-            if (c->order == 2) HIPCHK(launch_slope(c->cv, c->hv, c->n_kin, c->cur, s));
-        }
-        HIPCHK(launch_sweep(b, cases[i0]->hv, b.start[m], s));
-        if (timed && i0 + MAX_BATCH >= n && cases[0]->ev1) HIPCHK(hipEventRecord(cases[0]->ev1, s));
+    // A case is swept by the kernel it gets alone (16-byte rows or not): cases
+    // of the two kinds never share a launch, so its rows do not depend on the
+    // batch it comes in.  Within a launch the LDS is sized for the largest
+    // axes of its cases.
+    std::vector<gsis_case> part[2];
+    for (int j = 0; j < n; ++j) {
+        gsis_case one[1] = {cases[j]};
+        part[make_batch(one, 0, 1).v4 ? 1 : 0].push_back(cases[j]);
     }
+    bool first = true;
+    for (int k = 1; k >= 0; --k) {
+        const std::vector<gsis_case> &pc = part[k];
+        for (size_t i0 = 0; i0 < pc.size(); i0 += MAX_BATCH) {
+            const int m = (int)std::min<size_t>(MAX_BATCH, pc.size() - i0);
+            Batch b = make_batch(pc.data(), (int)i0, m);
+            CaseView hs = pc[i0]->hv;
+            for (int j = 1; j < m; ++j)
+                for (int d = 0; d < 3; ++d) hs.n[d] = std::max(hs.n[d], pc[i0 + j]->hv.n[d]);
+            if (timed && first && cases[0]->ev0) HIPCHK(hipEventRecord(cases[0]->ev0, s));
+            first = false;
+            // order 2: limited slopes of every case's f^n (the sweep reads its own
+            // and its neighbours')
+            for (int j = 0; j < m; ++j) {
+                gsis_case c = pc[i0 + j];
+                if (c->order == 2) HIPCHK(launch_slope(c->cv, c->hv, c->n_kin, c->cur, s));
+            }
+            HIPCHK(launch_sweep(b, hs, b.start[m], s));
+        }
+    }
+    if (timed && cases[0]->ev1) HIPCHK(hipEventRecord(cases[0]->ev1, s));
     // the events time the whole batched launch; they belong to the first case
     for (int j = 0; j < n; ++j) {
         cases[j]->cur ^= 1;

@@ -18,7 +18,7 @@ constexpr int MAXF = GSIS_MAX_FACES;
 constexpr int MAXW = GSIS_MAX_WALL_FACES;
 constexpr int MAXA = GSIS_MAX_AXIS;
 constexpr int NSUM = 24;               // per (slot, tile) partial sums, see below
-constexpr int MAX_BATCH = 16;          // cases per batched launch
+constexpr int MAX_BATCH = 64;          // cases per batched launch (the batch structures stay under 4 KB of kernel arguments)
 // per-slot moment record: the GSIS_NMOM moments, the MAXW outgoing wall
 // fluxes, then (polyatomic gas) T_r and q_r
 constexpr int MOMS = GSIS_NMOM + MAXW + 4;

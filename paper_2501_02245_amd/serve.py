@@ -23,6 +23,9 @@ from . import (E_CAPACITY, F32, MODE_AGSIS, MODE_GSIS, Case, GsisError, Mesh, So
                step)
 
 
+BATCH = 64   # cases per gsis_step call: the library's largest batched launch
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
@@ -227,8 +230,8 @@ class Server:
             for key, grp in groups.items():
                 # a batch lists the case with the largest velocity axes first
                 grp.sort(key=lambda a: -a.case.nv)
-                for j0 in range(0, len(grp), 16):
-                    part = grp[j0:j0 + 16]
+                for j0 in range(0, len(grp), BATCH):
+                    part = grp[j0:j0 + BATCH]
                     try:
                         eps = step([a.case for a in part],
                                    self._params(key[4], key[5], key[6], source_half=self.source_half))

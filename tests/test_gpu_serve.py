@@ -48,6 +48,28 @@ def test_served_equals_alone(g, half):
         assert np.array_equal(W, out.W)
 
 
+def test_served_equals_alone_across_sweep_kernels(g):
+    """1D boxes on 16^3 and 64^3 grids served together: the 16^3 rows take the
+    16-byte-row sweep and the 64^3 rows the 4-byte-row one, whatever else is in
+    the batch, so every request ends bitwise where it ends alone (a batch
+    swept with one kernel for all its cases changed the 16^3 results)."""
+    import paper_2501_02245_amd.serve as sv
+    reqs = _requests(6, 5, kinds=("couette", "fourier"), cells_1d=(24, 40), nv_1d=(16, 64), Kn_range=(0.02, 0.2),
+                     mach_range=(1.0, 2.0))
+    sizes = {r.grid["n"][0] if "n" in r.grid else len(r.grid["nodes"][0]) for r in reqs}
+    assert sizes == {16, 64}, sizes
+    for r in reqs:
+        r.arrival = 0.0
+    srv = sv.Server(budget_bytes=8 << 30, max_iter=12, source_half=True)
+    res = srv.run(reqs)
+    assert srv.peak_active == len(reqs)
+    for r, out in zip(reqs, res):
+        it, eps, nk, W, status = sv.solve_alone(r, g.F32, max_iter=12, source_half=True)
+        print(r.rid, r.kind, len(r.grid["nodes"][0]), status, out.status, it, out.iterations, flush=True)
+        assert status == out.status and it == out.iterations
+        assert np.array_equal(W, out.W)
+
+
 @pytest.mark.parametrize("half", [0, 1])
 def test_served_matches_oracle(g, oracle_mod, half):
     """Three 1D requests served in FP32 against the FP64 oracle run with the
