@@ -252,6 +252,30 @@ def serving(g, n, rates, max_iter, tol, n_check, source_half, seed=7):
     return out
 
 
+def stream_rate(torch, mib=1024, reps=5):
+    """A plain streaming kernel on this GPU (torch mul: reads and writes `mib`
+    MiB each), timed with events on its stream; the best of `reps`, in GB/s.
+    It is the attainable HBM rate the sweep's bytes are set against, beside
+    the published peak."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(reps):
+        e0.record()
+        torch.mul(x, 2.0, out=y)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    torch.cuda.synchronize()
+    return 2.0 * n * 4 / (best * 1e-3) / 1e9
+
+
 def fp64_sweep(g, torch, M, grid, W, flags, steps=3):
     """Plain FP64 sweeps of the initial region on the same GPU."""
     cap = int(flags.sum()) + 64
@@ -607,6 +631,9 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
+    copy_gbs = stream_rate(torch)
+    log("plain streaming kernel %.0f GB/s" % copy_gbs)
+
     fp64 = None
     if not a.no_fp64_sweep and dtype == g.F32:
         fp64 = fp64_sweep(g, torch, M, grid, W, flags)
@@ -653,7 +680,8 @@ def main():
                    "sweep_only": bool(a.sweep_only)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": sweep_kernel_name(),
-                     "kernel_ms": 1e3 * sweep_s},
+                     "kernel_ms": 1e3 * sweep_s, "copy_gbs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs if copy_gbs else None},
         "sweep_updates_per_s": n_kin_mean * nv / sweep_s,
         "fp64_sweep": fp64,
         "point_grid_sweep": points,
